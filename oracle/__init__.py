@@ -1,0 +1,259 @@
+"""Plain FP64 CPU oracle for the 2D vortex-particle FMM (test infrastructure).
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` import this package.  The product library never does: it shares
+no code, header, table or helper with the oracle.
+
+The arithmetic lives in ``fmm_oracle.c`` (see its header for the passages of
+the paper each function follows); this module only marshals numpy arrays
+through ctypes.  ``build()`` compiles the C file with gcc.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fmm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_lib = None
+
+
+def build() -> str:
+    """Compile the oracle into ``oracle/liboracle.so`` (always rebuilds)."""
+    cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fcx-limited-range",
+           "-fPIC", "-shared", "-std=gnu11", "-Wall", "-o", _LIB + ".tmp", _SRC,
+           "-lm", "-lpthread"]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build()
+    lib = C.CDLL(_LIB)
+    dp = C.POINTER(C.c_double)
+    i64 = C.c_int64
+    i32p = C.POINTER(C.c_int32)
+    u32p = C.POINTER(C.c_uint32)
+    i64p = C.POINTER(C.c_int64)
+    lib.oracle_init.restype = C.c_int
+    lib.oracle_bounding_square.argtypes = [i64, dp, dp, dp]
+    lib.oracle_quantize.argtypes = [i64, dp, dp, C.c_int, C.c_double, C.c_double, C.c_double, i32p, i32p]
+    lib.oracle_quantize.restype = i64
+    lib.oracle_morton.argtypes = [C.c_uint32, C.c_uint32]
+    lib.oracle_morton.restype = C.c_uint32
+    lib.oracle_tree.argtypes = [i64, dp, dp, C.c_int, C.c_double, C.c_double, C.c_double, u32p, u32p, i64p]
+    lib.oracle_tree.restype = i64
+    lib.oracle_direct.argtypes = [i64, dp, dp, dp, C.c_double, i64, i64p, dp, dp]
+    lib.oracle_direct_split.argtypes = [i64, dp, dp, dp, C.c_double, C.c_int, C.c_double, C.c_double,
+                                        C.c_double, i64, i64p, dp, dp]
+    lib.oracle_p2m.argtypes = [i64, dp, dp, dp, C.c_double, C.c_double, C.c_int, dp]
+    lib.oracle_me_eval.argtypes = [C.c_int, dp, C.c_double, C.c_double, C.c_double, C.c_double, dp]
+    lib.oracle_m2m.argtypes = [C.c_int, dp, C.c_double, C.c_double, dp]
+    lib.oracle_m2l.argtypes = [C.c_int, dp, C.c_double, C.c_double, dp]
+    lib.oracle_l2l.argtypes = [C.c_int, dp, C.c_double, C.c_double, dp]
+    lib.oracle_l2p.argtypes = [C.c_int, dp, C.c_double, C.c_double, C.c_double, C.c_double, dp]
+    lib.oracle_near_list.argtypes = [C.c_int, C.c_int, C.c_int, i32p, i32p]
+    lib.oracle_near_list.restype = C.c_int
+    lib.oracle_interaction_list.argtypes = [C.c_int, C.c_int, C.c_int, i32p, i32p]
+    lib.oracle_interaction_list.restype = C.c_int
+    lib.oracle_fmm.argtypes = [i64, dp, dp, dp, C.c_double, C.c_int, C.c_int, C.c_double, C.c_double,
+                               C.c_double, i64, i64p, dp, dp, dp, dp]
+    lib.oracle_fmm.restype = i64
+    lib.oracle_init()
+    _lib = lib
+    return lib
+
+
+PMAX = 64
+
+
+def _d(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _targets(tgt, n):
+    if tgt is None:
+        return None, n, None
+    t = np.ascontiguousarray(tgt, dtype=np.int64)
+    return t, int(t.shape[0]), t.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+def bounding_square(x, y):
+    """(x0, y0, W): the square the auto-domain mode uses."""
+    lib = _load()
+    x, y = _f64(x), _f64(y)
+    dom = np.zeros(3)
+    lib.oracle_bounding_square(x.shape[0], _d(x), _d(y), _d(dom))
+    return float(dom[0]), float(dom[1]), float(dom[2])
+
+
+def quantize(x, y, L, x0=0.0, y0=0.0, W=1.0):
+    """Level-L box coordinates (ia, ib) of every particle and the out-of-domain count."""
+    lib = _load()
+    x, y = _f64(x), _f64(y)
+    n = x.shape[0]
+    ia = np.zeros(n, np.int32)
+    ib = np.zeros(n, np.int32)
+    nbad = lib.oracle_quantize(n, _d(x), _d(y), L, x0, y0, W,
+                               ia.ctypes.data_as(C.POINTER(C.c_int32)),
+                               ib.ctypes.data_as(C.POINTER(C.c_int32)))
+    return ia, ib, int(nbad)
+
+
+def morton(a, b):
+    return int(_load().oracle_morton(int(a), int(b)))
+
+
+def tree(x, y, L, x0=0.0, y0=0.0, W=1.0):
+    """(key[n] u32, perm[n] u32, leaf_start[4^L+1] i64, n_out_of_domain)."""
+    lib = _load()
+    x, y = _f64(x), _f64(y)
+    n = x.shape[0]
+    key = np.zeros(n, np.uint32)
+    perm = np.zeros(n, np.uint32)
+    ls = np.zeros((1 << (2 * L)) + 1, np.int64)
+    nbad = lib.oracle_tree(n, _d(x), _d(y), L, x0, y0, W,
+                           key.ctypes.data_as(C.POINTER(C.c_uint32)),
+                           perm.ctypes.data_as(C.POINTER(C.c_uint32)),
+                           ls.ctypes.data_as(C.POINTER(C.c_int64)))
+    return key, perm, ls, int(nbad)
+
+
+def direct(x, y, g, sigma, targets=None):
+    """Regularised direct sum (eq. 9) at all particles or at ``targets``."""
+    lib = _load()
+    x, y, g = _f64(x), _f64(y), _f64(g)
+    n = x.shape[0]
+    t, nt, tp = _targets(targets, n)
+    u = np.zeros(nt)
+    v = np.zeros(nt)
+    lib.oracle_direct(n, _d(x), _d(y), _d(g), sigma, nt, tp, _d(u), _d(v))
+    return u, v
+
+
+def direct_split(x, y, g, sigma, L, x0=0.0, y0=0.0, W=1.0, targets=None):
+    """Split-kernel direct sum: Gaussian kernel for touching-leaf pairs, singular otherwise."""
+    lib = _load()
+    x, y, g = _f64(x), _f64(y), _f64(g)
+    n = x.shape[0]
+    t, nt, tp = _targets(targets, n)
+    u = np.zeros(nt)
+    v = np.zeros(nt)
+    lib.oracle_direct_split(n, _d(x), _d(y), _d(g), sigma, L, x0, y0, W, nt, tp, _d(u), _d(v))
+    return u, v
+
+
+def fmm(x, y, g, sigma, p, L, x0=0.0, y0=0.0, W=1.0, targets=None, dump=False):
+    """One FP64 FMM evaluation.  Returns (u, v) or (u, v, me, le, nbad) with dump=True.
+
+    me / le are complex arrays [Lambda, p] in the oracle's own layout: level l
+    starts at (4^l - 1)/3 and box (a, b) sits at row-major index b * 2^l + a.
+    """
+    lib = _load()
+    if not (1 <= p <= PMAX):
+        raise ValueError("p out of range")
+    x, y, g = _f64(x), _f64(y), _f64(g)
+    n = x.shape[0]
+    t, nt, tp = _targets(targets, n)
+    u = np.zeros(nt)
+    v = np.zeros(nt)
+    nbox = ((1 << (2 * (L + 1))) - 1) // 3
+    me = le = None
+    mep = lep = None
+    if dump:
+        me = np.zeros(nbox * p, np.complex128)
+        le = np.zeros(nbox * p, np.complex128)
+        mep = me.ctypes.data_as(C.POINTER(C.c_double))
+        lep = le.ctypes.data_as(C.POINTER(C.c_double))
+    nbad = lib.oracle_fmm(n, _d(x), _d(y), _d(g), sigma, p, L, x0, y0, W, nt, tp,
+                          _d(u), _d(v), mep, lep)
+    if dump:
+        return u, v, me.reshape(nbox, p), le.reshape(nbox, p), int(nbad)
+    return u, v
+
+
+# ---- single operators (used by the operator-identity pins) -------------------
+
+def p2m(x, y, g, cx, cy, p):
+    lib = _load()
+    x, y, g = _f64(x), _f64(y), _f64(g)
+    a = np.zeros(p, np.complex128)
+    lib.oracle_p2m(x.shape[0], _d(x), _d(y), _d(g), cx, cy, p, a.ctypes.data_as(C.POINTER(C.c_double)))
+    return a
+
+
+def me_eval(a, cx, cy, zx, zy):
+    lib = _load()
+    a = np.ascontiguousarray(a, np.complex128)
+    out = np.zeros(2)
+    lib.oracle_me_eval(a.shape[0], a.ctypes.data_as(C.POINTER(C.c_double)), cx, cy, zx, zy, _d(out))
+    return complex(out[0], out[1])
+
+
+def _op(fn, coeffs, dx, dy):
+    c = np.ascontiguousarray(coeffs, np.complex128)
+    out = np.zeros_like(c)
+    fn(c.shape[0], c.ctypes.data_as(C.POINTER(C.c_double)), dx, dy, out.ctypes.data_as(C.POINTER(C.c_double)))
+    return out
+
+
+def m2m(a_child, dx, dy):
+    """Shift a child ME by d = c_child - c_parent."""
+    return _op(_load().oracle_m2m, a_child, dx, dy)
+
+
+def m2l(a_src, tx, ty):
+    """ME about the source centre -> LE about the target centre, tau = c_s - c_t."""
+    return _op(_load().oracle_m2l, a_src, tx, ty)
+
+
+def l2l(b_parent, dx, dy):
+    """Re-centre an LE by d = c_child - c_parent."""
+    return _op(_load().oracle_l2l, b_parent, dx, dy)
+
+
+def l2p(b, cx, cy, zx, zy):
+    lib = _load()
+    b = np.ascontiguousarray(b, np.complex128)
+    out = np.zeros(2)
+    lib.oracle_l2p(b.shape[0], b.ctypes.data_as(C.POINTER(C.c_double)), cx, cy, zx, zy, _d(out))
+    return complex(out[0], out[1])
+
+
+def near_list(L, a, b):
+    lib = _load()
+    sa = np.zeros(9, np.int32)
+    sb = np.zeros(9, np.int32)
+    k = lib.oracle_near_list(L, a, b, sa.ctypes.data_as(C.POINTER(C.c_int32)),
+                             sb.ctypes.data_as(C.POINTER(C.c_int32)))
+    return list(zip(sa[:k].tolist(), sb[:k].tolist()))
+
+
+def interaction_list(l, a, b):
+    lib = _load()
+    sa = np.zeros(27, np.int32)
+    sb = np.zeros(27, np.int32)
+    k = lib.oracle_interaction_list(l, a, b, sa.ctypes.data_as(C.POINTER(C.c_int32)),
+                                    sb.ctypes.data_as(C.POINTER(C.c_int32)))
+    return list(zip(sa[:k].tolist(), sb[:k].tolist()))
+
+
+def rel_l2(u, v, uref, vref):
+    """sqrt(sum |w - w_ref|^2) / sqrt(sum |w_ref|^2) over 2-vectors w = (u, v)."""
+    num = np.sum((np.asarray(u) - uref) ** 2 + (np.asarray(v) - vref) ** 2)
+    den = np.sum(np.asarray(uref) ** 2 + np.asarray(vref) ** 2)
+    return float(np.sqrt(num / den))

@@ -1,0 +1,566 @@
+/*
+ * fmm_oracle.c -- plain FP64 CPU reference for the 2D vortex-particle FMM.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load this library.  The GPU library never
+ * links, loads or calls it, and the two share no source, header or table.
+ *
+ * What it computes, and the passage of Cruz, Knepley & Barba (PetFMM) each
+ * part follows:
+ *   - regularised Biot-Savart direct sum ............ Section 3, eqs. 8-9
+ *   - split-kernel direct sum (what the FMM approximates: the near field
+ *     uses the Gaussian-regularised kernel, the far field the singular
+ *     kernel whose expansions are used) ............. Section 3, text after eq. 9
+ *   - uniform quadtree, near field = the box and the boxes touching it,
+ *     interaction list = same-level far boxes whose parents touch
+ *     ............................................... Section 2.1, Fig. 1; Section 2.2
+ *   - z-order (Morton) box numbering .................. Section 5.1
+ *   - upward sweep (P2M, M2M), downward sweep (M2L over the interaction
+ *     list, L2L), evaluation (L2P + near-field direct) .. Section 2.2, Fig. 2
+ * The paper leaves out the expansion mathematics and points to Greengard and
+ * Rokhlin; the expansions below are the textbook complex-variable ones for the
+ * Cauchy kernel 1/z, kept unscaled (coefficients about geometric box centres).
+ *
+ * Complex form used throughout: z = x + i y and
+ *     phi(z_i) = sum_j gamma_j c_ij / (z_i - z_j),
+ *     c_ij = 1 - exp(-|z_i - z_j|^2 / (2 sigma^2))   (regularised pair)
+ *     c_ij = 1                                       (singular, far pair)
+ * so that the velocity of eq. 9 is u = Im(phi) / (2 pi), v = Re(phi) / (2 pi).
+ * A pair at zero distance contributes nothing (the kernel of eq. 8 tends to 0).
+ *
+ * Parity status: every function here is pinned by the CPU tests (closed
+ * forms, invariants, operator identities, brute force); none is unpinned.
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared -lm.
+ * -ffp-contract=off keeps the quantisation (x - x0) * s as two correctly
+ * rounded operations, which fixes the box of every particle exactly.
+ */
+#include <complex.h>
+#include <pthread.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex cplx;
+
+#define TWO_PI 6.283185307179586476925286766559
+
+/* ---------------------------------------------------------------------- */
+/* Domain and quantisation (Section 2.1: uniform subdivision of a square). */
+/* ---------------------------------------------------------------------- */
+
+/* Bounding square of the points: x0 = min x, y0 = min y, W = the larger
+ * extent (1 if the points span nothing).  NaNs are ignored here and counted
+ * as out-of-domain by the quantiser. */
+void oracle_bounding_square(int64_t n, const double* x, const double* y, double* dom)
+{
+    double xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
+    for (int64_t i = 0; i < n; ++i) {
+        if (x[i] == x[i]) { if (x[i] < xmin) xmin = x[i]; if (x[i] > xmax) xmax = x[i]; }
+        if (y[i] == y[i]) { if (y[i] < ymin) ymin = y[i]; if (y[i] > ymax) ymax = y[i]; }
+    }
+    double w = xmax - xmin;
+    if (ymax - ymin > w) w = ymax - ymin;
+    if (!(w > 0.0) || !isfinite(w)) { w = 1.0; }
+    if (!isfinite(xmin)) xmin = 0.0;
+    if (!isfinite(ymin)) ymin = 0.0;
+    dom[0] = xmin; dom[1] = ymin; dom[2] = w;
+}
+
+/* Box index along one axis at level L: t = (v - o) * s with s = 2^L / W, one
+ * correctly rounded division done by the caller.  A point is inside when
+ * 0 <= t <= 2^L; t == 2^L (the far edge) goes to the last box.  Points
+ * outside (or NaN) are clamped and reported through *bad. */
+static int64_t axis_box(double v, double o, double s, int64_t side, int* bad)
+{
+    double t = (v - o) * s;
+    if (!(t >= 0.0 && t <= (double)side)) {
+        *bad = 1;
+        if (t > (double)side) return side - 1;
+        return 0;                       /* below the domain, or NaN */
+    }
+    int64_t b = (int64_t)floor(t);
+    if (b > side - 1) b = side - 1;
+    return b;
+}
+
+/* Level-L box coordinates of every particle; returns the number of
+ * particles outside the square [x0, x0+W]^2. */
+int64_t oracle_quantize(int64_t n, const double* x, const double* y, int L,
+                        double x0, double y0, double W, int32_t* ia, int32_t* ib)
+{
+    const int64_t side = (int64_t)1 << L;
+    const double s = ldexp(1.0, L) / W;
+    int64_t nbad = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int bad = 0;
+        ia[i] = (int32_t)axis_box(x[i], x0, s, side, &bad);
+        ib[i] = (int32_t)axis_box(y[i], y0, s, side, &bad);
+        nbad += bad;
+    }
+    return nbad;
+}
+
+/* z-order number of box (a, b): bit k of a goes to bit 2k, bit k of b to
+ * bit 2k+1 (Section 5.1 uses the z-order numbering of quadtree nodes). */
+uint32_t oracle_morton(uint32_t a, uint32_t b)
+{
+    uint32_t key = 0;
+    for (int k = 0; k < 16; ++k) {
+        key |= ((a >> k) & 1u) << (2 * k);
+        key |= ((b >> k) & 1u) << (2 * k + 1);
+    }
+    return key;
+}
+
+typedef struct { uint32_t key; uint32_t idx; } key_idx;
+
+static int cmp_key_idx(const void* pa, const void* pb)
+{
+    const key_idx* a = (const key_idx*)pa;
+    const key_idx* b = (const key_idx*)pb;
+    if (a->key != b->key) return a->key < b->key ? -1 : 1;
+    if (a->idx != b->idx) return a->idx < b->idx ? -1 : 1;
+    return 0;
+}
+
+/* Tree build: leaf key of every particle (input order), the permutation that
+ * sorts particles by (key, input index), and leaf_start[4^L + 1] giving the
+ * sorted range of every leaf in z-order.  Returns the out-of-domain count. */
+int64_t oracle_tree(int64_t n, const double* x, const double* y, int L,
+                    double x0, double y0, double W,
+                    uint32_t* key, uint32_t* perm, int64_t* leaf_start)
+{
+    int32_t* ia = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t* ib = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int64_t nbad = oracle_quantize(n, x, y, L, x0, y0, W, ia, ib);
+    key_idx* ki = (key_idx*)malloc(sizeof(key_idx) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        key[i] = oracle_morton((uint32_t)ia[i], (uint32_t)ib[i]);
+        ki[i].key = key[i];
+        ki[i].idx = (uint32_t)i;
+    }
+    qsort(ki, (size_t)n, sizeof(key_idx), cmp_key_idx);
+    const int64_t nleaf = (int64_t)1 << (2 * L);
+    memset(leaf_start, 0, sizeof(int64_t) * (size_t)(nleaf + 1));
+    for (int64_t i = 0; i < n; ++i) {
+        perm[i] = ki[i].idx;
+        leaf_start[ki[i].key + 1] += 1;
+    }
+    for (int64_t m = 0; m < nleaf; ++m) leaf_start[m + 1] += leaf_start[m];
+    free(ki); free(ia); free(ib);
+    return nbad;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Kernels and direct sums (Section 3, eqs. 7-9).                          */
+/* ---------------------------------------------------------------------- */
+
+/* Contribution gamma * c / (z_i - z_j) of source j at target i, added to
+ * (*re, *im).  regularised != 0 uses the Gaussian core of eq. 8, otherwise the
+ * singular kernel of eq. 7.  Zero distance contributes nothing. */
+static void pair_phi(double xi, double yi, double xj, double yj, double gj,
+                     double inv_2s2, int regularised, double* re, double* im)
+{
+    double dx = xi - xj, dy = yi - yj;
+    double r2 = dx * dx + dy * dy;
+    if (r2 == 0.0) return;
+    double c = regularised ? -expm1(-r2 * inv_2s2) : 1.0;
+    /* 1 / (dx + i dy) = (dx - i dy) / r2 */
+    double q = gj * c / r2;
+    *re += q * dx;
+    *im -= q * dy;
+}
+
+/* Regularised direct sum, eq. 9: u_i = sum_{j != i} gamma_j K_sigma(x_i - x_j).
+ * tgt == NULL evaluates every particle (nt must equal n). */
+void oracle_direct(int64_t n, const double* x, const double* y, const double* g,
+                   double sigma, int64_t nt, const int64_t* tgt, double* u, double* v)
+{
+    const double inv_2s2 = 1.0 / (2.0 * sigma * sigma);
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < nt; ++t) {
+        int64_t i = tgt ? tgt[t] : t;
+        double re = 0.0, im = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            pair_phi(x[i], y[i], x[j], y[j], g[j], inv_2s2, 1, &re, &im);
+        }
+        u[t] = im / TWO_PI;
+        v[t] = re / TWO_PI;
+    }
+}
+
+/* Split-kernel direct sum: the regularised kernel for pairs whose level-L
+ * leaves touch (Chebyshev leaf distance <= 1), the singular kernel for every
+ * other pair.  This is exactly the sum the FMM approximates, since the far
+ * field is represented by expansions of the singular kernel (Section 3). */
+void oracle_direct_split(int64_t n, const double* x, const double* y, const double* g,
+                         double sigma, int L, double x0, double y0, double W,
+                         int64_t nt, const int64_t* tgt, double* u, double* v)
+{
+    const double inv_2s2 = 1.0 / (2.0 * sigma * sigma);
+    int32_t* ia = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t* ib = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    oracle_quantize(n, x, y, L, x0, y0, W, ia, ib);
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < nt; ++t) {
+        int64_t i = tgt ? tgt[t] : t;
+        double re = 0.0, im = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            int near = abs(ia[i] - ia[j]) <= 1 && abs(ib[i] - ib[j]) <= 1;
+            pair_phi(x[i], y[i], x[j], y[j], g[j], inv_2s2, near, &re, &im);
+        }
+        u[t] = im / TWO_PI;
+        v[t] = re / TWO_PI;
+    }
+    free(ia); free(ib);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Expansion operators: textbook complex expansions of 1/z, p terms        */
+/* (k = 0 .. p-1), unscaled.  Section 2 defines the ME and LE; the          */
+/* mathematics is Greengard and Rokhlin's.                                  */
+/* ---------------------------------------------------------------------- */
+
+/* Largest supported number of expansion terms. */
+#define ORACLE_PMAX 64
+
+/* Binomial coefficients C(n, k), n < 2 * ORACLE_PMAX, from Pascal's rule
+ * (exact while below 2^53, i.e. for every n <= 53). */
+static double BINOM[2 * ORACLE_PMAX][2 * ORACLE_PMAX];
+static pthread_once_t binom_once = PTHREAD_ONCE_INIT;
+
+static void binom_fill(void)
+{
+    for (int nn = 0; nn < 2 * ORACLE_PMAX; ++nn) {
+        BINOM[nn][0] = 1.0;
+        for (int k = 1; k <= nn; ++k)
+            BINOM[nn][k] = BINOM[nn - 1][k - 1] + (k < nn ? BINOM[nn - 1][k] : 0.0);
+    }
+}
+
+static double binom(int nn, int k)
+{
+    if (k < 0 || k > nn) return 0.0;
+    return BINOM[nn][k];
+}
+
+/* Integer powers d^0 .. d^(q-1) by repeated multiplication. */
+static void powers(cplx d, int q, cplx* out)
+{
+    cplx pw = 1.0;
+    for (int i = 0; i < q; ++i) { out[i] = pw; pw *= d; }
+}
+
+/* Must be called (single-threaded) before any operator below is used. */
+int oracle_init(void)
+{
+    pthread_once(&binom_once, binom_fill);
+    return ORACLE_PMAX;
+}
+
+/* P2M: a_k = sum_j gamma_j (z_j - c)^k, so that far from the cluster
+ * phi(z) = sum_k a_k / (z - c)^(k+1). */
+void oracle_p2m(int64_t n, const double* x, const double* y, const double* g,
+                double cx, double cy, int p, double* a_out)
+{
+    cplx* a = (cplx*)a_out;
+    const cplx c = cx + I * cy;
+    for (int k = 0; k < p; ++k) a[k] = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        cplx d = (x[j] + I * y[j]) - c;
+        cplx pw = 1.0;
+        for (int k = 0; k < p; ++k) { a[k] += g[j] * pw; pw *= d; }
+    }
+}
+
+/* Evaluate a multipole expansion about c at z: sum_k a_k / (z - c)^(k+1). */
+void oracle_me_eval(int p, const double* a_in, double cx, double cy,
+                    double zx, double zy, double* phi)
+{
+    const cplx* a = (const cplx*)a_in;
+    cplx w = 1.0 / ((zx + I * zy) - (cx + I * cy));
+    cplx pw = w, s = 0.0;
+    for (int k = 0; k < p; ++k) { s += a[k] * pw; pw *= w; }
+    phi[0] = creal(s); phi[1] = cimag(s);
+}
+
+/* M2M: shift a child ME to its parent centre, d = c_child - c_parent:
+ * a^P_k = sum_{m<=k} C(k,m) a^c_m d^(k-m).  Accumulates into aP. */
+void oracle_m2m(int p, const double* ac_in, double dx, double dy, double* aP_out)
+{
+    const cplx* ac = (const cplx*)ac_in;
+    cplx* aP = (cplx*)aP_out;
+    cplx dp[ORACLE_PMAX];
+    powers(dx + I * dy, p, dp);
+    for (int k = 0; k < p; ++k) {
+        cplx s = 0.0;
+        for (int m = 0; m <= k; ++m) s += binom(k, m) * ac[m] * dp[k - m];
+        aP[k] += s;
+    }
+}
+
+/* M2L: turn a source ME into a local expansion about the target centre,
+ * tau = c_source - c_target:
+ * b_l = sum_k (-1)^(k+1) C(k+l, k) a_k tau^-(k+l+1).  Accumulates into b. */
+void oracle_m2l(int p, const double* a_in, double tx, double ty, double* b_out)
+{
+    const cplx* a = (const cplx*)a_in;
+    cplx* b = (cplx*)b_out;
+    cplx ip[2 * ORACLE_PMAX + 1];                                   /* tau^-q */
+    powers(1.0 / (tx + I * ty), 2 * p + 1, ip);
+    for (int l = 0; l < p; ++l) {
+        cplx s = 0.0;
+        for (int k = 0; k < p; ++k) {
+            double sign = (k % 2 == 0) ? -1.0 : 1.0;                 /* (-1)^(k+1) */
+            s += sign * binom(k + l, k) * a[k] * ip[k + l + 1];
+        }
+        b[l] += s;
+    }
+}
+
+/* L2L: re-centre a local expansion (a polynomial) from the parent centre to
+ * the child centre, d = c_child - c_parent:
+ * b^c_m = sum_{l>=m} C(l,m) b^P_l d^(l-m).  Accumulates into bc. */
+void oracle_l2l(int p, const double* bP_in, double dx, double dy, double* bc_out)
+{
+    const cplx* bP = (const cplx*)bP_in;
+    cplx* bc = (cplx*)bc_out;
+    cplx dp[ORACLE_PMAX];
+    powers(dx + I * dy, p, dp);
+    for (int m = 0; m < p; ++m) {
+        cplx s = 0.0;
+        for (int l = m; l < p; ++l) s += binom(l, m) * bP[l] * dp[l - m];
+        bc[m] += s;
+    }
+}
+
+/* L2P: evaluate a local expansion about c at z: sum_l b_l (z - c)^l. */
+void oracle_l2p(int p, const double* b_in, double cx, double cy,
+                double zx, double zy, double* phi)
+{
+    const cplx* b = (const cplx*)b_in;
+    cplx d = (zx + I * zy) - (cx + I * cy);
+    cplx pw = 1.0, s = 0.0;
+    for (int l = 0; l < p; ++l) { s += b[l] * pw; pw *= d; }
+    phi[0] = creal(s); phi[1] = cimag(s);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Lists (Section 2.1, Fig. 1b; Section 2.2; Table 1: at most 27 IL boxes,  */
+/* 8 neighbours).                                                           */
+/* ---------------------------------------------------------------------- */
+
+static int cheb(int a0, int b0, int a1, int b1)
+{
+    int da = abs(a0 - a1), db = abs(b0 - b1);
+    return da > db ? da : db;
+}
+
+/* Near list of leaf (a, b) at level L: itself and every touching leaf. */
+int oracle_near_list(int L, int a, int b, int32_t* sa, int32_t* sb)
+{
+    const int side = 1 << L;
+    int cnt = 0;
+    for (int j = b - 1; j <= b + 1; ++j)
+        for (int i = a - 1; i <= a + 1; ++i) {
+            if (i < 0 || j < 0 || i >= side || j >= side) continue;
+            sa[cnt] = i; sb[cnt] = j; ++cnt;
+        }
+    return cnt;
+}
+
+/* Interaction list of box (a, b) at level l >= 2: the children of the
+ * parent's neighbours (parent included) that do not touch (a, b). */
+int oracle_interaction_list(int l, int a, int b, int32_t* sa, int32_t* sb)
+{
+    if (l < 2) return 0;
+    const int pside = 1 << (l - 1);
+    const int pa = a >> 1, pb = b >> 1;
+    int cnt = 0;
+    for (int qb = pb - 1; qb <= pb + 1; ++qb)
+        for (int qa = pa - 1; qa <= pa + 1; ++qa) {
+            if (qa < 0 || qb < 0 || qa >= pside || qb >= pside) continue;
+            for (int cb = 0; cb < 2; ++cb)
+                for (int ca = 0; ca < 2; ++ca) {
+                    int sa_ = 2 * qa + ca, sb_ = 2 * qb + cb;
+                    if (cheb(sa_, sb_, a, b) >= 2) { sa[cnt] = sa_; sb[cnt] = sb_; ++cnt; }
+                }
+        }
+    return cnt;
+}
+
+/* ---------------------------------------------------------------------- */
+/* The FMM (Section 2.2, Fig. 2).                                           */
+/* ---------------------------------------------------------------------- */
+
+static int64_t level_offset(int l) { return (((int64_t)1 << (2 * l)) - 1) / 3; }
+
+static void box_centre(int l, int a, int b, double x0, double y0, double W,
+                       double* cx, double* cy)
+{
+    double w = ldexp(W, -l);
+    *cx = x0 + ((double)a + 0.5) * w;
+    *cy = y0 + ((double)b + 0.5) * w;
+}
+
+/* One FMM evaluation.  Boxes are stored per level in row-major order
+ * (index b * 2^l + a) starting at level_offset(l); coefficients are p complex
+ * values per box.  tgt == NULL evaluates all particles (nt == n); otherwise
+ * only the listed particles, with the downward sweep restricted to their
+ * leaves and ancestors.  me_dump / le_dump, if not NULL, receive the
+ * multipole and local coefficients of every box (Lambda * p complex values).
+ * Returns the out-of-domain particle count. */
+int64_t oracle_fmm(int64_t n, const double* x, const double* y, const double* g,
+                   double sigma, int p, int L, double x0, double y0, double W,
+                   int64_t nt, const int64_t* tgt, double* u, double* v,
+                   double* me_dump, double* le_dump)
+{
+    oracle_init();
+    const int64_t side = (int64_t)1 << L;
+    const int64_t nleaf = side * side;
+    const int64_t nbox = level_offset(L + 1);
+    const double inv_2s2 = 1.0 / (2.0 * sigma * sigma);
+
+    int32_t* ia = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t* ib = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int64_t nbad = oracle_quantize(n, x, y, L, x0, y0, W, ia, ib);
+
+    /* leaf membership (row-major leaf order, particles in input order) */
+    int64_t* start = (int64_t*)calloc((size_t)(nleaf + 1), sizeof(int64_t));
+    int64_t* member = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) start[(int64_t)ib[i] * side + ia[i] + 1] += 1;
+    for (int64_t m = 0; m < nleaf; ++m) start[m + 1] += start[m];
+    {
+        int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)nleaf);
+        memcpy(fill, start, sizeof(int64_t) * (size_t)nleaf);
+        for (int64_t i = 0; i < n; ++i) member[fill[(int64_t)ib[i] * side + ia[i]]++] = i;
+        free(fill);
+    }
+
+    cplx* me = (cplx*)calloc((size_t)(nbox * p), sizeof(cplx));
+    cplx* le = (cplx*)calloc((size_t)(nbox * p), sizeof(cplx));
+
+    /* which boxes need a local expansion: all, or the targets' leaves and
+     * their ancestors */
+    char* need = (char*)calloc((size_t)nbox, 1);
+    if (!tgt) {
+        memset(need, 1, (size_t)nbox);
+    } else {
+        for (int64_t t = 0; t < nt; ++t) {
+            int64_t i = tgt[t];
+            int a = ia[i], b = ib[i];
+            for (int l = L; l >= 0; --l) {
+                need[level_offset(l) + ((int64_t)b << l) + a] = 1;
+                a >>= 1; b >>= 1;
+            }
+        }
+    }
+
+    /* Upward sweep: P2M at the leaves. */
+    #pragma omp parallel
+    {
+        double* xs = (double*)malloc(sizeof(double) * 3 * 4096);
+        size_t cap = 4096;
+        #pragma omp for schedule(dynamic, 64)
+        for (int64_t m = 0; m < nleaf; ++m) {
+            int64_t cnt = start[m + 1] - start[m];
+            if (cnt == 0) continue;
+            if ((size_t)cnt > cap) { cap = (size_t)cnt; xs = (double*)realloc(xs, sizeof(double) * 3 * cap); }
+            for (int64_t q = 0; q < cnt; ++q) {
+                int64_t i = member[start[m] + q];
+                xs[q] = x[i]; xs[cap + q] = y[i]; xs[2 * cap + q] = g[i];
+            }
+            double cx, cy;
+            box_centre(L, (int)(m % side), (int)(m / side), x0, y0, W, &cx, &cy);
+            oracle_p2m(cnt, xs, xs + cap, xs + 2 * cap, cx, cy, p,
+                       (double*)(me + (level_offset(L) + m) * p));
+        }
+        free(xs);
+    }
+
+    /* Upward sweep: M2M from level l+1 to level l, l = L-1 .. 2. */
+    for (int l = L - 1; l >= 2; --l) {
+        const int ls = 1 << l;
+        #pragma omp parallel for schedule(static)
+        for (int64_t m = 0; m < (int64_t)ls * ls; ++m) {
+            int a = (int)(m % ls), b = (int)(m / ls);
+            double px, py;
+            box_centre(l, a, b, x0, y0, W, &px, &py);
+            cplx* aP = me + (level_offset(l) + m) * p;
+            for (int cb = 0; cb < 2; ++cb)
+                for (int ca = 0; ca < 2; ++ca) {
+                    int c_a = 2 * a + ca, c_b = 2 * b + cb;
+                    double cx, cy;
+                    box_centre(l + 1, c_a, c_b, x0, y0, W, &cx, &cy);
+                    const cplx* ac = me + (level_offset(l + 1) + ((int64_t)c_b << (l + 1)) + c_a) * p;
+                    oracle_m2m(p, (const double*)ac, cx - px, cy - py, (double*)aP);
+                }
+        }
+    }
+
+    /* Downward sweep: for l = 2 .. L, L2L from the parent (nothing at
+     * level 2: at level 1 every box touches every other) plus M2L from
+     * every member of the interaction list. */
+    for (int l = 2; l <= L; ++l) {
+        const int ls = 1 << l;
+        #pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t m = 0; m < (int64_t)ls * ls; ++m) {
+            if (!need[level_offset(l) + m]) continue;
+            int a = (int)(m % ls), b = (int)(m / ls);
+            double tx, ty;
+            box_centre(l, a, b, x0, y0, W, &tx, &ty);
+            cplx* bt = le + (level_offset(l) + m) * p;
+            if (l > 2) {
+                int pa = a >> 1, pb = b >> 1;
+                double px, py;
+                box_centre(l - 1, pa, pb, x0, y0, W, &px, &py);
+                const cplx* bP = le + (level_offset(l - 1) + ((int64_t)pb << (l - 1)) + pa) * p;
+                oracle_l2l(p, (const double*)bP, tx - px, ty - py, (double*)bt);
+            }
+            int32_t sa[27], sb[27];
+            int cnt = oracle_interaction_list(l, a, b, sa, sb);
+            for (int s = 0; s < cnt; ++s) {
+                double sx, sy;
+                box_centre(l, sa[s], sb[s], x0, y0, W, &sx, &sy);
+                const cplx* as = me + (level_offset(l) + ((int64_t)sb[s] << l) + sa[s]) * p;
+                oracle_m2l(p, (const double*)as, sx - tx, sy - ty, (double*)bt);
+            }
+        }
+    }
+
+    /* Evaluation: L2P plus the near field with the regularised kernel. */
+    const int64_t count = tgt ? nt : n;
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t t = 0; t < count; ++t) {
+        int64_t i = tgt ? tgt[t] : t;
+        int a = ia[i], b = ib[i];
+        double phi[2] = {0.0, 0.0};
+        if (L >= 2) {
+            double cx, cy;
+            box_centre(L, a, b, x0, y0, W, &cx, &cy);
+            oracle_l2p(p, (const double*)(le + (level_offset(L) + (int64_t)b * side + a) * p),
+                       cx, cy, x[i], y[i], phi);
+        }
+        int32_t na[9], nb[9];
+        int nn = oracle_near_list(L, a, b, na, nb);
+        for (int s = 0; s < nn; ++s) {
+            int64_t leaf = (int64_t)nb[s] * side + na[s];
+            for (int64_t q = start[leaf]; q < start[leaf + 1]; ++q) {
+                int64_t j = member[q];
+                if (j == i) continue;
+                pair_phi(x[i], y[i], x[j], y[j], g[j], inv_2s2, 1, &phi[0], &phi[1]);
+            }
+        }
+        u[t] = phi[1] / TWO_PI;
+        v[t] = phi[0] / TWO_PI;
+    }
+
+    if (me_dump) memcpy(me_dump, me, sizeof(cplx) * (size_t)(nbox * p));
+    if (le_dump) memcpy(le_dump, le, sizeof(cplx) * (size_t)(nbox * p));
+    free(need); free(le); free(me); free(member); free(start); free(ia); free(ib);
+    return nbad;
+}
