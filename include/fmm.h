@@ -1,0 +1,154 @@
+/*
+ * fmm.h -- C ABI of libfmm_mi355x.so, a fast multipole evaluation of the
+ * velocity induced by N two-dimensional vortex particles, written for the
+ * AMD Instinct MI355X (gfx950).
+ *
+ * What one evaluation computes (Cruz, Knepley & Barba, "PetFMM"):
+ *   u(x_i) = sum_{j != i} gamma_j K(x_i - x_j)                    (Section 3, eq. 9)
+ * where K is the Gaussian-regularised Biot-Savart kernel of eq. 8,
+ *   K_sigma(x) = (-x2, x1) (1 - exp(-|x|^2 / (2 sigma^2))) / (2 pi |x|^2),
+ * for pairs whose leaves touch, and the singular kernel of eq. 7 (through
+ * its multipole and local expansions) for every other pair -- the kernel
+ * substitution described after eq. 9.  The tree is a uniform quadtree of
+ * depth L over a square domain (Section 2.1); the steps are the upward sweep
+ * (P2M, M2M), the downward sweep (M2L over the interaction list, L2L) and
+ * the evaluation step (L2P plus near-field direct interactions), Section 2.2
+ * and Fig. 2.  Expansions have p complex terms, k = 0 .. p-1 ("truncated
+ * after p terms", Section 2; 16p bytes per box in Table 1).
+ *
+ * Conventions shared by every entry point:
+ *   - Every function returns an fmm_status; no C++ exception crosses the ABI.
+ *   - "Device pointer" means memory on the current HIP device (hipMalloc or a
+ *     PyTorch CUDA/HIP tensor).  The library never frees caller memory.
+ *   - "stream" is a hipStream_t passed as void* (NULL = the default stream).
+ *     fmm_evaluate and fmm_evaluate_batch only enqueue work on it: they never
+ *     synchronise, never allocate device memory and never read device data
+ *     back to the host.
+ *   - A plan is not re-entrant: two evaluations of one plan must not overlap
+ *     (they share the workspace).  Separate plans are independent.
+ *   - Self-interaction and coincident particles contribute exactly 0 (the
+ *     kernel of eq. 8 tends to 0 at the origin).  The boundary is free space.
+ *   - Outputs are written (not accumulated) in the caller's input order.
+ */
+#ifndef FMM_MI355X_H
+#define FMM_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fmm_plan_s* fmm_plan_t;          /* opaque host handle */
+
+typedef enum {
+    FMM_OK = 0,
+    FMM_E_ARG = -1,          /* invalid argument (checked on the host, synchronously) */
+    FMM_E_CAPACITY = -2,     /* n larger than the plan's capacity, or workspace too small */
+    FMM_E_DOMAIN = -3,       /* fmm_get_status: particles outside the explicit domain or NaN */
+    FMM_E_NOMEM = -4,        /* host allocation failed */
+    FMM_E_DEVICE = -5,       /* a HIP runtime call failed */
+    FMM_E_UNSUPPORTED = -6   /* valid but not supported combination (e.g. p too large for FP32) */
+} fmm_status;
+
+typedef enum {
+    FMM_PREC_FP64 = 0,       /* every stage in FP64 */
+    FMM_PREC_MIXED = 1       /* FP32 near field and fine-level M2L; FP64 shifts and coarse M2L */
+} fmm_precision;
+
+/* Problem parameters, following the paper's problem statement: positions
+ * and circulations (eq. 9), one core size sigma for all particles
+ * (Section 7.1), expansion order p and tree level (Section 7.2). */
+typedef struct {
+    int64_t n_max;            /* capacity: largest n passed to fmm_evaluate (>= 0, < 2^31) */
+    double  sigma;            /* Gaussian core size, > 0 (eqs. 5 and 8) */
+    int32_t p;                /* number of expansion terms, 1 <= p <= 32 (<= 22 in mixed mode) */
+    int32_t depth;            /* leaf level L, 0 <= L <= 13; levels 0..L, 4^L leaves */
+    double  x0, y0, width;    /* domain [x0, x0+width]^2; width <= 0 selects the bounding
+                                 square of the particles, recomputed at every evaluation */
+    int32_t precision;        /* an fmm_precision value */
+    int32_t fp32_fine_levels; /* mixed mode: M2L at levels > L - fp32_fine_levels runs in
+                                 FP32 (0 .. L-1); ignored in FP64 mode */
+} fmm_params;
+
+/* Number of bytes of device workspace a plan with these parameters needs.
+ * Host only; touches no device.  Errors: FMM_E_ARG for invalid parameters
+ * or a NULL pointer, FMM_E_UNSUPPORTED for p > 22 in mixed mode. */
+fmm_status fmm_workspace_size(const fmm_params* prm, size_t* bytes);
+
+/* Create a plan.  d_workspace: caller-owned device buffer of at least
+ * fmm_workspace_size() bytes, 256-byte aligned, kept alive and unused by
+ * anyone else until fmm_destroy.  The operator tables (M2M, L2L shifts and
+ * the M2L translation data, derived from the expansions of 1/z) are built on
+ * the host in FP64 and copied into the workspace on `stream`.  *out receives a
+ * host handle.  Errors: FMM_E_ARG (NULL pointers, invalid parameters),
+ * FMM_E_CAPACITY (bytes too small), FMM_E_NOMEM, FMM_E_DEVICE. */
+fmm_status fmm_plan(const fmm_params* prm, void* d_workspace, size_t bytes,
+                    void* stream, fmm_plan_t* out);
+
+/* One full FMM evaluation: tree build (z-order keys, counting sort by leaf,
+ * leaf ranges), P2M, M2M, M2L, L2L, L2P and P2P.
+ *   n                  number of particles, 0 <= n <= n_max
+ *   d_x, d_y, d_gamma  device FP64 arrays [n]: positions and circulations
+ *   d_u, d_v           device FP64 arrays [n]: velocity components (eq. 9),
+ *                      overwritten, in input order
+ * Asynchronous on `stream`.  Particles outside an explicit domain (or with a
+ * NaN coordinate) are clamped into the nearest leaf and counted; read the
+ * count with fmm_get_status.  Errors (synchronous): FMM_E_ARG (NULL plan or
+ * pointers with n > 0), FMM_E_CAPACITY (n > n_max), FMM_E_DEVICE. */
+fmm_status fmm_evaluate(fmm_plan_t plan, int64_t n,
+                        const double* d_x, const double* d_y, const double* d_gamma,
+                        double* d_u, double* d_v, void* stream);
+
+/* Synchronises `stream` and reports the number of particles of the last
+ * evaluation that fell outside the explicit domain or had a NaN coordinate.
+ * Returns FMM_OK if there were none, FMM_E_DOMAIN otherwise. */
+fmm_status fmm_get_status(fmm_plan_t plan, void* stream, int64_t* n_bad);
+
+/* Stage timing.  fmm_set_timing(plan, 1) clears the totals; every later
+ * evaluation records HIP events on its own stream between its stages (no
+ * synchronisation: a ring of 32 event sets is drained as it wraps).
+ * fmm_stats synchronises and writes, for up to n_stages stages in the order
+ * of fmm_stage_name, the average GPU time in milliseconds over every timed
+ * evaluation since fmm_set_timing(plan, 1); *n_written gets the number of
+ * stages written and *n_evaluations (may be NULL) the number of evaluations
+ * averaged.  FMM_E_ARG if nothing was timed. */
+fmm_status fmm_set_timing(fmm_plan_t plan, int32_t on);
+fmm_status fmm_stats(fmm_plan_t plan, double* stage_ms, int32_t n_stages, int32_t* n_written,
+                     int64_t* n_evaluations);
+const char* fmm_stage_name(int32_t stage);
+
+/* Parity inspection (not on the hot path).  Synchronises and copies one of
+ * the plan's device arrays from the last evaluation into host_buf:
+ *   FMM_DUMP_KEYS       uint32 [n]      leaf z-order key of every particle (input order)
+ *   FMM_DUMP_PERM       uint32 [n]      sorted position -> input index
+ *   FMM_DUMP_LEAF_START int32 [4^L+1]   sorted range of every leaf, z-order
+ *   FMM_DUMP_ME         complex128 [Lambda][p] scaled multipole coefficients
+ *   FMM_DUMP_LE         complex128 [Lambda][p] scaled local coefficients
+ *   FMM_DUMP_DOMAIN     double [4]      x0, y0, width, 2^L / width
+ *   FMM_DUMP_ILIST      int32 [Lambda][27]  interaction list of every box as
+ *                       global box ids, -1 padded, as the M2L kernel walks it
+ * Boxes are numbered per level in z-order from (4^l - 1)/3 (the global box
+ * numbering of Section 6.2).  Scaled coefficients: a_k = ahat_k * w_l^k and
+ * b_l = bhat_l / w_l^(l+1), w_l the box width at level l.  If bytes is too
+ * small, *needed is set and FMM_E_CAPACITY returned. */
+enum {
+    FMM_DUMP_KEYS = 0, FMM_DUMP_PERM = 1, FMM_DUMP_LEAF_START = 2,
+    FMM_DUMP_ME = 3, FMM_DUMP_LE = 4, FMM_DUMP_DOMAIN = 5, FMM_DUMP_ILIST = 6
+};
+fmm_status fmm_debug_dump(fmm_plan_t plan, int32_t what, void* host_buf,
+                          size_t bytes, size_t* needed);
+
+/* Release the host handle and its HIP events.  Never frees the workspace or
+ * any other caller memory.  NULL is accepted. */
+fmm_status fmm_destroy(fmm_plan_t plan);
+
+/* Static description of a status code. */
+const char* fmm_status_string(fmm_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMM_MI355X_H */

@@ -46,6 +46,7 @@ def _load():
     u32p = C.POINTER(C.c_uint32)
     i64p = C.POINTER(C.c_int64)
     lib.oracle_init.restype = C.c_int
+    lib.oracle_threads.restype = C.c_int
     lib.oracle_bounding_square.argtypes = [i64, dp, dp, dp]
     lib.oracle_quantize.argtypes = [i64, dp, dp, C.c_int, C.c_double, C.c_double, C.c_double, i32p, i32p]
     lib.oracle_quantize.restype = i64
@@ -75,6 +76,11 @@ def _load():
 
 
 PMAX = 64
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(_load().oracle_threads())
 
 
 def _d(a):

@@ -37,6 +37,9 @@
  */
 #include <complex.h>
 #include <pthread.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -253,6 +256,16 @@ static void powers(cplx d, int q, cplx* out)
 {
     cplx pw = 1.0;
     for (int i = 0; i < q; ++i) { out[i] = pw; pw *= d; }
+}
+
+/* Number of OpenMP threads the parallel loops use. */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* Must be called (single-threaded) before any operator below is used. */

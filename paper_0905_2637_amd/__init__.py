@@ -1,0 +1,215 @@
+"""MI355X 2D vortex-particle FMM: thin ctypes binding over libfmm_mi355x.so.
+
+Every step of an evaluation runs in the library's HIP kernels; this module
+only marshals PyTorch device tensors (memory and streams) across the C ABI
+declared in ``include/fmm.h``.  There is no CPU fallback: if the library is
+not built, or no HIP device is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfmm_mi355x.so")
+
+FMM_OK = 0
+FMM_E_ARG = -1
+FMM_E_CAPACITY = -2
+FMM_E_DOMAIN = -3
+FMM_E_NOMEM = -4
+FMM_E_DEVICE = -5
+FMM_E_UNSUPPORTED = -6
+
+FMM_PREC_FP64 = 0
+FMM_PREC_MIXED = 1
+
+DUMP_KEYS, DUMP_PERM, DUMP_LEAF_START, DUMP_ME, DUMP_LE, DUMP_DOMAIN, DUMP_ILIST = range(7)
+
+EXPORTED = ["fmm_workspace_size", "fmm_plan", "fmm_evaluate", "fmm_get_status", "fmm_set_timing",
+            "fmm_stats", "fmm_stage_name", "fmm_debug_dump", "fmm_destroy", "fmm_status_string"]
+
+
+class FmmParams(C.Structure):
+    _fields_ = [("n_max", C.c_int64), ("sigma", C.c_double), ("p", C.c_int32), ("depth", C.c_int32),
+                ("x0", C.c_double), ("y0", C.c_double), ("width", C.c_double),
+                ("precision", C.c_int32), ("fp32_fine_levels", C.c_int32)]
+
+
+class FmmError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+
+
+_lib = None
+
+
+def load():
+    """Load the built library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run paper_0905_2637_amd.build.build()")
+    lib = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    lib.fmm_workspace_size.argtypes = [C.POINTER(FmmParams), C.POINTER(C.c_size_t)]
+    lib.fmm_plan.argtypes = [C.POINTER(FmmParams), vp, C.c_size_t, vp, C.POINTER(vp)]
+    lib.fmm_evaluate.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp]
+    lib.fmm_get_status.argtypes = [vp, vp, C.POINTER(C.c_int64)]
+    lib.fmm_set_timing.argtypes = [vp, C.c_int32]
+    lib.fmm_stats.argtypes = [vp, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32),
+                              C.POINTER(C.c_int64)]
+    lib.fmm_stage_name.argtypes = [C.c_int32]
+    lib.fmm_stage_name.restype = C.c_char_p
+    lib.fmm_debug_dump.argtypes = [vp, C.c_int32, vp, C.c_size_t, C.POINTER(C.c_size_t)]
+    lib.fmm_destroy.argtypes = [vp]
+    lib.fmm_status_string.argtypes = [C.c_int]
+    lib.fmm_status_string.restype = C.c_char_p
+    for name in ("fmm_workspace_size", "fmm_plan", "fmm_evaluate", "fmm_get_status", "fmm_set_timing",
+                 "fmm_stats", "fmm_debug_dump", "fmm_destroy"):
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def status_string(s: int) -> str:
+    return load().fmm_status_string(int(s)).decode()
+
+
+def make_params(n_max, sigma, p, depth, domain=(0.0, 0.0, 1.0), precision="fp64", fp32_fine_levels=2):
+    if domain is None:
+        x0, y0, w = 0.0, 0.0, 0.0
+    else:
+        x0, y0, w = domain
+    prec = {"fp64": FMM_PREC_FP64, "mixed": FMM_PREC_MIXED}[precision]
+    return FmmParams(int(n_max), float(sigma), int(p), int(depth), float(x0), float(y0), float(w), prec,
+                     int(fp32_fine_levels if precision == "mixed" else 0))
+
+
+def workspace_size(prm: FmmParams) -> int:
+    out = C.c_size_t(0)
+    s = load().fmm_workspace_size(C.byref(prm), C.byref(out))
+    if s != FMM_OK:
+        raise FmmError(s, "fmm_workspace_size")
+    return int(out.value)
+
+
+def _stream_handle(stream=None):
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(st.cuda_stream)
+
+
+class Plan:
+    """One FMM configuration bound to a device workspace.
+
+    Parameters follow the paper's problem statement: core size ``sigma``,
+    expansion order ``p`` and tree ``depth``; ``domain`` = (x0, y0, width) of
+    the square, or None for the particles' bounding square at every call.
+    """
+
+    def __init__(self, n_max, sigma, p, depth, domain=(0.0, 0.0, 1.0), precision="fp64",
+                 fp32_fine_levels=2, device="cuda"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the FMM runs only on the GPU")
+        self.params = make_params(n_max, sigma, p, depth, domain, precision, fp32_fine_levels)
+        self.n_max = int(n_max)
+        self.depth = int(depth)
+        self.p = int(p)
+        self.precision = precision
+        self.device = torch.device(device)
+        nbytes = workspace_size(self.params)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        self._ws_ptr = aligned
+        self._ws_bytes = nbytes
+        handle = C.c_void_p()
+        s = load().fmm_plan(C.byref(self.params), C.c_void_p(aligned), C.c_size_t(nbytes),
+                            _stream_handle(), C.byref(handle))
+        if s != FMM_OK:
+            raise FmmError(s, "fmm_plan")
+        self._h = handle
+        self.last_n = 0
+
+    def evaluate(self, x, y, gamma, u=None, v=None, check=False):
+        """Velocity (u, v) of eq. 9 at every particle; FP64 device tensors."""
+        import torch
+        n = int(x.shape[0])
+        for t in (x, y, gamma):
+            if t.dtype != torch.float64 or t.device.type != "cuda" or not t.is_contiguous() or t.shape[0] != n:
+                raise ValueError("x, y, gamma must be contiguous float64 CUDA tensors of equal length")
+        if u is None:
+            u = torch.empty(n, dtype=torch.float64, device=x.device)
+        if v is None:
+            v = torch.empty(n, dtype=torch.float64, device=x.device)
+        s = load().fmm_evaluate(self._h, n, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                C.c_void_p(gamma.data_ptr()), C.c_void_p(u.data_ptr()),
+                                C.c_void_p(v.data_ptr()), _stream_handle())
+        if s != FMM_OK:
+            raise FmmError(s, "fmm_evaluate")
+        self.last_n = n
+        if check:
+            nbad = self.out_of_domain()
+            if nbad:
+                raise FmmError(FMM_E_DOMAIN, f"fmm_evaluate: {nbad} particles outside the domain")
+        return u, v
+
+    def out_of_domain(self) -> int:
+        out = C.c_int64(0)
+        s = load().fmm_get_status(self._h, _stream_handle(), C.byref(out))
+        if s not in (FMM_OK, FMM_E_DOMAIN):
+            raise FmmError(s, "fmm_get_status")
+        return int(out.value)
+
+    def set_timing(self, on=True):
+        s = load().fmm_set_timing(self._h, 1 if on else 0)
+        if s != FMM_OK:
+            raise FmmError(s, "fmm_set_timing")
+
+    def stats(self) -> dict:
+        """Average GPU milliseconds per stage over the evaluations timed since set_timing(True)."""
+        buf = (C.c_double * 16)()
+        nw = C.c_int32(0)
+        ne = C.c_int64(0)
+        s = load().fmm_stats(self._h, buf, 16, C.byref(nw), C.byref(ne))
+        if s != FMM_OK:
+            raise FmmError(s, "fmm_stats")
+        lib = load()
+        out = {lib.fmm_stage_name(i).decode(): float(buf[i]) for i in range(nw.value)}
+        out["evaluations"] = int(ne.value)
+        return out
+
+    def dump(self, what: int) -> np.ndarray:
+        lib = load()
+        need = C.c_size_t(0)
+        lib.fmm_debug_dump(self._h, what, None, 0, C.byref(need))
+        dtype = {DUMP_KEYS: np.uint32, DUMP_PERM: np.uint32, DUMP_LEAF_START: np.int32,
+                 DUMP_ME: np.complex128, DUMP_LE: np.complex128, DUMP_DOMAIN: np.float64,
+                 DUMP_ILIST: np.int32}[what]
+        arr = np.zeros(max(1, need.value // np.dtype(dtype).itemsize), dtype=dtype)
+        s = lib.fmm_debug_dump(self._h, what, C.c_void_p(arr.ctypes.data), C.c_size_t(arr.nbytes), C.byref(need))
+        if s != FMM_OK:
+            raise FmmError(s, "fmm_debug_dump")
+        arr = arr[: need.value // np.dtype(dtype).itemsize]
+        if what in (DUMP_ME, DUMP_LE):
+            arr = arr.reshape(-1, self.p)
+        if what == DUMP_ILIST:
+            arr = arr.reshape(-1, 27)
+        return arr
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().fmm_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,245 @@
+// fmm_downward.hip -- downward sweep (Section 2.2, Fig. 2): M2L over every
+// box's interaction list, then L2L from each level to the next.
+//
+// Scaled coefficients make the translation operators level-independent.
+// With ahat_k = a_k / w^k (multipole) and bhat_l = b_l w^(l+1) (local), the
+// textbook M2L of the 1/z expansions, tau = (c_source - c_target) / w an
+// integer offset with max(|dx|, |dy|) in {2, 3}, reads
+//   bhat_l = sum_k (-1)^(k+1) C(k+l, k) tau^-(k+l+1) ahat_k .
+// Writing C(k+l, k) = (k+l)! / (k! l!) factors it into a Hankel matrix
+// between two diagonal scalings:
+//   bhat_l = (1/l!) sum_k h_{k+l}(tau) abar_k,
+//   h_n(tau) = n! tau^-(n+1),   abar_k = (-1)^(k+1) ahat_k / k!,
+// so each of the 40 offsets is described by 2p-1 numbers instead of p^2 and
+// the whole table (49 slots of a 7 x 7 grid, FP64 and FP32 copies) stays in
+// the scalar/L1 caches.  The product is dense: every (k, l) pair is one
+// complex multiply-add, 8 p^2 flops per interaction-list pair.
+//
+// Lane mapping: a workgroup of 4 wavefronts covers 16 x 16 target boxes of
+// one level; wavefront c holds the 64 boxes in child position c of their
+// parents, so the 27 interaction-list offsets, and with them the translation
+// data, are uniform across the wavefront.  Each lane owns one target box and
+// keeps all p local coefficients in registers.  Every level from 2 to L is
+// handled by one launch (M2L of different levels are independent); L2L then
+// runs level by level, adding the parent's shifted expansion.
+#include "fmm_device.h"
+
+namespace fmm {
+namespace {
+
+struct LevelBlocks {
+    int nlev;
+    int level[kMaxDepth + 1];
+    int begin[kMaxDepth + 2];
+};
+
+template <int P, typename T>
+__global__ void __launch_bounds__(256)
+k_m2l(LevelBlocks lb, int p, const cd* __restrict__ me, cd* __restrict__ le, const cplx<T>* __restrict__ H,
+      const double* __restrict__ sin_, const double* __restrict__ sout_)
+{
+    const int blk = blockIdx.x;
+    int li = 0;
+    while (li + 1 < lb.nlev && blk >= lb.begin[li + 1]) ++li;
+    const int l = lb.level[li];
+    const int side = 1 << l;
+    const int bl = blk - lb.begin[li];
+    const int bpr = side >= 16 ? side / 16 : 1;
+    const int bx = bl % bpr, by = bl / bpr;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int cx = wave & 1, cy = wave >> 1;
+    const int ta = 2 * (bx * 8 + (lane & 7)) + cx;
+    const int tb = 2 * (by * 8 + (lane >> 3)) + cy;
+    const bool active = ta < side && tb < side;
+    const cd* me_l = me + level_offset(l) * p;
+
+    T bx_[P], by_[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) { bx_[k] = T(0); by_[k] = T(0); }
+
+    for (int o = 0; o < 36; ++o) {
+        int dx, dy;
+        if (!il_offset(cx, cy, o, dx, dy)) continue;
+        const int sa = ta + dx, sb = tb + dy;
+        if (!(active && sa >= 0 && sb >= 0 && sa < side && sb < side)) continue;
+        const cd* src = me_l + int64_t(morton(uint32_t(sa), uint32_t(sb))) * p;
+        T ax[P], ay[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            if (k < p) {
+                const cd t = src[k];
+                const double sc = sin_[k];
+                ax[k] = T(t.x * sc);
+                ay[k] = T(t.y * sc);
+            } else {
+                ax[k] = T(0);
+                ay[k] = T(0);
+            }
+        }
+        const cplx<T>* h = H + ((dy + 3) * kHankelGrid + (dx + 3)) * (2 * P - 1);
+#pragma unroll
+        for (int nn = 0; nn < 2 * P - 1; ++nn) {
+            const cplx<T> hn = h[nn];
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                const int j = nn - k;
+                if (j >= 0 && j < P) cmac(bx_[j], by_[j], hn.x, hn.y, ax[k], ay[k]);
+            }
+        }
+    }
+    if (active) {
+        cd* dst = le + (level_offset(l) + int64_t(morton(uint32_t(ta), uint32_t(tb)))) * p;
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+            if (k < p) {
+                const double sc = sout_[k];
+                dst[k] = cd{double(bx_[k]) * sc, double(by_[k]) * sc};
+            }
+    }
+}
+
+// One thread per parent box at level l-1: shifts its local expansion to its
+// four children at level l and adds it to what M2L wrote there:
+//   bhat^c_m += sum_{j>=m} C(j,m) delta^(j-m) 2^-(m+1) bhat^P_j .
+template <int P>
+__global__ void __launch_bounds__(256)
+k_l2l(int64_t nparent, int p, const cd* __restrict__ parent, cd* __restrict__ child, const cd* __restrict__ Lt)
+{
+    const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (m >= nparent) return;
+    double bx[P], by[P];
+    const cd* src = parent + m * p;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        if (k < p) { const cd t = src[k]; bx[k] = t.x; by[k] = t.y; }
+        else { bx[k] = 0.0; by[k] = 0.0; }
+    }
+    for (int c = 0; c < 4; ++c) {
+        cd* dst = child + (4 * m + c) * p;
+        const cd* Lc = Lt + c * P * P;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            if (k < p) {
+                const cd cur = dst[k];
+                double ax = cur.x, ay = cur.y;
+#pragma unroll
+                for (int j = k; j < P; ++j) {
+                    const cd t = Lc[k * P + j];
+                    cmac(ax, ay, t.x, t.y, bx[j], by[j]);
+                }
+                dst[k] = cd{ax, ay};
+            }
+        }
+    }
+}
+
+// Debug: the interaction list of every box exactly as k_m2l walks it, as
+// global box ids, -1 padded to 27 entries.
+__global__ void __launch_bounds__(256) k_ilist(int L, int32_t* __restrict__ out)
+{
+    const int64_t nbox = level_offset(L + 1);
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= nbox) return;
+    int l = 0;
+    while (level_offset(l + 1) <= g) ++l;
+    const uint32_t k = uint32_t(g - level_offset(l));
+    const int ta = int(morton_x(k)), tb = int(morton_y(k)), side = 1 << l;
+    int32_t* dst = out + g * 27;
+    int cnt = 0;
+    if (l >= 2) {
+        const int cx = ta & 1, cy = tb & 1;
+        for (int o = 0; o < 36; ++o) {
+            int dx, dy;
+            if (!il_offset(cx, cy, o, dx, dy)) continue;
+            const int sa = ta + dx, sb = tb + dy;
+            if (sa < 0 || sb < 0 || sa >= side || sb >= side) continue;
+            dst[cnt++] = int32_t(level_offset(l) + morton(uint32_t(sa), uint32_t(sb)));
+        }
+    }
+    for (; cnt < 27; ++cnt) dst[cnt] = -1;
+}
+
+LevelBlocks make_levels(int lmin, int lmax)
+{
+    LevelBlocks lb{};
+    lb.nlev = 0;
+    int acc = 0;
+    for (int l = lmin; l <= lmax; ++l) {
+        const int side = 1 << l;
+        const int bpr = side >= 16 ? side / 16 : 1;
+        lb.level[lb.nlev] = l;
+        lb.begin[lb.nlev] = acc;
+        acc += bpr * bpr;
+        ++lb.nlev;
+    }
+    lb.begin[lb.nlev] = acc;
+    return lb;
+}
+
+template <int P>
+hipError_t m2l_impl(const Buffers& b, int p, int lmin, int lmax, bool fp32, hipStream_t st)
+{
+    if (lmax < lmin) return hipSuccess;
+    const LevelBlocks lb = make_levels(lmin, lmax);
+    const dim3 grid(unsigned(lb.begin[lb.nlev]));
+    if constexpr (P <= 24) {
+        if (fp32) {
+            hipLaunchKernelGGL((k_m2l<P, float>), grid, dim3(256), 0, st, lb, p, b.me, b.le,
+                               reinterpret_cast<const cplx<float>*>(b.t_h32), b.t_sin, b.t_sout);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_m2l<P, double>), grid, dim3(256), 0, st, lb, p, b.me, b.le,
+                       reinterpret_cast<const cplx<double>*>(b.t_h64), b.t_sin, b.t_sout);
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t l2l_impl(const Buffers& b, int p, int l, hipStream_t st)
+{
+    const int64_t np = int64_t(1) << (2 * (l - 1));
+    hipLaunchKernelGGL(k_l2l<P>, dim3(unsigned((np + 255) / 256)), dim3(256), 0, st, np, p,
+                       b.le + level_offset(l - 1) * p, b.le + level_offset(l) * p, b.t_l2l);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_m2l(const Buffers& b, int P, int p, int lmin, int lmax, bool fp32, hipStream_t st)
+{
+    switch (P) {
+        case 8: return m2l_impl<8>(b, p, lmin, lmax, fp32, st);
+        case 12: return m2l_impl<12>(b, p, lmin, lmax, fp32, st);
+        case 16: return m2l_impl<16>(b, p, lmin, lmax, fp32, st);
+        case 17: return m2l_impl<17>(b, p, lmin, lmax, fp32, st);
+        case 20: return m2l_impl<20>(b, p, lmin, lmax, fp32, st);
+        case 24: return m2l_impl<24>(b, p, lmin, lmax, fp32, st);
+        case 32:   // FP32 translation data would overflow: mixed mode stops at p = 22
+            return fp32 ? hipErrorInvalidValue : m2l_impl<32>(b, p, lmin, lmax, false, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_l2l(const Buffers& b, int P, int p, int l, hipStream_t st)
+{
+    switch (P) {
+        case 8: return l2l_impl<8>(b, p, l, st);
+        case 12: return l2l_impl<12>(b, p, l, st);
+        case 16: return l2l_impl<16>(b, p, l, st);
+        case 17: return l2l_impl<17>(b, p, l, st);
+        case 20: return l2l_impl<20>(b, p, l, st);
+        case 24: return l2l_impl<24>(b, p, l, st);
+        case 32: return l2l_impl<32>(b, p, l, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_ilist(const Buffers& b, int L, hipStream_t st)
+{
+    const int64_t nbox = level_offset(L + 1);
+    hipLaunchKernelGGL(k_ilist, dim3(unsigned((nbox + 255) / 256)), dim3(256), 0, st, L, b.ilist);
+    return hipGetLastError();
+}
+
+}  // namespace fmm

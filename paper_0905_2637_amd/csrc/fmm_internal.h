@@ -1,0 +1,94 @@
+// fmm_internal.h -- types and launcher declarations shared by the library's
+// translation units.  Not part of the public ABI (see include/fmm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fmm {
+
+// Square domain of one evaluation: [x0, x0 + W]^2 and s = 2^L / W, the
+// reciprocal of the leaf width, computed as one correctly rounded division.
+struct Domain {
+    double x0, y0, W, s;
+};
+
+struct cd { double x, y; };   // complex FP64
+struct cf { float x, y; };    // complex FP32
+
+constexpr int kMaxDepth = 13;
+constexpr int kMaxP = 32;
+constexpr int kMaxPMixed = 22;      // FP32 translation data overflows beyond this
+constexpr int kHankelGrid = 7;      // integer M2L offsets (dx, dy) with |dx|, |dy| <= 3
+constexpr int kBBoxBlocks = 256;
+
+// Number of boxes in levels 0 .. l-1, i.e. the global id of the first box of
+// level l (Section 5.3 counts (4^(L+1) - 1)/3 boxes in a full quadtree).
+__host__ __device__ inline int64_t level_offset(int l) { return ((int64_t(1) << (2 * l)) - 1) / 3; }
+
+// Expansion sizes the kernels are compiled for; a plan uses the smallest
+// one >= p and zero-pads coefficients k >= p, which leaves the p-term result
+// unchanged (every operator maps terms < p only from terms < p).
+inline int instantiated_terms(int p)
+{
+    static const int sizes[] = {8, 12, 16, 17, 20, 24, 32};
+    for (int s : sizes)
+        if (p <= s) return s;
+    return -1;
+}
+
+// Device pointers of one plan, all inside the caller's workspace.
+struct Buffers {
+    int64_t* status;       // [0]: particles outside the explicit domain / NaN
+    Domain* dom;
+    double* bbox;          // [4 * kBBoxBlocks] partial bounding boxes
+    int32_t* cnt;          // [nleaf] particles per leaf
+    int32_t* leaf_start;   // [nleaf + 1]
+    int32_t* scan_part;    // [nscan + 1]
+    uint32_t* key;         // [n_max] leaf z-order key per input particle
+    uint32_t* slot;        // [n_max] arrival slot inside the leaf
+    uint32_t* perm_tmp;    // [n_max] leaf-sorted, arbitrary order inside a leaf
+    uint32_t* perm;        // [n_max] sorted position -> input index
+    double* xs;            // [n_max] sorted positions and circulations
+    double* ys;
+    double* gs;
+    float4* pk;            // [n_max] mixed: leaf-relative FP32 (ox, oy, gamma, 0)
+    cd* me;                // [Lambda * p] scaled multipole coefficients
+    cd* le;                // [Lambda * p] scaled local coefficients
+    int32_t* ilist;        // [Lambda * 27] debug: interaction lists
+    cd* t_m2m;             // [4][P][P]
+    cd* t_l2l;             // [4][P][P]
+    cd* t_h64;             // [49][2P-1] M2L translation data, FP64
+    cf* t_h32;             // [49][2P-1] M2L translation data, FP32
+    double* t_sin;         // [P] (-1)^(k+1) / k!
+    double* t_sout;        // [P] 1 / l!
+};
+
+struct Layout {
+    size_t status, dom, bbox, cnt, leaf_start, scan_part, key, slot, perm_tmp, perm;
+    size_t xs, ys, gs, pk, me, le, ilist, t_m2m, t_l2l, t_h64, t_h32, t_sin, t_sout;
+    size_t total;
+};
+
+// Chunk of the leaf-count scan handled by one workgroup.
+constexpr int kScanChunk = 2048;
+
+// ---- launchers (each enqueues on `st` and returns the launch status) -------
+
+hipError_t launch_domain(const Buffers& b, int64_t nleaf, int n, const double* x, const double* y,
+                         int L, bool auto_domain, Domain explicit_dom, hipStream_t st);
+hipError_t launch_tree(const Buffers& b, int n, int L, const double* x, const double* y,
+                       const double* g, bool mixed, hipStream_t st);
+hipError_t launch_p2m(const Buffers& b, int P, int p, int L, hipStream_t st);
+hipError_t launch_m2m(const Buffers& b, int P, int p, int l, hipStream_t st);
+hipError_t launch_m2l(const Buffers& b, int P, int p, int lmin, int lmax, bool fp32, hipStream_t st);
+hipError_t launch_l2l(const Buffers& b, int P, int p, int l, hipStream_t st);
+hipError_t launch_p2p(const Buffers& b, int P, int p, int L, bool has_far, bool mixed, double sigma,
+                      double* u, double* v, hipStream_t st);
+hipError_t launch_ilist(const Buffers& b, int L, hipStream_t st);
+
+// ---- host-side operator tables (FP64, built once per plan) -----------------
+void build_tables(int P, int p, cd* m2m, cd* l2l, cd* h64, cf* h32, double* sin_, double* sout_);
+
+}  // namespace fmm

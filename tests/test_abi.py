@@ -1,0 +1,102 @@
+"""The C ABI library loads on a CPU-only host, exports every declared entry
+point, and validates host-visible arguments synchronously (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_0905_2637_amd as fm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fmm.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fmm_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(fm.LIB_PATH):
+        pytest.fail("libfmm_mi355x.so is not built (run __graft_entry__.build())")
+    return fm.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared_functions()
+    assert "fmm_plan" in names and "fmm_evaluate" in names and "fmm_destroy" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) <= set(fm.EXPORTED)
+
+
+def test_status_strings(lib):
+    for s in (0, -1, -2, -3, -4, -5, -6):
+        assert fm.status_string(s)
+    assert lib.fmm_stage_name(0) == b"tree"
+    assert lib.fmm_stage_name(99) is None
+
+
+def _ws(**kw):
+    base = dict(n_max=1000, sigma=0.01, p=12, depth=4)
+    base.update(kw)
+    prm = fm.make_params(base.pop("n_max"), base.pop("sigma"), base.pop("p"), base.pop("depth"), **base)
+    out = C.c_size_t(0)
+    return fm.load().fmm_workspace_size(C.byref(prm), C.byref(out)), out.value
+
+
+def test_workspace_size_grows_with_problem(lib):
+    s1, b1 = _ws()
+    s2, b2 = _ws(n_max=100000)
+    s3, b3 = _ws(depth=6)
+    s4, b4 = _ws(precision="mixed")
+    assert s1 == s2 == s3 == s4 == fm.FMM_OK
+    assert b2 > b1 and b3 > b1 and b4 > b1
+    # Lambda * p complex values for both ME and LE dominate a deep tree
+    s5, b5 = _ws(depth=10, p=20)
+    assert b5 >= 2 * 16 * 20 * ((4 ** 11 - 1) // 3)
+
+
+@pytest.mark.parametrize("kw,err", [
+    (dict(sigma=0.0), fm.FMM_E_ARG),
+    (dict(sigma=float("nan")), fm.FMM_E_ARG),
+    (dict(p=0), fm.FMM_E_ARG),
+    (dict(p=33), fm.FMM_E_ARG),
+    (dict(depth=-1), fm.FMM_E_ARG),
+    (dict(depth=14), fm.FMM_E_ARG),
+    (dict(n_max=-5), fm.FMM_E_ARG),
+    (dict(n_max=1 << 31), fm.FMM_E_ARG),
+    (dict(p=23, precision="mixed"), fm.FMM_E_UNSUPPORTED),
+    (dict(depth=4, precision="mixed", fp32_fine_levels=4), fm.FMM_E_ARG),
+])
+def test_invalid_parameters_rejected(lib, kw, err):
+    s, _ = _ws(**kw)
+    assert s == err
+
+
+def test_null_arguments_rejected(lib):
+    prm = fm.make_params(100, 0.01, 12, 3)
+    h = C.c_void_p()
+    assert lib.fmm_workspace_size(C.byref(prm), None) == fm.FMM_E_ARG
+    assert lib.fmm_plan(C.byref(prm), None, 1 << 20, None, C.byref(h)) == fm.FMM_E_ARG
+    assert lib.fmm_plan(C.byref(prm), C.c_void_p(256), 1 << 20, None, None) == fm.FMM_E_ARG
+    # misaligned workspace pointer
+    assert lib.fmm_plan(C.byref(prm), C.c_void_p(257), 1 << 30, None, C.byref(h)) == fm.FMM_E_ARG
+    # too small a workspace is reported before any device call
+    assert lib.fmm_plan(C.byref(prm), C.c_void_p(1 << 20), 16, None, C.byref(h)) == fm.FMM_E_CAPACITY
+    assert lib.fmm_evaluate(None, 10, None, None, None, None, None, None) == fm.FMM_E_ARG
+    assert lib.fmm_destroy(None) == fm.FMM_OK
+    nb = C.c_int64(0)
+    assert lib.fmm_get_status(None, None, C.byref(nb)) == fm.FMM_E_ARG
+
+
+def test_no_cpu_fallback_without_device():
+    """The binding refuses to run without a HIP device instead of computing on the CPU."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(RuntimeError):
+        fm.Plan(100, 0.01, 12, 3)
