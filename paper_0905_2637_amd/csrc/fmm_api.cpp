@@ -13,8 +13,8 @@ using namespace fmm;
 
 namespace {
 
-enum Stage { ST_TREE = 0, ST_P2M, ST_M2M, ST_M2L, ST_L2L, ST_P2P, ST_COUNT };
-const char* const kStageNames[ST_COUNT] = {"tree", "p2m", "m2m", "m2l", "l2l", "p2p_l2p"};
+enum Stage { ST_TREE = 0, ST_UP, ST_M2L, ST_DOWN, ST_P2P, ST_COUNT };
+const char* const kStageNames[ST_COUNT] = {"tree", "p2m_m2m", "m2l", "l2l", "p2p_l2p"};
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -286,11 +286,8 @@ fmm_status fmm_evaluate(fmm_plan_t plan, int64_t n, const double* d_x, const dou
     mark(ST_TREE);
     chk(launch_domain(b, nleaf, int(n), d_x, d_y, L, plan->auto_domain, dom, st));
     chk(launch_tree(b, int(n), L, d_x, d_y, d_gamma, plan->mixed, st));
-    mark(ST_P2M);
-    if (far) chk(launch_p2m(b, P, p, L, st));
-    mark(ST_M2M);
-    if (far)
-        for (int l = L - 1; l >= 2; --l) chk(launch_m2m(b, P, p, l, st));
+    mark(ST_UP);
+    if (far) chk(launch_upward(b, P, p, L, st));
     mark(ST_M2L);
     if (far) {
         const int fine = plan->mixed ? prm.fp32_fine_levels : 0;
@@ -298,9 +295,8 @@ fmm_status fmm_evaluate(fmm_plan_t plan, int64_t n, const double* d_x, const dou
         chk(launch_m2l(b, P, p, 2, split - 1, false, st));
         if (fine > 0) chk(launch_m2l(b, P, p, split, L, true, st));
     }
-    mark(ST_L2L);
-    if (far)
-        for (int l = 3; l <= L; ++l) chk(launch_l2l(b, P, p, l, st));
+    mark(ST_DOWN);
+    if (far) chk(launch_downward(b, P, p, L, st));
     mark(ST_P2P);
     chk(launch_p2p(b, P, p, L, far, plan->mixed, prm.sigma, d_u, d_v, st));
     mark(ST_COUNT);

@@ -21,7 +21,7 @@
 // data, are uniform across the wavefront.  Each lane owns one target box and
 // keeps all p local coefficients in registers.  Every level from 2 to L is
 // handled by one launch (M2L of different levels are independent); L2L then
-// runs level by level, adding the parent's shifted expansion.
+// runs down the tree, adding the parent's shifted expansion.
 #include "fmm_device.h"
 
 namespace fmm {
@@ -99,38 +99,50 @@ k_m2l(LevelBlocks lb, int p, const cd* __restrict__ me, cd* __restrict__ le, con
     }
 }
 
-// One thread per parent box at level l-1: shifts its local expansion to its
-// four children at level l and adds it to what M2L wrote there:
+// L2L, subtree-fused like the upward sweep: a workgroup owns one box at level
+// lt (whose local expansion is final) and walks up to three levels down its
+// z-order-contiguous subtree in LDS.  Each child adds the parent's shifted
+// expansion to what M2L wrote for it:
 //   bhat^c_m += sum_{j>=m} C(j,m) delta^(j-m) 2^-(m+1) bhat^P_j .
+constexpr int kDownThreads = 256;
+
 template <int P>
-__global__ void __launch_bounds__(256)
-k_l2l(int64_t nparent, int p, const cd* __restrict__ parent, cd* __restrict__ child, const cd* __restrict__ Lt)
+__global__ void __launch_bounds__(kDownThreads)
+k_downward(int lt, int d, int p, cd* __restrict__ le, const cd* __restrict__ Lt)
 {
-    const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (m >= nparent) return;
-    double bx[P], by[P];
-    const cd* src = parent + m * p;
-#pragma unroll
-    for (int k = 0; k < P; ++k) {
-        if (k < p) { const cd t = src[k]; bx[k] = t.x; by[k] = t.y; }
-        else { bx[k] = 0.0; by[k] = 0.0; }
-    }
-    for (int c = 0; c < 4; ++c) {
-        cd* dst = child + (4 * m + c) * p;
-        const cd* Lc = Lt + c * P * P;
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
+    __shared__ cd sh[85 * P];
+    const int tid = threadIdx.x;
+    const int64_t root = blockIdx.x;
+    const cd* src = le + (level_offset(lt) + root) * p;
+    for (int k = tid; k < P; k += kDownThreads) sh[k] = k < p ? src[k] : cd{0.0, 0.0};
+    __syncthreads();
+    int in_off = 0, out_off = P, n_in = 1;
+    for (int j = lt + 1; j <= lt + d; ++j) {
+        const int n_out = n_in << 2;
+        const int64_t gfirst = root << (2 * (j - lt));
+        cd* g = le + (level_offset(j) + gfirst) * p;
+        for (int e = tid; e < n_out * P; e += kDownThreads) {
+            const int o = e / P, k = e % P;
+            double bx = 0.0, by = 0.0;
             if (k < p) {
-                const cd cur = dst[k];
-                double ax = cur.x, ay = cur.y;
-#pragma unroll
-                for (int j = k; j < P; ++j) {
-                    const cd t = Lc[k * P + j];
-                    cmac(ax, ay, t.x, t.y, bx[j], by[j]);
+                const cd cur = g[int64_t(o) * p + k];
+                bx = cur.x;
+                by = cur.y;
+                const cd* par = sh + in_off + (o >> 2) * P;
+                const cd* Lr = Lt + ((o & 3) * P + k) * P;
+                for (int m = k; m < P; ++m) {
+                    const cd t = Lr[m];
+                    const cd s = par[m];
+                    cmac(bx, by, t.x, t.y, s.x, s.y);
                 }
-                dst[k] = cd{ax, ay};
+                g[int64_t(o) * p + k] = cd{bx, by};
             }
+            sh[out_off + e] = cd{bx, by};
         }
+        __syncthreads();
+        in_off = out_off;
+        out_off += n_out * P;
+        n_in = n_out;
     }
 }
 
@@ -196,11 +208,14 @@ hipError_t m2l_impl(const Buffers& b, int p, int lmin, int lmax, bool fp32, hipS
 }
 
 template <int P>
-hipError_t l2l_impl(const Buffers& b, int p, int l, hipStream_t st)
+hipError_t downward_impl(const Buffers& b, int p, int L, hipStream_t st)
 {
-    const int64_t np = int64_t(1) << (2 * (l - 1));
-    hipLaunchKernelGGL(k_l2l<P>, dim3(unsigned((np + 255) / 256)), dim3(256), 0, st, np, p,
-                       b.le + level_offset(l - 1) * p, b.le + level_offset(l) * p, b.t_l2l);
+    for (int lt = 2; lt < L; lt += 3) {
+        const int d = std::min(3, L - lt);
+        const int64_t nroot = int64_t(1) << (2 * lt);
+        hipLaunchKernelGGL(k_downward<P>, dim3(unsigned(nroot)), dim3(kDownThreads), 0, st, lt, d, p, b.le,
+                           b.t_l2l);
+    }
     return hipGetLastError();
 }
 
@@ -221,16 +236,16 @@ hipError_t launch_m2l(const Buffers& b, int P, int p, int lmin, int lmax, bool f
     }
 }
 
-hipError_t launch_l2l(const Buffers& b, int P, int p, int l, hipStream_t st)
+hipError_t launch_downward(const Buffers& b, int P, int p, int L, hipStream_t st)
 {
     switch (P) {
-        case 8: return l2l_impl<8>(b, p, l, st);
-        case 12: return l2l_impl<12>(b, p, l, st);
-        case 16: return l2l_impl<16>(b, p, l, st);
-        case 17: return l2l_impl<17>(b, p, l, st);
-        case 20: return l2l_impl<20>(b, p, l, st);
-        case 24: return l2l_impl<24>(b, p, l, st);
-        case 32: return l2l_impl<32>(b, p, l, st);
+        case 8: return downward_impl<8>(b, p, L, st);
+        case 12: return downward_impl<12>(b, p, L, st);
+        case 16: return downward_impl<16>(b, p, L, st);
+        case 17: return downward_impl<17>(b, p, L, st);
+        case 20: return downward_impl<20>(b, p, L, st);
+        case 24: return downward_impl<24>(b, p, L, st);
+        case 32: return downward_impl<32>(b, p, L, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -80,10 +80,9 @@ hipError_t launch_domain(const Buffers& b, int64_t nleaf, int n, const double* x
                          int L, bool auto_domain, Domain explicit_dom, hipStream_t st);
 hipError_t launch_tree(const Buffers& b, int n, int L, const double* x, const double* y,
                        const double* g, bool mixed, hipStream_t st);
-hipError_t launch_p2m(const Buffers& b, int P, int p, int L, hipStream_t st);
-hipError_t launch_m2m(const Buffers& b, int P, int p, int l, hipStream_t st);
+hipError_t launch_upward(const Buffers& b, int P, int p, int L, hipStream_t st);     // P2M + M2M
 hipError_t launch_m2l(const Buffers& b, int P, int p, int lmin, int lmax, bool fp32, hipStream_t st);
-hipError_t launch_l2l(const Buffers& b, int P, int p, int l, hipStream_t st);
+hipError_t launch_downward(const Buffers& b, int P, int p, int L, hipStream_t st);   // L2L
 hipError_t launch_p2p(const Buffers& b, int P, int p, int L, bool has_far, bool mixed, double sigma,
                       double* u, double* v, hipStream_t st);
 hipError_t launch_ilist(const Buffers& b, int L, hipStream_t st);

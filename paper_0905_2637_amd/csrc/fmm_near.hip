@@ -15,6 +15,9 @@
 // power of two), and the S partial sums are combined with cross-lane
 // shuffles.  Leaves with more than 64 particles are walked in target chunks.
 //
+// FP64: 1 - exp(-t) and the reciprocal are evaluated inline (polynomial and
+// Newton-refined hardware estimate) instead of library calls.
+//
 // Mixed precision: sources and targets are FP32 offsets from their own leaf
 // centre in leaf-width units; a source's leaf offset (-1, 0 or +1 per axis)
 // is added when it is staged, so every difference is taken between numbers
@@ -32,6 +35,53 @@ constexpr double kInv2Pi = 0.15915494309189533576888376337251;
 constexpr int kStage = 256;   // sources staged per chunk
 
 struct Src64 { double x, y, g; };
+
+// ln 2 split into its nearest double and the remainder (for the reduction
+// t = k ln2 - r done with fused multiply-adds).
+constexpr double kLn2Hi = 0.6931471805599453;
+constexpr double kLn2Lo = 2.3190468138462996e-17;
+constexpr double kLog2E = 1.4426950408889634;
+
+// 1 - exp(-t) for t >= 0 in FP64, within a few ulp for every t.  Reduce
+// t = k ln2 - r with |r| <= ln2/2 (Cody and Waite), take expm1(r) from its
+// Taylor series to r^14 (remainder below 1e-18 relative), and use
+//   1 - e^-t = (1 - 2^-k) - 2^-k expm1(r),
+// which is -expm1(-t) itself for k = 0 and free of cancellation for k >= 1.
+// Beyond t = 37 the result rounds to 1, so t is clamped at 40.
+__device__ __forceinline__ double one_minus_exp_neg(double t)
+{
+    t = fmin(t, 40.0);
+    const double k = rint(t * kLog2E);
+    double r = fma(k, kLn2Hi, -t);
+    r = fma(k, kLn2Lo, r);
+    double q = 1.1470745597729725e-11;      // 1/14!
+    q = fma(q, r, 1.6059043836821613e-10);  // 1/13!
+    q = fma(q, r, 2.08767569878681e-09);
+    q = fma(q, r, 2.505210838544172e-08);
+    q = fma(q, r, 2.755731922398589e-07);
+    q = fma(q, r, 2.7557319223985893e-06);
+    q = fma(q, r, 2.48015873015873e-05);
+    q = fma(q, r, 0.0001984126984126984);
+    q = fma(q, r, 0.001388888888888889);
+    q = fma(q, r, 0.008333333333333333);
+    q = fma(q, r, 0.041666666666666664);
+    q = fma(q, r, 0.16666666666666666);
+    q = fma(q, r, 0.5);
+    q = fma(q, r, 1.0);
+    const double em = q * r;                // expm1(r)
+    const double s = ldexp(1.0, -int(k));   // 2^-k, exact
+    return fma(-s, em, 1.0 - s);
+}
+
+// 1/x for a positive normal x: hardware estimate and two Newton steps.
+__device__ __forceinline__ double recip(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
 
 template <int P, bool MIXED>
 __global__ void __launch_bounds__(64)
@@ -129,9 +179,9 @@ k_p2p_l2p(int L, int p, int has_far, const int32_t* __restrict__ leaf_start, con
                 for (int jj = si; jj < cnt; jj += S) {
                     const Src64 t = src[jj];
                     const double dx = xi - t.x, dy = yi - t.y;
-                    const double r2 = dx * dx + dy * dy;
-                    const double f = -expm1(-r2 * inv2s2);
-                    const double q = r2 > 0.0 ? t.g * f / r2 : 0.0;
+                    const double r2 = fma(dx, dx, dy * dy);
+                    const double f = one_minus_exp_neg(r2 * inv2s2);
+                    const double q = r2 > 0.0 ? t.g * f * recip(r2) : 0.0;
                     acc_x = fma(q, dx, acc_x);
                     acc_y = fma(-q, dy, acc_y);
                 }

@@ -1,5 +1,5 @@
 // fmm_upward.hip -- upward sweep (Section 2.2, Fig. 2): P2M at the leaves and
-// M2M from every level to its parent level.
+// M2M from every level to its parent level, down to level 2.
 //
 // Coefficients are scaled by the box width w_l so that the shift operators do
 // not depend on the level: for a box of centre c,
@@ -9,131 +9,152 @@
 // position c (delta = (c_child - c_parent) / w_parent = (+-1 +- i)/4) reads
 //   ahat^P_k = sum_{m<=k} C(k,m) 2^-m delta^(k-m) ahat^child_m,
 // one of four fixed lower-triangular matrices built on the host.
+//
+// Subtree fusion: z-order makes the descendants of a box at any level one
+// contiguous run of boxes, so a workgroup that owns a box at level lt can
+// build up to three levels below it (64 + 16 + 4 + 1 boxes) in LDS and write
+// every level out for M2L.  The sweep is a handful of launches (levels
+// L -> L-3 -> ... -> 2) instead of one per level, and no level waits for a
+// grid-wide barrier inside a launch.
 #include "fmm_device.h"
 
 namespace fmm {
 namespace {
 
-// One thread per leaf: sum over the leaf's particles with incremental powers.
-template <int P>
-__global__ void __launch_bounds__(256)
-k_p2m(int L, int p, const int32_t* __restrict__ leaf_start, const double* __restrict__ xs,
-      const double* __restrict__ ys, const double* __restrict__ gs, const Domain* __restrict__ dom,
-      cd* __restrict__ me_leaf)
-{
-    const int64_t nleaf = int64_t(1) << (2 * L);
-    const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (m >= nleaf) return;
-    const Domain d = *dom;
-    const double w = ldexp(d.W, -L);
-    const double cx = d.x0 + (double(morton_x(uint32_t(m))) + 0.5) * w;
-    const double cy = d.y0 + (double(morton_y(uint32_t(m))) + 0.5) * w;
-    double ax[P], ay[P];
-#pragma unroll
-    for (int k = 0; k < P; ++k) { ax[k] = 0.0; ay[k] = 0.0; }
-    const int s0 = leaf_start[m], s1 = leaf_start[m + 1];
-    for (int q = s0; q < s1; ++q) {
-        const double zx = (xs[q] - cx) * d.s, zy = (ys[q] - cy) * d.s;
-        double px = gs[q], py = 0.0;
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
-            ax[k] += px;
-            ay[k] += py;
-            const double t = px * zx - py * zy;
-            py = px * zy + py * zx;
-            px = t;
-        }
-    }
-    cd* out = me_leaf + m * p;
-#pragma unroll
-    for (int k = 0; k < P; ++k)
-        if (k < p) out[k] = cd{ax[k], ay[k]};
-}
+constexpr int kUpThreads = 256;
+constexpr int kP2MLanes = 4;            // threads per leaf in P2M
 
-// One thread per parent box at level l: four children at level l+1.
+// Workgroup = one box at level lt = lb - d (d <= 3).  from_particles: the
+// 4^d boxes of level lb are leaves and get their expansion from P2M;
+// otherwise they are read from global memory.
 template <int P>
-__global__ void __launch_bounds__(256)
-k_m2m(int64_t nparent, int p, const cd* __restrict__ child, cd* __restrict__ parent, const cd* __restrict__ M)
+__global__ void __launch_bounds__(kUpThreads)
+k_upward(int L, int lt, int d, int p, int from_particles, const int32_t* __restrict__ leaf_start,
+         const double* __restrict__ xs, const double* __restrict__ ys, const double* __restrict__ gs,
+         const Domain* __restrict__ dom, cd* __restrict__ me, const cd* __restrict__ M)
 {
-    const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (m >= nparent) return;
-    double bx[P], by[P];
+    __shared__ cd sh[85 * P];            // 64 + 16 + 4 + 1 boxes
+    const int tid = threadIdx.x;
+    const int lb = lt + d;
+    const int64_t root = blockIdx.x;     // z-order index at level lt
+    const int nb = 1 << (2 * d);         // boxes at level lb under this root
+    const int64_t first = root << (2 * d);
+
+    // ---- level lb into sh[0 .. nb*P) ----
+    if (from_particles) {
+        const Domain dm = *dom;
+        const double w = ldexp(dm.W, -L);
+        constexpr int KR = (P + kP2MLanes - 1) / kP2MLanes;
+        for (int slot = tid; slot < nb * kP2MLanes; slot += kUpThreads) {
+            const int i = slot / kP2MLanes;
+            const int r = slot % kP2MLanes;           // this thread owns k = r, r+4, r+8, ...
+            const uint32_t leaf = uint32_t(first + i);
+            const double cx = dm.x0 + (double(morton_x(leaf)) + 0.5) * w;
+            const double cy = dm.y0 + (double(morton_y(leaf)) + 0.5) * w;
+            double ax[KR], ay[KR];
 #pragma unroll
-    for (int k = 0; k < P; ++k) { bx[k] = 0.0; by[k] = 0.0; }
-    for (int c = 0; c < 4; ++c) {
-        const cd* src = child + (4 * m + c) * p;
-        double ax[P], ay[P];
+            for (int q = 0; q < KR; ++q) { ax[q] = 0.0; ay[q] = 0.0; }
+            const int s0 = leaf_start[leaf], s1 = leaf_start[leaf + 1];
+            for (int j = s0; j < s1; ++j) {
+                const double zx = (xs[j] - cx) * dm.s, zy = (ys[j] - cy) * dm.s;
+                // z^4 and gamma z^r
+                const double z2x = zx * zx - zy * zy, z2y = 2.0 * zx * zy;
+                const double z4x = z2x * z2x - z2y * z2y, z4y = 2.0 * z2x * z2y;
+                double px = gs[j], py = 0.0;
+                for (int t = 0; t < r; ++t) {
+                    const double nx = px * zx - py * zy;
+                    py = px * zy + py * zx;
+                    px = nx;
+                }
 #pragma unroll
-        for (int k = 0; k < P; ++k) {
-            if (k < p) { const cd t = src[k]; ax[k] = t.x; ay[k] = t.y; }
-            else { ax[k] = 0.0; ay[k] = 0.0; }
-        }
-        const cd* Mc = M + c * P * P;
+                for (int q = 0; q < KR; ++q) {
+                    ax[q] += px;
+                    ay[q] += py;
+                    const double nx = px * z4x - py * z4y;
+                    py = px * z4y + py * z4x;
+                    px = nx;
+                }
+            }
+            cd* dst = me + (level_offset(L) + int64_t(leaf)) * p;
 #pragma unroll
-        for (int k = 0; k < P; ++k) {
-#pragma unroll
-            for (int j = 0; j <= k; ++j) {
-                const cd t = Mc[k * P + j];
-                cmac(bx[k], by[k], t.x, t.y, ax[j], ay[j]);
+            for (int q = 0; q < KR; ++q) {
+                const int k = r + kP2MLanes * q;
+                if (k < P) sh[i * P + k] = cd{k < p ? ax[q] : 0.0, k < p ? ay[q] : 0.0};
+                if (k < p) dst[k] = cd{ax[q], ay[q]};
             }
         }
+    } else {
+        const cd* src = me + (level_offset(lb) + first) * p;
+        for (int e = tid; e < nb * P; e += kUpThreads) {
+            const int i = e / P, k = e % P;
+            sh[e] = k < p ? src[int64_t(i) * p + k] : cd{0.0, 0.0};
+        }
     }
-    cd* dst = parent + m * p;
-#pragma unroll
-    for (int k = 0; k < P; ++k)
-        if (k < p) dst[k] = cd{bx[k], by[k]};
+    __syncthreads();
+
+    // ---- M2M from level j+1 to level j, j = lb-1 .. lt ----
+    int in_off = 0, out_off = nb * P, n_in = nb;
+    for (int j = lb - 1; j >= lt; --j) {
+        const int n_out = n_in >> 2;
+        const int64_t gfirst = root << (2 * (j - lt));
+        cd* gdst = me + (level_offset(j) + gfirst) * p;
+        for (int e = tid; e < n_out * P; e += kUpThreads) {
+            const int o = e / P, k = e % P;
+            double bx = 0.0, by = 0.0;
+            if (k < p) {
+                for (int c = 0; c < 4; ++c) {
+                    const cd* a = sh + in_off + (4 * o + c) * P;
+                    const cd* Mr = M + (c * P + k) * P;
+                    for (int m = 0; m <= k; ++m) {
+                        const cd t = Mr[m];
+                        const cd s = a[m];
+                        cmac(bx, by, t.x, t.y, s.x, s.y);
+                    }
+                }
+                gdst[int64_t(o) * p + k] = cd{bx, by};
+            }
+            sh[out_off + e] = cd{bx, by};
+        }
+        __syncthreads();
+        in_off = out_off;
+        out_off += n_out * P;
+        n_in = n_out;
+    }
 }
 
 template <int P>
-hipError_t p2m_impl(const Buffers& b, int p, int L, hipStream_t st)
+hipError_t upward_impl(const Buffers& b, int p, int L, hipStream_t st)
 {
-    const int64_t nleaf = int64_t(1) << (2 * L);
-    hipLaunchKernelGGL(k_p2m<P>, dim3(unsigned((nleaf + 255) / 256)), dim3(256), 0, st, L, p, b.leaf_start,
-                       b.xs, b.ys, b.gs, b.dom, b.me + level_offset(L) * p);
-    return hipGetLastError();
-}
-
-template <int P>
-hipError_t m2m_impl(const Buffers& b, int p, int l, hipStream_t st)
-{
-    const int64_t np = int64_t(1) << (2 * l);
-    hipLaunchKernelGGL(k_m2m<P>, dim3(unsigned((np + 255) / 256)), dim3(256), 0, st, np, p,
-                       b.me + level_offset(l + 1) * p, b.me + level_offset(l) * p, b.t_m2m);
+    if (L < 2) return hipSuccess;
+    int lb = L;
+    bool leaves = true;
+    for (;;) {
+        const int lt = std::max(2, lb - 3);
+        const int d = lb - lt;
+        const int64_t nroot = int64_t(1) << (2 * lt);
+        hipLaunchKernelGGL(k_upward<P>, dim3(unsigned(nroot)), dim3(kUpThreads), 0, st, L, lt, d, p,
+                           leaves ? 1 : 0, b.leaf_start, b.xs, b.ys, b.gs, b.dom, b.me, b.t_m2m);
+        leaves = false;
+        if (lt == 2) break;
+        lb = lt;
+    }
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_p2m(const Buffers& b, int P, int p, int L, hipStream_t st)
+hipError_t launch_upward(const Buffers& b, int P, int p, int L, hipStream_t st)
 {
-#define CALL_P2M(PP) p2m_impl<PP>(b, p, L, st)
     switch (P) {
-        case 8: return CALL_P2M(8);
-        case 12: return CALL_P2M(12);
-        case 16: return CALL_P2M(16);
-        case 17: return CALL_P2M(17);
-        case 20: return CALL_P2M(20);
-        case 24: return CALL_P2M(24);
-        case 32: return CALL_P2M(32);
+        case 8: return upward_impl<8>(b, p, L, st);
+        case 12: return upward_impl<12>(b, p, L, st);
+        case 16: return upward_impl<16>(b, p, L, st);
+        case 17: return upward_impl<17>(b, p, L, st);
+        case 20: return upward_impl<20>(b, p, L, st);
+        case 24: return upward_impl<24>(b, p, L, st);
+        case 32: return upward_impl<32>(b, p, L, st);
         default: return hipErrorInvalidValue;
     }
-#undef CALL_P2M
-}
-
-hipError_t launch_m2m(const Buffers& b, int P, int p, int l, hipStream_t st)
-{
-#define CALL_M2M(PP) m2m_impl<PP>(b, p, l, st)
-    switch (P) {
-        case 8: return CALL_M2M(8);
-        case 12: return CALL_M2M(12);
-        case 16: return CALL_M2M(16);
-        case 17: return CALL_M2M(17);
-        case 20: return CALL_M2M(20);
-        case 24: return CALL_M2M(24);
-        case 32: return CALL_M2M(32);
-        default: return hipErrorInvalidValue;
-    }
-#undef CALL_M2M
 }
 
 }  // namespace fmm
