@@ -44,28 +44,33 @@ Layout make_layout(const fmm_params& prm)
     const size_t n = size_t(std::max<int64_t>(prm.n_max, 1));
     const size_t nleaf = size_t(1) << (2 * L);
     const size_t nbox = size_t(level_offset(L + 1));
-    const size_t nscan = (nleaf + kScanChunk - 1) / kScanChunk;
+    const size_t nhist = size_t(256) * size_t(radix_blocks(int64_t(n)));
+    const size_t nscan = (nhist + kScanChunk - 1) / kScanChunk;
     const bool mixed = prm.precision == FMM_PREC_MIXED;
     Layout ly{};
     size_t off = 0;
     auto take = [&](size_t bytes) { const size_t o = off; off = align_up(off + bytes); return o; };
-    ly.status = take(64);
+    ly.bad_blk = take(sizeof(int32_t) * size_t(radix_blocks(int64_t(n))));
     ly.dom = take(sizeof(Domain));
     ly.bbox = take(sizeof(double) * 4 * kBBoxBlocks);
-    ly.cnt = take(sizeof(int32_t) * nleaf);
     ly.leaf_start = take(sizeof(int32_t) * (nleaf + 1));
+    ly.hist = take(sizeof(int32_t) * nhist);
+    ly.hist_scan = take(sizeof(int32_t) * (nhist + 1));   // + the grand total
     ly.scan_part = take(sizeof(int32_t) * (nscan + 1));
     ly.key = take(sizeof(uint32_t) * n);
-    ly.slot = take(sizeof(uint32_t) * n);
-    ly.perm_tmp = take(sizeof(uint32_t) * n);
+    ly.ksorted = take(sizeof(uint32_t) * n);
     ly.perm = take(sizeof(uint32_t) * n);
     ly.xs = take(sizeof(double) * n);
     ly.ys = take(sizeof(double) * n);
     ly.gs = take(sizeof(double) * n);
+    ly.ktmp = take(sizeof(uint32_t) * n);
+    ly.itmp = take(sizeof(uint32_t) * n);
+    ly.xt = take(sizeof(double) * n);
+    ly.yt = take(sizeof(double) * n);
+    ly.gt = take(sizeof(double) * n);
     ly.pk = take(mixed ? sizeof(float4) * n : 0);
     ly.me = take(sizeof(cd) * nbox * p);
     ly.le = take(sizeof(cd) * nbox * p);
-    ly.ilist = 0;
     ly.t_m2m = take(sizeof(cd) * 4 * P * P);
     ly.t_l2l = take(sizeof(cd) * 4 * P * P);
     ly.t_h64 = take(sizeof(cd) * kHankelGrid * kHankelGrid * (2 * P - 1));
@@ -176,19 +181,24 @@ fmm_status fmm_plan(const fmm_params* prm, void* d_workspace, size_t bytes, void
     pl->last_n = -1;
     char* base = static_cast<char*>(d_workspace);
     Buffers& b = pl->buf;
-    b.status = reinterpret_cast<int64_t*>(base + ly.status);
+    b.bad_blk = reinterpret_cast<int32_t*>(base + ly.bad_blk);
     b.dom = reinterpret_cast<Domain*>(base + ly.dom);
     b.bbox = reinterpret_cast<double*>(base + ly.bbox);
-    b.cnt = reinterpret_cast<int32_t*>(base + ly.cnt);
     b.leaf_start = reinterpret_cast<int32_t*>(base + ly.leaf_start);
+    b.hist = reinterpret_cast<int32_t*>(base + ly.hist);
+    b.hist_scan = reinterpret_cast<int32_t*>(base + ly.hist_scan);
     b.scan_part = reinterpret_cast<int32_t*>(base + ly.scan_part);
     b.key = reinterpret_cast<uint32_t*>(base + ly.key);
-    b.slot = reinterpret_cast<uint32_t*>(base + ly.slot);
-    b.perm_tmp = reinterpret_cast<uint32_t*>(base + ly.perm_tmp);
+    b.ksorted = reinterpret_cast<uint32_t*>(base + ly.ksorted);
     b.perm = reinterpret_cast<uint32_t*>(base + ly.perm);
     b.xs = reinterpret_cast<double*>(base + ly.xs);
     b.ys = reinterpret_cast<double*>(base + ly.ys);
     b.gs = reinterpret_cast<double*>(base + ly.gs);
+    b.ktmp = reinterpret_cast<uint32_t*>(base + ly.ktmp);
+    b.itmp = reinterpret_cast<uint32_t*>(base + ly.itmp);
+    b.xt = reinterpret_cast<double*>(base + ly.xt);
+    b.yt = reinterpret_cast<double*>(base + ly.yt);
+    b.gt = reinterpret_cast<double*>(base + ly.gt);
     b.pk = pl->mixed ? reinterpret_cast<float4*>(base + ly.pk) : nullptr;
     b.me = reinterpret_cast<cd*>(base + ly.me);
     b.le = reinterpret_cast<cd*>(base + ly.le);
@@ -280,12 +290,11 @@ fmm_status fmm_evaluate(fmm_plan_t plan, int64_t n, const double* d_x, const dou
         dom.W = prm.width;
         dom.s = std::ldexp(1.0, L) / prm.width;
     }
-    const int64_t nleaf = int64_t(1) << (2 * L);
     const bool far = L >= 2;
 
     mark(ST_TREE);
-    chk(launch_domain(b, nleaf, int(n), d_x, d_y, L, plan->auto_domain, dom, st));
-    chk(launch_tree(b, int(n), L, d_x, d_y, d_gamma, plan->mixed, st));
+    if (plan->auto_domain) chk(launch_domain(b, int(n), d_x, d_y, L, st));
+    chk(launch_tree(b, int(n), L, d_x, d_y, d_gamma, !plan->auto_domain, dom, plan->mixed, st));
     mark(ST_UP);
     if (far) chk(launch_upward(b, P, p, L, st));
     mark(ST_M2L);
@@ -310,9 +319,13 @@ fmm_status fmm_get_status(fmm_plan_t plan, void* stream, int64_t* n_bad)
     *n_bad = 0;
     if (plan->last_n <= 0) return FMM_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    int64_t v = 0;
-    if (hipMemcpyAsync(&v, plan->buf.status, sizeof(v), hipMemcpyDeviceToHost, st) != hipSuccess) return FMM_E_DEVICE;
+    const size_t nblk = size_t(radix_blocks(plan->last_n));
+    std::vector<int32_t> per(nblk);
+    if (hipMemcpyAsync(per.data(), plan->buf.bad_blk, nblk * sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess)
+        return FMM_E_DEVICE;
     if (hipStreamSynchronize(st) != hipSuccess) return FMM_E_DEVICE;
+    int64_t v = 0;
+    for (int32_t c : per) v += c;
     *n_bad = v;
     return v == 0 ? FMM_OK : FMM_E_DOMAIN;
 }

@@ -40,19 +40,24 @@ inline int instantiated_terms(int p)
 
 // Device pointers of one plan, all inside the caller's workspace.
 struct Buffers {
-    int64_t* status;       // [0]: particles outside the explicit domain / NaN
+    int32_t* bad_blk;      // [radix blocks] particles outside the explicit domain / NaN, per tile
     Domain* dom;
     double* bbox;          // [4 * kBBoxBlocks] partial bounding boxes
-    int32_t* cnt;          // [nleaf] particles per leaf
     int32_t* leaf_start;   // [nleaf + 1]
-    int32_t* scan_part;    // [nscan + 1]
+    int32_t* hist;         // [256 * radix blocks] digit-major tile histograms
+    int32_t* hist_scan;    // [256 * radix blocks + 1] exclusive scan of hist, then the total
+    int32_t* scan_part;    // [scan chunks + 1]
     uint32_t* key;         // [n_max] leaf z-order key per input particle
-    uint32_t* slot;        // [n_max] arrival slot inside the leaf
-    uint32_t* perm_tmp;    // [n_max] leaf-sorted, arbitrary order inside a leaf
+    uint32_t* ksorted;     // [n_max] sorted keys
     uint32_t* perm;        // [n_max] sorted position -> input index
     double* xs;            // [n_max] sorted positions and circulations
     double* ys;
     double* gs;
+    uint32_t* ktmp;        // [n_max] radix ping-pong partners of the five arrays above
+    uint32_t* itmp;
+    double* xt;
+    double* yt;
+    double* gt;
     float4* pk;            // [n_max] mixed: leaf-relative FP32 (ox, oy, gamma, 0)
     cd* me;                // [Lambda * p] scaled multipole coefficients
     cd* le;                // [Lambda * p] scaled local coefficients
@@ -66,20 +71,24 @@ struct Buffers {
 };
 
 struct Layout {
-    size_t status, dom, bbox, cnt, leaf_start, scan_part, key, slot, perm_tmp, perm;
-    size_t xs, ys, gs, pk, me, le, ilist, t_m2m, t_l2l, t_h64, t_h32, t_sin, t_sout;
+    size_t bad_blk, dom, bbox, leaf_start, hist, hist_scan, scan_part, key, ksorted, perm, xs, ys, gs;
+    size_t ktmp, itmp, xt, yt, gt, pk, me, le, t_m2m, t_l2l, t_h64, t_h32, t_sin, t_sout;
     size_t total;
 };
 
-// Chunk of the leaf-count scan handled by one workgroup.
+// Radix sort geometry (fmm_tree.hip): passes of 8-bit digits over 2L key
+// bits, and workgroup tiles of 4096 keys.
+int radix_passes(int L);
+int64_t radix_blocks(int64_t n);
+
+// Chunk of the histogram scan handled by one workgroup.
 constexpr int kScanChunk = 2048;
 
 // ---- launchers (each enqueues on `st` and returns the launch status) -------
 
-hipError_t launch_domain(const Buffers& b, int64_t nleaf, int n, const double* x, const double* y,
-                         int L, bool auto_domain, Domain explicit_dom, hipStream_t st);
-hipError_t launch_tree(const Buffers& b, int n, int L, const double* x, const double* y,
-                       const double* g, bool mixed, hipStream_t st);
+hipError_t launch_domain(const Buffers& b, int n, const double* x, const double* y, int L, hipStream_t st);
+hipError_t launch_tree(const Buffers& b, int n, int L, const double* x, const double* y, const double* g,
+                       bool explicit_dom, Domain hdom, bool mixed, hipStream_t st);
 hipError_t launch_upward(const Buffers& b, int P, int p, int L, hipStream_t st);     // P2M + M2M
 hipError_t launch_m2l(const Buffers& b, int P, int p, int lmin, int lmax, bool fp32, hipStream_t st);
 hipError_t launch_downward(const Buffers& b, int P, int p, int L, hipStream_t st);   // L2L

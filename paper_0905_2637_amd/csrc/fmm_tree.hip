@@ -1,16 +1,24 @@
-// fmm_tree.hip -- tree build on the GPU: domain, z-order leaf keys, counting
-// sort of the particles by leaf, leaf ranges, sorted particle arrays.
+// fmm_tree.hip -- tree build on the GPU: domain, z-order leaf keys, stable
+// LSD radix sort of the particles by key, leaf ranges, sorted particle arrays.
 //
 // The uniform quadtree of Section 2.1 needs no pointer structure: box (a, b)
 // at level l covers [x0 + a w_l, x0 + (a+1) w_l) x [...], its z-order number
 // (Section 5.1) is the bit interleave of (a, b), and the particles of any box
-// at any level form one contiguous range of the leaf-sorted particle array.
-// Sorting by leaf key is a counting sort with 4^L buckets (a radix sort whose
-// single digit is the whole key): one pass counts, a scan turns counts into
-// leaf starts, one pass scatters.  The atomics of the counting pass fix each
-// particle's slot inside its leaf in arrival order; a final pass re-ranks
-// every leaf's members by input index, so the permutation is the unique stable
-// one (ties in input order) and runs are bit-for-bit reproducible.
+// at any level form one contiguous range of the key-sorted particle array.
+//
+// Sort: least-significant-digit radix sort with 8-bit digits, ceil(2L/8)
+// passes.  Each pass is a per-tile digit histogram, an exclusive scan of the
+// digit-major histogram table, and a stable scatter in which every wavefront
+// ranks its 64 keys by digit with 8 ballots (lanes sharing a digit are found
+// by intersecting the ballots of the digit's bits).  Every pass is stable, so
+// the final permutation is the unique one with ties in input order, and no
+// global atomics are involved: the result is bit-for-bit reproducible.
+//
+// The particle record (key, input index, x, y, gamma) travels with the sort,
+// so every pass reads and writes whole streams (the scatter writes runs of
+// ~16 records per digit and tile) and no random gather follows: the last pass
+// writes the sorted arrays the later stages read, plus the mixed-precision
+// FP32 leaf-relative record.  The first histogram pass computes the keys.
 #include "fmm_device.h"
 
 namespace fmm {
@@ -72,21 +80,8 @@ __global__ void k_bbox_final(int nblk, const double* __restrict__ part, int L, D
     *dom = d;
 }
 
-// Zero the leaf counters and the status word; in explicit-domain mode also
-// store the domain.
-__global__ void __launch_bounds__(256)
-k_reset(int32_t* __restrict__ cnt, int64_t nleaf, int64_t* status, Domain* dom, Domain d, int write_dom)
-{
-    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nleaf; i += stride) cnt[i] = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        status[0] = 0;
-        if (write_dom) *dom = d;
-    }
-}
-
 // ---------------------------------------------------------------------------
-// Keys and counting
+// Keys
 // ---------------------------------------------------------------------------
 
 // Box index along one axis: t = (v - o) * s, two correctly rounded FP64
@@ -104,29 +99,8 @@ __device__ __forceinline__ int axis_box(double v, double o, double s, int side, 
     return b > side - 1 ? side - 1 : b;
 }
 
-__global__ void __launch_bounds__(256)
-k_keys(int n, const double* __restrict__ x, const double* __restrict__ y, const Domain* __restrict__ dom,
-       int L, uint32_t* __restrict__ key, uint32_t* __restrict__ slot, int32_t* __restrict__ cnt,
-       int64_t* __restrict__ status)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    bool bad = false;
-    if (i < n) {
-        const Domain d = *dom;
-        const int side = 1 << L;
-        const int a = axis_box(x[i], d.x0, d.s, side, bad);
-        const int b = axis_box(y[i], d.y0, d.s, side, bad);
-        const uint32_t k = morton(uint32_t(a), uint32_t(b));
-        key[i] = k;
-        slot[i] = uint32_t(atomicAdd(&cnt[k], 1));
-    }
-    const uint64_t m = __ballot(bad);
-    if (m != 0 && __lane_id() == uint32_t(__ffsll((unsigned long long)m) - 1))
-        atomicAdd((unsigned long long*)status, (unsigned long long)__popcll(m));
-}
-
 // ---------------------------------------------------------------------------
-// Exclusive scan of the leaf counts -> leaf_start[0 .. nleaf]
+// Exclusive scan (of the radix histogram table)
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ int wave_incl_scan(int v)
@@ -209,83 +183,323 @@ k_scan_down(int64_t m, int nb, const int32_t* __restrict__ in, const int32_t* __
 }
 
 // ---------------------------------------------------------------------------
-// Scatter, stable re-rank, gather
+// Radix passes
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256)
-k_scatter(int n, const uint32_t* __restrict__ key, const uint32_t* __restrict__ slot,
-          const int32_t* __restrict__ leaf_start, uint32_t* __restrict__ perm_tmp)
+constexpr int kRadixBins = 256;
+constexpr int kRadixThreads = 256;
+constexpr int kRadixRounds = 16;
+constexpr int kRadixTile = kRadixThreads * kRadixRounds;   // keys per workgroup
+
+// First pass: z-order key of every particle (kept in input order for
+// inspection), the out-of-domain count of the tile, and the tile's histogram
+// of the lowest digit.  In explicit-domain mode the domain comes as an
+// argument and block 0 stores it for the later stages.
+__global__ void __launch_bounds__(kRadixThreads)
+k_rhist_keys(int n, const double* __restrict__ x, const double* __restrict__ y, const Domain* ddom,
+             Domain hdom, int explicit_dom, int L, int nblk, uint32_t* __restrict__ key,
+             int32_t* __restrict__ hist, int32_t* __restrict__ bad_blk, Domain* dom_out)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) perm_tmp[leaf_start[key[i]] + slot[i]] = uint32_t(i);
+    __shared__ int h[kRadixBins];
+    __shared__ int nbad;
+    const Domain d = explicit_dom ? hdom : *ddom;
+    if (threadIdx.x == 0) {
+        nbad = 0;
+        if (explicit_dom && blockIdx.x == 0) *dom_out = hdom;
+    }
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int side = 1 << L;
+    const int64_t base = int64_t(blockIdx.x) * kRadixTile;
+    int mybad = 0;
+    for (int r = 0; r < kRadixRounds; ++r) {
+        const int64_t i = base + r * kRadixThreads + threadIdx.x;
+        if (i < n) {
+            bool bad = false;
+            const int a = axis_box(x[i], d.x0, d.s, side, bad);
+            const int b = axis_box(y[i], d.y0, d.s, side, bad);
+            const uint32_t k = morton(uint32_t(a), uint32_t(b));
+            key[i] = k;
+            atomicAdd(&h[k & (kRadixBins - 1)], 1);
+            mybad += bad ? 1 : 0;
+        }
+    }
+    if (mybad) atomicAdd(&nbad, mybad);
+    __syncthreads();
+    hist[int64_t(threadIdx.x) * nblk + blockIdx.x] = h[threadIdx.x];
+    if (threadIdx.x == 0) bad_blk[blockIdx.x] = nbad;
 }
 
-// One thread per leaf-sorted position: its final place inside the leaf is the
-// number of the leaf's members with a smaller input index.  Writes the
-// permutation and the sorted SoA copies; in mixed mode also the FP32
-// leaf-relative record (x - c, y - c) / w_L, gamma, where c is the leaf centre.
-__global__ void __launch_bounds__(256)
-k_gather(int n, int L, const uint32_t* __restrict__ key, const uint32_t* __restrict__ perm_tmp,
-         const int32_t* __restrict__ leaf_start, const double* __restrict__ x, const double* __restrict__ y,
-         const double* __restrict__ g, const Domain* __restrict__ dom, uint32_t* __restrict__ perm,
-         double* __restrict__ xs, double* __restrict__ ys, double* __restrict__ gs, float4* __restrict__ pk)
+// Digit histogram of one tile, written digit-major: hist[d * nblk + block].
+__global__ void __launch_bounds__(kRadixThreads)
+k_rhist(int n, const uint32_t* __restrict__ kin, int shift, int nblk, int32_t* __restrict__ hist)
 {
-    const int pos = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pos >= n) return;
-    const uint32_t j = perm_tmp[pos];
-    const uint32_t k = key[j];
-    const int s0 = leaf_start[k], s1 = leaf_start[k + 1];
-    int rank = 0;
-    for (int q = s0; q < s1; ++q) rank += perm_tmp[q] < j ? 1 : 0;
-    const int d = s0 + rank;
-    const double xv = x[j], yv = y[j], gv = g[j];
-    perm[d] = j;
-    xs[d] = xv;
-    ys[d] = yv;
-    gs[d] = gv;
+    __shared__ int h[kRadixBins];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = int64_t(blockIdx.x) * kRadixTile;
+    for (int r = 0; r < kRadixRounds; ++r) {
+        const int64_t i = base + r * kRadixThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(kin[i] >> shift) & (kRadixBins - 1)], 1);
+    }
+    __syncthreads();
+    hist[int64_t(threadIdx.x) * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+// Where a sorted record goes, and what it carries.
+struct Records {
+    uint32_t* k;
+    uint32_t* idx;
+    double* x;
+    double* y;
+    double* g;
+};
+
+// Stable scatter of one tile, in two phases.
+// Phase A ranks the tile: records are taken in input order, 256 per round;
+// wavefront w ranks its lanes by digit with 8 ballots and the per-wave digit
+// counts order the wavefronts, giving every record its position in the
+// digit-sorted tile.  Phase B stages each array through LDS in that order, so
+// that consecutive threads write consecutive addresses of each digit's run
+// (offs[d * nblk + block] is where the tile's run of digit d starts):
+// whole cache lines instead of scattered 8-byte writes.
+// iin == nullptr means the identity (first pass).  pk != nullptr (last pass,
+// mixed precision) also writes the FP32 leaf-relative record
+// (x - c, y - c) / w_L, gamma of the leaf centre c.
+constexpr int kPerThread = kRadixRounds;
+
+__global__ void __launch_bounds__(kRadixThreads)
+k_rscatter(int n, const uint32_t* __restrict__ kin, const uint32_t* __restrict__ iin,
+           const double* __restrict__ xin, const double* __restrict__ yin, const double* __restrict__ gin,
+           int shift, int nblk, const int32_t* __restrict__ hist, const int32_t* __restrict__ offs, Records out,
+           float4* __restrict__ pk, const Domain* __restrict__ dom, int L)
+{
+    __shared__ int gbase[kRadixBins];      // global start of this tile's run of digit d
+    __shared__ int tstart[kRadixBins];     // start of digit d in the sorted tile
+    __shared__ int run[kRadixBins];        // records of digit d placed so far
+    __shared__ int wcnt[kRadixThreads / 64][kRadixBins];
+    __shared__ uint32_t sk[kRadixTile];
+    __shared__ double sv[kRadixTile];
+    const int tid = threadIdx.x, lane = int(__lane_id()), w = tid >> 6;
+    const int64_t tile = int64_t(blockIdx.x) * kRadixTile;
+    const int tile_n = int(min(int64_t(kRadixTile), int64_t(n) - tile));
+
+    int total;
+    tstart[tid] = block_excl_scan(hist[int64_t(tid) * nblk + blockIdx.x], &total);
+    gbase[tid] = offs[int64_t(tid) * nblk + blockIdx.x];
+    run[tid] = 0;
+#pragma unroll
+    for (int q = 0; q < kRadixThreads / 64; ++q) wcnt[q][tid] = 0;
+    __syncthreads();
+
+    // ---- phase A: load the tile (input order) and rank it ----
+    const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
+    int lpos[kPerThread];
+    uint32_t kr[kPerThread], vr[kPerThread];
+    double xr[kPerThread], yr[kPerThread], gr[kPerThread];
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r) {
+        const int li = r * kRadixThreads + tid;
+        const bool valid = li < tile_n;
+        const int64_t i = tile + li;
+        kr[r] = valid ? kin[i] : 0u;
+        vr[r] = valid ? (iin ? iin[i] : uint32_t(i)) : 0u;
+        xr[r] = valid ? xin[i] : 0.0;
+        yr[r] = valid ? yin[i] : 0.0;
+        gr[r] = valid ? gin[i] : 0.0;
+        const int d = int((kr[r] >> shift) & (kRadixBins - 1));
+        uint64_t same = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1;
+            const uint64_t bb = __ballot(bit);
+            same &= bit ? bb : ~bb;
+        }
+        const int rank = __popcll(same & lt_mask);
+        if (valid && rank == 0) wcnt[w][d] = __popcll(same);
+        __syncthreads();
+        int pos = tstart[d] + run[d] + rank;
+        for (int q = 0; q < w; ++q) pos += wcnt[q][d];
+        lpos[r] = valid ? pos : -1;
+        __syncthreads();
+        int add = 0;
+#pragma unroll
+        for (int q = 0; q < kRadixThreads / 64; ++q) { add += wcnt[q][tid]; wcnt[q][tid] = 0; }
+        run[tid] += add;
+        __syncthreads();
+    }
+
+    // ---- phase B: stage each array in sorted order, write whole runs ----
+    int dst[kPerThread];
+    uint32_t ks_[kPerThread];
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r)
+        if (lpos[r] >= 0) sk[lpos[r]] = kr[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r) {
+        const int j = r * kRadixThreads + tid;
+        dst[r] = -1;
+        if (j < tile_n) {
+            const uint32_t k = sk[j];
+            const int d = int((k >> shift) & (kRadixBins - 1));
+            ks_[r] = k;
+            dst[r] = gbase[d] + (j - tstart[d]);
+            out.k[dst[r]] = k;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r)
+        if (lpos[r] >= 0) sk[lpos[r]] = vr[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r)
+        if (dst[r] >= 0) out.idx[dst[r]] = sk[r * kRadixThreads + tid];
+
+    double xs_[kPerThread], ys_[kPerThread];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r)
+        if (lpos[r] >= 0) sv[lpos[r]] = xr[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r) {
+        xs_[r] = sv[r * kRadixThreads + tid];
+        if (dst[r] >= 0) out.x[dst[r]] = xs_[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r)
+        if (lpos[r] >= 0) sv[lpos[r]] = yr[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r) {
+        ys_[r] = sv[r * kRadixThreads + tid];
+        if (dst[r] >= 0) out.y[dst[r]] = ys_[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r)
+        if (lpos[r] >= 0) sv[lpos[r]] = gr[r];
+    __syncthreads();
+    Domain dm{};
+    double wl = 0.0;
+    if (pk) {
+        dm = *dom;
+        wl = ldexp(dm.W, -L);
+    }
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r) {
+        if (dst[r] < 0) continue;
+        const double gv = sv[r * kRadixThreads + tid];
+        out.g[dst[r]] = gv;
+        if (pk) {
+            const uint32_t k = ks_[r];
+            const double cx = dm.x0 + (double(morton_x(k)) + 0.5) * wl;
+            const double cy = dm.y0 + (double(morton_y(k)) + 0.5) * wl;
+            pk[dst[r]] = make_float4(float((xs_[r] - cx) * dm.s), float((ys_[r] - cy) * dm.s), float(gv), 0.0f);
+        }
+    }
+}
+
+// Depth 0: one leaf, nothing to sort.
+__global__ void __launch_bounds__(256)
+k_copy_one_leaf(int n, const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ g,
+                Records out, float4* __restrict__ pk, const Domain* __restrict__ dom)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double xv = x[i], yv = y[i], gv = g[i];
+    out.k[i] = 0u;
+    out.idx[i] = uint32_t(i);
+    out.x[i] = xv;
+    out.y[i] = yv;
+    out.g[i] = gv;
     if (pk) {
         const Domain dm = *dom;
-        const double w = ldexp(dm.W, -L);
-        const double cx = dm.x0 + (double(morton_x(k)) + 0.5) * w;
-        const double cy = dm.y0 + (double(morton_y(k)) + 0.5) * w;
-        pk[d] = make_float4(float((xv - cx) * dm.s), float((yv - cy) * dm.s), float(gv), 0.0f);
+        const double cx = dm.x0 + 0.5 * dm.W, cy = dm.y0 + 0.5 * dm.W;
+        pk[i] = make_float4(float((xv - cx) * dm.s), float((yv - cy) * dm.s), float(gv), 0.0f);
     }
+}
+
+// leaf_start[k] = first sorted position whose key is >= k, for k = 0 .. nleaf:
+// position i owns the leaves in (key[i-1], key[i]].
+__global__ void __launch_bounds__(256)
+k_bounds(int n, int64_t nleaf, const uint32_t* __restrict__ ks, int32_t* __restrict__ leaf_start)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    const int64_t lo = i == 0 ? 0 : int64_t(ks[i - 1]) + 1;
+    const int64_t hi = i == n ? nleaf : int64_t(ks[i]);
+    for (int64_t k = lo; k <= hi; ++k) leaf_start[k] = i;
 }
 
 inline unsigned blocks_for(int64_t n, int bs) { return unsigned((n + bs - 1) / bs); }
 
 }  // namespace
 
-hipError_t launch_domain(const Buffers& b, int64_t nleaf, int n, const double* x, const double* y,
-                         int L, bool auto_domain, Domain explicit_dom, hipStream_t st)
+hipError_t launch_domain(const Buffers& b, int n, const double* x, const double* y, int L, hipStream_t st)
 {
-    if (auto_domain) {
-        hipLaunchKernelGGL(k_bbox_partial, dim3(kBBoxBlocks), dim3(256), 0, st, n, x, y, b.bbox);
-        hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, kBBoxBlocks, b.bbox, L, b.dom);
-    }
-    const unsigned nb = unsigned(std::min<int64_t>(4096, std::max<int64_t>(1, (nleaf + 255) / 256)));
-    hipLaunchKernelGGL(k_reset, dim3(nb), dim3(256), 0, st, b.cnt, nleaf, b.status, b.dom, explicit_dom,
-                       auto_domain ? 0 : 1);
+    hipLaunchKernelGGL(k_bbox_partial, dim3(kBBoxBlocks), dim3(256), 0, st, n, x, y, b.bbox);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, kBBoxBlocks, b.bbox, L, b.dom);
     return hipGetLastError();
 }
 
+int radix_passes(int L) { return (2 * L + 7) / 8; }
+
+int64_t radix_blocks(int64_t n) { return (n + kRadixTile - 1) / kRadixTile; }
+
+namespace {
+
+// Exclusive scan of hist[0..m) into out[0..m], out[m] = total.
+void scan_table(const Buffers& b, int64_t m, hipStream_t st)
+{
+    const int nsb = int((m + kScanChunk - 1) / kScanChunk);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nsb), dim3(256), 0, st, m, b.hist, b.scan_part);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, st, nsb, b.scan_part);
+    hipLaunchKernelGGL(k_scan_down, dim3(nsb), dim3(256), 0, st, m, nsb, b.hist, b.scan_part, b.hist_scan);
+}
+
+}  // namespace
+
 hipError_t launch_tree(const Buffers& b, int n, int L, const double* x, const double* y, const double* g,
-                       bool mixed, hipStream_t st)
+                       bool explicit_dom, Domain hdom, bool mixed, hipStream_t st)
 {
     const int64_t nleaf = int64_t(1) << (2 * L);
-    if (n > 0)
-        hipLaunchKernelGGL(k_keys, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, x, y, b.dom, L, b.key,
-                           b.slot, b.cnt, b.status);
-    const int nb = int((nleaf + kScanChunk - 1) / kScanChunk);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(256), 0, st, nleaf, b.cnt, b.scan_part);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, st, nb, b.scan_part);
-    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(256), 0, st, nleaf, nb, b.cnt, b.scan_part, b.leaf_start);
-    if (n > 0) {
-        hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, b.key, b.slot,
-                           b.leaf_start, b.perm_tmp);
-        hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, L, b.key, b.perm_tmp,
-                           b.leaf_start, x, y, g, b.dom, b.perm, b.xs, b.ys, b.gs, mixed ? b.pk : nullptr);
+    const int nblk = int(radix_blocks(n));
+    const int64_t m = int64_t(kRadixBins) * nblk;
+    float4* pk = mixed ? b.pk : nullptr;
+    const Records fin{b.ksorted, b.perm, b.xs, b.ys, b.gs};
+    const Records tmp{b.ktmp, b.itmp, b.xt, b.yt, b.gt};
+    hipLaunchKernelGGL(k_rhist_keys, dim3(nblk), dim3(kRadixThreads), 0, st, n, x, y, b.dom, hdom,
+                       explicit_dom ? 1 : 0, L, nblk, b.key, b.hist, b.bad_blk, b.dom);
+    const int npass = radix_passes(L);
+    if (npass == 0) {
+        hipLaunchKernelGGL(k_copy_one_leaf, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, x, y, g, fin, pk, b.dom);
+    } else {
+        // the last pass writes the final arrays, the others alternate with tmp
+        const uint32_t* kin = b.key;
+        const uint32_t* iin = nullptr;
+        const double *xin = x, *yin = y, *gin = g;
+        for (int pass = 0; pass < npass; ++pass) {
+            const Records& out = ((npass - 1 - pass) & 1) ? tmp : fin;
+            const int shift = 8 * pass;
+            if (pass > 0)
+                hipLaunchKernelGGL(k_rhist, dim3(nblk), dim3(kRadixThreads), 0, st, n, kin, shift, nblk, b.hist);
+            scan_table(b, m, st);
+            const bool last = pass == npass - 1;
+            hipLaunchKernelGGL(k_rscatter, dim3(nblk), dim3(kRadixThreads), 0, st, n, kin, iin, xin, yin, gin,
+                               shift, nblk, b.hist, b.hist_scan, out, last ? pk : nullptr, b.dom, L);
+            kin = out.k;
+            iin = out.idx;
+            xin = out.x;
+            yin = out.y;
+            gin = out.g;
+        }
     }
+    hipLaunchKernelGGL(k_bounds, dim3(blocks_for(int64_t(n) + 1, 256)), dim3(256), 0, st, n, nleaf, b.ksorted,
+                       b.leaf_start);
     return hipGetLastError();
 }
 
