@@ -39,7 +39,6 @@ fmm_status validate(const fmm_params* prm)
 Layout make_layout(const fmm_params& prm)
 {
     const int P = instantiated_terms(prm.p);
-    const int p = prm.p;
     const int L = prm.depth;
     const size_t n = size_t(std::max<int64_t>(prm.n_max, 1));
     const size_t nleaf = size_t(1) << (2 * L);
@@ -69,8 +68,14 @@ Layout make_layout(const fmm_params& prm)
     ly.yt = take(sizeof(double) * n);
     ly.gt = take(sizeof(double) * n);
     ly.pk = take(mixed ? sizeof(float4) * n : 0);
-    ly.me = take(sizeof(cd) * nbox * p);
-    ly.le = take(sizeof(cd) * nbox * p);
+    // expansions: P >= p coefficients per box (the compiled size), zero-padded
+    ly.me = take(sizeof(cd) * nbox * P);
+    ly.le = take(sizeof(cd) * nbox * P);
+    {
+        const size_t nsplit = size_t(level_offset(m2l_split_level(L) + 1));
+        ly.le_part[0] = take(sizeof(cd) * nsplit * P);
+        ly.le_part[1] = take(sizeof(cd) * nsplit * P);
+    }
     ly.t_m2m = take(sizeof(cd) * 4 * P * P);
     ly.t_l2l = take(sizeof(cd) * 4 * P * P);
     ly.t_h64 = take(sizeof(cd) * kHankelGrid * kHankelGrid * (2 * P - 1));
@@ -202,6 +207,8 @@ fmm_status fmm_plan(const fmm_params* prm, void* d_workspace, size_t bytes, void
     b.pk = pl->mixed ? reinterpret_cast<float4*>(base + ly.pk) : nullptr;
     b.me = reinterpret_cast<cd*>(base + ly.me);
     b.le = reinterpret_cast<cd*>(base + ly.le);
+    b.le_part[0] = reinterpret_cast<cd*>(base + ly.le_part[0]);
+    b.le_part[1] = reinterpret_cast<cd*>(base + ly.le_part[1]);
     b.ilist = nullptr;
     b.t_m2m = reinterpret_cast<cd*>(base + ly.t_m2m);
     b.t_l2l = reinterpret_cast<cd*>(base + ly.t_l2l);
@@ -298,14 +305,23 @@ fmm_status fmm_evaluate(fmm_plan_t plan, int64_t n, const double* d_x, const dou
     mark(ST_UP);
     if (far) chk(launch_upward(b, P, p, L, st));
     mark(ST_M2L);
+    const int sl = m2l_split_level(L);
     if (far) {
+        // levels [2, f32) in FP64, [f32, L] in FP32; levels <= sl with the
+        // interaction list split over three wavefronts
         const int fine = plan->mixed ? prm.fp32_fine_levels : 0;
-        const int split = std::max(2, L - fine + 1);   // first FP32 level
-        chk(launch_m2l(b, P, p, 2, split - 1, false, st));
-        if (fine > 0) chk(launch_m2l(b, P, p, split, L, true, st));
+        const int f32 = std::max(2, L - fine + 1);
+        auto run = [&](int lo, int hi, bool fp32) {
+            if (hi < lo) return;
+            const int mid = std::min(hi, sl);
+            if (lo <= mid) chk(launch_m2l(b, P, p, lo, mid, fp32, 3, st));
+            if (std::max(lo, mid + 1) <= hi) chk(launch_m2l(b, P, p, std::max(lo, mid + 1), hi, fp32, 1, st));
+        };
+        run(2, f32 - 1, false);
+        run(f32, L, true);
     }
     mark(ST_DOWN);
-    if (far) chk(launch_downward(b, P, p, L, st));
+    if (far) chk(launch_downward(b, P, p, L, sl, st));
     mark(ST_P2P);
     chk(launch_p2p(b, P, p, L, far, plan->mixed, prm.sigma, d_u, d_v, st));
     mark(ST_COUNT);
@@ -361,7 +377,7 @@ fmm_status fmm_debug_dump(fmm_plan_t plan, int32_t what, void* host_buf, size_t 
         case FMM_DUMP_KEYS: src = plan->buf.key; sz = n * sizeof(uint32_t); break;
         case FMM_DUMP_PERM: src = plan->buf.perm; sz = n * sizeof(uint32_t); break;
         case FMM_DUMP_LEAF_START: src = plan->buf.leaf_start; sz = (nleaf + 1) * sizeof(int32_t); break;
-        case FMM_DUMP_ME: src = plan->buf.me; sz = nbox * prm.p * sizeof(cd); break;
+        case FMM_DUMP_ME: src = plan->buf.me; sz = nbox * prm.p * sizeof(cd); break;   // stored with stride P
         case FMM_DUMP_LE: src = plan->buf.le; sz = nbox * prm.p * sizeof(cd); break;
         case FMM_DUMP_DOMAIN: src = plan->buf.dom; sz = sizeof(Domain); break;
         case FMM_DUMP_ILIST: sz = nbox * 27 * sizeof(int32_t); break;
@@ -381,6 +397,17 @@ fmm_status fmm_debug_dump(fmm_plan_t plan, int32_t what, void* host_buf, size_t 
         if (e == hipSuccess) e = hipMemcpy(host_buf, d, sz, hipMemcpyDeviceToHost);
         hipFree(d);
         return e == hipSuccess ? FMM_OK : FMM_E_DEVICE;
+    }
+    if (what == FMM_DUMP_ME || what == FMM_DUMP_LE) {
+        // device rows hold P coefficients; hand out the first p of each
+        const int P = plan->P, p = prm.p;
+        std::vector<cd> tmp(nbox * size_t(P));
+        if (hipMemcpy(tmp.data(), src, tmp.size() * sizeof(cd), hipMemcpyDeviceToHost) != hipSuccess)
+            return FMM_E_DEVICE;
+        cd* out = static_cast<cd*>(host_buf);
+        for (size_t bx = 0; bx < nbox; ++bx)
+            for (int k = 0; k < p; ++k) out[bx * p + k] = tmp[bx * P + k];
+        return FMM_OK;
     }
     if (hipMemcpy(host_buf, src, sz, hipMemcpyDeviceToHost) != hipSuccess) return FMM_E_DEVICE;
     return FMM_OK;

@@ -33,11 +33,19 @@ struct LevelBlocks {
     int begin[kMaxDepth + 2];
 };
 
+// gridDim.y = G in {1, 3}: workgroup row g takes every G-th member of the
+// interaction list and writes its partial sum to out[g] (out[0] = le).
+struct M2LOut {
+    cd* out[3];
+};
+
 template <int P, typename T>
 __global__ void __launch_bounds__(256)
-k_m2l(LevelBlocks lb, int p, const cd* __restrict__ me, cd* __restrict__ le, const cplx<T>* __restrict__ H,
+k_m2l(LevelBlocks lb, const cd* __restrict__ me, M2LOut dst_, const cplx<T>* __restrict__ H,
       const double* __restrict__ sin_, const double* __restrict__ sout_)
 {
+    const int G = gridDim.y, g = blockIdx.y;
+    cd* __restrict__ le = dst_.out[g];
     const int blk = blockIdx.x;
     int li = 0;
     while (li + 1 < lb.nlev && blk >= lb.begin[li + 1]) ++li;
@@ -52,30 +60,27 @@ k_m2l(LevelBlocks lb, int p, const cd* __restrict__ me, cd* __restrict__ le, con
     const int ta = 2 * (bx * 8 + (lane & 7)) + cx;
     const int tb = 2 * (by * 8 + (lane >> 3)) + cy;
     const bool active = ta < side && tb < side;
-    const cd* me_l = me + level_offset(l) * p;
+    const cd* me_l = me + level_offset(l) * P;
 
     T bx_[P], by_[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) { bx_[k] = T(0); by_[k] = T(0); }
 
+    int member = 0;
     for (int o = 0; o < 36; ++o) {
         int dx, dy;
         if (!il_offset(cx, cy, o, dx, dy)) continue;
+        if ((member++) % G != g) continue;
         const int sa = ta + dx, sb = tb + dy;
         if (!(active && sa >= 0 && sb >= 0 && sa < side && sb < side)) continue;
-        const cd* src = me_l + int64_t(morton(uint32_t(sa), uint32_t(sb))) * p;
+        const cd* src = me_l + int64_t(morton(uint32_t(sa), uint32_t(sb))) * P;
         T ax[P], ay[P];
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            if (k < p) {
-                const cd t = src[k];
-                const double sc = sin_[k];
-                ax[k] = T(t.x * sc);
-                ay[k] = T(t.y * sc);
-            } else {
-                ax[k] = T(0);
-                ay[k] = T(0);
-            }
+            const cd t = src[k];
+            const double sc = sin_[k];      // zero for k >= p
+            ax[k] = T(t.x * sc);
+            ay[k] = T(t.y * sc);
         }
         const cplx<T>* h = H + ((dy + 3) * kHankelGrid + (dx + 3)) * (2 * P - 1);
 #pragma unroll
@@ -89,13 +94,12 @@ k_m2l(LevelBlocks lb, int p, const cd* __restrict__ me, cd* __restrict__ le, con
         }
     }
     if (active) {
-        cd* dst = le + (level_offset(l) + int64_t(morton(uint32_t(ta), uint32_t(tb)))) * p;
+        cd* dst = le + (level_offset(l) + int64_t(morton(uint32_t(ta), uint32_t(tb)))) * P;
 #pragma unroll
-        for (int k = 0; k < P; ++k)
-            if (k < p) {
-                const double sc = sout_[k];
-                dst[k] = cd{double(bx_[k]) * sc, double(by_[k]) * sc};
-            }
+        for (int k = 0; k < P; ++k) {
+            const double sc = sout_[k];         // zero for k >= p
+            dst[k] = cd{double(bx_[k]) * sc, double(by_[k]) * sc};
+        }
     }
 }
 
@@ -106,37 +110,52 @@ k_m2l(LevelBlocks lb, int p, const cd* __restrict__ me, cd* __restrict__ le, con
 //   bhat^c_m += sum_{j>=m} C(j,m) delta^(j-m) 2^-(m+1) bhat^P_j .
 constexpr int kDownThreads = 256;
 
+// part[0], part[1]: partial M2L sums of levels <= split_level (M2L ran with
+// its interaction list split over three wavefronts there); they are added
+// to le when a level's M2L result is first read.
 template <int P>
 __global__ void __launch_bounds__(kDownThreads)
-k_downward(int lt, int d, int p, cd* __restrict__ le, const cd* __restrict__ Lt)
+k_downward(int lt, int d, cd* __restrict__ le, const cd* __restrict__ Lt, const cd* __restrict__ part0,
+           const cd* __restrict__ part1, int split_level)
 {
     __shared__ cd sh[85 * P];
+    __shared__ cd sL[4 * P * P];
     const int tid = threadIdx.x;
+    for (int e = tid; e < 4 * P * P; e += kDownThreads) sL[e] = Lt[e];
     const int64_t root = blockIdx.x;
-    const cd* src = le + (level_offset(lt) + root) * p;
-    for (int k = tid; k < P; k += kDownThreads) sh[k] = k < p ? src[k] : cd{0.0, 0.0};
+    const int64_t ri = (level_offset(lt) + root) * P;
+    for (int k = tid; k < P; k += kDownThreads) {
+        cd v = le[ri + k];
+        if (lt == 2 && lt <= split_level) {   // level 2 gets no L2L: finish its M2L sum here
+            v.x += part0[ri + k].x + part1[ri + k].x;
+            v.y += part0[ri + k].y + part1[ri + k].y;
+            le[ri + k] = v;
+        }
+        sh[k] = v;
+    }
     __syncthreads();
     int in_off = 0, out_off = P, n_in = 1;
     for (int j = lt + 1; j <= lt + d; ++j) {
         const int n_out = n_in << 2;
         const int64_t gfirst = root << (2 * (j - lt));
-        cd* g = le + (level_offset(j) + gfirst) * p;
+        cd* g = le + (level_offset(j) + gfirst) * P;
         for (int e = tid; e < n_out * P; e += kDownThreads) {
             const int o = e / P, k = e % P;
-            double bx = 0.0, by = 0.0;
-            if (k < p) {
-                const cd cur = g[int64_t(o) * p + k];
-                bx = cur.x;
-                by = cur.y;
-                const cd* par = sh + in_off + (o >> 2) * P;
-                const cd* Lr = Lt + ((o & 3) * P + k) * P;
-                for (int m = k; m < P; ++m) {
-                    const cd t = Lr[m];
-                    const cd s = par[m];
-                    cmac(bx, by, t.x, t.y, s.x, s.y);
-                }
-                g[int64_t(o) * p + k] = cd{bx, by};
+            const cd cur = g[e];
+            double bx = cur.x, by = cur.y;
+            if (j <= split_level) {
+                const int64_t pi = (level_offset(j) + gfirst) * P + e;
+                bx += part0[pi].x + part1[pi].x;
+                by += part0[pi].y + part1[pi].y;
             }
+            const cd* par = sh + in_off + (o >> 2) * P;
+            const cd* Lr = sL + ((o & 3) * P + k) * P;     // rows k >= p are zero
+            for (int m = k; m < P; ++m) {
+                const cd t = Lr[m];
+                const cd s = par[m];
+                cmac(bx, by, t.x, t.y, s.x, s.y);
+            }
+            g[e] = cd{bx, by};
             sh[out_off + e] = cd{bx, by};
         }
         __syncthreads();
@@ -190,62 +209,63 @@ LevelBlocks make_levels(int lmin, int lmax)
 }
 
 template <int P>
-hipError_t m2l_impl(const Buffers& b, int p, int lmin, int lmax, bool fp32, hipStream_t st)
+hipError_t m2l_impl(const Buffers& b, int p, int lmin, int lmax, bool fp32, int groups, hipStream_t st)
 {
     if (lmax < lmin) return hipSuccess;
     const LevelBlocks lb = make_levels(lmin, lmax);
-    const dim3 grid(unsigned(lb.begin[lb.nlev]));
+    const dim3 grid(unsigned(lb.begin[lb.nlev]), unsigned(groups));
+    const M2LOut out{{b.le, b.le_part[0], b.le_part[1]}};
     if constexpr (P <= 24) {
         if (fp32) {
-            hipLaunchKernelGGL((k_m2l<P, float>), grid, dim3(256), 0, st, lb, p, b.me, b.le,
+            hipLaunchKernelGGL((k_m2l<P, float>), grid, dim3(256), 0, st, lb, b.me, out,
                                reinterpret_cast<const cplx<float>*>(b.t_h32), b.t_sin, b.t_sout);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((k_m2l<P, double>), grid, dim3(256), 0, st, lb, p, b.me, b.le,
+    hipLaunchKernelGGL((k_m2l<P, double>), grid, dim3(256), 0, st, lb, b.me, out,
                        reinterpret_cast<const cplx<double>*>(b.t_h64), b.t_sin, b.t_sout);
     return hipGetLastError();
 }
 
 template <int P>
-hipError_t downward_impl(const Buffers& b, int p, int L, hipStream_t st)
+hipError_t downward_impl(const Buffers& b, int p, int L, int split_level, hipStream_t st)
 {
     for (int lt = 2; lt < L; lt += 3) {
         const int d = std::min(3, L - lt);
         const int64_t nroot = int64_t(1) << (2 * lt);
-        hipLaunchKernelGGL(k_downward<P>, dim3(unsigned(nroot)), dim3(kDownThreads), 0, st, lt, d, p, b.le,
-                           b.t_l2l);
+        hipLaunchKernelGGL(k_downward<P>, dim3(unsigned(nroot)), dim3(kDownThreads), 0, st, lt, d, b.le,
+                           b.t_l2l, b.le_part[0], b.le_part[1], split_level);
     }
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_m2l(const Buffers& b, int P, int p, int lmin, int lmax, bool fp32, hipStream_t st)
+hipError_t launch_m2l(const Buffers& b, int P, int p, int lmin, int lmax, bool fp32, int groups, hipStream_t st)
 {
     switch (P) {
-        case 8: return m2l_impl<8>(b, p, lmin, lmax, fp32, st);
-        case 12: return m2l_impl<12>(b, p, lmin, lmax, fp32, st);
-        case 16: return m2l_impl<16>(b, p, lmin, lmax, fp32, st);
-        case 17: return m2l_impl<17>(b, p, lmin, lmax, fp32, st);
-        case 20: return m2l_impl<20>(b, p, lmin, lmax, fp32, st);
-        case 24: return m2l_impl<24>(b, p, lmin, lmax, fp32, st);
+        case 8: return m2l_impl<8>(b, p, lmin, lmax, fp32, groups, st);
+        case 12: return m2l_impl<12>(b, p, lmin, lmax, fp32, groups, st);
+        case 16: return m2l_impl<16>(b, p, lmin, lmax, fp32, groups, st);
+        case 17: return m2l_impl<17>(b, p, lmin, lmax, fp32, groups, st);
+        case 20: return m2l_impl<20>(b, p, lmin, lmax, fp32, groups, st);
+        case 24: return m2l_impl<24>(b, p, lmin, lmax, fp32, groups, st);
         case 32:   // FP32 translation data would overflow: mixed mode stops at p = 22
-            return fp32 ? hipErrorInvalidValue : m2l_impl<32>(b, p, lmin, lmax, false, st);
+            return fp32 ? hipErrorInvalidValue : m2l_impl<32>(b, p, lmin, lmax, false, groups, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_downward(const Buffers& b, int P, int p, int L, hipStream_t st)
+hipError_t launch_downward(const Buffers& b, int P, int p, int L, int split_level, hipStream_t st)
 {
     switch (P) {
-        case 8: return downward_impl<8>(b, p, L, st);
-        case 12: return downward_impl<12>(b, p, L, st);
-        case 16: return downward_impl<16>(b, p, L, st);
-        case 17: return downward_impl<17>(b, p, L, st);
-        case 20: return downward_impl<20>(b, p, L, st);
-        case 24: return downward_impl<24>(b, p, L, st);
-        case 32: return downward_impl<32>(b, p, L, st);
+        case 8: return downward_impl<8>(b, p, L, split_level, st);
+        case 12: return downward_impl<12>(b, p, L, split_level, st);
+        case 16: return downward_impl<16>(b, p, L, split_level, st);
+        case 17: return downward_impl<17>(b, p, L, split_level, st);
+        case 20: return downward_impl<20>(b, p, L, split_level, st);
+        case 24: return downward_impl<24>(b, p, L, split_level, st);
+        case 32: return downward_impl<32>(b, p, L, split_level, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -61,6 +61,7 @@ struct Buffers {
     float4* pk;            // [n_max] mixed: leaf-relative FP32 (ox, oy, gamma, 0)
     cd* me;                // [Lambda * p] scaled multipole coefficients
     cd* le;                // [Lambda * p] scaled local coefficients
+    cd* le_part[2];        // [Lambda(split level) * p] partial M2L sums of the split levels
     int32_t* ilist;        // [Lambda * 27] debug: interaction lists
     cd* t_m2m;             // [4][P][P]
     cd* t_l2l;             // [4][P][P]
@@ -72,7 +73,7 @@ struct Buffers {
 
 struct Layout {
     size_t bad_blk, dom, bbox, leaf_start, hist, hist_scan, scan_part, key, ksorted, perm, xs, ys, gs;
-    size_t ktmp, itmp, xt, yt, gt, pk, me, le, t_m2m, t_l2l, t_h64, t_h32, t_sin, t_sout;
+    size_t ktmp, itmp, xt, yt, gt, pk, me, le, le_part[2], t_m2m, t_l2l, t_h64, t_h32, t_sin, t_sout;
     size_t total;
 };
 
@@ -90,8 +91,14 @@ hipError_t launch_domain(const Buffers& b, int n, const double* x, const double*
 hipError_t launch_tree(const Buffers& b, int n, int L, const double* x, const double* y, const double* g,
                        bool explicit_dom, Domain hdom, bool mixed, hipStream_t st);
 hipError_t launch_upward(const Buffers& b, int P, int p, int L, hipStream_t st);     // P2M + M2M
-hipError_t launch_m2l(const Buffers& b, int P, int p, int lmin, int lmax, bool fp32, hipStream_t st);
-hipError_t launch_downward(const Buffers& b, int P, int p, int L, hipStream_t st);   // L2L
+hipError_t launch_m2l(const Buffers& b, int P, int p, int lmin, int lmax, bool fp32, int groups, hipStream_t st);
+hipError_t launch_downward(const Buffers& b, int P, int p, int L, int split_level, hipStream_t st);   // L2L
+
+// Levels up to this one run M2L with the interaction list split over three
+// wavefronts (more parallelism where a level has few boxes); deeper levels
+// have enough boxes to fill the GPU with one wavefront per 64 boxes.
+constexpr int kM2LSplitMaxLevel = 8;
+inline int m2l_split_level(int L) { return L <= 2 ? 1 : (L < kM2LSplitMaxLevel ? L : kM2LSplitMaxLevel); }
 hipError_t launch_p2p(const Buffers& b, int P, int p, int L, bool has_far, bool mixed, double sigma,
                       double* u, double* v, hipStream_t st);
 hipError_t launch_ilist(const Buffers& b, int L, hipStream_t st);

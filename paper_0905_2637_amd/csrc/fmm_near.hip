@@ -8,12 +8,19 @@
 // / (z_i - z_j) over near pairs, plus L2P; u = Im(phi)/(2 pi), v = Re(phi)/(2 pi).
 // Zero-distance pairs contribute nothing.
 //
-// One wavefront per target leaf.  The sources of the 3 x 3 neighbourhood are
-// staged through LDS in chunks with coalesced loads (each leaf's particles are
-// contiguous in the sorted arrays); each lane owns one target and one of S
-// interleaved slices of the staged sources, S = 64 / (targets rounded up to a
-// power of two), and the S partial sums are combined with cross-lane
-// shuffles.  Leaves with more than 64 particles are walked in target chunks.
+// Work decomposition: one wavefront per target leaf, four independent
+// wavefronts (four z-order-consecutive leaves) per workgroup so that a CU
+// holds more wavefronts than its workgroup slots would allow with one-wave
+// groups; each wavefront stages into its own LDS region and synchronises only
+// with itself.  The particles of the
+// 3 x 3 neighbourhood are staged through LDS in chunks with coalesced loads
+// (each leaf's particles are contiguous in the sorted arrays), padded with
+// inert sources (zero circulation, far away) to a multiple of the slice
+// count so every lane runs the same, unrollable trip count.  Register
+// blocking: a lane owns R targets and one of S interleaved slices of the
+// staged sources, so each LDS read feeds R pair interactions; the S partial
+// sums are combined with cross-lane shuffles.  Leaves with more than 64
+// particles are walked in target chunks of 64.
 //
 // FP64: 1 - exp(-t) and the reciprocal are evaluated inline (polynomial and
 // Newton-refined hardware estimate) instead of library calls.
@@ -32,7 +39,6 @@ namespace fmm {
 namespace {
 
 constexpr double kInv2Pi = 0.15915494309189533576888376337251;
-constexpr int kStage = 256;   // sources staged per chunk
 
 struct Src64 { double x, y, g; };
 
@@ -54,9 +60,8 @@ __device__ __forceinline__ double one_minus_exp_neg(double t)
     const double k = rint(t * kLog2E);
     double r = fma(k, kLn2Hi, -t);
     r = fma(k, kLn2Lo, r);
-    double q = 1.1470745597729725e-11;      // 1/14!
-    q = fma(q, r, 1.6059043836821613e-10);  // 1/13!
-    q = fma(q, r, 2.08767569878681e-09);
+    double q = 1.6059043836821613e-10;      // 1/13!
+    q = fma(q, r, 2.08767569878681e-09);    // 1/12!
     q = fma(q, r, 2.505210838544172e-08);
     q = fma(q, r, 2.755731922398589e-07);
     q = fma(q, r, 2.7557319223985893e-06);
@@ -73,33 +78,220 @@ __device__ __forceinline__ double one_minus_exp_neg(double t)
     return fma(-s, em, 1.0 - s);
 }
 
-// 1/x for a positive normal x: hardware estimate and two Newton steps.
+// 1/x for a positive normal x: hardware estimate (about 2^-26 relative)
+// and one Newton step, which squares the relative error.
 __device__ __forceinline__ double recip(double x)
 {
-    double y = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, y, 1.0);
-    y = fma(y, e, y);
-    e = fma(-x, y, 1.0);
+    const double y = __builtin_amdgcn_rcp(x);
+    const double e = fma(-x, y, 1.0);
     return fma(y, e, y);
 }
 
+constexpr int kNearStage = 256;    // staged sources per chunk and wavefront
+constexpr int kNearWaves = 4;      // independent wavefronts per workgroup
+
+// Orders one wavefront's LDS writes before its later LDS reads (the lanes of
+// a wavefront run in lockstep, so this is all the synchronisation needed).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+constexpr int kR = 4;              // most targets per lane
+
+// Sum over staged sources jb + si, jb = 0, S, 2S, ... < padded for the R
+// targets a lane owns.  FP32 leaf-relative form: coordinates in leaf widths,
+// exp(-t) = 2^(-t log2 e) with c2 = w^2 log2(e) / (2 sigma^2).
+template <int R>
+__device__ __forceinline__ void p2p_f32(const float4* __restrict__ src, int padded, int S, int si, float c2,
+                                        const float* ox, const float* oy, float* fx, float* fy)
+{
+#pragma unroll 2
+    for (int jb = 0; jb < padded; jb += S) {
+        const float4 t = src[jb + si];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float dx = ox[r] - t.x, dy = oy[r] - t.y;
+            const float r2 = fmaf(dx, dx, dy * dy);
+            const float e = __builtin_amdgcn_exp2f(-r2 * c2);
+            const float q2 = fmaf(-t.z, e, t.z) * __builtin_amdgcn_rcpf(fmaxf(r2, 1e-30f));
+            fx[r] = fmaf(q2, dx, fx[r]);
+            fy[r] = fmaf(-q2, dy, fy[r]);
+        }
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void p2p_f64(const Src64* __restrict__ src, int padded, int S, int si, double inv2s2,
+                                        const double* x, const double* y, double* ax, double* ay)
+{
+    for (int jb = 0; jb < padded; jb += S) {
+        const Src64 t = src[jb + si];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double dx = x[r] - t.x, dy = y[r] - t.y;
+            const double r2 = fma(dx, dx, dy * dy);
+            const double f = one_minus_exp_neg(r2 * inv2s2);        // 0 at r2 = 0
+            const double q2 = t.g * f * recip(fmax(r2, 1e-300));
+            ax[r] = fma(q2, dx, ax[r]);
+            ay[r] = fma(-q2, dy, ay[r]);
+        }
+    }
+}
+
+// What one wavefront needs to know about its target leaf.
+struct LeafCtx {
+    uint32_t m;                 // z-order index of the target leaf
+    int s0, nt;                 // its sorted particle range
+    int nbeg[9], npre[10];      // the 3 x 3 neighbourhood: starts and running counts
+    int lgT;                    // log2 of the targets per chunk
+    double cx, cy, s, inv2s2;   // leaf centre, 1/leaf width, 1/(2 sigma^2)
+    float c2;                   // w^2 log2(e) / (2 sigma^2)
+};
+
+// All targets of one leaf, in chunks of T = 2^lgT; R targets per lane.
+template <int P, bool MIXED, int R>
+__device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* stage_raw, int has_far,
+                                              const double* __restrict__ xs, const double* __restrict__ ys,
+                                              const double* __restrict__ gs, const float4* __restrict__ pk,
+                                              const uint32_t* __restrict__ perm, const cd* __restrict__ le_leaf,
+                                              double* __restrict__ u, double* __restrict__ v)
+{
+    using Stage = typename std::conditional<MIXED, float4, Src64>::type;
+    Stage* src = static_cast<Stage*>(stage_raw);
+    constexpr int lgR = R == 4 ? 2 : (R == 2 ? 1 : 0);
+    const int T = 1 << c.lgT;
+    const int lgTG = c.lgT - lgR;
+    const int TG = 1 << lgTG;        // target groups
+    const int S = 64 >> lgTG;        // source slices
+    const int tg = lane & (TG - 1);
+    const int si = lane >> lgTG;
+    const int tot = c.npre[9];
+
+    for (int c0 = 0; c0 < c.nt; c0 += T) {
+        double xi[R], yi[R], ax[R], ay[R];
+        float oxi[R], oyi[R], fx[R], fy[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = c0 + tg + TG * r;
+            xi[r] = 0.0; yi[r] = 0.0; oxi[r] = 0.f; oyi[r] = 0.f;
+            ax[r] = 0.0; ay[r] = 0.0; fx[r] = 0.f; fy[r] = 0.f;
+            if (i < c.nt) {
+                if constexpr (MIXED) {
+                    const float4 t = pk[c.s0 + i];
+                    oxi[r] = t.x; oyi[r] = t.y;
+                } else {
+                    xi[r] = xs[c.s0 + i]; yi[r] = ys[c.s0 + i];
+                }
+            }
+        }
+
+        for (int base = 0; base < tot; base += kNearStage) {
+            const int cnt = min(kNearStage, tot - base);
+            const int padded = ((cnt + S - 1) / S) * S;
+            wave_sync();
+            // stage the neighbourhood's particles leaf by leaf (uniform loop)
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                const int lo = max(c.npre[q], base), hi = min(c.npre[q + 1], base + cnt);
+                for (int k = lo + lane; k < hi; k += 64) {
+                    const int j = c.nbeg[q] + (k - c.npre[q]);
+                    if constexpr (MIXED) {
+                        float4 t = pk[j];
+                        t.x += float((q % 3) - 1);   // source relative to the target leaf centre
+                        t.y += float((q / 3) - 1);
+                        src[k - base] = t;
+                    } else {
+                        src[k - base] = Src64{xs[j], ys[j], gs[j]};
+                    }
+                }
+            }
+            for (int k = cnt + lane; k < padded; k += 64) {
+                // inert padding: no circulation, far from every target
+                if constexpr (MIXED) src[k] = make_float4(1.0e4f, 1.0e4f, 0.0f, 0.0f);
+                else src[k] = Src64{1.0e10, 1.0e10, 0.0};
+            }
+            wave_sync();
+            if constexpr (MIXED) p2p_f32<R>(src, padded, S, si, c.c2, oxi, oyi, fx, fy);
+            else p2p_f64<R>(src, padded, S, si, c.inv2s2, xi, yi, ax, ay);
+        }
+
+        // combine the S slices: every lane of a target group ends with the sums
+        double sx[R], sy[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if constexpr (MIXED) {
+                float vx = fx[r], vy = fy[r];
+                for (int off = TG; off < 64; off <<= 1) {
+                    vx += __shfl_xor(vx, off, 64);
+                    vy += __shfl_xor(vy, off, 64);
+                }
+                sx[r] = double(vx) * c.s;   // leaf units -> physical: 1/(w z) = s/z
+                sy[r] = double(vy) * c.s;
+            } else {
+                double vx = ax[r], vy = ay[r];
+                for (int off = TG; off < 64; off <<= 1) {
+                    vx += __shfl_xor(vx, off, 64);
+                    vy += __shfl_xor(vy, off, 64);
+                }
+                sx[r] = vx;
+                sy[r] = vy;
+            }
+        }
+        // slice lane si < R finishes target r = si: far field and output
+        const int i = c0 + tg + TG * si;
+        if (si < R && i < c.nt) {
+            double accx = sx[0], accy = sy[0];
+#pragma unroll
+            for (int r = 1; r < R; ++r)
+                if (si == r) { accx = sx[r]; accy = sy[r]; }
+            const int ip = c.s0 + i;
+            if (has_far) {
+                const double zx = (xs[ip] - c.cx) * c.s, zy = (ys[ip] - c.cy) * c.s;
+                const cd* bl = le_leaf + int64_t(c.m) * P;      // terms >= p are zero
+                double hx = 0.0, hy = 0.0;
+#pragma unroll
+                for (int k = P - 1; k >= 0; --k) {
+                    const cd t = bl[k];
+                    const double nx = hx * zx - hy * zy + t.x;
+                    hy = hx * zy + hy * zx + t.y;
+                    hx = nx;
+                }
+                accx += hx * c.s;
+                accy += hy * c.s;
+            }
+            const uint32_t o = perm[ip];
+            u[o] = accy * kInv2Pi;
+            v[o] = accx * kInv2Pi;
+        }
+    }
+}
+
 template <int P, bool MIXED>
-__global__ void __launch_bounds__(64)
-k_p2p_l2p(int L, int p, int has_far, const int32_t* __restrict__ leaf_start, const double* __restrict__ xs,
+__global__ void __launch_bounds__(64 * kNearWaves)
+k_p2p_l2p(int L, int has_far, const int32_t* __restrict__ leaf_start, const double* __restrict__ xs,
           const double* __restrict__ ys, const double* __restrict__ gs, const float4* __restrict__ pk,
           const uint32_t* __restrict__ perm, const cd* __restrict__ le_leaf, const Domain* __restrict__ dom,
           double inv2s2, double* __restrict__ u, double* __restrict__ v)
 {
-    const uint32_t m = blockIdx.x;
-    const int s0 = leaf_start[m];
-    const int nt = leaf_start[m + 1] - s0;
-    if (nt == 0) return;
-    const int a = int(morton_x(m)), b = int(morton_y(m)), side = 1 << L;
-    const int lane = threadIdx.x;
+    using Stage = typename std::conditional<MIXED, float4, Src64>::type;
+    __shared__ Stage stage_all[kNearWaves][kNearStage];
+
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t nleaf = int64_t(1) << (2 * L);
+    const int64_t mm = int64_t(blockIdx.x) * kNearWaves + wv;
+    if (mm >= nleaf) return;
+    LeafCtx c;
+    c.m = uint32_t(mm);
+    c.s0 = leaf_start[c.m];
+    c.nt = leaf_start[c.m + 1] - c.s0;
+    if (c.nt == 0) return;
+    const int a = int(morton_x(c.m)), b = int(morton_y(c.m)), side = 1 << L;
+    const int lane = threadIdx.x & 63;
 
     // the 3 x 3 neighbourhood, row by row; clipped leaves are empty
-    int nbeg[9], npre[10];
-    npre[0] = 0;
+    c.npre[0] = 0;
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
         const int na = a + (q % 3) - 1, nb = b + (q / 3) - 1;
@@ -109,122 +301,30 @@ k_p2p_l2p(int L, int p, int has_far, const int32_t* __restrict__ leaf_start, con
             beg = leaf_start[sm];
             cnt = leaf_start[sm + 1] - beg;
         }
-        nbeg[q] = beg;
-        npre[q + 1] = npre[q] + cnt;
+        c.nbeg[q] = beg;
+        c.npre[q + 1] = c.npre[q] + cnt;
     }
-    const int tot = npre[9];
-
-    const int lgT = nt >= 64 ? 6 : (nt <= 1 ? 0 : 32 - __clz(nt - 1));
-    const int T = 1 << lgT;
-    const int S = 64 >> lgT;
-    const int ti = lane & (T - 1);
-    const int si = lane >> lgT;
+    c.lgT = c.nt >= 64 ? 6 : (c.nt <= 1 ? 0 : 32 - __clz(c.nt - 1));
 
     const Domain d = *dom;
     const double w = ldexp(d.W, -L);
-    const double cx = d.x0 + (double(a) + 0.5) * w;
-    const double cy = d.y0 + (double(b) + 0.5) * w;
+    c.cx = d.x0 + (double(a) + 0.5) * w;
+    c.cy = d.y0 + (double(b) + 0.5) * w;
+    c.s = d.s;
+    c.inv2s2 = inv2s2;
     // leaf-width units: |z|^2 / (2 sigma^2) = |zhat|^2 w^2 / (2 sigma^2), and
     // exp(-t) = 2^(-t log2(e)); w = 1/s
-    const float c2 = float(inv2s2 * 1.4426950408889634074 / (d.s * d.s));
+    c.c2 = float(inv2s2 * 1.4426950408889634074 / (d.s * d.s));
 
-    using Stage = typename std::conditional<MIXED, float4, Src64>::type;
-    __shared__ Stage src[kStage];
-
-    for (int c0 = 0; c0 < nt; c0 += T) {
-        const int i = c0 + ti;
-        const bool act = i < nt;
-        const int ip = s0 + (act ? i : 0);
-        double xi = 0.0, yi = 0.0;
-        float oxi = 0.f, oyi = 0.f;
-        if constexpr (MIXED) {
-            const float4 t = pk[ip];
-            oxi = t.x; oyi = t.y;
-        } else {
-            xi = xs[ip]; yi = ys[ip];
-        }
-        double acc_x = 0.0, acc_y = 0.0;
-        float facc_x = 0.f, facc_y = 0.f;
-
-        for (int base = 0; base < tot; base += kStage) {
-            const int cnt = min(kStage, tot - base);
-            __syncthreads();
-            for (int k = lane; k < cnt; k += 64) {
-                const int idx = base + k;
-                int q = 0;
-#pragma unroll
-                for (int r = 1; r < 9; ++r) q += (idx >= npre[r]) ? 1 : 0;
-                const int j = nbeg[q] + (idx - npre[q]);
-                if constexpr (MIXED) {
-                    float4 t = pk[j];
-                    t.x += float((q % 3) - 1);   // source position relative to the target leaf centre
-                    t.y += float((q / 3) - 1);
-                    src[k] = t;
-                } else {
-                    src[k] = Src64{xs[j], ys[j], gs[j]};
-                }
-            }
-            __syncthreads();
-            if constexpr (MIXED) {
-                for (int jj = si; jj < cnt; jj += S) {
-                    const float4 t = src[jj];
-                    const float dx = oxi - t.x, dy = oyi - t.y;
-                    const float r2 = fmaf(dx, dx, dy * dy);
-                    const float e = __builtin_amdgcn_exp2f(-r2 * c2);
-                    const float q = t.z * (1.0f - e) * __builtin_amdgcn_rcpf(fmaxf(r2, 1e-30f));
-                    facc_x = fmaf(q, dx, facc_x);
-                    facc_y = fmaf(-q, dy, facc_y);
-                }
-            } else {
-                for (int jj = si; jj < cnt; jj += S) {
-                    const Src64 t = src[jj];
-                    const double dx = xi - t.x, dy = yi - t.y;
-                    const double r2 = fma(dx, dx, dy * dy);
-                    const double f = one_minus_exp_neg(r2 * inv2s2);
-                    const double q = r2 > 0.0 ? t.g * f * recip(r2) : 0.0;
-                    acc_x = fma(q, dx, acc_x);
-                    acc_y = fma(-q, dy, acc_y);
-                }
-            }
-        }
-
-        if constexpr (MIXED) {
-            for (int off = T; off < 64; off <<= 1) {
-                facc_x += __shfl_xor(facc_x, off, 64);
-                facc_y += __shfl_xor(facc_y, off, 64);
-            }
-            acc_x = double(facc_x) * d.s;   // leaf units -> physical: 1/(w z) = s/z
-            acc_y = double(facc_y) * d.s;
-        } else {
-            for (int off = T; off < 64; off <<= 1) {
-                acc_x += __shfl_xor(acc_x, off, 64);
-                acc_y += __shfl_xor(acc_y, off, 64);
-            }
-        }
-
-        if (si == 0 && act) {
-            if (has_far) {
-                if constexpr (MIXED) { xi = xs[ip]; yi = ys[ip]; }
-                const double zx = (xi - cx) * d.s, zy = (yi - cy) * d.s;
-                const cd* bl = le_leaf + int64_t(m) * p;
-                double fx = 0.0, fy = 0.0;
-#pragma unroll
-                for (int k = P - 1; k >= 0; --k) {
-                    if (k < p) {
-                        const cd t = bl[k];
-                        const double nx = fx * zx - fy * zy + t.x;
-                        fy = fx * zy + fy * zx + t.y;
-                        fx = nx;
-                    }
-                }
-                acc_x += fx * d.s;
-                acc_y += fy * d.s;
-            }
-            const uint32_t o = perm[ip];
-            u[o] = acc_y * kInv2Pi;
-            v[o] = acc_x * kInv2Pi;
-        }
-    }
+    // register blocking pays once a chunk is full; sparse leaves keep one
+    // target per lane (fewer slices to combine)
+    void* st = stage_all[wv];
+    if (c.lgT == 6)
+        leaf_near_far<P, MIXED, 4>(c, lane, st, has_far, xs, ys, gs, pk, perm, le_leaf, u, v);
+    else if (c.lgT == 5)
+        leaf_near_far<P, MIXED, 2>(c, lane, st, has_far, xs, ys, gs, pk, perm, le_leaf, u, v);
+    else
+        leaf_near_far<P, MIXED, 1>(c, lane, st, has_far, xs, ys, gs, pk, perm, le_leaf, u, v);
 }
 
 template <int P>
@@ -233,12 +333,13 @@ hipError_t p2p_impl(const Buffers& b, int p, int L, bool has_far, bool mixed, do
 {
     const int64_t nleaf = int64_t(1) << (2 * L);
     const double inv2s2 = 1.0 / (2.0 * sigma * sigma);
-    const cd* le_leaf = b.le + level_offset(L) * p;
+    const cd* le_leaf = b.le + level_offset(L) * P;
+    const unsigned ngrp = unsigned((nleaf + kNearWaves - 1) / kNearWaves);
     if (mixed) {
-        hipLaunchKernelGGL((k_p2p_l2p<P, true>), dim3(unsigned(nleaf)), dim3(64), 0, st, L, p, has_far ? 1 : 0,
+        hipLaunchKernelGGL((k_p2p_l2p<P, true>), dim3(ngrp), dim3(64 * kNearWaves), 0, st, L, has_far ? 1 : 0,
                            b.leaf_start, b.xs, b.ys, b.gs, b.pk, b.perm, le_leaf, b.dom, inv2s2, u, v);
     } else {
-        hipLaunchKernelGGL((k_p2p_l2p<P, false>), dim3(unsigned(nleaf)), dim3(64), 0, st, L, p, has_far ? 1 : 0,
+        hipLaunchKernelGGL((k_p2p_l2p<P, false>), dim3(ngrp), dim3(64 * kNearWaves), 0, st, L, has_far ? 1 : 0,
                            b.leaf_start, b.xs, b.ys, b.gs, b.pk, b.perm, le_leaf, b.dom, inv2s2, u, v);
     }
     return hipGetLastError();

@@ -3,8 +3,9 @@
 // powers and factorials accumulated in long double before rounding).
 //
 //   M2M  (child position c, delta = (+-1 +- i)/4, see fmm_upward.hip)
-//        M[c][k][j] = C(k,j) 2^-j delta^(k-j),            j <= k
-//   L2L  Lt[c][k][j] = C(j,k) delta^(j-k) 2^-(k+1),       j >= k
+//        M[c][k][j] = C(k,j) 2^-j delta^(k-j),            j <= k < p
+//   L2L  Lt[c][k][j] = C(j,k) delta^(j-k) 2^-(k+1),       p > k, j >= k
+//        (rows k >= p of both are zero, so zero-padded terms stay zero)
 //   M2L  Hankel data h_n(tau) = n! tau^-(n+1) for the integer offsets
 //        tau = dx + i dy, |dx|, |dy| <= 3 (7 x 7 grid, the 9 touching offsets
 //        unused), n = 0 .. 2p-2; zero for n > 2p-2 so that zero-padded terms
@@ -46,8 +47,9 @@ void build_tables(int P, int p, cd* m2m, cd* l2l, cd* h64, cf* h32, double* sin_
         for (int k = 0; k < P; ++k)
             for (int j = 0; j < P; ++j) {
                 cld mv = 0.0L, lv = 0.0L;
-                if (j <= k) mv = binom(k, j) * std::pow(0.5L, (long double)j) * pw[k - j];
-                if (j >= k) lv = binom(j, k) * pw[j - k] * std::pow(0.5L, (long double)(k + 1));
+                // rows k >= p stay zero: the padded terms never fill up
+                if (k < p && j <= k) mv = binom(k, j) * std::pow(0.5L, (long double)j) * pw[k - j];
+                if (k < p && j >= k) lv = binom(j, k) * pw[j - k] * std::pow(0.5L, (long double)(k + 1));
                 m2m[(c * P + k) * P + j] = to_cd(mv);
                 l2l[(c * P + k) * P + j] = to_cd(lv);
             }

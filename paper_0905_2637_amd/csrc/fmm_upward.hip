@@ -10,6 +10,10 @@
 //   ahat^P_k = sum_{m<=k} C(k,m) 2^-m delta^(k-m) ahat^child_m,
 // one of four fixed lower-triangular matrices built on the host.
 //
+// Storage: every box holds P >= p coefficients (P the compiled expansion
+// size), terms k >= p zero; the operator rows k >= p are zero as well, so
+// the padding stays zero and no loop needs the runtime p.
+//
 // Subtree fusion: z-order makes the descendants of a box at any level one
 // contiguous run of boxes, so a workgroup that owns a box at level lt can
 // build up to three levels below it (64 + 16 + 4 + 1 boxes) in LDS and write
@@ -34,7 +38,10 @@ k_upward(int L, int lt, int d, int p, int from_particles, const int32_t* __restr
          const Domain* __restrict__ dom, cd* __restrict__ me, const cd* __restrict__ M)
 {
     __shared__ cd sh[85 * P];            // 64 + 16 + 4 + 1 boxes
+    __shared__ cd sM[4 * P * P];         // the four M2M matrices
     const int tid = threadIdx.x;
+    if (d > 0)
+        for (int e = tid; e < 4 * P * P; e += kUpThreads) sM[e] = M[e];
     const int lb = lt + d;
     const int64_t root = blockIdx.x;     // z-order index at level lt
     const int nb = 1 << (2 * d);         // boxes at level lb under this root
@@ -75,20 +82,20 @@ k_upward(int L, int lt, int d, int p, int from_particles, const int32_t* __restr
                     px = nx;
                 }
             }
-            cd* dst = me + (level_offset(L) + int64_t(leaf)) * p;
+            cd* dst = me + (level_offset(L) + int64_t(leaf)) * P;
 #pragma unroll
             for (int q = 0; q < KR; ++q) {
                 const int k = r + kP2MLanes * q;
-                if (k < P) sh[i * P + k] = cd{k < p ? ax[q] : 0.0, k < p ? ay[q] : 0.0};
-                if (k < p) dst[k] = cd{ax[q], ay[q]};
+                if (k < P) {
+                    const cd val = k < p ? cd{ax[q], ay[q]} : cd{0.0, 0.0};   // terms >= p stay zero
+                    sh[i * P + k] = val;
+                    dst[k] = val;
+                }
             }
         }
     } else {
-        const cd* src = me + (level_offset(lb) + first) * p;
-        for (int e = tid; e < nb * P; e += kUpThreads) {
-            const int i = e / P, k = e % P;
-            sh[e] = k < p ? src[int64_t(i) * p + k] : cd{0.0, 0.0};
-        }
+        const cd* src = me + (level_offset(lb) + first) * P;
+        for (int e = tid; e < nb * P; e += kUpThreads) sh[e] = src[e];
     }
     __syncthreads();
 
@@ -97,22 +104,20 @@ k_upward(int L, int lt, int d, int p, int from_particles, const int32_t* __restr
     for (int j = lb - 1; j >= lt; --j) {
         const int n_out = n_in >> 2;
         const int64_t gfirst = root << (2 * (j - lt));
-        cd* gdst = me + (level_offset(j) + gfirst) * p;
+        cd* gdst = me + (level_offset(j) + gfirst) * P;
         for (int e = tid; e < n_out * P; e += kUpThreads) {
             const int o = e / P, k = e % P;
             double bx = 0.0, by = 0.0;
-            if (k < p) {
-                for (int c = 0; c < 4; ++c) {
-                    const cd* a = sh + in_off + (4 * o + c) * P;
-                    const cd* Mr = M + (c * P + k) * P;
-                    for (int m = 0; m <= k; ++m) {
-                        const cd t = Mr[m];
-                        const cd s = a[m];
-                        cmac(bx, by, t.x, t.y, s.x, s.y);
-                    }
+            for (int c = 0; c < 4; ++c) {
+                const cd* a = sh + in_off + (4 * o + c) * P;
+                const cd* Mr = sM + (c * P + k) * P;     // rows k >= p are zero
+                for (int m = 0; m <= k; ++m) {
+                    const cd t = Mr[m];
+                    const cd s = a[m];
+                    cmac(bx, by, t.x, t.y, s.x, s.y);
                 }
-                gdst[int64_t(o) * p + k] = cd{bx, by};
             }
+            gdst[e] = cd{bx, by};
             sh[out_off + e] = cd{bx, by};
         }
         __syncthreads();
