@@ -87,8 +87,8 @@ fmm_status fmm_workspace_size(const fmm_params* prm, size_t* bytes);
 fmm_status fmm_plan(const fmm_params* prm, void* d_workspace, size_t bytes,
                     void* stream, fmm_plan_t* out);
 
-/* One full FMM evaluation: tree build (z-order keys, counting sort by leaf,
- * leaf ranges), P2M, M2M, M2L, L2L, L2P and P2P.
+/* One full FMM evaluation: tree build (z-order keys, stable radix sort by
+ * leaf, leaf ranges), P2M, M2M, M2L, L2L, L2P and P2P (Section 2.2).
  *   n                  number of particles, 0 <= n <= n_max
  *   d_x, d_y, d_gamma  device FP64 arrays [n]: positions and circulations
  *   d_u, d_v           device FP64 arrays [n]: velocity components (eq. 9),
@@ -100,6 +100,51 @@ fmm_status fmm_plan(const fmm_params* prm, void* d_workspace, size_t bytes,
 fmm_status fmm_evaluate(fmm_plan_t plan, int64_t n,
                         const double* d_x, const double* d_y, const double* d_gamma,
                         double* d_u, double* d_v, void* stream);
+
+/* Batched form: many independent problems, each evaluated exactly as
+ * fmm_evaluate would (the same operation; only the schedule differs),
+ * sharing sigma, p, precision and one explicit square [x0, x0+width]^2,
+ * each with its own
+ * particle count counts[i] >= 0 and tree depth depths[i] in 0..13.  Their
+ * particles are concatenated in instance order (instance i owns the
+ * counts[i] entries after those of instances 0..i-1); every stage is one
+ * launch over the work of all instances.  n_max and depth of prm are
+ * ignored; width must be > 0 (else FMM_E_UNSUPPORTED); 1 <= n_inst <= 65536
+ * and ceil(log2 n_inst) + 2 max(depths) <= 32 (else FMM_E_UNSUPPORTED).
+ * counts and depths are host arrays read during the call only. */
+fmm_status fmm_workspace_size_batch(const fmm_params* prm, int32_t n_inst, const int32_t* counts,
+                                    const int32_t* depths, size_t* bytes);
+fmm_status fmm_plan_batch(const fmm_params* prm, int32_t n_inst, const int32_t* counts,
+                          const int32_t* depths, void* d_workspace, size_t bytes, void* stream,
+                          fmm_plan_t* out);
+
+/* Evaluate every instance of a batched plan: device FP64 arrays of
+ * sum(counts) entries, laid out as described above; results in the same
+ * order.  The first call with a given set of five pointers captures the
+ * evaluation into a HIP graph (on a stream the plan owns); later calls with
+ * the same pointers replay it on `stream` with one launch.  Calls on one
+ * plan must not overlap.  Errors: FMM_E_ARG (a single-instance plan, NULL
+ * pointers), FMM_E_DEVICE.  fmm_get_status and fmm_debug_dump (KEYS, PERM,
+ * LEAF_START of all instances, segment after segment) work as for a single
+ * plan; stage timing is not available for batched plans. */
+fmm_status fmm_evaluate_batch(fmm_plan_t plan, const double* d_x, const double* d_y,
+                              const double* d_gamma, double* d_u, double* d_v, void* stream);
+
+/* Launch shapes.  p2p_waves: leaves (one wavefront each) per P2P workgroup,
+ * 2 or 4 (default 4).  m2l_split_max: M2L levels <= min(L, m2l_split_max)
+ * split each box's interaction list over three wavefronts (more parallelism
+ * on levels with few boxes), 0 .. 8 (default 8; below 2: never).  Results
+ * are identical up to the summation order of the split levels.
+ * fmm_set_tuning synchronises `stream`.  fmm_autotune times every
+ * combination of p2p_waves in {2, 4} and m2l_split_max in {0, 5, 8} on the
+ * caller's data (reps timed evaluations each, after one warm-up; the output
+ * arrays are overwritten), keeps the fastest and, when the environment
+ * variable FMM_AUTOTUNE_CACHE names a file, looks the choice up there first
+ * and appends it after a search.  For batched plans n is ignored. */
+fmm_status fmm_get_tuning(fmm_plan_t plan, int32_t* p2p_waves, int32_t* m2l_split_max);
+fmm_status fmm_set_tuning(fmm_plan_t plan, int32_t p2p_waves, int32_t m2l_split_max, void* stream);
+fmm_status fmm_autotune(fmm_plan_t plan, int64_t n, const double* d_x, const double* d_y,
+                        const double* d_gamma, double* d_u, double* d_v, void* stream, int32_t reps);
 
 /* Synchronises `stream` and reports the number of particles of the last
  * evaluation that fell outside the explicit domain or had a NaN coordinate.
@@ -123,7 +168,8 @@ const char* fmm_stage_name(int32_t stage);
  * the plan's device arrays from the last evaluation into host_buf:
  *   FMM_DUMP_KEYS       uint32 [n]      leaf z-order key of every particle (input order)
  *   FMM_DUMP_PERM       uint32 [n]      sorted position -> input index
- *   FMM_DUMP_LEAF_START int32 [4^L+1]   sorted range of every leaf, z-order
+ *   FMM_DUMP_LEAF_START int32 [4^L+1]   sorted range of every leaf, z-order (batched:
+ *                                       the segments of all instances, 4^L_i+1 each)
  *   FMM_DUMP_ME         complex128 [Lambda][p] scaled multipole coefficients
  *   FMM_DUMP_LE         complex128 [Lambda][p] scaled local coefficients
  *   FMM_DUMP_DOMAIN     double [4]      x0, y0, width, 2^L / width
@@ -140,8 +186,9 @@ enum {
 fmm_status fmm_debug_dump(fmm_plan_t plan, int32_t what, void* host_buf,
                           size_t bytes, size_t* needed);
 
-/* Release the host handle and its HIP events.  Never frees the workspace or
- * any other caller memory.  NULL is accepted. */
+/* Release the host handle, its HIP events, captured graph and private
+ * stream.  Never frees the workspace or any other caller memory.  NULL is
+ * accepted. */
 fmm_status fmm_destroy(fmm_plan_t plan);
 
 /* Static description of a status code. */

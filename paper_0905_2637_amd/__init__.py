@@ -28,8 +28,10 @@ FMM_PREC_MIXED = 1
 
 DUMP_KEYS, DUMP_PERM, DUMP_LEAF_START, DUMP_ME, DUMP_LE, DUMP_DOMAIN, DUMP_ILIST = range(7)
 
-EXPORTED = ["fmm_workspace_size", "fmm_plan", "fmm_evaluate", "fmm_get_status", "fmm_set_timing",
-            "fmm_stats", "fmm_stage_name", "fmm_debug_dump", "fmm_destroy", "fmm_status_string"]
+EXPORTED = ["fmm_workspace_size", "fmm_plan", "fmm_evaluate", "fmm_workspace_size_batch", "fmm_plan_batch",
+            "fmm_evaluate_batch", "fmm_get_status", "fmm_set_timing", "fmm_stats", "fmm_stage_name",
+            "fmm_get_tuning", "fmm_set_tuning", "fmm_autotune", "fmm_debug_dump", "fmm_destroy",
+            "fmm_status_string"]
 
 
 class FmmParams(C.Structure):
@@ -59,6 +61,13 @@ def load():
     lib.fmm_workspace_size.argtypes = [C.POINTER(FmmParams), C.POINTER(C.c_size_t)]
     lib.fmm_plan.argtypes = [C.POINTER(FmmParams), vp, C.c_size_t, vp, C.POINTER(vp)]
     lib.fmm_evaluate.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp]
+    i32p = C.POINTER(C.c_int32)
+    lib.fmm_workspace_size_batch.argtypes = [C.POINTER(FmmParams), C.c_int32, i32p, i32p, C.POINTER(C.c_size_t)]
+    lib.fmm_plan_batch.argtypes = [C.POINTER(FmmParams), C.c_int32, i32p, i32p, vp, C.c_size_t, vp, C.POINTER(vp)]
+    lib.fmm_evaluate_batch.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.fmm_get_tuning.argtypes = [vp, i32p, i32p]
+    lib.fmm_set_tuning.argtypes = [vp, C.c_int32, C.c_int32, vp]
+    lib.fmm_autotune.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp, C.c_int32]
     lib.fmm_get_status.argtypes = [vp, vp, C.POINTER(C.c_int64)]
     lib.fmm_set_timing.argtypes = [vp, C.c_int32]
     lib.fmm_stats.argtypes = [vp, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32),
@@ -69,8 +78,9 @@ def load():
     lib.fmm_destroy.argtypes = [vp]
     lib.fmm_status_string.argtypes = [C.c_int]
     lib.fmm_status_string.restype = C.c_char_p
-    for name in ("fmm_workspace_size", "fmm_plan", "fmm_evaluate", "fmm_get_status", "fmm_set_timing",
-                 "fmm_stats", "fmm_debug_dump", "fmm_destroy"):
+    for name in EXPORTED:
+        if name in ("fmm_stage_name", "fmm_status_string"):
+            continue
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -98,67 +108,46 @@ def workspace_size(prm: FmmParams) -> int:
     return int(out.value)
 
 
+def _i32_array(vals):
+    arr = (C.c_int32 * len(vals))(*[int(v) for v in vals])
+    return arr
+
+
+def workspace_size_batch(prm: FmmParams, counts, depths) -> int:
+    if len(counts) != len(depths):
+        raise ValueError("counts and depths differ in length")
+    out = C.c_size_t(0)
+    s = load().fmm_workspace_size_batch(C.byref(prm), len(counts), _i32_array(counts), _i32_array(depths),
+                                        C.byref(out))
+    if s != FMM_OK:
+        raise FmmError(s, "fmm_workspace_size_batch")
+    return int(out.value)
+
+
 def _stream_handle(stream=None):
     import torch
     st = stream if stream is not None else torch.cuda.current_stream()
     return C.c_void_p(st.cuda_stream)
 
 
-class Plan:
-    """One FMM configuration bound to a device workspace.
+def _check_inputs(n, tensors):
+    import torch
+    for t in tensors:
+        if t.dtype != torch.float64 or t.device.type != "cuda" or not t.is_contiguous() or t.shape[0] != n:
+            raise ValueError("x, y, gamma, u, v must be contiguous float64 CUDA tensors of equal length")
 
-    Parameters follow the paper's problem statement: core size ``sigma``,
-    expansion order ``p`` and tree ``depth``; ``domain`` = (x0, y0, width) of
-    the square, or None for the particles' bounding square at every call.
-    """
 
-    def __init__(self, n_max, sigma, p, depth, domain=(0.0, 0.0, 1.0), precision="fp64",
-                 fp32_fine_levels=2, device="cuda"):
+class _PlanBase:
+    """Shared handle management, status, timing, tuning and inspection."""
+
+    _h = None
+
+    def _alloc_workspace(self, nbytes):
         import torch
-        if not torch.cuda.is_available():
-            raise RuntimeError("no HIP device: the FMM runs only on the GPU")
-        self.params = make_params(n_max, sigma, p, depth, domain, precision, fp32_fine_levels)
-        self.n_max = int(n_max)
-        self.depth = int(depth)
-        self.p = int(p)
-        self.precision = precision
-        self.device = torch.device(device)
-        nbytes = workspace_size(self.params)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()
-        aligned = (base + 255) & ~255
-        self._ws_ptr = aligned
+        self._ws_ptr = (base + 255) & ~255
         self._ws_bytes = nbytes
-        handle = C.c_void_p()
-        s = load().fmm_plan(C.byref(self.params), C.c_void_p(aligned), C.c_size_t(nbytes),
-                            _stream_handle(), C.byref(handle))
-        if s != FMM_OK:
-            raise FmmError(s, "fmm_plan")
-        self._h = handle
-        self.last_n = 0
-
-    def evaluate(self, x, y, gamma, u=None, v=None, check=False):
-        """Velocity (u, v) of eq. 9 at every particle; FP64 device tensors."""
-        import torch
-        n = int(x.shape[0])
-        for t in (x, y, gamma):
-            if t.dtype != torch.float64 or t.device.type != "cuda" or not t.is_contiguous() or t.shape[0] != n:
-                raise ValueError("x, y, gamma must be contiguous float64 CUDA tensors of equal length")
-        if u is None:
-            u = torch.empty(n, dtype=torch.float64, device=x.device)
-        if v is None:
-            v = torch.empty(n, dtype=torch.float64, device=x.device)
-        s = load().fmm_evaluate(self._h, n, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
-                                C.c_void_p(gamma.data_ptr()), C.c_void_p(u.data_ptr()),
-                                C.c_void_p(v.data_ptr()), _stream_handle())
-        if s != FMM_OK:
-            raise FmmError(s, "fmm_evaluate")
-        self.last_n = n
-        if check:
-            nbad = self.out_of_domain()
-            if nbad:
-                raise FmmError(FMM_E_DOMAIN, f"fmm_evaluate: {nbad} particles outside the domain")
-        return u, v
 
     def out_of_domain(self) -> int:
         out = C.c_int64(0)
@@ -184,6 +173,19 @@ class Plan:
         out = {lib.fmm_stage_name(i).decode(): float(buf[i]) for i in range(nw.value)}
         out["evaluations"] = int(ne.value)
         return out
+
+    def tuning(self) -> dict:
+        w = C.c_int32(0)
+        sm = C.c_int32(0)
+        s = load().fmm_get_tuning(self._h, C.byref(w), C.byref(sm))
+        if s != FMM_OK:
+            raise FmmError(s, "fmm_get_tuning")
+        return {"p2p_waves": int(w.value), "m2l_split_max": int(sm.value)}
+
+    def set_tuning(self, p2p_waves=4, m2l_split_max=8):
+        s = load().fmm_set_tuning(self._h, int(p2p_waves), int(m2l_split_max), _stream_handle())
+        if s != FMM_OK:
+            raise FmmError(s, "fmm_set_tuning")
 
     def dump(self, what: int) -> np.ndarray:
         lib = load()
@@ -213,3 +215,137 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class Plan(_PlanBase):
+    """One FMM configuration bound to a device workspace.
+
+    Parameters follow the paper's problem statement: core size ``sigma``,
+    expansion order ``p`` and tree ``depth``; ``domain`` = (x0, y0, width) of
+    the square, or None for the particles' bounding square at every call.
+    """
+
+    def __init__(self, n_max, sigma, p, depth, domain=(0.0, 0.0, 1.0), precision="fp64",
+                 fp32_fine_levels=2, device="cuda"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the FMM runs only on the GPU")
+        self.params = make_params(n_max, sigma, p, depth, domain, precision, fp32_fine_levels)
+        self.n_max = int(n_max)
+        self.depth = int(depth)
+        self.p = int(p)
+        self.precision = precision
+        self.device = torch.device(device)
+        self._alloc_workspace(workspace_size(self.params))
+        handle = C.c_void_p()
+        s = load().fmm_plan(C.byref(self.params), C.c_void_p(self._ws_ptr), C.c_size_t(self._ws_bytes),
+                            _stream_handle(), C.byref(handle))
+        if s != FMM_OK:
+            raise FmmError(s, "fmm_plan")
+        self._h = handle
+        self.last_n = 0
+
+    def _outputs(self, x, u, v):
+        import torch
+        n = int(x.shape[0])
+        if u is None:
+            u = torch.empty(n, dtype=torch.float64, device=x.device)
+        if v is None:
+            v = torch.empty(n, dtype=torch.float64, device=x.device)
+        return u, v
+
+    def evaluate(self, x, y, gamma, u=None, v=None, check=False):
+        """Velocity (u, v) of eq. 9 at every particle; FP64 device tensors."""
+        n = int(x.shape[0])
+        u, v = self._outputs(x, u, v)
+        _check_inputs(n, (x, y, gamma, u, v))
+        s = load().fmm_evaluate(self._h, n, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                C.c_void_p(gamma.data_ptr()), C.c_void_p(u.data_ptr()),
+                                C.c_void_p(v.data_ptr()), _stream_handle())
+        if s != FMM_OK:
+            raise FmmError(s, "fmm_evaluate")
+        self.last_n = n
+        if check:
+            nbad = self.out_of_domain()
+            if nbad:
+                raise FmmError(FMM_E_DOMAIN, f"fmm_evaluate: {nbad} particles outside the domain")
+        return u, v
+
+    def autotune(self, x, y, gamma, u=None, v=None, reps=3) -> dict:
+        """Time the launch-shape candidates on these inputs and keep the fastest."""
+        n = int(x.shape[0])
+        u, v = self._outputs(x, u, v)
+        _check_inputs(n, (x, y, gamma, u, v))
+        s = load().fmm_autotune(self._h, n, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                C.c_void_p(gamma.data_ptr()), C.c_void_p(u.data_ptr()),
+                                C.c_void_p(v.data_ptr()), _stream_handle(), int(reps))
+        if s != FMM_OK:
+            raise FmmError(s, "fmm_autotune")
+        return self.tuning()
+
+
+class BatchPlan(_PlanBase):
+    """Many independent FMM problems evaluated together (one graph replay).
+
+    ``counts[i]`` particles of instance i follow those of instances 0..i-1
+    in the concatenated input arrays; instance i uses tree depth
+    ``depths[i]``.  All instances share ``sigma``, ``p``, the precision and
+    the explicit square ``domain`` = (x0, y0, width).
+    """
+
+    def __init__(self, counts, depths, sigma, p, domain=(0.0, 0.0, 1.0), precision="fp64",
+                 fp32_fine_levels=2, device="cuda"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the FMM runs only on the GPU")
+        if domain is None:
+            raise ValueError("a batched plan needs an explicit square domain")
+        self.counts = [int(c) for c in counts]
+        self.depths = [int(d) for d in depths]
+        self.n = sum(self.counts)
+        self.p = int(p)
+        self.precision = precision
+        self.params = make_params(self.n, sigma, p, max(self.depths), domain, precision, fp32_fine_levels)
+        self.device = torch.device(device)
+        self._alloc_workspace(workspace_size_batch(self.params, self.counts, self.depths))
+        handle = C.c_void_p()
+        s = load().fmm_plan_batch(C.byref(self.params), len(self.counts), _i32_array(self.counts),
+                                  _i32_array(self.depths), C.c_void_p(self._ws_ptr), C.c_size_t(self._ws_bytes),
+                                  _stream_handle(), C.byref(handle))
+        if s != FMM_OK:
+            raise FmmError(s, "fmm_plan_batch")
+        self._h = handle
+        self.offsets = np.concatenate([[0], np.cumsum(self.counts)]).astype(np.int64)
+
+    def _outputs(self, u, v):
+        import torch
+        if u is None:
+            u = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        if v is None:
+            v = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        return u, v
+
+    def evaluate(self, x, y, gamma, u=None, v=None, check=False):
+        """Velocities of every instance, concatenated like the inputs."""
+        u, v = self._outputs(u, v)
+        _check_inputs(self.n, (x, y, gamma, u, v))
+        s = load().fmm_evaluate_batch(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                      C.c_void_p(gamma.data_ptr()), C.c_void_p(u.data_ptr()),
+                                      C.c_void_p(v.data_ptr()), _stream_handle())
+        if s != FMM_OK:
+            raise FmmError(s, "fmm_evaluate_batch")
+        if check:
+            nbad = self.out_of_domain()
+            if nbad:
+                raise FmmError(FMM_E_DOMAIN, f"fmm_evaluate_batch: {nbad} particles outside the domain")
+        return u, v
+
+    def autotune(self, x, y, gamma, u=None, v=None, reps=3) -> dict:
+        u, v = self._outputs(u, v)
+        _check_inputs(self.n, (x, y, gamma, u, v))
+        s = load().fmm_autotune(self._h, self.n, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                C.c_void_p(gamma.data_ptr()), C.c_void_p(u.data_ptr()),
+                                C.c_void_p(v.data_ptr()), _stream_handle(), int(reps))
+        if s != FMM_OK:
+            raise FmmError(s, "fmm_autotune")
+        return self.tuning()

@@ -1,9 +1,13 @@
 // fmm_api.cpp -- the C ABI of include/fmm.h: argument validation, workspace
-// layout, plan construction and the stage sequence of one evaluation.
+// layout, the launch schedule of one evaluation (single or batched), hipGraph
+// replay of the batched form, stage timing, the autotuner and inspection.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/fmm.h"
@@ -18,41 +22,151 @@ const char* const kStageNames[ST_COUNT] = {"tree", "p2m_m2m", "m2l", "l2l", "p2p
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
-fmm_status validate(const fmm_params* prm)
+// Launch shapes the autotuner chooses among.
+struct Tuning {
+    int p2p_waves = 4;                   // leaves (wavefronts) per P2P workgroup: 2 or 4
+    int split_max = kM2LSplitMaxLevel;   // M2L list split on levels <= this; < 2: never
+};
+
+// Host description of the instances of a plan.
+struct Shape {
+    int n_inst = 1;
+    std::vector<int32_t> depth;
+    std::vector<int64_t> part_off;       // first particle of every instance
+    int64_t n_cap = 0;                   // particle capacity (the total count if batched)
+    int Lmax = 0;
+    int key_bits = 0;
+    int64_t leaf_entries = 0;            // sum (4^L_i + 1)
+    int64_t boxes = 0;                   // sum Lambda(L_i)
+    int64_t split_boxes = 0;             // sum Lambda(min(L_i, kM2LSplitMaxLevel))
+    std::vector<int64_t> leaf_off, box_off, split_off;
+};
+
+// Launches of one evaluation after the tree build: at most 4 upward groups,
+// 4 M2L (FP64 / FP32 x split / unsplit), 4 downward groups and the P2P.
+constexpr int kMaxLaunches = 16;
+
+enum LaunchKind { L_UP, L_M2L, L_DOWN, L_P2P };
+
+struct Launch {
+    LaunchKind kind;
+    int nwg;
+    int table;       // its work table
+    bool fp32;       // M2L
+    int groups;      // M2L: 3 with the list split, else 1
+    bool leaves;     // upward: the first group, from the particles
+};
+
+int ceil_log2(int64_t v)
+{
+    int b = 0;
+    while ((int64_t(1) << b) < v) ++b;
+    return b;
+}
+
+int table_ints(int n_inst) { return 3 * n_inst + 1; }   // wg_begin [n+1], arg [2n]
+
+int split_level(int L, int split_max) { return (L <= 2 || split_max < 2) ? 1 : std::min(L, split_max); }
+
+int level_blocks_host(int l)
+{
+    const int side = 1 << l;
+    const int bpr = side >= 16 ? side / 16 : 1;
+    return bpr * bpr;
+}
+
+fmm_status validate_common(const fmm_params* prm)
 {
     if (!prm) return FMM_E_ARG;
-    if (prm->n_max < 0 || prm->n_max > int64_t(0x7fffffff)) return FMM_E_ARG;
     if (!(prm->sigma > 0.0) || !std::isfinite(prm->sigma)) return FMM_E_ARG;
     if (prm->p < 1 || prm->p > kMaxP) return FMM_E_ARG;
-    if (prm->depth < 0 || prm->depth > kMaxDepth) return FMM_E_ARG;
     if (prm->precision != FMM_PREC_FP64 && prm->precision != FMM_PREC_MIXED) return FMM_E_ARG;
     if (prm->width > 0.0) {
         if (!std::isfinite(prm->width) || !std::isfinite(prm->x0) || !std::isfinite(prm->y0)) return FMM_E_ARG;
     }
     if (prm->precision == FMM_PREC_MIXED) {
-        if (prm->fp32_fine_levels < 0 || prm->fp32_fine_levels > std::max(0, prm->depth - 1)) return FMM_E_ARG;
+        if (prm->fp32_fine_levels < 0 || prm->fp32_fine_levels > kMaxDepth) return FMM_E_ARG;
         if (prm->p > kMaxPMixed) return FMM_E_UNSUPPORTED;
     }
     return FMM_OK;
 }
 
-Layout make_layout(const fmm_params& prm)
+fmm_status finish_shape(Shape& sh)
 {
-    const int P = instantiated_terms(prm.p);
-    const int L = prm.depth;
-    const size_t n = size_t(std::max<int64_t>(prm.n_max, 1));
-    const size_t nleaf = size_t(1) << (2 * L);
-    const size_t nbox = size_t(level_offset(L + 1));
-    const size_t nhist = size_t(256) * size_t(radix_blocks(int64_t(n)));
+    sh.Lmax = 0;
+    for (int L : sh.depth) sh.Lmax = std::max(sh.Lmax, L);
+    sh.key_bits = (sh.n_inst > 1 ? ceil_log2(sh.n_inst) : 0) + 2 * sh.Lmax;
+    if (sh.key_bits > 32) return FMM_E_UNSUPPORTED;
+    sh.leaf_off.resize(sh.n_inst);
+    sh.box_off.resize(sh.n_inst);
+    sh.split_off.resize(sh.n_inst);
+    sh.leaf_entries = sh.boxes = sh.split_boxes = 0;
+    for (int i = 0; i < sh.n_inst; ++i) {
+        const int L = sh.depth[i];
+        sh.leaf_off[i] = sh.leaf_entries;
+        sh.box_off[i] = sh.boxes;
+        sh.split_off[i] = sh.split_boxes;
+        sh.leaf_entries += (int64_t(1) << (2 * L)) + 1;
+        sh.boxes += level_offset(L + 1);
+        sh.split_boxes += level_offset(std::min(L, kM2LSplitMaxLevel) + 1);
+    }
+    // workgroup numbers of a launch are int32
+    if (sh.boxes > int64_t(0x3fffffff) || sh.leaf_entries > int64_t(0x7fffffff)) return FMM_E_UNSUPPORTED;
+    return FMM_OK;
+}
+
+fmm_status single_shape(const fmm_params* prm, Shape& sh)
+{
+    if (prm->n_max < 0 || prm->n_max > int64_t(0x7fffffff)) return FMM_E_ARG;
+    if (prm->depth < 0 || prm->depth > kMaxDepth) return FMM_E_ARG;
+    if (prm->precision == FMM_PREC_MIXED && prm->fp32_fine_levels > std::max(0, prm->depth - 1)) return FMM_E_ARG;
+    sh.n_inst = 1;
+    sh.depth = {prm->depth};
+    sh.part_off = {0};
+    sh.n_cap = prm->n_max;
+    return finish_shape(sh);
+}
+
+fmm_status batch_shape(const fmm_params* prm, int32_t n_inst, const int32_t* counts, const int32_t* depths,
+                       Shape& sh)
+{
+    if (n_inst < 1 || n_inst > kMaxInstances || !counts || !depths) return FMM_E_ARG;
+    if (!(prm->width > 0.0)) return FMM_E_UNSUPPORTED;   // batched instances need the explicit square
+    sh.n_inst = n_inst;
+    sh.depth.assign(depths, depths + n_inst);
+    sh.part_off.resize(n_inst);
+    int64_t tot = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        if (counts[i] < 0 || depths[i] < 0 || depths[i] > kMaxDepth) return FMM_E_ARG;
+        sh.part_off[i] = tot;
+        tot += counts[i];
+    }
+    if (tot > int64_t(0x7fffffff)) return FMM_E_ARG;
+    sh.n_cap = tot;
+    return finish_shape(sh);
+}
+
+struct Layout {
+    size_t inst, tables, bad_blk, bbox, leaf_start, hist, hist_scan, scan_part;
+    size_t key, ksorted, perm, xs, ys, gs, ktmp, itmp, xt, yt, gt, pk, me, le, le_part[2];
+    size_t t_m2m, t_l2l, t_h64, t_h32, t_sin, t_sout;
+    size_t total;
+};
+
+Layout make_layout(const Shape& sh, int P, bool mixed)
+{
+    const size_t n = size_t(std::max<int64_t>(sh.n_cap, 1));
+    const size_t nblk = size_t(radix_blocks(int64_t(n)));
+    const size_t nhist = size_t(256) * nblk;
     const size_t nscan = (nhist + kScanChunk - 1) / kScanChunk;
-    const bool mixed = prm.precision == FMM_PREC_MIXED;
     Layout ly{};
     size_t off = 0;
     auto take = [&](size_t bytes) { const size_t o = off; off = align_up(off + bytes); return o; };
-    ly.bad_blk = take(sizeof(int32_t) * size_t(radix_blocks(int64_t(n))));
-    ly.dom = take(sizeof(Domain));
+    ly.inst = take(sizeof(Inst) * size_t(sh.n_inst));
+    ly.tables = take(sizeof(int32_t) * size_t(kMaxLaunches) * size_t(table_ints(sh.n_inst)));
+    ly.bad_blk = take(sizeof(int32_t) * nblk);
     ly.bbox = take(sizeof(double) * 4 * kBBoxBlocks);
-    ly.leaf_start = take(sizeof(int32_t) * (nleaf + 1));
+    ly.leaf_start = take(sizeof(int32_t) * size_t(sh.leaf_entries));
     ly.hist = take(sizeof(int32_t) * nhist);
     ly.hist_scan = take(sizeof(int32_t) * (nhist + 1));   // + the grand total
     ly.scan_part = take(sizeof(int32_t) * (nscan + 1));
@@ -69,13 +183,10 @@ Layout make_layout(const fmm_params& prm)
     ly.gt = take(sizeof(double) * n);
     ly.pk = take(mixed ? sizeof(float4) * n : 0);
     // expansions: P >= p coefficients per box (the compiled size), zero-padded
-    ly.me = take(sizeof(cd) * nbox * P);
-    ly.le = take(sizeof(cd) * nbox * P);
-    {
-        const size_t nsplit = size_t(level_offset(m2l_split_level(L) + 1));
-        ly.le_part[0] = take(sizeof(cd) * nsplit * P);
-        ly.le_part[1] = take(sizeof(cd) * nsplit * P);
-    }
+    ly.me = take(sizeof(cd) * size_t(sh.boxes) * P);
+    ly.le = take(sizeof(cd) * size_t(sh.boxes) * P);
+    ly.le_part[0] = take(sizeof(cd) * size_t(sh.split_boxes) * P);
+    ly.le_part[1] = take(sizeof(cd) * size_t(sh.split_boxes) * P);
     ly.t_m2m = take(sizeof(cd) * 4 * P * P);
     ly.t_l2l = take(sizeof(cd) * 4 * P * P);
     ly.t_h64 = take(sizeof(cd) * kHankelGrid * kHankelGrid * (2 * P - 1));
@@ -99,8 +210,15 @@ struct fmm_plan_s {
     int P;
     bool auto_domain;
     bool mixed;
+    bool batch;
+    Shape shape;
+    Tuning tune;
+    std::vector<Launch> launches;
+    std::vector<int32_t> host_tables;    // kMaxLaunches work tables of table_ints(n_inst)
+    int32_t* d_tables;
     Buffers buf;
     int64_t last_n;
+    // stage timing
     bool timing;
     bool have_events;
     hipEvent_t ev[kTimingRing][ST_COUNT + 1];
@@ -108,6 +226,11 @@ struct fmm_plan_s {
     int64_t next_slot;
     int64_t n_timed;
     double total_ms[ST_COUNT];
+    // batched form: the evaluation captured once per set of arrays, replayed
+    hipStream_t cap_stream;
+    hipGraph_t graph;
+    hipGraphExec_t gexec;
+    const void* gptr[5];
 };
 
 namespace {
@@ -132,6 +255,277 @@ void destroy_events(fmm_plan_s* pl, int upto_slot)
 {
     for (int r = 0; r < upto_slot; ++r)
         for (int i = 0; i <= ST_COUNT; ++i) hipEventDestroy(pl->ev[r][i]);
+}
+
+void drop_graph(fmm_plan_s* pl)
+{
+    if (pl->gexec) hipGraphExecDestroy(pl->gexec);
+    if (pl->graph) hipGraphDestroy(pl->graph);
+    pl->gexec = nullptr;
+    pl->graph = nullptr;
+    for (auto& q : pl->gptr) q = nullptr;
+}
+
+// Launch list and work tables for the current tuning.  Workgroups of a launch
+// are numbered instance after instance; an instance without work in a launch
+// gets an empty range.
+void build_schedule(fmm_plan_s* pl)
+{
+    const Shape& sh = pl->shape;
+    const int n = sh.n_inst;
+    const int ti = table_ints(n);
+    pl->launches.clear();
+    pl->host_tables.assign(size_t(kMaxLaunches) * ti, 0);
+    std::vector<int32_t> wg(n), arg(2 * n);
+    auto add = [&](LaunchKind kind, bool fp32, int groups, bool leaves) {
+        const int t = int(pl->launches.size());
+        int32_t* tb = pl->host_tables.data() + size_t(t) * ti;
+        tb[0] = 0;
+        for (int i = 0; i < n; ++i) tb[i + 1] = tb[i] + wg[i];
+        for (int i = 0; i < 2 * n; ++i) tb[n + 1 + i] = arg[i];
+        if (tb[n] > 0) pl->launches.push_back(Launch{kind, tb[n], t, fp32, groups, leaves});
+    };
+    auto clear = [&]() {
+        std::fill(wg.begin(), wg.end(), 0);
+        std::fill(arg.begin(), arg.end(), 0);
+    };
+
+    // upward: groups of up to three M2M levels, leaves (P2M) first, to level 2
+    for (int g = 0;; ++g) {
+        clear();
+        bool any = false;
+        for (int i = 0; i < n; ++i) {
+            const int L = sh.depth[i];
+            if (L < 2) continue;
+            int lb = L, lt = std::max(2, L - 3), k = 0;
+            while (k < g && lt > 2) { lb = lt; lt = std::max(2, lb - 3); ++k; }
+            if (k < g) continue;                       // fewer groups for this instance
+            wg[i] = int(int64_t(1) << (2 * lt));
+            arg[2 * i] = lt;
+            arg[2 * i + 1] = lb - lt;
+            any = true;
+        }
+        if (!any) break;
+        add(L_UP, false, 1, g == 0);
+    }
+    // M2L: levels [2, f32) in FP64 and [f32, L] in FP32; levels <= the split
+    // level with the interaction list split over three wavefronts
+    for (int prec = 0; prec < 2; ++prec)
+        for (int part = 0; part < 2; ++part) {
+            clear();
+            for (int i = 0; i < n; ++i) {
+                const int L = sh.depth[i];
+                if (L < 2) continue;
+                const int fine = pl->mixed ? pl->prm.fp32_fine_levels : 0;
+                const int f32 = std::max(2, L - fine + 1);
+                const int lo = prec == 0 ? 2 : f32, hi = prec == 0 ? f32 - 1 : L;
+                const int sl = split_level(L, pl->tune.split_max);
+                const int a = part == 0 ? lo : std::max(lo, sl + 1);
+                const int b = part == 0 ? std::min(hi, sl) : hi;
+                if (b < a) continue;
+                int cnt = 0;
+                for (int l = a; l <= b; ++l) cnt += level_blocks_host(l);
+                wg[i] = cnt;
+                arg[2 * i] = a;
+                arg[2 * i + 1] = b;
+            }
+            add(L_M2L, prec == 1, part == 0 ? 3 : 1, false);
+        }
+    // downward: L2L in groups of up to three levels from level 2
+    for (int g = 0;; ++g) {
+        clear();
+        bool any = false;
+        for (int i = 0; i < n; ++i) {
+            const int L = sh.depth[i];
+            const int lt = 2 + 3 * g;
+            if (L < 2 || lt >= L) continue;
+            wg[i] = int(int64_t(1) << (2 * lt));
+            arg[2 * i] = lt;
+            arg[2 * i + 1] = std::min(3, L - lt);
+            any = true;
+        }
+        if (!any) break;
+        add(L_DOWN, false, 1, false);
+    }
+    // near field and L2P: p2p_waves leaves per workgroup
+    clear();
+    for (int i = 0; i < n; ++i) {
+        const int64_t nleaf = int64_t(1) << (2 * sh.depth[i]);
+        wg[i] = int((nleaf + pl->tune.p2p_waves - 1) / pl->tune.p2p_waves);
+    }
+    add(L_P2P, false, 1, false);
+}
+
+std::vector<Inst> build_inst(const fmm_plan_s* pl)
+{
+    const Shape& sh = pl->shape;
+    std::vector<Inst> v(sh.n_inst);
+    for (int i = 0; i < sh.n_inst; ++i) {
+        Inst& I = v[i];
+        I.part_off = sh.part_off[i];
+        I.leaf_off = sh.leaf_off[i];
+        I.box_off = sh.box_off[i];
+        I.split_off = sh.split_off[i];
+        I.L = sh.depth[i];
+        I.split = split_level(I.L, pl->tune.split_max);
+        if (pl->auto_domain)   // the bounding square is written on the device by every evaluation
+            I.dom = Domain{0.0, 0.0, 1.0, std::ldexp(1.0, I.L)};
+        else
+            I.dom = Domain{pl->prm.x0, pl->prm.y0, pl->prm.width, std::ldexp(1.0, I.L) / pl->prm.width};
+    }
+    return v;
+}
+
+hipError_t upload_schedule(fmm_plan_s* pl, hipStream_t st)
+{
+    build_schedule(pl);
+    std::vector<Inst> iv = build_inst(pl);
+    hipError_t e = hipSuccess;
+    if (pl->auto_domain && pl->last_n > 0) {
+        // keep the last evaluation's bounding square for inspection
+        e = hipMemcpyAsync(&iv[0].dom, &pl->buf.inst[0].dom, sizeof(Domain), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(pl->buf.inst, iv.data(), iv.size() * sizeof(Inst), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(pl->d_tables, pl->host_tables.data(), pl->host_tables.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);   // the host vectors go out of scope
+    drop_graph(pl);
+    return e;
+}
+
+Work work_of(const fmm_plan_s* pl, const Launch& ln)
+{
+    const int32_t* tb = pl->d_tables + size_t(ln.table) * table_ints(pl->shape.n_inst);
+    return Work{tb, tb + pl->shape.n_inst + 1};
+}
+
+// Enqueue one whole evaluation on st.
+hipError_t enqueue_all(fmm_plan_s* pl, int64_t n, const double* x, const double* y, const double* g, double* u,
+                       double* v, hipStream_t st, bool timing, int slot)
+{
+    const Buffers& b = pl->buf;
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+    auto mark = [&](int i) { if (timing) chk(hipEventRecord(pl->ev[slot][i], st)); };
+    const int P = pl->P, p = pl->prm.p;
+
+    mark(ST_TREE);
+    if (pl->auto_domain) chk(launch_domain(b, int(n), x, y, pl->shape.depth[0], st));
+    chk(launch_tree(b, int(n), x, y, g, pl->shape.key_bits, pl->shape.leaf_entries, pl->mixed, st));
+    int stage = ST_TREE;
+    for (const Launch& ln : pl->launches) {
+        const int want = ln.kind == L_UP ? ST_UP : ln.kind == L_M2L ? ST_M2L : ln.kind == L_DOWN ? ST_DOWN : ST_P2P;
+        while (stage < want) mark(++stage);
+        const Work w = work_of(pl, ln);
+        switch (ln.kind) {
+            case L_UP: chk(launch_upward(b, P, p, w, ln.nwg, ln.leaves, st)); break;
+            case L_M2L: chk(launch_m2l(b, P, w, ln.nwg, ln.fp32, ln.groups, st)); break;
+            case L_DOWN: chk(launch_downward(b, P, w, ln.nwg, st)); break;
+            case L_P2P:
+                chk(launch_p2p(b, P, w, ln.nwg, pl->tune.p2p_waves, pl->mixed, pl->prm.sigma, u, v, st));
+                break;
+        }
+    }
+    while (stage < ST_COUNT) mark(++stage);
+    return e;
+}
+
+fmm_status make_plan(const fmm_params* prm, Shape&& sh, bool batch, void* d_workspace, size_t bytes, void* stream,
+                     fmm_plan_t* out)
+{
+    if ((reinterpret_cast<uintptr_t>(d_workspace) & 255) != 0) return FMM_E_ARG;
+    const int P = instantiated_terms(prm->p);
+    const bool mixed = prm->precision == FMM_PREC_MIXED;
+    const Layout ly = make_layout(sh, P, mixed);
+    if (bytes < ly.total) return FMM_E_CAPACITY;
+
+    fmm_plan_s* pl = new (std::nothrow) fmm_plan_s();
+    if (!pl) return FMM_E_NOMEM;
+    pl->prm = *prm;
+    pl->P = P;
+    pl->auto_domain = !(prm->width > 0.0);
+    pl->mixed = mixed;
+    pl->batch = batch;
+    pl->shape = std::move(sh);
+    pl->last_n = -1;
+    char* base = static_cast<char*>(d_workspace);
+    Buffers& b = pl->buf;
+    b.inst = reinterpret_cast<Inst*>(base + ly.inst);
+    b.n_inst = pl->shape.n_inst;
+    b.key_shift = 2 * pl->shape.Lmax;
+    pl->d_tables = reinterpret_cast<int32_t*>(base + ly.tables);
+    b.bad_blk = reinterpret_cast<int32_t*>(base + ly.bad_blk);
+    b.bbox = reinterpret_cast<double*>(base + ly.bbox);
+    b.leaf_start = reinterpret_cast<int32_t*>(base + ly.leaf_start);
+    b.hist = reinterpret_cast<int32_t*>(base + ly.hist);
+    b.hist_scan = reinterpret_cast<int32_t*>(base + ly.hist_scan);
+    b.scan_part = reinterpret_cast<int32_t*>(base + ly.scan_part);
+    b.key = reinterpret_cast<uint32_t*>(base + ly.key);
+    b.ksorted = reinterpret_cast<uint32_t*>(base + ly.ksorted);
+    b.perm = reinterpret_cast<uint32_t*>(base + ly.perm);
+    b.xs = reinterpret_cast<double*>(base + ly.xs);
+    b.ys = reinterpret_cast<double*>(base + ly.ys);
+    b.gs = reinterpret_cast<double*>(base + ly.gs);
+    b.ktmp = reinterpret_cast<uint32_t*>(base + ly.ktmp);
+    b.itmp = reinterpret_cast<uint32_t*>(base + ly.itmp);
+    b.xt = reinterpret_cast<double*>(base + ly.xt);
+    b.yt = reinterpret_cast<double*>(base + ly.yt);
+    b.gt = reinterpret_cast<double*>(base + ly.gt);
+    b.pk = mixed ? reinterpret_cast<float4*>(base + ly.pk) : nullptr;
+    b.me = reinterpret_cast<cd*>(base + ly.me);
+    b.le = reinterpret_cast<cd*>(base + ly.le);
+    b.le_part[0] = reinterpret_cast<cd*>(base + ly.le_part[0]);
+    b.le_part[1] = reinterpret_cast<cd*>(base + ly.le_part[1]);
+    b.ilist = nullptr;
+    b.t_m2m = reinterpret_cast<cd*>(base + ly.t_m2m);
+    b.t_l2l = reinterpret_cast<cd*>(base + ly.t_l2l);
+    b.t_h64 = reinterpret_cast<cd*>(base + ly.t_h64);
+    b.t_h32 = reinterpret_cast<cf*>(base + ly.t_h32);
+    b.t_sin = reinterpret_cast<double*>(base + ly.t_sin);
+    b.t_sout = reinterpret_cast<double*>(base + ly.t_sout);
+
+    const size_t nh = size_t(kHankelGrid) * kHankelGrid * (2 * P - 1);
+    std::vector<cd> m2m(size_t(4) * P * P), l2l(size_t(4) * P * P), h64(nh);
+    std::vector<cf> h32(nh);
+    std::vector<double> sin_(P), sout_(P);
+    build_tables(P, prm->p, m2m.data(), l2l.data(), h64.data(), h32.data(), sin_.data(), sout_.data());
+
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    auto cp = [&](void* dst, const void* src, size_t nbytes) {
+        if (e == hipSuccess) e = hipMemcpyAsync(dst, src, nbytes, hipMemcpyHostToDevice, st);
+    };
+    cp(b.t_m2m, m2m.data(), m2m.size() * sizeof(cd));
+    cp(b.t_l2l, l2l.data(), l2l.size() * sizeof(cd));
+    cp(b.t_h64, h64.data(), h64.size() * sizeof(cd));
+    cp(b.t_h32, h32.data(), h32.size() * sizeof(cf));
+    cp(b.t_sin, sin_.data(), sin_.size() * sizeof(double));
+    cp(b.t_sout, sout_.data(), sout_.size() * sizeof(double));
+    if (e == hipSuccess) e = upload_schedule(pl, st);      // synchronises st
+    if (e != hipSuccess) {
+        delete pl;
+        return FMM_E_DEVICE;
+    }
+    pl->have_events = true;
+    for (int r = 0; r < kTimingRing && pl->have_events; ++r)
+        for (int i = 0; i <= ST_COUNT; ++i)
+            if (hipEventCreate(&pl->ev[r][i]) != hipSuccess) {
+                for (int j = 0; j < i; ++j) hipEventDestroy(pl->ev[r][j]);
+                destroy_events(pl, r);
+                pl->have_events = false;
+                break;
+            }
+    *out = pl;
+    return FMM_OK;
+}
+
+fmm_status run_once(fmm_plan_s* pl, int64_t n, const double* x, const double* y, const double* g, double* u,
+                    double* v, void* stream)
+{
+    return pl->batch ? fmm_evaluate_batch(pl, x, y, g, u, v, stream) : fmm_evaluate(pl, n, x, y, g, u, v, stream);
 }
 
 }  // namespace
@@ -161,9 +555,25 @@ const char* fmm_stage_name(int32_t stage)
 fmm_status fmm_workspace_size(const fmm_params* prm, size_t* bytes)
 {
     if (!bytes) return FMM_E_ARG;
-    const fmm_status s = validate(prm);
+    fmm_status s = validate_common(prm);
     if (s != FMM_OK) return s;
-    *bytes = make_layout(*prm).total;
+    Shape sh;
+    s = single_shape(prm, sh);
+    if (s != FMM_OK) return s;
+    *bytes = make_layout(sh, instantiated_terms(prm->p), prm->precision == FMM_PREC_MIXED).total;
+    return FMM_OK;
+}
+
+fmm_status fmm_workspace_size_batch(const fmm_params* prm, int32_t n_inst, const int32_t* counts,
+                                    const int32_t* depths, size_t* bytes)
+{
+    if (!bytes) return FMM_E_ARG;
+    fmm_status s = validate_common(prm);
+    if (s != FMM_OK) return s;
+    Shape sh;
+    s = batch_shape(prm, n_inst, counts, depths, sh);
+    if (s != FMM_OK) return s;
+    *bytes = make_layout(sh, instantiated_terms(prm->p), prm->precision == FMM_PREC_MIXED).total;
     return FMM_OK;
 }
 
@@ -171,92 +581,32 @@ fmm_status fmm_plan(const fmm_params* prm, void* d_workspace, size_t bytes, void
 {
     if (!out || !d_workspace) return FMM_E_ARG;
     *out = nullptr;
-    fmm_status s = validate(prm);
+    fmm_status s = validate_common(prm);
     if (s != FMM_OK) return s;
-    if ((reinterpret_cast<uintptr_t>(d_workspace) & 255) != 0) return FMM_E_ARG;
-    const Layout ly = make_layout(*prm);
-    if (bytes < ly.total) return FMM_E_CAPACITY;
+    Shape sh;
+    s = single_shape(prm, sh);
+    if (s != FMM_OK) return s;
+    return make_plan(prm, std::move(sh), false, d_workspace, bytes, stream, out);
+}
 
-    fmm_plan_s* pl = new (std::nothrow) fmm_plan_s();
-    if (!pl) return FMM_E_NOMEM;
-    pl->prm = *prm;
-    pl->P = instantiated_terms(prm->p);
-    pl->auto_domain = !(prm->width > 0.0);
-    pl->mixed = prm->precision == FMM_PREC_MIXED;
-    pl->last_n = -1;
-    char* base = static_cast<char*>(d_workspace);
-    Buffers& b = pl->buf;
-    b.bad_blk = reinterpret_cast<int32_t*>(base + ly.bad_blk);
-    b.dom = reinterpret_cast<Domain*>(base + ly.dom);
-    b.bbox = reinterpret_cast<double*>(base + ly.bbox);
-    b.leaf_start = reinterpret_cast<int32_t*>(base + ly.leaf_start);
-    b.hist = reinterpret_cast<int32_t*>(base + ly.hist);
-    b.hist_scan = reinterpret_cast<int32_t*>(base + ly.hist_scan);
-    b.scan_part = reinterpret_cast<int32_t*>(base + ly.scan_part);
-    b.key = reinterpret_cast<uint32_t*>(base + ly.key);
-    b.ksorted = reinterpret_cast<uint32_t*>(base + ly.ksorted);
-    b.perm = reinterpret_cast<uint32_t*>(base + ly.perm);
-    b.xs = reinterpret_cast<double*>(base + ly.xs);
-    b.ys = reinterpret_cast<double*>(base + ly.ys);
-    b.gs = reinterpret_cast<double*>(base + ly.gs);
-    b.ktmp = reinterpret_cast<uint32_t*>(base + ly.ktmp);
-    b.itmp = reinterpret_cast<uint32_t*>(base + ly.itmp);
-    b.xt = reinterpret_cast<double*>(base + ly.xt);
-    b.yt = reinterpret_cast<double*>(base + ly.yt);
-    b.gt = reinterpret_cast<double*>(base + ly.gt);
-    b.pk = pl->mixed ? reinterpret_cast<float4*>(base + ly.pk) : nullptr;
-    b.me = reinterpret_cast<cd*>(base + ly.me);
-    b.le = reinterpret_cast<cd*>(base + ly.le);
-    b.le_part[0] = reinterpret_cast<cd*>(base + ly.le_part[0]);
-    b.le_part[1] = reinterpret_cast<cd*>(base + ly.le_part[1]);
-    b.ilist = nullptr;
-    b.t_m2m = reinterpret_cast<cd*>(base + ly.t_m2m);
-    b.t_l2l = reinterpret_cast<cd*>(base + ly.t_l2l);
-    b.t_h64 = reinterpret_cast<cd*>(base + ly.t_h64);
-    b.t_h32 = reinterpret_cast<cf*>(base + ly.t_h32);
-    b.t_sin = reinterpret_cast<double*>(base + ly.t_sin);
-    b.t_sout = reinterpret_cast<double*>(base + ly.t_sout);
-
-    const int P = pl->P;
-    const size_t nh = size_t(kHankelGrid) * kHankelGrid * (2 * P - 1);
-    std::vector<cd> m2m(size_t(4) * P * P), l2l(size_t(4) * P * P), h64(nh);
-    std::vector<cf> h32(nh);
-    std::vector<double> sin_(P), sout_(P);
-    build_tables(P, prm->p, m2m.data(), l2l.data(), h64.data(), h32.data(), sin_.data(), sout_.data());
-
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    hipError_t e = hipSuccess;
-    auto cp = [&](void* dst, const void* src, size_t nbytes) {
-        if (e == hipSuccess) e = hipMemcpyAsync(dst, src, nbytes, hipMemcpyHostToDevice, st);
-    };
-    cp(b.t_m2m, m2m.data(), m2m.size() * sizeof(cd));
-    cp(b.t_l2l, l2l.data(), l2l.size() * sizeof(cd));
-    cp(b.t_h64, h64.data(), h64.size() * sizeof(cd));
-    cp(b.t_h32, h32.data(), h32.size() * sizeof(cf));
-    cp(b.t_sin, sin_.data(), sin_.size() * sizeof(double));
-    cp(b.t_sout, sout_.data(), sout_.size() * sizeof(double));
-    if (e == hipSuccess) e = hipStreamSynchronize(st);   // host tables go out of scope
-    if (e != hipSuccess) {
-        delete pl;
-        return FMM_E_DEVICE;
-    }
-    pl->have_events = true;
-    for (int r = 0; r < kTimingRing && pl->have_events; ++r)
-        for (int i = 0; i <= ST_COUNT; ++i)
-            if (hipEventCreate(&pl->ev[r][i]) != hipSuccess) {
-                for (int j = 0; j < i; ++j) hipEventDestroy(pl->ev[r][j]);
-                destroy_events(pl, r);
-                pl->have_events = false;
-                break;
-            }
-    *out = pl;
-    return FMM_OK;
+fmm_status fmm_plan_batch(const fmm_params* prm, int32_t n_inst, const int32_t* counts, const int32_t* depths,
+                          void* d_workspace, size_t bytes, void* stream, fmm_plan_t* out)
+{
+    if (!out || !d_workspace) return FMM_E_ARG;
+    *out = nullptr;
+    fmm_status s = validate_common(prm);
+    if (s != FMM_OK) return s;
+    Shape sh;
+    s = batch_shape(prm, n_inst, counts, depths, sh);
+    if (s != FMM_OK) return s;
+    return make_plan(prm, std::move(sh), true, d_workspace, bytes, stream, out);
 }
 
 fmm_status fmm_set_timing(fmm_plan_t plan, int32_t on)
 {
     if (!plan) return FMM_E_ARG;
     if (on && !plan->have_events) return FMM_E_DEVICE;
+    if (on && plan->batch) return FMM_E_UNSUPPORTED;       // a replayed graph has no stage events
     if (plan->have_events)
         for (int r = 0; r < kTimingRing; ++r)
             if (harvest(plan, r) != hipSuccess) return FMM_E_DEVICE;
@@ -269,64 +619,60 @@ fmm_status fmm_set_timing(fmm_plan_t plan, int32_t on)
 fmm_status fmm_evaluate(fmm_plan_t plan, int64_t n, const double* d_x, const double* d_y,
                         const double* d_gamma, double* d_u, double* d_v, void* stream)
 {
-    if (!plan) return FMM_E_ARG;
+    if (!plan || plan->batch) return FMM_E_ARG;
     if (n < 0) return FMM_E_ARG;
-    if (n > plan->prm.n_max) return FMM_E_CAPACITY;
+    if (n > plan->shape.n_cap) return FMM_E_CAPACITY;
     if (n > 0 && (!d_x || !d_y || !d_gamma || !d_u || !d_v)) return FMM_E_ARG;
     plan->last_n = n;
     if (n == 0) return FMM_OK;
-
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const fmm_params& prm = plan->prm;
-    const Buffers& b = plan->buf;
-    const int L = prm.depth, p = prm.p, P = plan->P;
-    const bool timing = plan->timing;
     hipError_t e = hipSuccess;
-    auto chk = [&](hipError_t r) { if (e == hipSuccess) e = r; };
     const int slot = int(plan->next_slot % kTimingRing);
-    if (timing) {
-        chk(harvest(plan, slot));
+    if (plan->timing) {
+        e = harvest(plan, slot);
         plan->next_slot += 1;
     }
-    auto mark = [&](int i) { if (timing) chk(hipEventRecord(plan->ev[slot][i], st)); };
-
-    Domain dom{};
-    if (!plan->auto_domain) {
-        dom.x0 = prm.x0;
-        dom.y0 = prm.y0;
-        dom.W = prm.width;
-        dom.s = std::ldexp(1.0, L) / prm.width;
-    }
-    const bool far = L >= 2;
-
-    mark(ST_TREE);
-    if (plan->auto_domain) chk(launch_domain(b, int(n), d_x, d_y, L, st));
-    chk(launch_tree(b, int(n), L, d_x, d_y, d_gamma, !plan->auto_domain, dom, plan->mixed, st));
-    mark(ST_UP);
-    if (far) chk(launch_upward(b, P, p, L, st));
-    mark(ST_M2L);
-    const int sl = m2l_split_level(L);
-    if (far) {
-        // levels [2, f32) in FP64, [f32, L] in FP32; levels <= sl with the
-        // interaction list split over three wavefronts
-        const int fine = plan->mixed ? prm.fp32_fine_levels : 0;
-        const int f32 = std::max(2, L - fine + 1);
-        auto run = [&](int lo, int hi, bool fp32) {
-            if (hi < lo) return;
-            const int mid = std::min(hi, sl);
-            if (lo <= mid) chk(launch_m2l(b, P, p, lo, mid, fp32, 3, st));
-            if (std::max(lo, mid + 1) <= hi) chk(launch_m2l(b, P, p, std::max(lo, mid + 1), hi, fp32, 1, st));
-        };
-        run(2, f32 - 1, false);
-        run(f32, L, true);
-    }
-    mark(ST_DOWN);
-    if (far) chk(launch_downward(b, P, p, L, sl, st));
-    mark(ST_P2P);
-    chk(launch_p2p(b, P, p, L, far, plan->mixed, prm.sigma, d_u, d_v, st));
-    mark(ST_COUNT);
-    if (timing && e == hipSuccess) plan->pending[slot] = true;
+    if (e == hipSuccess) e = enqueue_all(plan, n, d_x, d_y, d_gamma, d_u, d_v, st, plan->timing, slot);
+    if (plan->timing && e == hipSuccess) plan->pending[slot] = true;
     return e == hipSuccess ? FMM_OK : FMM_E_DEVICE;
+}
+
+fmm_status fmm_evaluate_batch(fmm_plan_t plan, const double* d_x, const double* d_y, const double* d_gamma,
+                              double* d_u, double* d_v, void* stream)
+{
+    if (!plan || !plan->batch) return FMM_E_ARG;
+    const int64_t n = plan->shape.n_cap;
+    if (n > 0 && (!d_x || !d_y || !d_gamma || !d_u || !d_v)) return FMM_E_ARG;
+    plan->last_n = n;
+    if (n == 0) return FMM_OK;
+    const void* ptrs[5] = {d_x, d_y, d_gamma, d_u, d_v};
+    bool same = plan->gexec != nullptr;
+    for (int i = 0; i < 5 && same; ++i) same = plan->gptr[i] == ptrs[i];
+    if (!same) {
+        // capture the evaluation for these arrays on the plan's own stream
+        drop_graph(plan);
+        if (!plan->cap_stream && hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+            plan->cap_stream = nullptr;
+            return FMM_E_DEVICE;
+        }
+        if (hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return FMM_E_DEVICE;
+        const hipError_t ce = enqueue_all(plan, n, d_x, d_y, d_gamma, d_u, d_v, plan->cap_stream, false, 0);
+        hipGraph_t gr = nullptr;
+        const hipError_t ee = hipStreamEndCapture(plan->cap_stream, &gr);
+        if (ce != hipSuccess || ee != hipSuccess || !gr) {
+            if (gr) hipGraphDestroy(gr);
+            return FMM_E_DEVICE;
+        }
+        plan->graph = gr;
+        if (hipGraphInstantiate(&plan->gexec, gr, nullptr, nullptr, 0) != hipSuccess) {
+            plan->gexec = nullptr;
+            drop_graph(plan);
+            return FMM_E_DEVICE;
+        }
+        for (int i = 0; i < 5; ++i) plan->gptr[i] = ptrs[i];
+    }
+    return hipGraphLaunch(plan->gexec, static_cast<hipStream_t>(stream)) == hipSuccess ? FMM_OK : FMM_E_DEVICE;
 }
 
 fmm_status fmm_get_status(fmm_plan_t plan, void* stream, int64_t* n_bad)
@@ -337,7 +683,8 @@ fmm_status fmm_get_status(fmm_plan_t plan, void* stream, int64_t* n_bad)
     hipStream_t st = static_cast<hipStream_t>(stream);
     const size_t nblk = size_t(radix_blocks(plan->last_n));
     std::vector<int32_t> per(nblk);
-    if (hipMemcpyAsync(per.data(), plan->buf.bad_blk, nblk * sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess)
+    if (hipMemcpyAsync(per.data(), plan->buf.bad_blk, nblk * sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
+        hipSuccess)
         return FMM_E_DEVICE;
     if (hipStreamSynchronize(st) != hipSuccess) return FMM_E_DEVICE;
     int64_t v = 0;
@@ -363,24 +710,134 @@ fmm_status fmm_stats(fmm_plan_t plan, double* stage_ms, int32_t n_stages, int32_
     return FMM_OK;
 }
 
+fmm_status fmm_get_tuning(fmm_plan_t plan, int32_t* p2p_waves, int32_t* m2l_split_max)
+{
+    if (!plan || !p2p_waves || !m2l_split_max) return FMM_E_ARG;
+    *p2p_waves = plan->tune.p2p_waves;
+    *m2l_split_max = plan->tune.split_max;
+    return FMM_OK;
+}
+
+fmm_status fmm_set_tuning(fmm_plan_t plan, int32_t p2p_waves, int32_t m2l_split_max, void* stream)
+{
+    if (!plan) return FMM_E_ARG;
+    if (p2p_waves != 2 && p2p_waves != 4) return FMM_E_ARG;
+    if (m2l_split_max < 0 || m2l_split_max > kM2LSplitMaxLevel) return FMM_E_ARG;
+    plan->tune.p2p_waves = p2p_waves;
+    plan->tune.split_max = m2l_split_max;
+    return upload_schedule(plan, static_cast<hipStream_t>(stream)) == hipSuccess ? FMM_OK : FMM_E_DEVICE;
+}
+
+fmm_status fmm_autotune(fmm_plan_t plan, int64_t n, const double* d_x, const double* d_y, const double* d_gamma,
+                        double* d_u, double* d_v, void* stream, int32_t reps)
+{
+    if (!plan) return FMM_E_ARG;
+    if (plan->batch) n = plan->shape.n_cap;
+    if (n <= 0 || n > plan->shape.n_cap) return FMM_E_ARG;
+    if (!d_x || !d_y || !d_gamma || !d_u || !d_v) return FMM_E_ARG;
+    if (reps < 1) reps = 3;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+
+    // signature of the problem: compiled size, precision, n and the depth mix
+    char sig[512];
+    {
+        int64_t hist[kMaxDepth + 1] = {0};
+        for (int L : plan->shape.depth) hist[L]++;
+        std::string d;
+        for (int L = 0; L <= kMaxDepth; ++L)
+            if (hist[L]) d += std::to_string(L) + "x" + std::to_string(hist[L]) + ",";
+        std::snprintf(sig, sizeof(sig), "P%d-%s-f%d-n%lld-%s", plan->P, plan->mixed ? "mixed" : "fp64",
+                      plan->mixed ? plan->prm.fp32_fine_levels : 0, (long long)n, d.c_str());
+    }
+    const char* cache = std::getenv("FMM_AUTOTUNE_CACHE");
+    if (cache && *cache) {
+        if (FILE* f = std::fopen(cache, "r")) {
+            char key[512];
+            int w = 0, sm = 0;
+            bool found = false;
+            while (std::fscanf(f, "%511s %d %d", key, &w, &sm) == 3)
+                if (std::strcmp(key, sig) == 0) found = true;   // the last entry wins
+            std::fclose(f);
+            if (found) return fmm_set_tuning(plan, w, sm, stream);
+        }
+    }
+
+    const Tuning saved = plan->tune;
+    const bool was_timing = plan->timing;
+    plan->timing = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess) return FMM_E_DEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return FMM_E_DEVICE;
+    }
+    const int waves[2] = {2, 4};
+    const int splits[3] = {0, 5, kM2LSplitMaxLevel};
+    float best = 1e30f;
+    Tuning best_t = saved;
+    fmm_status rs = FMM_OK;
+    for (int wi = 0; wi < 2 && rs == FMM_OK; ++wi)
+        for (int si = 0; si < 3 && rs == FMM_OK; ++si) {
+            rs = fmm_set_tuning(plan, waves[wi], splits[si], stream);
+            if (rs == FMM_OK) rs = run_once(plan, n, d_x, d_y, d_gamma, d_u, d_v, stream);   // warm-up, capture
+            float tmin = 1e30f;
+            for (int r = 0; r < reps && rs == FMM_OK; ++r) {
+                if (hipEventRecord(e0, st) != hipSuccess) { rs = FMM_E_DEVICE; break; }
+                rs = run_once(plan, n, d_x, d_y, d_gamma, d_u, d_v, stream);
+                if (rs != FMM_OK) break;
+                if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                    rs = FMM_E_DEVICE;
+                    break;
+                }
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rs = FMM_E_DEVICE; break; }
+                tmin = std::min(tmin, ms);
+            }
+            if (rs == FMM_OK && tmin < best) {
+                best = tmin;
+                best_t = plan->tune;
+            }
+        }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    plan->timing = was_timing;
+    if (rs != FMM_OK) {
+        plan->tune = saved;
+        upload_schedule(plan, st);
+        return rs;
+    }
+    rs = fmm_set_tuning(plan, best_t.p2p_waves, best_t.split_max, stream);
+    if (rs == FMM_OK && cache && *cache) {
+        if (FILE* f = std::fopen(cache, "a")) {
+            std::fprintf(f, "%s %d %d\n", sig, best_t.p2p_waves, best_t.split_max);
+            std::fclose(f);
+        }
+    }
+    return rs;
+}
+
 fmm_status fmm_debug_dump(fmm_plan_t plan, int32_t what, void* host_buf, size_t bytes, size_t* needed)
 {
     if (!plan || !needed) return FMM_E_ARG;
     const fmm_params& prm = plan->prm;
-    const int L = prm.depth;
     const size_t n = size_t(std::max<int64_t>(plan->last_n, 0));
-    const size_t nleaf = size_t(1) << (2 * L);
-    const size_t nbox = size_t(level_offset(L + 1));
+    const size_t nbox = size_t(plan->shape.boxes);
     const void* src = nullptr;
     size_t sz = 0;
     switch (what) {
         case FMM_DUMP_KEYS: src = plan->buf.key; sz = n * sizeof(uint32_t); break;
         case FMM_DUMP_PERM: src = plan->buf.perm; sz = n * sizeof(uint32_t); break;
-        case FMM_DUMP_LEAF_START: src = plan->buf.leaf_start; sz = (nleaf + 1) * sizeof(int32_t); break;
-        case FMM_DUMP_ME: src = plan->buf.me; sz = nbox * prm.p * sizeof(cd); break;   // stored with stride P
+        case FMM_DUMP_LEAF_START:
+            src = plan->buf.leaf_start;
+            sz = size_t(plan->shape.leaf_entries) * sizeof(int32_t);
+            break;
+        case FMM_DUMP_ME: src = plan->buf.me; sz = nbox * prm.p * sizeof(cd); break;   // device rows: stride P
         case FMM_DUMP_LE: src = plan->buf.le; sz = nbox * prm.p * sizeof(cd); break;
-        case FMM_DUMP_DOMAIN: src = plan->buf.dom; sz = sizeof(Domain); break;
-        case FMM_DUMP_ILIST: sz = nbox * 27 * sizeof(int32_t); break;
+        case FMM_DUMP_DOMAIN: src = &plan->buf.inst[0].dom; sz = sizeof(Domain); break;
+        case FMM_DUMP_ILIST:
+            if (plan->shape.n_inst != 1) return FMM_E_UNSUPPORTED;
+            sz = nbox * 27 * sizeof(int32_t);
+            break;
         default: return FMM_E_ARG;
     }
     *needed = sz;
@@ -388,12 +845,12 @@ fmm_status fmm_debug_dump(fmm_plan_t plan, int32_t what, void* host_buf, size_t 
     if (sz == 0) return FMM_OK;
     if (hipDeviceSynchronize() != hipSuccess) return FMM_E_DEVICE;
     if (what == FMM_DUMP_ILIST) {
-        // debug only: a temporary device buffer for the lists
+        // inspection only: a temporary device buffer for the lists
         int32_t* d = nullptr;
         if (hipMalloc(&d, sz) != hipSuccess) return FMM_E_DEVICE;
         Buffers b = plan->buf;
         b.ilist = d;
-        hipError_t e = launch_ilist(b, L, nullptr);
+        hipError_t e = launch_ilist(b, plan->shape.depth[0], nullptr);
         if (e == hipSuccess) e = hipMemcpy(host_buf, d, sz, hipMemcpyDeviceToHost);
         hipFree(d);
         return e == hipSuccess ? FMM_OK : FMM_E_DEVICE;
@@ -420,6 +877,8 @@ fmm_status fmm_destroy(fmm_plan_t plan)
         for (int r = 0; r < kTimingRing; ++r) harvest(plan, r);
         destroy_events(plan, kTimingRing);
     }
+    drop_graph(plan);
+    if (plan->cap_stream) hipStreamDestroy(plan->cap_stream);
     delete plan;
     return FMM_OK;
 }

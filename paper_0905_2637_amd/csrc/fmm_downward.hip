@@ -27,11 +27,13 @@
 namespace fmm {
 namespace {
 
-struct LevelBlocks {
-    int nlev;
-    int level[kMaxDepth + 1];
-    int begin[kMaxDepth + 2];
-};
+// Workgroups of one level: 16 x 16 target boxes each (one for levels < 4).
+__host__ __device__ inline int level_blocks(int l)
+{
+    const int side = 1 << l;
+    const int bpr = side >= 16 ? side / 16 : 1;
+    return bpr * bpr;
+}
 
 // gridDim.y = G in {1, 3}: workgroup row g takes every G-th member of the
 // interaction list and writes its partial sum to out[g] (out[0] = le).
@@ -39,19 +41,20 @@ struct M2LOut {
     cd* out[3];
 };
 
+// Work table arg: the instance's level range [lmin, lmax] in this launch.
 template <int P, typename T>
 __global__ void __launch_bounds__(256)
-k_m2l(LevelBlocks lb, const cd* __restrict__ me, M2LOut dst_, const cplx<T>* __restrict__ H,
-      const double* __restrict__ sin_, const double* __restrict__ sout_)
+k_m2l(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restrict__ me_all, M2LOut dst_,
+      const cplx<T>* __restrict__ H, const double* __restrict__ sin_, const double* __restrict__ sout_)
 {
     const int G = gridDim.y, g = blockIdx.y;
-    cd* __restrict__ le = dst_.out[g];
-    const int blk = blockIdx.x;
-    int li = 0;
-    while (li + 1 < lb.nlev && blk >= lb.begin[li + 1]) ++li;
-    const int l = lb.level[li];
+    const int q = find_inst(wk.wg_begin, n_inst, blockIdx.x);
+    int bl = blockIdx.x - wk.wg_begin[q];
+    int l = wk.arg[2 * q];
+    while (bl >= level_blocks(l)) { bl -= level_blocks(l); ++l; }
+    const cd* me = me_all + inst[q].box_off * P;
+    cd* __restrict__ le = g == 0 ? dst_.out[0] + inst[q].box_off * P : dst_.out[g] + inst[q].split_off * P;
     const int side = 1 << l;
-    const int bl = blk - lb.begin[li];
     const int bpr = side >= 16 ? side / 16 : 1;
     const int bx = bl % bpr, by = bl / bpr;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -113,16 +116,23 @@ constexpr int kDownThreads = 256;
 // part[0], part[1]: partial M2L sums of levels <= split_level (M2L ran with
 // its interaction list split over three wavefronts there); they are added
 // to le when a level's M2L result is first read.
+// Work table arg: lt, d.
 template <int P>
 __global__ void __launch_bounds__(kDownThreads)
-k_downward(int lt, int d, cd* __restrict__ le, const cd* __restrict__ Lt, const cd* __restrict__ part0,
-           const cd* __restrict__ part1, int split_level)
+k_downward(Work wk, int n_inst, const Inst* __restrict__ inst, cd* __restrict__ le_all,
+           const cd* __restrict__ Lt, const cd* __restrict__ part0_all, const cd* __restrict__ part1_all)
 {
     __shared__ cd sh[85 * P];
     __shared__ cd sL[4 * P * P];
     const int tid = threadIdx.x;
+    const int q = find_inst(wk.wg_begin, n_inst, blockIdx.x);
+    const int64_t root = blockIdx.x - wk.wg_begin[q];
+    const int lt = wk.arg[2 * q], d = wk.arg[2 * q + 1];
+    const int split_level = inst[q].split;
+    cd* le = le_all + inst[q].box_off * P;
+    const cd* part0 = part0_all + inst[q].split_off * P;
+    const cd* part1 = part1_all + inst[q].split_off * P;
     for (int e = tid; e < 4 * P * P; e += kDownThreads) sL[e] = Lt[e];
-    const int64_t root = blockIdx.x;
     const int64_t ri = (level_offset(lt) + root) * P;
     for (int k = tid; k < P; k += kDownThreads) {
         cd v = le[ri + k];
@@ -191,81 +201,60 @@ __global__ void __launch_bounds__(256) k_ilist(int L, int32_t* __restrict__ out)
     for (; cnt < 27; ++cnt) dst[cnt] = -1;
 }
 
-LevelBlocks make_levels(int lmin, int lmax)
-{
-    LevelBlocks lb{};
-    lb.nlev = 0;
-    int acc = 0;
-    for (int l = lmin; l <= lmax; ++l) {
-        const int side = 1 << l;
-        const int bpr = side >= 16 ? side / 16 : 1;
-        lb.level[lb.nlev] = l;
-        lb.begin[lb.nlev] = acc;
-        acc += bpr * bpr;
-        ++lb.nlev;
-    }
-    lb.begin[lb.nlev] = acc;
-    return lb;
-}
-
 template <int P>
-hipError_t m2l_impl(const Buffers& b, int p, int lmin, int lmax, bool fp32, int groups, hipStream_t st)
+hipError_t m2l_impl(const Buffers& b, const Work& w, int nwg, bool fp32, int groups, hipStream_t st)
 {
-    if (lmax < lmin) return hipSuccess;
-    const LevelBlocks lb = make_levels(lmin, lmax);
-    const dim3 grid(unsigned(lb.begin[lb.nlev]), unsigned(groups));
+    if (nwg <= 0) return hipSuccess;
+    const dim3 grid{unsigned(nwg), unsigned(groups), 1u};
     const M2LOut out{{b.le, b.le_part[0], b.le_part[1]}};
     if constexpr (P <= 24) {
         if (fp32) {
-            hipLaunchKernelGGL((k_m2l<P, float>), grid, dim3(256), 0, st, lb, b.me, out,
+            hipLaunchKernelGGL((k_m2l<P, float>), grid, dim3(256), 0, st, w, b.n_inst, b.inst, b.me, out,
                                reinterpret_cast<const cplx<float>*>(b.t_h32), b.t_sin, b.t_sout);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((k_m2l<P, double>), grid, dim3(256), 0, st, lb, b.me, out,
+    hipLaunchKernelGGL((k_m2l<P, double>), grid, dim3(256), 0, st, w, b.n_inst, b.inst, b.me, out,
                        reinterpret_cast<const cplx<double>*>(b.t_h64), b.t_sin, b.t_sout);
     return hipGetLastError();
 }
 
 template <int P>
-hipError_t downward_impl(const Buffers& b, int p, int L, int split_level, hipStream_t st)
+hipError_t downward_impl(const Buffers& b, const Work& w, int nwg, hipStream_t st)
 {
-    for (int lt = 2; lt < L; lt += 3) {
-        const int d = std::min(3, L - lt);
-        const int64_t nroot = int64_t(1) << (2 * lt);
-        hipLaunchKernelGGL(k_downward<P>, dim3(unsigned(nroot)), dim3(kDownThreads), 0, st, lt, d, b.le,
-                           b.t_l2l, b.le_part[0], b.le_part[1], split_level);
-    }
+    if (nwg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_downward<P>, dim3(unsigned(nwg)), dim3(kDownThreads), 0, st, w, b.n_inst, b.inst, b.le,
+                       b.t_l2l, b.le_part[0], b.le_part[1]);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_m2l(const Buffers& b, int P, int p, int lmin, int lmax, bool fp32, int groups, hipStream_t st)
+hipError_t launch_m2l(const Buffers& b, int P, const Work& w, int nwg, bool fp32, int groups, hipStream_t st)
 {
     switch (P) {
-        case 8: return m2l_impl<8>(b, p, lmin, lmax, fp32, groups, st);
-        case 12: return m2l_impl<12>(b, p, lmin, lmax, fp32, groups, st);
-        case 16: return m2l_impl<16>(b, p, lmin, lmax, fp32, groups, st);
-        case 17: return m2l_impl<17>(b, p, lmin, lmax, fp32, groups, st);
-        case 20: return m2l_impl<20>(b, p, lmin, lmax, fp32, groups, st);
-        case 24: return m2l_impl<24>(b, p, lmin, lmax, fp32, groups, st);
+        case 8: return m2l_impl<8>(b, w, nwg, fp32, groups, st);
+        case 12: return m2l_impl<12>(b, w, nwg, fp32, groups, st);
+        case 16: return m2l_impl<16>(b, w, nwg, fp32, groups, st);
+        case 17: return m2l_impl<17>(b, w, nwg, fp32, groups, st);
+        case 20: return m2l_impl<20>(b, w, nwg, fp32, groups, st);
+        case 24: return m2l_impl<24>(b, w, nwg, fp32, groups, st);
         case 32:   // FP32 translation data would overflow: mixed mode stops at p = 22
-            return fp32 ? hipErrorInvalidValue : m2l_impl<32>(b, p, lmin, lmax, false, groups, st);
+            return fp32 ? hipErrorInvalidValue : m2l_impl<32>(b, w, nwg, false, groups, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_downward(const Buffers& b, int P, int p, int L, int split_level, hipStream_t st)
+hipError_t launch_downward(const Buffers& b, int P, const Work& w, int nwg, hipStream_t st)
 {
     switch (P) {
-        case 8: return downward_impl<8>(b, p, L, split_level, st);
-        case 12: return downward_impl<12>(b, p, L, split_level, st);
-        case 16: return downward_impl<16>(b, p, L, split_level, st);
-        case 17: return downward_impl<17>(b, p, L, split_level, st);
-        case 20: return downward_impl<20>(b, p, L, split_level, st);
-        case 24: return downward_impl<24>(b, p, L, split_level, st);
-        case 32: return downward_impl<32>(b, p, L, split_level, st);
+        case 8: return downward_impl<8>(b, w, nwg, st);
+        case 12: return downward_impl<12>(b, w, nwg, st);
+        case 16: return downward_impl<16>(b, w, nwg, st);
+        case 17: return downward_impl<17>(b, w, nwg, st);
+        case 20: return downward_impl<20>(b, w, nwg, st);
+        case 24: return downward_impl<24>(b, w, nwg, st);
+        case 32: return downward_impl<32>(b, w, nwg, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -1,5 +1,14 @@
 // fmm_internal.h -- types and launcher declarations shared by the library's
 // translation units.  Not part of the public ABI (see include/fmm.h).
+//
+// A plan holds one or more FMM instances (a single evaluation is a batch of
+// one).  Every instance has its own uniform quadtree of depth L_i over its own
+// square; the instances' particles are concatenated, and their leaf ranges,
+// multipole and local expansions live in per-instance segments of shared
+// arrays.  Each stage is one launch over the work of all instances: the
+// workgroups of a launch are numbered instance after instance, and a
+// workgroup finds its instance in a prefix table built on the host at plan
+// time.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -8,7 +17,7 @@
 
 namespace fmm {
 
-// Square domain of one evaluation: [x0, x0 + W]^2 and s = 2^L / W, the
+// Square domain of one instance: [x0, x0 + W]^2 and s = 2^L / W, the
 // reciprocal of the leaf width, computed as one correctly rounded division.
 struct Domain {
     double x0, y0, W, s;
@@ -22,6 +31,7 @@ constexpr int kMaxP = 32;
 constexpr int kMaxPMixed = 22;      // FP32 translation data overflows beyond this
 constexpr int kHankelGrid = 7;      // integer M2L offsets (dx, dy) with |dx|, |dy| <= 3
 constexpr int kBBoxBlocks = 256;
+constexpr int kMaxInstances = 1 << 16;
 
 // Number of boxes in levels 0 .. l-1, i.e. the global id of the first box of
 // level l (Section 5.3 counts (4^(L+1) - 1)/3 boxes in a full quadtree).
@@ -38,16 +48,53 @@ inline int instantiated_terms(int p)
     return -1;
 }
 
+// M2L on levels up to an instance's split level runs with the interaction
+// list split over three wavefronts (more parallelism where levels have few
+// boxes); the partial sums go to two extra buffers sized for levels up to
+// kM2LSplitMaxLevel and are added by the downward sweep.
+constexpr int kM2LSplitMaxLevel = 8;
+
+// One instance of a plan (device table, built on the host).
+struct Inst {
+    int64_t part_off;    // first particle in the concatenated arrays
+    int64_t leaf_off;    // first entry of its leaf_start segment (4^L + 1 entries)
+    int64_t box_off;     // first box of its expansion segments (Lambda(L) boxes)
+    int64_t split_off;   // first box of its partial-M2L segments
+    int32_t L;           // depth
+    int32_t split;       // M2L split level (levels 2 .. split have partial sums)
+    Domain dom;          // its square; s = 2^L / W
+};
+
+// Per-launch work table: workgroups [wg_begin[i], wg_begin[i+1]) belong to
+// instance i; arg[2i], arg[2i+1] carry launch-specific values for it.
+struct Work {
+    const int32_t* wg_begin;
+    const int32_t* arg;
+};
+
+// Instance of workgroup `wg` (uniform binary search over the prefix table).
+__device__ __forceinline__ int find_inst(const int32_t* __restrict__ wg_begin, int n_inst, int wg)
+{
+    int lo = 0, hi = n_inst;      // wg_begin[lo] <= wg < wg_begin[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (wg_begin[mid] <= wg) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
 // Device pointers of one plan, all inside the caller's workspace.
 struct Buffers {
-    int32_t* bad_blk;      // [radix blocks] particles outside the explicit domain / NaN, per tile
-    Domain* dom;
+    Inst* inst;            // [n_inst]
+    int n_inst;
+    int key_shift;         // 2 * (deepest depth): the instance id sits above it
+    int32_t* bad_blk;      // [radix blocks] particles outside the domain / NaN, per tile
     double* bbox;          // [4 * kBBoxBlocks] partial bounding boxes
-    int32_t* leaf_start;   // [nleaf + 1]
+    int32_t* leaf_start;   // [sum (4^L_i + 1)] sorted ranges of every leaf of every instance
     int32_t* hist;         // [256 * radix blocks] digit-major tile histograms
     int32_t* hist_scan;    // [256 * radix blocks + 1] exclusive scan of hist, then the total
     int32_t* scan_part;    // [scan chunks + 1]
-    uint32_t* key;         // [n_max] leaf z-order key per input particle
+    uint32_t* key;         // [n_max] instance and leaf key per input particle
     uint32_t* ksorted;     // [n_max] sorted keys
     uint32_t* perm;        // [n_max] sorted position -> input index
     double* xs;            // [n_max] sorted positions and circulations
@@ -59,10 +106,10 @@ struct Buffers {
     double* yt;
     double* gt;
     float4* pk;            // [n_max] mixed: leaf-relative FP32 (ox, oy, gamma, 0)
-    cd* me;                // [Lambda * p] scaled multipole coefficients
-    cd* le;                // [Lambda * p] scaled local coefficients
-    cd* le_part[2];        // [Lambda(split level) * p] partial M2L sums of the split levels
-    int32_t* ilist;        // [Lambda * 27] debug: interaction lists
+    cd* me;                // [sum Lambda_i * P] scaled multipole coefficients, zero-padded to P
+    cd* le;                // [sum Lambda_i * P] scaled local coefficients
+    cd* le_part[2];        // [sum Lambda(split)_i * P] partial M2L sums of the split levels
+    int32_t* ilist;        // debug: interaction lists
     cd* t_m2m;             // [4][P][P]
     cd* t_l2l;             // [4][P][P]
     cd* t_h64;             // [49][2P-1] M2L translation data, FP64
@@ -71,35 +118,26 @@ struct Buffers {
     double* t_sout;        // [P] 1 / l!
 };
 
-struct Layout {
-    size_t bad_blk, dom, bbox, leaf_start, hist, hist_scan, scan_part, key, ksorted, perm, xs, ys, gs;
-    size_t ktmp, itmp, xt, yt, gt, pk, me, le, le_part[2], t_m2m, t_l2l, t_h64, t_h32, t_sin, t_sout;
-    size_t total;
-};
-
-// Radix sort geometry (fmm_tree.hip): passes of 8-bit digits over 2L key
-// bits, and workgroup tiles of 4096 keys.
-int radix_passes(int L);
-int64_t radix_blocks(int64_t n);
-
 // Chunk of the histogram scan handled by one workgroup.
 constexpr int kScanChunk = 2048;
 
+// Radix sort geometry (fmm_tree.hip): passes of 8-bit digits over the key
+// bits, and workgroup tiles of 4096 keys.
+int radix_passes(int key_bits);
+int64_t radix_blocks(int64_t n);
+
 // ---- launchers (each enqueues on `st` and returns the launch status) -------
 
+// auto domain (single instance): bounding square into inst[0].dom
 hipError_t launch_domain(const Buffers& b, int n, const double* x, const double* y, int L, hipStream_t st);
-hipError_t launch_tree(const Buffers& b, int n, int L, const double* x, const double* y, const double* g,
-                       bool explicit_dom, Domain hdom, bool mixed, hipStream_t st);
-hipError_t launch_upward(const Buffers& b, int P, int p, int L, hipStream_t st);     // P2M + M2M
-hipError_t launch_m2l(const Buffers& b, int P, int p, int lmin, int lmax, bool fp32, int groups, hipStream_t st);
-hipError_t launch_downward(const Buffers& b, int P, int p, int L, int split_level, hipStream_t st);   // L2L
-
-// Levels up to this one run M2L with the interaction list split over three
-// wavefronts (more parallelism where a level has few boxes); deeper levels
-// have enough boxes to fill the GPU with one wavefront per 64 boxes.
-constexpr int kM2LSplitMaxLevel = 8;
-inline int m2l_split_level(int L) { return L <= 2 ? 1 : (L < kM2LSplitMaxLevel ? L : kM2LSplitMaxLevel); }
-hipError_t launch_p2p(const Buffers& b, int P, int p, int L, bool has_far, bool mixed, double sigma,
+hipError_t launch_tree(const Buffers& b, int n, const double* x, const double* y, const double* g,
+                       int key_bits, int64_t leaf_entries, bool mixed, hipStream_t st);
+// P2M + M2M of up to three levels per launch; `from_particles` for the first
+hipError_t launch_upward(const Buffers& b, int P, int p, const Work& w, int nwg, bool from_particles,
+                         hipStream_t st);
+hipError_t launch_m2l(const Buffers& b, int P, const Work& w, int nwg, bool fp32, int groups, hipStream_t st);
+hipError_t launch_downward(const Buffers& b, int P, const Work& w, int nwg, hipStream_t st);   // L2L
+hipError_t launch_p2p(const Buffers& b, int P, const Work& w, int nwg, int waves, bool mixed, double sigma,
                       double* u, double* v, hipStream_t st);
 hipError_t launch_ilist(const Buffers& b, int L, hipStream_t st);
 

@@ -88,7 +88,6 @@ __device__ __forceinline__ double recip(double x)
 }
 
 constexpr int kNearStage = 256;    // staged sources per chunk and wavefront
-constexpr int kNearWaves = 4;      // independent wavefronts per workgroup
 
 // Orders one wavefront's LDS writes before its later LDS reads (the lanes of
 // a wavefront run in lockstep, so this is all the synchronisation needed).
@@ -268,19 +267,26 @@ __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* 
     }
 }
 
-template <int P, bool MIXED>
-__global__ void __launch_bounds__(64 * kNearWaves)
-k_p2p_l2p(int L, int has_far, const int32_t* __restrict__ leaf_start, const double* __restrict__ xs,
-          const double* __restrict__ ys, const double* __restrict__ gs, const float4* __restrict__ pk,
-          const uint32_t* __restrict__ perm, const cd* __restrict__ le_leaf, const Domain* __restrict__ dom,
+// WAVES independent wavefronts per workgroup, one leaf each; the work table
+// gives every instance ceil(4^L / WAVES) workgroups.
+template <int P, bool MIXED, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES)
+k_p2p_l2p(Work wk, int n_inst, const Inst* __restrict__ inst, const int32_t* __restrict__ leaf_start_all,
+          const double* __restrict__ xs, const double* __restrict__ ys, const double* __restrict__ gs,
+          const float4* __restrict__ pk, const uint32_t* __restrict__ perm, const cd* __restrict__ le_all,
           double inv2s2, double* __restrict__ u, double* __restrict__ v)
 {
     using Stage = typename std::conditional<MIXED, float4, Src64>::type;
-    __shared__ Stage stage_all[kNearWaves][kNearStage];
+    __shared__ Stage stage_all[WAVES][kNearStage];
 
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int qi = find_inst(wk.wg_begin, n_inst, blockIdx.x);
+    const int L = inst[qi].L;
+    const int has_far = L >= 2 ? 1 : 0;
+    const int32_t* leaf_start = leaf_start_all + inst[qi].leaf_off;
+    const cd* le_leaf = le_all + (inst[qi].box_off + level_offset(L)) * P;
     const int64_t nleaf = int64_t(1) << (2 * L);
-    const int64_t mm = int64_t(blockIdx.x) * kNearWaves + wv;
+    const int64_t mm = int64_t(blockIdx.x - wk.wg_begin[qi]) * WAVES + wv;
     if (mm >= nleaf) return;
     LeafCtx c;
     c.m = uint32_t(mm);
@@ -306,7 +312,7 @@ k_p2p_l2p(int L, int has_far, const int32_t* __restrict__ leaf_start, const doub
     }
     c.lgT = c.nt >= 64 ? 6 : (c.nt <= 1 ? 0 : 32 - __clz(c.nt - 1));
 
-    const Domain d = *dom;
+    const Domain d = inst[qi].dom;
     const double w = ldexp(d.W, -L);
     c.cx = d.x0 + (double(a) + 0.5) * w;
     c.cy = d.y0 + (double(b) + 0.5) * w;
@@ -327,37 +333,45 @@ k_p2p_l2p(int L, int has_far, const int32_t* __restrict__ leaf_start, const doub
         leaf_near_far<P, MIXED, 1>(c, lane, st, has_far, xs, ys, gs, pk, perm, le_leaf, u, v);
 }
 
-template <int P>
-hipError_t p2p_impl(const Buffers& b, int p, int L, bool has_far, bool mixed, double sigma, double* u,
-                    double* v, hipStream_t st)
+template <int P, int WAVES>
+hipError_t p2p_impl(const Buffers& b, const Work& w, int nwg, bool mixed, double sigma, double* u, double* v,
+                    hipStream_t st)
 {
-    const int64_t nleaf = int64_t(1) << (2 * L);
+    if (nwg <= 0) return hipSuccess;
     const double inv2s2 = 1.0 / (2.0 * sigma * sigma);
-    const cd* le_leaf = b.le + level_offset(L) * P;
-    const unsigned ngrp = unsigned((nleaf + kNearWaves - 1) / kNearWaves);
-    if (mixed) {
-        hipLaunchKernelGGL((k_p2p_l2p<P, true>), dim3(ngrp), dim3(64 * kNearWaves), 0, st, L, has_far ? 1 : 0,
-                           b.leaf_start, b.xs, b.ys, b.gs, b.pk, b.perm, le_leaf, b.dom, inv2s2, u, v);
-    } else {
-        hipLaunchKernelGGL((k_p2p_l2p<P, false>), dim3(ngrp), dim3(64 * kNearWaves), 0, st, L, has_far ? 1 : 0,
-                           b.leaf_start, b.xs, b.ys, b.gs, b.pk, b.perm, le_leaf, b.dom, inv2s2, u, v);
-    }
+    if (mixed)
+        hipLaunchKernelGGL((k_p2p_l2p<P, true, WAVES>), dim3(unsigned(nwg)), dim3(64 * WAVES), 0, st, w, b.n_inst,
+                           b.inst, b.leaf_start, b.xs, b.ys, b.gs, b.pk, b.perm, b.le, inv2s2, u, v);
+    else
+        hipLaunchKernelGGL((k_p2p_l2p<P, false, WAVES>), dim3(unsigned(nwg)), dim3(64 * WAVES), 0, st, w, b.n_inst,
+                           b.inst, b.leaf_start, b.xs, b.ys, b.gs, b.pk, b.perm, b.le, inv2s2, u, v);
     return hipGetLastError();
+}
+
+template <int P>
+hipError_t p2p_waves(const Buffers& b, const Work& w, int nwg, int waves, bool mixed, double sigma, double* u,
+                     double* v, hipStream_t st)
+{
+    switch (waves) {
+        case 2: return p2p_impl<P, 2>(b, w, nwg, mixed, sigma, u, v, st);
+        case 4: return p2p_impl<P, 4>(b, w, nwg, mixed, sigma, u, v, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
 
-hipError_t launch_p2p(const Buffers& b, int P, int p, int L, bool has_far, bool mixed, double sigma,
+hipError_t launch_p2p(const Buffers& b, int P, const Work& w, int nwg, int waves, bool mixed, double sigma,
                       double* u, double* v, hipStream_t st)
 {
     switch (P) {
-        case 8: return p2p_impl<8>(b, p, L, has_far, mixed, sigma, u, v, st);
-        case 12: return p2p_impl<12>(b, p, L, has_far, mixed, sigma, u, v, st);
-        case 16: return p2p_impl<16>(b, p, L, has_far, mixed, sigma, u, v, st);
-        case 17: return p2p_impl<17>(b, p, L, has_far, mixed, sigma, u, v, st);
-        case 20: return p2p_impl<20>(b, p, L, has_far, mixed, sigma, u, v, st);
-        case 24: return p2p_impl<24>(b, p, L, has_far, mixed, sigma, u, v, st);
-        case 32: return p2p_impl<32>(b, p, L, has_far, mixed, sigma, u, v, st);
+        case 8: return p2p_waves<8>(b, w, nwg, waves, mixed, sigma, u, v, st);
+        case 12: return p2p_waves<12>(b, w, nwg, waves, mixed, sigma, u, v, st);
+        case 16: return p2p_waves<16>(b, w, nwg, waves, mixed, sigma, u, v, st);
+        case 17: return p2p_waves<17>(b, w, nwg, waves, mixed, sigma, u, v, st);
+        case 20: return p2p_waves<20>(b, w, nwg, waves, mixed, sigma, u, v, st);
+        case 24: return p2p_waves<24>(b, w, nwg, waves, mixed, sigma, u, v, st);
+        case 32: return p2p_waves<32>(b, w, nwg, waves, mixed, sigma, u, v, st);
         default: return hipErrorInvalidValue;
     }
 }

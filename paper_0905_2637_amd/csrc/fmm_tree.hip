@@ -14,6 +14,11 @@
 // the final permutation is the unique one with ties in input order, and no
 // global atomics are involved: the result is bit-for-bit reproducible.
 //
+// Several instances sort together: the key of a particle of instance i is
+// (i << 2 L_max) | (leaf key at depth L_i << 2 (L_max - L_i)), which orders
+// instances first and leaves within each instance, so every instance's
+// particles end up contiguous and in their own leaf order.
+//
 // The particle record (key, input index, x, y, gamma) travels with the sort,
 // so every pass reads and writes whole streams (the scatter writes runs of
 // ~16 records per digit and tile) and no random gather follows: the last pass
@@ -191,34 +196,43 @@ constexpr int kRadixThreads = 256;
 constexpr int kRadixRounds = 16;
 constexpr int kRadixTile = kRadixThreads * kRadixRounds;   // keys per workgroup
 
-// First pass: z-order key of every particle (kept in input order for
+// Instance owning input particle i (its particles are [part_off, next part_off)).
+__device__ __forceinline__ int particle_inst(const Inst* __restrict__ inst, int n_inst, int64_t i)
+{
+    int lo = 0, hi = n_inst;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (inst[mid].part_off <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// First pass: the sort key of every particle (kept in input order for
 // inspection), the out-of-domain count of the tile, and the tile's histogram
-// of the lowest digit.  In explicit-domain mode the domain comes as an
-// argument and block 0 stores it for the later stages.
+// of the lowest digit.
 __global__ void __launch_bounds__(kRadixThreads)
-k_rhist_keys(int n, const double* __restrict__ x, const double* __restrict__ y, const Domain* ddom,
-             Domain hdom, int explicit_dom, int L, int nblk, uint32_t* __restrict__ key,
-             int32_t* __restrict__ hist, int32_t* __restrict__ bad_blk, Domain* dom_out)
+k_rhist_keys(int n, const double* __restrict__ x, const double* __restrict__ y, const Inst* __restrict__ inst,
+             int n_inst, int key_shift, int nblk, uint32_t* __restrict__ key, int32_t* __restrict__ hist,
+             int32_t* __restrict__ bad_blk)
 {
     __shared__ int h[kRadixBins];
     __shared__ int nbad;
-    const Domain d = explicit_dom ? hdom : *ddom;
-    if (threadIdx.x == 0) {
-        nbad = 0;
-        if (explicit_dom && blockIdx.x == 0) *dom_out = hdom;
-    }
+    if (threadIdx.x == 0) nbad = 0;
     h[threadIdx.x] = 0;
     __syncthreads();
-    const int side = 1 << L;
     const int64_t base = int64_t(blockIdx.x) * kRadixTile;
     int mybad = 0;
     for (int r = 0; r < kRadixRounds; ++r) {
         const int64_t i = base + r * kRadixThreads + threadIdx.x;
         if (i < n) {
+            const int q = n_inst == 1 ? 0 : particle_inst(inst, n_inst, i);
+            const int L = inst[q].L;
+            const Domain d = inst[q].dom;
+            const int side = 1 << L;
             bool bad = false;
             const int a = axis_box(x[i], d.x0, d.s, side, bad);
             const int b = axis_box(y[i], d.y0, d.s, side, bad);
-            const uint32_t k = morton(uint32_t(a), uint32_t(b));
+            const uint32_t k = (uint32_t(q) << key_shift) | (morton(uint32_t(a), uint32_t(b)) << (key_shift - 2 * L));
             key[i] = k;
             atomicAdd(&h[k & (kRadixBins - 1)], 1);
             mybad += bad ? 1 : 0;
@@ -228,6 +242,22 @@ k_rhist_keys(int n, const double* __restrict__ x, const double* __restrict__ y, 
     __syncthreads();
     hist[int64_t(threadIdx.x) * nblk + blockIdx.x] = h[threadIdx.x];
     if (threadIdx.x == 0) bad_blk[blockIdx.x] = nbad;
+}
+
+// Leaf (a, b), depth and domain of a sort key.
+struct KeyLeaf {
+    int q, L;
+    uint32_t local;      // leaf key at depth L
+};
+
+__device__ __forceinline__ KeyLeaf key_leaf(uint32_t k, const Inst* __restrict__ inst, int key_shift)
+{
+    KeyLeaf r;
+    r.q = key_shift >= 32 ? 0 : int(k >> key_shift);
+    r.L = inst[r.q].L;
+    const uint32_t mask = key_shift >= 32 ? 0xFFFFFFFFu : ((1u << key_shift) - 1u);
+    r.local = (k & mask) >> (key_shift - 2 * r.L);
+    return r;
 }
 
 // Digit histogram of one tile, written digit-major: hist[d * nblk + block].
@@ -272,7 +302,7 @@ __global__ void __launch_bounds__(kRadixThreads)
 k_rscatter(int n, const uint32_t* __restrict__ kin, const uint32_t* __restrict__ iin,
            const double* __restrict__ xin, const double* __restrict__ yin, const double* __restrict__ gin,
            int shift, int nblk, const int32_t* __restrict__ hist, const int32_t* __restrict__ offs, Records out,
-           float4* __restrict__ pk, const Domain* __restrict__ dom, int L)
+           float4* __restrict__ pk, const Inst* __restrict__ inst, int key_shift)
 {
     __shared__ int gbase[kRadixBins];      // global start of this tile's run of digit d
     __shared__ int tstart[kRadixBins];     // start of digit d in the sorted tile
@@ -383,21 +413,17 @@ k_rscatter(int n, const uint32_t* __restrict__ kin, const uint32_t* __restrict__
     for (int r = 0; r < kPerThread; ++r)
         if (lpos[r] >= 0) sv[lpos[r]] = gr[r];
     __syncthreads();
-    Domain dm{};
-    double wl = 0.0;
-    if (pk) {
-        dm = *dom;
-        wl = ldexp(dm.W, -L);
-    }
 #pragma unroll
     for (int r = 0; r < kPerThread; ++r) {
         if (dst[r] < 0) continue;
         const double gv = sv[r * kRadixThreads + tid];
         out.g[dst[r]] = gv;
         if (pk) {
-            const uint32_t k = ks_[r];
-            const double cx = dm.x0 + (double(morton_x(k)) + 0.5) * wl;
-            const double cy = dm.y0 + (double(morton_y(k)) + 0.5) * wl;
+            const KeyLeaf kl = key_leaf(ks_[r], inst, key_shift);
+            const Domain dm = inst[kl.q].dom;
+            const double wl = ldexp(dm.W, -kl.L);
+            const double cx = dm.x0 + (double(morton_x(kl.local)) + 0.5) * wl;
+            const double cy = dm.y0 + (double(morton_y(kl.local)) + 0.5) * wl;
             pk[dst[r]] = make_float4(float((xs_[r] - cx) * dm.s), float((ys_[r] - cy) * dm.s), float(gv), 0.0f);
         }
     }
@@ -406,7 +432,7 @@ k_rscatter(int n, const uint32_t* __restrict__ kin, const uint32_t* __restrict__
 // Depth 0: one leaf, nothing to sort.
 __global__ void __launch_bounds__(256)
 k_copy_one_leaf(int n, const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ g,
-                Records out, float4* __restrict__ pk, const Domain* __restrict__ dom)
+                Records out, float4* __restrict__ pk, const Inst* __restrict__ inst)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -417,22 +443,32 @@ k_copy_one_leaf(int n, const double* __restrict__ x, const double* __restrict__ 
     out.y[i] = yv;
     out.g[i] = gv;
     if (pk) {
-        const Domain dm = *dom;
+        const Domain dm = inst[0].dom;
         const double cx = dm.x0 + 0.5 * dm.W, cy = dm.y0 + 0.5 * dm.W;
         pk[i] = make_float4(float((xv - cx) * dm.s), float((yv - cy) * dm.s), float(gv), 0.0f);
     }
 }
 
-// leaf_start[k] = first sorted position whose key is >= k, for k = 0 .. nleaf:
-// position i owns the leaves in (key[i-1], key[i]].
+// Sorted position -> global leaf_start entry (instance segment + leaf).
+__device__ __forceinline__ int64_t leaf_entry(uint32_t k, const Inst* __restrict__ inst, int key_shift)
+{
+    const KeyLeaf kl = key_leaf(k, inst, key_shift);
+    return inst[kl.q].leaf_off + int64_t(kl.local);
+}
+
+// leaf_start[e] = first sorted position whose leaf entry is >= e, for every
+// entry e < entries: position i owns the entries in (entry(i-1), entry(i)].
+// Each instance's segment ends with one extra entry, which thereby receives
+// the first position of the next instance (its particle count end).
 __global__ void __launch_bounds__(256)
-k_bounds(int n, int64_t nleaf, const uint32_t* __restrict__ ks, int32_t* __restrict__ leaf_start)
+k_bounds(int n, int64_t entries, const uint32_t* __restrict__ ks, const Inst* __restrict__ inst, int key_shift,
+         int32_t* __restrict__ leaf_start)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i > n) return;
-    const int64_t lo = i == 0 ? 0 : int64_t(ks[i - 1]) + 1;
-    const int64_t hi = i == n ? nleaf : int64_t(ks[i]);
-    for (int64_t k = lo; k <= hi; ++k) leaf_start[k] = i;
+    const int64_t lo = i == 0 ? 0 : leaf_entry(ks[i - 1], inst, key_shift) + 1;
+    const int64_t hi = i == n ? entries - 1 : leaf_entry(ks[i], inst, key_shift);
+    for (int64_t e = lo; e <= hi; ++e) leaf_start[e] = i;
 }
 
 inline unsigned blocks_for(int64_t n, int bs) { return unsigned((n + bs - 1) / bs); }
@@ -442,11 +478,11 @@ inline unsigned blocks_for(int64_t n, int bs) { return unsigned((n + bs - 1) / b
 hipError_t launch_domain(const Buffers& b, int n, const double* x, const double* y, int L, hipStream_t st)
 {
     hipLaunchKernelGGL(k_bbox_partial, dim3(kBBoxBlocks), dim3(256), 0, st, n, x, y, b.bbox);
-    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, kBBoxBlocks, b.bbox, L, b.dom);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, kBBoxBlocks, b.bbox, L, &b.inst[0].dom);
     return hipGetLastError();
 }
 
-int radix_passes(int L) { return (2 * L + 7) / 8; }
+int radix_passes(int key_bits) { return (key_bits + 7) / 8; }
 
 int64_t radix_blocks(int64_t n) { return (n + kRadixTile - 1) / kRadixTile; }
 
@@ -463,20 +499,19 @@ void scan_table(const Buffers& b, int64_t m, hipStream_t st)
 
 }  // namespace
 
-hipError_t launch_tree(const Buffers& b, int n, int L, const double* x, const double* y, const double* g,
-                       bool explicit_dom, Domain hdom, bool mixed, hipStream_t st)
+hipError_t launch_tree(const Buffers& b, int n, const double* x, const double* y, const double* g,
+                       int key_bits, int64_t leaf_entries, bool mixed, hipStream_t st)
 {
-    const int64_t nleaf = int64_t(1) << (2 * L);
     const int nblk = int(radix_blocks(n));
     const int64_t m = int64_t(kRadixBins) * nblk;
     float4* pk = mixed ? b.pk : nullptr;
     const Records fin{b.ksorted, b.perm, b.xs, b.ys, b.gs};
     const Records tmp{b.ktmp, b.itmp, b.xt, b.yt, b.gt};
-    hipLaunchKernelGGL(k_rhist_keys, dim3(nblk), dim3(kRadixThreads), 0, st, n, x, y, b.dom, hdom,
-                       explicit_dom ? 1 : 0, L, nblk, b.key, b.hist, b.bad_blk, b.dom);
-    const int npass = radix_passes(L);
+    hipLaunchKernelGGL(k_rhist_keys, dim3(nblk), dim3(kRadixThreads), 0, st, n, x, y, b.inst, b.n_inst,
+                       b.key_shift, nblk, b.key, b.hist, b.bad_blk);
+    const int npass = radix_passes(key_bits);
     if (npass == 0) {
-        hipLaunchKernelGGL(k_copy_one_leaf, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, x, y, g, fin, pk, b.dom);
+        hipLaunchKernelGGL(k_copy_one_leaf, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, x, y, g, fin, pk, b.inst);
     } else {
         // the last pass writes the final arrays, the others alternate with tmp
         const uint32_t* kin = b.key;
@@ -490,7 +525,7 @@ hipError_t launch_tree(const Buffers& b, int n, int L, const double* x, const do
             scan_table(b, m, st);
             const bool last = pass == npass - 1;
             hipLaunchKernelGGL(k_rscatter, dim3(nblk), dim3(kRadixThreads), 0, st, n, kin, iin, xin, yin, gin,
-                               shift, nblk, b.hist, b.hist_scan, out, last ? pk : nullptr, b.dom, L);
+                               shift, nblk, b.hist, b.hist_scan, out, last ? pk : nullptr, b.inst, b.key_shift);
             kin = out.k;
             iin = out.idx;
             xin = out.x;
@@ -498,8 +533,8 @@ hipError_t launch_tree(const Buffers& b, int n, int L, const double* x, const do
             gin = out.g;
         }
     }
-    hipLaunchKernelGGL(k_bounds, dim3(blocks_for(int64_t(n) + 1, 256)), dim3(256), 0, st, n, nleaf, b.ksorted,
-                       b.leaf_start);
+    hipLaunchKernelGGL(k_bounds, dim3(blocks_for(int64_t(n) + 1, 256)), dim3(256), 0, st, n, leaf_entries,
+                       b.ksorted, b.inst, b.key_shift, b.leaf_start);
     return hipGetLastError();
 }
 

@@ -28,28 +28,34 @@ namespace {
 constexpr int kUpThreads = 256;
 constexpr int kP2MLanes = 4;            // threads per leaf in P2M
 
-// Workgroup = one box at level lt = lb - d (d <= 3).  from_particles: the
-// 4^d boxes of level lb are leaves and get their expansion from P2M;
-// otherwise they are read from global memory.
+// Workgroup = one box at level lt = lb - d (d <= 3) of one instance (work
+// table arg: lt, d).  from_particles: the 4^d boxes of level lb are leaves
+// and get their expansion from P2M; otherwise they are read from global
+// memory.
 template <int P>
 __global__ void __launch_bounds__(kUpThreads)
-k_upward(int L, int lt, int d, int p, int from_particles, const int32_t* __restrict__ leaf_start,
-         const double* __restrict__ xs, const double* __restrict__ ys, const double* __restrict__ gs,
-         const Domain* __restrict__ dom, cd* __restrict__ me, const cd* __restrict__ M)
+k_upward(Work wk, int n_inst, const Inst* __restrict__ inst, int p, int from_particles,
+         const int32_t* __restrict__ leaf_start_all, const double* __restrict__ xs, const double* __restrict__ ys,
+         const double* __restrict__ gs, cd* __restrict__ me_all, const cd* __restrict__ M)
 {
     __shared__ cd sh[85 * P];            // 64 + 16 + 4 + 1 boxes
     __shared__ cd sM[4 * P * P];         // the four M2M matrices
     const int tid = threadIdx.x;
+    const int q = find_inst(wk.wg_begin, n_inst, blockIdx.x);
+    const int64_t root = blockIdx.x - wk.wg_begin[q];     // z-order index at level lt
+    const int lt = wk.arg[2 * q], d = wk.arg[2 * q + 1];
+    const int L = inst[q].L;
+    const int32_t* leaf_start = leaf_start_all + inst[q].leaf_off;
+    cd* me = me_all + inst[q].box_off * P;
     if (d > 0)
         for (int e = tid; e < 4 * P * P; e += kUpThreads) sM[e] = M[e];
     const int lb = lt + d;
-    const int64_t root = blockIdx.x;     // z-order index at level lt
     const int nb = 1 << (2 * d);         // boxes at level lb under this root
     const int64_t first = root << (2 * d);
 
     // ---- level lb into sh[0 .. nb*P) ----
     if (from_particles) {
-        const Domain dm = *dom;
+        const Domain dm = inst[q].dom;
         const double w = ldexp(dm.W, -L);
         constexpr int KR = (P + kP2MLanes - 1) / kP2MLanes;
         for (int slot = tid; slot < nb * kP2MLanes; slot += kUpThreads) {
@@ -128,36 +134,27 @@ k_upward(int L, int lt, int d, int p, int from_particles, const int32_t* __restr
 }
 
 template <int P>
-hipError_t upward_impl(const Buffers& b, int p, int L, hipStream_t st)
+hipError_t upward_impl(const Buffers& b, int p, const Work& w, int nwg, bool leaves, hipStream_t st)
 {
-    if (L < 2) return hipSuccess;
-    int lb = L;
-    bool leaves = true;
-    for (;;) {
-        const int lt = std::max(2, lb - 3);
-        const int d = lb - lt;
-        const int64_t nroot = int64_t(1) << (2 * lt);
-        hipLaunchKernelGGL(k_upward<P>, dim3(unsigned(nroot)), dim3(kUpThreads), 0, st, L, lt, d, p,
-                           leaves ? 1 : 0, b.leaf_start, b.xs, b.ys, b.gs, b.dom, b.me, b.t_m2m);
-        leaves = false;
-        if (lt == 2) break;
-        lb = lt;
-    }
+    if (nwg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_upward<P>, dim3(unsigned(nwg)), dim3(kUpThreads), 0, st, w, b.n_inst, b.inst, p,
+                       leaves ? 1 : 0, b.leaf_start, b.xs, b.ys, b.gs, b.me, b.t_m2m);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_upward(const Buffers& b, int P, int p, int L, hipStream_t st)
+hipError_t launch_upward(const Buffers& b, int P, int p, const Work& w, int nwg, bool from_particles,
+                         hipStream_t st)
 {
     switch (P) {
-        case 8: return upward_impl<8>(b, p, L, st);
-        case 12: return upward_impl<12>(b, p, L, st);
-        case 16: return upward_impl<16>(b, p, L, st);
-        case 17: return upward_impl<17>(b, p, L, st);
-        case 20: return upward_impl<20>(b, p, L, st);
-        case 24: return upward_impl<24>(b, p, L, st);
-        case 32: return upward_impl<32>(b, p, L, st);
+        case 8: return upward_impl<8>(b, p, w, nwg, from_particles, st);
+        case 12: return upward_impl<12>(b, p, w, nwg, from_particles, st);
+        case 16: return upward_impl<16>(b, p, w, nwg, from_particles, st);
+        case 17: return upward_impl<17>(b, p, w, nwg, from_particles, st);
+        case 20: return upward_impl<20>(b, p, w, nwg, from_particles, st);
+        case 24: return upward_impl<24>(b, p, w, nwg, from_particles, st);
+        case 32: return upward_impl<32>(b, p, w, nwg, from_particles, st);
         default: return hipErrorInvalidValue;
     }
 }

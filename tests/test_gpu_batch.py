@@ -1,0 +1,251 @@
+"""Batched form and launch-shape tuning, through the C ABI.
+
+A batched evaluation must give every instance exactly what a single
+evaluation of that instance gives (same kernels, same arithmetic order), and
+therefore what the oracle gives; a replayed graph must match the eager
+result on every replay; every launch shape the autotuner may pick must give
+the same velocities up to the summation order of the split M2L levels.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import run
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+
+
+def _fm():
+    import paper_0905_2637_amd as fm
+    return fm
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    oracle.build()
+
+
+def _dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, np.float64), device="cuda")
+
+
+def _instances(counts, depths, seed):
+    """Uneven instances in the unit square: uniform, clustered and tiny ones."""
+    rng = np.random.default_rng(seed)
+    xs, ys, gs = [], [], []
+    for i, n in enumerate(counts):
+        if i % 3 == 1 and n > 10:
+            m = n // 2
+            x = np.concatenate([rng.random(n - m), 0.4 + 0.01 * rng.standard_normal(m)])
+            y = np.concatenate([rng.random(n - m), 0.7 + 0.01 * rng.standard_normal(m)])
+        else:
+            x = rng.random(n)
+            y = rng.random(n)
+        xs.append(np.clip(x, 0.0, np.nextafter(1.0, 0.0)))
+        ys.append(np.clip(y, 0.0, np.nextafter(1.0, 0.0)))
+        gs.append(rng.uniform(-1.0, 1.0, n))
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    return np.concatenate(xs), np.concatenate(ys), np.concatenate(gs), off
+
+
+def _batch(counts, depths, x, y, g, sigma, p, precision="fp64", fine=2):
+    import torch
+    fm = _fm()
+    bp = fm.BatchPlan(counts, depths, sigma, p, precision=precision, fp32_fine_levels=fine)
+    u, v = bp.evaluate(_dev(x), _dev(y), _dev(g), check=True)
+    torch.cuda.synchronize()
+    return u.cpu().numpy(), v.cpu().numpy(), bp
+
+
+COUNTS = [3000, 700, 0, 1, 2, 5000, 64, 1500, 12000]
+DEPTHS = [4, 3, 2, 0, 1, 5, 2, 3, 6]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_equals_single_evaluations(precision):
+    """Instance i of a batch == a single evaluation of instance i, bit for bit,
+    including the permutation and leaf ranges of its segment."""
+    fm = _fm()
+    x, y, g, off = _instances(COUNTS, DEPTHS, 11)
+    ub, vb, bp = _batch(COUNTS, DEPTHS, x, y, g, 0.004, 12, precision)
+    perm_b = bp.dump(fm.DUMP_PERM).astype(np.int64)
+    ls_b = bp.dump(fm.DUMP_LEAF_START).astype(np.int64)
+    seg = 0
+    for i, (n, L) in enumerate(zip(COUNTS, DEPTHS)):
+        a, b = off[i], off[i + 1]
+        nent = 4 ** L + 1
+        if n > 0:
+            # a single plan takes at most L-1 FP32 levels; more means the same (all of 2..L)
+            us, vs, sp = run(x[a:b], y[a:b], g[a:b], 0.004, 12, L, precision=precision,
+                             fine=min(2, max(0, L - 1)))
+            assert np.array_equal(ub[a:b], us) and np.array_equal(vb[a:b], vs), f"instance {i}"
+            assert np.array_equal(perm_b[a:b] - a, sp.dump(fm.DUMP_PERM).astype(np.int64)), f"perm {i}"
+            assert np.array_equal(ls_b[seg:seg + nent] - a, sp.dump(fm.DUMP_LEAF_START)), f"leaf ranges {i}"
+            sp.close()
+        else:
+            assert np.all(ls_b[seg:seg + nent] == a)
+        seg += nent
+    assert seg == len(ls_b)
+
+
+def test_batch_matches_oracle_fmm():
+    x, y, g, off = _instances(COUNTS, DEPTHS, 12)
+    ub, vb, _ = _batch(COUNTS, DEPTHS, x, y, g, 0.004, 12)
+    for i, (n, L) in enumerate(zip(COUNTS, DEPTHS)):
+        a, b = off[i], off[i + 1]
+        if n == 0:
+            continue
+        uo, vo = oracle.fmm(x[a:b], y[a:b], g[a:b], 0.004, 12, L)
+        if n == 1:
+            assert ub[a] == 0.0 and vb[a] == 0.0
+            continue
+        err = oracle.rel_l2(ub[a:b], vb[a:b], uo, vo)
+        assert err < FP64_TOL, f"instance {i}: rel L2 {err:.3e}"
+
+
+def test_graph_replays_match_eager():
+    """The captured graph is replayed several times, with other device work and
+    synchronisations in between; every replay equals the eager result."""
+    import torch
+    x, y, g, off = _instances(COUNTS, DEPTHS, 13)
+    fm = _fm()
+    bp = fm.BatchPlan(COUNTS, DEPTHS, 0.004, 12)
+    xt, yt, gt = _dev(x), _dev(y), _dev(g)
+    u = torch.empty_like(xt)
+    v = torch.empty_like(xt)
+    # eager reference: single evaluations instance by instance
+    ue = np.zeros(len(x))
+    ve = np.zeros(len(x))
+    for i, (n, L) in enumerate(zip(COUNTS, DEPTHS)):
+        a, b = off[i], off[i + 1]
+        if n:
+            ue[a:b], ve[a:b], sp = run(x[a:b], y[a:b], g[a:b], 0.004, 12, L)
+            sp.close()
+    other = fm.Plan(4096, 0.005, 12, 4)
+    wl = workloads.make("C1")
+    ox, oy, og = _dev(wl.x), _dev(wl.y), _dev(wl.gamma)
+    for rep in range(4):
+        u.fill_(np.nan)
+        v.fill_(np.nan)
+        bp.evaluate(xt, yt, gt, u, v)
+        torch.cuda.synchronize()
+        assert np.array_equal(u.cpu().numpy(), ue) and np.array_equal(v.cpu().numpy(), ve), f"replay {rep}"
+        # unrelated eager work on the same device between replays
+        other.evaluate(ox, oy, og)
+        (xt * 2.0).sum().item()
+        torch.cuda.synchronize()
+    # new output arrays: a fresh capture, same result
+    u2, v2 = bp.evaluate(xt, yt, gt)
+    torch.cuda.synchronize()
+    assert np.array_equal(u2.cpu().numpy(), ue) and np.array_equal(v2.cpu().numpy(), ve)
+    # changed inputs through the same pointers: the replay reads the new values
+    xt2 = xt.clone()
+    yt2 = yt.clone()
+    gt2 = (gt * -0.5).contiguous()
+    u3, v3 = bp.evaluate(xt2, yt2, gt2)
+    gt2.mul_(-2.0)    # now equal to gt again
+    u4, v4 = bp.evaluate(xt2, yt2, gt2, u3, v3)
+    torch.cuda.synchronize()
+    assert np.array_equal(u4.cpu().numpy(), ue) and np.array_equal(v4.cpu().numpy(), ve)
+    other.close()
+    bp.close()
+
+
+def test_batch_out_of_domain_counted():
+    import torch
+    fm = _fm()
+    counts = [100, 200]
+    x, y, g, off = _instances(counts, [2, 3], 14)
+    x[5] = 1.5
+    y[150] = -0.25
+    bp = fm.BatchPlan(counts, [2, 3], 0.01, 8)
+    bp.evaluate(_dev(x), _dev(y), _dev(g))
+    torch.cuda.synchronize()
+    assert bp.out_of_domain() == 2
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_every_launch_shape_agrees(precision):
+    """All tuning candidates give the same velocities (the split M2L levels only
+    reassociate the sum) and the split-free shape is reproducible bitwise."""
+    import torch
+    fm = _fm()
+    wl = workloads.make("C1")
+    x, y, g = _dev(wl.x), _dev(wl.y), _dev(wl.gamma)
+    plan = fm.Plan(wl.n, wl.sigma, wl.p, 5, precision=precision)
+    ref = None
+    for waves in (2, 4):
+        for split in (0, 5, 8):
+            plan.set_tuning(waves, split)
+            assert plan.tuning() == {"p2p_waves": waves, "m2l_split_max": split}
+            u, v = plan.evaluate(x, y, g)
+            torch.cuda.synchronize()
+            u, v = u.cpu().numpy(), v.cpu().numpy()
+            if ref is None:
+                ref = (u, v)
+            else:
+                err = oracle.rel_l2(u, v, *ref)
+                assert err < (1e-14 if precision == "fp64" else 1e-6), (waves, split, err)
+    plan.close()
+
+
+def test_autotune_and_cache(tmp_path, monkeypatch):
+    import torch
+    fm = _fm()
+    wl = workloads.make("C1")
+    x, y, g = _dev(wl.x), _dev(wl.y), _dev(wl.gamma)
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("FMM_AUTOTUNE_CACHE", str(cache))
+    plan = fm.Plan(wl.n, wl.sigma, wl.p, wl.depth)
+    t = plan.autotune(x, y, g, reps=2)
+    assert t["p2p_waves"] in (2, 4) and t["m2l_split_max"] in (0, 5, 8)
+    lines = cache.read_text().split("\n")
+    assert len([ln for ln in lines if ln.strip()]) == 1
+    # a planted entry is taken from the cache without a search
+    key = lines[0].split()[0]
+    cache.write_text(f"{key} 2 0\n")
+    plan2 = fm.Plan(wl.n, wl.sigma, wl.p, wl.depth)
+    assert plan2.autotune(x, y, g) == {"p2p_waves": 2, "m2l_split_max": 0}
+    u, v = plan2.evaluate(x, y, g)
+    torch.cuda.synchronize()
+    uo, vo = oracle.fmm(wl.x, wl.y, wl.gamma, wl.sigma, wl.p, wl.depth)
+    assert oracle.rel_l2(u.cpu().numpy(), v.cpu().numpy(), uo, vo) < FP64_TOL
+    plan.close()
+    plan2.close()
+
+
+def test_c4_batch_sampled_against_single_and_direct():
+    """The 512-instance workload at full size: a batched, autotuned graph
+    replay; sampled instances equal their single evaluations bit for bit and
+    stay within the mixed-precision gate of the FP64 split-kernel direct sum
+    (the gate is loosened to what p = 12 truncation allows)."""
+    import torch
+    fm = _fm()
+    wl = workloads.make("C4")
+    counts = np.diff(wl.offsets).tolist()
+    depths = wl.depths.tolist()
+    bp = fm.BatchPlan(counts, depths, wl.sigma, wl.p, precision=wl.precision,
+                      fp32_fine_levels=wl.fp32_fine_levels)
+    xt, yt, gt = _dev(wl.x), _dev(wl.y), _dev(wl.gamma)
+    bp.autotune(xt, yt, gt, reps=1)
+    u, v = bp.evaluate(xt, yt, gt, check=True)
+    torch.cuda.synchronize()
+    u, v = u.cpu().numpy(), v.cpu().numpy()
+    rng = np.random.default_rng(40)
+    for i in sorted(rng.choice(len(counts), 6, replace=False)):
+        a, b = wl.offsets[i], wl.offsets[i + 1]
+        us, vs, sp = run(wl.x[a:b], wl.y[a:b], wl.gamma[a:b], wl.sigma, wl.p, depths[i],
+                         precision=wl.precision, fine=wl.fp32_fine_levels)
+        sp.set_tuning(**bp.tuning())
+        us, vs = sp.evaluate(_dev(wl.x[a:b]), _dev(wl.y[a:b]), _dev(wl.gamma[a:b]))
+        torch.cuda.synchronize()
+        assert np.array_equal(u[a:b], us.cpu().numpy()) and np.array_equal(v[a:b], vs.cpu().numpy()), i
+        sp.close()
+        t = workloads.sample_targets(int(b - a), 256, 41 + int(i))
+        ud, vd = oracle.direct_split(wl.x[a:b], wl.y[a:b], wl.gamma[a:b], wl.sigma, depths[i], targets=t)
+        err = oracle.rel_l2(u[a:b][t], v[a:b][t], ud, vd)
+        assert err < 1e-5, f"instance {i}: rel L2 vs split direct {err:.3e}"

@@ -160,7 +160,7 @@ def make(name: str) -> Workload:
         depths = np.array([batched_depth(int(n_i)) for n_i in ns], dtype=np.int32)
         return Workload("C4", np.concatenate(xs), np.concatenate(ys), np.concatenate(gs),
                         sigma=0.005, depth=int(depths.max()), p=12, precision="mixed",
-                        fp32_fine_levels=0, offsets=offsets, depths=depths)
+                        fp32_fine_levels=2, offsets=offsets, depths=depths)
     if name == "C5":
         x, y, g = uniform_square(1 << 26, 5)
         return Workload("C5", x, y, g, sigma=2e-4, depth=11, p=20,
