@@ -4,23 +4,30 @@
 Default workload (the configuration the headline metric is quoted on): the
 1,048,576-particle jittered Lamb-Oseen lattice, sigma = 0.002, depth 8,
 p = 17, every stage in FP64.  A "step" is one complete evaluation -- tree
-build (z-order keys, counting sort, leaf ranges), P2M, M2M, M2L, L2L, L2P and
-P2P -- with inputs already resident in HBM.
+build (z-order keys, radix sort, leaf ranges), P2M, M2M, M2L, L2L, L2P and
+P2P -- with inputs already resident in HBM.  ``--config C4`` runs the
+batched form instead: 512 uneven instances, one graph replay per step.
 
 Prints ONE JSON line.  ``value`` is particles per second over the timed
 steps (wall clock, bracketed by device synchronisation).  ``roofline``
-describes the stage with the largest GPU time, measured with HIP events
-recorded on the evaluation's own stream during the timed steps.
-``cpu_baseline`` times the FP64 CPU oracle on the host cores for one full
-evaluation of the same workload (rank 0, N = 1 only) and, from the same run,
-reports the parity of the GPU result and its accuracy against the direct sums.
+describes the kernel of the stage with the largest GPU time; its duration
+is measured with HIP events that the library records on the evaluation's
+own stream during the timed steps (for the batched form: during extra,
+eagerly enqueued timed evaluations, since a replayed graph carries no
+events).  ``forms`` (default workload only) times the mixed-precision form
+of the same workload and the batched form against plain FP64 single
+evaluations of the same instances.  ``cpu_baseline`` times the FP64 CPU
+oracle on the host cores (rank 0, N = 1 only) and, from the same leg,
+reports the GPU result's parity with the oracle and its accuracy against
+the direct sums.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
+import re
 import sys
 import time
 
@@ -34,17 +41,48 @@ import workloads  # noqa: E402
 
 METRIC = "particles/s per full FMM eval at ≤1e-6 rel. L2 vs direct; FP64 vs mixed"
 
-# MI355X published peaks used for the roofline.  Packed FP32 instructions are
-# disabled in this build, so FP32 vector arithmetic issues at the FP64 rate:
-# 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz = 78.6 TFLOP/s.
-PEAK_VALU_TFLOPS = 78.6
+# MI355X published vector peaks (256 CUs x 4 SIMDs x 16 lanes x 2 flops x
+# 2.4 GHz = 78.6 TFLOP/s; FP32 counts the packed dual rate, 157.3).  Packed
+# FP32 instructions are not generated in this build, so 78.6 TFLOP/s is the
+# FP32 ceiling the kernels can reach; the published figure is kept as the peak.
+PEAK_VALU_TFLOPS = {"f64": 78.6, "f32": 157.3}
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic work per unit (see DESIGN.md):
+# Algorithmic work per unit:
 #  P2P: 14 flops per near pair (2 differences, 3 for |d|^2, 1 scaling, 1 exp,
 #       1 for 1 - e, 1 product, 1 division, 4 for the complex accumulation).
 #  M2L: 8 p^2 flops per interaction-list pair (dense complex p x p product).
 P2P_FLOPS_PER_PAIR = 14
+
+# Kernel sources whose HBM traffic a committed counter summary describes.
+TRAFFIC_SOURCES = {
+    "k_p2p_l2p": ["paper_0905_2637_amd/csrc/fmm_near.hip", "paper_0905_2637_amd/csrc/fmm_device.h",
+                  "paper_0905_2637_amd/csrc/fmm_internal.h"],
+    "k_m2l": ["paper_0905_2637_amd/csrc/fmm_downward.hip", "paper_0905_2637_amd/csrc/fmm_device.h",
+              "paper_0905_2637_amd/csrc/fmm_internal.h"],
+}
+
+
+def source_hash(kernel: str) -> str:
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES[kernel]:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from profiles/<kernel>_<workload>_traffic.md, or None
+    when there is no summary or the kernel's sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
+    if kernel not in TRAFFIC_SOURCES or not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_hash = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", text)
+    m_bytes = re.search(r"traffic_bytes_per_launch:\s*([0-9]+)", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != source_hash(kernel):
+        return None
+    return int(m_bytes.group(1))
 
 
 def m2l_pairs(L: int) -> int:
@@ -69,18 +107,219 @@ def near_pairs(leaf_start: np.ndarray, L: int) -> int:
     return int(np.sum(grid * nb) - np.sum(grid))
 
 
-def make_workload(name: str):
-    wl = workloads.make(name)
-    if wl.offsets is not None:
-        raise SystemExit(f"workload {name} is batched; this bench runs single evaluations")
-    return wl
-
-
 def describe(wl) -> str:
-    prec = "FP64" if wl.precision == "fp64" else f"mixed (FP32 P2P, FP32 M2L on the finest {wl.fp32_fine_levels} levels)"
+    prec = "FP64" if wl.precision == "fp64" else \
+        f"mixed (FP32 P2P, FP32 M2L on the finest {wl.fp32_fine_levels} levels)"
+    if wl.offsets is not None:
+        return (f"{wl.name}: {len(wl.depths)} instances, {wl.n:,} particles in total, uniform unit square, "
+                f"sigma={wl.sigma}, depths {int(wl.depths.min())}-{int(wl.depths.max())}, p={wl.p}, {prec}, batched")
     kind = {"C1": "uniform unit square", "C2": "jittered Lamb-Oseen lattice",
             "C3": "16-component Gaussian mixture", "C5": "uniform unit square"}[wl.name]
     return f"{wl.name}: {wl.n:,} particles, {kind}, sigma={wl.sigma}, depth {wl.depth}, p={wl.p}, {prec}"
+
+
+def timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def roofline_of(stage_ms, pairs_near, pairs_m2l, p, dtype, workload_key):
+    dominant = max(stage_ms, key=stage_ms.get)
+    t = stage_ms[dominant] * 1e-3
+    if dominant == "p2p_l2p":
+        work, kernel = pairs_near * P2P_FLOPS_PER_PAIR, "k_p2p_l2p"
+        note = f"{pairs_near} near pairs x {P2P_FLOPS_PER_PAIR} flops"
+    elif dominant == "m2l":
+        work, kernel = pairs_m2l * 8 * p * p, "k_m2l"
+        note = f"{pairs_m2l} M2L pairs x 8p^2 flops"
+    else:
+        return {"bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": None,
+                "traffic": None, "kernel": dominant, "stage_ms": round(stage_ms[dominant], 4)}
+    achieved = work / t / 1e12
+    peak = PEAK_VALU_TFLOPS[dtype]
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": measured_traffic(kernel, workload_key),
+            "kernel": kernel, "stage_ms": round(stage_ms[dominant], 4), "work": note}
+
+
+def dev_arrays(wl, dev):
+    import torch
+    return tuple(torch.as_tensor(a, device=dev) for a in (wl.x, wl.y, wl.gamma))
+
+
+# ---------------------------------------------------------------------------
+# single evaluation
+# ---------------------------------------------------------------------------
+
+def run_single(wl, args, dev):
+    import torch
+    import paper_0905_2637_amd as fm
+    x, y, g = dev_arrays(wl, dev)
+    u = torch.empty(wl.n, dtype=torch.float64, device=dev)
+    v = torch.empty(wl.n, dtype=torch.float64, device=dev)
+    plan = fm.Plan(wl.n, wl.sigma, wl.p, wl.depth, domain=(wl.x0, wl.y0, wl.width),
+                   precision=wl.precision, fp32_fine_levels=wl.fp32_fine_levels)
+    for _ in range(args.warmup):
+        plan.evaluate(x, y, g, u, v)
+    torch.cuda.synchronize()
+    if plan.out_of_domain():
+        raise SystemExit("particles outside the domain")
+    plan.set_timing(True)
+    sec = timed(lambda: plan.evaluate(x, y, g, u, v), args.steps, 0)
+    stages = plan.stats()
+    plan.set_timing(False)
+    stage_ms = {k: vv for k, vv in stages.items() if k != "evaluations"}
+    leaf_start = plan.dump(fm.DUMP_LEAF_START)
+    pn, pm = near_pairs(leaf_start, wl.depth), m2l_pairs(wl.depth)
+    res = {"sec": sec, "stage_ms": stage_ms, "near_pairs": pn, "m2l_pairs": pm,
+           "roofline": roofline_of(stage_ms, pn, pm, wl.p, "f64" if wl.precision == "fp64" else "f32", wl.name),
+           "u": u, "v": v, "tuning": plan.tuning()}
+    plan.close()
+    return res
+
+
+# ---------------------------------------------------------------------------
+# batched form
+# ---------------------------------------------------------------------------
+
+def run_batch(wl, args, dev, precision=None, autotune=True):
+    import torch
+    import paper_0905_2637_amd as fm
+    precision = precision or wl.precision
+    x, y, g = dev_arrays(wl, dev)
+    u = torch.empty(wl.n, dtype=torch.float64, device=dev)
+    v = torch.empty(wl.n, dtype=torch.float64, device=dev)
+    counts = np.diff(wl.offsets).tolist()
+    depths = wl.depths.tolist()
+    bp = fm.BatchPlan(counts, depths, wl.sigma, wl.p, domain=(wl.x0, wl.y0, wl.width), precision=precision,
+                      fp32_fine_levels=wl.fp32_fine_levels)
+    if autotune:
+        bp.autotune(x, y, g, u, v, reps=2)
+    bp.evaluate(x, y, g, u, v)
+    torch.cuda.synchronize()
+    if bp.out_of_domain():
+        raise SystemExit("particles outside the domain")
+    sec = timed(lambda: bp.evaluate(x, y, g, u, v), args.steps, args.warmup)
+    # stage breakdown from eagerly enqueued timed evaluations (same kernels)
+    bp.set_timing(True)
+    for _ in range(max(3, min(args.steps, 10))):
+        bp.evaluate(x, y, g, u, v)
+    torch.cuda.synchronize()
+    stages = bp.stats()
+    bp.set_timing(False)
+    stage_ms = {k: vv for k, vv in stages.items() if k != "evaluations"}
+    ls = bp.dump(fm.DUMP_LEAF_START)
+    pn = pm = 0
+    seg = 0
+    for L in depths:
+        pn += near_pairs(ls[seg:seg + 4 ** L + 1] - ls[seg], L)
+        pm += m2l_pairs(L)
+        seg += 4 ** L + 1
+    res = {"sec": sec, "stage_ms": stage_ms, "near_pairs": pn, "m2l_pairs": pm,
+           "roofline": roofline_of(stage_ms, pn, pm, wl.p, "f64" if precision == "fp64" else "f32", wl.name),
+           "u": u, "v": v, "tuning": bp.tuning()}
+    bp.close()
+    return res
+
+
+def run_sequential_fp64(wl, args, dev):
+    """Plain FP64 GPU FMM over the same instances, one single evaluation each."""
+    import torch
+    import paper_0905_2637_amd as fm
+    x, y, g = dev_arrays(wl, dev)
+    u = torch.empty(wl.n, dtype=torch.float64, device=dev)
+    v = torch.empty(wl.n, dtype=torch.float64, device=dev)
+    counts = np.diff(wl.offsets)
+    plans = {}
+    for L in sorted(set(wl.depths.tolist())):
+        nmax = int(counts[wl.depths == L].max())
+        plans[L] = fm.Plan(nmax, wl.sigma, wl.p, L, domain=(wl.x0, wl.y0, wl.width))
+
+    def step():
+        for i, L in enumerate(wl.depths.tolist()):
+            a, b = int(wl.offsets[i]), int(wl.offsets[i + 1])
+            plans[L].evaluate(x[a:b], y[a:b], g[a:b], u[a:b], v[a:b])
+
+    sec = timed(step, max(2, min(args.steps, 10)), 1)
+    for p in plans.values():
+        p.close()
+    return sec
+
+
+# ---------------------------------------------------------------------------
+# CPU oracle leg (the only part of the bench that touches the oracle)
+# ---------------------------------------------------------------------------
+
+def cpu_baseline_leg(wl, res, args, forms):
+    import oracle
+    oracle.build()
+    budget = args.cpu_seconds
+    u_gpu = res["u"].cpu().numpy()
+    v_gpu = res["v"].cpu().numpy()
+    out = {}
+    if wl.offsets is None:
+        # whole evaluations of the same workload, repeated until the budget is spent
+        reps, t_cpu = 0, 0.0
+        while True:
+            t1 = time.perf_counter()
+            uo, vo = oracle.fmm(wl.x, wl.y, wl.gamma, wl.sigma, wl.p, wl.depth, wl.x0, wl.y0, wl.width)
+            t_cpu += time.perf_counter() - t1
+            reps += 1
+            if t_cpu >= budget or reps >= 50:
+                break
+        out["cpu_baseline"] = {
+            "value": wl.n * reps / t_cpu, "unit": "particles/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{reps} full FP64 oracle FMM evaluations of the same {wl.n:,}-particle workload "
+                      f"({t_cpu:.1f} s)"}
+        tgt = workloads.sample_targets(wl.n, args.accuracy_targets, 1000 + int(wl.name[1]))
+        us, vs = oracle.direct_split(wl.x, wl.y, wl.gamma, wl.sigma, wl.depth, wl.x0, wl.y0, wl.width,
+                                     targets=tgt)
+        ur, vr = oracle.direct(wl.x, wl.y, wl.gamma, wl.sigma, targets=tgt)
+        acc = {"rel_l2_vs_oracle_fmm": oracle.rel_l2(u_gpu, v_gpu, uo, vo),
+               "rel_l2_vs_split_direct": oracle.rel_l2(u_gpu[tgt], v_gpu[tgt], us, vs),
+               "rel_l2_vs_regularised_direct": oracle.rel_l2(u_gpu[tgt], v_gpu[tgt], ur, vr),
+               "direct_targets": int(tgt.shape[0])}
+        if forms and "mixed" in forms:
+            um, vm = forms.pop("_mixed_uv")
+            um, vm = um.cpu().numpy(), vm.cpu().numpy()
+            forms["mixed"]["rel_l2_vs_fp64_split_direct"] = oracle.rel_l2(um[tgt], vm[tgt], us, vs)
+            forms["mixed"]["rel_l2_vs_regularised_direct"] = oracle.rel_l2(um[tgt], vm[tgt], ur, vr)
+            forms["mixed"]["rel_l2_vs_gpu_fp64"] = oracle.rel_l2(um, vm, u_gpu, v_gpu)
+        out["accuracy"] = acc
+    else:
+        # oracle FMM over instances in workload order until the budget is spent
+        done, n_done, t_cpu = 0, 0, 0.0
+        errs = []
+        for i, L in enumerate(wl.depths.tolist()):
+            a, b = int(wl.offsets[i]), int(wl.offsets[i + 1])
+            t1 = time.perf_counter()
+            uo, vo = oracle.fmm(wl.x[a:b], wl.y[a:b], wl.gamma[a:b], wl.sigma, wl.p, L, wl.x0, wl.y0, wl.width)
+            t_cpu += time.perf_counter() - t1
+            done += 1
+            n_done += b - a
+            tgt = workloads.sample_targets(b - a, 64, 2000 + i)
+            us, vs = oracle.direct_split(wl.x[a:b], wl.y[a:b], wl.gamma[a:b], wl.sigma, L, wl.x0, wl.y0,
+                                         wl.width, targets=tgt)
+            errs.append((oracle.rel_l2(u_gpu[a:b], v_gpu[a:b], uo, vo),
+                         oracle.rel_l2(u_gpu[a:b][tgt], v_gpu[a:b][tgt], us, vs)))
+            if t_cpu >= budget:
+                break
+        out["cpu_baseline"] = {
+            "value": n_done / t_cpu, "unit": "particles/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"FP64 oracle FMM of the first {done} of {len(wl.depths)} instances "
+                      f"({n_done:,} particles, {t_cpu:.1f} s)"}
+        out["accuracy"] = {"instances_checked": done,
+                           "max_rel_l2_vs_oracle_fmm": max(e[0] for e in errs),
+                           "max_rel_l2_vs_split_direct": max(e[1] for e in errs),
+                           "direct_targets_per_instance": 64}
+    return out
 
 
 def main() -> int:
@@ -88,79 +327,61 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="C2", help="workload: C1, C2 (default), C3 or C5")
+    ap.add_argument("--config", default="C2", help="workload: C1, C2 (default), C3, C4 (batched) or C5")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-forms", action="store_true", help="skip the mixed and batched form comparison")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="time budget of the CPU oracle leg")
     ap.add_argument("--accuracy-targets", type=int, default=1024)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="after the timed region, run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
-                          "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (how the evaluation "
+                                   "would shard is described in the design notes)", "n_gpus": args.gpus}))
         return 2
 
     import torch
-    import paper_0905_2637_amd as fm
 
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no HIP device"}))
         return 1
     dev = torch.device("cuda:0")
-    wl = make_workload(args.config)
-    n = wl.n
-    x = torch.as_tensor(wl.x, device=dev)
-    y = torch.as_tensor(wl.y, device=dev)
-    g = torch.as_tensor(wl.gamma, device=dev)
-    u = torch.empty(n, dtype=torch.float64, device=dev)
-    v = torch.empty(n, dtype=torch.float64, device=dev)
-    plan = fm.Plan(n, wl.sigma, wl.p, wl.depth, domain=(wl.x0, wl.y0, wl.width),
-                   precision=wl.precision, fp32_fine_levels=wl.fp32_fine_levels)
+    wl = workloads.make(args.config)
+    batched = wl.offsets is not None
+    res = run_batch(wl, args, dev) if batched else run_single(wl, args, dev)
+    value = wl.n / res["sec"]
 
-    for _ in range(args.warmup):
-        plan.evaluate(x, y, g, u, v)
-    torch.cuda.synchronize()
-    if plan.out_of_domain():
-        raise SystemExit("particles outside the domain")
+    forms = None
+    if not args.no_forms and not batched and wl.name == "C2":
+        forms = {"fp64": {"ms": round(res["sec"] * 1e3, 4), "value": value}}
+        wm = workloads.make("C2")
+        wm.precision, wm.fp32_fine_levels = "mixed", 2
+        rm = run_single(wm, args, dev)
+        forms["mixed"] = {"workload": describe(wm), "ms": round(rm["sec"] * 1e3, 4), "value": wm.n / rm["sec"],
+                          "speedup_vs_fp64": res["sec"] / rm["sec"],
+                          "stages_ms": {k: round(x, 4) for k, x in rm["stage_ms"].items()},
+                          "roofline": rm["roofline"]}
+        forms["_mixed_uv"] = (rm["u"], rm["v"])
+        w4 = workloads.make("C4")
+        rb = run_batch(w4, args, dev)
+        rb64 = run_batch(w4, args, dev, precision="fp64")
+        seq = run_sequential_fp64(w4, args, dev)
+        forms["batched"] = {"workload": describe(w4), "ms": round(rb["sec"] * 1e3, 4), "value": w4.n / rb["sec"],
+                            "fp64_batched_ms": round(rb64["sec"] * 1e3, 4),
+                            "fp64_sequential_single_ms": round(seq * 1e3, 4),
+                            "speedup_vs_fp64_sequential": seq / rb["sec"],
+                            "speedup_fp64_batched_vs_sequential": seq / rb64["sec"],
+                            "tuning": rb["tuning"], "roofline": rb["roofline"]}
 
-    plan.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.evaluate(x, y, g, u, v)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    stages = plan.stats()
-    plan.set_timing(False)
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = n * args.steps / elapsed
-
-    # ---- roofline of the dominant stage ------------------------------------
-    leaf_start = plan.dump(fm.DUMP_LEAF_START)
-    stage_ms = {k: vv for k, vv in stages.items() if k != "evaluations"}
-    dominant = max(stage_ms, key=stage_ms.get)
-    pairs_near = near_pairs(leaf_start, wl.depth)
-    pairs_m2l = m2l_pairs(wl.depth)
-    if dominant == "p2p_l2p":
-        work = pairs_near * P2P_FLOPS_PER_PAIR
-        kernel = "k_p2p_l2p"
-        unit_note = f"{pairs_near} near pairs x {P2P_FLOPS_PER_PAIR} flops"
-    elif dominant == "m2l":
-        work = pairs_m2l * 8 * wl.p * wl.p
-        kernel = "k_m2l"
-        unit_note = f"{pairs_m2l} M2L pairs x 8p^2 flops"
-    else:
-        work = None
-        kernel = dominant
-        unit_note = "tree/HBM-bound stage"
-    t_dom = stage_ms[dominant] * 1e-3
-    if work is not None:
-        achieved = work / t_dom / 1e12
-        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_VALU_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(achieved / PEAK_VALU_TFLOPS, 4), "traffic": None,
-                    "kernel": kernel, "stage_ms": round(stage_ms[dominant], 4), "work": unit_note}
-    else:
-        roofline = {"bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": None,
-                    "traffic": None, "kernel": kernel, "stage_ms": round(stage_ms[dominant], 4)}
+    if args.calibrate_copy_mib > 0:
+        nel = args.calibrate_copy_mib * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
 
     out = {
         "metric": METRIC,
@@ -169,40 +390,24 @@ def main() -> int:
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": res["sec"] * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if wl.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": describe(wl), "n": n, "depth": wl.depth, "p": wl.p, "sigma": wl.sigma,
+        "config": {"workload": describe(wl), "n": wl.n, "depth": wl.depth, "p": wl.p, "sigma": wl.sigma,
                    "precision": wl.precision, "parallelism": "single GPU"},
-        "stages_ms": {k: round(vv, 4) for k, vv in stage_ms.items()},
-        "work": {"near_pairs": pairs_near, "m2l_pairs": pairs_m2l},
-        "roofline": roofline,
+        "stages_ms": {k: round(x, 4) for k, x in res["stage_ms"].items()},
+        "work": {"near_pairs": res["near_pairs"], "m2l_pairs": res["m2l_pairs"]},
+        "tuning": res["tuning"],
+        "roofline": res["roofline"],
     }
-
-    # ---- CPU oracle beside it ---------------------------------------------
     if not args.no_cpu_baseline:
-        import oracle
-        u_gpu = u.cpu().numpy()
-        v_gpu = v.cpu().numpy()
-        t1 = time.perf_counter()
-        uo, vo = oracle.fmm(wl.x, wl.y, wl.gamma, wl.sigma, wl.p, wl.depth, wl.x0, wl.y0, wl.width)
-        t_cpu = time.perf_counter() - t1
-        tgt = workloads.sample_targets(n, args.accuracy_targets, 1000 + int(wl.name[1]))
-        us, vs = oracle.direct_split(wl.x, wl.y, wl.gamma, wl.sigma, wl.depth, wl.x0, wl.y0, wl.width, targets=tgt)
-        ur, vr = oracle.direct(wl.x, wl.y, wl.gamma, wl.sigma, targets=tgt)
-        out["cpu_baseline"] = {
-            "value": n / t_cpu, "unit": "particles/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"one full FP64 oracle FMM evaluation of the same {n:,}-particle workload ({t_cpu:.2f} s)",
-        }
-        out["accuracy"] = {
-            "rel_l2_vs_oracle_fmm": oracle.rel_l2(u_gpu, v_gpu, uo, vo),
-            "rel_l2_vs_split_direct": oracle.rel_l2(u_gpu[tgt], v_gpu[tgt], us, vs),
-            "rel_l2_vs_regularised_direct": oracle.rel_l2(u_gpu[tgt], v_gpu[tgt], ur, vr),
-            "direct_targets": int(tgt.shape[0]),
-        }
+        out.update(cpu_baseline_leg(wl, res, args, forms))
+    if forms is not None:
+        forms.pop("_mixed_uv", None)
+        out["forms"] = forms
     print(json.dumps(out))
     return 0
 

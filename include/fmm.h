@@ -126,7 +126,8 @@ fmm_status fmm_plan_batch(const fmm_params* prm, int32_t n_inst, const int32_t* 
  * plan must not overlap.  Errors: FMM_E_ARG (a single-instance plan, NULL
  * pointers), FMM_E_DEVICE.  fmm_get_status and fmm_debug_dump (KEYS, PERM,
  * LEAF_START of all instances, segment after segment) work as for a single
- * plan; stage timing is not available for batched plans. */
+ * plan.  With stage timing on (fmm_set_timing) the evaluation is enqueued
+ * eagerly, with the stage events between its launches, instead of replayed. */
 fmm_status fmm_evaluate_batch(fmm_plan_t plan, const double* d_x, const double* d_y,
                               const double* d_gamma, double* d_u, double* d_v, void* stream);
 

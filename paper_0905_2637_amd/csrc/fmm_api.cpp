@@ -606,7 +606,6 @@ fmm_status fmm_set_timing(fmm_plan_t plan, int32_t on)
 {
     if (!plan) return FMM_E_ARG;
     if (on && !plan->have_events) return FMM_E_DEVICE;
-    if (on && plan->batch) return FMM_E_UNSUPPORTED;       // a replayed graph has no stage events
     if (plan->have_events)
         for (int r = 0; r < kTimingRing; ++r)
             if (harvest(plan, r) != hipSuccess) return FMM_E_DEVICE;
@@ -645,6 +644,16 @@ fmm_status fmm_evaluate_batch(fmm_plan_t plan, const double* d_x, const double* 
     if (n > 0 && (!d_x || !d_y || !d_gamma || !d_u || !d_v)) return FMM_E_ARG;
     plan->last_n = n;
     if (n == 0) return FMM_OK;
+    if (plan->timing) {
+        // timed: enqueued eagerly with stage events, no graph
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        const int slot = int(plan->next_slot % kTimingRing);
+        hipError_t e = harvest(plan, slot);
+        plan->next_slot += 1;
+        if (e == hipSuccess) e = enqueue_all(plan, n, d_x, d_y, d_gamma, d_u, d_v, st, true, slot);
+        if (e == hipSuccess) plan->pending[slot] = true;
+        return e == hipSuccess ? FMM_OK : FMM_E_DEVICE;
+    }
     const void* ptrs[5] = {d_x, d_y, d_gamma, d_u, d_v};
     bool same = plan->gexec != nullptr;
     for (int i = 0; i < 5 && same; ++i) same = plan->gptr[i] == ptrs[i];
