@@ -149,9 +149,12 @@ struct LeafCtx {
     float c2;                   // w^2 log2(e) / (2 sigma^2)
 };
 
+constexpr int kStageSlots = kNearStage / 64;   // staged sources per lane and chunk
+
 // All targets of one leaf, in chunks of T = 2^lgT; R targets per lane.
+// le_sh: this wavefront's LDS copy of the leaf's local expansion (P terms).
 template <int P, bool MIXED, int R>
-__device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* stage_raw, int has_far,
+__device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* stage_raw, cd* le_sh, int has_far,
                                               const double* __restrict__ xs, const double* __restrict__ ys,
                                               const double* __restrict__ gs, const float4* __restrict__ pk,
                                               const uint32_t* __restrict__ perm, const cd* __restrict__ le_leaf,
@@ -167,6 +170,11 @@ __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* 
     const int tg = lane & (TG - 1);
     const int si = lane >> lgTG;
     const int tot = c.npre[9];
+
+    // the leaf's local expansion goes through LDS (read back as broadcasts),
+    // keeping P complex values out of the scalar registers
+    if (has_far)
+        for (int k = lane; k < P; k += 64) le_sh[k] = le_leaf[int64_t(c.m) * P + k];
 
     for (int c0 = 0; c0 < c.nt; c0 += T) {
         double xi[R], yi[R], ax[R], ay[R];
@@ -185,31 +193,54 @@ __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* 
                 }
             }
         }
+        // slice lane si < R finishes target c0 + tg + TG si; its output slot
+        // (and, in mixed mode, its FP64 position for L2P) is fetched up front
+        const int il = c0 + tg + TG * si;
+        const bool own = si < R && il < c.nt;
+        uint32_t o = 0;
+        double px = 0.0, py = 0.0;
+        if (own) {
+            o = perm[c.s0 + il];
+            if constexpr (MIXED) { px = xs[c.s0 + il]; py = ys[c.s0 + il]; }
+        }
 
         for (int base = 0; base < tot; base += kNearStage) {
             const int cnt = min(kNearStage, tot - base);
             const int padded = ((cnt + S - 1) / S) * S;
-            wave_sync();
-            // stage the neighbourhood's particles leaf by leaf (uniform loop)
+            // every lane finds the neighbour leaf of each of its slots, then all
+            // loads are issued before the first wait (one memory round trip)
+            Stage val[kStageSlots];
 #pragma unroll
-            for (int q = 0; q < 9; ++q) {
-                const int lo = max(c.npre[q], base), hi = min(c.npre[q + 1], base + cnt);
-                for (int k = lo + lane; k < hi; k += 64) {
-                    const int j = c.nbeg[q] + (k - c.npre[q]);
+            for (int sl = 0; sl < kStageSlots; ++sl) {
+                const int k = lane + 64 * sl;
+                if constexpr (MIXED) val[sl] = make_float4(1.0e4f, 1.0e4f, 0.0f, 0.0f);   // inert
+                else val[sl] = Src64{1.0e10, 1.0e10, 0.0};
+                if (k < cnt) {
+                    const int j = base + k;             // position in the neighbourhood run
+                    int delta = c.nbeg[0], q = 0;       // npre[0] = 0
+#pragma unroll
+                    for (int qq = 1; qq < 9; ++qq) {
+                        const bool ge = j >= c.npre[qq];
+                        delta = ge ? c.nbeg[qq] - c.npre[qq] : delta;
+                        q = ge ? qq : q;
+                    }
+                    const int gi = j + delta;
                     if constexpr (MIXED) {
-                        float4 t = pk[j];
-                        t.x += float((q % 3) - 1);   // source relative to the target leaf centre
-                        t.y += float((q / 3) - 1);
-                        src[k - base] = t;
+                        float4 t = pk[gi];
+                        const int qy = (q * 11) >> 5;   // q / 3 for q < 9
+                        t.x += float(q - 3 * qy - 1);   // source relative to the target leaf centre
+                        t.y += float(qy - 1);
+                        val[sl] = t;
                     } else {
-                        src[k - base] = Src64{xs[j], ys[j], gs[j]};
+                        val[sl] = Src64{xs[gi], ys[gi], gs[gi]};
                     }
                 }
             }
-            for (int k = cnt + lane; k < padded; k += 64) {
-                // inert padding: no circulation, far from every target
-                if constexpr (MIXED) src[k] = make_float4(1.0e4f, 1.0e4f, 0.0f, 0.0f);
-                else src[k] = Src64{1.0e10, 1.0e10, 0.0};
+            wave_sync();
+#pragma unroll
+            for (int sl = 0; sl < kStageSlots; ++sl) {
+                const int k = lane + 64 * sl;
+                if (k < padded) src[k] = val[sl];
             }
             wave_sync();
             if constexpr (MIXED) p2p_f32<R>(src, padded, S, si, c.c2, oxi, oyi, fx, fy);
@@ -238,21 +269,22 @@ __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* 
                 sy[r] = vy;
             }
         }
-        // slice lane si < R finishes target r = si: far field and output
-        const int i = c0 + tg + TG * si;
-        if (si < R && i < c.nt) {
+        if (own) {
             double accx = sx[0], accy = sy[0];
+            if constexpr (!MIXED) { px = xi[0]; py = yi[0]; }
 #pragma unroll
             for (int r = 1; r < R; ++r)
-                if (si == r) { accx = sx[r]; accy = sy[r]; }
-            const int ip = c.s0 + i;
+                if (si == r) {
+                    accx = sx[r];
+                    accy = sy[r];
+                    if constexpr (!MIXED) { px = xi[r]; py = yi[r]; }
+                }
             if (has_far) {
-                const double zx = (xs[ip] - c.cx) * c.s, zy = (ys[ip] - c.cy) * c.s;
-                const cd* bl = le_leaf + int64_t(c.m) * P;      // terms >= p are zero
+                const double zx = (px - c.cx) * c.s, zy = (py - c.cy) * c.s;
                 double hx = 0.0, hy = 0.0;
 #pragma unroll
-                for (int k = P - 1; k >= 0; --k) {
-                    const cd t = bl[k];
+                for (int k = P - 1; k >= 0; --k) {     // terms >= p are zero
+                    const cd t = le_sh[k];
                     const double nx = hx * zx - hy * zy + t.x;
                     hy = hx * zy + hy * zx + t.y;
                     hx = nx;
@@ -260,7 +292,6 @@ __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* 
                 accx += hx * c.s;
                 accy += hy * c.s;
             }
-            const uint32_t o = perm[ip];
             u[o] = accy * kInv2Pi;
             v[o] = accx * kInv2Pi;
         }
@@ -278,6 +309,7 @@ k_p2p_l2p(Work wk, int n_inst, const Inst* __restrict__ inst, const int32_t* __r
 {
     using Stage = typename std::conditional<MIXED, float4, Src64>::type;
     __shared__ Stage stage_all[WAVES][kNearStage];
+    __shared__ cd le_all_sh[WAVES][P];
 
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int qi = find_inst(wk.wg_begin, n_inst, blockIdx.x);
@@ -325,12 +357,13 @@ k_p2p_l2p(Work wk, int n_inst, const Inst* __restrict__ inst, const int32_t* __r
     // register blocking pays once a chunk is full; sparse leaves keep one
     // target per lane (fewer slices to combine)
     void* st = stage_all[wv];
+    cd* lsh = le_all_sh[wv];
     if (c.lgT == 6)
-        leaf_near_far<P, MIXED, 4>(c, lane, st, has_far, xs, ys, gs, pk, perm, le_leaf, u, v);
+        leaf_near_far<P, MIXED, 4>(c, lane, st, lsh, has_far, xs, ys, gs, pk, perm, le_leaf, u, v);
     else if (c.lgT == 5)
-        leaf_near_far<P, MIXED, 2>(c, lane, st, has_far, xs, ys, gs, pk, perm, le_leaf, u, v);
+        leaf_near_far<P, MIXED, 2>(c, lane, st, lsh, has_far, xs, ys, gs, pk, perm, le_leaf, u, v);
     else
-        leaf_near_far<P, MIXED, 1>(c, lane, st, has_far, xs, ys, gs, pk, perm, le_leaf, u, v);
+        leaf_near_far<P, MIXED, 1>(c, lane, st, lsh, has_far, xs, ys, gs, pk, perm, le_leaf, u, v);
 }
 
 template <int P, int WAVES>

@@ -68,24 +68,35 @@ k_upward(Work wk, int n_inst, const Inst* __restrict__ inst, int p, int from_par
 #pragma unroll
             for (int q = 0; q < KR; ++q) { ax[q] = 0.0; ay[q] = 0.0; }
             const int s0 = leaf_start[leaf], s1 = leaf_start[leaf + 1];
-            for (int j = s0; j < s1; ++j) {
-                const double zx = (xs[j] - cx) * dm.s, zy = (ys[j] - cy) * dm.s;
-                // z^4 and gamma z^r
-                const double z2x = zx * zx - zy * zy, z2y = 2.0 * zx * zy;
-                const double z4x = z2x * z2x - z2y * z2y, z4y = 2.0 * z2x * z2y;
-                double px = gs[j], py = 0.0;
-                for (int t = 0; t < r; ++t) {
-                    const double nx = px * zx - py * zy;
-                    py = px * zy + py * zx;
-                    px = nx;
+            constexpr int kBatch = 4;       // particles whose loads are issued together
+            for (int j0 = s0; j0 < s1; j0 += kBatch) {
+                double bxp[kBatch], byp[kBatch], bgp[kBatch];
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    // past the end: reload the last particle with zero circulation
+                    const int j = min(j0 + u, s1 - 1);
+                    bxp[u] = xs[j];
+                    byp[u] = ys[j];
+                    bgp[u] = j0 + u < s1 ? gs[j] : 0.0;
                 }
 #pragma unroll
-                for (int q = 0; q < KR; ++q) {
-                    ax[q] += px;
-                    ay[q] += py;
-                    const double nx = px * z4x - py * z4y;
-                    py = px * z4y + py * z4x;
-                    px = nx;
+                for (int u = 0; u < kBatch; ++u) {
+                    const double zx = (bxp[u] - cx) * dm.s, zy = (byp[u] - cy) * dm.s;
+                    // z^2, z^3, z^4 and gamma z^r (r = this thread's first term)
+                    const double z2x = zx * zx - zy * zy, z2y = 2.0 * zx * zy;
+                    const double z3x = z2x * zx - z2y * zy, z3y = z2x * zy + z2y * zx;
+                    const double z4x = z2x * z2x - z2y * z2y, z4y = 2.0 * z2x * z2y;
+                    const double rx = r == 0 ? 1.0 : (r == 1 ? zx : (r == 2 ? z2x : z3x));
+                    const double ry = r == 0 ? 0.0 : (r == 1 ? zy : (r == 2 ? z2y : z3y));
+                    double px = bgp[u] * rx, py = bgp[u] * ry;
+#pragma unroll
+                    for (int q = 0; q < KR; ++q) {
+                        ax[q] += px;
+                        ay[q] += py;
+                        const double nx = px * z4x - py * z4y;
+                        py = px * z4y + py * z4x;
+                        px = nx;
+                    }
                 }
             }
             cd* dst = me + (level_offset(L) + int64_t(leaf)) * P;
