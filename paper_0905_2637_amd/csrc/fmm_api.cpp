@@ -865,14 +865,24 @@ fmm_status fmm_debug_dump(fmm_plan_t plan, int32_t what, void* host_buf, size_t 
         return e == hipSuccess ? FMM_OK : FMM_E_DEVICE;
     }
     if (what == FMM_DUMP_ME || what == FMM_DUMP_LE) {
-        // device rows hold P coefficients; hand out the first p of each
+        // device rows hold P coefficients; hand out the first p of each.
+        // Multipole rows hold abar_k = (-1)^(k+1) ahat_k / k!: undo that.
         const int P = plan->P, p = prm.p;
         std::vector<cd> tmp(nbox * size_t(P));
         if (hipMemcpy(tmp.data(), src, tmp.size() * sizeof(cd), hipMemcpyDeviceToHost) != hipSuccess)
             return FMM_E_DEVICE;
+        std::vector<double> unscale(p, 1.0);
+        if (what == FMM_DUMP_ME) {
+            long double f = 1.0L;
+            for (int k = 0; k < p; ++k) {
+                if (k > 0) f *= (long double)k;
+                unscale[k] = double((k % 2) ? f : -f);
+            }
+        }
         cd* out = static_cast<cd*>(host_buf);
         for (size_t bx = 0; bx < nbox; ++bx)
-            for (int k = 0; k < p; ++k) out[bx * p + k] = tmp[bx * P + k];
+            for (int k = 0; k < p; ++k)
+                out[bx * p + k] = cd{tmp[bx * P + k].x * unscale[k], tmp[bx * P + k].y * unscale[k]};
         return FMM_OK;
     }
     if (hipMemcpy(host_buf, src, sz, hipMemcpyDeviceToHost) != hipSuccess) return FMM_E_DEVICE;

@@ -12,8 +12,10 @@
 //   h_n(tau) = n! tau^-(n+1),   abar_k = (-1)^(k+1) ahat_k / k!,
 // so each of the 40 offsets is described by 2p-1 numbers instead of p^2 and
 // the whole table (49 slots of a 7 x 7 grid, FP64 and FP32 copies) stays in
-// the scalar/L1 caches.  The product is dense: every (k, l) pair is one
-// complex multiply-add, 8 p^2 flops per interaction-list pair.
+// the scalar/L1 caches.  The multipole arrays already hold abar (the upward
+// sweep stores them that way), so only the output scaling 1/l! remains.  The
+// product is dense: every (k, l) pair is one complex multiply-add, 8 p^2
+// flops per interaction-list pair.
 //
 // Lane mapping: a workgroup of 4 wavefronts covers 16 x 16 target boxes of
 // one level; wavefront c holds the 64 boxes in child position c of their
@@ -23,6 +25,8 @@
 // handled by one launch (M2L of different levels are independent); L2L then
 // runs down the tree, adding the parent's shifted expansion.
 #include "fmm_device.h"
+
+#include <type_traits>
 
 namespace fmm {
 namespace {
@@ -45,8 +49,23 @@ struct M2LOut {
 template <int P, typename T>
 __global__ void __launch_bounds__(256)
 k_m2l(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restrict__ me_all, M2LOut dst_,
-      const cplx<T>* __restrict__ H, const double* __restrict__ sin_, const double* __restrict__ sout_)
+      const cplx<T>* __restrict__ H, const double* __restrict__ sout_)
 {
+    // FP32 (fine levels, the bulk of the pairs): the translation data of all
+    // 49 offset slots is staged once per workgroup and read back as LDS
+    // broadcasts, and the source terms are applied in blocks of at most 8;
+    // both keep the register count down (more wavefronts per SIMD).  FP64
+    // reads the data through scalar loads and applies all terms at once,
+    // which measured faster there.
+    constexpr bool kF32 = std::is_same<T, float>::value;
+    constexpr int NH = 2 * P - 1;
+    __shared__ cplx<T> sH[kF32 ? kHankelGrid * kHankelGrid * NH : 1];
+    const cplx<T>* Hs = H;
+    if constexpr (kF32) {
+        for (int e = threadIdx.x; e < kHankelGrid * kHankelGrid * NH; e += 256) sH[e] = H[e];
+        __syncthreads();
+        Hs = sH;
+    }
     const int G = gridDim.y, g = blockIdx.y;
     const int q = find_inst(wk.wg_begin, n_inst, blockIdx.x);
     int bl = blockIdx.x - wk.wg_begin[q];
@@ -65,34 +84,110 @@ k_m2l(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restrict__
     const bool active = ta < side && tb < side;
     const cd* me_l = me + level_offset(l) * P;
 
+    constexpr int kHStep = 4;                  // FP32: translation values in flight
+    constexpr int NB = kF32 ? (P + 7) / 8 : 1; // input blocks
+    constexpr int KB = (P + NB - 1) / NB;      // terms per block
     T bx_[P], by_[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) { bx_[k] = T(0); by_[k] = T(0); }
 
     int member = 0;
-    for (int o = 0; o < 36; ++o) {
-        int dx, dy;
-        if (!il_offset(cx, cy, o, dx, dy)) continue;
-        if ((member++) % G != g) continue;
-        const int sa = ta + dx, sb = tb + dy;
-        if (!(active && sa >= 0 && sb >= 0 && sa < side && sb < side)) continue;
-        const cd* src = me_l + int64_t(morton(uint32_t(sa), uint32_t(sb))) * P;
-        T ax[P], ay[P];
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
-            const cd t = src[k];
-            const double sc = sin_[k];      // zero for k >= p
-            ax[k] = T(t.x * sc);
-            ay[k] = T(t.y * sc);
+    // next interaction-list slot at or after o that belongs to this
+    // workgroup row (uniform), 36 when there is none
+    auto next_member = [&](int o) -> int {
+        for (; o < 36; ++o) {
+            int dx, dy;
+            if (!il_offset(cx, cy, o, dx, dy)) continue;
+            if ((member++) % G == g) return o;
         }
-        const cplx<T>* h = H + ((dy + 3) * kHankelGrid + (dx + 3)) * (2 * P - 1);
+        return 36;
+    };
+    auto source = [&](int o, bool& ok) -> const cd* {
+        int dx, dy;
+        il_offset(cx, cy, o, dx, dy);
+        const int sa = ta + dx, sb = tb + dy;
+        ok = active && sa >= 0 && sb >= 0 && sa < side && sb < side;
+        return me_l + int64_t(morton(uint32_t(ok ? sa : 0), uint32_t(ok ? sb : 0))) * P;
+    };
+    auto table = [&](int o) -> const cplx<T>* {
+        int dx, dy;
+        il_offset(cx, cy, o, dx, dy);
+        return Hs + ((dy + 3) * kHankelGrid + (dx + 3)) * NH;
+    };
+
+    if constexpr (!kF32) {
+        // FP64: the next member's source terms are loaded while the current
+        // member's are applied (two register buffers, all p terms at once)
+        T ax0[P], ay0[P], ax1[P], ay1[P];
+        bool ok0 = false, ok1 = false;
+        auto load = [&](int o, T (&ax)[P], T (&ay)[P], bool& ok) {
+            const cd* src = source(o, ok);
+            if (ok) {
 #pragma unroll
-        for (int nn = 0; nn < 2 * P - 1; ++nn) {
-            const cplx<T> hn = h[nn];
+                for (int k = 0; k < P; ++k) {
+                    const cd t = src[k];            // abar_k, zero for k >= p
+                    ax[k] = t.x;
+                    ay[k] = t.y;
+                }
+            }
+        };
+        auto apply = [&](int o, const T (&ax)[P], const T (&ay)[P], bool ok) {
+            const cplx<T>* h = table(o);
+            if (ok) {
 #pragma unroll
-            for (int k = 0; k < P; ++k) {
-                const int j = nn - k;
-                if (j >= 0 && j < P) cmac(bx_[j], by_[j], hn.x, hn.y, ax[k], ay[k]);
+                for (int nn = 0; nn < 2 * P - 1; ++nn) {
+                    const cplx<T> hn = h[nn];
+#pragma unroll
+                    for (int k = 0; k < P; ++k) {
+                        const int j = nn - k;
+                        if (j >= 0 && j < P) cmac(bx_[j], by_[j], hn.x, hn.y, ax[k], ay[k]);
+                    }
+                }
+            }
+        };
+        int oa = next_member(0);
+        if (oa < 36) load(oa, ax0, ay0, ok0);
+        while (oa < 36) {
+            const int ob = next_member(oa + 1);
+            if (ob < 36) load(ob, ax1, ay1, ok1);
+            apply(oa, ax0, ay0, ok0);
+            if (ob >= 36) break;
+            oa = next_member(ob + 1);
+            if (oa < 36) load(oa, ax0, ay0, ok0);
+            apply(ob, ax1, ay1, ok1);
+        }
+    } else {
+        // FP32: source terms in blocks of KB, only one block live next to the
+        // P accumulators
+        for (int o = next_member(0); o < 36; o = next_member(o + 1)) {
+            bool ok;
+            const cd* src = source(o, ok);
+            if (!ok) continue;
+            const cplx<T>* h = table(o);
+#pragma unroll
+            for (int kb = 0; kb < P; kb += KB) {
+                T ax[KB], ay[KB];
+#pragma unroll
+                for (int kk = 0; kk < KB; ++kk) {
+                    const int k = kb + kk;
+                    if (k < P) {
+                        const cd t = src[k];        // abar_k, zero for k >= p
+                        ax[kk] = T(t.x);
+                        ay[kk] = T(t.y);
+                    }
+                }
+#pragma unroll
+                for (int nn = kb; nn < kb + KB + P - 1; ++nn) {
+                    if (nn > 2 * P - 2) break;
+                    const cplx<T> hn = h[nn];
+#pragma unroll
+                    for (int kk = 0; kk < KB; ++kk) {
+                        const int k = kb + kk, j = nn - k;
+                        if (k < P && j >= 0 && j < P) cmac(bx_[j], by_[j], hn.x, hn.y, ax[kk], ay[kk]);
+                    }
+                    if ((nn - kb) % kHStep == kHStep - 1) __builtin_amdgcn_sched_barrier(0);
+                }
+                if (NB > 1) __builtin_amdgcn_sched_barrier(0);
             }
         }
     }
@@ -210,12 +305,12 @@ hipError_t m2l_impl(const Buffers& b, const Work& w, int nwg, bool fp32, int gro
     if constexpr (P <= 24) {
         if (fp32) {
             hipLaunchKernelGGL((k_m2l<P, float>), grid, dim3(256), 0, st, w, b.n_inst, b.inst, b.me, out,
-                               reinterpret_cast<const cplx<float>*>(b.t_h32), b.t_sin, b.t_sout);
+                               reinterpret_cast<const cplx<float>*>(b.t_h32), b.t_sout);
             return hipGetLastError();
         }
     }
     hipLaunchKernelGGL((k_m2l<P, double>), grid, dim3(256), 0, st, w, b.n_inst, b.inst, b.me, out,
-                       reinterpret_cast<const cplx<double>*>(b.t_h64), b.t_sin, b.t_sout);
+                       reinterpret_cast<const cplx<double>*>(b.t_h64), b.t_sout);
     return hipGetLastError();
 }
 

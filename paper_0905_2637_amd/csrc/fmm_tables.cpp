@@ -2,15 +2,20 @@
 // operators of the scaled 1/z expansions (built once per plan, FP64, with the
 // powers and factorials accumulated in long double before rounding).
 //
-//   M2M  (child position c, delta = (+-1 +- i)/4, see fmm_upward.hip)
-//        M[c][k][j] = C(k,j) 2^-j delta^(k-j),            j <= k < p
+// Multipole coefficients are stored as abar_k = s_k ahat_k with
+// s_k = (-1)^(k+1) / k!, the input scaling of the factored M2L, so that M2L
+// reads them as they are.
+//   M2M  (child position c, delta = (+-1 +- i)/4, see fmm_upward.hip) on
+//        ahat: M[k][j] = C(k,j) 2^-j delta^(k-j), j <= k < p; on abar the same
+//        map is S M S^-1:
+//        M'[c][k][j] = (-1)^(k-j) 2^-j delta^(k-j) / (k-j)!
 //   L2L  Lt[c][k][j] = C(j,k) delta^(j-k) 2^-(k+1),       p > k, j >= k
 //        (rows k >= p of both are zero, so zero-padded terms stay zero)
 //   M2L  Hankel data h_n(tau) = n! tau^-(n+1) for the integer offsets
 //        tau = dx + i dy, |dx|, |dy| <= 3 (7 x 7 grid, the 9 touching offsets
 //        unused), n = 0 .. 2p-2; zero for n > 2p-2 so that zero-padded terms
 //        never meet an overflowed FP32 entry.
-//        sin[k] = (-1)^(k+1) / k!,  sout[l] = 1 / l!   (see fmm_downward.hip)
+//        sin[k] = s_k = (-1)^(k+1) / k!,  sout[l] = 1 / l!   (see fmm_downward.hip)
 #include <complex>
 #include <vector>
 
@@ -48,7 +53,12 @@ void build_tables(int P, int p, cd* m2m, cd* l2l, cd* h64, cf* h32, double* sin_
             for (int j = 0; j < P; ++j) {
                 cld mv = 0.0L, lv = 0.0L;
                 // rows k >= p stay zero: the padded terms never fill up
-                if (k < p && j <= k) mv = binom(k, j) * std::pow(0.5L, (long double)j) * pw[k - j];
+                if (k < p && j <= k) {
+                    long double f = 1.0L;                       // (k - j)!
+                    for (int i = 2; i <= k - j; ++i) f *= (long double)i;
+                    const long double sg = ((k - j) % 2) ? -1.0L : 1.0L;
+                    mv = sg * std::pow(0.5L, (long double)j) * pw[k - j] / f;
+                }
                 if (k < p && j >= k) lv = binom(j, k) * pw[j - k] * std::pow(0.5L, (long double)(k + 1));
                 m2m[(c * P + k) * P + j] = to_cd(mv);
                 l2l[(c * P + k) * P + j] = to_cd(lv);

@@ -153,38 +153,30 @@ k_scan_reduce(int64_t m, const int32_t* __restrict__ in, int32_t* __restrict__ p
     if (threadIdx.x == 0) part[blockIdx.x] = total;
 }
 
-// Single workgroup: exclusive scan of the chunk sums, part[nb] = grand total.
-__global__ void __launch_bounds__(256) k_scan_top(int nb, int32_t* __restrict__ part)
-{
-    int carry = 0;
-    for (int base = 0; base < nb; base += 256) {
-        const int i = base + threadIdx.x;
-        const int v = i < nb ? part[i] : 0;
-        int total;
-        const int e = block_excl_scan(v, &total);
-        if (i < nb) part[i] = carry + e;
-        carry += total;
-    }
-    if (threadIdx.x == 0) part[nb] = carry;
-}
-
+// Second level: every workgroup adds up the chunk sums before its own (there
+// are few: n / 4096 tiles x 256 digits / 2048 per chunk), scans its chunk
+// and the last one writes the grand total to out[m].
 __global__ void __launch_bounds__(256)
 k_scan_down(int64_t m, int nb, const int32_t* __restrict__ in, const int32_t* __restrict__ part,
             int32_t* __restrict__ out)
 {
+    int pre = 0;
+    for (int i = threadIdx.x; i < int(blockIdx.x); i += 256) pre += part[i];
+    int before;
+    block_excl_scan(pre, &before);          // the block sum of pre: every chunk before this one
     const int64_t base = int64_t(blockIdx.x) * kScanChunk + int64_t(threadIdx.x) * kScanPerThread;
     int v[kScanPerThread];
     int s = 0;
 #pragma unroll
     for (int k = 0; k < kScanPerThread; ++k) { v[k] = (base + k < m) ? in[base + k] : 0; s += v[k]; }
     int total;
-    int run = block_excl_scan(s, &total) + part[blockIdx.x];
+    int run = block_excl_scan(s, &total) + before;
 #pragma unroll
     for (int k = 0; k < kScanPerThread; ++k) {
         if (base + k < m) out[base + k] = run;
         run += v[k];
     }
-    if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[m] = part[nb];
+    if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[m] = before + total;
 }
 
 // ---------------------------------------------------------------------------
@@ -222,6 +214,16 @@ k_rhist_keys(int n, const double* __restrict__ x, const double* __restrict__ y, 
     __syncthreads();
     const int64_t base = int64_t(blockIdx.x) * kRadixTile;
     int mybad = 0;
+    // all coordinate loads first, then keys and counting
+    double xv[kRadixRounds], yv[kRadixRounds];
+#pragma unroll
+    for (int r = 0; r < kRadixRounds; ++r) {
+        const int64_t i = base + r * kRadixThreads + threadIdx.x;
+        const int64_t ic = i < n ? i : base;
+        xv[r] = x[ic];
+        yv[r] = y[ic];
+    }
+#pragma unroll
     for (int r = 0; r < kRadixRounds; ++r) {
         const int64_t i = base + r * kRadixThreads + threadIdx.x;
         if (i < n) {
@@ -230,8 +232,8 @@ k_rhist_keys(int n, const double* __restrict__ x, const double* __restrict__ y, 
             const Domain d = inst[q].dom;
             const int side = 1 << L;
             bool bad = false;
-            const int a = axis_box(x[i], d.x0, d.s, side, bad);
-            const int b = axis_box(y[i], d.y0, d.s, side, bad);
+            const int a = axis_box(xv[r], d.x0, d.s, side, bad);
+            const int b = axis_box(yv[r], d.y0, d.s, side, bad);
             const uint32_t k = (uint32_t(q) << key_shift) | (morton(uint32_t(a), uint32_t(b)) << (key_shift - 2 * L));
             key[i] = k;
             atomicAdd(&h[k & (kRadixBins - 1)], 1);
@@ -268,9 +270,16 @@ k_rhist(int n, const uint32_t* __restrict__ kin, int shift, int nblk, int32_t* _
     h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = int64_t(blockIdx.x) * kRadixTile;
+    uint32_t kv[kRadixRounds];
+#pragma unroll
     for (int r = 0; r < kRadixRounds; ++r) {
         const int64_t i = base + r * kRadixThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[(kin[i] >> shift) & (kRadixBins - 1)], 1);
+        kv[r] = kin[i < n ? i : base];
+    }
+#pragma unroll
+    for (int r = 0; r < kRadixRounds; ++r) {
+        const int64_t i = base + r * kRadixThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(kv[r] >> shift) & (kRadixBins - 1)], 1);
     }
     __syncthreads();
     hist[int64_t(threadIdx.x) * nblk + blockIdx.x] = h[threadIdx.x];
@@ -306,37 +315,43 @@ k_rscatter(int n, const uint32_t* __restrict__ kin, const uint32_t* __restrict__
 {
     __shared__ int gbase[kRadixBins];      // global start of this tile's run of digit d
     __shared__ int tstart[kRadixBins];     // start of digit d in the sorted tile
-    __shared__ int run[kRadixBins];        // records of digit d placed so far
-    __shared__ int wcnt[kRadixThreads / 64][kRadixBins];
+    __shared__ int whist[kRadixThreads / 64][kRadixBins];   // per wavefront: records of digit d so far
     __shared__ uint32_t sk[kRadixTile];
     __shared__ double sv[kRadixTile];
     const int tid = threadIdx.x, lane = int(__lane_id()), w = tid >> 6;
     const int64_t tile = int64_t(blockIdx.x) * kRadixTile;
     const int tile_n = int(min(int64_t(kRadixTile), int64_t(n) - tile));
 
+    // ---- phase A: load the tile and rank it ----
+    // Wavefront w owns the input positions [w * kWaveKeys, (w + 1) * kWaveKeys)
+    // of the tile, 64 per round.
+    constexpr int kWaveKeys = kRadixTile / (kRadixThreads / 64);
+    uint32_t kr[kPerThread], vr[kPerThread];
+    double xr[kPerThread], yr[kPerThread], gr[kPerThread];
     int total;
     tstart[tid] = block_excl_scan(hist[int64_t(tid) * nblk + blockIdx.x], &total);
     gbase[tid] = offs[int64_t(tid) * nblk + blockIdx.x];
-    run[tid] = 0;
 #pragma unroll
-    for (int q = 0; q < kRadixThreads / 64; ++q) wcnt[q][tid] = 0;
+    for (int q = 0; q < kRadixThreads / 64; ++q) whist[q][tid] = 0;
     __syncthreads();
 
-    // ---- phase A: load the tile (input order) and rank it ----
+    // rank within the wavefront, round after round (input order): equal
+    // digits of one round are told apart by 8 ballots, earlier rounds by the
+    // wavefront's running count of the digit
     const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
-    int lpos[kPerThread];
-    uint32_t kr[kPerThread], vr[kPerThread];
-    double xr[kPerThread], yr[kPerThread], gr[kPerThread];
+    int lpos[kPerThread], dig[kPerThread];
 #pragma unroll
     for (int r = 0; r < kPerThread; ++r) {
-        const int li = r * kRadixThreads + tid;
+        const int li = w * kWaveKeys + r * 64 + lane;
         const bool valid = li < tile_n;
-        const int64_t i = tile + li;
-        kr[r] = valid ? kin[i] : 0u;
-        vr[r] = valid ? (iin ? iin[i] : uint32_t(i)) : 0u;
-        xr[r] = valid ? xin[i] : 0.0;
-        yr[r] = valid ? yin[i] : 0.0;
-        gr[r] = valid ? gin[i] : 0.0;
+        {
+            const int64_t i = tile + (valid ? li : 0);
+            kr[r] = valid ? kin[i] : 0u;
+            vr[r] = iin ? iin[i] : uint32_t(i);
+            xr[r] = xin[i];
+            yr[r] = yin[i];
+            gr[r] = gin[i];
+        }
         const int d = int((kr[r] >> shift) & (kRadixBins - 1));
         uint64_t same = __ballot(valid);
 #pragma unroll
@@ -346,18 +361,30 @@ k_rscatter(int n, const uint32_t* __restrict__ kin, const uint32_t* __restrict__
             same &= bit ? bb : ~bb;
         }
         const int rank = __popcll(same & lt_mask);
-        if (valid && rank == 0) wcnt[w][d] = __popcll(same);
-        __syncthreads();
-        int pos = tstart[d] + run[d] + rank;
-        for (int q = 0; q < w; ++q) pos += wcnt[q][d];
-        lpos[r] = valid ? pos : -1;
-        __syncthreads();
-        int add = 0;
-#pragma unroll
-        for (int q = 0; q < kRadixThreads / 64; ++q) { add += wcnt[q][tid]; wcnt[q][tid] = 0; }
-        run[tid] += add;
-        __syncthreads();
+        const int before = whist[w][d];
+        __builtin_amdgcn_wave_barrier();
+        if (valid && rank == 0) whist[w][d] = before + __popcll(same);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        lpos[r] = valid ? before + rank : -1;
+        dig[r] = d;
     }
+    __syncthreads();
+    // exclusive prefix over the wavefronts, per digit
+    {
+        int acc = 0;
+#pragma unroll
+        for (int q = 0; q < kRadixThreads / 64; ++q) {
+            const int t = whist[q][tid];
+            whist[q][tid] = acc;
+            acc += t;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r)
+        if (lpos[r] >= 0) lpos[r] += tstart[dig[r]] + whist[w][dig[r]];
 
     // ---- phase B: stage each array in sorted order, write whole runs ----
     int dst[kPerThread];
@@ -460,15 +487,39 @@ __device__ __forceinline__ int64_t leaf_entry(uint32_t k, const Inst* __restrict
 // entry e < entries: position i owns the entries in (entry(i-1), entry(i)].
 // Each instance's segment ends with one extra entry, which thereby receives
 // the first position of the next instance (its particle count end).
+// A workgroup takes kBoundsRounds x 256 consecutive positions, 256 per round
+// (coalesced); all its key loads are issued before any range is written,
+// and a single-instance plan reads its instance record once.
+constexpr int kBoundsRounds = 16;
+
 __global__ void __launch_bounds__(256)
-k_bounds(int n, int64_t entries, const uint32_t* __restrict__ ks, const Inst* __restrict__ inst, int key_shift,
-         int32_t* __restrict__ leaf_start)
+k_bounds(int n, int64_t entries, const uint32_t* __restrict__ ks, const Inst* __restrict__ inst, int n_inst,
+         int key_shift, int32_t* __restrict__ leaf_start)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > n) return;
-    const int64_t lo = i == 0 ? 0 : leaf_entry(ks[i - 1], inst, key_shift) + 1;
-    const int64_t hi = i == n ? entries - 1 : leaf_entry(ks[i], inst, key_shift);
-    for (int64_t e = lo; e <= hi; ++e) leaf_start[e] = i;
+    const int64_t base = int64_t(blockIdx.x) * (256 * kBoundsRounds) + threadIdx.x;
+    uint32_t kp[kBoundsRounds], kc[kBoundsRounds];      // keys of i - 1 and i
+#pragma unroll
+    for (int r = 0; r < kBoundsRounds; ++r) {
+        const int64_t i = base + int64_t(r) * 256;
+        const int64_t ip = i - 1 < 0 ? 0 : (i - 1 < n ? i - 1 : n - 1);
+        const int64_t ic = i < n ? i : n - 1;
+        kp[r] = ks[ip];
+        kc[r] = ks[ic];
+    }
+    const int L0 = inst[0].L;
+    const int64_t off0 = inst[0].leaf_off;
+    auto entry = [&](uint32_t k) -> int64_t {
+        if (n_inst == 1) return off0 + int64_t(k >> (key_shift - 2 * L0));
+        return leaf_entry(k, inst, key_shift);
+    };
+#pragma unroll
+    for (int r = 0; r < kBoundsRounds; ++r) {
+        const int64_t i = base + int64_t(r) * 256;
+        if (i > n) break;
+        const int64_t lo = i == 0 ? 0 : entry(kp[r]) + 1;
+        const int64_t hi = i == n ? entries - 1 : entry(kc[r]);
+        for (int64_t e = lo; e <= hi; ++e) leaf_start[e] = int32_t(i);
+    }
 }
 
 inline unsigned blocks_for(int64_t n, int bs) { return unsigned((n + bs - 1) / bs); }
@@ -493,7 +544,6 @@ void scan_table(const Buffers& b, int64_t m, hipStream_t st)
 {
     const int nsb = int((m + kScanChunk - 1) / kScanChunk);
     hipLaunchKernelGGL(k_scan_reduce, dim3(nsb), dim3(256), 0, st, m, b.hist, b.scan_part);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, st, nsb, b.scan_part);
     hipLaunchKernelGGL(k_scan_down, dim3(nsb), dim3(256), 0, st, m, nsb, b.hist, b.scan_part, b.hist_scan);
 }
 
@@ -533,8 +583,8 @@ hipError_t launch_tree(const Buffers& b, int n, const double* x, const double* y
             gin = out.g;
         }
     }
-    hipLaunchKernelGGL(k_bounds, dim3(blocks_for(int64_t(n) + 1, 256)), dim3(256), 0, st, n, leaf_entries,
-                       b.ksorted, b.inst, b.key_shift, b.leaf_start);
+    hipLaunchKernelGGL(k_bounds, dim3(blocks_for(int64_t(n) + 1, 256 * kBoundsRounds)), dim3(256), 0, st, n,
+                       leaf_entries, b.ksorted, b.inst, b.n_inst, b.key_shift, b.leaf_start);
     return hipGetLastError();
 }
 

@@ -10,6 +10,11 @@
 //   ahat^P_k = sum_{m<=k} C(k,m) 2^-m delta^(k-m) ahat^child_m,
 // one of four fixed lower-triangular matrices built on the host.
 //
+// What is stored is abar_k = s_k ahat_k, s_k = (-1)^(k+1) / k! (the input
+// scaling of the factored M2L, which then reads the coefficients as they
+// are): P2M multiplies by s_k once, and the M2M matrices are built for abar
+// (S M S^-1, entries (-1)^(k-m) 2^-m delta^(k-m) / (k-m)!).
+//
 // Storage: every box holds P >= p coefficients (P the compiled expansion
 // size), terms k >= p zero; the operator rows k >= p are zero as well, so
 // the padding stays zero and no loop needs the runtime p.
@@ -36,7 +41,8 @@ template <int P>
 __global__ void __launch_bounds__(kUpThreads)
 k_upward(Work wk, int n_inst, const Inst* __restrict__ inst, int p, int from_particles,
          const int32_t* __restrict__ leaf_start_all, const double* __restrict__ xs, const double* __restrict__ ys,
-         const double* __restrict__ gs, cd* __restrict__ me_all, const cd* __restrict__ M)
+         const double* __restrict__ gs, cd* __restrict__ me_all, const cd* __restrict__ M,
+         const double* __restrict__ sk)
 {
     __shared__ cd sh[85 * P];            // 64 + 16 + 4 + 1 boxes
     __shared__ cd sM[4 * P * P];         // the four M2M matrices
@@ -104,7 +110,8 @@ k_upward(Work wk, int n_inst, const Inst* __restrict__ inst, int p, int from_par
             for (int q = 0; q < KR; ++q) {
                 const int k = r + kP2MLanes * q;
                 if (k < P) {
-                    const cd val = k < p ? cd{ax[q], ay[q]} : cd{0.0, 0.0};   // terms >= p stay zero
+                    const double sc = sk[k];                  // s_k; zero for k >= p
+                    const cd val = cd{ax[q] * sc, ay[q] * sc};
                     sh[i * P + k] = val;
                     dst[k] = val;
                 }
@@ -149,7 +156,7 @@ hipError_t upward_impl(const Buffers& b, int p, const Work& w, int nwg, bool lea
 {
     if (nwg <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_upward<P>, dim3(unsigned(nwg)), dim3(kUpThreads), 0, st, w, b.n_inst, b.inst, p,
-                       leaves ? 1 : 0, b.leaf_start, b.xs, b.ys, b.gs, b.me, b.t_m2m);
+                       leaves ? 1 : 0, b.leaf_start, b.xs, b.ys, b.gs, b.me, b.t_m2m, b.t_sin);
     return hipGetLastError();
 }
 
