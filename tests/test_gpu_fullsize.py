@@ -1,0 +1,84 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py
+times (default launch shapes, the workload's own precision).
+
+Integer work (keys, permutation, leaf ranges) is compared bit for bit with
+the oracle over every particle.  Velocities are compared on a seeded sample
+of targets the oracle computes one by one: the FP64 workload against the
+oracle FMM (1e-12) and the FP64 split-kernel direct sum; the mixed-precision
+workloads against the FP64 split-kernel direct sum, within the 1e-6 gate.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    oracle.build()
+
+
+def _run(wl):
+    import torch
+    import paper_0905_2637_amd as fm
+    dev = torch.device("cuda")
+    x, y, g = (torch.as_tensor(a, device=dev) for a in (wl.x, wl.y, wl.gamma))
+    plan = fm.Plan(wl.n, wl.sigma, wl.p, wl.depth, domain=(wl.x0, wl.y0, wl.width),
+                   precision=wl.precision, fp32_fine_levels=wl.fp32_fine_levels)
+    u, v = plan.evaluate(x, y, g, check=True)
+    torch.cuda.synchronize()
+    out = (u.cpu().numpy(), v.cpu().numpy(), plan.dump(fm.DUMP_KEYS), plan.dump(fm.DUMP_PERM),
+           plan.dump(fm.DUMP_LEAF_START))
+    plan.close()
+    del x, y, g, u, v
+    torch.cuda.empty_cache()
+    return out
+
+
+def _tree_bit_exact(wl, keys, perm, leaf_start):
+    key_o, perm_o, ls_o, nbad = oracle.tree(wl.x, wl.y, wl.depth, wl.x0, wl.y0, wl.width)
+    assert nbad == 0
+    assert np.array_equal(keys, key_o), "keys differ from the oracle"
+    assert np.array_equal(perm, perm_o), "sort permutation differs from the oracle"
+    assert np.array_equal(leaf_start.astype(np.int64), ls_o), "leaf ranges differ from the oracle"
+
+
+def test_c2_full_size_fp64():
+    """1,048,576-particle Lamb-Oseen lattice, depth 8, p = 17, FP64."""
+    wl = workloads.make("C2")
+    u, v, keys, perm, ls = _run(wl)
+    _tree_bit_exact(wl, keys, perm, ls)
+    t = workloads.sample_targets(wl.n, 4096, 1002)
+    uo, vo = oracle.fmm(wl.x, wl.y, wl.gamma, wl.sigma, wl.p, wl.depth, wl.x0, wl.y0, wl.width, targets=t)
+    err = oracle.rel_l2(u[t], v[t], uo, vo)
+    assert err < 1e-12, f"rel L2 vs the oracle FMM {err:.3e}"
+    t2 = workloads.sample_targets(wl.n, 1024, 1012)
+    us, vs = oracle.direct_split(wl.x, wl.y, wl.gamma, wl.sigma, wl.depth, wl.x0, wl.y0, wl.width, targets=t2)
+    gate = oracle.rel_l2(u[t2], v[t2], us, vs)
+    assert gate < 1e-6, f"rel L2 vs the FP64 split direct sum {gate:.3e}"
+
+
+def test_c3_full_size_mixed():
+    """4,194,304 particles from a 16-component Gaussian mixture, depth 9,
+    p = 17, mixed precision (dense leaves of several hundred particles)."""
+    wl = workloads.make("C3")
+    u, v, keys, perm, ls = _run(wl)
+    _tree_bit_exact(wl, keys, perm, ls)
+    t = workloads.sample_targets(wl.n, 1024, 1003)
+    us, vs = oracle.direct_split(wl.x, wl.y, wl.gamma, wl.sigma, wl.depth, wl.x0, wl.y0, wl.width, targets=t)
+    gate = oracle.rel_l2(u[t], v[t], us, vs)
+    assert gate < 1e-6, f"rel L2 vs the FP64 split direct sum {gate:.3e}"
+
+
+def test_c5_full_size_mixed():
+    """2^26 particles uniform in the unit square, depth 11, p = 20, mixed."""
+    wl = workloads.make("C5")
+    u, v, keys, perm, ls = _run(wl)
+    _tree_bit_exact(wl, keys, perm, ls)
+    t = workloads.sample_targets(wl.n, 256, 1005)
+    us, vs = oracle.direct_split(wl.x, wl.y, wl.gamma, wl.sigma, wl.depth, wl.x0, wl.y0, wl.width, targets=t)
+    gate = oracle.rel_l2(u[t], v[t], us, vs)
+    assert gate < 1e-6, f"rel L2 vs the FP64 split direct sum {gate:.3e}"
