@@ -134,16 +134,20 @@ fmm_status fmm_evaluate_batch(fmm_plan_t plan, const double* d_x, const double* 
 /* Launch shapes.  p2p_waves: leaves (one wavefront each) per P2P workgroup,
  * 2 or 4 (default 4).  m2l_split_max: M2L levels <= min(L, m2l_split_max)
  * split each box's interaction list over three wavefronts (more parallelism
- * on levels with few boxes), 0 .. 8 (default 8; below 2: never).  Results
- * are identical up to the summation order of the split levels.
+ * on levels with few boxes), 0 .. 8 (default 8; below 2: never).
+ * m2l_mfma: 1 runs the FP32 M2L levels of the mixed form on the matrix
+ * cores (MFMA), 0 (default) on the vector units; FP64 levels always use the
+ * vector units.  Results are identical up to the summation order.
  * fmm_set_tuning synchronises `stream`.  fmm_autotune times every
- * combination of p2p_waves in {2, 4} and m2l_split_max in {0, 5, 8} on the
- * caller's data (reps timed evaluations each, after one warm-up; the output
- * arrays are overwritten), keeps the fastest and, when the environment
- * variable FMM_AUTOTUNE_CACHE names a file, looks the choice up there first
- * and appends it after a search.  For batched plans n is ignored. */
-fmm_status fmm_get_tuning(fmm_plan_t plan, int32_t* p2p_waves, int32_t* m2l_split_max);
-fmm_status fmm_set_tuning(fmm_plan_t plan, int32_t p2p_waves, int32_t m2l_split_max, void* stream);
+ * combination of p2p_waves in {2, 4}, m2l_split_max in {0, 5, 8} and, for a
+ * mixed plan, m2l_mfma in {0, 1} on the caller's data (reps timed
+ * evaluations each, after one warm-up; the output arrays are overwritten),
+ * keeps the fastest and, when the environment variable FMM_AUTOTUNE_CACHE
+ * names a file, looks the choice up there first and appends it after a
+ * search.  For batched plans n is ignored. */
+fmm_status fmm_get_tuning(fmm_plan_t plan, int32_t* p2p_waves, int32_t* m2l_split_max, int32_t* m2l_mfma);
+fmm_status fmm_set_tuning(fmm_plan_t plan, int32_t p2p_waves, int32_t m2l_split_max, int32_t m2l_mfma,
+                          void* stream);
 fmm_status fmm_autotune(fmm_plan_t plan, int64_t n, const double* d_x, const double* d_y,
                         const double* d_gamma, double* d_u, double* d_v, void* stream, int32_t reps);
 

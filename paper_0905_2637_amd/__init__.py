@@ -65,8 +65,8 @@ def load():
     lib.fmm_workspace_size_batch.argtypes = [C.POINTER(FmmParams), C.c_int32, i32p, i32p, C.POINTER(C.c_size_t)]
     lib.fmm_plan_batch.argtypes = [C.POINTER(FmmParams), C.c_int32, i32p, i32p, vp, C.c_size_t, vp, C.POINTER(vp)]
     lib.fmm_evaluate_batch.argtypes = [vp, vp, vp, vp, vp, vp, vp]
-    lib.fmm_get_tuning.argtypes = [vp, i32p, i32p]
-    lib.fmm_set_tuning.argtypes = [vp, C.c_int32, C.c_int32, vp]
+    lib.fmm_get_tuning.argtypes = [vp, i32p, i32p, i32p]
+    lib.fmm_set_tuning.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp]
     lib.fmm_autotune.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp, C.c_int32]
     lib.fmm_get_status.argtypes = [vp, vp, C.POINTER(C.c_int64)]
     lib.fmm_set_timing.argtypes = [vp, C.c_int32]
@@ -177,13 +177,14 @@ class _PlanBase:
     def tuning(self) -> dict:
         w = C.c_int32(0)
         sm = C.c_int32(0)
-        s = load().fmm_get_tuning(self._h, C.byref(w), C.byref(sm))
+        mf = C.c_int32(0)
+        s = load().fmm_get_tuning(self._h, C.byref(w), C.byref(sm), C.byref(mf))
         if s != FMM_OK:
             raise FmmError(s, "fmm_get_tuning")
-        return {"p2p_waves": int(w.value), "m2l_split_max": int(sm.value)}
+        return {"p2p_waves": int(w.value), "m2l_split_max": int(sm.value), "m2l_mfma": int(mf.value)}
 
-    def set_tuning(self, p2p_waves=4, m2l_split_max=8):
-        s = load().fmm_set_tuning(self._h, int(p2p_waves), int(m2l_split_max), _stream_handle())
+    def set_tuning(self, p2p_waves=4, m2l_split_max=8, m2l_mfma=0):
+        s = load().fmm_set_tuning(self._h, int(p2p_waves), int(m2l_split_max), int(m2l_mfma), _stream_handle())
         if s != FMM_OK:
             raise FmmError(s, "fmm_set_tuning")
 

@@ -26,6 +26,7 @@ size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 struct Tuning {
     int p2p_waves = 4;                   // leaves (wavefronts) per P2P workgroup: 2 or 4
     int split_max = kM2LSplitMaxLevel;   // M2L list split on levels <= this; < 2: never
+    int m2l_mfma = 0;                    // FP32 M2L levels on the matrix cores (else vector units)
 };
 
 // Host description of the instances of a plan.
@@ -422,7 +423,7 @@ hipError_t enqueue_all(fmm_plan_s* pl, int64_t n, const double* x, const double*
         const Work w = work_of(pl, ln);
         switch (ln.kind) {
             case L_UP: chk(launch_upward(b, P, p, w, ln.nwg, ln.leaves, st)); break;
-            case L_M2L: chk(launch_m2l(b, P, w, ln.nwg, ln.fp32, ln.groups, st)); break;
+            case L_M2L: chk(launch_m2l(b, P, w, ln.nwg, ln.fp32, pl->tune.m2l_mfma != 0, ln.groups, st)); break;
             case L_DOWN: chk(launch_downward(b, P, w, ln.nwg, st)); break;
             case L_P2P:
                 chk(launch_p2p(b, P, w, ln.nwg, pl->tune.p2p_waves, pl->mixed, pl->prm.sigma, u, v, st));
@@ -719,21 +720,24 @@ fmm_status fmm_stats(fmm_plan_t plan, double* stage_ms, int32_t n_stages, int32_
     return FMM_OK;
 }
 
-fmm_status fmm_get_tuning(fmm_plan_t plan, int32_t* p2p_waves, int32_t* m2l_split_max)
+fmm_status fmm_get_tuning(fmm_plan_t plan, int32_t* p2p_waves, int32_t* m2l_split_max, int32_t* m2l_mfma)
 {
-    if (!plan || !p2p_waves || !m2l_split_max) return FMM_E_ARG;
+    if (!plan || !p2p_waves || !m2l_split_max || !m2l_mfma) return FMM_E_ARG;
     *p2p_waves = plan->tune.p2p_waves;
     *m2l_split_max = plan->tune.split_max;
+    *m2l_mfma = plan->tune.m2l_mfma;
     return FMM_OK;
 }
 
-fmm_status fmm_set_tuning(fmm_plan_t plan, int32_t p2p_waves, int32_t m2l_split_max, void* stream)
+fmm_status fmm_set_tuning(fmm_plan_t plan, int32_t p2p_waves, int32_t m2l_split_max, int32_t m2l_mfma, void* stream)
 {
     if (!plan) return FMM_E_ARG;
     if (p2p_waves != 2 && p2p_waves != 4) return FMM_E_ARG;
     if (m2l_split_max < 0 || m2l_split_max > kM2LSplitMaxLevel) return FMM_E_ARG;
+    if (m2l_mfma != 0 && m2l_mfma != 1) return FMM_E_ARG;
     plan->tune.p2p_waves = p2p_waves;
     plan->tune.split_max = m2l_split_max;
+    plan->tune.m2l_mfma = m2l_mfma;
     return upload_schedule(plan, static_cast<hipStream_t>(stream)) == hipSuccess ? FMM_OK : FMM_E_DEVICE;
 }
 
@@ -762,12 +766,12 @@ fmm_status fmm_autotune(fmm_plan_t plan, int64_t n, const double* d_x, const dou
     if (cache && *cache) {
         if (FILE* f = std::fopen(cache, "r")) {
             char key[512];
-            int w = 0, sm = 0;
+            int w = 0, sm = 0, mf = 0;
             bool found = false;
-            while (std::fscanf(f, "%511s %d %d", key, &w, &sm) == 3)
+            while (std::fscanf(f, "%511s %d %d %d", key, &w, &sm, &mf) == 4)
                 if (std::strcmp(key, sig) == 0) found = true;   // the last entry wins
             std::fclose(f);
-            if (found) return fmm_set_tuning(plan, w, sm, stream);
+            if (found) return fmm_set_tuning(plan, w, sm, mf, stream);
         }
     }
 
@@ -782,31 +786,34 @@ fmm_status fmm_autotune(fmm_plan_t plan, int64_t n, const double* d_x, const dou
     }
     const int waves[2] = {2, 4};
     const int splits[3] = {0, 5, kM2LSplitMaxLevel};
+    // the matrix-core choice matters only where some M2L level runs in FP32
+    const int n_mfma = (plan->mixed && plan->P <= 24) ? 2 : 1;
     float best = 1e30f;
     Tuning best_t = saved;
     fmm_status rs = FMM_OK;
-    for (int wi = 0; wi < 2 && rs == FMM_OK; ++wi)
-        for (int si = 0; si < 3 && rs == FMM_OK; ++si) {
-            rs = fmm_set_tuning(plan, waves[wi], splits[si], stream);
-            if (rs == FMM_OK) rs = run_once(plan, n, d_x, d_y, d_gamma, d_u, d_v, stream);   // warm-up, capture
-            float tmin = 1e30f;
-            for (int r = 0; r < reps && rs == FMM_OK; ++r) {
-                if (hipEventRecord(e0, st) != hipSuccess) { rs = FMM_E_DEVICE; break; }
-                rs = run_once(plan, n, d_x, d_y, d_gamma, d_u, d_v, stream);
-                if (rs != FMM_OK) break;
-                if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-                    rs = FMM_E_DEVICE;
-                    break;
+    for (int mi = 0; mi < n_mfma && rs == FMM_OK; ++mi)
+        for (int wi = 0; wi < 2 && rs == FMM_OK; ++wi)
+            for (int si = 0; si < 3 && rs == FMM_OK; ++si) {
+                rs = fmm_set_tuning(plan, waves[wi], splits[si], n_mfma == 2 ? mi : saved.m2l_mfma, stream);
+                if (rs == FMM_OK) rs = run_once(plan, n, d_x, d_y, d_gamma, d_u, d_v, stream);   // warm-up, capture
+                float tmin = 1e30f;
+                for (int r = 0; r < reps && rs == FMM_OK; ++r) {
+                    if (hipEventRecord(e0, st) != hipSuccess) { rs = FMM_E_DEVICE; break; }
+                    rs = run_once(plan, n, d_x, d_y, d_gamma, d_u, d_v, stream);
+                    if (rs != FMM_OK) break;
+                    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                        rs = FMM_E_DEVICE;
+                        break;
+                    }
+                    float ms = 0.f;
+                    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rs = FMM_E_DEVICE; break; }
+                    tmin = std::min(tmin, ms);
                 }
-                float ms = 0.f;
-                if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rs = FMM_E_DEVICE; break; }
-                tmin = std::min(tmin, ms);
+                if (rs == FMM_OK && tmin < best) {
+                    best = tmin;
+                    best_t = plan->tune;
+                }
             }
-            if (rs == FMM_OK && tmin < best) {
-                best = tmin;
-                best_t = plan->tune;
-            }
-        }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     plan->timing = was_timing;
@@ -815,10 +822,10 @@ fmm_status fmm_autotune(fmm_plan_t plan, int64_t n, const double* d_x, const dou
         upload_schedule(plan, st);
         return rs;
     }
-    rs = fmm_set_tuning(plan, best_t.p2p_waves, best_t.split_max, stream);
+    rs = fmm_set_tuning(plan, best_t.p2p_waves, best_t.split_max, best_t.m2l_mfma, stream);
     if (rs == FMM_OK && cache && *cache) {
         if (FILE* f = std::fopen(cache, "a")) {
-            std::fprintf(f, "%s %d %d\n", sig, best_t.p2p_waves, best_t.split_max);
+            std::fprintf(f, "%s %d %d %d\n", sig, best_t.p2p_waves, best_t.split_max, best_t.m2l_mfma);
             std::fclose(f);
         }
     }

@@ -201,6 +201,126 @@ k_m2l(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restrict__
     }
 }
 
+// FP32 M2L on the matrix cores.  Written real-valued, the factored M2L of
+// one interaction-list member is a dense product
+//   [Re b; Im b] = [[Hr, -Hi], [Hi, Hr]] [Re abar; Im abar],  H[l][k] = h_{k+l}(tau),
+// a (2P x 2P) matrix times the 2P terms of the source.  A wavefront holds
+// the 64 targets of one child class (the same tau for all of them) as four
+// column tiles of 16, and accumulates 16 x 16 output tiles over all its
+// members with v_mfma_f32_16x16x4f32 (A[i][k] in lane i + 16k, B[k][j] in
+// lane j + 16k, D[i][j] in lane j + 16 (i/4), element i % 4).  The operator
+// fragments are read from the workgroup's LDS copy of the h_n; rows and
+// columns past 2P are zero.  Same grid, member split and outputs as k_m2l.
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+template <int P>
+__global__ void __launch_bounds__(256)
+k_m2l_mfma(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restrict__ me_all, M2LOut dst_,
+           const cplx<float>* __restrict__ H, const double* __restrict__ sout_)
+{
+    constexpr int NH = 2 * P - 1;
+    constexpr int R2 = 2 * P;                  // real-valued size
+    constexpr int MT = (R2 + 15) / 16;         // output row tiles
+    constexpr int KS = (R2 + 3) / 4;           // steps of 4 input terms
+    __shared__ cplx<float> sH[kHankelGrid * kHankelGrid * NH];
+    for (int e = threadIdx.x; e < kHankelGrid * kHankelGrid * NH; e += 256) sH[e] = H[e];
+    __syncthreads();
+
+    const int G = gridDim.y, g = blockIdx.y;
+    const int q = find_inst(wk.wg_begin, n_inst, blockIdx.x);
+    int bl = blockIdx.x - wk.wg_begin[q];
+    int l = wk.arg[2 * q];
+    while (bl >= level_blocks(l)) { bl -= level_blocks(l); ++l; }
+    const cd* me = me_all + inst[q].box_off * P;
+    cd* __restrict__ le = g == 0 ? dst_.out[0] + inst[q].box_off * P : dst_.out[g] + inst[q].split_off * P;
+    const int side = 1 << l;
+    const int bpr = side >= 16 ? side / 16 : 1;
+    const int bx = bl % bpr, by = bl / bpr;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int cx = wave & 1, cy = wave >> 1;
+    const int li = lane & 15, lq = lane >> 4;  // fragment row / column, and k quarter
+    const cd* me_l = me + level_offset(l) * P;
+
+    // the lane's target in each column tile: t = 16 n + li, laid out 8 x 8
+    int ta[4], tb[4];
+    bool act[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        const int t = 16 * n + li;
+        ta[n] = 2 * (bx * 8 + (t & 7)) + cx;
+        tb[n] = 2 * (by * 8 + (t >> 3)) + cy;
+        act[n] = ta[n] < side && tb[n] < side;
+    }
+
+    mfma_f4 acc[MT][4];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[m][n] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+
+    int member = 0;
+    for (int o = 0; o < 36; ++o) {
+        int dx, dy;
+        if (!il_offset(cx, cy, o, dx, dy)) continue;
+        if ((member++) % G != g) continue;
+        // source terms (B fragments): column li of tile n, rows 4 ks + lq
+        float bv[4][KS];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            const int sa = ta[n] + dx, sb = tb[n] + dy;
+            const bool ok = act[n] && sa >= 0 && sb >= 0 && sa < side && sb < side;
+            const cd* src = me_l + int64_t(morton(uint32_t(ok ? sa : 0), uint32_t(ok ? sb : 0))) * P;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int sidx = 4 * ks + lq;
+                float val = 0.f;
+                if (ok && sidx < R2) val = float(sidx < P ? src[sidx].x : src[sidx - P].y);
+                bv[n][ks] = val;
+            }
+        }
+        const cplx<float>* h = sH + ((dy + 3) * kHankelGrid + (dx + 3)) * NH;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            // operator fragments: row 16 m + li, column 4 ks + lq
+            float av[MT];
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                const int r = 16 * m + li, c = 4 * ks + lq;
+                float val = 0.f;
+                if (r < R2 && c < R2) {
+                    const bool rim = r >= P, cim = c >= P;
+                    const cplx<float> hn = h[(rim ? r - P : r) + (cim ? c - P : c)];
+                    val = rim == cim ? hn.x : (rim ? hn.y : -hn.y);
+                }
+                av[m] = val;
+            }
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int n = 0; n < 4; ++n)
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[m], bv[n][ks], acc[m][n], 0, 0, 0);
+        }
+    }
+
+    // rows r < P are Re b_r, rows P <= r < 2P are Im b_(r-P); scaled by 1/l!
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        if (!act[n]) continue;
+        double* dst = reinterpret_cast<double*>(le + (level_offset(l) + int64_t(morton(uint32_t(ta[n]), uint32_t(tb[n])))) * P);
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * m + 4 * lq + v;
+                if (r < R2) {
+                    const int k = r < P ? r : r - P;
+                    dst[2 * k + (r < P ? 0 : 1)] = double(acc[m][n][v]) * sout_[k];   // zero for k >= p
+                }
+            }
+    }
+}
+
 // L2L, subtree-fused like the upward sweep: a workgroup owns one box at level
 // lt (whose local expansion is final) and walks up to three levels down its
 // z-order-contiguous subtree in LDS.  Each child adds the parent's shifted
@@ -297,12 +417,17 @@ __global__ void __launch_bounds__(256) k_ilist(int L, int32_t* __restrict__ out)
 }
 
 template <int P>
-hipError_t m2l_impl(const Buffers& b, const Work& w, int nwg, bool fp32, int groups, hipStream_t st)
+hipError_t m2l_impl(const Buffers& b, const Work& w, int nwg, bool fp32, bool mfma, int groups, hipStream_t st)
 {
     if (nwg <= 0) return hipSuccess;
     const dim3 grid{unsigned(nwg), unsigned(groups), 1u};
     const M2LOut out{{b.le, b.le_part[0], b.le_part[1]}};
     if constexpr (P <= 24) {
+        if (fp32 && mfma) {
+            hipLaunchKernelGGL((k_m2l_mfma<P>), grid, dim3(256), 0, st, w, b.n_inst, b.inst, b.me, out,
+                               reinterpret_cast<const cplx<float>*>(b.t_h32), b.t_sout);
+            return hipGetLastError();
+        }
         if (fp32) {
             hipLaunchKernelGGL((k_m2l<P, float>), grid, dim3(256), 0, st, w, b.n_inst, b.inst, b.me, out,
                                reinterpret_cast<const cplx<float>*>(b.t_h32), b.t_sout);
@@ -325,17 +450,18 @@ hipError_t downward_impl(const Buffers& b, const Work& w, int nwg, hipStream_t s
 
 }  // namespace
 
-hipError_t launch_m2l(const Buffers& b, int P, const Work& w, int nwg, bool fp32, int groups, hipStream_t st)
+hipError_t launch_m2l(const Buffers& b, int P, const Work& w, int nwg, bool fp32, bool mfma, int groups,
+                      hipStream_t st)
 {
     switch (P) {
-        case 8: return m2l_impl<8>(b, w, nwg, fp32, groups, st);
-        case 12: return m2l_impl<12>(b, w, nwg, fp32, groups, st);
-        case 16: return m2l_impl<16>(b, w, nwg, fp32, groups, st);
-        case 17: return m2l_impl<17>(b, w, nwg, fp32, groups, st);
-        case 20: return m2l_impl<20>(b, w, nwg, fp32, groups, st);
-        case 24: return m2l_impl<24>(b, w, nwg, fp32, groups, st);
+        case 8: return m2l_impl<8>(b, w, nwg, fp32, mfma, groups, st);
+        case 12: return m2l_impl<12>(b, w, nwg, fp32, mfma, groups, st);
+        case 16: return m2l_impl<16>(b, w, nwg, fp32, mfma, groups, st);
+        case 17: return m2l_impl<17>(b, w, nwg, fp32, mfma, groups, st);
+        case 20: return m2l_impl<20>(b, w, nwg, fp32, mfma, groups, st);
+        case 24: return m2l_impl<24>(b, w, nwg, fp32, mfma, groups, st);
         case 32:   // FP32 translation data would overflow: mixed mode stops at p = 22
-            return fp32 ? hipErrorInvalidValue : m2l_impl<32>(b, w, nwg, false, groups, st);
+            return fp32 ? hipErrorInvalidValue : m2l_impl<32>(b, w, nwg, false, false, groups, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -135,7 +135,9 @@ hipError_t launch_tree(const Buffers& b, int n, const double* x, const double* y
 // P2M + M2M of up to three levels per launch; `from_particles` for the first
 hipError_t launch_upward(const Buffers& b, int P, int p, const Work& w, int nwg, bool from_particles,
                          hipStream_t st);
-hipError_t launch_m2l(const Buffers& b, int P, const Work& w, int nwg, bool fp32, int groups, hipStream_t st);
+// fp32 levels on the matrix cores when mfma is set
+hipError_t launch_m2l(const Buffers& b, int P, const Work& w, int nwg, bool fp32, bool mfma, int groups,
+                      hipStream_t st);
 hipError_t launch_downward(const Buffers& b, int P, const Work& w, int nwg, hipStream_t st);   // L2L
 hipError_t launch_p2p(const Buffers& b, int P, const Work& w, int nwg, int waves, bool mixed, double sigma,
                       double* u, double* v, hipStream_t st);

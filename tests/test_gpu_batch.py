@@ -178,18 +178,19 @@ def test_every_launch_shape_agrees(precision):
     x, y, g = _dev(wl.x), _dev(wl.y), _dev(wl.gamma)
     plan = fm.Plan(wl.n, wl.sigma, wl.p, 5, precision=precision)
     ref = None
-    for waves in (2, 4):
-        for split in (0, 5, 8):
-            plan.set_tuning(waves, split)
-            assert plan.tuning() == {"p2p_waves": waves, "m2l_split_max": split}
-            u, v = plan.evaluate(x, y, g)
-            torch.cuda.synchronize()
-            u, v = u.cpu().numpy(), v.cpu().numpy()
-            if ref is None:
-                ref = (u, v)
-            else:
-                err = oracle.rel_l2(u, v, *ref)
-                assert err < (1e-14 if precision == "fp64" else 1e-6), (waves, split, err)
+    for mfma in ((0, 1) if precision == "mixed" else (0,)):
+        for waves in (2, 4):
+            for split in (0, 5, 8):
+                plan.set_tuning(waves, split, mfma)
+                assert plan.tuning() == {"p2p_waves": waves, "m2l_split_max": split, "m2l_mfma": mfma}
+                u, v = plan.evaluate(x, y, g)
+                torch.cuda.synchronize()
+                u, v = u.cpu().numpy(), v.cpu().numpy()
+                if ref is None:
+                    ref = (u, v)
+                else:
+                    err = oracle.rel_l2(u, v, *ref)
+                    assert err < (1e-14 if precision == "fp64" else 1e-6), (mfma, waves, split, err)
     plan.close()
 
 
@@ -202,14 +203,14 @@ def test_autotune_and_cache(tmp_path, monkeypatch):
     monkeypatch.setenv("FMM_AUTOTUNE_CACHE", str(cache))
     plan = fm.Plan(wl.n, wl.sigma, wl.p, wl.depth)
     t = plan.autotune(x, y, g, reps=2)
-    assert t["p2p_waves"] in (2, 4) and t["m2l_split_max"] in (0, 5, 8)
+    assert t["p2p_waves"] in (2, 4) and t["m2l_split_max"] in (0, 5, 8) and t["m2l_mfma"] in (0, 1)
     lines = cache.read_text().split("\n")
     assert len([ln for ln in lines if ln.strip()]) == 1
     # a planted entry is taken from the cache without a search
     key = lines[0].split()[0]
-    cache.write_text(f"{key} 2 0\n")
+    cache.write_text(f"{key} 2 0 0\n")
     plan2 = fm.Plan(wl.n, wl.sigma, wl.p, wl.depth)
-    assert plan2.autotune(x, y, g) == {"p2p_waves": 2, "m2l_split_max": 0}
+    assert plan2.autotune(x, y, g) == {"p2p_waves": 2, "m2l_split_max": 0, "m2l_mfma": 0}
     u, v = plan2.evaluate(x, y, g)
     torch.cuda.synchronize()
     uo, vo = oracle.fmm(wl.x, wl.y, wl.gamma, wl.sigma, wl.p, wl.depth)
