@@ -375,7 +375,10 @@ k_downward(Work wk, int n_inst, const Inst* __restrict__ inst, cd* __restrict__ 
             }
             const cd* par = sh + in_off + (o >> 2) * P;
             const cd* Lr = sL + ((o & 3) * P + k) * P;     // rows k >= p are zero
-            for (int m = k; m < P; ++m) {
+            // the full row (entries m < k are zero): a fixed trip count lets
+            // the LDS loads be issued together
+#pragma unroll
+            for (int m = 0; m < P; ++m) {
                 const cd t = Lr[m];
                 const cd s = par[m];
                 cmac(bx, by, t.x, t.y, s.x, s.y);

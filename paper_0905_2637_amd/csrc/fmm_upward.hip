@@ -132,10 +132,14 @@ k_upward(Work wk, int n_inst, const Inst* __restrict__ inst, int p, int from_par
         for (int e = tid; e < n_out * P; e += kUpThreads) {
             const int o = e / P, k = e % P;
             double bx = 0.0, by = 0.0;
+            // the full row (entries m > k are zero): a fixed trip count lets
+            // the LDS loads be issued together
+#pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const cd* a = sh + in_off + (4 * o + c) * P;
                 const cd* Mr = sM + (c * P + k) * P;     // rows k >= p are zero
-                for (int m = 0; m <= k; ++m) {
+#pragma unroll
+                for (int m = 0; m < P; ++m) {
                     const cd t = Mr[m];
                     const cd s = a[m];
                     cmac(bx, by, t.x, t.y, s.x, s.y);
