@@ -116,11 +116,11 @@ k_m2l(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restrict__
     };
 
     if constexpr (!kF32) {
-        // FP64: the next member's source terms are loaded while the current
-        // member's are applied (two register buffers, all p terms at once)
-        T ax0[P], ay0[P], ax1[P], ay1[P];
-        bool ok0 = false, ok1 = false;
-        auto load = [&](int o, T (&ax)[P], T (&ay)[P], bool& ok) {
+        // FP64: all p source terms of a member at once (a software prefetch
+        // of the next member measured no faster)
+        T ax[P], ay[P];
+        bool ok = false;
+        auto load = [&](int o) {
             const cd* src = source(o, ok);
             if (ok) {
 #pragma unroll
@@ -131,7 +131,7 @@ k_m2l(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restrict__
                 }
             }
         };
-        auto apply = [&](int o, const T (&ax)[P], const T (&ay)[P], bool ok) {
+        auto apply = [&](int o) {
             const cplx<T>* h = table(o);
             if (ok) {
 #pragma unroll
@@ -145,16 +145,9 @@ k_m2l(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restrict__
                 }
             }
         };
-        int oa = next_member(0);
-        if (oa < 36) load(oa, ax0, ay0, ok0);
-        while (oa < 36) {
-            const int ob = next_member(oa + 1);
-            if (ob < 36) load(ob, ax1, ay1, ok1);
-            apply(oa, ax0, ay0, ok0);
-            if (ob >= 36) break;
-            oa = next_member(ob + 1);
-            if (oa < 36) load(oa, ax0, ay0, ok0);
-            apply(ob, ax1, ay1, ok1);
+        for (int o = next_member(0); o < 36; o = next_member(o + 1)) {
+            load(o);
+            apply(o);
         }
     } else {
         // FP32: source terms in blocks of KB, only one block live next to the
