@@ -15,8 +15,9 @@ is measured with HIP events that the library records on the evaluation's
 own stream during the timed steps (for the batched form: during extra,
 eagerly enqueued timed evaluations, since a replayed graph carries no
 events).  ``forms`` (default workload only) times the mixed-precision form
-of the same workload and the batched form against plain FP64 single
-evaluations of the same instances.  ``cpu_baseline`` times the FP64 CPU
+of the same workload, the batched form against plain FP64 single
+evaluations of the same instances, and the vortex-method time stepping
+(explicit midpoint steps, graph-replayed).  ``cpu_baseline`` times the FP64 CPU
 oracle on the host cores (rank 0, N = 1 only) and, from the same leg,
 reports the GPU result's parity with the oracle and its accuracy against
 the direct sums.
@@ -253,6 +254,26 @@ def run_sequential_fp64(wl, args, dev):
     return sec
 
 
+def run_time_stepping(wl, args, dev, steps=20):
+    """Explicit midpoint steps of the vortex method (two evaluations and two
+    particle updates per step, one graph replay each) on the bounding square."""
+    import torch
+    import paper_0905_2637_amd as fm
+    x, y, g = dev_arrays(wl, dev)
+    scratch = torch.empty(4 * wl.n, dtype=torch.float64, device=dev)
+    plan = fm.Plan(wl.n, wl.sigma, wl.p, wl.depth, domain=None, precision=wl.precision,
+                   fp32_fine_levels=wl.fp32_fine_levels)
+    dt = 1e-4
+    plan.advance_rk2(x, y, g, dt, 2, scratch)              # warm-up and graph capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.advance_rk2(x, y, g, dt, steps, scratch)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    plan.close()
+    return sec
+
+
 # ---------------------------------------------------------------------------
 # CPU oracle leg (the only part of the bench that touches the oracle)
 # ---------------------------------------------------------------------------
@@ -364,6 +385,11 @@ def main() -> int:
                           "stages_ms": {k: round(x, 4) for k, x in rm["stage_ms"].items()},
                           "roofline": rm["roofline"]}
         forms["_mixed_uv"] = (rm["u"], rm["v"])
+        ts = run_time_stepping(workloads.make("C2"), args, dev)
+        forms["time_stepping"] = {"workload": "C2 particles moved by the explicit midpoint rule (two FP64 "
+                                              "evaluations per step, bounding-square domain)",
+                                  "ms_per_step": round(ts * 1e3, 4), "particle_steps_per_s": wl.n / ts,
+                                  "step_vs_two_evaluations": ts / (2 * res["sec"])}
         w4 = workloads.make("C4")
         rb = run_batch(w4, args, dev)
         rb64 = run_batch(w4, args, dev, precision="fp64")

@@ -131,6 +131,24 @@ fmm_status fmm_plan_batch(const fmm_params* prm, int32_t n_inst, const int32_t* 
 fmm_status fmm_evaluate_batch(fmm_plan_t plan, const double* d_x, const double* d_y,
                               const double* d_gamma, double* d_u, double* d_v, void* stream);
 
+/* Vortex-method time stepping (Section 3, eq. 6: in ideal 2D flow every
+ * particle moves with its velocity and keeps its circulation).  Advances
+ * d_x, d_y (device FP64 [n], in place; d_gamma unchanged) by n_steps steps
+ * of the explicit midpoint rule, the paper naming no integrator:
+ *   x_mid = x + dt/2 u(x),   x <- x + dt u(x_mid),
+ * each velocity a full evaluation of this plan (tree rebuilt every stage).
+ * d_scratch: caller-owned device FP64 [4 n] (stage velocities and midpoint
+ * positions), overwritten.  A single-instance plan only; use the bounding-
+ * square domain (width <= 0) or an explicit square the particles stay in
+ * (escapes are counted as by fmm_evaluate: fmm_get_status reports the last
+ * evaluation).  The first call for a given set of arrays, n and dt captures
+ * one step into a HIP graph (on a stream the plan owns); every step is a
+ * replay of it on `stream`.  Asynchronous.  Errors: FMM_E_ARG (batched plan,
+ * NULL pointers, n < 0, n_steps < 0, dt not finite), FMM_E_CAPACITY,
+ * FMM_E_DEVICE. */
+fmm_status fmm_advance_rk2(fmm_plan_t plan, int64_t n, double* d_x, double* d_y, const double* d_gamma,
+                           double dt, int32_t n_steps, double* d_scratch, void* stream);
+
 /* Launch shapes.  p2p_waves: leaves (one wavefront each) per P2P workgroup,
  * 2 or 4 (default 4).  m2l_split_max: M2L levels <= min(L, m2l_split_max)
  * split each box's interaction list over three wavefronts (more parallelism

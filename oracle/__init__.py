@@ -70,6 +70,8 @@ def _load():
     lib.oracle_fmm.argtypes = [i64, dp, dp, dp, C.c_double, C.c_int, C.c_int, C.c_double, C.c_double,
                                C.c_double, i64, i64p, dp, dp, dp, dp]
     lib.oracle_fmm.restype = i64
+    lib.oracle_advance_rk2.argtypes = [i64, dp, dp, dp, C.c_double, C.c_int, C.c_int, C.c_int, C.c_double,
+                                       C.c_int]
     lib.oracle_init()
     _lib = lib
     return lib
@@ -263,3 +265,19 @@ def rel_l2(u, v, uref, vref):
     num = np.sum((np.asarray(u) - uref) ** 2 + (np.asarray(v) - vref) ** 2)
     den = np.sum(np.asarray(uref) ** 2 + np.asarray(vref) ** 2)
     return float(np.sqrt(num / den))
+
+
+def advance_rk2(x, y, g, sigma, dt, steps, p=12, L=4, velocity="fmm"):
+    """Explicit midpoint-rule time stepping of the particles (Section 3, eq. 6).
+
+    velocity="fmm": the oracle FMM on the particles' bounding square at every
+    stage; velocity="direct": the regularised direct sum.  Returns new (x, y).
+    """
+    lib = _load()
+    x, y, g = _f64(x).copy(), _f64(y).copy(), _f64(g)
+    if velocity not in ("fmm", "direct"):
+        raise ValueError(velocity)
+    lib.oracle_advance_rk2(x.shape[0], _d(x), _d(y), _d(g), float(sigma), int(p), int(L),
+                           1 if velocity == "fmm" else 0, float(dt), int(steps))
+    return x, y
+

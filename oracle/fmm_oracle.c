@@ -577,3 +577,46 @@ int64_t oracle_fmm(int64_t n, const double* x, const double* y, const double* g,
     free(need); free(le); free(me); free(member); free(start); free(ia); free(ib);
     return nbad;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Vortex-method time stepping (Section 3, eq. 6): in ideal 2D flow every  */
+/* particle moves with the local velocity and keeps its circulation.  The  */
+/* paper names no integrator; this is the explicit midpoint rule (second-  */
+/* order Runge-Kutta):                                                     */
+/*   k1 = u(x_n),  x_mid = x_n + dt/2 k1,  k2 = u(x_mid),  x_n+1 = x_n + dt k2 */
+/* with the velocity from the FMM above (use_fmm != 0; the particles'      */
+/* bounding square recomputed at every stage) or from the regularised      */
+/* direct sum.  x, y are advanced in place.                                */
+/* ---------------------------------------------------------------------- */
+void oracle_advance_rk2(int64_t n, double* x, double* y, const double* g, double sigma, int p, int L,
+                        int use_fmm, double dt, int steps)
+{
+    double* u = malloc(sizeof(double) * (size_t)n);
+    double* v = malloc(sizeof(double) * (size_t)n);
+    double* xm = malloc(sizeof(double) * (size_t)n);
+    double* ym = malloc(sizeof(double) * (size_t)n);
+    double dom[3];
+    for (int s = 0; s < steps; ++s) {
+        if (use_fmm) {
+            oracle_bounding_square(n, x, y, dom);
+            oracle_fmm(n, x, y, g, sigma, p, L, dom[0], dom[1], dom[2], n, NULL, u, v, NULL, NULL);
+        } else {
+            oracle_direct(n, x, y, g, sigma, n, NULL, u, v);
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            xm[i] = x[i] + 0.5 * dt * u[i];
+            ym[i] = y[i] + 0.5 * dt * v[i];
+        }
+        if (use_fmm) {
+            oracle_bounding_square(n, xm, ym, dom);
+            oracle_fmm(n, xm, ym, g, sigma, p, L, dom[0], dom[1], dom[2], n, NULL, u, v, NULL, NULL);
+        } else {
+            oracle_direct(n, xm, ym, g, sigma, n, NULL, u, v);
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            x[i] = x[i] + dt * u[i];
+            y[i] = y[i] + dt * v[i];
+        }
+    }
+    free(u); free(v); free(xm); free(ym);
+}

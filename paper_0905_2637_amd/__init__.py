@@ -29,7 +29,7 @@ FMM_PREC_MIXED = 1
 DUMP_KEYS, DUMP_PERM, DUMP_LEAF_START, DUMP_ME, DUMP_LE, DUMP_DOMAIN, DUMP_ILIST = range(7)
 
 EXPORTED = ["fmm_workspace_size", "fmm_plan", "fmm_evaluate", "fmm_workspace_size_batch", "fmm_plan_batch",
-            "fmm_evaluate_batch", "fmm_get_status", "fmm_set_timing", "fmm_stats", "fmm_stage_name",
+            "fmm_evaluate_batch", "fmm_advance_rk2", "fmm_get_status", "fmm_set_timing", "fmm_stats", "fmm_stage_name",
             "fmm_get_tuning", "fmm_set_tuning", "fmm_autotune", "fmm_debug_dump", "fmm_destroy",
             "fmm_status_string"]
 
@@ -65,6 +65,7 @@ def load():
     lib.fmm_workspace_size_batch.argtypes = [C.POINTER(FmmParams), C.c_int32, i32p, i32p, C.POINTER(C.c_size_t)]
     lib.fmm_plan_batch.argtypes = [C.POINTER(FmmParams), C.c_int32, i32p, i32p, vp, C.c_size_t, vp, C.POINTER(vp)]
     lib.fmm_evaluate_batch.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.fmm_advance_rk2.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_double, C.c_int32, vp, vp]
     lib.fmm_get_tuning.argtypes = [vp, i32p, i32p, i32p]
     lib.fmm_set_tuning.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp]
     lib.fmm_autotune.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp, C.c_int32]
@@ -271,6 +272,24 @@ class Plan(_PlanBase):
             if nbad:
                 raise FmmError(FMM_E_DOMAIN, f"fmm_evaluate: {nbad} particles outside the domain")
         return u, v
+
+    def advance_rk2(self, x, y, gamma, dt, steps, scratch=None):
+        """Move the particles (x, y updated in place) by `steps` explicit
+        midpoint steps of the vortex method (Section 3, eq. 6)."""
+        import torch
+        n = int(x.shape[0])
+        if scratch is None:
+            scratch = torch.empty(4 * max(n, 1), dtype=torch.float64, device=x.device)
+        _check_inputs(n, (x, y, gamma))
+        if scratch.dtype != torch.float64 or not scratch.is_contiguous() or scratch.numel() < 4 * n:
+            raise ValueError("scratch must be a contiguous float64 tensor of at least 4 n elements")
+        s = load().fmm_advance_rk2(self._h, n, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                   C.c_void_p(gamma.data_ptr()), float(dt), int(steps),
+                                   C.c_void_p(scratch.data_ptr()), _stream_handle())
+        if s != FMM_OK:
+            raise FmmError(s, "fmm_advance_rk2")
+        self.last_n = n
+        return x, y
 
     def autotune(self, x, y, gamma, u=None, v=None, reps=3) -> dict:
         """Time the launch-shape candidates on these inputs and keep the fastest."""

@@ -232,6 +232,12 @@ struct fmm_plan_s {
     hipGraph_t graph;
     hipGraphExec_t gexec;
     const void* gptr[5];
+    // time stepping: one step captured once per set of arrays, n and dt
+    hipGraph_t sgraph;
+    hipGraphExec_t sgexec;
+    const void* sptr[4];
+    int64_t sn;
+    double sdt;
 };
 
 namespace {
@@ -265,6 +271,44 @@ void drop_graph(fmm_plan_s* pl)
     pl->gexec = nullptr;
     pl->graph = nullptr;
     for (auto& q : pl->gptr) q = nullptr;
+    if (pl->sgexec) hipGraphExecDestroy(pl->sgexec);
+    if (pl->sgraph) hipGraphDestroy(pl->sgraph);
+    pl->sgexec = nullptr;
+    pl->sgraph = nullptr;
+    for (auto& q : pl->sptr) q = nullptr;
+    pl->sn = -1;
+}
+
+// Capture the enqueue callback into a graph on the plan's private stream.
+template <typename F>
+hipError_t capture(fmm_plan_s* pl, F&& enqueue, hipGraph_t* graph, hipGraphExec_t* exec)
+{
+    *graph = nullptr;
+    *exec = nullptr;
+    if (!pl->cap_stream) {
+        const hipError_t e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            pl->cap_stream = nullptr;
+            return e;
+        }
+    }
+    hipError_t e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const hipError_t ce = enqueue(pl->cap_stream);
+    hipGraph_t gr = nullptr;
+    e = hipStreamEndCapture(pl->cap_stream, &gr);
+    if (ce != hipSuccess || e != hipSuccess || !gr) {
+        if (gr) hipGraphDestroy(gr);
+        return ce != hipSuccess ? ce : (e != hipSuccess ? e : hipErrorUnknown);
+    }
+    e = hipGraphInstantiate(exec, gr, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(gr);
+        *exec = nullptr;
+        return e;
+    }
+    *graph = gr;
+    return hipSuccess;
 }
 
 // Launch list and work tables for the current tuning.  Workgroups of a launch
@@ -452,6 +496,7 @@ fmm_status make_plan(const fmm_params* prm, Shape&& sh, bool batch, void* d_work
     pl->batch = batch;
     pl->shape = std::move(sh);
     pl->last_n = -1;
+    pl->sn = -1;
     char* base = static_cast<char*>(d_workspace);
     Buffers& b = pl->buf;
     b.inst = reinterpret_cast<Inst*>(base + ly.inst);
@@ -660,29 +705,57 @@ fmm_status fmm_evaluate_batch(fmm_plan_t plan, const double* d_x, const double* 
     for (int i = 0; i < 5 && same; ++i) same = plan->gptr[i] == ptrs[i];
     if (!same) {
         // capture the evaluation for these arrays on the plan's own stream
-        drop_graph(plan);
-        if (!plan->cap_stream && hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking) != hipSuccess) {
-            plan->cap_stream = nullptr;
-            return FMM_E_DEVICE;
-        }
-        if (hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
-            return FMM_E_DEVICE;
-        const hipError_t ce = enqueue_all(plan, n, d_x, d_y, d_gamma, d_u, d_v, plan->cap_stream, false, 0);
-        hipGraph_t gr = nullptr;
-        const hipError_t ee = hipStreamEndCapture(plan->cap_stream, &gr);
-        if (ce != hipSuccess || ee != hipSuccess || !gr) {
-            if (gr) hipGraphDestroy(gr);
-            return FMM_E_DEVICE;
-        }
-        plan->graph = gr;
-        if (hipGraphInstantiate(&plan->gexec, gr, nullptr, nullptr, 0) != hipSuccess) {
-            plan->gexec = nullptr;
-            drop_graph(plan);
-            return FMM_E_DEVICE;
-        }
+        if (plan->gexec) hipGraphExecDestroy(plan->gexec);
+        if (plan->graph) hipGraphDestroy(plan->graph);
+        plan->gexec = nullptr;
+        plan->graph = nullptr;
+        const hipError_t e = capture(
+            plan, [&](hipStream_t cs) { return enqueue_all(plan, n, d_x, d_y, d_gamma, d_u, d_v, cs, false, 0); },
+            &plan->graph, &plan->gexec);
+        if (e != hipSuccess) return FMM_E_DEVICE;
         for (int i = 0; i < 5; ++i) plan->gptr[i] = ptrs[i];
     }
     return hipGraphLaunch(plan->gexec, static_cast<hipStream_t>(stream)) == hipSuccess ? FMM_OK : FMM_E_DEVICE;
+}
+
+fmm_status fmm_advance_rk2(fmm_plan_t plan, int64_t n, double* d_x, double* d_y, const double* d_gamma, double dt,
+                           int32_t n_steps, double* d_scratch, void* stream)
+{
+    if (!plan || plan->batch) return FMM_E_ARG;
+    if (n < 0 || n_steps < 0 || !std::isfinite(dt)) return FMM_E_ARG;
+    if (n > plan->shape.n_cap) return FMM_E_CAPACITY;
+    if (n == 0 || n_steps == 0) return FMM_OK;
+    if (!d_x || !d_y || !d_gamma || !d_scratch) return FMM_E_ARG;
+    plan->last_n = n;
+    double* u = d_scratch;
+    double* v = d_scratch + n;
+    double* xm = d_scratch + 2 * n;
+    double* ym = d_scratch + 3 * n;
+    const void* ptrs[4] = {d_x, d_y, d_gamma, d_scratch};
+    bool same = plan->sgexec != nullptr && plan->sn == n && plan->sdt == dt;
+    for (int i = 0; i < 4 && same; ++i) same = plan->sptr[i] == ptrs[i];
+    if (!same) {
+        if (plan->sgexec) hipGraphExecDestroy(plan->sgexec);
+        if (plan->sgraph) hipGraphDestroy(plan->sgraph);
+        plan->sgexec = nullptr;
+        plan->sgraph = nullptr;
+        // one explicit-midpoint step: two evaluations and two particle updates
+        auto step = [&](hipStream_t cs) -> hipError_t {
+            hipError_t e = enqueue_all(plan, n, d_x, d_y, d_gamma, u, v, cs, false, 0);
+            if (e == hipSuccess) e = launch_advance(n, d_x, d_y, u, v, 0.5 * dt, xm, ym, cs);
+            if (e == hipSuccess) e = enqueue_all(plan, n, xm, ym, d_gamma, u, v, cs, false, 0);
+            if (e == hipSuccess) e = launch_advance(n, d_x, d_y, u, v, dt, d_x, d_y, cs);
+            return e;
+        };
+        if (capture(plan, step, &plan->sgraph, &plan->sgexec) != hipSuccess) return FMM_E_DEVICE;
+        for (int i = 0; i < 4; ++i) plan->sptr[i] = ptrs[i];
+        plan->sn = n;
+        plan->sdt = dt;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    for (int32_t s = 0; s < n_steps; ++s)
+        if (hipGraphLaunch(plan->sgexec, st) != hipSuccess) return FMM_E_DEVICE;
+    return FMM_OK;
 }
 
 fmm_status fmm_get_status(fmm_plan_t plan, void* stream, int64_t* n_bad)

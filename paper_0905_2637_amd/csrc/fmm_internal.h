@@ -142,6 +142,9 @@ hipError_t launch_downward(const Buffers& b, int P, const Work& w, int nwg, hipS
 hipError_t launch_p2p(const Buffers& b, int P, const Work& w, int nwg, int waves, bool mixed, double sigma,
                       double* u, double* v, hipStream_t st);
 hipError_t launch_ilist(const Buffers& b, int L, hipStream_t st);
+// time stepping: (xo, yo) = (x, y) + c (u, v); xo, yo may alias x, y
+hipError_t launch_advance(int64_t n, const double* x, const double* y, const double* u, const double* v, double c,
+                          double* xo, double* yo, hipStream_t st);
 
 // ---- host-side operator tables (FP64, built once per plan) -----------------
 void build_tables(int P, int p, cd* m2m, cd* l2l, cd* h64, cf* h32, double* sin_, double* sout_);

@@ -153,3 +153,7 @@ def test_batch_entry_points_reject_null(lib):
     assert lib.fmm_autotune(None, 10, None, None, None, None, None, None, 3) == fm.FMM_E_ARG
     w = C.c_int32(0)
     assert lib.fmm_get_tuning(None, C.byref(w), C.byref(w), C.byref(w)) == fm.FMM_E_ARG
+
+
+def test_advance_rejects_bad_arguments(lib):
+    assert lib.fmm_advance_rk2(None, 10, None, None, None, 1e-3, 1, None, None) == fm.FMM_E_ARG
