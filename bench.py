@@ -190,7 +190,7 @@ def run_single(wl, args, dev):
 # batched form
 # ---------------------------------------------------------------------------
 
-def run_batch(wl, args, dev, precision=None, autotune=True):
+def run_batch(wl, args, dev, precision=None, autotune=True, work_order=1):
     import torch
     import paper_0905_2637_amd as fm
     precision = precision or wl.precision
@@ -203,6 +203,10 @@ def run_batch(wl, args, dev, precision=None, autotune=True):
                       fp32_fine_levels=wl.fp32_fine_levels)
     if autotune:
         bp.autotune(x, y, g, u, v, reps=2)
+    if work_order != 1:
+        t = bp.tuning()
+        t["work_order"] = work_order
+        bp.set_tuning(**t)
     bp.evaluate(x, y, g, u, v)
     torch.cuda.synchronize()
     if bp.out_of_domain():
@@ -393,12 +397,15 @@ def main() -> int:
         w4 = workloads.make("C4")
         rb = run_batch(w4, args, dev)
         rb64 = run_batch(w4, args, dev, precision="fp64")
+        rb_in_order = run_batch(w4, args, dev, work_order=0)
         seq = run_sequential_fp64(w4, args, dev)
         forms["batched"] = {"workload": describe(w4), "ms": round(rb["sec"] * 1e3, 4), "value": w4.n / rb["sec"],
                             "fp64_batched_ms": round(rb64["sec"] * 1e3, 4),
                             "fp64_sequential_single_ms": round(seq * 1e3, 4),
                             "speedup_vs_fp64_sequential": seq / rb["sec"],
                             "speedup_fp64_batched_vs_sequential": seq / rb64["sec"],
+                            "input_order_ms": round(rb_in_order["sec"] * 1e3, 4),
+                            "work_order_speedup": rb_in_order["sec"] / rb["sec"],
                             "tuning": rb["tuning"], "roofline": rb["roofline"]}
 
     if args.calibrate_copy_mib > 0:

@@ -155,7 +155,11 @@ fmm_status fmm_advance_rk2(fmm_plan_t plan, int64_t n, double* d_x, double* d_y,
  * on levels with few boxes), 0 .. 8 (default 8; below 2: never).
  * m2l_mfma: 1 runs the FP32 M2L levels of the mixed form on the matrix
  * cores (MFMA), 0 (default) on the vector units; FP64 levels always use the
- * vector units.  Results are identical up to the summation order.
+ * vector units.  work_order (batched plans): 1 (default) launches the
+ * instances of every stage in decreasing order of the paper's work estimate
+ * (eqs. 13-15, see fmm_work_estimate), so the heaviest workgroups are
+ * dispatched first; 0 keeps the input order.  Results are identical up to
+ * the summation order (bit for bit for work_order).
  * fmm_set_tuning synchronises `stream`.  fmm_autotune times every
  * combination of p2p_waves in {2, 4}, m2l_split_max in {0, 5, 8} and, for a
  * mixed plan, m2l_mfma in {0, 1} on the caller's data (reps timed
@@ -163,11 +167,21 @@ fmm_status fmm_advance_rk2(fmm_plan_t plan, int64_t n, double* d_x, double* d_y,
  * keeps the fastest and, when the environment variable FMM_AUTOTUNE_CACHE
  * names a file, looks the choice up there first and appends it after a
  * search.  For batched plans n is ignored. */
-fmm_status fmm_get_tuning(fmm_plan_t plan, int32_t* p2p_waves, int32_t* m2l_split_max, int32_t* m2l_mfma);
+fmm_status fmm_get_tuning(fmm_plan_t plan, int32_t* p2p_waves, int32_t* m2l_split_max, int32_t* m2l_mfma,
+                          int32_t* work_order);
 fmm_status fmm_set_tuning(fmm_plan_t plan, int32_t p2p_waves, int32_t m2l_split_max, int32_t m2l_mfma,
-                          void* stream);
+                          int32_t work_order, void* stream);
 fmm_status fmm_autotune(fmm_plan_t plan, int64_t n, const double* d_x, const double* d_y,
                         const double* d_gamma, double* d_u, double* d_v, void* stream, int32_t reps);
+
+/* The paper's work model (Section 5.2) for every instance of the plan, in
+ * input order: non-leaf boxes p^2 (2 n_c + n_IL) each (eq. 13), leaves
+ * 2 N_i p + p^2 n_IL + n_nd N_i^2 each (eq. 14), summed over the tree of
+ * depth L (eq. 15), with n_c = 4, n_IL = 27, n_nd = 9 and the mean leaf
+ * occupancy N_i = N / 4^L (N = n_max for a single-instance plan).  Host only.
+ * Writes min(n_out, instances) values; *n_written (may be NULL) gets that
+ * count. */
+fmm_status fmm_work_estimate(fmm_plan_t plan, double* work, int32_t n_out, int32_t* n_written);
 
 /* Synchronises `stream` and reports the number of particles of the last
  * evaluation that fell outside the explicit domain or had a NaN coordinate.

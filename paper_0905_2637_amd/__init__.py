@@ -30,7 +30,7 @@ DUMP_KEYS, DUMP_PERM, DUMP_LEAF_START, DUMP_ME, DUMP_LE, DUMP_DOMAIN, DUMP_ILIST
 
 EXPORTED = ["fmm_workspace_size", "fmm_plan", "fmm_evaluate", "fmm_workspace_size_batch", "fmm_plan_batch",
             "fmm_evaluate_batch", "fmm_advance_rk2", "fmm_get_status", "fmm_set_timing", "fmm_stats", "fmm_stage_name",
-            "fmm_get_tuning", "fmm_set_tuning", "fmm_autotune", "fmm_debug_dump", "fmm_destroy",
+            "fmm_get_tuning", "fmm_set_tuning", "fmm_autotune", "fmm_work_estimate", "fmm_debug_dump", "fmm_destroy",
             "fmm_status_string"]
 
 
@@ -66,8 +66,9 @@ def load():
     lib.fmm_plan_batch.argtypes = [C.POINTER(FmmParams), C.c_int32, i32p, i32p, vp, C.c_size_t, vp, C.POINTER(vp)]
     lib.fmm_evaluate_batch.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.fmm_advance_rk2.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_double, C.c_int32, vp, vp]
-    lib.fmm_get_tuning.argtypes = [vp, i32p, i32p, i32p]
-    lib.fmm_set_tuning.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp]
+    lib.fmm_get_tuning.argtypes = [vp, i32p, i32p, i32p, i32p]
+    lib.fmm_set_tuning.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp]
+    lib.fmm_work_estimate.argtypes = [vp, C.POINTER(C.c_double), C.c_int32, i32p]
     lib.fmm_autotune.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp, C.c_int32]
     lib.fmm_get_status.argtypes = [vp, vp, C.POINTER(C.c_int64)]
     lib.fmm_set_timing.argtypes = [vp, C.c_int32]
@@ -176,18 +177,28 @@ class _PlanBase:
         return out
 
     def tuning(self) -> dict:
-        w = C.c_int32(0)
-        sm = C.c_int32(0)
-        mf = C.c_int32(0)
-        s = load().fmm_get_tuning(self._h, C.byref(w), C.byref(sm), C.byref(mf))
+        w, sm, mf, wo = C.c_int32(0), C.c_int32(0), C.c_int32(0), C.c_int32(0)
+        s = load().fmm_get_tuning(self._h, C.byref(w), C.byref(sm), C.byref(mf), C.byref(wo))
         if s != FMM_OK:
             raise FmmError(s, "fmm_get_tuning")
-        return {"p2p_waves": int(w.value), "m2l_split_max": int(sm.value), "m2l_mfma": int(mf.value)}
+        return {"p2p_waves": int(w.value), "m2l_split_max": int(sm.value), "m2l_mfma": int(mf.value),
+                "work_order": int(wo.value)}
 
-    def set_tuning(self, p2p_waves=4, m2l_split_max=8, m2l_mfma=0):
-        s = load().fmm_set_tuning(self._h, int(p2p_waves), int(m2l_split_max), int(m2l_mfma), _stream_handle())
+    def set_tuning(self, p2p_waves=4, m2l_split_max=8, m2l_mfma=0, work_order=1):
+        s = load().fmm_set_tuning(self._h, int(p2p_waves), int(m2l_split_max), int(m2l_mfma), int(work_order),
+                                  _stream_handle())
         if s != FMM_OK:
             raise FmmError(s, "fmm_set_tuning")
+
+    def work_estimate(self) -> np.ndarray:
+        """The paper's work model (eqs. 13-15) per instance, in input order."""
+        n = len(getattr(self, "counts", [0]))
+        out = (C.c_double * n)()
+        nw = C.c_int32(0)
+        s = load().fmm_work_estimate(self._h, out, n, C.byref(nw))
+        if s != FMM_OK:
+            raise FmmError(s, "fmm_work_estimate")
+        return np.array(out[: nw.value])
 
     def dump(self, what: int) -> np.ndarray:
         lib = load()

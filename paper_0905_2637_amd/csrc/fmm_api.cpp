@@ -27,6 +27,7 @@ struct Tuning {
     int p2p_waves = 4;                   // leaves (wavefronts) per P2P workgroup: 2 or 4
     int split_max = kM2LSplitMaxLevel;   // M2L list split on levels <= this; < 2: never
     int m2l_mfma = 0;                    // FP32 M2L levels on the matrix cores (else vector units)
+    int work_order = 1;                  // launch order: most estimated work first (else input order)
 };
 
 // Host description of the instances of a plan.
@@ -41,6 +42,8 @@ struct Shape {
     int64_t boxes = 0;                   // sum Lambda(L_i)
     int64_t split_boxes = 0;             // sum Lambda(min(L_i, kM2LSplitMaxLevel))
     std::vector<int64_t> leaf_off, box_off, split_off;
+    std::vector<double> work;            // eq. 13-15 estimate per instance
+    std::vector<int32_t> by_work;        // instances by decreasing estimate (stable)
 };
 
 // Launches of one evaluation after the tree build: at most 4 upward groups,
@@ -65,9 +68,25 @@ int ceil_log2(int64_t v)
     return b;
 }
 
-int table_ints(int n_inst) { return 3 * n_inst + 1; }   // wg_begin [n+1], arg [2n]
+int table_ints(int n_inst) { return 4 * n_inst + 1; }   // wg_begin [n+1], arg [2n], order [n]
 
 int split_level(int L, int split_max) { return (L <= 2 || split_max < 2) ? 1 : std::min(L, split_max); }
+
+// The paper's work model (Section 5.2): a non-leaf box costs p^2 (2 n_c +
+// n_IL) (eq. 13), a leaf 2 N_i p + p^2 n_IL + n_nd N_i^2 (eq. 14), and a tree
+// the sum over its boxes (eq. 15, read for the whole tree of depth L: levels
+// 0 .. L-1 non-leaf, 4^L leaves).  N_i is the mean occupancy N / 4^L; n_c =
+// 4, n_IL = 27 (Table 1), n_nd = 9 (the leaf and its 8 neighbours).
+double work_estimate(int64_t n, int L, int p)
+{
+    const double pp = double(p) * p;
+    const double nc = 4.0, nil = 27.0, nnd = 9.0;
+    double nonleaf = 0.0;
+    for (int l = 0; l < L; ++l) nonleaf += std::ldexp(1.0, 2 * l) * pp * (2.0 * nc + nil);
+    const double leaves = std::ldexp(1.0, 2 * L);
+    const double ni = double(n) / leaves;
+    return nonleaf + leaves * (2.0 * ni * p + pp * nil + nnd * ni * ni);
+}
 
 int level_blocks_host(int l)
 {
@@ -322,12 +341,20 @@ void build_schedule(fmm_plan_s* pl)
     pl->launches.clear();
     pl->host_tables.assign(size_t(kMaxLaunches) * ti, 0);
     std::vector<int32_t> wg(n), arg(2 * n);
+    // launch order of the instances: by decreasing estimated work, or as given
+    std::vector<int32_t> ord(n);
+    for (int k = 0; k < n; ++k) ord[k] = pl->tune.work_order ? sh.by_work[k] : k;
     auto add = [&](LaunchKind kind, bool fp32, int groups, bool leaves) {
         const int t = int(pl->launches.size());
         int32_t* tb = pl->host_tables.data() + size_t(t) * ti;
         tb[0] = 0;
-        for (int i = 0; i < n; ++i) tb[i + 1] = tb[i] + wg[i];
-        for (int i = 0; i < 2 * n; ++i) tb[n + 1 + i] = arg[i];
+        for (int k = 0; k < n; ++k) {
+            const int i = ord[k];
+            tb[k + 1] = tb[k] + wg[i];
+            tb[n + 1 + 2 * k] = arg[2 * i];
+            tb[n + 2 + 2 * k] = arg[2 * i + 1];
+            tb[3 * n + 1 + k] = i;
+        }
         if (tb[n] > 0) pl->launches.push_back(Launch{kind, tb[n], t, fp32, groups, leaves});
     };
     auto clear = [&]() {
@@ -443,8 +470,9 @@ hipError_t upload_schedule(fmm_plan_s* pl, hipStream_t st)
 
 Work work_of(const fmm_plan_s* pl, const Launch& ln)
 {
-    const int32_t* tb = pl->d_tables + size_t(ln.table) * table_ints(pl->shape.n_inst);
-    return Work{tb, tb + pl->shape.n_inst + 1};
+    const int n = pl->shape.n_inst;
+    const int32_t* tb = pl->d_tables + size_t(ln.table) * table_ints(n);
+    return Work{tb, tb + n + 1, tb + 3 * n + 1};
 }
 
 // Enqueue one whole evaluation on st.
@@ -478,9 +506,23 @@ hipError_t enqueue_all(fmm_plan_s* pl, int64_t n, const double* x, const double*
     return e;
 }
 
+void rank_by_work(Shape& sh, int p)
+{
+    sh.work.resize(sh.n_inst);
+    for (int i = 0; i < sh.n_inst; ++i) {
+        const int64_t end = i + 1 < sh.n_inst ? sh.part_off[i + 1] : sh.n_cap;
+        sh.work[i] = work_estimate(end - sh.part_off[i], sh.depth[i], p);
+    }
+    sh.by_work.resize(sh.n_inst);
+    for (int i = 0; i < sh.n_inst; ++i) sh.by_work[i] = i;
+    std::stable_sort(sh.by_work.begin(), sh.by_work.end(),
+                     [&](int32_t a, int32_t b) { return sh.work[a] > sh.work[b]; });
+}
+
 fmm_status make_plan(const fmm_params* prm, Shape&& sh, bool batch, void* d_workspace, size_t bytes, void* stream,
                      fmm_plan_t* out)
 {
+    rank_by_work(sh, prm->p);
     if ((reinterpret_cast<uintptr_t>(d_workspace) & 255) != 0) return FMM_E_ARG;
     const int P = instantiated_terms(prm->p);
     const bool mixed = prm->precision == FMM_PREC_MIXED;
@@ -793,25 +835,38 @@ fmm_status fmm_stats(fmm_plan_t plan, double* stage_ms, int32_t n_stages, int32_
     return FMM_OK;
 }
 
-fmm_status fmm_get_tuning(fmm_plan_t plan, int32_t* p2p_waves, int32_t* m2l_split_max, int32_t* m2l_mfma)
+fmm_status fmm_get_tuning(fmm_plan_t plan, int32_t* p2p_waves, int32_t* m2l_split_max, int32_t* m2l_mfma,
+                          int32_t* work_order)
 {
-    if (!plan || !p2p_waves || !m2l_split_max || !m2l_mfma) return FMM_E_ARG;
+    if (!plan || !p2p_waves || !m2l_split_max || !m2l_mfma || !work_order) return FMM_E_ARG;
     *p2p_waves = plan->tune.p2p_waves;
     *m2l_split_max = plan->tune.split_max;
     *m2l_mfma = plan->tune.m2l_mfma;
+    *work_order = plan->tune.work_order;
     return FMM_OK;
 }
 
-fmm_status fmm_set_tuning(fmm_plan_t plan, int32_t p2p_waves, int32_t m2l_split_max, int32_t m2l_mfma, void* stream)
+fmm_status fmm_set_tuning(fmm_plan_t plan, int32_t p2p_waves, int32_t m2l_split_max, int32_t m2l_mfma,
+                          int32_t work_order, void* stream)
 {
     if (!plan) return FMM_E_ARG;
     if (p2p_waves != 2 && p2p_waves != 4) return FMM_E_ARG;
     if (m2l_split_max < 0 || m2l_split_max > kM2LSplitMaxLevel) return FMM_E_ARG;
-    if (m2l_mfma != 0 && m2l_mfma != 1) return FMM_E_ARG;
+    if ((m2l_mfma != 0 && m2l_mfma != 1) || (work_order != 0 && work_order != 1)) return FMM_E_ARG;
     plan->tune.p2p_waves = p2p_waves;
     plan->tune.split_max = m2l_split_max;
     plan->tune.m2l_mfma = m2l_mfma;
+    plan->tune.work_order = work_order;
     return upload_schedule(plan, static_cast<hipStream_t>(stream)) == hipSuccess ? FMM_OK : FMM_E_DEVICE;
+}
+
+fmm_status fmm_work_estimate(fmm_plan_t plan, double* work, int32_t n_out, int32_t* n_written)
+{
+    if (!plan || (n_out > 0 && !work)) return FMM_E_ARG;
+    const int m = std::min<int>(n_out, plan->shape.n_inst);
+    for (int i = 0; i < m; ++i) work[i] = plan->shape.work[i];
+    if (n_written) *n_written = m;
+    return FMM_OK;
 }
 
 fmm_status fmm_autotune(fmm_plan_t plan, int64_t n, const double* d_x, const double* d_y, const double* d_gamma,
@@ -844,7 +899,7 @@ fmm_status fmm_autotune(fmm_plan_t plan, int64_t n, const double* d_x, const dou
             while (std::fscanf(f, "%511s %d %d %d", key, &w, &sm, &mf) == 4)
                 if (std::strcmp(key, sig) == 0) found = true;   // the last entry wins
             std::fclose(f);
-            if (found) return fmm_set_tuning(plan, w, sm, mf, stream);
+            if (found) return fmm_set_tuning(plan, w, sm, mf, plan->tune.work_order, stream);
         }
     }
 
@@ -867,7 +922,8 @@ fmm_status fmm_autotune(fmm_plan_t plan, int64_t n, const double* d_x, const dou
     for (int mi = 0; mi < n_mfma && rs == FMM_OK; ++mi)
         for (int wi = 0; wi < 2 && rs == FMM_OK; ++wi)
             for (int si = 0; si < 3 && rs == FMM_OK; ++si) {
-                rs = fmm_set_tuning(plan, waves[wi], splits[si], n_mfma == 2 ? mi : saved.m2l_mfma, stream);
+                rs = fmm_set_tuning(plan, waves[wi], splits[si], n_mfma == 2 ? mi : saved.m2l_mfma, saved.work_order,
+                                    stream);
                 if (rs == FMM_OK) rs = run_once(plan, n, d_x, d_y, d_gamma, d_u, d_v, stream);   // warm-up, capture
                 float tmin = 1e30f;
                 for (int r = 0; r < reps && rs == FMM_OK; ++r) {
@@ -895,7 +951,7 @@ fmm_status fmm_autotune(fmm_plan_t plan, int64_t n, const double* d_x, const dou
         upload_schedule(plan, st);
         return rs;
     }
-    rs = fmm_set_tuning(plan, best_t.p2p_waves, best_t.split_max, best_t.m2l_mfma, stream);
+    rs = fmm_set_tuning(plan, best_t.p2p_waves, best_t.split_max, best_t.m2l_mfma, best_t.work_order, stream);
     if (rs == FMM_OK && cache && *cache) {
         if (FILE* f = std::fopen(cache, "a")) {
             std::fprintf(f, "%s %d %d %d\n", sig, best_t.p2p_waves, best_t.split_max, best_t.m2l_mfma);

@@ -67,9 +67,10 @@ k_m2l(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restrict__
         Hs = sH;
     }
     const int G = gridDim.y, g = blockIdx.y;
-    const int q = find_inst(wk.wg_begin, n_inst, blockIdx.x);
-    int bl = blockIdx.x - wk.wg_begin[q];
-    int l = wk.arg[2 * q];
+    const int pos = find_inst(wk.wg_begin, n_inst, blockIdx.x);   // place in the launch order
+    const int q = wk.order[pos];
+    int bl = blockIdx.x - wk.wg_begin[pos];
+    int l = wk.arg[2 * pos];
     while (bl >= level_blocks(l)) { bl -= level_blocks(l); ++l; }
     const cd* me = me_all + inst[q].box_off * P;
     cd* __restrict__ le = g == 0 ? dst_.out[0] + inst[q].box_off * P : dst_.out[g] + inst[q].split_off * P;
@@ -220,9 +221,10 @@ k_m2l_mfma(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restr
     __syncthreads();
 
     const int G = gridDim.y, g = blockIdx.y;
-    const int q = find_inst(wk.wg_begin, n_inst, blockIdx.x);
-    int bl = blockIdx.x - wk.wg_begin[q];
-    int l = wk.arg[2 * q];
+    const int pos = find_inst(wk.wg_begin, n_inst, blockIdx.x);   // place in the launch order
+    const int q = wk.order[pos];
+    int bl = blockIdx.x - wk.wg_begin[pos];
+    int l = wk.arg[2 * pos];
     while (bl >= level_blocks(l)) { bl -= level_blocks(l); ++l; }
     const cd* me = me_all + inst[q].box_off * P;
     cd* __restrict__ le = g == 0 ? dst_.out[0] + inst[q].box_off * P : dst_.out[g] + inst[q].split_off * P;
@@ -333,9 +335,10 @@ k_downward(Work wk, int n_inst, const Inst* __restrict__ inst, cd* __restrict__ 
     __shared__ cd sh[85 * P];
     __shared__ cd sL[4 * P * P];
     const int tid = threadIdx.x;
-    const int q = find_inst(wk.wg_begin, n_inst, blockIdx.x);
-    const int64_t root = blockIdx.x - wk.wg_begin[q];
-    const int lt = wk.arg[2 * q], d = wk.arg[2 * q + 1];
+    const int pos = find_inst(wk.wg_begin, n_inst, blockIdx.x);   // place in the launch order
+    const int q = wk.order[pos];
+    const int64_t root = blockIdx.x - wk.wg_begin[pos];
+    const int lt = wk.arg[2 * pos], d = wk.arg[2 * pos + 1];
     const int split_level = inst[q].split;
     cd* le = le_all + inst[q].box_off * P;
     const cd* part0 = part0_all + inst[q].split_off * P;

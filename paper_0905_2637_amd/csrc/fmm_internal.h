@@ -65,14 +65,19 @@ struct Inst {
     Domain dom;          // its square; s = 2^L / W
 };
 
-// Per-launch work table: workgroups [wg_begin[i], wg_begin[i+1]) belong to
-// instance i; arg[2i], arg[2i+1] carry launch-specific values for it.
+// Per-launch work table, in launch order: workgroups [wg_begin[k],
+// wg_begin[k+1]) belong to instance order[k]; arg[2k], arg[2k+1] carry
+// launch-specific values for it.  The order puts the instances with the most
+// estimated work first (the paper's work model, eqs. 13-15), so the heaviest
+// workgroups are dispatched first and the lightest fill the tail.
 struct Work {
     const int32_t* wg_begin;
     const int32_t* arg;
+    const int32_t* order;
 };
 
-// Instance of workgroup `wg` (uniform binary search over the prefix table).
+// Place in the launch order of workgroup `wg` (uniform binary search over the
+// prefix table).
 __device__ __forceinline__ int find_inst(const int32_t* __restrict__ wg_begin, int n_inst, int wg)
 {
     int lo = 0, hi = n_inst;      // wg_begin[lo] <= wg < wg_begin[hi]

@@ -312,13 +312,14 @@ k_p2p_l2p(Work wk, int n_inst, const Inst* __restrict__ inst, const int32_t* __r
     __shared__ cd le_all_sh[WAVES][P];
 
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int qi = find_inst(wk.wg_begin, n_inst, blockIdx.x);
+    const int pos = find_inst(wk.wg_begin, n_inst, blockIdx.x);   // place in the launch order
+    const int qi = wk.order[pos];
     const int L = inst[qi].L;
     const int has_far = L >= 2 ? 1 : 0;
     const int32_t* leaf_start = leaf_start_all + inst[qi].leaf_off;
     const cd* le_leaf = le_all + (inst[qi].box_off + level_offset(L)) * P;
     const int64_t nleaf = int64_t(1) << (2 * L);
-    const int64_t mm = int64_t(blockIdx.x - wk.wg_begin[qi]) * WAVES + wv;
+    const int64_t mm = int64_t(blockIdx.x - wk.wg_begin[pos]) * WAVES + wv;
     if (mm >= nleaf) return;
     LeafCtx c;
     c.m = uint32_t(mm);

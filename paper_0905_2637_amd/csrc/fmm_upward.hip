@@ -47,9 +47,10 @@ k_upward(Work wk, int n_inst, const Inst* __restrict__ inst, int p, int from_par
     __shared__ cd sh[85 * P];            // 64 + 16 + 4 + 1 boxes
     __shared__ cd sM[4 * P * P];         // the four M2M matrices
     const int tid = threadIdx.x;
-    const int q = find_inst(wk.wg_begin, n_inst, blockIdx.x);
-    const int64_t root = blockIdx.x - wk.wg_begin[q];     // z-order index at level lt
-    const int lt = wk.arg[2 * q], d = wk.arg[2 * q + 1];
+    const int pos = find_inst(wk.wg_begin, n_inst, blockIdx.x);   // place in the launch order
+    const int q = wk.order[pos];
+    const int64_t root = blockIdx.x - wk.wg_begin[pos];     // z-order index at level lt
+    const int lt = wk.arg[2 * pos], d = wk.arg[2 * pos + 1];
     const int L = inst[q].L;
     const int32_t* leaf_start = leaf_start_all + inst[q].leaf_off;
     cd* me = me_all + inst[q].box_off * P;

@@ -182,7 +182,8 @@ def test_every_launch_shape_agrees(precision):
         for waves in (2, 4):
             for split in (0, 5, 8):
                 plan.set_tuning(waves, split, mfma)
-                assert plan.tuning() == {"p2p_waves": waves, "m2l_split_max": split, "m2l_mfma": mfma}
+                assert plan.tuning() == {"p2p_waves": waves, "m2l_split_max": split, "m2l_mfma": mfma,
+                                         "work_order": 1}
                 u, v = plan.evaluate(x, y, g)
                 torch.cuda.synchronize()
                 u, v = u.cpu().numpy(), v.cpu().numpy()
@@ -210,7 +211,7 @@ def test_autotune_and_cache(tmp_path, monkeypatch):
     key = lines[0].split()[0]
     cache.write_text(f"{key} 2 0 0\n")
     plan2 = fm.Plan(wl.n, wl.sigma, wl.p, wl.depth)
-    assert plan2.autotune(x, y, g) == {"p2p_waves": 2, "m2l_split_max": 0, "m2l_mfma": 0}
+    assert plan2.autotune(x, y, g) == {"p2p_waves": 2, "m2l_split_max": 0, "m2l_mfma": 0, "work_order": 1}
     u, v = plan2.evaluate(x, y, g)
     torch.cuda.synchronize()
     uo, vo = oracle.fmm(wl.x, wl.y, wl.gamma, wl.sigma, wl.p, wl.depth)
@@ -241,7 +242,7 @@ def test_c4_batch_sampled_against_single_and_direct():
         a, b = wl.offsets[i], wl.offsets[i + 1]
         us, vs, sp = run(wl.x[a:b], wl.y[a:b], wl.gamma[a:b], wl.sigma, wl.p, depths[i],
                          precision=wl.precision, fine=wl.fp32_fine_levels)
-        sp.set_tuning(**bp.tuning())
+        sp.set_tuning(**bp.tuning())     # work_order has no effect on a single instance
         us, vs = sp.evaluate(_dev(wl.x[a:b]), _dev(wl.y[a:b]), _dev(wl.gamma[a:b]))
         torch.cuda.synchronize()
         assert np.array_equal(u[a:b], us.cpu().numpy()) and np.array_equal(v[a:b], vs.cpu().numpy()), i
@@ -250,3 +251,46 @@ def test_c4_batch_sampled_against_single_and_direct():
         ud, vd = oracle.direct_split(wl.x[a:b], wl.y[a:b], wl.gamma[a:b], wl.sigma, depths[i], targets=t)
         err = oracle.rel_l2(u[a:b][t], v[a:b][t], ud, vd)
         assert err < 1e-5, f"instance {i}: rel L2 vs split direct {err:.3e}"
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_work_order_leaves_results_unchanged(precision):
+    """Launching the instances heaviest-first (the paper's work model) only
+    reorders workgroups: every instance's arithmetic, and so its result, is
+    the same bit for bit."""
+    import torch
+    fm = _fm()
+    x, y, g, off = _instances(COUNTS, DEPTHS, 15)
+    bp = fm.BatchPlan(COUNTS, DEPTHS, 0.004, 12, precision=precision)
+    xt, yt, gt = _dev(x), _dev(y), _dev(g)
+    assert bp.tuning()["work_order"] == 1
+    u1, v1 = bp.evaluate(xt, yt, gt)
+    t = bp.tuning()
+    t["work_order"] = 0
+    bp.set_tuning(**t)
+    u0, v0 = bp.evaluate(xt, yt, gt)
+    torch.cuda.synchronize()
+    assert np.array_equal(u1.cpu().numpy(), u0.cpu().numpy()) and np.array_equal(v1.cpu().numpy(), v0.cpu().numpy())
+    bp.close()
+
+
+def test_work_estimate_is_the_papers_model():
+    """eqs. 13-15 with n_c = 4, n_IL = 27, n_nd = 9: an empty tree of depth L
+    costs (4^L - 1)/3 p^2 (2*4 + 27) + 4^L p^2 27, and particles add
+    4^L (2 N_i p + 9 N_i^2) with N_i = N / 4^L."""
+    fm = _fm()
+    counts = [0, 4096, 0, 16384, 1000]
+    depths = [3, 3, 5, 5, 2]
+    p = 12
+    bp = fm.BatchPlan(counts, depths, 0.004, p)
+    w = bp.work_estimate()
+    assert w.shape == (5,)
+    for n, L, got in zip(counts, depths, w):
+        leaves = 4 ** L
+        empty = (leaves - 1) / 3 * p * p * 35 + leaves * p * p * 27
+        ni = n / leaves
+        assert got == pytest.approx(empty + leaves * (2 * ni * p + 9 * ni * ni), rel=1e-12)
+    # heavier instances come first in the launch order: the estimate grows
+    # with the particle count at a fixed depth
+    assert w[1] > w[0] and w[3] > w[2]
+    bp.close()
