@@ -151,8 +151,8 @@ fmm_status fmm_advance_rk2(fmm_plan_t plan, int64_t n, double* d_x, double* d_y,
 
 /* Launch shapes.  p2p_waves: leaves (one wavefront each) per P2P workgroup,
  * 2 or 4 (default 4).  m2l_split_max: M2L levels <= min(L, m2l_split_max)
- * split each box's interaction list over three wavefronts (more parallelism
- * on levels with few boxes), 0 .. 8 (default 8; below 2: never).
+ * split each box's interaction list over two or three wavefronts (more
+ * parallelism on levels with few boxes), 0 .. 8 (default 8; below 2: never).
  * m2l_mfma: 1 runs the FP32 M2L levels of the mixed form on the matrix
  * cores (MFMA), 0 (default) on the vector units; FP64 levels always use the
  * vector units.  work_order (batched plans): 1 (default) launches the

@@ -57,7 +57,7 @@ struct Launch {
     int nwg;
     int table;       // its work table
     bool fp32;       // M2L
-    int groups;      // M2L: 3 with the list split, else 1
+    int groups;      // M2L: 2 or 3 with the list split, else 1
     bool leaves;     // upward: the first group, from the particles
 };
 
@@ -71,6 +71,13 @@ int ceil_log2(int64_t v)
 int table_ints(int n_inst) { return 4 * n_inst + 1; }   // wg_begin [n+1], arg [2n], order [n]
 
 int split_level(int L, int split_max) { return (L <= 2 || split_max < 2) ? 1 : std::min(L, split_max); }
+
+// Split M2L levels: FP32 levels split each list over three wavefronts; the
+// FP64 levels of an instance over two when they have at least this many
+// workgroup tiles, else three (few tiles are bound by one wavefront's serial
+// work).  Decided per instance, so that a batched evaluation computes every
+// instance exactly as a single one does.  Measured on 1M-64M particle trees.
+constexpr int kM2LFewTiles = 256;
 
 // The paper's work model (Section 5.2): a non-leaf box costs p^2 (2 n_c +
 // n_IL) (eq. 13), a leaf 2 N_i p + p^2 n_IL + n_nd N_i^2 (eq. 14), and a tree
@@ -235,6 +242,8 @@ struct fmm_plan_s {
     Tuning tune;
     std::vector<Launch> launches;
     std::vector<int32_t> host_tables;    // kMaxLaunches work tables of table_ints(n_inst)
+    std::vector<int32_t> part1_levels;   // per instance: bit l set if M2L level l has a second partial sum
+    std::vector<int32_t> g64;            // per instance: wavefronts per list on its split FP64 M2L levels
     int32_t* d_tables;
     Buffers buf;
     int64_t last_n;
@@ -344,6 +353,8 @@ void build_schedule(fmm_plan_s* pl)
     // launch order of the instances: by decreasing estimated work, or as given
     std::vector<int32_t> ord(n);
     for (int k = 0; k < n; ++k) ord[k] = pl->tune.work_order ? sh.by_work[k] : k;
+    pl->part1_levels.assign(n, 0);
+    pl->g64.assign(n, 2);
     auto add = [&](LaunchKind kind, bool fp32, int groups, bool leaves) {
         const int t = int(pl->launches.size());
         int32_t* tb = pl->host_tables.data() + size_t(t) * ti;
@@ -381,7 +392,7 @@ void build_schedule(fmm_plan_s* pl)
         add(L_UP, false, 1, g == 0);
     }
     // M2L: levels [2, f32) in FP64 and [f32, L] in FP32; levels <= the split
-    // level with the interaction list split over three wavefronts
+    // level with the interaction list split over two or three wavefronts
     for (int prec = 0; prec < 2; ++prec)
         for (int part = 0; part < 2; ++part) {
             clear();
@@ -401,7 +412,17 @@ void build_schedule(fmm_plan_s* pl)
                 arg[2 * i] = a;
                 arg[2 * i + 1] = b;
             }
-            add(L_M2L, prec == 1, part == 0 ? 3 : 1, false);
+            int groups = 1;
+            if (part == 0)
+                for (int i = 0; i < n; ++i) {
+                    if (wg[i] == 0) continue;
+                    const int gi = (prec == 1 || wg[i] < kM2LFewTiles) ? 3 : 2;
+                    if (prec == 0) pl->g64[i] = gi;
+                    groups = std::max(groups, gi);
+                    if (gi == 3)
+                        for (int l = arg[2 * i]; l <= arg[2 * i + 1]; ++l) pl->part1_levels[i] |= 1 << l;
+                }
+            add(L_M2L, prec == 1, groups, false);
         }
     // downward: L2L in groups of up to three levels from level 2
     for (int g = 0;; ++g) {
@@ -440,6 +461,8 @@ std::vector<Inst> build_inst(const fmm_plan_s* pl)
         I.split_off = sh.split_off[i];
         I.L = sh.depth[i];
         I.split = split_level(I.L, pl->tune.split_max);
+        I.part1 = pl->part1_levels[i];
+        I.g64 = pl->g64[i];
         if (pl->auto_domain)   // the bounding square is written on the device by every evaluation
             I.dom = Domain{0.0, 0.0, 1.0, std::ldexp(1.0, I.L)};
         else

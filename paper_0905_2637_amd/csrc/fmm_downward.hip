@@ -39,7 +39,12 @@ __host__ __device__ inline int level_blocks(int l)
     return bpr * bpr;
 }
 
-// gridDim.y = G in {1, 3}: workgroup row g takes every G-th member of the
+// Runs of consecutive M2L workgroups kept on one XCD (xcd_runs): neighbouring
+// tiles read overlapping source halos.  Measured 1-2 % faster than the plain
+// round-robin placement on 1M-64M particle trees.
+constexpr int kM2LXcdRun = 8;
+
+// gridDim.y = G in {1, 2, 3}: workgroup row g takes every G-th member of the
 // interaction list and writes its partial sum to out[g] (out[0] = le).
 struct M2LOut {
     cd* out[3];
@@ -66,10 +71,14 @@ k_m2l(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restrict__
         __syncthreads();
         Hs = sH;
     }
-    const int G = gridDim.y, g = blockIdx.y;
-    const int pos = find_inst(wk.wg_begin, n_inst, blockIdx.x);   // place in the launch order
+    const int lin = xcd_runs(int(blockIdx.x + gridDim.x * blockIdx.y), int(gridDim.x * gridDim.y), kM2LXcdRun);
+    const int g = lin / int(gridDim.x), blk = lin % int(gridDim.x);
+    const int pos = find_inst(wk.wg_begin, n_inst, blk);   // place in the launch order
     const int q = wk.order[pos];
-    int bl = blockIdx.x - wk.wg_begin[pos];
+    // a split FP64 launch serves instances split two or three ways
+    const int G = kF32 ? int(gridDim.y) : min(int(gridDim.y), inst[q].g64);
+    if (g >= G) return;
+    int bl = blk - wk.wg_begin[pos];
     int l = wk.arg[2 * pos];
     while (bl >= level_blocks(l)) { bl -= level_blocks(l); ++l; }
     const cd* me = me_all + inst[q].box_off * P;
@@ -220,10 +229,12 @@ k_m2l_mfma(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restr
     for (int e = threadIdx.x; e < kHankelGrid * kHankelGrid * NH; e += 256) sH[e] = H[e];
     __syncthreads();
 
-    const int G = gridDim.y, g = blockIdx.y;
-    const int pos = find_inst(wk.wg_begin, n_inst, blockIdx.x);   // place in the launch order
+    const int G = gridDim.y;
+    const int lin = xcd_runs(int(blockIdx.x + gridDim.x * blockIdx.y), int(gridDim.x * gridDim.y), kM2LXcdRun);
+    const int g = lin / int(gridDim.x), blk = lin % int(gridDim.x);
+    const int pos = find_inst(wk.wg_begin, n_inst, blk);   // place in the launch order
     const int q = wk.order[pos];
-    int bl = blockIdx.x - wk.wg_begin[pos];
+    int bl = blk - wk.wg_begin[pos];
     int l = wk.arg[2 * pos];
     while (bl >= level_blocks(l)) { bl -= level_blocks(l); ++l; }
     const cd* me = me_all + inst[q].box_off * P;
@@ -324,8 +335,9 @@ k_m2l_mfma(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restr
 constexpr int kDownThreads = 256;
 
 // part[0], part[1]: partial M2L sums of levels <= split_level (M2L ran with
-// its interaction list split over three wavefronts there); they are added
-// to le when a level's M2L result is first read.
+// its interaction list split over two or three wavefronts there; part[1]
+// only on the levels of Inst::part1); they are added to le when a level's M2L
+// result is first read.
 // Work table arg: lt, d.
 template <int P>
 __global__ void __launch_bounds__(kDownThreads)
@@ -343,13 +355,18 @@ k_downward(Work wk, int n_inst, const Inst* __restrict__ inst, cd* __restrict__ 
     cd* le = le_all + inst[q].box_off * P;
     const cd* part0 = part0_all + inst[q].split_off * P;
     const cd* part1 = part1_all + inst[q].split_off * P;
+    const int part1_levels = inst[q].part1;
     for (int e = tid; e < 4 * P * P; e += kDownThreads) sL[e] = Lt[e];
     const int64_t ri = (level_offset(lt) + root) * P;
     for (int k = tid; k < P; k += kDownThreads) {
         cd v = le[ri + k];
         if (lt == 2 && lt <= split_level) {   // level 2 gets no L2L: finish its M2L sum here
-            v.x += part0[ri + k].x + part1[ri + k].x;
-            v.y += part0[ri + k].y + part1[ri + k].y;
+            v.x += part0[ri + k].x;
+            v.y += part0[ri + k].y;
+            if ((part1_levels >> lt) & 1) {
+                v.x += part1[ri + k].x;
+                v.y += part1[ri + k].y;
+            }
             le[ri + k] = v;
         }
         sh[k] = v;
@@ -366,8 +383,12 @@ k_downward(Work wk, int n_inst, const Inst* __restrict__ inst, cd* __restrict__ 
             double bx = cur.x, by = cur.y;
             if (j <= split_level) {
                 const int64_t pi = (level_offset(j) + gfirst) * P + e;
-                bx += part0[pi].x + part1[pi].x;
-                by += part0[pi].y + part1[pi].y;
+                bx += part0[pi].x;
+                by += part0[pi].y;
+                if ((part1_levels >> j) & 1) {
+                    bx += part1[pi].x;
+                    by += part1[pi].y;
+                }
             }
             const cd* par = sh + in_off + (o >> 2) * P;
             const cd* Lr = sL + ((o & 3) * P + k) * P;     // rows k >= p are zero

@@ -49,9 +49,10 @@ inline int instantiated_terms(int p)
 }
 
 // M2L on levels up to an instance's split level runs with the interaction
-// list split over three wavefronts (more parallelism where levels have few
-// boxes); the partial sums go to two extra buffers sized for levels up to
-// kM2LSplitMaxLevel and are added by the downward sweep.
+// list split over several wavefronts (more parallelism where levels have few
+// boxes), two or three.  The partial sums beyond the first go to extra
+// buffers sized for levels up to kM2LSplitMaxLevel and are added by the
+// downward sweep.
 constexpr int kM2LSplitMaxLevel = 8;
 
 // One instance of a plan (device table, built on the host).
@@ -62,6 +63,8 @@ struct Inst {
     int64_t split_off;   // first box of its partial-M2L segments
     int32_t L;           // depth
     int32_t split;       // M2L split level (levels 2 .. split have partial sums)
+    int32_t part1;       // bit l set: M2L level l has a second partial sum
+    int32_t g64;         // wavefronts its split FP64 M2L levels divide a list over
     Domain dom;          // its square; s = 2^L / W
 };
 
@@ -86,6 +89,22 @@ __device__ __forceinline__ int find_inst(const int32_t* __restrict__ wg_begin, i
         if (wg_begin[mid] <= wg) lo = mid; else hi = mid;
     }
     return lo;
+}
+
+// Workgroups are handed to the chip's 8 XCDs in turn (workgroup b to XCD
+// b mod 8), and each XCD has an L2 of its own.  xcd_runs renumbers them so
+// that every XCD takes runs of `run` consecutive logical workgroups, the runs
+// dealt out in turn: neighbouring workgroups, which read much of the same
+// data, then share an L2, and the order in which work starts is kept at the
+// granularity of 8 runs.  A bijection on [0, G); the last G mod (8 run)
+// workgroups keep their numbers.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_runs(int b, int G, int run)
+{
+    const int span = kXcds * run;
+    if (run <= 1 || b >= G - G % span) return b;
+    const int x = b % kXcds, k = b / kXcds;
+    return ((k / run) * kXcds + x) * run + k % run;
 }
 
 // Device pointers of one plan, all inside the caller's workspace.

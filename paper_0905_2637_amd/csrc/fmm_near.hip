@@ -43,25 +43,32 @@ constexpr double kInv2Pi = 0.15915494309189533576888376337251;
 struct Src64 { double x, y, g; };
 
 // ln 2 split into its nearest double and the remainder (for the reduction
-// t = k ln2 - r done with fused multiply-adds).
+// -t = k ln2 + r done with fused multiply-adds).
 constexpr double kLn2Hi = 0.6931471805599453;
 constexpr double kLn2Lo = 2.3190468138462996e-17;
 constexpr double kLog2E = 1.4426950408889634;
+// 1.5 * 2^52: adding it to a double of magnitude below 2^51 rounds that
+// double to the nearest integer and leaves the integer, in two's complement,
+// in the low 32 bits of the sum's significand.
+constexpr double kRoundMagic = 6755399441055744.0;
 
-// 1 - exp(-t) for t >= 0 in FP64, within 1.5 ulp for every t (checked
-// against a long-double reference on 2e7 points).  Reduce t = k ln2 - r with
-// |r| <= ln2/2 (Cody and Waite), take expm1(r) = r q(r) with q the degree-10
-// Chebyshev fit of expm1(r)/r on that interval (fit error 2e-17 relative),
-// and use
-//   1 - e^-t = (1 - 2^-k) - 2^-k expm1(r),
-// which is -expm1(-t) itself for k = 0 and free of cancellation for k >= 1.
-// Beyond t = 37 the result rounds to 1, so t is clamped at 40.
-__device__ __forceinline__ double one_minus_exp_neg(double t)
+// 1 - exp(nt) for nt = -t <= 0 in FP64, within 1.5 ulp for every t (checked
+// against a long-double reference on 2e7 points).  Reduce nt = k ln2 + r with
+// k = round(nt log2 e) <= 0 and |r| <= ln2/2 (Cody and Waite), take
+// expm1(r) = r q(r) with q the degree-10 Chebyshev fit of expm1(r)/r on that
+// interval (fit error 2e-17 relative), and use
+//   1 - e^nt = (1 - 2^k) - 2^k expm1(r),
+// which is -expm1(nt) itself for k = 0 and free of cancellation for k <= -1.
+// Below nt = -37 the result rounds to 1, so nt is clamped at -40, which also
+// keeps k in [-58, 0].
+__device__ __forceinline__ double one_minus_exp(double nt)
 {
-    t = fmin(t, 40.0);
-    const double k = rint(t * kLog2E);
-    double r = fma(k, kLn2Hi, -t);
-    r = fma(k, kLn2Lo, r);
+    nt = fmax(nt, -40.0);
+    const double rk = fma(nt, kLog2E, kRoundMagic);
+    const int ki = int(__double_as_longlong(rk));   // k, read from the low bits
+    const double k = rk - kRoundMagic;              // k as a double, exact
+    double r = fma(k, -kLn2Hi, nt);
+    r = fma(k, -kLn2Lo, r);
     double q = 2.5105206373957011e-08;
     q = fma(q, r, 2.7626357241447223e-07);
     q = fma(q, r, 2.7557255425746435e-06);
@@ -74,7 +81,7 @@ __device__ __forceinline__ double one_minus_exp_neg(double t)
     q = fma(q, r, 0.50000000000000056);
     q = fma(q, r, 1.0);
     const double em = q * r;                // expm1(r)
-    const double s = ldexp(1.0, -int(k));   // 2^-k, exact
+    const double s = ldexp(1.0, ki);        // 2^k, exact
     return fma(-s, em, 1.0 - s);
 }
 
@@ -112,9 +119,9 @@ __device__ __forceinline__ void p2p_f32(const float4* __restrict__ src, int padd
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const float dx = ox[r] - t.x, dy = oy[r] - t.y;
-            const float r2 = fmaf(dx, dx, dy * dy);
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));    // > 0, as in the FP64 form
             const float e = __builtin_amdgcn_exp2f(-r2 * c2);
-            const float q2 = fmaf(-t.z, e, t.z) * __builtin_amdgcn_rcpf(fmaxf(r2, 1e-30f));
+            const float q2 = fmaf(-t.z, e, t.z) * __builtin_amdgcn_rcpf(r2);
             fx[r] = fmaf(q2, dx, fx[r]);
             fy[r] = fmaf(-q2, dy, fy[r]);
         }
@@ -122,7 +129,7 @@ __device__ __forceinline__ void p2p_f32(const float4* __restrict__ src, int padd
 }
 
 template <int R>
-__device__ __forceinline__ void p2p_f64(const Src64* __restrict__ src, int padded, int S, int si, double inv2s2,
+__device__ __forceinline__ void p2p_f64(const Src64* __restrict__ src, int padded, int S, int si, double ninv2s2,
                                         const double* x, const double* y, double* ax, double* ay)
 {
     for (int jb = 0; jb < padded; jb += S) {
@@ -130,9 +137,12 @@ __device__ __forceinline__ void p2p_f64(const Src64* __restrict__ src, int padde
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const double dx = x[r] - t.x, dy = y[r] - t.y;
-            const double r2 = fma(dx, dx, dy * dy);
-            const double f = one_minus_exp_neg(r2 * inv2s2);        // 0 at r2 = 0
-            const double q2 = t.g * f * recip(fmax(r2, 1e-300));
+            // 1e-300 keeps r2 positive for coincident points, whose term
+            // then vanishes through dx = dy = 0; it changes r2 only for
+            // points closer than about 1e-142
+            const double r2 = fma(dx, dx, fma(dy, dy, 1e-300));
+            const double f = one_minus_exp(r2 * ninv2s2);
+            const double q2 = t.g * f * recip(r2);
             ax[r] = fma(q2, dx, ax[r]);
             ay[r] = fma(-q2, dy, ay[r]);
         }
@@ -244,7 +254,7 @@ __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* 
             }
             wave_sync();
             if constexpr (MIXED) p2p_f32<R>(src, padded, S, si, c.c2, oxi, oyi, fx, fy);
-            else p2p_f64<R>(src, padded, S, si, c.inv2s2, xi, yi, ax, ay);
+            else p2p_f64<R>(src, padded, S, si, -c.inv2s2, xi, yi, ax, ay);
         }
 
         // combine the S slices: every lane of a target group ends with the sums

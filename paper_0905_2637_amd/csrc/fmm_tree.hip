@@ -184,9 +184,7 @@ k_scan_down(int64_t m, int nb, const int32_t* __restrict__ in, const int32_t* __
 // ---------------------------------------------------------------------------
 
 constexpr int kRadixBins = 256;
-constexpr int kRadixThreads = 256;
-constexpr int kRadixRounds = 16;
-constexpr int kRadixTile = kRadixThreads * kRadixRounds;   // keys per workgroup
+constexpr int kRadixTile = 4096;   // keys per workgroup
 
 // Instance owning input particle i (its particles are [part_off, next part_off)).
 __device__ __forceinline__ int particle_inst(const Inst* __restrict__ inst, int n_inst, int64_t i)
@@ -199,33 +197,41 @@ __device__ __forceinline__ int particle_inst(const Inst* __restrict__ inst, int 
     return lo;
 }
 
+// The histogram kernels and the scatter take the same 4096-key tiles with
+// TPB-thread workgroups, 4096 / TPB keys per thread.  Few tiles (small n)
+// run with 1024 threads, so that every CU still holds many wavefronts to hide
+// the memory latency of these passes; many tiles run with 256 threads and 16
+// keys per thread, which measured faster there.
+
 // First pass: the sort key of every particle (kept in input order for
 // inspection), the out-of-domain count of the tile, and the tile's histogram
 // of the lowest digit.
-__global__ void __launch_bounds__(kRadixThreads)
+template <int TPB>
+__global__ void __launch_bounds__(TPB)
 k_rhist_keys(int n, const double* __restrict__ x, const double* __restrict__ y, const Inst* __restrict__ inst,
              int n_inst, int key_shift, int nblk, uint32_t* __restrict__ key, int32_t* __restrict__ hist,
              int32_t* __restrict__ bad_blk)
 {
+    constexpr int kTileRounds = kRadixTile / TPB;
     __shared__ int h[kRadixBins];
     __shared__ int nbad;
     if (threadIdx.x == 0) nbad = 0;
-    h[threadIdx.x] = 0;
-    __syncthreads();
+    if (threadIdx.x < kRadixBins) h[threadIdx.x] = 0;
     const int64_t base = int64_t(blockIdx.x) * kRadixTile;
     int mybad = 0;
     // all coordinate loads first, then keys and counting
-    double xv[kRadixRounds], yv[kRadixRounds];
+    double xv[kTileRounds], yv[kTileRounds];
 #pragma unroll
-    for (int r = 0; r < kRadixRounds; ++r) {
-        const int64_t i = base + r * kRadixThreads + threadIdx.x;
+    for (int r = 0; r < kTileRounds; ++r) {
+        const int64_t i = base + r * TPB + threadIdx.x;
         const int64_t ic = i < n ? i : base;
         xv[r] = x[ic];
         yv[r] = y[ic];
     }
+    __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kRadixRounds; ++r) {
-        const int64_t i = base + r * kRadixThreads + threadIdx.x;
+    for (int r = 0; r < kTileRounds; ++r) {
+        const int64_t i = base + r * TPB + threadIdx.x;
         if (i < n) {
             const int q = n_inst == 1 ? 0 : particle_inst(inst, n_inst, i);
             const int L = inst[q].L;
@@ -242,7 +248,7 @@ k_rhist_keys(int n, const double* __restrict__ x, const double* __restrict__ y, 
     }
     if (mybad) atomicAdd(&nbad, mybad);
     __syncthreads();
-    hist[int64_t(threadIdx.x) * nblk + blockIdx.x] = h[threadIdx.x];
+    if (threadIdx.x < kRadixBins) hist[int64_t(threadIdx.x) * nblk + blockIdx.x] = h[threadIdx.x];
     if (threadIdx.x == 0) bad_blk[blockIdx.x] = nbad;
 }
 
@@ -263,26 +269,28 @@ __device__ __forceinline__ KeyLeaf key_leaf(uint32_t k, const Inst* __restrict__
 }
 
 // Digit histogram of one tile, written digit-major: hist[d * nblk + block].
-__global__ void __launch_bounds__(kRadixThreads)
+template <int TPB>
+__global__ void __launch_bounds__(TPB)
 k_rhist(int n, const uint32_t* __restrict__ kin, int shift, int nblk, int32_t* __restrict__ hist)
 {
+    constexpr int kTileRounds = kRadixTile / TPB;
     __shared__ int h[kRadixBins];
-    h[threadIdx.x] = 0;
-    __syncthreads();
+    if (threadIdx.x < kRadixBins) h[threadIdx.x] = 0;
     const int64_t base = int64_t(blockIdx.x) * kRadixTile;
-    uint32_t kv[kRadixRounds];
+    uint32_t kv[kTileRounds];
 #pragma unroll
-    for (int r = 0; r < kRadixRounds; ++r) {
-        const int64_t i = base + r * kRadixThreads + threadIdx.x;
+    for (int r = 0; r < kTileRounds; ++r) {
+        const int64_t i = base + r * TPB + threadIdx.x;
         kv[r] = kin[i < n ? i : base];
     }
+    __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kRadixRounds; ++r) {
-        const int64_t i = base + r * kRadixThreads + threadIdx.x;
+    for (int r = 0; r < kTileRounds; ++r) {
+        const int64_t i = base + r * TPB + threadIdx.x;
         if (i < n) atomicAdd(&h[(kv[r] >> shift) & (kRadixBins - 1)], 1);
     }
     __syncthreads();
-    hist[int64_t(threadIdx.x) * nblk + blockIdx.x] = h[threadIdx.x];
+    if (threadIdx.x < kRadixBins) hist[int64_t(threadIdx.x) * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
 // Where a sorted record goes, and what it carries.
@@ -295,45 +303,77 @@ struct Records {
 };
 
 // Stable scatter of one tile, in two phases.
-// Phase A ranks the tile: records are taken in input order, 256 per round;
-// wavefront w ranks its lanes by digit with 8 ballots and the per-wave digit
-// counts order the wavefronts, giving every record its position in the
-// digit-sorted tile.  Phase B stages each array through LDS in that order, so
-// that consecutive threads write consecutive addresses of each digit's run
-// (offs[d * nblk + block] is where the tile's run of digit d starts):
-// whole cache lines instead of scattered 8-byte writes.
+// Phase A ranks the tile: wavefront w owns input positions
+// [4096 w / W, 4096 (w + 1) / W) of the W = TPB / 64 wavefronts and takes
+// them 64 per round, in input order (loaded up front for 4 rounds, round by
+// round for 16, which measured faster for each); it ranks
+// its lanes by digit with 8 ballots, and the per-wavefront digit counts order
+// the wavefronts, giving every record its position in the digit-sorted tile.
+// Phase B stages each array through LDS in that order, so that consecutive
+// threads write consecutive addresses of each digit's run (offs[d * nblk +
+// block] is where the tile's run of digit d starts): whole cache lines
+// instead of scattered 8-byte writes.
 // iin == nullptr means the identity (first pass).  pk != nullptr (last pass,
 // mixed precision) also writes the FP32 leaf-relative record
 // (x - c, y - c) / w_L, gamma of the leaf centre c.
-constexpr int kPerThread = kRadixRounds;
-
-__global__ void __launch_bounds__(kRadixThreads)
+template <int TPB>
+__global__ void __launch_bounds__(TPB)
 k_rscatter(int n, const uint32_t* __restrict__ kin, const uint32_t* __restrict__ iin,
            const double* __restrict__ xin, const double* __restrict__ yin, const double* __restrict__ gin,
            int shift, int nblk, const int32_t* __restrict__ hist, const int32_t* __restrict__ offs, Records out,
            float4* __restrict__ pk, const Inst* __restrict__ inst, int key_shift)
 {
+    constexpr int kScatterThreads = TPB;
+    constexpr int kScatterWaves = TPB / 64;
+    constexpr int kPerThread = kRadixTile / TPB;
+    constexpr bool kUpFront = kPerThread <= 4;
     __shared__ int gbase[kRadixBins];      // global start of this tile's run of digit d
     __shared__ int tstart[kRadixBins];     // start of digit d in the sorted tile
-    __shared__ int whist[kRadixThreads / 64][kRadixBins];   // per wavefront: records of digit d so far
+    __shared__ int wsum[4];
+    __shared__ int whist[kScatterWaves][kRadixBins];   // per wavefront: records of digit d so far
     __shared__ uint32_t sk[kRadixTile];
     __shared__ double sv[kRadixTile];
     const int tid = threadIdx.x, lane = int(__lane_id()), w = tid >> 6;
     const int64_t tile = int64_t(blockIdx.x) * kRadixTile;
     const int tile_n = int(min(int64_t(kRadixTile), int64_t(n) - tile));
+    constexpr int kWaveKeys = kRadixTile / kScatterWaves;
 
-    // ---- phase A: load the tile and rank it ----
-    // Wavefront w owns the input positions [w * kWaveKeys, (w + 1) * kWaveKeys)
-    // of the tile, 64 per round.
-    constexpr int kWaveKeys = kRadixTile / (kRadixThreads / 64);
+    // the tile's histogram (one digit per thread of the first 256) scanned
+    // into tstart; the first four wavefronts hold it
+    int hv = 0, hinc = 0;
+    if (tid < kRadixBins) {
+        hv = hist[int64_t(tid) * nblk + blockIdx.x];
+        gbase[tid] = offs[int64_t(tid) * nblk + blockIdx.x];
+        hinc = wave_incl_scan(hv);
+        if (lane == 63) wsum[w] = hinc;
+    }
+#pragma unroll
+    for (int e = tid; e < kScatterWaves * kRadixBins; e += kScatterThreads) (&whist[0][0])[e] = 0;
+
     uint32_t kr[kPerThread], vr[kPerThread];
     double xr[kPerThread], yr[kPerThread], gr[kPerThread];
-    int total;
-    tstart[tid] = block_excl_scan(hist[int64_t(tid) * nblk + blockIdx.x], &total);
-    gbase[tid] = offs[int64_t(tid) * nblk + blockIdx.x];
+    bool valid[kPerThread];
+    auto load = [&](int r) {
+        const int li = w * kWaveKeys + r * 64 + lane;
+        valid[r] = li < tile_n;
+        const int64_t i = tile + (valid[r] ? li : 0);
+        kr[r] = valid[r] ? kin[i] : 0u;
+        vr[r] = iin ? iin[i] : uint32_t(i);
+        xr[r] = xin[i];
+        yr[r] = yin[i];
+        gr[r] = gin[i];
+    };
+    if constexpr (kUpFront) {
 #pragma unroll
-    for (int q = 0; q < kRadixThreads / 64; ++q) whist[q][tid] = 0;
+        for (int r = 0; r < kPerThread; ++r) load(r);
+    }
     __syncthreads();
+    if (tid < kRadixBins) {
+        int before = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) before += q < w ? wsum[q] : 0;
+        tstart[tid] = before + hinc - hv;
+    }
 
     // rank within the wavefront, round after round (input order): equal
     // digits of one round are told apart by 8 ballots, earlier rounds by the
@@ -342,18 +382,9 @@ k_rscatter(int n, const uint32_t* __restrict__ kin, const uint32_t* __restrict__
     int lpos[kPerThread], dig[kPerThread];
 #pragma unroll
     for (int r = 0; r < kPerThread; ++r) {
-        const int li = w * kWaveKeys + r * 64 + lane;
-        const bool valid = li < tile_n;
-        {
-            const int64_t i = tile + (valid ? li : 0);
-            kr[r] = valid ? kin[i] : 0u;
-            vr[r] = iin ? iin[i] : uint32_t(i);
-            xr[r] = xin[i];
-            yr[r] = yin[i];
-            gr[r] = gin[i];
-        }
+        if constexpr (!kUpFront) load(r);
         const int d = int((kr[r] >> shift) & (kRadixBins - 1));
-        uint64_t same = __ballot(valid);
+        uint64_t same = __ballot(valid[r]);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
             const bool bit = (d >> b) & 1;
@@ -363,19 +394,19 @@ k_rscatter(int n, const uint32_t* __restrict__ kin, const uint32_t* __restrict__
         const int rank = __popcll(same & lt_mask);
         const int before = whist[w][d];
         __builtin_amdgcn_wave_barrier();
-        if (valid && rank == 0) whist[w][d] = before + __popcll(same);
+        if (valid[r] && rank == 0) whist[w][d] = before + __popcll(same);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        lpos[r] = valid ? before + rank : -1;
+        lpos[r] = valid[r] ? before + rank : -1;
         dig[r] = d;
     }
     __syncthreads();
     // exclusive prefix over the wavefronts, per digit
-    {
+    if (tid < kRadixBins) {
         int acc = 0;
 #pragma unroll
-        for (int q = 0; q < kRadixThreads / 64; ++q) {
+        for (int q = 0; q < kScatterWaves; ++q) {
             const int t = whist[q][tid];
             whist[q][tid] = acc;
             acc += t;
@@ -395,7 +426,7 @@ k_rscatter(int n, const uint32_t* __restrict__ kin, const uint32_t* __restrict__
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kPerThread; ++r) {
-        const int j = r * kRadixThreads + tid;
+        const int j = r * kScatterThreads + tid;
         dst[r] = -1;
         if (j < tile_n) {
             const uint32_t k = sk[j];
@@ -412,17 +443,16 @@ k_rscatter(int n, const uint32_t* __restrict__ kin, const uint32_t* __restrict__
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kPerThread; ++r)
-        if (dst[r] >= 0) out.idx[dst[r]] = sk[r * kRadixThreads + tid];
+        if (dst[r] >= 0) out.idx[dst[r]] = sk[r * kScatterThreads + tid];
 
     double xs_[kPerThread], ys_[kPerThread];
-    __syncthreads();
 #pragma unroll
     for (int r = 0; r < kPerThread; ++r)
         if (lpos[r] >= 0) sv[lpos[r]] = xr[r];
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kPerThread; ++r) {
-        xs_[r] = sv[r * kRadixThreads + tid];
+        xs_[r] = sv[r * kScatterThreads + tid];
         if (dst[r] >= 0) out.x[dst[r]] = xs_[r];
     }
     __syncthreads();
@@ -432,7 +462,7 @@ k_rscatter(int n, const uint32_t* __restrict__ kin, const uint32_t* __restrict__
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kPerThread; ++r) {
-        ys_[r] = sv[r * kRadixThreads + tid];
+        ys_[r] = sv[r * kScatterThreads + tid];
         if (dst[r] >= 0) out.y[dst[r]] = ys_[r];
     }
     __syncthreads();
@@ -443,7 +473,7 @@ k_rscatter(int n, const uint32_t* __restrict__ kin, const uint32_t* __restrict__
 #pragma unroll
     for (int r = 0; r < kPerThread; ++r) {
         if (dst[r] < 0) continue;
-        const double gv = sv[r * kRadixThreads + tid];
+        const double gv = sv[r * kScatterThreads + tid];
         out.g[dst[r]] = gv;
         if (pk) {
             const KeyLeaf kl = key_leaf(ks_[r], inst, key_shift);
@@ -539,6 +569,12 @@ int64_t radix_blocks(int64_t n) { return (n + kRadixTile - 1) / kRadixTile; }
 
 namespace {
 
+// Radix passes of at most this many tiles use the 1024-thread kernels.
+#ifndef FMM_TREE_TPB
+#define FMM_TREE_TPB 0
+#endif
+constexpr int kWideTilesMax = 2048;
+
 // Exclusive scan of hist[0..m) into out[0..m], out[m] = total.
 void scan_table(const Buffers& b, int64_t m, hipStream_t st)
 {
@@ -557,8 +593,13 @@ hipError_t launch_tree(const Buffers& b, int n, const double* x, const double* y
     float4* pk = mixed ? b.pk : nullptr;
     const Records fin{b.ksorted, b.perm, b.xs, b.ys, b.gs};
     const Records tmp{b.ktmp, b.itmp, b.xt, b.yt, b.gt};
-    hipLaunchKernelGGL(k_rhist_keys, dim3(nblk), dim3(kRadixThreads), 0, st, n, x, y, b.inst, b.n_inst,
-                       b.key_shift, nblk, b.key, b.hist, b.bad_blk);
+    const bool wide = FMM_TREE_TPB == 1024 || (FMM_TREE_TPB == 0 && nblk <= kWideTilesMax);
+    if (wide)
+        hipLaunchKernelGGL(k_rhist_keys<1024>, dim3(nblk), dim3(1024), 0, st, n, x, y, b.inst, b.n_inst,
+                           b.key_shift, nblk, b.key, b.hist, b.bad_blk);
+    else
+        hipLaunchKernelGGL(k_rhist_keys<256>, dim3(nblk), dim3(256), 0, st, n, x, y, b.inst, b.n_inst,
+                           b.key_shift, nblk, b.key, b.hist, b.bad_blk);
     const int npass = radix_passes(key_bits);
     if (npass == 0) {
         hipLaunchKernelGGL(k_copy_one_leaf, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, x, y, g, fin, pk, b.inst);
@@ -570,12 +611,18 @@ hipError_t launch_tree(const Buffers& b, int n, const double* x, const double* y
         for (int pass = 0; pass < npass; ++pass) {
             const Records& out = ((npass - 1 - pass) & 1) ? tmp : fin;
             const int shift = 8 * pass;
-            if (pass > 0)
-                hipLaunchKernelGGL(k_rhist, dim3(nblk), dim3(kRadixThreads), 0, st, n, kin, shift, nblk, b.hist);
+            if (pass > 0 && wide)
+                hipLaunchKernelGGL(k_rhist<1024>, dim3(nblk), dim3(1024), 0, st, n, kin, shift, nblk, b.hist);
+            else if (pass > 0)
+                hipLaunchKernelGGL(k_rhist<256>, dim3(nblk), dim3(256), 0, st, n, kin, shift, nblk, b.hist);
             scan_table(b, m, st);
             const bool last = pass == npass - 1;
-            hipLaunchKernelGGL(k_rscatter, dim3(nblk), dim3(kRadixThreads), 0, st, n, kin, iin, xin, yin, gin,
-                               shift, nblk, b.hist, b.hist_scan, out, last ? pk : nullptr, b.inst, b.key_shift);
+            if (wide)
+                hipLaunchKernelGGL(k_rscatter<1024>, dim3(nblk), dim3(1024), 0, st, n, kin, iin, xin, yin, gin,
+                                   shift, nblk, b.hist, b.hist_scan, out, last ? pk : nullptr, b.inst, b.key_shift);
+            else
+                hipLaunchKernelGGL(k_rscatter<256>, dim3(nblk), dim3(256), 0, st, n, kin, iin, xin, yin, gin,
+                                   shift, nblk, b.hist, b.hist_scan, out, last ? pk : nullptr, b.inst, b.key_shift);
             kin = out.k;
             iin = out.idx;
             xin = out.x;
