@@ -424,17 +424,21 @@ void build_schedule(fmm_plan_s* pl)
                 }
             add(L_M2L, prec == 1, groups, false);
         }
-    // downward: L2L in groups of up to three levels from level 2
+    // downward: L2L in groups of up to three levels from level 2, the
+    // remainder of (L - 2) / 3 first, so that the large launches near the
+    // leaves cover three full levels
     for (int g = 0;; ++g) {
         clear();
         bool any = false;
         for (int i = 0; i < n; ++i) {
             const int L = sh.depth[i];
-            const int lt = 2 + 3 * g;
-            if (L < 2 || lt >= L) continue;
+            if (L < 3) continue;
+            const int r = (L - 2) % 3;
+            const int lt = g == 0 ? 2 : 2 + (r ? r : 3) + 3 * (g - 1);
+            if (lt >= L) continue;
             wg[i] = int(int64_t(1) << (2 * lt));
             arg[2 * i] = lt;
-            arg[2 * i + 1] = std::min(3, L - lt);
+            arg[2 * i + 1] = g == 0 && r ? r : 3;
             any = true;
         }
         if (!any) break;

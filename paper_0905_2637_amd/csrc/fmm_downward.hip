@@ -338,58 +338,115 @@ constexpr int kDownThreads = 256;
 // its interaction list split over two or three wavefronts there; part[1]
 // only on the levels of Inst::part1); they are added to le when a level's M2L
 // result is first read.
+// All of the subtree's M2L results are loaded before the first wait: the
+// levels above the last into LDS, the last level (at most 64 boxes) into the
+// registers of the threads that finish it, which also keeps the LDS small
+// enough for several workgroups per CU.
 // Work table arg: lt, d.
 template <int P>
 __global__ void __launch_bounds__(kDownThreads)
 k_downward(Work wk, int n_inst, const Inst* __restrict__ inst, cd* __restrict__ le_all,
            const cd* __restrict__ Lt, const cd* __restrict__ part0_all, const cd* __restrict__ part1_all)
 {
-    __shared__ cd sh[85 * P];
+    constexpr int kUp = (21 * P + kDownThreads - 1) / kDownThreads;     // levels lt .. lt+d-1 per thread
+    constexpr int kLast = (64 * P + kDownThreads - 1) / kDownThreads;   // last level per thread
+    __shared__ cd sh[21 * P];            // levels lt, lt+1, lt+2 (1 + 4 + 16 boxes) at P (4^t - 1) / 3
     __shared__ cd sL[4 * P * P];
     const int tid = threadIdx.x;
     const int pos = find_inst(wk.wg_begin, n_inst, blockIdx.x);   // place in the launch order
     const int q = wk.order[pos];
     const int64_t root = blockIdx.x - wk.wg_begin[pos];
     const int lt = wk.arg[2 * pos], d = wk.arg[2 * pos + 1];
+    const int last = lt + d;
     const int split_level = inst[q].split;
     cd* le = le_all + inst[q].box_off * P;
     const cd* part0 = part0_all + inst[q].split_off * P;
     const cd* part1 = part1_all + inst[q].split_off * P;
     const int part1_levels = inst[q].part1;
-    for (int e = tid; e < 4 * P * P; e += kDownThreads) sL[e] = Lt[e];
-    const int64_t ri = (level_offset(lt) + root) * P;
-    for (int k = tid; k < P; k += kDownThreads) {
-        cd v = le[ri + k];
-        if (lt == 2 && lt <= split_level) {   // level 2 gets no L2L: finish its M2L sum here
-            v.x += part0[ri + k].x;
-            v.y += part0[ri + k].y;
-            if ((part1_levels >> lt) & 1) {
-                v.x += part1[ri + k].x;
-                v.y += part1[ri + k].y;
-            }
-            le[ri + k] = v;
+    // What M2L left for each coefficient of the subtree, with the partial
+    // sums added; the root (level lt) is final unless lt = 2, which gets no
+    // L2L and finishes its M2L sum here.  Every thread issues the same loads
+    // (indices clamped past the subtree's end; a partial-sum array only when
+    // some level of the workgroup has one), all before the first wait, and
+    // combines them afterwards.  The launches are grouped so that the large
+    // ones cover three full levels.
+    const int lo = lt == 2 ? lt : lt + 1;             // first level that takes partial sums
+    const bool any0 = lo <= min(split_level, last);
+    const bool any1 = any0 && ((part1_levels >> lo) & ((2 << (min(split_level, last) - lo)) - 1)) != 0;
+    const int n_up = P * ((1 << (2 * d)) - 1) / 3;     // coefficients of levels lt .. last-1
+    const int n_last = P << (2 * d);
+    // slot i < kUp: coefficient tid + 256 i of levels lt .. last-1; slot
+    // kUp + i: coefficient tid + 256 i of the last level
+    constexpr int kSlots = kUp + kLast;
+    int64_t gi[kSlots];
+    bool a0[kSlots], a1[kSlots];
+#pragma unroll
+    for (int i = 0; i < kSlots; ++i) {
+        int j, e;
+        if (i < kUp) {
+            const int e0 = tid + kDownThreads * i;
+            const int ec = e0 < n_up ? e0 : 0;
+            const int t = ec < P ? 0 : (ec < 5 * P ? 1 : 2);   // level lt + t
+            j = lt + t;
+            e = ec - P * ((1 << (2 * t)) - 1) / 3;
+        } else {
+            const int e0 = tid + kDownThreads * (i - kUp);
+            j = last;
+            e = e0 < n_last ? e0 : 0;
         }
-        sh[k] = v;
+        gi[i] = (level_offset(j) + (root << (2 * (j - lt)))) * P + e;
+        a0[i] = j >= lo && j <= split_level;
+        a1[i] = a0[i] && ((part1_levels >> j) & 1);
+    }
+    cd rv[kSlots], r0[kSlots], r1[kSlots];
+#pragma unroll
+    for (int i = 0; i < kSlots; ++i) rv[i] = le[gi[i]];
+    if (any0) {
+#pragma unroll
+        for (int i = 0; i < kSlots; ++i) r0[i] = part0[a0[i] ? gi[i] : 0];   // entry 0 always exists
+    }
+    if (any1) {
+#pragma unroll
+        for (int i = 0; i < kSlots; ++i) r1[i] = part1[a1[i] ? gi[i] : 0];
+    }
+    cd up[kUp], lastv[kLast];
+#pragma unroll
+    for (int i = 0; i < kSlots; ++i) {
+        double x = rv[i].x, y = rv[i].y;
+        if (any0) {
+            x = a0[i] ? x + r0[i].x : x;
+            y = a0[i] ? y + r0[i].y : y;
+        }
+        if (any1) {
+            x = a1[i] ? x + r1[i].x : x;
+            y = a1[i] ? y + r1[i].y : y;
+        }
+        if (i < kUp) up[i] = cd{x, y};
+        else lastv[i - kUp] = cd{x, y};
+    }
+    for (int e = tid; e < 4 * P * P; e += kDownThreads) sL[e] = Lt[e];
+#pragma unroll
+    for (int i = 0; i < kUp; ++i) {
+        const int e = tid + kDownThreads * i;
+        if (e < n_up) {
+            sh[e] = up[i];
+            if (e < P && lt == 2 && lt <= split_level) le[level_offset(lt) * P + root * P + e] = up[i];
+        }
     }
     __syncthreads();
-    int in_off = 0, out_off = P, n_in = 1;
-    for (int j = lt + 1; j <= lt + d; ++j) {
+    int n_in = 1;
+    for (int j = lt + 1; j <= last; ++j) {
         const int n_out = n_in << 2;
+        const int in_off = P * (n_in - 1) / 3, out_off = P * (n_out - 1) / 3;
         const int64_t gfirst = root << (2 * (j - lt));
         cd* g = le + (level_offset(j) + gfirst) * P;
-        for (int e = tid; e < n_out * P; e += kDownThreads) {
+#pragma unroll
+        for (int i = 0; i < kLast; ++i) {
+            const int e = tid + kDownThreads * i;
+            if (e >= n_out * P) continue;
             const int o = e / P, k = e % P;
-            const cd cur = g[e];
+            const cd cur = j == last ? lastv[i] : sh[out_off + e];
             double bx = cur.x, by = cur.y;
-            if (j <= split_level) {
-                const int64_t pi = (level_offset(j) + gfirst) * P + e;
-                bx += part0[pi].x;
-                by += part0[pi].y;
-                if ((part1_levels >> j) & 1) {
-                    bx += part1[pi].x;
-                    by += part1[pi].y;
-                }
-            }
             const cd* par = sh + in_off + (o >> 2) * P;
             const cd* Lr = sL + ((o & 3) * P + k) * P;     // rows k >= p are zero
             // the full row (entries m < k are zero): a fixed trip count lets
@@ -401,11 +458,10 @@ k_downward(Work wk, int n_inst, const Inst* __restrict__ inst, cd* __restrict__ 
                 cmac(bx, by, t.x, t.y, s.x, s.y);
             }
             g[e] = cd{bx, by};
-            sh[out_off + e] = cd{bx, by};
+            if (j < last) sh[out_off + e] = cd{bx, by};
         }
+        if (j == last) break;
         __syncthreads();
-        in_off = out_off;
-        out_off += n_out * P;
         n_in = n_out;
     }
 }

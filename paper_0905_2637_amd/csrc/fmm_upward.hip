@@ -36,15 +36,19 @@ constexpr int kP2MLanes = 4;            // threads per leaf in P2M
 // Workgroup = one box at level lt = lb - d (d <= 3) of one instance (work
 // table arg: lt, d).  from_particles: the 4^d boxes of level lb are leaves
 // and get their expansion from P2M; otherwise they are read from global
-// memory.
+// memory, all loads issued before the first wait.  LDS holds one level at a
+// time (each M2M level is computed into registers, then written over its
+// input after a barrier), and the kernel is held to 128 VGPRs: four
+// workgroups fit on a CU, so a launch of 4 x 256 workgroups runs in one
+// round.
 template <int P>
-__global__ void __launch_bounds__(kUpThreads)
+__global__ void __launch_bounds__(kUpThreads, 4)
 k_upward(Work wk, int n_inst, const Inst* __restrict__ inst, int p, int from_particles,
          const int32_t* __restrict__ leaf_start_all, const double* __restrict__ xs, const double* __restrict__ ys,
          const double* __restrict__ gs, cd* __restrict__ me_all, const cd* __restrict__ M,
          const double* __restrict__ sk)
 {
-    __shared__ cd sh[85 * P];            // 64 + 16 + 4 + 1 boxes
+    __shared__ cd sh[64 * P + 1];        // the current level of the subtree (<= 64 boxes) + a junk slot
     __shared__ cd sM[4 * P * P];         // the four M2M matrices
     const int tid = threadIdx.x;
     const int pos = find_inst(wk.wg_begin, n_inst, blockIdx.x);   // place in the launch order
@@ -75,7 +79,7 @@ k_upward(Work wk, int n_inst, const Inst* __restrict__ inst, int p, int from_par
 #pragma unroll
             for (int q = 0; q < KR; ++q) { ax[q] = 0.0; ay[q] = 0.0; }
             const int s0 = leaf_start[leaf], s1 = leaf_start[leaf + 1];
-            constexpr int kBatch = 4;       // particles whose loads are issued together
+            constexpr int kBatch = 8;       // particles whose loads are issued together
             for (int j0 = s0; j0 < s1; j0 += kBatch) {
                 double bxp[kBatch], byp[kBatch], bgp[kBatch];
 #pragma unroll
@@ -119,25 +123,45 @@ k_upward(Work wk, int n_inst, const Inst* __restrict__ inst, int p, int from_par
             }
         }
     } else {
+        constexpr int kIn = (64 * P + kUpThreads - 1) / kUpThreads;
         const cd* src = me + (level_offset(lb) + first) * P;
-        for (int e = tid; e < nb * P; e += kUpThreads) sh[e] = src[e];
+        cd in[kIn];
+#pragma unroll
+        for (int i = 0; i < kIn; ++i) {      // unconditional (clamped) loads, all in flight
+            const int e = tid + kUpThreads * i;
+            in[i] = src[e < nb * P ? e : 0];
+        }
+        // unconditional stores (out-of-range ones to the junk slot), so that
+        // no load is sunk into a branch behind the previous one's wait
+#pragma unroll
+        for (int i = 0; i < kIn; ++i) {
+            const int e = tid + kUpThreads * i;
+            sh[e < nb * P ? e : 64 * P] = in[i];
+        }
     }
     __syncthreads();
 
     // ---- M2M from level j+1 to level j, j = lb-1 .. lt ----
-    int in_off = 0, out_off = nb * P, n_in = nb;
+    // (at most 16 P outputs per level: kOut per thread)
+    constexpr int kOut = (16 * P + kUpThreads - 1) / kUpThreads;
+    int n_in = nb;
     for (int j = lb - 1; j >= lt; --j) {
         const int n_out = n_in >> 2;
         const int64_t gfirst = root << (2 * (j - lt));
         cd* gdst = me + (level_offset(j) + gfirst) * P;
-        for (int e = tid; e < n_out * P; e += kUpThreads) {
+        cd res[kOut];
+#pragma unroll
+        for (int i = 0; i < kOut; ++i) {
+            const int e = tid + kUpThreads * i;
+            res[i] = cd{0.0, 0.0};
+            if (e >= n_out * P) continue;
             const int o = e / P, k = e % P;
             double bx = 0.0, by = 0.0;
             // the full row (entries m > k are zero): a fixed trip count lets
             // the LDS loads be issued together
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const cd* a = sh + in_off + (4 * o + c) * P;
+                const cd* a = sh + (4 * o + c) * P;
                 const cd* Mr = sM + (c * P + k) * P;     // rows k >= p are zero
 #pragma unroll
                 for (int m = 0; m < P; ++m) {
@@ -146,12 +170,17 @@ k_upward(Work wk, int n_inst, const Inst* __restrict__ inst, int p, int from_par
                     cmac(bx, by, t.x, t.y, s.x, s.y);
                 }
             }
-            gdst[e] = cd{bx, by};
-            sh[out_off + e] = cd{bx, by};
+            res[i] = cd{bx, by};
+            gdst[e] = res[i];
+        }
+        if (j == lt) break;
+        __syncthreads();                 // every thread has read level j+1
+#pragma unroll
+        for (int i = 0; i < kOut; ++i) {
+            const int e = tid + kUpThreads * i;
+            if (e < n_out * P) sh[e] = res[i];
         }
         __syncthreads();
-        in_off = out_off;
-        out_off += n_out * P;
         n_in = n_out;
     }
 }
