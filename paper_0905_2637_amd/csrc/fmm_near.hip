@@ -163,12 +163,14 @@ constexpr int kStageSlots = kNearStage / 64;   // staged sources per lane and ch
 
 // All targets of one leaf, in chunks of T = 2^lgT; R targets per lane.
 // le_sh: this wavefront's LDS copy of the leaf's local expansion (P terms).
+// sink != nullptr: the near-field sums (physical units, before the 1 / 2 pi)
+// go to sink[i] for target i of the leaf instead of being finished here.
 template <int P, bool MIXED, int R>
 __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* stage_raw, cd* le_sh, int has_far,
                                               const double* __restrict__ xs, const double* __restrict__ ys,
                                               const double* __restrict__ gs, const float4* __restrict__ pk,
                                               const uint32_t* __restrict__ perm, const cd* __restrict__ le_leaf,
-                                              double* __restrict__ u, double* __restrict__ v)
+                                              cd* sink, double* __restrict__ u, double* __restrict__ v)
 {
     using Stage = typename std::conditional<MIXED, float4, Src64>::type;
     Stage* src = static_cast<Stage*>(stage_raw);
@@ -209,7 +211,7 @@ __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* 
         const bool own = si < R && il < c.nt;
         uint32_t o = 0;
         double px = 0.0, py = 0.0;
-        if (own) {
+        if (own && !sink) {
             o = perm[c.s0 + il];
             if constexpr (MIXED) { px = xs[c.s0 + il]; py = ys[c.s0 + il]; }
         }
@@ -289,6 +291,10 @@ __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* 
                     accy = sy[r];
                     if constexpr (!MIXED) { px = xi[r]; py = yi[r]; }
                 }
+            if (sink) {
+                sink[il] = cd{accx, accy};
+                continue;
+            }
             if (has_far) {
                 const double zx = (px - c.cx) * c.s, zy = (py - c.cy) * c.s;
                 double hx = 0.0, hy = 0.0;
@@ -308,44 +314,23 @@ __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* 
     }
 }
 
-// WAVES independent wavefronts per workgroup, one leaf each; the work table
-// gives every instance ceil(4^L / WAVES) workgroups.
-template <int P, bool MIXED, int WAVES>
-__global__ void __launch_bounds__(64 * WAVES)
-k_p2p_l2p(Work wk, int n_inst, const Inst* __restrict__ inst, const int32_t* __restrict__ leaf_start_all,
-          const double* __restrict__ xs, const double* __restrict__ ys, const double* __restrict__ gs,
-          const float4* __restrict__ pk, const uint32_t* __restrict__ perm, const cd* __restrict__ le_all,
-          double inv2s2, double* __restrict__ u, double* __restrict__ v)
+// Context of leaf m of an instance: its range and its 3 x 3 neighbourhood,
+// row by row (clipped leaves are empty; with no_siblings, so are the other
+// three leaves of its quad).
+__device__ __forceinline__ void make_ctx(LeafCtx& c, uint32_t m, int L, const int32_t* __restrict__ leaf_start,
+                                         const Domain& d, double inv2s2, bool no_siblings)
 {
-    using Stage = typename std::conditional<MIXED, float4, Src64>::type;
-    __shared__ Stage stage_all[WAVES][kNearStage];
-    __shared__ cd le_all_sh[WAVES][P];
-
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int pos = find_inst(wk.wg_begin, n_inst, blockIdx.x);   // place in the launch order
-    const int qi = wk.order[pos];
-    const int L = inst[qi].L;
-    const int has_far = L >= 2 ? 1 : 0;
-    const int32_t* leaf_start = leaf_start_all + inst[qi].leaf_off;
-    const cd* le_leaf = le_all + (inst[qi].box_off + level_offset(L)) * P;
-    const int64_t nleaf = int64_t(1) << (2 * L);
-    const int64_t mm = int64_t(blockIdx.x - wk.wg_begin[pos]) * WAVES + wv;
-    if (mm >= nleaf) return;
-    LeafCtx c;
-    c.m = uint32_t(mm);
-    c.s0 = leaf_start[c.m];
-    c.nt = leaf_start[c.m + 1] - c.s0;
-    if (c.nt == 0) return;
-    const int a = int(morton_x(c.m)), b = int(morton_y(c.m)), side = 1 << L;
-    const int lane = threadIdx.x & 63;
-
-    // the 3 x 3 neighbourhood, row by row; clipped leaves are empty
+    c.m = m;
+    c.s0 = leaf_start[m];
+    c.nt = leaf_start[m + 1] - c.s0;
+    const int a = int(morton_x(m)), b = int(morton_y(m)), side = 1 << L;
     c.npre[0] = 0;
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
         const int na = a + (q % 3) - 1, nb = b + (q / 3) - 1;
         int cnt = 0, beg = 0;
-        if (na >= 0 && nb >= 0 && na < side && nb < side) {
+        const bool sib = no_siblings && (na >> 1) == (a >> 1) && (nb >> 1) == (b >> 1);
+        if (na >= 0 && nb >= 0 && na < side && nb < side && !sib) {
             const uint32_t sm = morton(uint32_t(na), uint32_t(nb));
             beg = leaf_start[sm];
             cnt = leaf_start[sm + 1] - beg;
@@ -354,8 +339,6 @@ k_p2p_l2p(Work wk, int n_inst, const Inst* __restrict__ inst, const int32_t* __r
         c.npre[q + 1] = c.npre[q] + cnt;
     }
     c.lgT = c.nt >= 64 ? 6 : (c.nt <= 1 ? 0 : 32 - __clz(c.nt - 1));
-
-    const Domain d = inst[qi].dom;
     const double w = ldexp(d.W, -L);
     c.cx = d.x0 + (double(a) + 0.5) * w;
     c.cy = d.y0 + (double(b) + 0.5) * w;
@@ -364,17 +347,158 @@ k_p2p_l2p(Work wk, int n_inst, const Inst* __restrict__ inst, const int32_t* __r
     // leaf-width units: |z|^2 / (2 sigma^2) = |zhat|^2 w^2 / (2 sigma^2), and
     // exp(-t) = 2^(-t log2(e)); w = 1/s
     c.c2 = float(inv2s2 * 1.4426950408889634074 / (d.s * d.s));
+}
 
-    // register blocking pays once a chunk is full; sparse leaves keep one
-    // target per lane (fewer slices to combine)
+// register blocking pays once a chunk is full; sparse leaves keep one target
+// per lane (fewer slices to combine)
+template <int P, bool MIXED>
+__device__ __forceinline__ void leaf_dispatch(const LeafCtx& c, int lane, void* st, cd* lsh, int has_far,
+                                              const double* __restrict__ xs, const double* __restrict__ ys,
+                                              const double* __restrict__ gs, const float4* __restrict__ pk,
+                                              const uint32_t* __restrict__ perm, const cd* __restrict__ le_leaf,
+                                              cd* sink, double* __restrict__ u, double* __restrict__ v)
+{
+    if (c.lgT == 6)
+        leaf_near_far<P, MIXED, 4>(c, lane, st, lsh, has_far, xs, ys, gs, pk, perm, le_leaf, sink, u, v);
+    else if (c.lgT == 5)
+        leaf_near_far<P, MIXED, 2>(c, lane, st, lsh, has_far, xs, ys, gs, pk, perm, le_leaf, sink, u, v);
+    else
+        leaf_near_far<P, MIXED, 1>(c, lane, st, lsh, has_far, xs, ys, gs, pk, perm, le_leaf, sink, u, v);
+}
+
+// Quads of sibling leaves: the four leaves of a 2 x 2 block touch each other,
+// so every pair of particles inside a quad is a near pair of both of its
+// particles, and the kernel is odd (K(-z) = -K(z)).  A workgroup of four
+// wavefronts owns one quad of at most kQuadMax particles, staged with one
+// particle per lane; wavefront w takes the rotations s = 8w + 1 .. 8w + 8
+// (s = 32 on the lower half of the lanes only), lane i meeting particle
+// (i + s) mod 64 once and handing the reverse term to that lane by a
+// cross-lane shuffle.  Each unordered pair is evaluated once; the five
+// neighbours outside the quad are summed per leaf as before.  All partial
+// sums meet in LDS and are added in a fixed order, so the result does not
+// depend on scheduling.  FP64 only: in the mixed form a pair costs a third as
+// much, and the staging, barriers and shuffles measured slower than the work
+// they save.
+constexpr int kQuadMax = 64;
+
+__device__ __forceinline__ void quad_pairs(const Src64* qsh, int lane, int w, double ninv2s2, double& sx, double& sy)
+{
+    const Src64 me = qsh[lane];
+    double ax = 0.0, ay = 0.0;
+    auto step = [&](int s, bool act) {
+        const Src64 t = qsh[(lane + s) & 63];
+        const double dx = me.x - t.x, dy = me.y - t.y;
+        const double r2 = fma(dx, dx, fma(dy, dy, 1e-300));
+        const double q = one_minus_exp(r2 * ninv2s2) * recip(r2);
+        const double qi = act ? t.g * q : 0.0, qj = act ? me.g * q : 0.0;
+        ax = fma(qi, dx, ax);
+        ay = fma(-qi, dy, ay);
+        const int from = (lane - s) & 63;
+        ax += __shfl(-qj * dx, from, 64);
+        ay += __shfl(qj * dy, from, 64);
+    };
+    for (int k = 0; k < (w == 3 ? 7 : 8); ++k) step(8 * w + 1 + k, true);
+    if (w == 3) step(32, lane < 32);
+    sx = ax;
+    sy = ay;
+}
+
+// WAVES wavefronts per workgroup, one leaf each (four: one quad); the work
+// table gives every instance ceil(4^L / WAVES) workgroups.
+template <int P, bool MIXED, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES)
+k_p2p_l2p(Work wk, int n_inst, const Inst* __restrict__ inst, const int32_t* __restrict__ leaf_start_all,
+          const double* __restrict__ xs, const double* __restrict__ ys, const double* __restrict__ gs,
+          const float4* __restrict__ pk, const uint32_t* __restrict__ perm, const cd* __restrict__ le_all,
+          double inv2s2, double* __restrict__ u, double* __restrict__ v)
+{
+    using Stage = typename std::conditional<MIXED, float4, Src64>::type;
+    constexpr bool kQuads = WAVES == 4 && !MIXED;
+    __shared__ Stage stage_all[WAVES][kNearStage];
+    __shared__ cd le_all_sh[WAVES][P];
+    __shared__ Src64 qsh[kQuads ? kQuadMax : 1];
+    __shared__ cd part_sh[kQuads ? 5 : 1][kQuads ? kQuadMax : 1];   // outside, then the 4 rotation groups
+
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int pos = find_inst(wk.wg_begin, n_inst, blockIdx.x);   // place in the launch order
+    const int qi = wk.order[pos];
+    const int L = inst[qi].L;
+    const int has_far = L >= 2 ? 1 : 0;
+    const int32_t* leaf_start = leaf_start_all + inst[qi].leaf_off;
+    const cd* le_leaf = le_all + (inst[qi].box_off + level_offset(L)) * P;
+    const int64_t nleaf = int64_t(1) << (2 * L);
+    const int64_t mm = int64_t(blockIdx.x - wk.wg_begin[pos]) * WAVES + wv;
+    const Domain d = inst[qi].dom;
     void* st = stage_all[wv];
     cd* lsh = le_all_sh[wv];
-    if (c.lgT == 6)
-        leaf_near_far<P, MIXED, 4>(c, lane, st, lsh, has_far, xs, ys, gs, pk, perm, le_leaf, u, v);
-    else if (c.lgT == 5)
-        leaf_near_far<P, MIXED, 2>(c, lane, st, lsh, has_far, xs, ys, gs, pk, perm, le_leaf, u, v);
-    else
-        leaf_near_far<P, MIXED, 1>(c, lane, st, lsh, has_far, xs, ys, gs, pk, perm, le_leaf, u, v);
+
+    // quad path: a whole quad (L >= 1) of 2 .. kQuadMax particles; the same
+    // decision in every wavefront of the workgroup
+    int sq = 0, nq = 0;
+    if constexpr (kQuads) {
+        if (L >= 1) {
+            const int64_t m0 = mm - wv;
+            sq = leaf_start[m0];
+            nq = leaf_start[m0 + 4] - sq;
+        }
+    }
+    if (!(kQuads && nq > 1 && nq <= kQuadMax)) {
+        if (mm >= nleaf) return;
+        LeafCtx c;
+        make_ctx(c, uint32_t(mm), L, leaf_start, d, inv2s2, false);
+        if (c.nt == 0) return;
+        leaf_dispatch<P, MIXED>(c, lane, st, lsh, has_far, xs, ys, gs, pk, perm, le_leaf, nullptr, u, v);
+        return;
+    }
+
+    LeafCtx c;
+    make_ctx(c, uint32_t(mm), L, leaf_start, d, inv2s2, true);
+    // stage the quad, one particle per lane (past nq: inert, far away and
+    // without circulation)
+    if (wv == 0) {
+        const int i = sq + min(lane, nq - 1);
+        qsh[lane] = lane < nq ? Src64{xs[i], ys[i], gs[i]} : Src64{1.0e10, 1.0e10, 0.0};
+    }
+    __syncthreads();
+    // the leaf's targets against the neighbours outside the quad
+    if (c.nt > 0)
+        leaf_dispatch<P, MIXED>(c, lane, st, lsh, 0, xs, ys, gs, pk, perm, le_leaf, part_sh[0] + (c.s0 - sq), u, v);
+    // this wavefront's share of the pairs inside the quad
+    double ix, iy;
+    quad_pairs(qsh, lane, wv, -inv2s2, ix, iy);
+    part_sh[1 + wv][lane] = cd{ix, iy};
+    __syncthreads();
+    if (c.nt == 0) return;
+    if (has_far)
+        for (int k = lane; k < P; k += 64) lsh[k] = le_leaf[int64_t(c.m) * P + k];
+    wave_sync();
+    if (lane < c.nt) {
+        const int j = c.s0 - sq + lane;
+        double accx = part_sh[0][j].x, accy = part_sh[0][j].y;
+#pragma unroll
+        for (int g = 1; g < 5; ++g) {
+            accx += part_sh[g][j].x;
+            accy += part_sh[g][j].y;
+        }
+        const int i = c.s0 + lane;
+        if (has_far) {
+            const double zx = (xs[i] - c.cx) * c.s, zy = (ys[i] - c.cy) * c.s;
+            double hx = 0.0, hy = 0.0;
+#pragma unroll
+            for (int k = P - 1; k >= 0; --k) {     // terms >= p are zero
+                const cd t = lsh[k];
+                const double nx = hx * zx - hy * zy + t.x;
+                hy = hx * zy + hy * zx + t.y;
+                hx = nx;
+            }
+            accx += hx * c.s;
+            accy += hy * c.s;
+        }
+        const uint32_t o = perm[i];
+        u[o] = accy * kInv2Pi;
+        v[o] = accx * kInv2Pi;
+    }
 }
 
 template <int P, int WAVES>

@@ -153,6 +153,26 @@ def test_fp64_parameter_grid(n, L, p, sigma, seed):
     assert oracle.rel_l2(u, v, uo, vo) < FP64_TOL
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_quad_pairs(precision):
+    """The near field inside a 2 x 2 block of sibling leaves is evaluated once
+    per pair of particles, for both (quads of 2..64 particles); a lattice
+    with exactly 64 per quad, a sparse set with empty leaves in some quads,
+    and a set where quads fall on both sides of the 64 limit."""
+    rng = np.random.default_rng(31)
+    m = 64
+    gx, gy = np.meshgrid((np.arange(m) + 0.5) / m, (np.arange(m) + 0.5) / m)
+    lattice = (gx.ravel() + 0.3 / m * rng.uniform(-1, 1, m * m), gy.ravel() + 0.3 / m * rng.uniform(-1, 1, m * m))
+    cases = [(lattice[0], lattice[1], 4), (*workloads.uniform_square(700, 32)[:2], 5),
+             (*workloads.uniform_square(3500, 33)[:2], 4)]
+    for x, y, L in cases:
+        g = rng.uniform(-1.0, 1.0, len(x))
+        u, v, _ = run(x, y, g, 0.01, 17, L, precision=precision)
+        uo, vo = oracle.fmm(x, y, g, 0.01, 17, L)
+        # mixed: the FP32 parts add at most a few 1e-7 on top of the FP64 result
+        assert oracle.rel_l2(u, v, uo, vo) < (FP64_TOL if precision == "fp64" else 5e-7)
+
+
 def test_dense_and_empty_leaves():
     """Leaves with > 64 and > 256 particles (target chunks, staged source
     chunks) next to empty ones."""
