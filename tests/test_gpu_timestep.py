@@ -4,7 +4,9 @@ step captured into a HIP graph and replayed.
 
 * parity with the oracle's time stepping driven by the oracle FMM;
 * graph replays compose exactly (two steps == one step twice);
-* the vorticity centroid is conserved (the FMM's net force vanishes);
+* the vorticity centroid is conserved (the FMM's net force vanishes), and
+  the angular impulse sum(g |z|^2) drifts only at the level of the time
+  discretisation and the expansion's truncation;
 * a Lamb-Oseen vortex sampled on a lattice rotates differentially with the
   angular velocity of its blob-smoothed profile (Section 7.1, eq. 16), and
   the error against that exact motion falls at second order in dt.
@@ -73,6 +75,8 @@ def test_vorticity_centroid_is_conserved():
     cx1, cy1 = np.sum(g * xn) / np.sum(g), np.sum(g * yn) / np.sum(g)
     assert float(np.max(np.hypot(xn - x, yn - y))) > 1e-5
     assert abs(cx1 - cx0) < 1e-13 and abs(cy1 - cy0) < 1e-13, (cx1 - cx0, cy1 - cy0)
+    i0, i1 = np.sum(g * (x * x + y * y)), np.sum(g * (xn * xn + yn * yn))
+    assert abs(i1 - i0) < 1e-8 * abs(i0), (i1 - i0) / i0
 
 
 def _lamb_oseen_error(dt, T=0.02):

@@ -9,7 +9,12 @@ the mathematics fixes rather than against the oracle itself:
 * the vorticity centroid sum(g x) / sum(g) is an exact invariant of any
   Runge-Kutta step whenever sum(g u) = 0, which holds to rounding for the
   direct sum (the kernel is odd) and for the FMM (its far field is
-  antisymmetric), so it is conserved to rounding.
+  antisymmetric), so it is conserved to rounding;
+* the angular impulse I = sum(g |z|^2) has dI/dt = 2 sum(g (x u + y v)),
+  a double sum whose terms cancel pairwise (the kernel is odd and radial),
+  so the direct sum's rate is zero to rounding and the FMM's to its
+  truncation error; the midpoint rule's drift of I over a fixed time falls
+  at least at second order in dt.
 """
 import math
 
@@ -71,3 +76,34 @@ def test_fmm_stepping_follows_direct_stepping():
     xa, ya = oracle.advance_rk2(x, y, g, 0.004, 1e-3, 3, p=24, L=3, velocity="fmm")
     xb, yb = oracle.advance_rk2(x, y, g, 0.004, 1e-3, 3, velocity="direct")
     assert float(np.max(np.hypot(xa - xb, ya - yb))) < 1e-10
+
+
+def _angular_set():
+    rng = np.random.default_rng(7)
+    n = 40
+    x = 0.4 + 0.2 * rng.random(n)
+    y = 0.4 + 0.2 * rng.random(n)
+    g = 0.01 * rng.uniform(-1.0, 1.0, n)
+    return x, y, g
+
+
+def test_angular_impulse_rate_vanishes():
+    x, y, g = _angular_set()
+    u, v = oracle.direct(x, y, g, 0.01)
+    scale = np.sum(np.abs(g) * (np.abs(x * u) + np.abs(y * v)))
+    assert abs(np.sum(g * (x * u + y * v))) < 1e-14 * scale
+    uf, vf = oracle.fmm(x, y, g, 0.01, 20, 2, *oracle.bounding_square(x, y))
+    assert abs(np.sum(g * (x * uf + y * vf))) < 1e-9 * scale
+
+
+def test_angular_impulse_drift_falls_with_dt():
+    x, y, g = _angular_set()
+    i0 = np.sum(g * (x * x + y * y))
+    scale = np.sum(np.abs(g) * (x * x + y * y))
+    drift = []
+    for dt in (4e-3, 2e-3, 1e-3):
+        xn, yn = oracle.advance_rk2(x, y, g, 0.01, dt, int(round(0.4 / dt)), velocity="direct")
+        assert float(np.max(np.hypot(xn - x, yn - y))) > 0.05       # a real rotation of the set
+        drift.append(abs(np.sum(g * (xn * xn + yn * yn)) - i0) / scale)
+    assert drift[0] < 1e-8, drift
+    assert drift[0] / drift[1] > 3.5 and drift[1] / drift[2] > 3.5, drift
