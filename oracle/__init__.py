@@ -72,6 +72,12 @@ def _load():
     lib.oracle_fmm.restype = i64
     lib.oracle_advance_rk2.argtypes = [i64, dp, dp, dp, C.c_double, C.c_int, C.c_int, C.c_int, C.c_double,
                                        C.c_int]
+    lib.oracle_direct_at.argtypes = [i64, dp, dp, dp, C.c_double, i64, dp, dp, dp, dp]
+    lib.oracle_direct_split_at.argtypes = [i64, dp, dp, dp, C.c_double, C.c_int, C.c_double, C.c_double,
+                                           C.c_double, i64, dp, dp, dp, dp]
+    lib.oracle_fmm_at.argtypes = [i64, dp, dp, dp, C.c_double, C.c_int, C.c_int, C.c_double, C.c_double,
+                                  C.c_double, i64, dp, dp, dp, dp]
+    lib.oracle_fmm_at.restype = i64
     lib.oracle_init()
     _lib = lib
     return lib
@@ -281,3 +287,34 @@ def advance_rk2(x, y, g, sigma, dt, steps, p=12, L=4, velocity="fmm"):
                            1 if velocity == "fmm" else 0, float(dt), int(steps))
     return x, y
 
+
+def direct_at(x, y, g, sigma, tx, ty):
+    """Regularised sum of eq. 1 at target points distinct from the sources."""
+    lib = _load()
+    x, y, g, tx, ty = _f64(x), _f64(y), _f64(g), _f64(tx), _f64(ty)
+    m = tx.shape[0]
+    u, v = np.zeros(m), np.zeros(m)
+    lib.oracle_direct_at(x.shape[0], _d(x), _d(y), _d(g), sigma, m, _d(tx), _d(ty), _d(u), _d(v))
+    return u, v
+
+
+def direct_split_at(x, y, g, sigma, L, tx, ty, x0=0.0, y0=0.0, W=1.0):
+    """Split-kernel sum at target points: Gaussian kernel for sources in touching leaves."""
+    lib = _load()
+    x, y, g, tx, ty = _f64(x), _f64(y), _f64(g), _f64(tx), _f64(ty)
+    m = tx.shape[0]
+    u, v = np.zeros(m), np.zeros(m)
+    lib.oracle_direct_split_at(x.shape[0], _d(x), _d(y), _d(g), sigma, L, x0, y0, W, m, _d(tx), _d(ty),
+                               _d(u), _d(v))
+    return u, v
+
+
+def fmm_at(x, y, g, sigma, p, L, tx, ty, x0=0.0, y0=0.0, W=1.0):
+    """FP64 FMM of the particles evaluated at target points; returns (u, v, nbad)."""
+    lib = _load()
+    x, y, g, tx, ty = _f64(x), _f64(y), _f64(g), _f64(tx), _f64(ty)
+    m = tx.shape[0]
+    u, v = np.zeros(m), np.zeros(m)
+    nbad = lib.oracle_fmm_at(x.shape[0], _d(x), _d(y), _d(g), sigma, p, L, x0, y0, W, m, _d(tx), _d(ty),
+                             _d(u), _d(v))
+    return u, v, int(nbad)

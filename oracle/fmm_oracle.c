@@ -222,6 +222,49 @@ void oracle_direct_split(int64_t n, const double* x, const double* y, const doub
     free(ia); free(ib);
 }
 
+/* The regularised sum of eq. 1 at m target points (tx, ty) distinct from
+ * the sources: no pair is excluded, and a target on top of a source gets
+ * nothing from it (the regularised kernel vanishes at zero distance). */
+void oracle_direct_at(int64_t n, const double* x, const double* y, const double* g, double sigma,
+                      int64_t m, const double* tx, const double* ty, double* u, double* v)
+{
+    const double inv_2s2 = 1.0 / (2.0 * sigma * sigma);
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < m; ++t) {
+        double re = 0.0, im = 0.0;
+        for (int64_t j = 0; j < n; ++j)
+            pair_phi(tx[t], ty[t], x[j], y[j], g[j], inv_2s2, 1, &re, &im);
+        u[t] = im / TWO_PI;
+        v[t] = re / TWO_PI;
+    }
+}
+
+/* The split-kernel sum at target points: the regularised kernel for sources
+ * whose leaf touches the target's leaf, the singular kernel otherwise. */
+void oracle_direct_split_at(int64_t n, const double* x, const double* y, const double* g, double sigma,
+                            int L, double x0, double y0, double W, int64_t m, const double* tx,
+                            const double* ty, double* u, double* v)
+{
+    const double inv_2s2 = 1.0 / (2.0 * sigma * sigma);
+    int32_t* ia = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t* ib = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t* ta = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    int32_t* tb = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    oracle_quantize(n, x, y, L, x0, y0, W, ia, ib);
+    oracle_quantize(m, tx, ty, L, x0, y0, W, ta, tb);
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < m; ++t) {
+        double re = 0.0, im = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            int near = abs(ta[t] - ia[j]) <= 1 && abs(tb[t] - ib[j]) <= 1;
+            pair_phi(tx[t], ty[t], x[j], y[j], g[j], inv_2s2, near, &re, &im);
+        }
+        u[t] = im / TWO_PI;
+        v[t] = re / TWO_PI;
+    }
+    free(ia); free(ib); free(ta); free(tb);
+}
+
 /* ---------------------------------------------------------------------- */
 /* Expansion operators: textbook complex expansions of 1/z, p terms        */
 /* (k = 0 .. p-1), unscaled.  Section 2 defines the ME and LE; the          */
@@ -427,10 +470,10 @@ static void box_centre(int l, int a, int b, double x0, double y0, double W,
  * leaves and ancestors.  me_dump / le_dump, if not NULL, receive the
  * multipole and local coefficients of every box (Lambda * p complex values).
  * Returns the out-of-domain particle count. */
-int64_t oracle_fmm(int64_t n, const double* x, const double* y, const double* g,
-                   double sigma, int p, int L, double x0, double y0, double W,
-                   int64_t nt, const int64_t* tgt, double* u, double* v,
-                   double* me_dump, double* le_dump)
+static int64_t fmm_core(int64_t n, const double* x, const double* y, const double* g,
+                        double sigma, int p, int L, double x0, double y0, double W,
+                        int64_t nt, const int64_t* tgt, const double* ptx, const double* pty,
+                        double* u, double* v, double* me_dump, double* le_dump)
 {
     oracle_init();
     const int64_t side = (int64_t)1 << L;
@@ -457,15 +500,23 @@ int64_t oracle_fmm(int64_t n, const double* x, const double* y, const double* g,
     cplx* me = (cplx*)calloc((size_t)(nbox * p), sizeof(cplx));
     cplx* le = (cplx*)calloc((size_t)(nbox * p), sizeof(cplx));
 
+    /* target points (ptx != NULL): their leaves */
+    int32_t* pa = NULL;
+    int32_t* pb = NULL;
+    if (ptx) {
+        pa = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nt > 0 ? nt : 1));
+        pb = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nt > 0 ? nt : 1));
+        nbad += oracle_quantize(nt, ptx, pty, L, x0, y0, W, pa, pb);
+    }
+
     /* which boxes need a local expansion: all, or the targets' leaves and
      * their ancestors */
     char* need = (char*)calloc((size_t)nbox, 1);
-    if (!tgt) {
+    if (!tgt && !ptx) {
         memset(need, 1, (size_t)nbox);
     } else {
         for (int64_t t = 0; t < nt; ++t) {
-            int64_t i = tgt[t];
-            int a = ia[i], b = ib[i];
+            int a = ptx ? pa[t] : ia[tgt[t]], b = ptx ? pb[t] : ib[tgt[t]];
             for (int l = L; l >= 0; --l) {
                 need[level_offset(l) + ((int64_t)b << l) + a] = 1;
                 a >>= 1; b >>= 1;
@@ -545,18 +596,21 @@ int64_t oracle_fmm(int64_t n, const double* x, const double* y, const double* g,
         }
     }
 
-    /* Evaluation: L2P plus the near field with the regularised kernel. */
-    const int64_t count = tgt ? nt : n;
+    /* Evaluation: L2P plus the near field with the regularised kernel, at
+     * particles (a particle skips itself) or at target points (which skip
+     * nothing: a coincident source contributes zero). */
+    const int64_t count = (tgt || ptx) ? nt : n;
     #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t t = 0; t < count; ++t) {
-        int64_t i = tgt ? tgt[t] : t;
-        int a = ia[i], b = ib[i];
+        const int64_t i = ptx ? -1 : (tgt ? tgt[t] : t);
+        const int a = ptx ? pa[t] : ia[i], b = ptx ? pb[t] : ib[i];
+        const double px = ptx ? ptx[t] : x[i], py = ptx ? pty[t] : y[i];
         double phi[2] = {0.0, 0.0};
         if (L >= 2) {
             double cx, cy;
             box_centre(L, a, b, x0, y0, W, &cx, &cy);
             oracle_l2p(p, (const double*)(le + (level_offset(L) + (int64_t)b * side + a) * p),
-                       cx, cy, x[i], y[i], phi);
+                       cx, cy, px, py, phi);
         }
         int32_t na[9], nb[9];
         int nn = oracle_near_list(L, a, b, na, nb);
@@ -565,7 +619,7 @@ int64_t oracle_fmm(int64_t n, const double* x, const double* y, const double* g,
             for (int64_t q = start[leaf]; q < start[leaf + 1]; ++q) {
                 int64_t j = member[q];
                 if (j == i) continue;
-                pair_phi(x[i], y[i], x[j], y[j], g[j], inv_2s2, 1, &phi[0], &phi[1]);
+                pair_phi(px, py, x[j], y[j], g[j], inv_2s2, 1, &phi[0], &phi[1]);
             }
         }
         u[t] = phi[1] / TWO_PI;
@@ -574,8 +628,27 @@ int64_t oracle_fmm(int64_t n, const double* x, const double* y, const double* g,
 
     if (me_dump) memcpy(me_dump, me, sizeof(cplx) * (size_t)(nbox * p));
     if (le_dump) memcpy(le_dump, le, sizeof(cplx) * (size_t)(nbox * p));
-    free(need); free(le); free(me); free(member); free(start); free(ia); free(ib);
+    free(need); free(le); free(me); free(member); free(start); free(ia); free(ib); free(pa); free(pb);
     return nbad;
+}
+
+int64_t oracle_fmm(int64_t n, const double* x, const double* y, const double* g,
+                   double sigma, int p, int L, double x0, double y0, double W,
+                   int64_t nt, const int64_t* tgt, double* u, double* v,
+                   double* me_dump, double* le_dump)
+{
+    return fmm_core(n, x, y, g, sigma, p, L, x0, y0, W, nt, tgt, NULL, NULL, u, v, me_dump, le_dump);
+}
+
+/* The FMM of the particles evaluated at m target points (tx, ty) (eq. 1 with
+ * targets distinct from the sources): each point takes L2P from its leaf and
+ * the regularised near field from the sources of the touching leaves.
+ * Returns the number of sources and targets outside the domain. */
+int64_t oracle_fmm_at(int64_t n, const double* x, const double* y, const double* g,
+                      double sigma, int p, int L, double x0, double y0, double W,
+                      int64_t m, const double* tx, const double* ty, double* u, double* v)
+{
+    return fmm_core(n, x, y, g, sigma, p, L, x0, y0, W, m, NULL, tx, ty, u, v, NULL, NULL);
 }
 
 /* ---------------------------------------------------------------------- */
