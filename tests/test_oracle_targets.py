@@ -34,7 +34,7 @@ def test_one_source_closed_form():
     for t in range(1, len(tx)):
         dx, dy = tx[t] - 0.5, ty[t] - 0.5
         r2 = dx * dx + dy * dy
-        speed = gam / (2 * math.pi * math.sqrt(r2)) * (1 - math.exp(-r2 / (2 * sigma * sigma)))
+        speed = gam / (2 * math.pi * math.sqrt(r2)) * -math.expm1(-r2 / (2 * sigma * sigma))
         # counter-clockwise for gamma > 0: (u, v) = speed (-dy, dx) / r
         assert abs(u[t] + speed * dy / math.sqrt(r2)) < 1e-14 * speed
         assert abs(v[t] - speed * dx / math.sqrt(r2)) < 1e-14 * speed
