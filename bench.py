@@ -278,6 +278,29 @@ def run_time_stepping(wl, args, dev, steps=20):
     return sec
 
 
+def run_points(wl, args, dev, m_side=1024):
+    """The velocity of the workload's particles on an m_side^2 vertex lattice
+    of points (fmm_evaluate_at, FP64, the workload's explicit square)."""
+    import torch
+    import paper_0905_2637_amd as fm
+    x, y, g = dev_arrays(wl, dev)
+    px, py = (torch.as_tensor(a, device=dev) for a in workloads.probe_lattice(m_side))
+    m = int(px.shape[0])
+    u = torch.empty(m, dtype=torch.float64, device=dev)
+    v = torch.empty(m, dtype=torch.float64, device=dev)
+    plan = fm.Plan(wl.n, wl.sigma, wl.p, wl.depth, domain=(wl.x0, wl.y0, wl.width), m_max=m)
+    for _ in range(args.warmup):
+        plan.evaluate_at(x, y, g, px, py, u, v)
+    torch.cuda.synchronize()
+    if plan.out_of_domain():
+        raise SystemExit("particles or points outside the domain")
+    plan.set_timing(True)
+    sec = timed(lambda: plan.evaluate_at(x, y, g, px, py, u, v), args.steps, 0)
+    stages = plan.stats()
+    plan.close()
+    return sec, m, {k: round(vv, 4) for k, vv in stages.items() if k != "evaluations"}
+
+
 # ---------------------------------------------------------------------------
 # CPU oracle leg (the only part of the bench that touches the oracle)
 # ---------------------------------------------------------------------------
@@ -394,6 +417,10 @@ def main() -> int:
                                               "evaluations per step, bounding-square domain)",
                                   "ms_per_step": round(ts * 1e3, 4), "particle_steps_per_s": wl.n / ts,
                                   "step_vs_two_evaluations": ts / (2 * res["sec"])}
+        tp, mp, sp = run_points(workloads.make("C2"), args, dev)
+        forms["points"] = {"workload": "C2 particles, velocity on a 1024 x 1024 vertex lattice of points "
+                                       "(FP64, eq. 1 with targets apart from the sources)",
+                           "ms": round(tp * 1e3, 4), "points_per_s": mp / tp, "stages_ms": sp}
         w4 = workloads.make("C4")
         rb = run_batch(w4, args, dev)
         rb64 = run_batch(w4, args, dev, precision="fp64")

@@ -70,6 +70,8 @@ typedef struct {
     int32_t precision;        /* an fmm_precision value */
     int32_t fp32_fine_levels; /* mixed mode: M2L at levels > L - fp32_fine_levels runs in
                                  FP32 (0 .. L-1); ignored in FP64 mode */
+    int64_t m_max;            /* capacity: largest m passed to fmm_evaluate_at (>= 0, < 2^31);
+                                 0 = no target points.  Single-instance plans only */
 } fmm_params;
 
 /* Number of bytes of device workspace a plan with these parameters needs.
@@ -101,6 +103,30 @@ fmm_status fmm_evaluate(fmm_plan_t plan, int64_t n,
                         const double* d_x, const double* d_y, const double* d_gamma,
                         double* d_u, double* d_v, void* stream);
 
+/* The velocity at m target points distinct from the particles: the sum of
+ * eq. 1 with the regularised kernel (eqs. 5 and 8), evaluated by the same
+ * FMM.  The target points are sorted into the particles' tree; each takes
+ * L2P from its leaf's local expansion and the regularised near field from
+ * the particles of its leaf and the touching leaves (Section 2.2).  A point
+ * on top of a particle gets nothing from it (the regularised kernel
+ * vanishes at zero distance).
+ *   n, d_x, d_y, d_gamma  particles as for fmm_evaluate, 0 <= n <= n_max
+ *   m                     number of target points, 0 <= m <= m_max
+ *   d_tx, d_ty            device FP64 arrays [m]: target positions
+ *   d_u, d_v              device FP64 arrays [m]: velocity at the points,
+ *                         overwritten, in input order (zero when n == 0)
+ * With the bounding-square domain (width <= 0) the square bounds the
+ * particles and the points together.  Points outside an explicit domain or
+ * with a NaN coordinate are clamped into the nearest leaf and counted with
+ * the particles (fmm_get_status).  m == 0 does nothing.  Asynchronous on
+ * `stream`.  FP64 single-instance plans only.  Errors (synchronous):
+ * FMM_E_ARG (NULL plan or pointers, negative counts, a batched plan),
+ * FMM_E_UNSUPPORTED (a mixed-precision plan), FMM_E_CAPACITY (n > n_max or
+ * m > m_max), FMM_E_DEVICE. */
+fmm_status fmm_evaluate_at(fmm_plan_t plan, int64_t n, const double* d_x, const double* d_y,
+                           const double* d_gamma, int64_t m, const double* d_tx, const double* d_ty,
+                           double* d_u, double* d_v, void* stream);
+
 /* Batched form: many independent problems, each evaluated exactly as
  * fmm_evaluate would (the same operation; only the schedule differs),
  * sharing sigma, p, precision and one explicit square [x0, x0+width]^2,
@@ -109,7 +135,8 @@ fmm_status fmm_evaluate(fmm_plan_t plan, int64_t n,
  * particles are concatenated in instance order (instance i owns the
  * counts[i] entries after those of instances 0..i-1); every stage is one
  * launch over the work of all instances.  n_max and depth of prm are
- * ignored; width must be > 0 (else FMM_E_UNSUPPORTED); 1 <= n_inst <= 65536
+ * ignored; m_max must be 0 (else FMM_E_ARG); width must be > 0 (else
+ * FMM_E_UNSUPPORTED); 1 <= n_inst <= 65536
  * and ceil(log2 n_inst) + 2 max(depths) <= 32 (else FMM_E_UNSUPPORTED).
  * counts and depths are host arrays read during the call only. */
 fmm_status fmm_workspace_size_batch(const fmm_params* prm, int32_t n_inst, const int32_t* counts,
@@ -184,7 +211,8 @@ fmm_status fmm_autotune(fmm_plan_t plan, int64_t n, const double* d_x, const dou
 fmm_status fmm_work_estimate(fmm_plan_t plan, double* work, int32_t n_out, int32_t* n_written);
 
 /* Synchronises `stream` and reports the number of particles of the last
- * evaluation that fell outside the explicit domain or had a NaN coordinate.
+ * evaluation (with fmm_evaluate_at: particles and target points) that fell
+ * outside the explicit domain or had a NaN coordinate.
  * Returns FMM_OK if there were none, FMM_E_DOMAIN otherwise. */
 fmm_status fmm_get_status(fmm_plan_t plan, void* stream, int64_t* n_bad);
 
@@ -212,13 +240,17 @@ const char* fmm_stage_name(int32_t stage);
  *   FMM_DUMP_DOMAIN     double [4]      x0, y0, width, 2^L / width
  *   FMM_DUMP_ILIST      int32 [Lambda][27]  interaction list of every box as
  *                       global box ids, -1 padded, as the M2L kernel walks it
+ *   FMM_DUMP_TKEYS, FMM_DUMP_TPERM, FMM_DUMP_TLEAF_START  the same three
+ *                       arrays for the m target points of the last
+ *                       fmm_evaluate_at (empty after other evaluations)
  * Boxes are numbered per level in z-order from (4^l - 1)/3 (the global box
  * numbering of Section 6.2).  Scaled coefficients: a_k = ahat_k * w_l^k and
  * b_l = bhat_l / w_l^(l+1), w_l the box width at level l.  If bytes is too
  * small, *needed is set and FMM_E_CAPACITY returned. */
 enum {
     FMM_DUMP_KEYS = 0, FMM_DUMP_PERM = 1, FMM_DUMP_LEAF_START = 2,
-    FMM_DUMP_ME = 3, FMM_DUMP_LE = 4, FMM_DUMP_DOMAIN = 5, FMM_DUMP_ILIST = 6
+    FMM_DUMP_ME = 3, FMM_DUMP_LE = 4, FMM_DUMP_DOMAIN = 5, FMM_DUMP_ILIST = 6,
+    FMM_DUMP_TKEYS = 7, FMM_DUMP_TPERM = 8, FMM_DUMP_TLEAF_START = 9
 };
 fmm_status fmm_debug_dump(fmm_plan_t plan, int32_t what, void* host_buf,
                           size_t bytes, size_t* needed);

@@ -27,9 +27,10 @@ FMM_PREC_FP64 = 0
 FMM_PREC_MIXED = 1
 
 DUMP_KEYS, DUMP_PERM, DUMP_LEAF_START, DUMP_ME, DUMP_LE, DUMP_DOMAIN, DUMP_ILIST = range(7)
+DUMP_TKEYS, DUMP_TPERM, DUMP_TLEAF_START = range(7, 10)
 
-EXPORTED = ["fmm_workspace_size", "fmm_plan", "fmm_evaluate", "fmm_workspace_size_batch", "fmm_plan_batch",
-            "fmm_evaluate_batch", "fmm_advance_rk2", "fmm_get_status", "fmm_set_timing", "fmm_stats", "fmm_stage_name",
+EXPORTED = ["fmm_workspace_size", "fmm_plan", "fmm_evaluate", "fmm_evaluate_at", "fmm_workspace_size_batch",
+            "fmm_plan_batch", "fmm_evaluate_batch", "fmm_advance_rk2", "fmm_get_status", "fmm_set_timing", "fmm_stats", "fmm_stage_name",
             "fmm_get_tuning", "fmm_set_tuning", "fmm_autotune", "fmm_work_estimate", "fmm_debug_dump", "fmm_destroy",
             "fmm_status_string"]
 
@@ -37,7 +38,7 @@ EXPORTED = ["fmm_workspace_size", "fmm_plan", "fmm_evaluate", "fmm_workspace_siz
 class FmmParams(C.Structure):
     _fields_ = [("n_max", C.c_int64), ("sigma", C.c_double), ("p", C.c_int32), ("depth", C.c_int32),
                 ("x0", C.c_double), ("y0", C.c_double), ("width", C.c_double),
-                ("precision", C.c_int32), ("fp32_fine_levels", C.c_int32)]
+                ("precision", C.c_int32), ("fp32_fine_levels", C.c_int32), ("m_max", C.c_int64)]
 
 
 class FmmError(RuntimeError):
@@ -61,6 +62,7 @@ def load():
     lib.fmm_workspace_size.argtypes = [C.POINTER(FmmParams), C.POINTER(C.c_size_t)]
     lib.fmm_plan.argtypes = [C.POINTER(FmmParams), vp, C.c_size_t, vp, C.POINTER(vp)]
     lib.fmm_evaluate.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp]
+    lib.fmm_evaluate_at.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_int64, vp, vp, vp, vp, vp]
     i32p = C.POINTER(C.c_int32)
     lib.fmm_workspace_size_batch.argtypes = [C.POINTER(FmmParams), C.c_int32, i32p, i32p, C.POINTER(C.c_size_t)]
     lib.fmm_plan_batch.argtypes = [C.POINTER(FmmParams), C.c_int32, i32p, i32p, vp, C.c_size_t, vp, C.POINTER(vp)]
@@ -92,14 +94,14 @@ def status_string(s: int) -> str:
     return load().fmm_status_string(int(s)).decode()
 
 
-def make_params(n_max, sigma, p, depth, domain=(0.0, 0.0, 1.0), precision="fp64", fp32_fine_levels=2):
+def make_params(n_max, sigma, p, depth, domain=(0.0, 0.0, 1.0), precision="fp64", fp32_fine_levels=2, m_max=0):
     if domain is None:
         x0, y0, w = 0.0, 0.0, 0.0
     else:
         x0, y0, w = domain
     prec = {"fp64": FMM_PREC_FP64, "mixed": FMM_PREC_MIXED}[precision]
     return FmmParams(int(n_max), float(sigma), int(p), int(depth), float(x0), float(y0), float(w), prec,
-                     int(fp32_fine_levels if precision == "mixed" else 0))
+                     int(fp32_fine_levels if precision == "mixed" else 0), int(m_max))
 
 
 def workspace_size(prm: FmmParams) -> int:
@@ -206,7 +208,8 @@ class _PlanBase:
         lib.fmm_debug_dump(self._h, what, None, 0, C.byref(need))
         dtype = {DUMP_KEYS: np.uint32, DUMP_PERM: np.uint32, DUMP_LEAF_START: np.int32,
                  DUMP_ME: np.complex128, DUMP_LE: np.complex128, DUMP_DOMAIN: np.float64,
-                 DUMP_ILIST: np.int32}[what]
+                 DUMP_ILIST: np.int32, DUMP_TKEYS: np.uint32, DUMP_TPERM: np.uint32,
+                 DUMP_TLEAF_START: np.int32}[what]
         arr = np.zeros(max(1, need.value // np.dtype(dtype).itemsize), dtype=dtype)
         s = lib.fmm_debug_dump(self._h, what, C.c_void_p(arr.ctypes.data), C.c_size_t(arr.nbytes), C.byref(need))
         if s != FMM_OK:
@@ -236,15 +239,17 @@ class Plan(_PlanBase):
     Parameters follow the paper's problem statement: core size ``sigma``,
     expansion order ``p`` and tree ``depth``; ``domain`` = (x0, y0, width) of
     the square, or None for the particles' bounding square at every call.
+    ``m_max`` > 0 reserves room for that many target points (``evaluate_at``).
     """
 
     def __init__(self, n_max, sigma, p, depth, domain=(0.0, 0.0, 1.0), precision="fp64",
-                 fp32_fine_levels=2, device="cuda"):
+                 fp32_fine_levels=2, device="cuda", m_max=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the FMM runs only on the GPU")
-        self.params = make_params(n_max, sigma, p, depth, domain, precision, fp32_fine_levels)
+        self.params = make_params(n_max, sigma, p, depth, domain, precision, fp32_fine_levels, m_max)
         self.n_max = int(n_max)
+        self.m_max = int(m_max)
         self.depth = int(depth)
         self.p = int(p)
         self.precision = precision
@@ -282,6 +287,26 @@ class Plan(_PlanBase):
             nbad = self.out_of_domain()
             if nbad:
                 raise FmmError(FMM_E_DOMAIN, f"fmm_evaluate: {nbad} particles outside the domain")
+        return u, v
+
+    def evaluate_at(self, x, y, gamma, tx, ty, u=None, v=None, check=False):
+        """Velocity (u, v) at the target points (tx, ty) induced by the
+        particles (eq. 1 with distinct targets); FP64 device tensors."""
+        n, m = int(x.shape[0]), int(tx.shape[0])
+        u, v = self._outputs(tx, u, v)
+        _check_inputs(n, (x, y, gamma))
+        _check_inputs(m, (tx, ty, u, v))
+        s = load().fmm_evaluate_at(self._h, n, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                   C.c_void_p(gamma.data_ptr()), m, C.c_void_p(tx.data_ptr()),
+                                   C.c_void_p(ty.data_ptr()), C.c_void_p(u.data_ptr()), C.c_void_p(v.data_ptr()),
+                                   _stream_handle())
+        if s != FMM_OK:
+            raise FmmError(s, "fmm_evaluate_at")
+        self.last_n = n
+        if check:
+            nbad = self.out_of_domain()
+            if nbad:
+                raise FmmError(FMM_E_DOMAIN, f"fmm_evaluate_at: {nbad} particles or points outside the domain")
         return u, v
 
     def advance_rk2(self, x, y, gamma, dt, steps, scratch=None):

@@ -36,6 +36,7 @@ struct Shape {
     std::vector<int32_t> depth;
     std::vector<int64_t> part_off;       // first particle of every instance
     int64_t n_cap = 0;                   // particle capacity (the total count if batched)
+    int64_t m_cap = 0;                   // target point capacity (single plans; 0: none)
     int Lmax = 0;
     int key_bits = 0;
     int64_t leaf_entries = 0;            // sum (4^L_i + 1)
@@ -108,6 +109,7 @@ fmm_status validate_common(const fmm_params* prm)
     if (!(prm->sigma > 0.0) || !std::isfinite(prm->sigma)) return FMM_E_ARG;
     if (prm->p < 1 || prm->p > kMaxP) return FMM_E_ARG;
     if (prm->precision != FMM_PREC_FP64 && prm->precision != FMM_PREC_MIXED) return FMM_E_ARG;
+    if (prm->m_max < 0 || prm->m_max > int64_t(0x7fffffff)) return FMM_E_ARG;
     if (prm->width > 0.0) {
         if (!std::isfinite(prm->width) || !std::isfinite(prm->x0) || !std::isfinite(prm->y0)) return FMM_E_ARG;
     }
@@ -151,6 +153,7 @@ fmm_status single_shape(const fmm_params* prm, Shape& sh)
     sh.depth = {prm->depth};
     sh.part_off = {0};
     sh.n_cap = prm->n_max;
+    sh.m_cap = prm->m_max;
     return finish_shape(sh);
 }
 
@@ -159,6 +162,7 @@ fmm_status batch_shape(const fmm_params* prm, int32_t n_inst, const int32_t* cou
 {
     if (n_inst < 1 || n_inst > kMaxInstances || !counts || !depths) return FMM_E_ARG;
     if (!(prm->width > 0.0)) return FMM_E_UNSUPPORTED;   // batched instances need the explicit square
+    if (prm->m_max != 0) return FMM_E_ARG;                 // target points: single plans only
     sh.n_inst = n_inst;
     sh.depth.assign(depths, depths + n_inst);
     sh.part_off.resize(n_inst);
@@ -176,6 +180,7 @@ fmm_status batch_shape(const fmm_params* prm, int32_t n_inst, const int32_t* cou
 struct Layout {
     size_t inst, tables, bad_blk, bbox, leaf_start, hist, hist_scan, scan_part;
     size_t key, ksorted, perm, xs, ys, gs, ktmp, itmp, xt, yt, gt, pk, me, le, le_part[2];
+    size_t tkey, tks, tperm, txs, tys, tleaf_start, tbad;
     size_t t_m2m, t_l2l, t_h64, t_h32, t_sin, t_sout;
     size_t total;
 };
@@ -183,7 +188,9 @@ struct Layout {
 Layout make_layout(const Shape& sh, int P, bool mixed)
 {
     const size_t n = size_t(std::max<int64_t>(sh.n_cap, 1));
-    const size_t nblk = size_t(radix_blocks(int64_t(n)));
+    const size_t m = size_t(sh.m_cap);
+    const size_t nm = std::max(n, m);   // the radix temporaries serve both point sets
+    const size_t nblk = size_t(radix_blocks(int64_t(nm)));
     const size_t nhist = size_t(256) * nblk;
     const size_t nscan = (nhist + kScanChunk - 1) / kScanChunk;
     Layout ly{};
@@ -192,7 +199,7 @@ Layout make_layout(const Shape& sh, int P, bool mixed)
     ly.inst = take(sizeof(Inst) * size_t(sh.n_inst));
     ly.tables = take(sizeof(int32_t) * size_t(kMaxLaunches) * size_t(table_ints(sh.n_inst)));
     ly.bad_blk = take(sizeof(int32_t) * nblk);
-    ly.bbox = take(sizeof(double) * 4 * kBBoxBlocks);
+    ly.bbox = take(sizeof(double) * 8 * kBBoxBlocks);
     ly.leaf_start = take(sizeof(int32_t) * size_t(sh.leaf_entries));
     ly.hist = take(sizeof(int32_t) * nhist);
     ly.hist_scan = take(sizeof(int32_t) * (nhist + 1));   // + the grand total
@@ -203,11 +210,18 @@ Layout make_layout(const Shape& sh, int P, bool mixed)
     ly.xs = take(sizeof(double) * n);
     ly.ys = take(sizeof(double) * n);
     ly.gs = take(sizeof(double) * n);
-    ly.ktmp = take(sizeof(uint32_t) * n);
-    ly.itmp = take(sizeof(uint32_t) * n);
-    ly.xt = take(sizeof(double) * n);
-    ly.yt = take(sizeof(double) * n);
+    ly.ktmp = take(sizeof(uint32_t) * nm);
+    ly.itmp = take(sizeof(uint32_t) * nm);
+    ly.xt = take(sizeof(double) * nm);
+    ly.yt = take(sizeof(double) * nm);
     ly.gt = take(sizeof(double) * n);
+    ly.tkey = take(sizeof(uint32_t) * m);
+    ly.tks = take(sizeof(uint32_t) * m);
+    ly.tperm = take(sizeof(uint32_t) * m);
+    ly.txs = take(sizeof(double) * m);
+    ly.tys = take(sizeof(double) * m);
+    ly.tleaf_start = take(m ? sizeof(int32_t) * size_t(sh.leaf_entries) : 0);
+    ly.tbad = take(sizeof(int32_t) * size_t(radix_blocks(int64_t(m))));
     ly.pk = take(mixed ? sizeof(float4) * n : 0);
     // expansions: P >= p coefficients per box (the compiled size), zero-padded
     ly.me = take(sizeof(cd) * size_t(sh.boxes) * P);
@@ -247,6 +261,7 @@ struct fmm_plan_s {
     int32_t* d_tables;
     Buffers buf;
     int64_t last_n;
+    int64_t last_m;                      // target points of the last evaluation (0: none)
     // stage timing
     bool timing;
     bool have_events;
@@ -502,9 +517,11 @@ Work work_of(const fmm_plan_s* pl, const Launch& ln)
     return Work{tb, tb + n + 1, tb + 3 * n + 1};
 }
 
-// Enqueue one whole evaluation on st.
+// Enqueue one whole evaluation on st: velocities at the particles, or, when
+// m > 0, at the m target points (tx, ty), sorted into the same tree.
 hipError_t enqueue_all(fmm_plan_s* pl, int64_t n, const double* x, const double* y, const double* g, double* u,
-                       double* v, hipStream_t st, bool timing, int slot)
+                       double* v, hipStream_t st, bool timing, int slot, int64_t m = 0, const double* tx = nullptr,
+                       const double* ty = nullptr)
 {
     const Buffers& b = pl->buf;
     hipError_t e = hipSuccess;
@@ -513,8 +530,9 @@ hipError_t enqueue_all(fmm_plan_s* pl, int64_t n, const double* x, const double*
     const int P = pl->P, p = pl->prm.p;
 
     mark(ST_TREE);
-    if (pl->auto_domain) chk(launch_domain(b, int(n), x, y, pl->shape.depth[0], st));
+    if (pl->auto_domain) chk(launch_domain(b, int(n), x, y, pl->shape.depth[0], st, int(m), tx, ty));
     chk(launch_tree(b, int(n), x, y, g, pl->shape.key_bits, pl->shape.leaf_entries, pl->mixed, st));
+    if (m > 0) chk(launch_tree_points(b, int(m), tx, ty, pl->shape.key_bits, pl->shape.leaf_entries, st));
     int stage = ST_TREE;
     for (const Launch& ln : pl->launches) {
         const int want = ln.kind == L_UP ? ST_UP : ln.kind == L_M2L ? ST_M2L : ln.kind == L_DOWN ? ST_DOWN : ST_P2P;
@@ -525,7 +543,10 @@ hipError_t enqueue_all(fmm_plan_s* pl, int64_t n, const double* x, const double*
             case L_M2L: chk(launch_m2l(b, P, w, ln.nwg, ln.fp32, pl->tune.m2l_mfma != 0, ln.groups, st)); break;
             case L_DOWN: chk(launch_downward(b, P, w, ln.nwg, st)); break;
             case L_P2P:
-                chk(launch_p2p(b, P, w, ln.nwg, pl->tune.p2p_waves, pl->mixed, pl->prm.sigma, u, v, st));
+                if (m > 0)
+                    chk(launch_p2p_at(b, P, pl->shape.depth[0], pl->prm.sigma, u, v, st));
+                else
+                    chk(launch_p2p(b, P, w, ln.nwg, pl->tune.p2p_waves, pl->mixed, pl->prm.sigma, u, v, st));
                 break;
         }
     }
@@ -565,6 +586,7 @@ fmm_status make_plan(const fmm_params* prm, Shape&& sh, bool batch, void* d_work
     pl->batch = batch;
     pl->shape = std::move(sh);
     pl->last_n = -1;
+    pl->last_m = 0;
     pl->sn = -1;
     char* base = static_cast<char*>(d_workspace);
     Buffers& b = pl->buf;
@@ -590,6 +612,14 @@ fmm_status make_plan(const fmm_params* prm, Shape&& sh, bool batch, void* d_work
     b.yt = reinterpret_cast<double*>(base + ly.yt);
     b.gt = reinterpret_cast<double*>(base + ly.gt);
     b.pk = mixed ? reinterpret_cast<float4*>(base + ly.pk) : nullptr;
+    const bool targets = pl->shape.m_cap > 0;
+    b.tkey = targets ? reinterpret_cast<uint32_t*>(base + ly.tkey) : nullptr;
+    b.tks = targets ? reinterpret_cast<uint32_t*>(base + ly.tks) : nullptr;
+    b.tperm = targets ? reinterpret_cast<uint32_t*>(base + ly.tperm) : nullptr;
+    b.txs = targets ? reinterpret_cast<double*>(base + ly.txs) : nullptr;
+    b.tys = targets ? reinterpret_cast<double*>(base + ly.tys) : nullptr;
+    b.tleaf_start = targets ? reinterpret_cast<int32_t*>(base + ly.tleaf_start) : nullptr;
+    b.tbad = targets ? reinterpret_cast<int32_t*>(base + ly.tbad) : nullptr;
     b.me = reinterpret_cast<cd*>(base + ly.me);
     b.le = reinterpret_cast<cd*>(base + ly.le);
     b.le_part[0] = reinterpret_cast<cd*>(base + ly.le_part[0]);
@@ -738,6 +768,7 @@ fmm_status fmm_evaluate(fmm_plan_t plan, int64_t n, const double* d_x, const dou
     if (n > plan->shape.n_cap) return FMM_E_CAPACITY;
     if (n > 0 && (!d_x || !d_y || !d_gamma || !d_u || !d_v)) return FMM_E_ARG;
     plan->last_n = n;
+    plan->last_m = 0;
     if (n == 0) return FMM_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e = hipSuccess;
@@ -751,6 +782,39 @@ fmm_status fmm_evaluate(fmm_plan_t plan, int64_t n, const double* d_x, const dou
     return e == hipSuccess ? FMM_OK : FMM_E_DEVICE;
 }
 
+fmm_status fmm_evaluate_at(fmm_plan_t plan, int64_t n, const double* d_x, const double* d_y,
+                           const double* d_gamma, int64_t m, const double* d_tx, const double* d_ty, double* d_u,
+                           double* d_v, void* stream)
+{
+    if (!plan || plan->batch) return FMM_E_ARG;
+    if (n < 0 || m < 0) return FMM_E_ARG;
+    if (plan->mixed) return FMM_E_UNSUPPORTED;
+    if (n > plan->shape.n_cap || m > plan->shape.m_cap) return FMM_E_CAPACITY;
+    if (n > 0 && (!d_x || !d_y || !d_gamma)) return FMM_E_ARG;
+    if (m > 0 && (!d_tx || !d_ty || !d_u || !d_v)) return FMM_E_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    plan->last_n = 0;
+    plan->last_m = 0;
+    if (m == 0) return FMM_OK;
+    if (n == 0) {   // no sources: the velocity vanishes everywhere
+        hipError_t e = hipMemsetAsync(d_u, 0, size_t(m) * sizeof(double), st);
+        if (e == hipSuccess) e = hipMemsetAsync(d_v, 0, size_t(m) * sizeof(double), st);
+        return e == hipSuccess ? FMM_OK : FMM_E_DEVICE;
+    }
+    plan->last_n = n;
+    plan->last_m = m;
+    hipError_t e = hipSuccess;
+    const int slot = int(plan->next_slot % kTimingRing);
+    if (plan->timing) {
+        e = harvest(plan, slot);
+        plan->next_slot += 1;
+    }
+    if (e == hipSuccess)
+        e = enqueue_all(plan, n, d_x, d_y, d_gamma, d_u, d_v, st, plan->timing, slot, m, d_tx, d_ty);
+    if (plan->timing && e == hipSuccess) plan->pending[slot] = true;
+    return e == hipSuccess ? FMM_OK : FMM_E_DEVICE;
+}
+
 fmm_status fmm_evaluate_batch(fmm_plan_t plan, const double* d_x, const double* d_y, const double* d_gamma,
                               double* d_u, double* d_v, void* stream)
 {
@@ -758,6 +822,7 @@ fmm_status fmm_evaluate_batch(fmm_plan_t plan, const double* d_x, const double* 
     const int64_t n = plan->shape.n_cap;
     if (n > 0 && (!d_x || !d_y || !d_gamma || !d_u || !d_v)) return FMM_E_ARG;
     plan->last_n = n;
+    plan->last_m = 0;
     if (n == 0) return FMM_OK;
     if (plan->timing) {
         // timed: enqueued eagerly with stage events, no graph
@@ -796,6 +861,7 @@ fmm_status fmm_advance_rk2(fmm_plan_t plan, int64_t n, double* d_x, double* d_y,
     if (n == 0 || n_steps == 0) return FMM_OK;
     if (!d_x || !d_y || !d_gamma || !d_scratch) return FMM_E_ARG;
     plan->last_n = n;
+    plan->last_m = 0;
     double* u = d_scratch;
     double* v = d_scratch + n;
     double* xm = d_scratch + 2 * n;
@@ -834,9 +900,13 @@ fmm_status fmm_get_status(fmm_plan_t plan, void* stream, int64_t* n_bad)
     if (plan->last_n <= 0) return FMM_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const size_t nblk = size_t(radix_blocks(plan->last_n));
-    std::vector<int32_t> per(nblk);
+    const size_t tblk = size_t(radix_blocks(plan->last_m));
+    std::vector<int32_t> per(nblk + tblk);
     if (hipMemcpyAsync(per.data(), plan->buf.bad_blk, nblk * sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
         hipSuccess)
+        return FMM_E_DEVICE;
+    if (tblk > 0 && hipMemcpyAsync(per.data() + nblk, plan->buf.tbad, tblk * sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, st) != hipSuccess)
         return FMM_E_DEVICE;
     if (hipStreamSynchronize(st) != hipSuccess) return FMM_E_DEVICE;
     int64_t v = 0;
@@ -1006,6 +1076,12 @@ fmm_status fmm_debug_dump(fmm_plan_t plan, int32_t what, void* host_buf, size_t 
         case FMM_DUMP_ME: src = plan->buf.me; sz = nbox * prm.p * sizeof(cd); break;   // device rows: stride P
         case FMM_DUMP_LE: src = plan->buf.le; sz = nbox * prm.p * sizeof(cd); break;
         case FMM_DUMP_DOMAIN: src = &plan->buf.inst[0].dom; sz = sizeof(Domain); break;
+        case FMM_DUMP_TKEYS: src = plan->buf.tkey; sz = size_t(plan->last_m) * sizeof(uint32_t); break;
+        case FMM_DUMP_TPERM: src = plan->buf.tperm; sz = size_t(plan->last_m) * sizeof(uint32_t); break;
+        case FMM_DUMP_TLEAF_START:
+            src = plan->buf.tleaf_start;
+            sz = plan->last_m > 0 ? size_t(plan->shape.leaf_entries) * sizeof(int32_t) : 0;
+            break;
         case FMM_DUMP_ILIST:
             if (plan->shape.n_inst != 1) return FMM_E_UNSUPPORTED;
             sz = nbox * 27 * sizeof(int32_t);

@@ -113,7 +113,7 @@ struct Buffers {
     int n_inst;
     int key_shift;         // 2 * (deepest depth): the instance id sits above it
     int32_t* bad_blk;      // [radix blocks] particles outside the domain / NaN, per tile
-    double* bbox;          // [4 * kBBoxBlocks] partial bounding boxes
+    double* bbox;          // [8 * kBBoxBlocks] partial bounding boxes (particles, then target points)
     int32_t* leaf_start;   // [sum (4^L_i + 1)] sorted ranges of every leaf of every instance
     int32_t* hist;         // [256 * radix blocks] digit-major tile histograms
     int32_t* hist_scan;    // [256 * radix blocks + 1] exclusive scan of hist, then the total
@@ -130,6 +130,15 @@ struct Buffers {
     double* yt;
     double* gt;
     float4* pk;            // [n_max] mixed: leaf-relative FP32 (ox, oy, gamma, 0)
+    // target points (fmm_evaluate_at), sorted like the particles; null when
+    // the plan has no target capacity
+    uint32_t* tkey;        // [m_max] leaf key per input point
+    uint32_t* tks;         // [m_max] sorted keys
+    uint32_t* tperm;       // [m_max] sorted position -> input index
+    double* txs;           // [m_max] sorted positions
+    double* tys;
+    int32_t* tleaf_start;  // [4^L + 1] sorted ranges of the points of every leaf
+    int32_t* tbad;         // [radix blocks of m_max] points outside the domain / NaN, per tile
     cd* me;                // [sum Lambda_i * P] scaled multipole coefficients, zero-padded to P
     cd* le;                // [sum Lambda_i * P] scaled local coefficients
     cd* le_part[2];        // [sum Lambda(split)_i * P] partial M2L sums of the split levels
@@ -152,10 +161,15 @@ int64_t radix_blocks(int64_t n);
 
 // ---- launchers (each enqueues on `st` and returns the launch status) -------
 
-// auto domain (single instance): bounding square into inst[0].dom
-hipError_t launch_domain(const Buffers& b, int n, const double* x, const double* y, int L, hipStream_t st);
+// auto domain (single instance): bounding square of the particles and the m
+// target points into inst[0].dom
+hipError_t launch_domain(const Buffers& b, int n, const double* x, const double* y, int L, hipStream_t st,
+                         int m = 0, const double* tx = nullptr, const double* ty = nullptr);
 hipError_t launch_tree(const Buffers& b, int n, const double* x, const double* y, const double* g,
                        int key_bits, int64_t leaf_entries, bool mixed, hipStream_t st);
+// the target points' keys, sort and leaf ranges (single instance)
+hipError_t launch_tree_points(const Buffers& b, int m, const double* tx, const double* ty, int key_bits,
+                              int64_t leaf_entries, hipStream_t st);
 // P2M + M2M of up to three levels per launch; `from_particles` for the first
 hipError_t launch_upward(const Buffers& b, int P, int p, const Work& w, int nwg, bool from_particles,
                          hipStream_t st);
@@ -165,6 +179,8 @@ hipError_t launch_m2l(const Buffers& b, int P, const Work& w, int nwg, bool fp32
 hipError_t launch_downward(const Buffers& b, int P, const Work& w, int nwg, hipStream_t st);   // L2L
 hipError_t launch_p2p(const Buffers& b, int P, const Work& w, int nwg, int waves, bool mixed, double sigma,
                       double* u, double* v, hipStream_t st);
+// near field + L2P at the sorted target points of a single-instance FP64 plan
+hipError_t launch_p2p_at(const Buffers& b, int P, int L, double sigma, double* u, double* v, hipStream_t st);
 hipError_t launch_ilist(const Buffers& b, int L, hipStream_t st);
 // time stepping: (xo, yo) = (x, y) + c (u, v); xo, yo may alias x, y
 hipError_t launch_advance(int64_t n, const double* x, const double* y, const double* u, const double* v, double c,

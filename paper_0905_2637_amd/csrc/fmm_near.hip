@@ -165,8 +165,11 @@ constexpr int kStageSlots = kNearStage / 64;   // staged sources per lane and ch
 // le_sh: this wavefront's LDS copy of the leaf's local expansion (P terms).
 // sink != nullptr: the near-field sums (physical units, before the 1 / 2 pi)
 // go to sink[i] for target i of the leaf instead of being finished here.
+// tx, ty: the targets' sorted positions (the particles' own for the particle
+// sum), perm: their sorted position -> output index.
 template <int P, bool MIXED, int R>
 __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* stage_raw, cd* le_sh, int has_far,
+                                              const double* __restrict__ tx, const double* __restrict__ ty,
                                               const double* __restrict__ xs, const double* __restrict__ ys,
                                               const double* __restrict__ gs, const float4* __restrict__ pk,
                                               const uint32_t* __restrict__ perm, const cd* __restrict__ le_leaf,
@@ -201,7 +204,7 @@ __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* 
                     const float4 t = pk[c.s0 + i];
                     oxi[r] = t.x; oyi[r] = t.y;
                 } else {
-                    xi[r] = xs[c.s0 + i]; yi[r] = ys[c.s0 + i];
+                    xi[r] = tx[c.s0 + i]; yi[r] = ty[c.s0 + i];
                 }
             }
         }
@@ -213,7 +216,7 @@ __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* 
         double px = 0.0, py = 0.0;
         if (own && !sink) {
             o = perm[c.s0 + il];
-            if constexpr (MIXED) { px = xs[c.s0 + il]; py = ys[c.s0 + il]; }
+            if constexpr (MIXED) { px = tx[c.s0 + il]; py = ty[c.s0 + il]; }
         }
 
         for (int base = 0; base < tot; base += kNearStage) {
@@ -353,17 +356,18 @@ __device__ __forceinline__ void make_ctx(LeafCtx& c, uint32_t m, int L, const in
 // per lane (fewer slices to combine)
 template <int P, bool MIXED>
 __device__ __forceinline__ void leaf_dispatch(const LeafCtx& c, int lane, void* st, cd* lsh, int has_far,
+                                              const double* __restrict__ tx, const double* __restrict__ ty,
                                               const double* __restrict__ xs, const double* __restrict__ ys,
                                               const double* __restrict__ gs, const float4* __restrict__ pk,
                                               const uint32_t* __restrict__ perm, const cd* __restrict__ le_leaf,
                                               cd* sink, double* __restrict__ u, double* __restrict__ v)
 {
     if (c.lgT == 6)
-        leaf_near_far<P, MIXED, 4>(c, lane, st, lsh, has_far, xs, ys, gs, pk, perm, le_leaf, sink, u, v);
+        leaf_near_far<P, MIXED, 4>(c, lane, st, lsh, has_far, tx, ty, xs, ys, gs, pk, perm, le_leaf, sink, u, v);
     else if (c.lgT == 5)
-        leaf_near_far<P, MIXED, 2>(c, lane, st, lsh, has_far, xs, ys, gs, pk, perm, le_leaf, sink, u, v);
+        leaf_near_far<P, MIXED, 2>(c, lane, st, lsh, has_far, tx, ty, xs, ys, gs, pk, perm, le_leaf, sink, u, v);
     else
-        leaf_near_far<P, MIXED, 1>(c, lane, st, lsh, has_far, xs, ys, gs, pk, perm, le_leaf, sink, u, v);
+        leaf_near_far<P, MIXED, 1>(c, lane, st, lsh, has_far, tx, ty, xs, ys, gs, pk, perm, le_leaf, sink, u, v);
 }
 
 // Quads of sibling leaves: the four leaves of a 2 x 2 block touch each other,
@@ -448,7 +452,7 @@ k_p2p_l2p(Work wk, int n_inst, const Inst* __restrict__ inst, const int32_t* __r
         LeafCtx c;
         make_ctx(c, uint32_t(mm), L, leaf_start, d, inv2s2, false);
         if (c.nt == 0) return;
-        leaf_dispatch<P, MIXED>(c, lane, st, lsh, has_far, xs, ys, gs, pk, perm, le_leaf, nullptr, u, v);
+        leaf_dispatch<P, MIXED>(c, lane, st, lsh, has_far, xs, ys, xs, ys, gs, pk, perm, le_leaf, nullptr, u, v);
         return;
     }
 
@@ -463,7 +467,8 @@ k_p2p_l2p(Work wk, int n_inst, const Inst* __restrict__ inst, const int32_t* __r
     __syncthreads();
     // the leaf's targets against the neighbours outside the quad
     if (c.nt > 0)
-        leaf_dispatch<P, MIXED>(c, lane, st, lsh, 0, xs, ys, gs, pk, perm, le_leaf, part_sh[0] + (c.s0 - sq), u, v);
+        leaf_dispatch<P, MIXED>(c, lane, st, lsh, 0, xs, ys, xs, ys, gs, pk, perm, le_leaf, part_sh[0] + (c.s0 - sq),
+                                u, v);
     // this wavefront's share of the pairs inside the quad
     double ix, iy;
     quad_pairs(qsh, lane, wv, -inv2s2, ix, iy);
@@ -501,6 +506,35 @@ k_p2p_l2p(Work wk, int n_inst, const Inst* __restrict__ inst, const int32_t* __r
     }
 }
 
+// Target points (eq. 1 with targets distinct from the sources): one
+// wavefront per leaf of the points' tree, its points against the particles
+// of the 3 x 3 neighbourhood, plus L2P from the leaf's local expansion.
+// Single instance, FP64.
+template <int P>
+__global__ void __launch_bounds__(256)
+k_p2p_at(int L, const Inst* __restrict__ inst, const int32_t* __restrict__ leaf_start,
+         const int32_t* __restrict__ tleaf_start, const double* __restrict__ xs, const double* __restrict__ ys,
+         const double* __restrict__ gs, const double* __restrict__ txs, const double* __restrict__ tys,
+         const uint32_t* __restrict__ tperm, const cd* __restrict__ le_all, double inv2s2, double* __restrict__ u,
+         double* __restrict__ v)
+{
+    __shared__ Src64 stage_all[4][kNearStage];
+    __shared__ cd le_all_sh[4][P];
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t mm = int64_t(blockIdx.x) * 4 + wv;
+    if (mm >= (int64_t(1) << (2 * L))) return;
+    LeafCtx c;
+    make_ctx(c, uint32_t(mm), L, leaf_start, inst[0].dom, inv2s2, false);   // the particles around the leaf
+    c.s0 = tleaf_start[mm];                                                    // and the leaf's points
+    c.nt = tleaf_start[mm + 1] - c.s0;
+    if (c.nt == 0) return;
+    c.lgT = c.nt >= 64 ? 6 : (c.nt <= 1 ? 0 : 32 - __clz(c.nt - 1));
+    const cd* le_leaf = le_all + (inst[0].box_off + level_offset(L)) * P;
+    leaf_dispatch<P, false>(c, lane, stage_all[wv], le_all_sh[wv], L >= 2 ? 1 : 0, txs, tys, xs, ys, gs, nullptr,
+                            tperm, le_leaf, nullptr, u, v);
+}
+
 template <int P, int WAVES>
 hipError_t p2p_impl(const Buffers& b, const Work& w, int nwg, bool mixed, double sigma, double* u, double* v,
                     hipStream_t st)
@@ -528,6 +562,28 @@ hipError_t p2p_waves(const Buffers& b, const Work& w, int nwg, int waves, bool m
 }
 
 }  // namespace
+
+hipError_t launch_p2p_at(const Buffers& b, int P, int L, double sigma, double* u, double* v, hipStream_t st)
+{
+    const double inv2s2 = 1.0 / (2.0 * sigma * sigma);
+    const dim3 grid{unsigned(((int64_t(1) << (2 * L)) + 3) / 4)};
+#define FMM_AT_CASE(PP)                                                                                          \
+    case PP:                                                                                                     \
+        hipLaunchKernelGGL(k_p2p_at<PP>, grid, dim3(256), 0, st, L, b.inst, b.leaf_start, b.tleaf_start, b.xs, \
+                           b.ys, b.gs, b.txs, b.tys, b.tperm, b.le, inv2s2, u, v);                               \
+        return hipGetLastError();
+    switch (P) {
+        FMM_AT_CASE(8)
+        FMM_AT_CASE(12)
+        FMM_AT_CASE(16)
+        FMM_AT_CASE(17)
+        FMM_AT_CASE(20)
+        FMM_AT_CASE(24)
+        FMM_AT_CASE(32)
+        default: return hipErrorInvalidValue;
+    }
+#undef FMM_AT_CASE
+}
 
 hipError_t launch_p2p(const Buffers& b, int P, const Work& w, int nwg, int waves, bool mixed, double sigma,
                       double* u, double* v, hipStream_t st)

@@ -361,7 +361,7 @@ k_rscatter(int n, const uint32_t* __restrict__ kin, const uint32_t* __restrict__
         vr[r] = iin ? iin[i] : uint32_t(i);
         xr[r] = xin[i];
         yr[r] = yin[i];
-        gr[r] = gin[i];
+        gr[r] = gin ? gin[i] : 0.0;
     };
     if constexpr (kUpFront) {
 #pragma unroll
@@ -465,6 +465,7 @@ k_rscatter(int n, const uint32_t* __restrict__ kin, const uint32_t* __restrict__
         ys_[r] = sv[r * kScatterThreads + tid];
         if (dst[r] >= 0) out.y[dst[r]] = ys_[r];
     }
+    if (!out.g) return;                    // point records (target points) carry no circulation
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kPerThread; ++r)
@@ -493,12 +494,12 @@ k_copy_one_leaf(int n, const double* __restrict__ x, const double* __restrict__ 
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double xv = x[i], yv = y[i], gv = g[i];
+    const double xv = x[i], yv = y[i], gv = g ? g[i] : 0.0;
     out.k[i] = 0u;
     out.idx[i] = uint32_t(i);
     out.x[i] = xv;
     out.y[i] = yv;
-    out.g[i] = gv;
+    if (out.g) out.g[i] = gv;
     if (pk) {
         const Domain dm = inst[0].dom;
         const double cx = dm.x0 + 0.5 * dm.W, cy = dm.y0 + 0.5 * dm.W;
@@ -556,10 +557,14 @@ inline unsigned blocks_for(int64_t n, int bs) { return unsigned((n + bs - 1) / b
 
 }  // namespace
 
-hipError_t launch_domain(const Buffers& b, int n, const double* x, const double* y, int L, hipStream_t st)
+hipError_t launch_domain(const Buffers& b, int n, const double* x, const double* y, int L, hipStream_t st,
+                         int m, const double* tx, const double* ty)
 {
     hipLaunchKernelGGL(k_bbox_partial, dim3(kBBoxBlocks), dim3(256), 0, st, n, x, y, b.bbox);
-    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, kBBoxBlocks, b.bbox, L, &b.inst[0].dom);
+    if (m > 0)   // target points: their partial boxes follow the particles'
+        hipLaunchKernelGGL(k_bbox_partial, dim3(kBBoxBlocks), dim3(256), 0, st, m, tx, ty, b.bbox + 4 * kBBoxBlocks);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, m > 0 ? 2 * kBBoxBlocks : kBBoxBlocks, b.bbox, L,
+                       &b.inst[0].dom);
     return hipGetLastError();
 }
 
@@ -585,27 +590,30 @@ void scan_table(const Buffers& b, int64_t m, hipStream_t st)
 
 }  // namespace
 
-hipError_t launch_tree(const Buffers& b, int n, const double* x, const double* y, const double* g,
-                       int key_bits, int64_t leaf_entries, bool mixed, hipStream_t st)
+namespace {
+
+// Keys, sort and leaf ranges of one point set: records (key, index, x, y and,
+// when g != nullptr, gamma), final arrays in fin, leaf ranges in leaf_start.
+void sort_points(const Buffers& b, int n, const double* x, const double* y, const double* g, uint32_t* key,
+                 int32_t* bad_blk, const Records& fin, float4* pk, int32_t* leaf_start, int key_bits,
+                 int64_t leaf_entries, hipStream_t st)
 {
     const int nblk = int(radix_blocks(n));
     const int64_t m = int64_t(kRadixBins) * nblk;
-    float4* pk = mixed ? b.pk : nullptr;
-    const Records fin{b.ksorted, b.perm, b.xs, b.ys, b.gs};
-    const Records tmp{b.ktmp, b.itmp, b.xt, b.yt, b.gt};
+    const Records tmp{b.ktmp, b.itmp, b.xt, b.yt, g ? b.gt : nullptr};
     const bool wide = FMM_TREE_TPB == 1024 || (FMM_TREE_TPB == 0 && nblk <= kWideTilesMax);
     if (wide)
         hipLaunchKernelGGL(k_rhist_keys<1024>, dim3(nblk), dim3(1024), 0, st, n, x, y, b.inst, b.n_inst,
-                           b.key_shift, nblk, b.key, b.hist, b.bad_blk);
+                           b.key_shift, nblk, key, b.hist, bad_blk);
     else
         hipLaunchKernelGGL(k_rhist_keys<256>, dim3(nblk), dim3(256), 0, st, n, x, y, b.inst, b.n_inst,
-                           b.key_shift, nblk, b.key, b.hist, b.bad_blk);
+                           b.key_shift, nblk, key, b.hist, bad_blk);
     const int npass = radix_passes(key_bits);
     if (npass == 0) {
         hipLaunchKernelGGL(k_copy_one_leaf, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, x, y, g, fin, pk, b.inst);
     } else {
         // the last pass writes the final arrays, the others alternate with tmp
-        const uint32_t* kin = b.key;
+        const uint32_t* kin = key;
         const uint32_t* iin = nullptr;
         const double *xin = x, *yin = y, *gin = g;
         for (int pass = 0; pass < npass; ++pass) {
@@ -631,7 +639,25 @@ hipError_t launch_tree(const Buffers& b, int n, const double* x, const double* y
         }
     }
     hipLaunchKernelGGL(k_bounds, dim3(blocks_for(int64_t(n) + 1, 256 * kBoundsRounds)), dim3(256), 0, st, n,
-                       leaf_entries, b.ksorted, b.inst, b.n_inst, b.key_shift, b.leaf_start);
+                       leaf_entries, fin.k, b.inst, b.n_inst, b.key_shift, leaf_start);
+}
+
+}  // namespace
+
+hipError_t launch_tree(const Buffers& b, int n, const double* x, const double* y, const double* g,
+                       int key_bits, int64_t leaf_entries, bool mixed, hipStream_t st)
+{
+    const Records fin{b.ksorted, b.perm, b.xs, b.ys, b.gs};
+    sort_points(b, n, x, y, g, b.key, b.bad_blk, fin, mixed ? b.pk : nullptr, b.leaf_start, key_bits,
+                leaf_entries, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_tree_points(const Buffers& b, int m, const double* tx, const double* ty, int key_bits,
+                              int64_t leaf_entries, hipStream_t st)
+{
+    const Records fin{b.tks, b.tperm, b.txs, b.tys, nullptr};
+    sort_points(b, m, tx, ty, nullptr, b.tkey, b.tbad, fin, nullptr, b.tleaf_start, key_bits, leaf_entries, st);
     return hipGetLastError();
 }
 

@@ -168,6 +168,16 @@ def make(name: str) -> Workload:
     raise KeyError(name)
 
 
+def probe_lattice(m: int, lo: float = 0.0, hi: float = 1.0) -> tuple[np.ndarray, np.ndarray]:
+    """m x m vertex lattice lo + (i, j) (hi - lo) / m, i, j = 0 .. m-1, row by
+    row: evaluation points for the velocity field (with m a multiple of the
+    leaf count per side, every leaf edge carries points)."""
+    h = (hi - lo) / m
+    c = lo + np.arange(m, dtype=np.float64) * h
+    X, Y = np.meshgrid(c, c, indexing="xy")
+    return X.ravel().copy(), Y.ravel().copy()
+
+
 def sample_targets(n: int, m: int, seed: int) -> np.ndarray:
     """Seeded target subset (sorted int64 indices) for sampled error checks."""
     if m >= n:
