@@ -7,6 +7,9 @@ no code, header, table or helper with the oracle.
 The arithmetic lives in ``fmm_oracle.c`` (see its header for the passages of
 the paper each function follows); this module only marshals numpy arrays
 through ctypes.  ``build()`` compiles the C file with gcc.
+
+Every sum and FMM takes the Gaussian core size ``sigma``; ``sigma = 0``
+selects the singular kernel of eq. 7 (point vortices) for every pair.
 """
 from __future__ import annotations
 

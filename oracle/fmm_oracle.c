@@ -28,6 +28,11 @@
  * so that the velocity of eq. 9 is u = Im(phi) / (2 pi), v = Re(phi) / (2 pi).
  * A pair at zero distance contributes nothing (the kernel of eq. 8 tends to 0).
  *
+ * sigma = 0 selects the singular kernel of eq. 7 (point vortices) for every
+ * pair, near ones included: c_ij = 1, the sigma -> 0 limit of the Gaussian
+ * core.  A pair at zero distance still contributes nothing (the singular
+ * kernel has no value there; the sums leave such pairs out).
+ *
  * Parity status: every function here is pinned by the CPU tests (closed
  * forms, invariants, operator identities, brute force); none is unpinned.
  *
@@ -176,19 +181,24 @@ static void pair_phi(double xi, double yi, double xj, double yj, double gj,
     *im -= q * dy;
 }
 
-/* Regularised direct sum, eq. 9: u_i = sum_{j != i} gamma_j K_sigma(x_i - x_j).
- * tgt == NULL evaluates every particle (nt must equal n). */
+/* 1/(2 sigma^2) of the Gaussian core; 0 (unused) for the singular kernel. */
+static double core_factor(double sigma) { return sigma > 0.0 ? 1.0 / (2.0 * sigma * sigma) : 0.0; }
+
+/* Regularised direct sum, eq. 9: u_i = sum_{j != i} gamma_j K_sigma(x_i - x_j)
+ * (sigma = 0: the singular sum of eq. 7 over every pair j != i at nonzero
+ * distance).  tgt == NULL evaluates every particle (nt must equal n). */
 void oracle_direct(int64_t n, const double* x, const double* y, const double* g,
                    double sigma, int64_t nt, const int64_t* tgt, double* u, double* v)
 {
-    const double inv_2s2 = 1.0 / (2.0 * sigma * sigma);
+    const double inv_2s2 = core_factor(sigma);
+    const int reg = sigma > 0.0;   /* 0: singular kernel everywhere */
     #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t t = 0; t < nt; ++t) {
         int64_t i = tgt ? tgt[t] : t;
         double re = 0.0, im = 0.0;
         for (int64_t j = 0; j < n; ++j) {
             if (j == i) continue;
-            pair_phi(x[i], y[i], x[j], y[j], g[j], inv_2s2, 1, &re, &im);
+            pair_phi(x[i], y[i], x[j], y[j], g[j], inv_2s2, reg, &re, &im);
         }
         u[t] = im / TWO_PI;
         v[t] = re / TWO_PI;
@@ -203,7 +213,8 @@ void oracle_direct_split(int64_t n, const double* x, const double* y, const doub
                          double sigma, int L, double x0, double y0, double W,
                          int64_t nt, const int64_t* tgt, double* u, double* v)
 {
-    const double inv_2s2 = 1.0 / (2.0 * sigma * sigma);
+    const double inv_2s2 = core_factor(sigma);
+    const int reg = sigma > 0.0;   /* 0: singular kernel everywhere */
     int32_t* ia = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     int32_t* ib = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     oracle_quantize(n, x, y, L, x0, y0, W, ia, ib);
@@ -214,7 +225,7 @@ void oracle_direct_split(int64_t n, const double* x, const double* y, const doub
         for (int64_t j = 0; j < n; ++j) {
             if (j == i) continue;
             int near = abs(ia[i] - ia[j]) <= 1 && abs(ib[i] - ib[j]) <= 1;
-            pair_phi(x[i], y[i], x[j], y[j], g[j], inv_2s2, near, &re, &im);
+            pair_phi(x[i], y[i], x[j], y[j], g[j], inv_2s2, reg && near, &re, &im);
         }
         u[t] = im / TWO_PI;
         v[t] = re / TWO_PI;
@@ -228,12 +239,13 @@ void oracle_direct_split(int64_t n, const double* x, const double* y, const doub
 void oracle_direct_at(int64_t n, const double* x, const double* y, const double* g, double sigma,
                       int64_t m, const double* tx, const double* ty, double* u, double* v)
 {
-    const double inv_2s2 = 1.0 / (2.0 * sigma * sigma);
+    const double inv_2s2 = core_factor(sigma);
+    const int reg = sigma > 0.0;   /* 0: singular kernel everywhere */
     #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t t = 0; t < m; ++t) {
         double re = 0.0, im = 0.0;
         for (int64_t j = 0; j < n; ++j)
-            pair_phi(tx[t], ty[t], x[j], y[j], g[j], inv_2s2, 1, &re, &im);
+            pair_phi(tx[t], ty[t], x[j], y[j], g[j], inv_2s2, reg, &re, &im);
         u[t] = im / TWO_PI;
         v[t] = re / TWO_PI;
     }
@@ -245,7 +257,8 @@ void oracle_direct_split_at(int64_t n, const double* x, const double* y, const d
                             int L, double x0, double y0, double W, int64_t m, const double* tx,
                             const double* ty, double* u, double* v)
 {
-    const double inv_2s2 = 1.0 / (2.0 * sigma * sigma);
+    const double inv_2s2 = core_factor(sigma);
+    const int reg = sigma > 0.0;   /* 0: singular kernel everywhere */
     int32_t* ia = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     int32_t* ib = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     int32_t* ta = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
@@ -257,7 +270,7 @@ void oracle_direct_split_at(int64_t n, const double* x, const double* y, const d
         double re = 0.0, im = 0.0;
         for (int64_t j = 0; j < n; ++j) {
             int near = abs(ta[t] - ia[j]) <= 1 && abs(tb[t] - ib[j]) <= 1;
-            pair_phi(tx[t], ty[t], x[j], y[j], g[j], inv_2s2, near, &re, &im);
+            pair_phi(tx[t], ty[t], x[j], y[j], g[j], inv_2s2, reg && near, &re, &im);
         }
         u[t] = im / TWO_PI;
         v[t] = re / TWO_PI;
@@ -479,7 +492,8 @@ static int64_t fmm_core(int64_t n, const double* x, const double* y, const doubl
     const int64_t side = (int64_t)1 << L;
     const int64_t nleaf = side * side;
     const int64_t nbox = level_offset(L + 1);
-    const double inv_2s2 = 1.0 / (2.0 * sigma * sigma);
+    const double inv_2s2 = core_factor(sigma);
+    const int reg = sigma > 0.0;   /* 0: singular kernel everywhere */
 
     int32_t* ia = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     int32_t* ib = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
@@ -619,7 +633,7 @@ static int64_t fmm_core(int64_t n, const double* x, const double* y, const doubl
             for (int64_t q = start[leaf]; q < start[leaf + 1]; ++q) {
                 int64_t j = member[q];
                 if (j == i) continue;
-                pair_phi(px, py, x[j], y[j], g[j], inv_2s2, 1, &phi[0], &phi[1]);
+                pair_phi(px, py, x[j], y[j], g[j], inv_2s2, reg, &phi[0], &phi[1]);
             }
         }
         u[t] = phi[1] / TWO_PI;
