@@ -57,12 +57,23 @@ typedef enum {
     FMM_PREC_MIXED = 1       /* FP32 near field and fine-level M2L; FP64 shifts and coarse M2L */
 } fmm_precision;
 
+/* Pair kernel of the near field.  The far field always uses the expansions
+ * of the singular kernel (Section 3, text after eq. 9), so the choice only
+ * changes the direct sum over touching leaves.  Section 6.1 templates the
+ * evaluator over its kernel for exactly this kind of substitution. */
+typedef enum {
+    FMM_KERNEL_GAUSSIAN = 0, /* regularised Biot-Savart kernel of eq. 8, core sigma > 0 */
+    FMM_KERNEL_SINGULAR = 1  /* singular Biot-Savart kernel of eq. 7 (point vortices); sigma is
+                                ignored; a pair at zero distance contributes nothing */
+} fmm_kernel;
+
 /* Problem parameters, following the paper's problem statement: positions
  * and circulations (eq. 9), one core size sigma for all particles
  * (Section 7.1), expansion order p and tree level (Section 7.2). */
 typedef struct {
     int64_t n_max;            /* capacity: largest n passed to fmm_evaluate (>= 0, < 2^31) */
-    double  sigma;            /* Gaussian core size, > 0 (eqs. 5 and 8) */
+    double  sigma;            /* Gaussian core size, > 0 (eqs. 5 and 8); ignored by the singular
+                                 kernel */
     int32_t p;                /* number of expansion terms, 1 <= p <= 32 (<= 22 in mixed mode) */
     int32_t depth;            /* leaf level L, 0 <= L <= 13; levels 0..L, 4^L leaves */
     double  x0, y0, width;    /* domain [x0, x0+width]^2; width <= 0 selects the bounding
@@ -72,6 +83,7 @@ typedef struct {
                                  FP32 (0 .. L-1); ignored in FP64 mode */
     int64_t m_max;            /* capacity: largest m passed to fmm_evaluate_at (>= 0, < 2^31);
                                  0 = no target points.  Single-instance plans only */
+    int32_t kernel;           /* an fmm_kernel value (0: the Gaussian kernel of eq. 8) */
 } fmm_params;
 
 /* Number of bytes of device workspace a plan with these parameters needs.

@@ -22,6 +22,8 @@ FMM_E_DOMAIN = -3
 FMM_E_NOMEM = -4
 FMM_E_DEVICE = -5
 FMM_E_UNSUPPORTED = -6
+FMM_KERNEL_GAUSSIAN, FMM_KERNEL_SINGULAR = 0, 1
+KERNELS = {"gaussian": FMM_KERNEL_GAUSSIAN, "singular": FMM_KERNEL_SINGULAR}
 
 FMM_PREC_FP64 = 0
 FMM_PREC_MIXED = 1
@@ -38,7 +40,8 @@ EXPORTED = ["fmm_workspace_size", "fmm_plan", "fmm_evaluate", "fmm_evaluate_at",
 class FmmParams(C.Structure):
     _fields_ = [("n_max", C.c_int64), ("sigma", C.c_double), ("p", C.c_int32), ("depth", C.c_int32),
                 ("x0", C.c_double), ("y0", C.c_double), ("width", C.c_double),
-                ("precision", C.c_int32), ("fp32_fine_levels", C.c_int32), ("m_max", C.c_int64)]
+                ("precision", C.c_int32), ("fp32_fine_levels", C.c_int32), ("m_max", C.c_int64),
+                ("kernel", C.c_int32)]
 
 
 class FmmError(RuntimeError):
@@ -94,14 +97,15 @@ def status_string(s: int) -> str:
     return load().fmm_status_string(int(s)).decode()
 
 
-def make_params(n_max, sigma, p, depth, domain=(0.0, 0.0, 1.0), precision="fp64", fp32_fine_levels=2, m_max=0):
+def make_params(n_max, sigma, p, depth, domain=(0.0, 0.0, 1.0), precision="fp64", fp32_fine_levels=2, m_max=0,
+                kernel="gaussian"):
     if domain is None:
         x0, y0, w = 0.0, 0.0, 0.0
     else:
         x0, y0, w = domain
     prec = {"fp64": FMM_PREC_FP64, "mixed": FMM_PREC_MIXED}[precision]
     return FmmParams(int(n_max), float(sigma), int(p), int(depth), float(x0), float(y0), float(w), prec,
-                     int(fp32_fine_levels if precision == "mixed" else 0), int(m_max))
+                     int(fp32_fine_levels if precision == "mixed" else 0), int(m_max), KERNELS[kernel])
 
 
 def workspace_size(prm: FmmParams) -> int:
@@ -240,14 +244,16 @@ class Plan(_PlanBase):
     expansion order ``p`` and tree ``depth``; ``domain`` = (x0, y0, width) of
     the square, or None for the particles' bounding square at every call.
     ``m_max`` > 0 reserves room for that many target points (``evaluate_at``).
+    ``kernel`` = "gaussian" (eq. 8, core ``sigma``) or "singular" (eq. 7,
+    point vortices; ``sigma`` ignored) for the near field.
     """
 
     def __init__(self, n_max, sigma, p, depth, domain=(0.0, 0.0, 1.0), precision="fp64",
-                 fp32_fine_levels=2, device="cuda", m_max=0):
+                 fp32_fine_levels=2, device="cuda", m_max=0, kernel="gaussian"):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the FMM runs only on the GPU")
-        self.params = make_params(n_max, sigma, p, depth, domain, precision, fp32_fine_levels, m_max)
+        self.params = make_params(n_max, sigma, p, depth, domain, precision, fp32_fine_levels, m_max, kernel)
         self.n_max = int(n_max)
         self.m_max = int(m_max)
         self.depth = int(depth)
@@ -345,12 +351,12 @@ class BatchPlan(_PlanBase):
 
     ``counts[i]`` particles of instance i follow those of instances 0..i-1
     in the concatenated input arrays; instance i uses tree depth
-    ``depths[i]``.  All instances share ``sigma``, ``p``, the precision and
-    the explicit square ``domain`` = (x0, y0, width).
+    ``depths[i]``.  All instances share ``sigma``, ``p``, the precision, the
+    near-field ``kernel`` and the explicit square ``domain`` = (x0, y0, width).
     """
 
     def __init__(self, counts, depths, sigma, p, domain=(0.0, 0.0, 1.0), precision="fp64",
-                 fp32_fine_levels=2, device="cuda"):
+                 fp32_fine_levels=2, device="cuda", kernel="gaussian"):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the FMM runs only on the GPU")
@@ -361,7 +367,8 @@ class BatchPlan(_PlanBase):
         self.n = sum(self.counts)
         self.p = int(p)
         self.precision = precision
-        self.params = make_params(self.n, sigma, p, max(self.depths), domain, precision, fp32_fine_levels)
+        self.params = make_params(self.n, sigma, p, max(self.depths), domain, precision, fp32_fine_levels,
+                                  kernel=kernel)
         self.device = torch.device(device)
         self._alloc_workspace(workspace_size_batch(self.params, self.counts, self.depths))
         handle = C.c_void_p()

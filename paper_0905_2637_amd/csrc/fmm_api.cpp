@@ -106,7 +106,9 @@ int level_blocks_host(int l)
 fmm_status validate_common(const fmm_params* prm)
 {
     if (!prm) return FMM_E_ARG;
-    if (!(prm->sigma > 0.0) || !std::isfinite(prm->sigma)) return FMM_E_ARG;
+    if (prm->kernel != FMM_KERNEL_GAUSSIAN && prm->kernel != FMM_KERNEL_SINGULAR) return FMM_E_ARG;
+    if (prm->kernel == FMM_KERNEL_GAUSSIAN && (!(prm->sigma > 0.0) || !std::isfinite(prm->sigma)))
+        return FMM_E_ARG;
     if (prm->p < 1 || prm->p > kMaxP) return FMM_E_ARG;
     if (prm->precision != FMM_PREC_FP64 && prm->precision != FMM_PREC_MIXED) return FMM_E_ARG;
     if (prm->m_max < 0 || prm->m_max > int64_t(0x7fffffff)) return FMM_E_ARG;
@@ -528,6 +530,7 @@ hipError_t enqueue_all(fmm_plan_s* pl, int64_t n, const double* x, const double*
     auto chk = [&](hipError_t r) { if (e == hipSuccess) e = r; };
     auto mark = [&](int i) { if (timing) chk(hipEventRecord(pl->ev[slot][i], st)); };
     const int P = pl->P, p = pl->prm.p;
+    const bool sing = pl->prm.kernel == FMM_KERNEL_SINGULAR;
 
     mark(ST_TREE);
     if (pl->auto_domain) chk(launch_domain(b, int(n), x, y, pl->shape.depth[0], st, int(m), tx, ty));
@@ -544,9 +547,10 @@ hipError_t enqueue_all(fmm_plan_s* pl, int64_t n, const double* x, const double*
             case L_DOWN: chk(launch_downward(b, P, w, ln.nwg, st)); break;
             case L_P2P:
                 if (m > 0)
-                    chk(launch_p2p_at(b, P, pl->shape.depth[0], pl->prm.sigma, u, v, st));
+                    chk(launch_p2p_at(b, P, pl->shape.depth[0], sing, pl->prm.sigma, u, v, st));
                 else
-                    chk(launch_p2p(b, P, w, ln.nwg, pl->tune.p2p_waves, pl->mixed, pl->prm.sigma, u, v, st));
+                    chk(launch_p2p(b, P, w, ln.nwg, pl->tune.p2p_waves, pl->mixed, sing, pl->prm.sigma, u, v,
+                                   st));
                 break;
         }
     }

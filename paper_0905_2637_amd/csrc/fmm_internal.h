@@ -177,10 +177,12 @@ hipError_t launch_upward(const Buffers& b, int P, int p, const Work& w, int nwg,
 hipError_t launch_m2l(const Buffers& b, int P, const Work& w, int nwg, bool fp32, bool mfma, int groups,
                       hipStream_t st);
 hipError_t launch_downward(const Buffers& b, int P, const Work& w, int nwg, hipStream_t st);   // L2L
-hipError_t launch_p2p(const Buffers& b, int P, const Work& w, int nwg, int waves, bool mixed, double sigma,
-                      double* u, double* v, hipStream_t st);
+// near field with the Gaussian kernel of core sigma, or the singular kernel
+hipError_t launch_p2p(const Buffers& b, int P, const Work& w, int nwg, int waves, bool mixed, bool singular,
+                      double sigma, double* u, double* v, hipStream_t st);
 // near field + L2P at the sorted target points of a single-instance FP64 plan
-hipError_t launch_p2p_at(const Buffers& b, int P, int L, double sigma, double* u, double* v, hipStream_t st);
+hipError_t launch_p2p_at(const Buffers& b, int P, int L, bool singular, double sigma, double* u, double* v,
+                         hipStream_t st);
 hipError_t launch_ilist(const Buffers& b, int L, hipStream_t st);
 // time stepping: (xo, yo) = (x, y) + c (u, v); xo, yo may alias x, y
 hipError_t launch_advance(int64_t n, const double* x, const double* y, const double* u, const double* v, double c,

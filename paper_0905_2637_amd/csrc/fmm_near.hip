@@ -2,7 +2,9 @@
 // field from its leaf's local expansion (L2P) plus the near field summed
 // directly over the leaf and its touching leaves (P2P) with the Gaussian
 // regularised kernel of eq. 8, written out as the velocity of eq. 9 in the
-// caller's order.
+// caller's order.  A plan may select the singular kernel of eq. 7 (point
+// vortices) instead: the Gaussian factor below is then 1, and the kernels
+// are compiled without it.
 //
 // Complex form: phi(z_i) = sum_j gamma_j (1 - exp(-|z_i - z_j|^2 / 2 sigma^2))
 // / (z_i - z_j) over near pairs, plus L2P; u = Im(phi)/(2 pi), v = Re(phi)/(2 pi).
@@ -108,8 +110,9 @@ constexpr int kR = 4;              // most targets per lane
 
 // Sum over staged sources jb + si, jb = 0, S, 2S, ... < padded for the R
 // targets a lane owns.  FP32 leaf-relative form: coordinates in leaf widths,
-// exp(-t) = 2^(-t log2 e) with c2 = w^2 log2(e) / (2 sigma^2).
-template <int R>
+// exp(-t) = 2^(-t log2 e) with c2 = w^2 log2(e) / (2 sigma^2).  SING: the
+// singular kernel of eq. 7 (no Gaussian factor).
+template <int R, bool SING>
 __device__ __forceinline__ void p2p_f32(const float4* __restrict__ src, int padded, int S, int si, float c2,
                                         const float* ox, const float* oy, float* fx, float* fy)
 {
@@ -120,15 +123,20 @@ __device__ __forceinline__ void p2p_f32(const float4* __restrict__ src, int padd
         for (int r = 0; r < R; ++r) {
             const float dx = ox[r] - t.x, dy = oy[r] - t.y;
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));    // > 0, as in the FP64 form
-            const float e = __builtin_amdgcn_exp2f(-r2 * c2);
-            const float q2 = fmaf(-t.z, e, t.z) * __builtin_amdgcn_rcpf(r2);
+            float q2;
+            if constexpr (SING) {
+                q2 = t.z * __builtin_amdgcn_rcpf(r2);
+            } else {
+                const float e = __builtin_amdgcn_exp2f(-r2 * c2);
+                q2 = fmaf(-t.z, e, t.z) * __builtin_amdgcn_rcpf(r2);
+            }
             fx[r] = fmaf(q2, dx, fx[r]);
             fy[r] = fmaf(-q2, dy, fy[r]);
         }
     }
 }
 
-template <int R>
+template <int R, bool SING>
 __device__ __forceinline__ void p2p_f64(const Src64* __restrict__ src, int padded, int S, int si, double ninv2s2,
                                         const double* x, const double* y, double* ax, double* ay)
 {
@@ -141,8 +149,9 @@ __device__ __forceinline__ void p2p_f64(const Src64* __restrict__ src, int padde
             // then vanishes through dx = dy = 0; it changes r2 only for
             // points closer than about 1e-142
             const double r2 = fma(dx, dx, fma(dy, dy, 1e-300));
-            const double f = one_minus_exp(r2 * ninv2s2);
-            const double q2 = t.g * f * recip(r2);
+            double q2;
+            if constexpr (SING) q2 = t.g * recip(r2);
+            else q2 = t.g * one_minus_exp(r2 * ninv2s2) * recip(r2);
             ax[r] = fma(q2, dx, ax[r]);
             ay[r] = fma(-q2, dy, ay[r]);
         }
@@ -167,7 +176,7 @@ constexpr int kStageSlots = kNearStage / 64;   // staged sources per lane and ch
 // go to sink[i] for target i of the leaf instead of being finished here.
 // tx, ty: the targets' sorted positions (the particles' own for the particle
 // sum), perm: their sorted position -> output index.
-template <int P, bool MIXED, int R>
+template <int P, bool MIXED, int R, bool SING>
 __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* stage_raw, cd* le_sh, int has_far,
                                               const double* __restrict__ tx, const double* __restrict__ ty,
                                               const double* __restrict__ xs, const double* __restrict__ ys,
@@ -258,8 +267,8 @@ __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* 
                 if (k < padded) src[k] = val[sl];
             }
             wave_sync();
-            if constexpr (MIXED) p2p_f32<R>(src, padded, S, si, c.c2, oxi, oyi, fx, fy);
-            else p2p_f64<R>(src, padded, S, si, -c.inv2s2, xi, yi, ax, ay);
+            if constexpr (MIXED) p2p_f32<R, SING>(src, padded, S, si, c.c2, oxi, oyi, fx, fy);
+            else p2p_f64<R, SING>(src, padded, S, si, -c.inv2s2, xi, yi, ax, ay);
         }
 
         // combine the S slices: every lane of a target group ends with the sums
@@ -354,7 +363,7 @@ __device__ __forceinline__ void make_ctx(LeafCtx& c, uint32_t m, int L, const in
 
 // register blocking pays once a chunk is full; sparse leaves keep one target
 // per lane (fewer slices to combine)
-template <int P, bool MIXED>
+template <int P, bool MIXED, bool SING>
 __device__ __forceinline__ void leaf_dispatch(const LeafCtx& c, int lane, void* st, cd* lsh, int has_far,
                                               const double* __restrict__ tx, const double* __restrict__ ty,
                                               const double* __restrict__ xs, const double* __restrict__ ys,
@@ -363,11 +372,11 @@ __device__ __forceinline__ void leaf_dispatch(const LeafCtx& c, int lane, void* 
                                               cd* sink, double* __restrict__ u, double* __restrict__ v)
 {
     if (c.lgT == 6)
-        leaf_near_far<P, MIXED, 4>(c, lane, st, lsh, has_far, tx, ty, xs, ys, gs, pk, perm, le_leaf, sink, u, v);
+        leaf_near_far<P, MIXED, 4, SING>(c, lane, st, lsh, has_far, tx, ty, xs, ys, gs, pk, perm, le_leaf, sink, u, v);
     else if (c.lgT == 5)
-        leaf_near_far<P, MIXED, 2>(c, lane, st, lsh, has_far, tx, ty, xs, ys, gs, pk, perm, le_leaf, sink, u, v);
+        leaf_near_far<P, MIXED, 2, SING>(c, lane, st, lsh, has_far, tx, ty, xs, ys, gs, pk, perm, le_leaf, sink, u, v);
     else
-        leaf_near_far<P, MIXED, 1>(c, lane, st, lsh, has_far, tx, ty, xs, ys, gs, pk, perm, le_leaf, sink, u, v);
+        leaf_near_far<P, MIXED, 1, SING>(c, lane, st, lsh, has_far, tx, ty, xs, ys, gs, pk, perm, le_leaf, sink, u, v);
 }
 
 // Quads of sibling leaves: the four leaves of a 2 x 2 block touch each other,
@@ -385,6 +394,7 @@ __device__ __forceinline__ void leaf_dispatch(const LeafCtx& c, int lane, void* 
 // they save.
 constexpr int kQuadMax = 64;
 
+template <bool SING>
 __device__ __forceinline__ void quad_pairs(const Src64* qsh, int lane, int w, double ninv2s2, double& sx, double& sy)
 {
     const Src64 me = qsh[lane];
@@ -393,7 +403,9 @@ __device__ __forceinline__ void quad_pairs(const Src64* qsh, int lane, int w, do
         const Src64 t = qsh[(lane + s) & 63];
         const double dx = me.x - t.x, dy = me.y - t.y;
         const double r2 = fma(dx, dx, fma(dy, dy, 1e-300));
-        const double q = one_minus_exp(r2 * ninv2s2) * recip(r2);
+        double q;
+        if constexpr (SING) q = recip(r2);
+        else q = one_minus_exp(r2 * ninv2s2) * recip(r2);
         const double qi = act ? t.g * q : 0.0, qj = act ? me.g * q : 0.0;
         ax = fma(qi, dx, ax);
         ay = fma(-qi, dy, ay);
@@ -409,7 +421,7 @@ __device__ __forceinline__ void quad_pairs(const Src64* qsh, int lane, int w, do
 
 // WAVES wavefronts per workgroup, one leaf each (four: one quad); the work
 // table gives every instance ceil(4^L / WAVES) workgroups.
-template <int P, bool MIXED, int WAVES>
+template <int P, bool MIXED, int WAVES, bool SING>
 __global__ void __launch_bounds__(64 * WAVES)
 k_p2p_l2p(Work wk, int n_inst, const Inst* __restrict__ inst, const int32_t* __restrict__ leaf_start_all,
           const double* __restrict__ xs, const double* __restrict__ ys, const double* __restrict__ gs,
@@ -452,7 +464,8 @@ k_p2p_l2p(Work wk, int n_inst, const Inst* __restrict__ inst, const int32_t* __r
         LeafCtx c;
         make_ctx(c, uint32_t(mm), L, leaf_start, d, inv2s2, false);
         if (c.nt == 0) return;
-        leaf_dispatch<P, MIXED>(c, lane, st, lsh, has_far, xs, ys, xs, ys, gs, pk, perm, le_leaf, nullptr, u, v);
+        leaf_dispatch<P, MIXED, SING>(c, lane, st, lsh, has_far, xs, ys, xs, ys, gs, pk, perm, le_leaf, nullptr, u,
+                                      v);
         return;
     }
 
@@ -467,11 +480,11 @@ k_p2p_l2p(Work wk, int n_inst, const Inst* __restrict__ inst, const int32_t* __r
     __syncthreads();
     // the leaf's targets against the neighbours outside the quad
     if (c.nt > 0)
-        leaf_dispatch<P, MIXED>(c, lane, st, lsh, 0, xs, ys, xs, ys, gs, pk, perm, le_leaf, part_sh[0] + (c.s0 - sq),
-                                u, v);
+        leaf_dispatch<P, MIXED, SING>(c, lane, st, lsh, 0, xs, ys, xs, ys, gs, pk, perm, le_leaf,
+                                      part_sh[0] + (c.s0 - sq), u, v);
     // this wavefront's share of the pairs inside the quad
     double ix, iy;
-    quad_pairs(qsh, lane, wv, -inv2s2, ix, iy);
+    quad_pairs<SING>(qsh, lane, wv, -inv2s2, ix, iy);
     part_sh[1 + wv][lane] = cd{ix, iy};
     __syncthreads();
     if (c.nt == 0) return;
@@ -510,7 +523,7 @@ k_p2p_l2p(Work wk, int n_inst, const Inst* __restrict__ inst, const int32_t* __r
 // wavefront per leaf of the points' tree, its points against the particles
 // of the 3 x 3 neighbourhood, plus L2P from the leaf's local expansion.
 // Single instance, FP64.
-template <int P>
+template <int P, bool SING>
 __global__ void __launch_bounds__(256)
 k_p2p_at(int L, const Inst* __restrict__ inst, const int32_t* __restrict__ leaf_start,
          const int32_t* __restrict__ tleaf_start, const double* __restrict__ xs, const double* __restrict__ ys,
@@ -531,46 +544,54 @@ k_p2p_at(int L, const Inst* __restrict__ inst, const int32_t* __restrict__ leaf_
     if (c.nt == 0) return;
     c.lgT = c.nt >= 64 ? 6 : (c.nt <= 1 ? 0 : 32 - __clz(c.nt - 1));
     const cd* le_leaf = le_all + (inst[0].box_off + level_offset(L)) * P;
-    leaf_dispatch<P, false>(c, lane, stage_all[wv], le_all_sh[wv], L >= 2 ? 1 : 0, txs, tys, xs, ys, gs, nullptr,
-                            tperm, le_leaf, nullptr, u, v);
+    leaf_dispatch<P, false, SING>(c, lane, stage_all[wv], le_all_sh[wv], L >= 2 ? 1 : 0, txs, tys, xs, ys, gs,
+                                  nullptr, tperm, le_leaf, nullptr, u, v);
 }
 
-template <int P, int WAVES>
-hipError_t p2p_impl(const Buffers& b, const Work& w, int nwg, bool mixed, double sigma, double* u, double* v,
-                    hipStream_t st)
+// 1/(2 sigma^2) of the Gaussian core; unused (0) by the singular kernel
+double core_factor(double sigma, bool singular) { return singular ? 0.0 : 1.0 / (2.0 * sigma * sigma); }
+
+template <int P, int WAVES, bool SING>
+void p2p_launch(const Buffers& b, const Work& w, int nwg, bool mixed, double inv2s2, double* u, double* v,
+                hipStream_t st)
 {
-    if (nwg <= 0) return hipSuccess;
-    const double inv2s2 = 1.0 / (2.0 * sigma * sigma);
     if (mixed)
-        hipLaunchKernelGGL((k_p2p_l2p<P, true, WAVES>), dim3(unsigned(nwg)), dim3(64 * WAVES), 0, st, w, b.n_inst,
-                           b.inst, b.leaf_start, b.xs, b.ys, b.gs, b.pk, b.perm, b.le, inv2s2, u, v);
+        hipLaunchKernelGGL((k_p2p_l2p<P, true, WAVES, SING>), dim3(unsigned(nwg)), dim3(64 * WAVES), 0, st, w,
+                           b.n_inst, b.inst, b.leaf_start, b.xs, b.ys, b.gs, b.pk, b.perm, b.le, inv2s2, u, v);
     else
-        hipLaunchKernelGGL((k_p2p_l2p<P, false, WAVES>), dim3(unsigned(nwg)), dim3(64 * WAVES), 0, st, w, b.n_inst,
-                           b.inst, b.leaf_start, b.xs, b.ys, b.gs, b.pk, b.perm, b.le, inv2s2, u, v);
-    return hipGetLastError();
+        hipLaunchKernelGGL((k_p2p_l2p<P, false, WAVES, SING>), dim3(unsigned(nwg)), dim3(64 * WAVES), 0, st, w,
+                           b.n_inst, b.inst, b.leaf_start, b.xs, b.ys, b.gs, b.pk, b.perm, b.le, inv2s2, u, v);
 }
 
 template <int P>
-hipError_t p2p_waves(const Buffers& b, const Work& w, int nwg, int waves, bool mixed, double sigma, double* u,
-                     double* v, hipStream_t st)
+hipError_t p2p_waves(const Buffers& b, const Work& w, int nwg, int waves, bool mixed, bool singular, double sigma,
+                     double* u, double* v, hipStream_t st)
 {
-    switch (waves) {
-        case 2: return p2p_impl<P, 2>(b, w, nwg, mixed, sigma, u, v, st);
-        case 4: return p2p_impl<P, 4>(b, w, nwg, mixed, sigma, u, v, st);
-        default: return hipErrorInvalidValue;
-    }
+    if (nwg <= 0) return hipSuccess;
+    if (waves != 2 && waves != 4) return hipErrorInvalidValue;
+    const double inv2s2 = core_factor(sigma, singular);
+    if (waves == 2 && singular) p2p_launch<P, 2, true>(b, w, nwg, mixed, inv2s2, u, v, st);
+    else if (waves == 2) p2p_launch<P, 2, false>(b, w, nwg, mixed, inv2s2, u, v, st);
+    else if (singular) p2p_launch<P, 4, true>(b, w, nwg, mixed, inv2s2, u, v, st);
+    else p2p_launch<P, 4, false>(b, w, nwg, mixed, inv2s2, u, v, st);
+    return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_p2p_at(const Buffers& b, int P, int L, double sigma, double* u, double* v, hipStream_t st)
+hipError_t launch_p2p_at(const Buffers& b, int P, int L, bool singular, double sigma, double* u, double* v,
+                         hipStream_t st)
 {
-    const double inv2s2 = 1.0 / (2.0 * sigma * sigma);
+    const double inv2s2 = core_factor(sigma, singular);
     const dim3 grid{unsigned(((int64_t(1) << (2 * L)) + 3) / 4)};
-#define FMM_AT_CASE(PP)                                                                                          \
-    case PP:                                                                                                     \
-        hipLaunchKernelGGL(k_p2p_at<PP>, grid, dim3(256), 0, st, L, b.inst, b.leaf_start, b.tleaf_start, b.xs, \
-                           b.ys, b.gs, b.txs, b.tys, b.tperm, b.le, inv2s2, u, v);                               \
+#define FMM_AT_CASE(PP)                                                                                            \
+    case PP:                                                                                                       \
+        if (singular)                                                                                              \
+            hipLaunchKernelGGL((k_p2p_at<PP, true>), grid, dim3(256), 0, st, L, b.inst, b.leaf_start,             \
+                               b.tleaf_start, b.xs, b.ys, b.gs, b.txs, b.tys, b.tperm, b.le, inv2s2, u, v);        \
+        else                                                                                                       \
+            hipLaunchKernelGGL((k_p2p_at<PP, false>), grid, dim3(256), 0, st, L, b.inst, b.leaf_start,            \
+                               b.tleaf_start, b.xs, b.ys, b.gs, b.txs, b.tys, b.tperm, b.le, inv2s2, u, v);        \
         return hipGetLastError();
     switch (P) {
         FMM_AT_CASE(8)
@@ -585,17 +606,17 @@ hipError_t launch_p2p_at(const Buffers& b, int P, int L, double sigma, double* u
 #undef FMM_AT_CASE
 }
 
-hipError_t launch_p2p(const Buffers& b, int P, const Work& w, int nwg, int waves, bool mixed, double sigma,
-                      double* u, double* v, hipStream_t st)
+hipError_t launch_p2p(const Buffers& b, int P, const Work& w, int nwg, int waves, bool mixed, bool singular,
+                      double sigma, double* u, double* v, hipStream_t st)
 {
     switch (P) {
-        case 8: return p2p_waves<8>(b, w, nwg, waves, mixed, sigma, u, v, st);
-        case 12: return p2p_waves<12>(b, w, nwg, waves, mixed, sigma, u, v, st);
-        case 16: return p2p_waves<16>(b, w, nwg, waves, mixed, sigma, u, v, st);
-        case 17: return p2p_waves<17>(b, w, nwg, waves, mixed, sigma, u, v, st);
-        case 20: return p2p_waves<20>(b, w, nwg, waves, mixed, sigma, u, v, st);
-        case 24: return p2p_waves<24>(b, w, nwg, waves, mixed, sigma, u, v, st);
-        case 32: return p2p_waves<32>(b, w, nwg, waves, mixed, sigma, u, v, st);
+        case 8: return p2p_waves<8>(b, w, nwg, waves, mixed, singular, sigma, u, v, st);
+        case 12: return p2p_waves<12>(b, w, nwg, waves, mixed, singular, sigma, u, v, st);
+        case 16: return p2p_waves<16>(b, w, nwg, waves, mixed, singular, sigma, u, v, st);
+        case 17: return p2p_waves<17>(b, w, nwg, waves, mixed, singular, sigma, u, v, st);
+        case 20: return p2p_waves<20>(b, w, nwg, waves, mixed, singular, sigma, u, v, st);
+        case 24: return p2p_waves<24>(b, w, nwg, waves, mixed, singular, sigma, u, v, st);
+        case 32: return p2p_waves<32>(b, w, nwg, waves, mixed, singular, sigma, u, v, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -71,10 +71,29 @@ def test_workspace_size_grows_with_problem(lib):
     (dict(n_max=1 << 31), fm.FMM_E_ARG),
     (dict(p=23, precision="mixed"), fm.FMM_E_UNSUPPORTED),
     (dict(depth=4, precision="mixed", fp32_fine_levels=4), fm.FMM_E_ARG),
+    (dict(m_max=-1), fm.FMM_E_ARG),
+    (dict(m_max=1 << 31), fm.FMM_E_ARG),
 ])
 def test_invalid_parameters_rejected(lib, kw, err):
     s, _ = _ws(**kw)
     assert s == err
+
+
+def test_kernel_choice(lib):
+    # the singular kernel ignores sigma; the Gaussian one needs sigma > 0
+    assert _ws(kernel="singular", sigma=0.0)[0] == fm.FMM_OK
+    assert _ws(kernel="singular", sigma=float("nan"))[0] == fm.FMM_OK
+    assert _ws(kernel="gaussian", sigma=0.0)[0] == fm.FMM_E_ARG
+    prm = fm.make_params(100, 0.01, 12, 3)
+    prm.kernel = 2
+    out = C.c_size_t(0)
+    assert lib.fmm_workspace_size(C.byref(prm), C.byref(out)) == fm.FMM_E_ARG
+
+
+def test_target_capacity_adds_workspace(lib):
+    _, b0 = _ws()
+    s1, b1 = _ws(m_max=5000)
+    assert s1 == fm.FMM_OK and b1 > b0 + 5000 * 32
 
 
 def test_null_arguments_rejected(lib):

@@ -77,3 +77,18 @@ def test_singular_fmm_converges_to_the_direct_sum():
     # the split sum with the singular kernel is the singular sum
     us, vs = oracle.direct_split(x, y, g, 0.0, 4)
     assert np.array_equal(us, ud) and np.array_equal(vs, vd)
+
+
+def test_polygon_rotates_rigidly_under_time_stepping():
+    """Kelvin's polygon turns with angular velocity (N - 1) gamma / (4 pi R^2);
+    the midpoint rule's position error falls fourfold when dt halves."""
+    N, gam, R, T = 6, 0.37, 0.3, 1.0
+    omega = (N - 1) * gam / (4 * math.pi * R * R)
+    th = 2 * math.pi * np.arange(N) / N + 0.1
+    errs = []
+    for steps in (25, 50):
+        x, y = oracle.advance_rk2(0.5 + R * np.cos(th), 0.5 + R * np.sin(th), np.full(N, gam), 0.0, T / steps,
+                                  steps, p=32, L=3, velocity="fmm")
+        errs.append(float(np.max(np.hypot(x - 0.5 - R * np.cos(th + omega * T),
+                                          y - 0.5 - R * np.sin(th + omega * T)))))
+    assert errs[0] < 1e-3 and 3.8 < errs[0] / errs[1] < 4.2, errs
