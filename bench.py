@@ -159,14 +159,14 @@ def dev_arrays(wl, dev):
 # single evaluation
 # ---------------------------------------------------------------------------
 
-def run_single(wl, args, dev):
+def run_single(wl, args, dev, kernel="gaussian"):
     import torch
     import paper_0905_2637_amd as fm
     x, y, g = dev_arrays(wl, dev)
     u = torch.empty(wl.n, dtype=torch.float64, device=dev)
     v = torch.empty(wl.n, dtype=torch.float64, device=dev)
     plan = fm.Plan(wl.n, wl.sigma, wl.p, wl.depth, domain=(wl.x0, wl.y0, wl.width),
-                   precision=wl.precision, fp32_fine_levels=wl.fp32_fine_levels)
+                   precision=wl.precision, fp32_fine_levels=wl.fp32_fine_levels, kernel=kernel)
     for _ in range(args.warmup):
         plan.evaluate(x, y, g, u, v)
     torch.cuda.synchronize()
@@ -417,6 +417,11 @@ def main() -> int:
                                               "evaluations per step, bounding-square domain)",
                                   "ms_per_step": round(ts * 1e3, 4), "particle_steps_per_s": wl.n / ts,
                                   "step_vs_two_evaluations": ts / (2 * res["sec"])}
+        rs = run_single(workloads.make("C2"), args, dev, kernel="singular")
+        forms["singular_kernel"] = {"workload": "C2 with the singular kernel of eq. 7 in the near field (point "
+                                                "vortices, FP64)",
+                                    "ms": round(rs["sec"] * 1e3, 4), "value": wl.n / rs["sec"],
+                                    "stages_ms": {k: round(x, 4) for k, x in rs["stage_ms"].items()}}
         tp, mp, sp = run_points(workloads.make("C2"), args, dev)
         forms["points"] = {"workload": "C2 particles, velocity on a 1024 x 1024 vertex lattice of points "
                                        "(FP64, eq. 1 with targets apart from the sources)",
