@@ -801,9 +801,7 @@ fmm_status fmm_evaluate_at(fmm_plan_t plan, int64_t n, const double* d_x, const 
     plan->last_m = 0;
     if (m == 0) return FMM_OK;
     if (n == 0) {   // no sources: the velocity vanishes everywhere
-        hipError_t e = hipMemsetAsync(d_u, 0, size_t(m) * sizeof(double), st);
-        if (e == hipSuccess) e = hipMemsetAsync(d_v, 0, size_t(m) * sizeof(double), st);
-        return e == hipSuccess ? FMM_OK : FMM_E_DEVICE;
+        return launch_zero2(m, d_u, d_v, st) == hipSuccess ? FMM_OK : FMM_E_DEVICE;
     }
     plan->last_n = n;
     plan->last_m = m;

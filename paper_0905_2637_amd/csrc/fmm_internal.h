@@ -184,6 +184,8 @@ hipError_t launch_p2p(const Buffers& b, int P, const Work& w, int nwg, int waves
 hipError_t launch_p2p_at(const Buffers& b, int P, int L, bool singular, double sigma, double* u, double* v,
                          hipStream_t st);
 hipError_t launch_ilist(const Buffers& b, int L, hipStream_t st);
+// a[0..n) = b[0..n) = 0
+hipError_t launch_zero2(int64_t n, double* a, double* b, hipStream_t st);
 // time stepping: (xo, yo) = (x, y) + c (u, v); xo, yo may alias x, y
 hipError_t launch_advance(int64_t n, const double* x, const double* y, const double* u, const double* v, double c,
                           double* xo, double* yo, hipStream_t st);

@@ -32,6 +32,29 @@ k_advance(int64_t n, const double* x, const double* y, const double* __restrict_
 
 }  // namespace
 
+// a = b = 0 over n entries (a fill kernel rather than a memset node, so that
+// a caller may capture it into a graph)
+__global__ void __launch_bounds__(kStepThreads) k_zero2(int64_t n, double* a, double* b)
+{
+    const int64_t base = int64_t(blockIdx.x) * (kStepThreads * kStepPer) + threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < kStepPer; ++r) {
+        const int64_t i = base + int64_t(r) * kStepThreads;
+        if (i < n) {
+            a[i] = 0.0;
+            b[i] = 0.0;
+        }
+    }
+}
+
+hipError_t launch_zero2(int64_t n, double* a, double* b, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t per_block = int64_t(kStepThreads) * kStepPer;
+    hipLaunchKernelGGL(k_zero2, dim3(unsigned((n + per_block - 1) / per_block)), dim3(kStepThreads), 0, st, n, a, b);
+    return hipGetLastError();
+}
+
 hipError_t launch_advance(int64_t n, const double* x, const double* y, const double* u, const double* v, double c,
                           double* xo, double* yo, hipStream_t st)
 {
