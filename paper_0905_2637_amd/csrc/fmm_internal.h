@@ -107,6 +107,17 @@ __device__ __forceinline__ int xcd_runs(int b, int G, int run)
     return ((k / run) * kXcds + x) * run + k % run;
 }
 
+// A launch counts its work-items in 32 bits per grid dimension, so a launch
+// of one wavefront per leaf at depth 13 (2^26 leaves x 64 lanes) does not fit
+// in one row.  Such launches take rows of at most kGridRow workgroups in y;
+// flat_block() is the workgroup's place in the flattened grid.
+constexpr int64_t kGridRow = int64_t(1) << 20;
+inline dim3 row_grid(int64_t nwg)
+{
+    return dim3(unsigned(nwg < kGridRow ? nwg : kGridRow), unsigned((nwg + kGridRow - 1) / kGridRow));
+}
+__device__ __forceinline__ int64_t flat_block() { return blockIdx.x + int64_t(gridDim.x) * blockIdx.y; }
+
 // Device pointers of one plan, all inside the caller's workspace.
 struct Buffers {
     Inst* inst;            // [n_inst]

@@ -437,14 +437,16 @@ k_p2p_l2p(Work wk, int n_inst, const Inst* __restrict__ inst, const int32_t* __r
 
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int pos = find_inst(wk.wg_begin, n_inst, blockIdx.x);   // place in the launch order
+    const int64_t blk = flat_block();
+    if (blk >= wk.wg_begin[n_inst]) return;                        // past the last row's end
+    const int pos = find_inst(wk.wg_begin, n_inst, int(blk));      // place in the launch order
     const int qi = wk.order[pos];
     const int L = inst[qi].L;
     const int has_far = L >= 2 ? 1 : 0;
     const int32_t* leaf_start = leaf_start_all + inst[qi].leaf_off;
     const cd* le_leaf = le_all + (inst[qi].box_off + level_offset(L)) * P;
     const int64_t nleaf = int64_t(1) << (2 * L);
-    const int64_t mm = int64_t(blockIdx.x - wk.wg_begin[pos]) * WAVES + wv;
+    const int64_t mm = (blk - wk.wg_begin[pos]) * WAVES + wv;
     const Domain d = inst[qi].dom;
     void* st = stage_all[wv];
     cd* lsh = le_all_sh[wv];
@@ -535,7 +537,7 @@ k_p2p_at(int L, const Inst* __restrict__ inst, const int32_t* __restrict__ leaf_
     __shared__ cd le_all_sh[4][P];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int64_t mm = int64_t(blockIdx.x) * 4 + wv;
+    const int64_t mm = flat_block() * 4 + wv;
     if (mm >= (int64_t(1) << (2 * L))) return;
     LeafCtx c;
     make_ctx(c, uint32_t(mm), L, leaf_start, inst[0].dom, inv2s2, false);   // the particles around the leaf
@@ -556,10 +558,10 @@ void p2p_launch(const Buffers& b, const Work& w, int nwg, bool mixed, double inv
                 hipStream_t st)
 {
     if (mixed)
-        hipLaunchKernelGGL((k_p2p_l2p<P, true, WAVES, SING>), dim3(unsigned(nwg)), dim3(64 * WAVES), 0, st, w,
+        hipLaunchKernelGGL((k_p2p_l2p<P, true, WAVES, SING>), row_grid(nwg), dim3(64 * WAVES), 0, st, w,
                            b.n_inst, b.inst, b.leaf_start, b.xs, b.ys, b.gs, b.pk, b.perm, b.le, inv2s2, u, v);
     else
-        hipLaunchKernelGGL((k_p2p_l2p<P, false, WAVES, SING>), dim3(unsigned(nwg)), dim3(64 * WAVES), 0, st, w,
+        hipLaunchKernelGGL((k_p2p_l2p<P, false, WAVES, SING>), row_grid(nwg), dim3(64 * WAVES), 0, st, w,
                            b.n_inst, b.inst, b.leaf_start, b.xs, b.ys, b.gs, b.pk, b.perm, b.le, inv2s2, u, v);
 }
 
@@ -583,7 +585,7 @@ hipError_t launch_p2p_at(const Buffers& b, int P, int L, bool singular, double s
                          hipStream_t st)
 {
     const double inv2s2 = core_factor(sigma, singular);
-    const dim3 grid{unsigned(((int64_t(1) << (2 * L)) + 3) / 4)};
+    const dim3 grid = row_grid(((int64_t(1) << (2 * L)) + 3) / 4);
 #define FMM_AT_CASE(PP)                                                                                            \
     case PP:                                                                                                       \
         if (singular)                                                                                              \

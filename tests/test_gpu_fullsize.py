@@ -82,3 +82,19 @@ def test_c5_full_size_mixed():
     us, vs = oracle.direct_split(wl.x, wl.y, wl.gamma, wl.sigma, wl.depth, wl.x0, wl.y0, wl.width, targets=t)
     gate = oracle.rel_l2(u[t], v[t], us, vs)
     assert gate < 1e-6, f"rel L2 vs the FP64 split direct sum {gate:.3e}"
+
+
+def test_deepest_tree_fp64():
+    """The deepest tree the library takes (depth 13: 4^13 leaves, 26-bit keys,
+    four radix passes, 89 million boxes per expansion array, held dense),
+    with 200,000 clustered particles and p = 24: the tree bit for bit, and
+    sampled velocities against the FP64 split-kernel direct sum."""
+    import workloads as W
+    x, y, g, _, _ = W.gaussian_mixture(200000, 6, 1030)
+    wl = W.Workload("deep", x, y, g, sigma=2e-5, depth=13, p=24)
+    u, v, keys, perm, ls = _run(wl)
+    _tree_bit_exact(wl, keys, perm, ls)
+    t = W.sample_targets(wl.n, 1024, 1031)
+    us, vs = oracle.direct_split(wl.x, wl.y, wl.gamma, wl.sigma, wl.depth, targets=t)
+    err = oracle.rel_l2(u[t], v[t], us, vs)
+    assert err < 1e-9, f"rel L2 vs the FP64 split direct sum {err:.3e}"
