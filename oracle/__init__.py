@@ -81,6 +81,9 @@ def _load():
     lib.oracle_fmm_at.argtypes = [i64, dp, dp, dp, C.c_double, C.c_int, C.c_int, C.c_double, C.c_double,
                                   C.c_double, i64, dp, dp, dp, dp]
     lib.oracle_fmm_at.restype = i64
+    lib.oracle_lj_forces.argtypes = [i64, dp, dp, C.c_double, C.c_double, C.c_double, i64, i64p, dp, dp]
+    lib.oracle_lj_energy.argtypes = [i64, dp, dp, C.c_double, C.c_double, C.c_double]
+    lib.oracle_lj_energy.restype = C.c_double
     lib.oracle_init()
     _lib = lib
     return lib
@@ -321,3 +324,21 @@ def fmm_at(x, y, g, sigma, p, L, tx, ty, x0=0.0, y0=0.0, W=1.0):
     nbad = lib.oracle_fmm_at(x.shape[0], _d(x), _d(y), _d(g), sigma, p, L, x0, y0, W, m, _d(tx), _d(ty),
                              _d(u), _d(v))
     return u, v, int(nbad)
+
+
+def lj_forces(x, y, eps, sig, rc, targets=None):
+    """Lennard-Jones forces (truncated at rc) on all particles or on ``targets``."""
+    lib = _load()
+    x, y = _f64(x), _f64(y)
+    n = x.shape[0]
+    t, nt, tp = _targets(targets, n)
+    fx, fy = np.zeros(nt), np.zeros(nt)
+    lib.oracle_lj_forces(n, _d(x), _d(y), eps, sig, rc, nt, tp, _d(fx), _d(fy))
+    return fx, fy
+
+
+def lj_energy(x, y, eps, sig, rc):
+    """Total Lennard-Jones energy (truncated at rc), each pair once."""
+    x, y = _f64(x), _f64(y)
+    return float(_load().oracle_lj_energy(x.shape[0], _d(x), _d(y), eps, sig, rc))
+

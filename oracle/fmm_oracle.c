@@ -17,6 +17,8 @@
  *   - z-order (Morton) box numbering .................. Section 5.1
  *   - upward sweep (P2M, M2M), downward sweep (M2L over the interaction
  *     list, L2L), evaluation (L2P + near-field direct) .. Section 2.2, Fig. 2
+ *   - Lennard-Jones forces and energy with a cutoff (a further kernel the
+ *     paper names for molecular dynamics) ............ Section 8
  * The paper leaves out the expansion mathematics and points to Greengard and
  * Rokhlin; the expansions below are the textbook complex-variable ones for the
  * Cauchy kernel 1/z, kept unscaled (coefficients about geometric box centres).
@@ -663,6 +665,63 @@ int64_t oracle_fmm_at(int64_t n, const double* x, const double* y, const double*
                       int64_t m, const double* tx, const double* ty, double* u, double* v)
 {
     return fmm_core(n, x, y, g, sigma, p, L, x0, y0, W, m, NULL, tx, ty, u, v, NULL, NULL);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Lennard-Jones particles (Section 8 names the Lennard-Jones potential of   */
+/* molecular dynamics as a further kernel): the pair potential              */
+/*   V(r) = 4 eps ((s/r)^12 - (s/r)^6)  for 0 < r < rc, 0 otherwise         */
+/* (truncated at the cutoff rc, not shifted), and the force on i,           */
+/*   F_i = sum_{j != i} -V'(r_ij) (x_i - x_j) / r_ij,                         */
+/*   -V'(r) / r = 24 eps (2 (s/r)^12 - (s/r)^6) / r^2.                        */
+/* A pair at zero distance contributes nothing.  Plain O(N^2) sums.          */
+/* ---------------------------------------------------------------------- */
+static int lj_pair(double dx, double dy, double eps, double sig, double rc, double* fr, double* v)
+{
+    const double r2 = dx * dx + dy * dy;
+    if (r2 == 0.0 || r2 >= rc * rc) return 0;
+    const double sr2 = sig * sig / r2;
+    const double sr6 = sr2 * sr2 * sr2;
+    *fr = 24.0 * eps * (2.0 * sr6 * sr6 - sr6) / r2;   /* -V'(r) / r */
+    *v = 4.0 * eps * (sr6 * sr6 - sr6);
+    return 1;
+}
+
+/* Force (fx, fy) on every particle, or on the particles tgt[0..nt) when tgt
+ * != NULL (nt == n otherwise). */
+void oracle_lj_forces(int64_t n, const double* x, const double* y, double eps, double sig, double rc,
+                      int64_t nt, const int64_t* tgt, double* fx, double* fy)
+{
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < nt; ++t) {
+        const int64_t i = tgt ? tgt[t] : t;
+        double ax = 0.0, ay = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double fr, v;
+            if (j == i) continue;
+            const double dx = x[i] - x[j], dy = y[i] - y[j];
+            if (lj_pair(dx, dy, eps, sig, rc, &fr, &v)) {
+                ax += fr * dx;
+                ay += fr * dy;
+            }
+        }
+        fx[t] = ax;
+        fy[t] = ay;
+    }
+}
+
+/* Total potential energy, each pair counted once. */
+double oracle_lj_energy(int64_t n, const double* x, const double* y, double eps, double sig, double rc)
+{
+    double e = 0.0;
+    #pragma omp parallel for schedule(dynamic, 16) reduction(+ : e)
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = i + 1; j < n; ++j) {
+            double fr, v;
+            if (lj_pair(x[i] - x[j], y[i] - y[j], eps, sig, rc, &fr, &v)) e += v;
+        }
+    }
+    return e;
 }
 
 /* ---------------------------------------------------------------------- */
