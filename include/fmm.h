@@ -57,14 +57,27 @@ typedef enum {
     FMM_PREC_MIXED = 1       /* FP32 near field and fine-level M2L; FP64 shifts and coarse M2L */
 } fmm_precision;
 
-/* Pair kernel of the near field.  The far field always uses the expansions
- * of the singular kernel (Section 3, text after eq. 9), so the choice only
- * changes the direct sum over touching leaves.  Section 6.1 templates the
- * evaluator over its kernel for exactly this kind of substitution. */
+/* Pair kernel of the near field.  Section 6.1 templates the evaluator over
+ * its kernel so that one equation can replace another; Section 8 names
+ * further kernels, among them the Lennard-Jones potential of molecular
+ * dynamics.  For the two vortex kernels the far field uses the expansions of
+ * the singular kernel (Section 3, text after eq. 9), so the choice only
+ * changes the direct sum over touching leaves. */
 typedef enum {
     FMM_KERNEL_GAUSSIAN = 0, /* regularised Biot-Savart kernel of eq. 8, core sigma > 0 */
-    FMM_KERNEL_SINGULAR = 1  /* singular Biot-Savart kernel of eq. 7 (point vortices); sigma is
+    FMM_KERNEL_SINGULAR = 1, /* singular Biot-Savart kernel of eq. 7 (point vortices); sigma is
                                 ignored; a pair at zero distance contributes nothing */
+    FMM_KERNEL_LENNARD_JONES = 2
+                             /* Lennard-Jones force, V(r) = 4 eps ((s/r)^12 - (s/r)^6) for
+                                0 < r < cutoff, 0 beyond (truncated, not shifted): d_u, d_v
+                                receive the force sum_j 24 eps (2 (s/r)^12 - (s/r)^6) (x_i -
+                                x_j) / r^2; s = sigma > 0, eps = lj_epsilon > 0, d_gamma is
+                                ignored.  Short range, so there is no far field: the tree
+                                serves as a cell list, and the cutoff may not exceed the leaf
+                                width width / 2^depth (else FMM_E_UNSUPPORTED; a pair closer
+                                than the cutoff by no more than a rounding error at a leaf
+                                edge may be missed).  Needs an explicit square and FP64;
+                                fmm_evaluate and the batched form only */
 } fmm_kernel;
 
 /* Problem parameters, following the paper's problem statement: positions
@@ -84,6 +97,8 @@ typedef struct {
     int64_t m_max;            /* capacity: largest m passed to fmm_evaluate_at (>= 0, < 2^31);
                                  0 = no target points.  Single-instance plans only */
     int32_t kernel;           /* an fmm_kernel value (0: the Gaussian kernel of eq. 8) */
+    double  lj_epsilon;       /* Lennard-Jones energy eps (kernel FMM_KERNEL_LENNARD_JONES only) */
+    double  cutoff;           /* Lennard-Jones cutoff (kernel FMM_KERNEL_LENNARD_JONES only) */
 } fmm_params;
 
 /* Number of bytes of device workspace a plan with these parameters needs.

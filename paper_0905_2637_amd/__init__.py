@@ -22,8 +22,9 @@ FMM_E_DOMAIN = -3
 FMM_E_NOMEM = -4
 FMM_E_DEVICE = -5
 FMM_E_UNSUPPORTED = -6
-FMM_KERNEL_GAUSSIAN, FMM_KERNEL_SINGULAR = 0, 1
-KERNELS = {"gaussian": FMM_KERNEL_GAUSSIAN, "singular": FMM_KERNEL_SINGULAR}
+FMM_KERNEL_GAUSSIAN, FMM_KERNEL_SINGULAR, FMM_KERNEL_LENNARD_JONES = 0, 1, 2
+KERNELS = {"gaussian": FMM_KERNEL_GAUSSIAN, "singular": FMM_KERNEL_SINGULAR,
+           "lennard-jones": FMM_KERNEL_LENNARD_JONES}
 
 FMM_PREC_FP64 = 0
 FMM_PREC_MIXED = 1
@@ -41,7 +42,7 @@ class FmmParams(C.Structure):
     _fields_ = [("n_max", C.c_int64), ("sigma", C.c_double), ("p", C.c_int32), ("depth", C.c_int32),
                 ("x0", C.c_double), ("y0", C.c_double), ("width", C.c_double),
                 ("precision", C.c_int32), ("fp32_fine_levels", C.c_int32), ("m_max", C.c_int64),
-                ("kernel", C.c_int32)]
+                ("kernel", C.c_int32), ("lj_epsilon", C.c_double), ("cutoff", C.c_double)]
 
 
 class FmmError(RuntimeError):
@@ -98,14 +99,15 @@ def status_string(s: int) -> str:
 
 
 def make_params(n_max, sigma, p, depth, domain=(0.0, 0.0, 1.0), precision="fp64", fp32_fine_levels=2, m_max=0,
-                kernel="gaussian"):
+                kernel="gaussian", lj_epsilon=0.0, cutoff=0.0):
     if domain is None:
         x0, y0, w = 0.0, 0.0, 0.0
     else:
         x0, y0, w = domain
     prec = {"fp64": FMM_PREC_FP64, "mixed": FMM_PREC_MIXED}[precision]
     return FmmParams(int(n_max), float(sigma), int(p), int(depth), float(x0), float(y0), float(w), prec,
-                     int(fp32_fine_levels if precision == "mixed" else 0), int(m_max), KERNELS[kernel])
+                     int(fp32_fine_levels if precision == "mixed" else 0), int(m_max), KERNELS[kernel],
+                     float(lj_epsilon), float(cutoff))
 
 
 def workspace_size(prm: FmmParams) -> int:
@@ -245,15 +247,18 @@ class Plan(_PlanBase):
     the square, or None for the particles' bounding square at every call.
     ``m_max`` > 0 reserves room for that many target points (``evaluate_at``).
     ``kernel`` = "gaussian" (eq. 8, core ``sigma``) or "singular" (eq. 7,
-    point vortices; ``sigma`` ignored) for the near field.
+    point vortices; ``sigma`` ignored) for the near field, or
+    "lennard-jones" (length ``sigma``, energy ``lj_epsilon``, ``cutoff`` at
+    most the leaf width): ``evaluate`` then returns the forces.
     """
 
     def __init__(self, n_max, sigma, p, depth, domain=(0.0, 0.0, 1.0), precision="fp64",
-                 fp32_fine_levels=2, device="cuda", m_max=0, kernel="gaussian"):
+                 fp32_fine_levels=2, device="cuda", m_max=0, kernel="gaussian", lj_epsilon=0.0, cutoff=0.0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the FMM runs only on the GPU")
-        self.params = make_params(n_max, sigma, p, depth, domain, precision, fp32_fine_levels, m_max, kernel)
+        self.params = make_params(n_max, sigma, p, depth, domain, precision, fp32_fine_levels, m_max, kernel,
+                                  lj_epsilon, cutoff)
         self.n_max = int(n_max)
         self.m_max = int(m_max)
         self.depth = int(depth)
@@ -356,7 +361,7 @@ class BatchPlan(_PlanBase):
     """
 
     def __init__(self, counts, depths, sigma, p, domain=(0.0, 0.0, 1.0), precision="fp64",
-                 fp32_fine_levels=2, device="cuda", kernel="gaussian"):
+                 fp32_fine_levels=2, device="cuda", kernel="gaussian", lj_epsilon=0.0, cutoff=0.0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the FMM runs only on the GPU")
@@ -368,7 +373,7 @@ class BatchPlan(_PlanBase):
         self.p = int(p)
         self.precision = precision
         self.params = make_params(self.n, sigma, p, max(self.depths), domain, precision, fp32_fine_levels,
-                                  kernel=kernel)
+                                  kernel=kernel, lj_epsilon=lj_epsilon, cutoff=cutoff)
         self.device = torch.device(device)
         self._alloc_workspace(workspace_size_batch(self.params, self.counts, self.depths))
         handle = C.c_void_p()

@@ -106,9 +106,18 @@ int level_blocks_host(int l)
 fmm_status validate_common(const fmm_params* prm)
 {
     if (!prm) return FMM_E_ARG;
-    if (prm->kernel != FMM_KERNEL_GAUSSIAN && prm->kernel != FMM_KERNEL_SINGULAR) return FMM_E_ARG;
-    if (prm->kernel == FMM_KERNEL_GAUSSIAN && (!(prm->sigma > 0.0) || !std::isfinite(prm->sigma)))
+    if (prm->kernel != FMM_KERNEL_GAUSSIAN && prm->kernel != FMM_KERNEL_SINGULAR &&
+        prm->kernel != FMM_KERNEL_LENNARD_JONES)
         return FMM_E_ARG;
+    if (prm->kernel != FMM_KERNEL_SINGULAR && (!(prm->sigma > 0.0) || !std::isfinite(prm->sigma)))
+        return FMM_E_ARG;
+    if (prm->kernel == FMM_KERNEL_LENNARD_JONES) {
+        if (!(prm->lj_epsilon > 0.0) || !std::isfinite(prm->lj_epsilon)) return FMM_E_ARG;
+        if (!(prm->cutoff > 0.0) || !std::isfinite(prm->cutoff)) return FMM_E_ARG;
+        // the 3 x 3 leaves around a particle must hold every partner within the cutoff
+        if (!(prm->width > 0.0)) return FMM_E_UNSUPPORTED;
+        if (prm->precision != FMM_PREC_FP64) return FMM_E_UNSUPPORTED;
+    }
     if (prm->p < 1 || prm->p > kMaxP) return FMM_E_ARG;
     if (prm->precision != FMM_PREC_FP64 && prm->precision != FMM_PREC_MIXED) return FMM_E_ARG;
     if (prm->m_max < 0 || prm->m_max > int64_t(0x7fffffff)) return FMM_E_ARG;
@@ -146,6 +155,13 @@ fmm_status finish_shape(Shape& sh)
     return FMM_OK;
 }
 
+// Lennard-Jones: every partner within the cutoff must lie in the 3 x 3 leaves
+// around a particle, so the cutoff may not exceed the deepest leaf width.
+bool cutoff_fits(const fmm_params* prm, int deepest)
+{
+    return prm->kernel != FMM_KERNEL_LENNARD_JONES || prm->cutoff <= std::ldexp(prm->width, -deepest);
+}
+
 fmm_status single_shape(const fmm_params* prm, Shape& sh)
 {
     if (prm->n_max < 0 || prm->n_max > int64_t(0x7fffffff)) return FMM_E_ARG;
@@ -156,6 +172,7 @@ fmm_status single_shape(const fmm_params* prm, Shape& sh)
     sh.part_off = {0};
     sh.n_cap = prm->n_max;
     sh.m_cap = prm->m_max;
+    if (!cutoff_fits(prm, prm->depth)) return FMM_E_UNSUPPORTED;
     return finish_shape(sh);
 }
 
@@ -176,6 +193,7 @@ fmm_status batch_shape(const fmm_params* prm, int32_t n_inst, const int32_t* cou
     }
     if (tot > int64_t(0x7fffffff)) return FMM_E_ARG;
     sh.n_cap = tot;
+    if (!cutoff_fits(prm, *std::max_element(depths, depths + n_inst))) return FMM_E_UNSUPPORTED;
     return finish_shape(sh);
 }
 
@@ -530,7 +548,8 @@ hipError_t enqueue_all(fmm_plan_s* pl, int64_t n, const double* x, const double*
     auto chk = [&](hipError_t r) { if (e == hipSuccess) e = r; };
     auto mark = [&](int i) { if (timing) chk(hipEventRecord(pl->ev[slot][i], st)); };
     const int P = pl->P, p = pl->prm.p;
-    const bool sing = pl->prm.kernel == FMM_KERNEL_SINGULAR;
+    const NearKernel nk{pl->prm.kernel, pl->prm.sigma, pl->prm.lj_epsilon, pl->prm.cutoff};
+    const bool far = pl->prm.kernel != FMM_KERNEL_LENNARD_JONES;   // short range: near field only
 
     mark(ST_TREE);
     if (pl->auto_domain) chk(launch_domain(b, int(n), x, y, pl->shape.depth[0], st, int(m), tx, ty));
@@ -541,16 +560,16 @@ hipError_t enqueue_all(fmm_plan_s* pl, int64_t n, const double* x, const double*
         const int want = ln.kind == L_UP ? ST_UP : ln.kind == L_M2L ? ST_M2L : ln.kind == L_DOWN ? ST_DOWN : ST_P2P;
         while (stage < want) mark(++stage);
         const Work w = work_of(pl, ln);
+        if (!far && ln.kind != L_P2P) continue;
         switch (ln.kind) {
             case L_UP: chk(launch_upward(b, P, p, w, ln.nwg, ln.leaves, st)); break;
             case L_M2L: chk(launch_m2l(b, P, w, ln.nwg, ln.fp32, pl->tune.m2l_mfma != 0, ln.groups, st)); break;
             case L_DOWN: chk(launch_downward(b, P, w, ln.nwg, st)); break;
             case L_P2P:
                 if (m > 0)
-                    chk(launch_p2p_at(b, P, pl->shape.depth[0], sing, pl->prm.sigma, u, v, st));
+                    chk(launch_p2p_at(b, P, pl->shape.depth[0], nk, u, v, st));
                 else
-                    chk(launch_p2p(b, P, w, ln.nwg, pl->tune.p2p_waves, pl->mixed, sing, pl->prm.sigma, u, v,
-                                   st));
+                    chk(launch_p2p(b, P, w, ln.nwg, pl->tune.p2p_waves, pl->mixed, nk, u, v, st));
                 break;
         }
     }
@@ -792,7 +811,7 @@ fmm_status fmm_evaluate_at(fmm_plan_t plan, int64_t n, const double* d_x, const 
 {
     if (!plan || plan->batch) return FMM_E_ARG;
     if (n < 0 || m < 0) return FMM_E_ARG;
-    if (plan->mixed) return FMM_E_UNSUPPORTED;
+    if (plan->mixed || plan->prm.kernel == FMM_KERNEL_LENNARD_JONES) return FMM_E_UNSUPPORTED;
     if (n > plan->shape.n_cap || m > plan->shape.m_cap) return FMM_E_CAPACITY;
     if (n > 0 && (!d_x || !d_y || !d_gamma)) return FMM_E_ARG;
     if (m > 0 && (!d_tx || !d_ty || !d_u || !d_v)) return FMM_E_ARG;
@@ -859,6 +878,7 @@ fmm_status fmm_advance_rk2(fmm_plan_t plan, int64_t n, double* d_x, double* d_y,
 {
     if (!plan || plan->batch) return FMM_E_ARG;
     if (n < 0 || n_steps < 0 || !std::isfinite(dt)) return FMM_E_ARG;
+    if (plan->prm.kernel == FMM_KERNEL_LENNARD_JONES) return FMM_E_UNSUPPORTED;   // forces, not velocities
     if (n > plan->shape.n_cap) return FMM_E_CAPACITY;
     if (n == 0 || n_steps == 0) return FMM_OK;
     if (!d_x || !d_y || !d_gamma || !d_scratch) return FMM_E_ARG;

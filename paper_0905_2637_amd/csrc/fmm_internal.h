@@ -118,6 +118,17 @@ inline dim3 row_grid(int64_t nwg)
 }
 __device__ __forceinline__ int64_t flat_block() { return blockIdx.x + int64_t(gridDim.x) * blockIdx.y; }
 
+// Near-field pair kernel of a plan.  The far field, where there is one,
+// always uses the expansions of the singular kernel; the Lennard-Jones force
+// is cut off within a leaf width and has none.
+enum NearKind : int { kNearGauss = 0, kNearSingular = 1, kNearLJ = 2 };
+struct NearKernel {
+    int kind;
+    double sigma;     // Gaussian core size, or the Lennard-Jones length s
+    double eps;       // Lennard-Jones energy
+    double cutoff;    // Lennard-Jones cutoff
+};
+
 // Device pointers of one plan, all inside the caller's workspace.
 struct Buffers {
     Inst* inst;            // [n_inst]
@@ -188,12 +199,12 @@ hipError_t launch_upward(const Buffers& b, int P, int p, const Work& w, int nwg,
 hipError_t launch_m2l(const Buffers& b, int P, const Work& w, int nwg, bool fp32, bool mfma, int groups,
                       hipStream_t st);
 hipError_t launch_downward(const Buffers& b, int P, const Work& w, int nwg, hipStream_t st);   // L2L
-// near field with the Gaussian kernel of core sigma, or the singular kernel
-hipError_t launch_p2p(const Buffers& b, int P, const Work& w, int nwg, int waves, bool mixed, bool singular,
-                      double sigma, double* u, double* v, hipStream_t st);
+// near field (+ L2P where there is a far field) with the plan's pair kernel
+hipError_t launch_p2p(const Buffers& b, int P, const Work& w, int nwg, int waves, bool mixed, const NearKernel& nk,
+                      double* u, double* v, hipStream_t st);
 // near field + L2P at the sorted target points of a single-instance FP64 plan
-hipError_t launch_p2p_at(const Buffers& b, int P, int L, bool singular, double sigma, double* u, double* v,
-                         hipStream_t st);
+// (Gaussian or singular kernel)
+hipError_t launch_p2p_at(const Buffers& b, int P, int L, const NearKernel& nk, double* u, double* v, hipStream_t st);
 hipError_t launch_ilist(const Buffers& b, int L, hipStream_t st);
 // a[0..n) = b[0..n) = 0
 hipError_t launch_zero2(int64_t n, double* a, double* b, hipStream_t st);

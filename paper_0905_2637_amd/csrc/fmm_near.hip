@@ -4,7 +4,10 @@
 // regularised kernel of eq. 8, written out as the velocity of eq. 9 in the
 // caller's order.  A plan may select the singular kernel of eq. 7 (point
 // vortices) instead: the Gaussian factor below is then 1, and the kernels
-// are compiled without it.
+// are compiled without it.  Or the Lennard-Jones force of molecular dynamics
+// (a short-range kernel, cut off within a leaf width): then the pair term is
+// 24 eps (2 (s/r)^12 - (s/r)^6) / r^2 times the separation, the output the
+// force itself, and there is no far field.
 //
 // Complex form: phi(z_i) = sum_j gamma_j (1 - exp(-|z_i - z_j|^2 / 2 sigma^2))
 // / (z_i - z_j) over near pairs, plus L2P; u = Im(phi)/(2 pi), v = Re(phi)/(2 pi).
@@ -43,6 +46,12 @@ namespace {
 constexpr double kInv2Pi = 0.15915494309189533576888376337251;
 
 struct Src64 { double x, y, g; };
+
+// Constants of the pair kernel (uniform over a launch).
+struct PairK {
+    double ninv2s2;          // Gaussian core: -1 / (2 sigma^2)
+    double s2, rc2, e24;     // Lennard-Jones: s^2, cutoff^2, 24 eps
+};
 
 // ln 2 split into its nearest double and the remainder (for the reduction
 // -t = k ln2 + r done with fused multiply-adds).
@@ -110,9 +119,9 @@ constexpr int kR = 4;              // most targets per lane
 
 // Sum over staged sources jb + si, jb = 0, S, 2S, ... < padded for the R
 // targets a lane owns.  FP32 leaf-relative form: coordinates in leaf widths,
-// exp(-t) = 2^(-t log2 e) with c2 = w^2 log2(e) / (2 sigma^2).  SING: the
-// singular kernel of eq. 7 (no Gaussian factor).
-template <int R, bool SING>
+// exp(-t) = 2^(-t log2 e) with c2 = w^2 log2(e) / (2 sigma^2).  The singular
+// kernel of eq. 7 has no Gaussian factor.  (No Lennard-Jones form in FP32.)
+template <int R, int KER>
 __device__ __forceinline__ void p2p_f32(const float4* __restrict__ src, int padded, int S, int si, float c2,
                                         const float* ox, const float* oy, float* fx, float* fy)
 {
@@ -124,7 +133,7 @@ __device__ __forceinline__ void p2p_f32(const float4* __restrict__ src, int padd
             const float dx = ox[r] - t.x, dy = oy[r] - t.y;
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));    // > 0, as in the FP64 form
             float q2;
-            if constexpr (SING) {
+            if constexpr (KER == kNearSingular) {
                 q2 = t.z * __builtin_amdgcn_rcpf(r2);
             } else {
                 const float e = __builtin_amdgcn_exp2f(-r2 * c2);
@@ -136,8 +145,20 @@ __device__ __forceinline__ void p2p_f32(const float4* __restrict__ src, int padd
     }
 }
 
-template <int R, bool SING>
-__device__ __forceinline__ void p2p_f64(const Src64* __restrict__ src, int padded, int S, int si, double ninv2s2,
+// Lennard-Jones pair term -V'(r) / r = 24 eps (2 (s/r)^12 - (s/r)^6) / r^2 for
+// 0 < r < rc, else 0 (a select, so the infinities of r = 0 never reach the
+// sums).
+__device__ __forceinline__ double lj_term(double r2, const PairK& k)
+{
+    const double ir2 = recip(r2);
+    const double s2 = k.s2 * ir2;
+    const double s6 = s2 * s2 * s2;
+    const double f = k.e24 * s6 * fma(2.0, s6, -1.0) * ir2;
+    return (r2 > 0.0 && r2 < k.rc2) ? f : 0.0;
+}
+
+template <int R, int KER>
+__device__ __forceinline__ void p2p_f64(const Src64* __restrict__ src, int padded, int S, int si, const PairK& k,
                                         const double* x, const double* y, double* ax, double* ay)
 {
     for (int jb = 0; jb < padded; jb += S) {
@@ -148,10 +169,14 @@ __device__ __forceinline__ void p2p_f64(const Src64* __restrict__ src, int padde
             // 1e-300 keeps r2 positive for coincident points, whose term
             // then vanishes through dx = dy = 0; it changes r2 only for
             // points closer than about 1e-142
-            const double r2 = fma(dx, dx, fma(dy, dy, 1e-300));
             double q2;
-            if constexpr (SING) q2 = t.g * recip(r2);
-            else q2 = t.g * one_minus_exp(r2 * ninv2s2) * recip(r2);
+            if constexpr (KER == kNearLJ) {
+                q2 = lj_term(fma(dx, dx, dy * dy), k);   // gamma takes no part
+            } else {
+                const double r2 = fma(dx, dx, fma(dy, dy, 1e-300));
+                if constexpr (KER == kNearSingular) q2 = t.g * recip(r2);
+                else q2 = t.g * one_minus_exp(r2 * k.ninv2s2) * recip(r2);
+            }
             ax[r] = fma(q2, dx, ax[r]);
             ay[r] = fma(-q2, dy, ay[r]);
         }
@@ -164,8 +189,9 @@ struct LeafCtx {
     int s0, nt;                 // its sorted particle range
     int nbeg[9], npre[10];      // the 3 x 3 neighbourhood: starts and running counts
     int lgT;                    // log2 of the targets per chunk
-    double cx, cy, s, inv2s2;   // leaf centre, 1/leaf width, 1/(2 sigma^2)
+    double cx, cy, s;           // leaf centre, 1/leaf width
     float c2;                   // w^2 log2(e) / (2 sigma^2)
+    PairK k;                    // the pair kernel's constants
 };
 
 constexpr int kStageSlots = kNearStage / 64;   // staged sources per lane and chunk
@@ -176,7 +202,7 @@ constexpr int kStageSlots = kNearStage / 64;   // staged sources per lane and ch
 // go to sink[i] for target i of the leaf instead of being finished here.
 // tx, ty: the targets' sorted positions (the particles' own for the particle
 // sum), perm: their sorted position -> output index.
-template <int P, bool MIXED, int R, bool SING>
+template <int P, bool MIXED, int R, int KER>
 __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* stage_raw, cd* le_sh, int has_far,
                                               const double* __restrict__ tx, const double* __restrict__ ty,
                                               const double* __restrict__ xs, const double* __restrict__ ys,
@@ -267,8 +293,8 @@ __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* 
                 if (k < padded) src[k] = val[sl];
             }
             wave_sync();
-            if constexpr (MIXED) p2p_f32<R, SING>(src, padded, S, si, c.c2, oxi, oyi, fx, fy);
-            else p2p_f64<R, SING>(src, padded, S, si, -c.inv2s2, xi, yi, ax, ay);
+            if constexpr (MIXED) p2p_f32<R, KER>(src, padded, S, si, c.c2, oxi, oyi, fx, fy);
+            else p2p_f64<R, KER>(src, padded, S, si, c.k, xi, yi, ax, ay);
         }
 
         // combine the S slices: every lane of a target group ends with the sums
@@ -320,8 +346,13 @@ __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* 
                 accx += hx * c.s;
                 accy += hy * c.s;
             }
-            u[o] = accy * kInv2Pi;
-            v[o] = accx * kInv2Pi;
+            if constexpr (KER == kNearLJ) {    // the force (Fx, Fy) = (sum q dx, sum q dy)
+                u[o] = accx;
+                v[o] = -accy;
+            } else {
+                u[o] = accy * kInv2Pi;
+                v[o] = accx * kInv2Pi;
+            }
         }
     }
 }
@@ -330,8 +361,10 @@ __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* 
 // row by row (clipped leaves are empty; with no_siblings, so are the other
 // three leaves of its quad).
 __device__ __forceinline__ void make_ctx(LeafCtx& c, uint32_t m, int L, const int32_t* __restrict__ leaf_start,
-                                         const Domain& d, double inv2s2, bool no_siblings)
+                                         const Domain& d, const PairK& k, bool no_siblings)
 {
+    const double inv2s2 = -k.ninv2s2;
+    c.k = k;
     c.m = m;
     c.s0 = leaf_start[m];
     c.nt = leaf_start[m + 1] - c.s0;
@@ -355,7 +388,6 @@ __device__ __forceinline__ void make_ctx(LeafCtx& c, uint32_t m, int L, const in
     c.cx = d.x0 + (double(a) + 0.5) * w;
     c.cy = d.y0 + (double(b) + 0.5) * w;
     c.s = d.s;
-    c.inv2s2 = inv2s2;
     // leaf-width units: |z|^2 / (2 sigma^2) = |zhat|^2 w^2 / (2 sigma^2), and
     // exp(-t) = 2^(-t log2(e)); w = 1/s
     c.c2 = float(inv2s2 * 1.4426950408889634074 / (d.s * d.s));
@@ -363,7 +395,7 @@ __device__ __forceinline__ void make_ctx(LeafCtx& c, uint32_t m, int L, const in
 
 // register blocking pays once a chunk is full; sparse leaves keep one target
 // per lane (fewer slices to combine)
-template <int P, bool MIXED, bool SING>
+template <int P, bool MIXED, int KER>
 __device__ __forceinline__ void leaf_dispatch(const LeafCtx& c, int lane, void* st, cd* lsh, int has_far,
                                               const double* __restrict__ tx, const double* __restrict__ ty,
                                               const double* __restrict__ xs, const double* __restrict__ ys,
@@ -372,11 +404,11 @@ __device__ __forceinline__ void leaf_dispatch(const LeafCtx& c, int lane, void* 
                                               cd* sink, double* __restrict__ u, double* __restrict__ v)
 {
     if (c.lgT == 6)
-        leaf_near_far<P, MIXED, 4, SING>(c, lane, st, lsh, has_far, tx, ty, xs, ys, gs, pk, perm, le_leaf, sink, u, v);
+        leaf_near_far<P, MIXED, 4, KER>(c, lane, st, lsh, has_far, tx, ty, xs, ys, gs, pk, perm, le_leaf, sink, u, v);
     else if (c.lgT == 5)
-        leaf_near_far<P, MIXED, 2, SING>(c, lane, st, lsh, has_far, tx, ty, xs, ys, gs, pk, perm, le_leaf, sink, u, v);
+        leaf_near_far<P, MIXED, 2, KER>(c, lane, st, lsh, has_far, tx, ty, xs, ys, gs, pk, perm, le_leaf, sink, u, v);
     else
-        leaf_near_far<P, MIXED, 1, SING>(c, lane, st, lsh, has_far, tx, ty, xs, ys, gs, pk, perm, le_leaf, sink, u, v);
+        leaf_near_far<P, MIXED, 1, KER>(c, lane, st, lsh, has_far, tx, ty, xs, ys, gs, pk, perm, le_leaf, sink, u, v);
 }
 
 // Quads of sibling leaves: the four leaves of a 2 x 2 block touch each other,
@@ -394,19 +426,27 @@ __device__ __forceinline__ void leaf_dispatch(const LeafCtx& c, int lane, void* 
 // they save.
 constexpr int kQuadMax = 64;
 
-template <bool SING>
-__device__ __forceinline__ void quad_pairs(const Src64* qsh, int lane, int w, double ninv2s2, double& sx, double& sy)
+template <int KER>
+__device__ __forceinline__ void quad_pairs(const Src64* qsh, int lane, int w, const PairK& k, double& sx, double& sy)
 {
     const Src64 me = qsh[lane];
     double ax = 0.0, ay = 0.0;
     auto step = [&](int s, bool act) {
         const Src64 t = qsh[(lane + s) & 63];
         const double dx = me.x - t.x, dy = me.y - t.y;
-        const double r2 = fma(dx, dx, fma(dy, dy, 1e-300));
-        double q;
-        if constexpr (SING) q = recip(r2);
-        else q = one_minus_exp(r2 * ninv2s2) * recip(r2);
-        const double qi = act ? t.g * q : 0.0, qj = act ? me.g * q : 0.0;
+        double qi, qj;
+        if constexpr (KER == kNearLJ) {       // no circulation; the padding lies out of range
+            const double q = lj_term(fma(dx, dx, dy * dy), k);
+            qi = act ? q : 0.0;
+            qj = qi;
+        } else {
+            const double r2 = fma(dx, dx, fma(dy, dy, 1e-300));
+            double q;
+            if constexpr (KER == kNearSingular) q = recip(r2);
+            else q = one_minus_exp(r2 * k.ninv2s2) * recip(r2);
+            qi = act ? t.g * q : 0.0;
+            qj = act ? me.g * q : 0.0;
+        }
         ax = fma(qi, dx, ax);
         ay = fma(-qi, dy, ay);
         const int from = (lane - s) & 63;
@@ -421,12 +461,12 @@ __device__ __forceinline__ void quad_pairs(const Src64* qsh, int lane, int w, do
 
 // WAVES wavefronts per workgroup, one leaf each (four: one quad); the work
 // table gives every instance ceil(4^L / WAVES) workgroups.
-template <int P, bool MIXED, int WAVES, bool SING>
+template <int P, bool MIXED, int WAVES, int KER>
 __global__ void __launch_bounds__(64 * WAVES)
 k_p2p_l2p(Work wk, int n_inst, const Inst* __restrict__ inst, const int32_t* __restrict__ leaf_start_all,
           const double* __restrict__ xs, const double* __restrict__ ys, const double* __restrict__ gs,
           const float4* __restrict__ pk, const uint32_t* __restrict__ perm, const cd* __restrict__ le_all,
-          double inv2s2, double* __restrict__ u, double* __restrict__ v)
+          PairK kp, double* __restrict__ u, double* __restrict__ v)
 {
     using Stage = typename std::conditional<MIXED, float4, Src64>::type;
     constexpr bool kQuads = WAVES == 4 && !MIXED;
@@ -442,7 +482,7 @@ k_p2p_l2p(Work wk, int n_inst, const Inst* __restrict__ inst, const int32_t* __r
     const int pos = find_inst(wk.wg_begin, n_inst, int(blk));      // place in the launch order
     const int qi = wk.order[pos];
     const int L = inst[qi].L;
-    const int has_far = L >= 2 ? 1 : 0;
+    const int has_far = KER != kNearLJ && L >= 2 ? 1 : 0;   // Lennard-Jones: no far field
     const int32_t* leaf_start = leaf_start_all + inst[qi].leaf_off;
     const cd* le_leaf = le_all + (inst[qi].box_off + level_offset(L)) * P;
     const int64_t nleaf = int64_t(1) << (2 * L);
@@ -464,15 +504,14 @@ k_p2p_l2p(Work wk, int n_inst, const Inst* __restrict__ inst, const int32_t* __r
     if (!(kQuads && nq > 1 && nq <= kQuadMax)) {
         if (mm >= nleaf) return;
         LeafCtx c;
-        make_ctx(c, uint32_t(mm), L, leaf_start, d, inv2s2, false);
+        make_ctx(c, uint32_t(mm), L, leaf_start, d, kp, false);
         if (c.nt == 0) return;
-        leaf_dispatch<P, MIXED, SING>(c, lane, st, lsh, has_far, xs, ys, xs, ys, gs, pk, perm, le_leaf, nullptr, u,
-                                      v);
+        leaf_dispatch<P, MIXED, KER>(c, lane, st, lsh, has_far, xs, ys, xs, ys, gs, pk, perm, le_leaf, nullptr, u, v);
         return;
     }
 
     LeafCtx c;
-    make_ctx(c, uint32_t(mm), L, leaf_start, d, inv2s2, true);
+    make_ctx(c, uint32_t(mm), L, leaf_start, d, kp, true);
     // stage the quad, one particle per lane (past nq: inert, far away and
     // without circulation)
     if (wv == 0) {
@@ -482,11 +521,11 @@ k_p2p_l2p(Work wk, int n_inst, const Inst* __restrict__ inst, const int32_t* __r
     __syncthreads();
     // the leaf's targets against the neighbours outside the quad
     if (c.nt > 0)
-        leaf_dispatch<P, MIXED, SING>(c, lane, st, lsh, 0, xs, ys, xs, ys, gs, pk, perm, le_leaf,
-                                      part_sh[0] + (c.s0 - sq), u, v);
+        leaf_dispatch<P, MIXED, KER>(c, lane, st, lsh, 0, xs, ys, xs, ys, gs, pk, perm, le_leaf,
+                                     part_sh[0] + (c.s0 - sq), u, v);
     // this wavefront's share of the pairs inside the quad
     double ix, iy;
-    quad_pairs<SING>(qsh, lane, wv, -inv2s2, ix, iy);
+    quad_pairs<KER>(qsh, lane, wv, kp, ix, iy);
     part_sh[1 + wv][lane] = cd{ix, iy};
     __syncthreads();
     if (c.nt == 0) return;
@@ -516,8 +555,13 @@ k_p2p_l2p(Work wk, int n_inst, const Inst* __restrict__ inst, const int32_t* __r
             accy += hy * c.s;
         }
         const uint32_t o = perm[i];
-        u[o] = accy * kInv2Pi;
-        v[o] = accx * kInv2Pi;
+        if constexpr (KER == kNearLJ) {
+            u[o] = accx;
+            v[o] = -accy;
+        } else {
+            u[o] = accy * kInv2Pi;
+            v[o] = accx * kInv2Pi;
+        }
     }
 }
 
@@ -525,12 +569,12 @@ k_p2p_l2p(Work wk, int n_inst, const Inst* __restrict__ inst, const int32_t* __r
 // wavefront per leaf of the points' tree, its points against the particles
 // of the 3 x 3 neighbourhood, plus L2P from the leaf's local expansion.
 // Single instance, FP64.
-template <int P, bool SING>
+template <int P, int KER>
 __global__ void __launch_bounds__(256)
 k_p2p_at(int L, const Inst* __restrict__ inst, const int32_t* __restrict__ leaf_start,
          const int32_t* __restrict__ tleaf_start, const double* __restrict__ xs, const double* __restrict__ ys,
          const double* __restrict__ gs, const double* __restrict__ txs, const double* __restrict__ tys,
-         const uint32_t* __restrict__ tperm, const cd* __restrict__ le_all, double inv2s2, double* __restrict__ u,
+         const uint32_t* __restrict__ tperm, const cd* __restrict__ le_all, PairK kp, double* __restrict__ u,
          double* __restrict__ v)
 {
     __shared__ Src64 stage_all[4][kNearStage];
@@ -540,60 +584,83 @@ k_p2p_at(int L, const Inst* __restrict__ inst, const int32_t* __restrict__ leaf_
     const int64_t mm = flat_block() * 4 + wv;
     if (mm >= (int64_t(1) << (2 * L))) return;
     LeafCtx c;
-    make_ctx(c, uint32_t(mm), L, leaf_start, inst[0].dom, inv2s2, false);   // the particles around the leaf
+    make_ctx(c, uint32_t(mm), L, leaf_start, inst[0].dom, kp, false);   // the particles around the leaf
     c.s0 = tleaf_start[mm];                                                    // and the leaf's points
     c.nt = tleaf_start[mm + 1] - c.s0;
     if (c.nt == 0) return;
     c.lgT = c.nt >= 64 ? 6 : (c.nt <= 1 ? 0 : 32 - __clz(c.nt - 1));
     const cd* le_leaf = le_all + (inst[0].box_off + level_offset(L)) * P;
-    leaf_dispatch<P, false, SING>(c, lane, stage_all[wv], le_all_sh[wv], L >= 2 ? 1 : 0, txs, tys, xs, ys, gs,
-                                  nullptr, tperm, le_leaf, nullptr, u, v);
+    leaf_dispatch<P, false, KER>(c, lane, stage_all[wv], le_all_sh[wv], L >= 2 ? 1 : 0, txs, tys, xs, ys, gs,
+                                 nullptr, tperm, le_leaf, nullptr, u, v);
 }
 
-// 1/(2 sigma^2) of the Gaussian core; unused (0) by the singular kernel
-double core_factor(double sigma, bool singular) { return singular ? 0.0 : 1.0 / (2.0 * sigma * sigma); }
+// The pair kernel's constants from the plan's choice.
+PairK pair_constants(const NearKernel& nk)
+{
+    PairK k{};
+    if (nk.kind == kNearGauss) k.ninv2s2 = -1.0 / (2.0 * nk.sigma * nk.sigma);
+    if (nk.kind == kNearLJ) {
+        k.s2 = nk.sigma * nk.sigma;
+        k.rc2 = nk.cutoff * nk.cutoff;
+        k.e24 = 24.0 * nk.eps;
+    }
+    return k;
+}
 
-template <int P, int WAVES, bool SING>
-void p2p_launch(const Buffers& b, const Work& w, int nwg, bool mixed, double inv2s2, double* u, double* v,
+template <int P, int WAVES, int KER>
+void p2p_launch(const Buffers& b, const Work& w, int nwg, bool mixed, const PairK& k, double* u, double* v,
                 hipStream_t st)
 {
-    if (mixed)
-        hipLaunchKernelGGL((k_p2p_l2p<P, true, WAVES, SING>), row_grid(nwg), dim3(64 * WAVES), 0, st, w,
-                           b.n_inst, b.inst, b.leaf_start, b.xs, b.ys, b.gs, b.pk, b.perm, b.le, inv2s2, u, v);
-    else
-        hipLaunchKernelGGL((k_p2p_l2p<P, false, WAVES, SING>), row_grid(nwg), dim3(64 * WAVES), 0, st, w,
-                           b.n_inst, b.inst, b.leaf_start, b.xs, b.ys, b.gs, b.pk, b.perm, b.le, inv2s2, u, v);
+    if constexpr (KER != kNearLJ) {
+        if (mixed) {
+            hipLaunchKernelGGL((k_p2p_l2p<P, true, WAVES, KER>), row_grid(nwg), dim3(64 * WAVES), 0, st, w,
+                               b.n_inst, b.inst, b.leaf_start, b.xs, b.ys, b.gs, b.pk, b.perm, b.le, k, u, v);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_p2p_l2p<P, false, WAVES, KER>), row_grid(nwg), dim3(64 * WAVES), 0, st, w, b.n_inst,
+                       b.inst, b.leaf_start, b.xs, b.ys, b.gs, b.pk, b.perm, b.le, k, u, v);
+}
+
+template <int P, int WAVES>
+void p2p_kernel(const Buffers& b, const Work& w, int nwg, bool mixed, const NearKernel& nk, double* u, double* v,
+                hipStream_t st)
+{
+    const PairK k = pair_constants(nk);
+    if (nk.kind == kNearSingular) p2p_launch<P, WAVES, kNearSingular>(b, w, nwg, mixed, k, u, v, st);
+    else if (nk.kind == kNearLJ) p2p_launch<P, WAVES, kNearLJ>(b, w, nwg, mixed, k, u, v, st);
+    else p2p_launch<P, WAVES, kNearGauss>(b, w, nwg, mixed, k, u, v, st);
 }
 
 template <int P>
-hipError_t p2p_waves(const Buffers& b, const Work& w, int nwg, int waves, bool mixed, bool singular, double sigma,
+hipError_t p2p_waves(const Buffers& b, const Work& w, int nwg, int waves, bool mixed, const NearKernel& nk,
                      double* u, double* v, hipStream_t st)
 {
     if (nwg <= 0) return hipSuccess;
     if (waves != 2 && waves != 4) return hipErrorInvalidValue;
-    const double inv2s2 = core_factor(sigma, singular);
-    if (waves == 2 && singular) p2p_launch<P, 2, true>(b, w, nwg, mixed, inv2s2, u, v, st);
-    else if (waves == 2) p2p_launch<P, 2, false>(b, w, nwg, mixed, inv2s2, u, v, st);
-    else if (singular) p2p_launch<P, 4, true>(b, w, nwg, mixed, inv2s2, u, v, st);
-    else p2p_launch<P, 4, false>(b, w, nwg, mixed, inv2s2, u, v, st);
+    if (nk.kind != kNearGauss && nk.kind != kNearSingular && nk.kind != kNearLJ) return hipErrorInvalidValue;
+    if (mixed && nk.kind == kNearLJ) return hipErrorInvalidValue;
+    if (waves == 2) p2p_kernel<P, 2>(b, w, nwg, mixed, nk, u, v, st);
+    else p2p_kernel<P, 4>(b, w, nwg, mixed, nk, u, v, st);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_p2p_at(const Buffers& b, int P, int L, bool singular, double sigma, double* u, double* v,
-                         hipStream_t st)
+hipError_t launch_p2p_at(const Buffers& b, int P, int L, const NearKernel& nk, double* u, double* v, hipStream_t st)
 {
-    const double inv2s2 = core_factor(sigma, singular);
+    if (nk.kind != kNearGauss && nk.kind != kNearSingular) return hipErrorInvalidValue;
+    const bool singular = nk.kind == kNearSingular;
+    const PairK kp = pair_constants(nk);
     const dim3 grid = row_grid(((int64_t(1) << (2 * L)) + 3) / 4);
 #define FMM_AT_CASE(PP)                                                                                            \
     case PP:                                                                                                       \
         if (singular)                                                                                              \
-            hipLaunchKernelGGL((k_p2p_at<PP, true>), grid, dim3(256), 0, st, L, b.inst, b.leaf_start,             \
-                               b.tleaf_start, b.xs, b.ys, b.gs, b.txs, b.tys, b.tperm, b.le, inv2s2, u, v);        \
+            hipLaunchKernelGGL((k_p2p_at<PP, kNearSingular>), grid, dim3(256), 0, st, L, b.inst, b.leaf_start,    \
+                               b.tleaf_start, b.xs, b.ys, b.gs, b.txs, b.tys, b.tperm, b.le, kp, u, v);            \
         else                                                                                                       \
-            hipLaunchKernelGGL((k_p2p_at<PP, false>), grid, dim3(256), 0, st, L, b.inst, b.leaf_start,            \
-                               b.tleaf_start, b.xs, b.ys, b.gs, b.txs, b.tys, b.tperm, b.le, inv2s2, u, v);        \
+            hipLaunchKernelGGL((k_p2p_at<PP, kNearGauss>), grid, dim3(256), 0, st, L, b.inst, b.leaf_start,       \
+                               b.tleaf_start, b.xs, b.ys, b.gs, b.txs, b.tys, b.tperm, b.le, kp, u, v);            \
         return hipGetLastError();
     switch (P) {
         FMM_AT_CASE(8)
@@ -608,17 +675,17 @@ hipError_t launch_p2p_at(const Buffers& b, int P, int L, bool singular, double s
 #undef FMM_AT_CASE
 }
 
-hipError_t launch_p2p(const Buffers& b, int P, const Work& w, int nwg, int waves, bool mixed, bool singular,
-                      double sigma, double* u, double* v, hipStream_t st)
+hipError_t launch_p2p(const Buffers& b, int P, const Work& w, int nwg, int waves, bool mixed, const NearKernel& nk,
+                      double* u, double* v, hipStream_t st)
 {
     switch (P) {
-        case 8: return p2p_waves<8>(b, w, nwg, waves, mixed, singular, sigma, u, v, st);
-        case 12: return p2p_waves<12>(b, w, nwg, waves, mixed, singular, sigma, u, v, st);
-        case 16: return p2p_waves<16>(b, w, nwg, waves, mixed, singular, sigma, u, v, st);
-        case 17: return p2p_waves<17>(b, w, nwg, waves, mixed, singular, sigma, u, v, st);
-        case 20: return p2p_waves<20>(b, w, nwg, waves, mixed, singular, sigma, u, v, st);
-        case 24: return p2p_waves<24>(b, w, nwg, waves, mixed, singular, sigma, u, v, st);
-        case 32: return p2p_waves<32>(b, w, nwg, waves, mixed, singular, sigma, u, v, st);
+        case 8: return p2p_waves<8>(b, w, nwg, waves, mixed, nk, u, v, st);
+        case 12: return p2p_waves<12>(b, w, nwg, waves, mixed, nk, u, v, st);
+        case 16: return p2p_waves<16>(b, w, nwg, waves, mixed, nk, u, v, st);
+        case 17: return p2p_waves<17>(b, w, nwg, waves, mixed, nk, u, v, st);
+        case 20: return p2p_waves<20>(b, w, nwg, waves, mixed, nk, u, v, st);
+        case 24: return p2p_waves<24>(b, w, nwg, waves, mixed, nk, u, v, st);
+        case 32: return p2p_waves<32>(b, w, nwg, waves, mixed, nk, u, v, st);
         default: return hipErrorInvalidValue;
     }
 }
