@@ -301,6 +301,34 @@ def run_points(wl, args, dev, m_side=1024):
     return sec, m, {k: round(vv, 4) for k, vv in stages.items() if k != "evaluations"}
 
 
+def run_lennard_jones(args, dev, m_side=1024):
+    """Lennard-Jones forces on an m_side^2 jittered lattice in the unit square
+    (spacing a, s = a / 1.12, cutoff 2.5 s, depth 8: leaves of 16 particles,
+    wider than the cutoff), FP64, near field only."""
+    import torch
+    import paper_0905_2637_amd as fm
+    rng = np.random.default_rng(900)
+    a = 1.0 / m_side
+    c = (np.arange(m_side) + 0.5) * a
+    X, Y = np.meshgrid(c, c)
+    n = m_side * m_side
+    x = torch.as_tensor(X.ravel() + rng.uniform(-0.2 * a, 0.2 * a, n), device=dev)
+    y = torch.as_tensor(Y.ravel() + rng.uniform(-0.2 * a, 0.2 * a, n), device=dev)
+    g = torch.zeros(n, dtype=torch.float64, device=dev)
+    fx = torch.empty_like(g)
+    fy = torch.empty_like(g)
+    s = a / 1.12
+    plan = fm.Plan(n, s, 8, 8, kernel="lennard-jones", lj_epsilon=1.0, cutoff=2.5 * s)
+    for _ in range(args.warmup):
+        plan.evaluate(x, y, g, fx, fy)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    sec = timed(lambda: plan.evaluate(x, y, g, fx, fy), args.steps, 0)
+    stages = plan.stats()
+    plan.close()
+    return sec, n, {k: round(vv, 4) for k, vv in stages.items() if k in ("tree", "p2p_l2p")}
+
+
 # ---------------------------------------------------------------------------
 # CPU oracle leg (the only part of the bench that touches the oracle)
 # ---------------------------------------------------------------------------
@@ -426,6 +454,10 @@ def main() -> int:
         forms["points"] = {"workload": "C2 particles, velocity on a 1024 x 1024 vertex lattice of points "
                                        "(FP64, eq. 1 with targets apart from the sources)",
                            "ms": round(tp * 1e3, 4), "points_per_s": mp / tp, "stages_ms": sp}
+        tl, nl, sl = run_lennard_jones(args, dev)
+        forms["lennard_jones"] = {"workload": "2^20 Lennard-Jones particles, jittered 1024 x 1024 lattice, s = a/1.12, "
+                                              "cutoff 2.5 s, depth 8 (FP64 forces, near field only)",
+                                  "ms": round(tl * 1e3, 4), "particles_per_s": nl / tl, "stages_ms": sl}
         w4 = workloads.make("C4")
         rb = run_batch(w4, args, dev)
         rb64 = run_batch(w4, args, dev, precision="fp64")
