@@ -121,8 +121,11 @@ fmm_status fmm_plan(const fmm_params* prm, void* d_workspace, size_t bytes,
  *   n                  number of particles, 0 <= n <= n_max
  *   d_x, d_y, d_gamma  device FP64 arrays [n]: positions and circulations
  *   d_u, d_v           device FP64 arrays [n]: velocity components (eq. 9),
- *                      overwritten, in input order
- * Asynchronous on `stream`.  Particles outside an explicit domain (or with a
+ *                      overwritten, in input order (with the Lennard-Jones
+ *                      kernel: the force, after the tree and the near field
+ *                      alone)
+ * Asynchronous on `stream`; kernels only (no allocation, no memset, no
+ * synchronisation), so a caller may capture it into a graph.  Particles outside an explicit domain (or with a
  * NaN coordinate) are clamped into the nearest leaf and counted; read the
  * count with fmm_get_status.  Errors (synchronous): FMM_E_ARG (NULL plan or
  * pointers with n > 0), FMM_E_CAPACITY (n > n_max), FMM_E_DEVICE. */

@@ -144,7 +144,7 @@ def _check_inputs(n, tensors):
     import torch
     for t in tensors:
         if t.dtype != torch.float64 or t.device.type != "cuda" or not t.is_contiguous() or t.shape[0] != n:
-            raise ValueError("x, y, gamma, u, v must be contiguous float64 CUDA tensors of equal length")
+            raise ValueError(f"inputs and outputs must be contiguous float64 CUDA tensors of length {n}")
 
 
 class _PlanBase:
@@ -284,7 +284,8 @@ class Plan(_PlanBase):
         return u, v
 
     def evaluate(self, x, y, gamma, u=None, v=None, check=False):
-        """Velocity (u, v) of eq. 9 at every particle; FP64 device tensors."""
+        """Velocity (u, v) of eq. 9 at every particle (with the Lennard-Jones
+        kernel: the force); FP64 device tensors."""
         n = int(x.shape[0])
         u, v = self._outputs(x, u, v)
         _check_inputs(n, (x, y, gamma, u, v))
