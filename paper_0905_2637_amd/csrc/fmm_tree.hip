@@ -293,6 +293,11 @@ k_rhist(int n, const uint32_t* __restrict__ kin, int shift, int nblk, int32_t* _
     if (threadIdx.x < kRadixBins) hist[int64_t(threadIdx.x) * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
+// Scatter tiles go to the XCDs in runs of this many from this many tiles on
+// (below it the remapping measured no gain).
+constexpr int kScatterXcdRun = 16;
+constexpr int kScatterXcdMinTiles = 512;
+
 // Where a sorted record goes, and what it carries.
 struct Records {
     uint32_t* k;
@@ -334,7 +339,11 @@ k_rscatter(int n, const uint32_t* __restrict__ kin, const uint32_t* __restrict__
     __shared__ uint32_t sk[kRadixTile];
     __shared__ double sv[kRadixTile];
     const int tid = threadIdx.x, lane = int(__lane_id()), w = tid >> 6;
-    const int64_t tile = int64_t(blockIdx.x) * kRadixTile;
+    // large sorts: runs of kScatterXcdRun consecutive tiles per XCD, so that
+    // the runs of one digit that neighbouring tiles write side by side meet
+    // in one L2 (whole lines go out) instead of leaving partial lines in two
+    const int blk = nblk >= kScatterXcdMinTiles ? xcd_runs(int(blockIdx.x), nblk, kScatterXcdRun) : int(blockIdx.x);
+    const int64_t tile = int64_t(blk) * kRadixTile;
     const int tile_n = int(min(int64_t(kRadixTile), int64_t(n) - tile));
     constexpr int kWaveKeys = kRadixTile / kScatterWaves;
 
@@ -342,8 +351,8 @@ k_rscatter(int n, const uint32_t* __restrict__ kin, const uint32_t* __restrict__
     // into tstart; the first four wavefronts hold it
     int hv = 0, hinc = 0;
     if (tid < kRadixBins) {
-        hv = hist[int64_t(tid) * nblk + blockIdx.x];
-        gbase[tid] = offs[int64_t(tid) * nblk + blockIdx.x];
+        hv = hist[int64_t(tid) * nblk + blk];
+        gbase[tid] = offs[int64_t(tid) * nblk + blk];
         hinc = wave_incl_scan(hv);
         if (lane == 63) wsum[w] = hinc;
     }
