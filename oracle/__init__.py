@@ -84,6 +84,11 @@ def _load():
     lib.oracle_lj_forces.argtypes = [i64, dp, dp, C.c_double, C.c_double, C.c_double, i64, i64p, dp, dp]
     lib.oracle_lj_energy.argtypes = [i64, dp, dp, C.c_double, C.c_double, C.c_double]
     lib.oracle_lj_energy.restype = C.c_double
+    lib.oracle_hermite.argtypes = [C.c_int, C.c_double, dp]
+    lib.oracle_gauss_direct.argtypes = [i64, dp, dp, dp, C.c_double, i64, i64p, dp]
+    lib.oracle_fgt.argtypes = [i64, dp, dp, dp, C.c_double, C.c_int, C.c_int, C.c_double, C.c_double,
+                               C.c_double, C.c_int, dp]
+    lib.oracle_fgt.restype = i64
     lib.oracle_init()
     _lib = lib
     return lib
@@ -341,4 +346,31 @@ def lj_energy(x, y, eps, sig, rc):
     """Total Lennard-Jones energy (truncated at rc), each pair once."""
     x, y = _f64(x), _f64(y)
     return float(_load().oracle_lj_energy(x.shape[0], _d(x), _d(y), eps, sig, rc))
+
+
+def hermite(m, t):
+    """Hermite functions h_0 .. h_{m-1} at t (h_n = (-1)^n d^n/dt^n exp(-t^2))."""
+    h = np.zeros(max(m, 1))
+    _load().oracle_hermite(int(m), float(t), _d(h))
+    return h[:m]
+
+
+def gauss_direct(x, y, q, sigma, targets=None):
+    """Plain Gauss transform sum_j q_j exp(-|x_i - x_j|^2 / (2 sigma^2)) at the particles."""
+    lib = _load()
+    x, y, q = _f64(x), _f64(y), _f64(q)
+    n = x.shape[0]
+    t, nt, tp = _targets(targets, n)
+    G = np.zeros(nt)
+    lib.oracle_gauss_direct(n, _d(x), _d(y), _d(q), sigma, nt, tp, _d(G))
+    return G
+
+
+def fgt(x, y, q, sigma, p, L, nc, x0=0.0, y0=0.0, W=1.0):
+    """Fast Gauss transform (Hermite / Taylor on the leaf boxes); returns (G, nbad)."""
+    lib = _load()
+    x, y, q = _f64(x), _f64(y), _f64(q)
+    G = np.zeros(x.shape[0])
+    nbad = lib.oracle_fgt(x.shape[0], _d(x), _d(y), _d(q), sigma, int(p), int(L), x0, y0, W, int(nc), _d(G))
+    return G, int(nbad)
 

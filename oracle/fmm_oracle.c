@@ -19,6 +19,8 @@
  *     list, L2L), evaluation (L2P + near-field direct) .. Section 2.2, Fig. 2
  *   - Lennard-Jones forces and energy with a cutoff (a further kernel the
  *     paper names for molecular dynamics) ............ Section 8
+ *   - Gauss transform, plain and fast (Greengard and Strain's Hermite /
+ *     Taylor algorithm on the leaf boxes; a transform the paper names) .. Section 8
  * The paper leaves out the expansion mathematics and points to Greengard and
  * Rokhlin; the expansions below are the textbook complex-variable ones for the
  * Cauchy kernel 1/z, kept unscaled (coefficients about geometric box centres).
@@ -722,6 +724,124 @@ double oracle_lj_energy(int64_t n, const double* x, const double* y, double eps,
         }
     }
     return e;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Gauss transform (Section 8 names the fast Gauss transform among the      */
+/* transforms the library should take next):                                */
+/*   G(y_i) = sum_j q_j exp(-|y_i - x_j|^2 / delta),  delta = 2 sigma^2,    */
+/* at the particles themselves (the term j = i included).  The fast form is */
+/* the published algorithm of Greengard and Strain (SIAM J. Sci. Stat.      */
+/* Comput. 12, 1991) on the quadtree's leaf boxes:                          */
+/*   - Hermite expansion of every box B about its centre c_B, with          */
+/*     s = (x - c_B) / sqrt(delta):                                          */
+/*       A_a = sum_{j in B} q_j s1^a1 s2^a2 / (a1! a2!),   a1, a2 < p;       */
+/*     it represents B's field as sum_a A_a h_a1(t1) h_a2(t2),              */
+/*     t = (y - c_B) / sqrt(delta), h_n(t) = (-1)^n d^n/dt^n exp(-t^2)      */
+/*     (e^{-(t-s)^2} = sum_n s^n / n! h_n(t));                               */
+/*   - Hermite to Taylor: for every box C and every box B whose Chebyshev    */
+/*     box distance is at most nc, with tau = (c_C - c_B) / sqrt(delta),     */
+/*       B_b += (-1)^(b1+b2) / (b1! b2!) sum_a A_a h_{a1+b1}(tau1)          */
+/*              h_{a2+b2}(tau2),   b1, b2 < p;                               */
+/*   - evaluation: G(y) = sum_b B_b u1^b1 u2^b2, u = (y - c_C) / sqrt(delta). */
+/* Boxes farther apart than nc contribute less than exp(-(nc w)^2 / delta)  */
+/* per unit of source strength and are left out.                           */
+/* ---------------------------------------------------------------------- */
+
+/* h_0 .. h_{m-1} at t by the three-term recurrence
+ * h_{n+1}(t) = 2 t h_n(t) - 2 n h_{n-1}(t), h_0 = exp(-t^2), h_1 = 2 t h_0. */
+void oracle_hermite(int m, double t, double* h)
+{
+    if (m <= 0) return;
+    h[0] = exp(-t * t);
+    if (m > 1) h[1] = 2.0 * t * h[0];
+    for (int k = 1; k + 1 < m; ++k) h[k + 1] = 2.0 * t * h[k] - 2.0 * (double)k * h[k - 1];
+}
+
+/* The plain sum at the particles tgt[0..nt) (all of them if tgt == NULL). */
+void oracle_gauss_direct(int64_t n, const double* x, const double* y, const double* q, double sigma,
+                         int64_t nt, const int64_t* tgt, double* G)
+{
+    const double inv_delta = 1.0 / (2.0 * sigma * sigma);
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < nt; ++t) {
+        const int64_t i = tgt ? tgt[t] : t;
+        double acc = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            const double dx = x[i] - x[j], dy = y[i] - y[j];
+            acc += q[j] * exp(-(dx * dx + dy * dy) * inv_delta);
+        }
+        G[t] = acc;
+    }
+}
+
+/* The fast form on the 4^L leaf boxes of [x0, x0+W]^2, p Hermite terms per
+ * axis (1 <= p <= 32), boxes within Chebyshev distance nc.  Returns the
+ * number of particles outside the square. */
+int64_t oracle_fgt(int64_t n, const double* x, const double* y, const double* q, double sigma, int p, int L,
+                   double x0, double y0, double W, int nc, double* G)
+{
+    const int64_t side = (int64_t)1 << L;
+    const int64_t nbox = side * side;
+    const double sd = sqrt(2.0 * sigma * sigma);        /* sqrt(delta) */
+    const int pp = p * p;
+    int32_t* ia = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t* ib = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    const int64_t nbad = oracle_quantize(n, x, y, L, x0, y0, W, ia, ib);
+    double* A = (double*)calloc((size_t)(nbox * pp), sizeof(double));
+    double* B = (double*)calloc((size_t)(nbox * pp), sizeof(double));
+    double fact[64];
+    fact[0] = 1.0;
+    for (int k = 1; k < 64; ++k) fact[k] = fact[k - 1] * (double)k;
+
+    /* Hermite expansions (row-major boxes, a = a1 * p + a2) */
+    for (int64_t j = 0; j < n; ++j) {
+        double cx, cy;
+        box_centre(L, ia[j], ib[j], x0, y0, W, &cx, &cy);
+        const double s1 = (x[j] - cx) / sd, s2 = (y[j] - cy) / sd;
+        double* Ab = A + ((int64_t)ib[j] * side + ia[j]) * pp;
+        for (int a1 = 0; a1 < p; ++a1)
+            for (int a2 = 0; a2 < p; ++a2)
+                Ab[a1 * p + a2] += q[j] * pow(s1, a1) * pow(s2, a2) / (fact[a1] * fact[a2]);
+    }
+    /* Hermite to Taylor */
+    #pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t c = 0; c < nbox; ++c) {
+        const int ca = (int)(c % side), cb = (int)(c / side);
+        double h1[64], h2[64];
+        for (int db = -nc; db <= nc; ++db) {
+            for (int da = -nc; da <= nc; ++da) {
+                const int sa = ca - da, sb = cb - db;          /* source box, tau = (da, db) w / sd */
+                if (sa < 0 || sb < 0 || sa >= side || sb >= side) continue;
+                const double* As = A + ((int64_t)sb * side + sa) * pp;
+                const double w = ldexp(W, -L);
+                oracle_hermite(2 * p - 1, (double)da * w / sd, h1);
+                oracle_hermite(2 * p - 1, (double)db * w / sd, h2);
+                for (int b1 = 0; b1 < p; ++b1)
+                    for (int b2 = 0; b2 < p; ++b2) {
+                        double acc = 0.0;
+                        for (int a1 = 0; a1 < p; ++a1)
+                            for (int a2 = 0; a2 < p; ++a2) acc += As[a1 * p + a2] * h1[a1 + b1] * h2[a2 + b2];
+                        const double sgn = ((b1 + b2) & 1) ? -1.0 : 1.0;
+                        B[c * pp + b1 * p + b2] += sgn * acc / (fact[b1] * fact[b2]);
+                    }
+            }
+        }
+    }
+    /* evaluation */
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double cx, cy;
+        box_centre(L, ia[i], ib[i], x0, y0, W, &cx, &cy);
+        const double u1 = (x[i] - cx) / sd, u2 = (y[i] - cy) / sd;
+        const double* Bc = B + ((int64_t)ib[i] * side + ia[i]) * pp;
+        double acc = 0.0;
+        for (int b1 = 0; b1 < p; ++b1)
+            for (int b2 = 0; b2 < p; ++b2) acc += Bc[b1 * p + b2] * pow(u1, b1) * pow(u2, b2);
+        G[i] = acc;
+    }
+    free(A); free(B); free(ia); free(ib);
+    return nbad;
 }
 
 /* ---------------------------------------------------------------------- */
