@@ -67,7 +67,7 @@ typedef enum {
     FMM_KERNEL_GAUSSIAN = 0, /* regularised Biot-Savart kernel of eq. 8, core sigma > 0 */
     FMM_KERNEL_SINGULAR = 1, /* singular Biot-Savart kernel of eq. 7 (point vortices); sigma is
                                 ignored; a pair at zero distance contributes nothing */
-    FMM_KERNEL_LENNARD_JONES = 2
+    FMM_KERNEL_LENNARD_JONES = 2,
                              /* Lennard-Jones force, V(r) = 4 eps ((s/r)^12 - (s/r)^6) for
                                 0 < r < cutoff, 0 beyond (truncated, not shifted): d_u, d_v
                                 receive the force sum_j 24 eps (2 (s/r)^12 - (s/r)^6) (x_i -
@@ -78,6 +78,22 @@ typedef enum {
                                 than the cutoff by no more than a rounding error at a leaf
                                 edge may be missed).  Needs an explicit square and FP64;
                                 fmm_evaluate and the batched form only */
+    FMM_KERNEL_GAUSS_TRANSFORM = 3
+                             /* the discrete Gauss transform (Section 8 names the fast
+                                Gauss transform): d_u receives G_i = sum_j gamma_j
+                                exp(-|x_i - x_j|^2 / (2 sigma^2)) (the term j = i
+                                included), d_v is cleared.  Computed by Greengard and
+                                Strain's fast Gauss transform on the 4^depth leaf boxes:
+                                p Hermite terms per axis (p <= 16) for every box, Hermite
+                                to Taylor translation between boxes within Chebyshev
+                                distance nc = ceil(sqrt(ln 1e16) sqrt(2) sigma / w) (w the
+                                leaf width; a left-out term is below 1e-16 of its source's
+                                strength), Taylor evaluation at the particles.  The error
+                                falls with p and with w / sigma: w <= sigma and p = 12-16
+                                give 1e-10 to 1e-14 relative.  Needs an explicit square,
+                                FP64, a single-instance plan, nc <= 63 (else
+                                FMM_E_UNSUPPORTED); fmm_evaluate only.  Stage timing
+                                reports the transform's three launches under "p2m_m2m" */
 } fmm_kernel;
 
 /* Problem parameters, following the paper's problem statement: positions

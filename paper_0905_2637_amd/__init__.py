@@ -22,9 +22,9 @@ FMM_E_DOMAIN = -3
 FMM_E_NOMEM = -4
 FMM_E_DEVICE = -5
 FMM_E_UNSUPPORTED = -6
-FMM_KERNEL_GAUSSIAN, FMM_KERNEL_SINGULAR, FMM_KERNEL_LENNARD_JONES = 0, 1, 2
+FMM_KERNEL_GAUSSIAN, FMM_KERNEL_SINGULAR, FMM_KERNEL_LENNARD_JONES, FMM_KERNEL_GAUSS_TRANSFORM = 0, 1, 2, 3
 KERNELS = {"gaussian": FMM_KERNEL_GAUSSIAN, "singular": FMM_KERNEL_SINGULAR,
-           "lennard-jones": FMM_KERNEL_LENNARD_JONES}
+           "lennard-jones": FMM_KERNEL_LENNARD_JONES, "gauss-transform": FMM_KERNEL_GAUSS_TRANSFORM}
 
 FMM_PREC_FP64 = 0
 FMM_PREC_MIXED = 1
@@ -249,7 +249,9 @@ class Plan(_PlanBase):
     ``kernel`` = "gaussian" (eq. 8, core ``sigma``) or "singular" (eq. 7,
     point vortices; ``sigma`` ignored) for the near field, or
     "lennard-jones" (length ``sigma``, energy ``lj_epsilon``, ``cutoff`` at
-    most the leaf width): ``evaluate`` then returns the forces.
+    most the leaf width): ``evaluate`` then returns the forces; or
+    "gauss-transform" (``evaluate`` returns the Gauss transform with width
+    ``sigma`` in u, and zeros in v; p <= 16 Hermite terms per axis).
     """
 
     def __init__(self, n_max, sigma, p, depth, domain=(0.0, 0.0, 1.0), precision="fp64",

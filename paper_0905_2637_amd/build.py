@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfmm_mi355x.so")
 
 SOURCES = ["fmm_api.cpp", "fmm_tables.cpp", "fmm_tree.hip", "fmm_upward.hip", "fmm_downward.hip",
-           "fmm_near.hip", "fmm_step.hip"]
+           "fmm_near.hip", "fmm_step.hip", "fmm_fgt.hip"]
 
 ARCH = os.environ.get("FMM_OFFLOAD_ARCH", "gfx950")
 

@@ -37,6 +37,7 @@ struct Shape {
     std::vector<int64_t> part_off;       // first particle of every instance
     int64_t n_cap = 0;                   // particle capacity (the total count if batched)
     int64_t m_cap = 0;                   // target point capacity (single plans; 0: none)
+    int fgt_nc = -1;                     // Gauss transform: box range (-1: not a Gauss transform plan)
     int Lmax = 0;
     int key_bits = 0;
     int64_t leaf_entries = 0;            // sum (4^L_i + 1)
@@ -50,6 +51,11 @@ struct Shape {
 // Launches of one evaluation after the tree build: at most 4 upward groups,
 // 4 M2L (FP64 / FP32 x split / unsplit), 4 downward groups and the P2P.
 constexpr int kMaxLaunches = 16;
+
+// Gauss transform plans: at most 16 Hermite terms per axis and a box range of
+// at most 63 (the Hermite table of the range fits in a workgroup's LDS).
+constexpr int kFgtMaxP = 16;
+constexpr int kFgtMaxRange = 63;
 
 enum LaunchKind { L_UP, L_M2L, L_DOWN, L_P2P };
 
@@ -107,7 +113,7 @@ fmm_status validate_common(const fmm_params* prm)
 {
     if (!prm) return FMM_E_ARG;
     if (prm->kernel != FMM_KERNEL_GAUSSIAN && prm->kernel != FMM_KERNEL_SINGULAR &&
-        prm->kernel != FMM_KERNEL_LENNARD_JONES)
+        prm->kernel != FMM_KERNEL_LENNARD_JONES && prm->kernel != FMM_KERNEL_GAUSS_TRANSFORM)
         return FMM_E_ARG;
     if (prm->kernel != FMM_KERNEL_SINGULAR && (!(prm->sigma > 0.0) || !std::isfinite(prm->sigma)))
         return FMM_E_ARG;
@@ -117,6 +123,11 @@ fmm_status validate_common(const fmm_params* prm)
         // the 3 x 3 leaves around a particle must hold every partner within the cutoff
         if (!(prm->width > 0.0)) return FMM_E_UNSUPPORTED;
         if (prm->precision != FMM_PREC_FP64) return FMM_E_UNSUPPORTED;
+    }
+    if (prm->kernel == FMM_KERNEL_GAUSS_TRANSFORM) {
+        // the box range follows from sigma and the leaf width
+        if (!(prm->width > 0.0)) return FMM_E_UNSUPPORTED;
+        if (prm->precision != FMM_PREC_FP64 || prm->p > kFgtMaxP) return FMM_E_UNSUPPORTED;
     }
     if (prm->p < 1 || prm->p > kMaxP) return FMM_E_ARG;
     if (prm->precision != FMM_PREC_FP64 && prm->precision != FMM_PREC_MIXED) return FMM_E_ARG;
@@ -155,6 +166,17 @@ fmm_status finish_shape(Shape& sh)
     return FMM_OK;
 }
 
+// Gauss transform: boxes farther than nc apart are left out.  Their particles
+// lie at least nc w apart, so exp(-(nc w)^2 / delta) <= 1e-16 (delta =
+// 2 sigma^2) bounds a left-out term: nc = ceil(sqrt(ln 1e16) sqrt(delta) / w),
+// at most the grid's extent.
+int fgt_range(double sigma, double w, int L)
+{
+    const double nc = std::ceil(std::sqrt(std::log(1e16)) * std::sqrt(2.0) * sigma / w);
+    const double side = std::ldexp(1.0, L);
+    return int(std::min(nc, side - 1.0 > 0.0 ? side - 1.0 : 0.0) + 0.5);
+}
+
 // Lennard-Jones: every partner within the cutoff must lie in the 3 x 3 leaves
 // around a particle, so the cutoff may not exceed the deepest leaf width.
 bool cutoff_fits(const fmm_params* prm, int deepest)
@@ -173,6 +195,11 @@ fmm_status single_shape(const fmm_params* prm, Shape& sh)
     sh.n_cap = prm->n_max;
     sh.m_cap = prm->m_max;
     if (!cutoff_fits(prm, prm->depth)) return FMM_E_UNSUPPORTED;
+    if (prm->kernel == FMM_KERNEL_GAUSS_TRANSFORM) {
+        if (prm->m_max != 0) return FMM_E_UNSUPPORTED;
+        sh.fgt_nc = fgt_range(prm->sigma, std::ldexp(prm->width, -prm->depth), prm->depth);
+        if (sh.fgt_nc > kFgtMaxRange) return FMM_E_UNSUPPORTED;
+    }
     return finish_shape(sh);
 }
 
@@ -182,6 +209,7 @@ fmm_status batch_shape(const fmm_params* prm, int32_t n_inst, const int32_t* cou
     if (n_inst < 1 || n_inst > kMaxInstances || !counts || !depths) return FMM_E_ARG;
     if (!(prm->width > 0.0)) return FMM_E_UNSUPPORTED;   // batched instances need the explicit square
     if (prm->m_max != 0) return FMM_E_ARG;                 // target points: single plans only
+    if (prm->kernel == FMM_KERNEL_GAUSS_TRANSFORM) return FMM_E_UNSUPPORTED;
     sh.n_inst = n_inst;
     sh.depth.assign(depths, depths + n_inst);
     sh.part_off.resize(n_inst);
@@ -201,6 +229,7 @@ struct Layout {
     size_t inst, tables, bad_blk, bbox, leaf_start, hist, hist_scan, scan_part;
     size_t key, ksorted, perm, xs, ys, gs, ktmp, itmp, xt, yt, gt, pk, me, le, le_part[2];
     size_t tkey, tks, tperm, txs, tys, tleaf_start, tbad;
+    size_t fgt_a, fgt_b, fgt_h;
     size_t t_m2m, t_l2l, t_h64, t_h32, t_sin, t_sout;
     size_t total;
 };
@@ -254,6 +283,11 @@ Layout make_layout(const Shape& sh, int P, bool mixed)
     ly.t_h32 = take(sizeof(cf) * kHankelGrid * kHankelGrid * (2 * P - 1));
     ly.t_sin = take(sizeof(double) * P);
     ly.t_sout = take(sizeof(double) * P);
+    const bool fgt = sh.fgt_nc >= 0;
+    const size_t fgt_boxes = fgt ? size_t(1) << (2 * sh.depth[0]) : 0;
+    ly.fgt_a = take(sizeof(double) * fgt_boxes * P * P);
+    ly.fgt_b = take(sizeof(double) * fgt_boxes * P * P);
+    ly.fgt_h = take(fgt ? sizeof(double) * size_t(2 * sh.fgt_nc + 1) * (2 * P - 1) : 0);
     ly.total = off;
     return ly;
 }
@@ -555,6 +589,12 @@ hipError_t enqueue_all(fmm_plan_s* pl, int64_t n, const double* x, const double*
     if (pl->auto_domain) chk(launch_domain(b, int(n), x, y, pl->shape.depth[0], st, int(m), tx, ty));
     chk(launch_tree(b, int(n), x, y, g, pl->shape.key_bits, pl->shape.leaf_entries, pl->mixed, st));
     if (m > 0) chk(launch_tree_points(b, int(m), tx, ty, pl->shape.key_bits, pl->shape.leaf_entries, st));
+    if (pl->shape.fgt_nc >= 0) {   // Gauss transform: Hermite, Hermite to Taylor, Taylor evaluation
+        mark(ST_UP);
+        chk(launch_fgt(b, P, int(n), pl->shape.depth[0], pl->prm.sigma, pl->shape.fgt_nc, u, v, st));
+        for (int s2 = ST_M2L; s2 <= ST_COUNT; ++s2) mark(s2);
+        return e;
+    }
     int stage = ST_TREE;
     for (const Launch& ln : pl->launches) {
         const int want = ln.kind == L_UP ? ST_UP : ln.kind == L_M2L ? ST_M2L : ln.kind == L_DOWN ? ST_DOWN : ST_P2P;
@@ -654,6 +694,10 @@ fmm_status make_plan(const fmm_params* prm, Shape&& sh, bool batch, void* d_work
     b.t_h32 = reinterpret_cast<cf*>(base + ly.t_h32);
     b.t_sin = reinterpret_cast<double*>(base + ly.t_sin);
     b.t_sout = reinterpret_cast<double*>(base + ly.t_sout);
+    const bool fgt = pl->shape.fgt_nc >= 0;
+    b.fgt_a = fgt ? reinterpret_cast<double*>(base + ly.fgt_a) : nullptr;
+    b.fgt_b = fgt ? reinterpret_cast<double*>(base + ly.fgt_b) : nullptr;
+    b.fgt_h = fgt ? reinterpret_cast<double*>(base + ly.fgt_h) : nullptr;
 
     const size_t nh = size_t(kHankelGrid) * kHankelGrid * (2 * P - 1);
     std::vector<cd> m2m(size_t(4) * P * P), l2l(size_t(4) * P * P), h64(nh);
@@ -672,6 +716,14 @@ fmm_status make_plan(const fmm_params* prm, Shape&& sh, bool batch, void* d_work
     cp(b.t_h32, h32.data(), h32.size() * sizeof(cf));
     cp(b.t_sin, sin_.data(), sin_.size() * sizeof(double));
     cp(b.t_sout, sout_.data(), sout_.size() * sizeof(double));
+    std::vector<double> fgt_h;
+    if (fgt) {
+        const int nc = pl->shape.fgt_nc;
+        fgt_h.resize(size_t(2 * nc + 1) * (2 * P - 1));
+        const double w = std::ldexp(prm->width, -pl->shape.depth[0]);
+        fgt_hermite_table(P, nc, w / (std::sqrt(2.0) * prm->sigma), fgt_h.data());
+        cp(b.fgt_h, fgt_h.data(), fgt_h.size() * sizeof(double));
+    }
     if (e == hipSuccess) e = upload_schedule(pl, st);      // synchronises st
     if (e != hipSuccess) {
         delete pl;
@@ -811,7 +863,8 @@ fmm_status fmm_evaluate_at(fmm_plan_t plan, int64_t n, const double* d_x, const 
 {
     if (!plan || plan->batch) return FMM_E_ARG;
     if (n < 0 || m < 0) return FMM_E_ARG;
-    if (plan->mixed || plan->prm.kernel == FMM_KERNEL_LENNARD_JONES) return FMM_E_UNSUPPORTED;
+    if (plan->mixed || plan->prm.kernel == FMM_KERNEL_LENNARD_JONES || plan->prm.kernel == FMM_KERNEL_GAUSS_TRANSFORM)
+        return FMM_E_UNSUPPORTED;
     if (n > plan->shape.n_cap || m > plan->shape.m_cap) return FMM_E_CAPACITY;
     if (n > 0 && (!d_x || !d_y || !d_gamma)) return FMM_E_ARG;
     if (m > 0 && (!d_tx || !d_ty || !d_u || !d_v)) return FMM_E_ARG;
@@ -878,7 +931,8 @@ fmm_status fmm_advance_rk2(fmm_plan_t plan, int64_t n, double* d_x, double* d_y,
 {
     if (!plan || plan->batch) return FMM_E_ARG;
     if (n < 0 || n_steps < 0 || !std::isfinite(dt)) return FMM_E_ARG;
-    if (plan->prm.kernel == FMM_KERNEL_LENNARD_JONES) return FMM_E_UNSUPPORTED;   // forces, not velocities
+    if (plan->prm.kernel == FMM_KERNEL_LENNARD_JONES || plan->prm.kernel == FMM_KERNEL_GAUSS_TRANSFORM)
+        return FMM_E_UNSUPPORTED;   // forces or a transform, not velocities
     if (n > plan->shape.n_cap) return FMM_E_CAPACITY;
     if (n == 0 || n_steps == 0) return FMM_OK;
     if (!d_x || !d_y || !d_gamma || !d_scratch) return FMM_E_ARG;

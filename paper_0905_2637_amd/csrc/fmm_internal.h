@@ -171,6 +171,11 @@ struct Buffers {
     cf* t_h32;             // [49][2P-1] M2L translation data, FP32
     double* t_sin;         // [P] (-1)^(k+1) / k!
     double* t_sout;        // [P] 1 / l!
+    // Gauss transform plans: Hermite and Taylor coefficients of every leaf
+    // box, and the Hermite functions at the box offsets
+    double* fgt_a;         // [4^L][P][P]
+    double* fgt_b;         // [4^L][P][P]
+    double* fgt_h;         // [2 nc + 1][2P - 1]
 };
 
 // Chunk of the histogram scan handled by one workgroup.
@@ -206,6 +211,12 @@ hipError_t launch_p2p(const Buffers& b, int P, const Work& w, int nwg, int waves
 // (Gaussian or singular kernel)
 hipError_t launch_p2p_at(const Buffers& b, int P, int L, const NearKernel& nk, double* u, double* v, hipStream_t st);
 hipError_t launch_ilist(const Buffers& b, int L, hipStream_t st);
+// the fast Gauss transform of a single-instance plan (after the tree): P
+// Hermite terms per axis (8, 12 or 16), boxes within Chebyshev distance nc
+hipError_t launch_fgt(const Buffers& b, int P, int n, int L, double sigma, int nc, double* u, double* v,
+                      hipStream_t st);
+// h_n(d w / sqrt(delta)), |d| <= nc, n < 2P - 1, into out[(d + nc) (2P - 1) + n]
+void fgt_hermite_table(int P, int nc, double w_over_sd, double* out);
 // a[0..n) = b[0..n) = 0
 hipError_t launch_zero2(int64_t n, double* a, double* b, hipStream_t st);
 // time stepping: (xo, yo) = (x, y) + c (u, v); xo, yo may alias x, y
