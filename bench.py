@@ -329,6 +329,26 @@ def run_lennard_jones(args, dev, m_side=1024):
     return sec, n, {k: round(vv, 4) for k, vv in stages.items() if k in ("tree", "p2p_l2p")}
 
 
+def run_gauss_transform(wl, args, dev, sigma=0.02, depth=6, p=12):
+    """The fast Gauss transform of the workload's particles (strengths = their
+    circulations), Gaussian width sigma, leaf boxes at the given depth, p
+    Hermite terms per axis, FP64."""
+    import torch
+    import paper_0905_2637_amd as fm
+    x, y, g = dev_arrays(wl, dev)
+    G = torch.empty(wl.n, dtype=torch.float64, device=dev)
+    v = torch.empty_like(G)
+    plan = fm.Plan(wl.n, sigma, p, depth, domain=(wl.x0, wl.y0, wl.width), kernel="gauss-transform")
+    for _ in range(args.warmup):
+        plan.evaluate(x, y, g, G, v)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    sec = timed(lambda: plan.evaluate(x, y, g, G, v), args.steps, 0)
+    stages = plan.stats()
+    plan.close()
+    return sec, G, {"tree": round(stages["tree"], 4), "transform": round(stages["p2m_m2m"], 4)}
+
+
 # ---------------------------------------------------------------------------
 # CPU oracle leg (the only part of the bench that touches the oracle)
 # ---------------------------------------------------------------------------
@@ -368,6 +388,11 @@ def cpu_baseline_leg(wl, res, args, forms):
             forms["mixed"]["rel_l2_vs_fp64_split_direct"] = oracle.rel_l2(um[tgt], vm[tgt], us, vs)
             forms["mixed"]["rel_l2_vs_regularised_direct"] = oracle.rel_l2(um[tgt], vm[tgt], ur, vr)
             forms["mixed"]["rel_l2_vs_gpu_fp64"] = oracle.rel_l2(um, vm, u_gpu, v_gpu)
+        if forms and "_gauss_G" in forms:
+            Gg = forms.pop("_gauss_G").cpu().numpy()
+            Gd = oracle.gauss_direct(wl.x, wl.y, wl.gamma, 0.02, targets=tgt)
+            forms["gauss_transform"]["rel_l2_vs_plain_sum"] = float(np.linalg.norm(Gg[tgt] - Gd) /
+                                                                    np.linalg.norm(Gd))
         out["accuracy"] = acc
     else:
         # oracle FMM over instances in workload order until the budget is spent
@@ -458,6 +483,11 @@ def main() -> int:
         forms["lennard_jones"] = {"workload": "2^20 Lennard-Jones particles, jittered 1024 x 1024 lattice, s = a/1.12, "
                                               "cutoff 2.5 s, depth 8 (FP64 forces, near field only)",
                                   "ms": round(tl * 1e3, 4), "particles_per_s": nl / tl, "stages_ms": sl}
+        tg, Gg, sg = run_gauss_transform(workloads.make("C2"), args, dev)
+        forms["gauss_transform"] = {"workload": "fast Gauss transform of C2's particles (strengths = circulations), "
+                                                "sigma = 0.02, 4096 leaf boxes (depth 6), p = 12 per axis, FP64",
+                                    "ms": round(tg * 1e3, 4), "particles_per_s": wl.n / tg, "stages_ms": sg}
+        forms["_gauss_G"] = Gg
         w4 = workloads.make("C4")
         rb = run_batch(w4, args, dev)
         rb64 = run_batch(w4, args, dev, precision="fp64")
@@ -504,6 +534,7 @@ def main() -> int:
         out.update(cpu_baseline_leg(wl, res, args, forms))
     if forms is not None:
         forms.pop("_mixed_uv", None)
+        forms.pop("_gauss_G", None)
         out["forms"] = forms
     print(json.dumps(out))
     return 0

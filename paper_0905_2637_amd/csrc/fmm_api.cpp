@@ -286,7 +286,8 @@ Layout make_layout(const Shape& sh, int P, bool mixed)
     const bool fgt = sh.fgt_nc >= 0;
     const size_t fgt_boxes = fgt ? size_t(1) << (2 * sh.depth[0]) : 0;
     ly.fgt_a = take(sizeof(double) * fgt_boxes * P * P);
-    ly.fgt_b = take(sizeof(double) * fgt_boxes * P * P);
+    const size_t parts = fgt ? size_t(fgt_parts(P, sh.depth[0], sh.fgt_nc)) : 0;
+    ly.fgt_b = take(sizeof(double) * parts * fgt_boxes * P * P);
     ly.fgt_h = take(fgt ? sizeof(double) * size_t(2 * sh.fgt_nc + 1) * (2 * P - 1) : 0);
     ly.total = off;
     return ly;
@@ -591,7 +592,8 @@ hipError_t enqueue_all(fmm_plan_s* pl, int64_t n, const double* x, const double*
     if (m > 0) chk(launch_tree_points(b, int(m), tx, ty, pl->shape.key_bits, pl->shape.leaf_entries, st));
     if (pl->shape.fgt_nc >= 0) {   // Gauss transform: Hermite, Hermite to Taylor, Taylor evaluation
         mark(ST_UP);
-        chk(launch_fgt(b, P, int(n), pl->shape.depth[0], pl->prm.sigma, pl->shape.fgt_nc, u, v, st));
+        const int L = pl->shape.depth[0], nc = pl->shape.fgt_nc;
+        chk(launch_fgt(b, P, int(n), L, pl->prm.sigma, nc, fgt_parts(P, L, nc), u, v, st));
         for (int s2 = ST_M2L; s2 <= ST_COUNT; ++s2) mark(s2);
         return e;
     }

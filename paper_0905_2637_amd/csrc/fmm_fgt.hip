@@ -15,7 +15,9 @@
 // |d| <= nc, and the h_n(tau) form one small table (built on the host).
 // H2T is the matrix product Hx^T A Hy per box pair, done as two passes of p^2
 // fused multiply-adds per lane: lane (box, b1) forms C_a2 = sum_a1 A_a1a2
-// h_{a1+b1}(tau1), then B_b1b2 += sum_a2 C_a2 h_{a2+b2}(tau2).
+// h_{a1+b1}(tau1), then B_b1b2 += sum_a2 C_a2 h_{a2+b2}(tau2).  With few
+// boxes the rows of the range are split over up to 8 workgroup rows, each
+// writing a partial expansion; a fixed-order sum joins them.
 #include "fmm_device.h"
 
 namespace fmm {
@@ -81,6 +83,9 @@ __global__ void __launch_bounds__(kFgtThreads)
 k_h2t(int L, int nc, const double* __restrict__ A, const double* __restrict__ ht, const double* __restrict__ fk,
       double* __restrict__ B)
 {
+    // this workgroup row's share of the range's rows db
+    const int rows = 2 * nc + 1, per = (rows + int(gridDim.y) - 1) / int(gridDim.y);
+    const int db0 = -nc + int(blockIdx.y) * per, db1 = min(nc, db0 + per - 1);
     using G = Groups<P>;
     constexpr int NH = 2 * P - 1;
     extern __shared__ double sht[];
@@ -96,7 +101,7 @@ k_h2t(int L, int nc, const double* __restrict__ A, const double* __restrict__ ht
     double acc[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) acc[k] = 0.0;
-    for (int db = -nc; db <= nc; ++db) {
+    for (int db = db0; db <= db1; ++db) {
         const int sb = cb - db;
         if (sb < 0 || sb >= side) continue;
         const double* hy = sht + (db + nc) * NH;
@@ -123,11 +128,21 @@ k_h2t(int L, int nc, const double* __restrict__ A, const double* __restrict__ ht
             }
         }
     }
-    // (-1)^(b1+b2) / (b1! b2!), zero for terms >= p
-    double* dst = B + m * (P * P) + b1 * P;
+    // (-1)^(b1+b2) / (b1! b2!), zero for terms >= p; partial expansion blockIdx.y
+    double* dst = B + (int64_t(blockIdx.y) * side * side + m) * (P * P) + b1 * P;
     const double f1 = (b1 & 1) ? -fk[b1] : fk[b1];
 #pragma unroll
     for (int b2 = 0; b2 < P; ++b2) dst[b2] = acc[b2] * ((b2 & 1) ? -f1 : f1) * fk[b2];
+}
+
+// Partial expansions 1 .. parts-1 added to partial 0, in that order.
+__global__ void __launch_bounds__(kFgtThreads) k_fgt_join(int64_t len, int parts, double* __restrict__ B)
+{
+    const int64_t e = int64_t(blockIdx.x) * kFgtThreads + threadIdx.x;
+    if (e >= len) return;
+    double s = B[e];
+    for (int g = 1; g < parts; ++g) s += B[int64_t(g) * len + e];
+    B[e] = s;
 }
 
 // T2P: one particle per thread (sorted order), G to its input position; v
@@ -160,16 +175,23 @@ k_t2p(int n, int L, const Inst* __restrict__ inst, const uint32_t* __restrict__ 
 }
 
 template <int P>
-hipError_t fgt_impl(const Buffers& b, int n, int L, double sigma, int nc, double* u, double* v, hipStream_t st)
+hipError_t fgt_impl(const Buffers& b, int n, int L, double sigma, int nc, int parts, double* u, double* v,
+                    hipStream_t st)
 {
     using G = Groups<P>;
     const int64_t nbox = int64_t(1) << (2 * L);
     const double rsd = 1.0 / std::sqrt(2.0 * sigma * sigma);
-    const dim3 grid(unsigned((nbox + G::kPerBlock - 1) / G::kPerBlock));
-    hipLaunchKernelGGL(k_p2h<P>, grid, dim3(kFgtThreads), 0, st, L, b.inst, b.leaf_start, b.xs, b.ys, b.gs,
+    const unsigned gx = unsigned((nbox + G::kPerBlock - 1) / G::kPerBlock);
+    hipLaunchKernelGGL(k_p2h<P>, dim3(gx), dim3(kFgtThreads), 0, st, L, b.inst, b.leaf_start, b.xs, b.ys, b.gs,
                        b.t_sout, rsd, b.fgt_a);
     const size_t lds = sizeof(double) * size_t(2 * nc + 1) * (2 * P - 1);
-    hipLaunchKernelGGL(k_h2t<P>, grid, dim3(kFgtThreads), lds, st, L, nc, b.fgt_a, b.fgt_h, b.t_sout, b.fgt_b);
+    hipLaunchKernelGGL(k_h2t<P>, dim3(gx, unsigned(parts)), dim3(kFgtThreads), lds, st, L, nc, b.fgt_a, b.fgt_h,
+                       b.t_sout, b.fgt_b);
+    if (parts > 1) {
+        const int64_t len = nbox * P * P;
+        hipLaunchKernelGGL(k_fgt_join, dim3(unsigned((len + kFgtThreads - 1) / kFgtThreads)), dim3(kFgtThreads), 0,
+                           st, len, parts, b.fgt_b);
+    }
     hipLaunchKernelGGL(k_t2p<P>, dim3(unsigned((n + kFgtThreads - 1) / kFgtThreads)), dim3(kFgtThreads), 0, st, n,
                        L, b.inst, b.ksorted, b.xs, b.ys, b.perm, b.fgt_b, rsd, u, v);
     return hipGetLastError();
@@ -177,16 +199,26 @@ hipError_t fgt_impl(const Buffers& b, int n, int L, double sigma, int nc, double
 
 }  // namespace
 
-hipError_t launch_fgt(const Buffers& b, int P, int n, int L, double sigma, int nc, double* u, double* v,
+hipError_t launch_fgt(const Buffers& b, int P, int n, int L, double sigma, int nc, int parts, double* u, double* v,
                       hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
+    if (parts < 1 || parts > 2 * nc + 1) return hipErrorInvalidValue;
     switch (P) {
-        case 8: return fgt_impl<8>(b, n, L, sigma, nc, u, v, st);
-        case 12: return fgt_impl<12>(b, n, L, sigma, nc, u, v, st);
-        case 16: return fgt_impl<16>(b, n, L, sigma, nc, u, v, st);
+        case 8: return fgt_impl<8>(b, n, L, sigma, nc, parts, u, v, st);
+        case 12: return fgt_impl<12>(b, n, L, sigma, nc, parts, u, v, st);
+        case 16: return fgt_impl<16>(b, n, L, sigma, nc, parts, u, v, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+int fgt_parts(int P, int L, int nc)
+{
+    // enough workgroup rows for about 4096 wavefronts, at most 8 and at most
+    // one per row of the range
+    const int64_t waves = ((int64_t(1) << (2 * L)) + (64 / P) - 1) / (64 / P);
+    const int64_t want = (4096 + waves - 1) / waves;
+    return int(std::max<int64_t>(1, std::min<int64_t>({want, 8, 2 * nc + 1})));
 }
 
 void fgt_hermite_table(int P, int nc, double w_over_sd, double* out)

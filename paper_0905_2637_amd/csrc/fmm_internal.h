@@ -174,7 +174,7 @@ struct Buffers {
     // Gauss transform plans: Hermite and Taylor coefficients of every leaf
     // box, and the Hermite functions at the box offsets
     double* fgt_a;         // [4^L][P][P]
-    double* fgt_b;         // [4^L][P][P]
+    double* fgt_b;         // [parts][4^L][P][P] (partial Taylor expansions, joined into part 0)
     double* fgt_h;         // [2 nc + 1][2P - 1]
 };
 
@@ -212,9 +212,11 @@ hipError_t launch_p2p(const Buffers& b, int P, const Work& w, int nwg, int waves
 hipError_t launch_p2p_at(const Buffers& b, int P, int L, const NearKernel& nk, double* u, double* v, hipStream_t st);
 hipError_t launch_ilist(const Buffers& b, int L, hipStream_t st);
 // the fast Gauss transform of a single-instance plan (after the tree): P
-// Hermite terms per axis (8, 12 or 16), boxes within Chebyshev distance nc
-hipError_t launch_fgt(const Buffers& b, int P, int n, int L, double sigma, int nc, double* u, double* v,
+// Hermite terms per axis (8, 12 or 16), boxes within Chebyshev distance nc,
+// the range's rows split over `parts` partial expansions
+hipError_t launch_fgt(const Buffers& b, int P, int n, int L, double sigma, int nc, int parts, double* u, double* v,
                       hipStream_t st);
+int fgt_parts(int P, int L, int nc);
 // h_n(d w / sqrt(delta)), |d| <= nc, n < 2P - 1, into out[(d + nc) (2P - 1) + n]
 void fgt_hermite_table(int P, int nc, double w_over_sd, double* out);
 // a[0..n) = b[0..n) = 0
