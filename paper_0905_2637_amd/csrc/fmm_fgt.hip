@@ -13,9 +13,10 @@
 //        u = (y - c_C) / sqrt(delta) (the Taylor expansion about c_C).
 // The box offsets are integers, so tau takes the values d w / sqrt(delta),
 // |d| <= nc, and the h_n(tau) form one small table (built on the host).
-// H2T is the matrix product Hx^T A Hy per box pair, done as two passes of p^2
-// fused multiply-adds per lane: lane (box, b1) forms C_a2 = sum_a1 A_a1a2
-// h_{a1+b1}(tau1), then B_b1b2 += sum_a2 C_a2 h_{a2+b2}(tau2).  With few
+// H2T is the matrix product Hx^T A Hy per box pair, done as two passes of
+// fused multiply-adds: a lane owns one or two output rows b1, forms C_b1,a2 =
+// sum_a1 h_{a1+b1}(tau1) A_a1a2, then adds sum_a2 C_b1,a2 h_{a2+b2}(tau2)
+// to B_b1b2.  With few
 // boxes the rows of the range are split over up to 8 workgroup rows, each
 // writing a partial expansion; a fixed-order sum joins them.
 #include "fmm_device.h"
@@ -76,63 +77,94 @@ k_p2h(int L, const Inst* __restrict__ inst, const int32_t* __restrict__ leaf_sta
     for (int k = 0; k < P; ++k) dst[k] = acc[k] * f1 * fk[k];
 }
 
-// H2T: lane (box, b1); the table ht holds h_n(d w / sqrt(delta)) at
-// [(d + nc) * (2P - 1) + n], staged in LDS.
+// H2T lanes: R output rows b1 per lane (each coefficient of A a lane loads
+// then feeds R multiply-adds), P / R lanes per box.
+template <int P>
+struct H2TGroups {
+    static constexpr int kRows = P <= 12 ? 2 : 1;
+    static constexpr int kLanes = P / kRows;
+    static constexpr int kPerWave = 64 / kLanes;
+    static constexpr int kPerBlock = kPerWave * (kFgtThreads / 64);
+};
+
+// H2T: lane (box, rows b1 = q, q + P/R, ...).  The table ht holds h_n(d w /
+// sqrt(delta)) at [(d + nc) (2P - 1) + n]: the lane-dependent Hx values come
+// from an LDS copy, the Hy values (the same for the whole workgroup: they
+// depend on the row offset db only) straight from memory through scalar
+// loads.  Stage 1 forms C_b1,a2 = sum_a1 h_{a1+b1}(tau1) A_a1a2, stage 2 adds
+// sum_a2 C_b1,a2 h_{a2+b2}(tau2) to B_b1b2.
 template <int P>
 __global__ void __launch_bounds__(kFgtThreads)
 k_h2t(int L, int nc, const double* __restrict__ A, const double* __restrict__ ht, const double* __restrict__ fk,
       double* __restrict__ B)
 {
+    using G = H2TGroups<P>;
+    constexpr int R = G::kRows, NH = 2 * P - 1;
     // this workgroup row's share of the range's rows db
     const int rows = 2 * nc + 1, per = (rows + int(gridDim.y) - 1) / int(gridDim.y);
     const int db0 = -nc + int(blockIdx.y) * per, db1 = min(nc, db0 + per - 1);
-    using G = Groups<P>;
-    constexpr int NH = 2 * P - 1;
     extern __shared__ double sht[];
-    const int nt = (2 * nc + 1) * NH;
+    const int nt = rows * NH;
     for (int e = threadIdx.x; e < nt; e += kFgtThreads) sht[e] = ht[e];
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int grp = lane / P, b1 = lane % P;
+    const int grp = lane / G::kLanes, q = lane % G::kLanes;
     const int side = 1 << L;
     const int64_t m = int64_t(blockIdx.x) * G::kPerBlock + wv * G::kPerWave + grp;
     if (grp >= G::kPerWave || m >= int64_t(side) * side) return;
     const int ca = int(morton_x(uint32_t(m))), cb = int(morton_y(uint32_t(m)));
-    double acc[P];
+    double acc[R][P];
 #pragma unroll
-    for (int k = 0; k < P; ++k) acc[k] = 0.0;
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int k = 0; k < P; ++k) acc[r][k] = 0.0;
     for (int db = db0; db <= db1; ++db) {
         const int sb = cb - db;
         if (sb < 0 || sb >= side) continue;
-        const double* hy = sht + (db + nc) * NH;
+        const double* hy = ht + (db + nc) * NH;
         for (int da = -nc; da <= nc; ++da) {
             const int sa = ca - da;
             if (sa < 0 || sa >= side) continue;
-            const double* hx = sht + (da + nc) * NH + b1;
+            const double* hx = sht + (da + nc) * NH + q;
             const double* As = A + int64_t(morton(uint32_t(sa), uint32_t(sb))) * (P * P);
-            double c[P];
+            double c[R][P];
 #pragma unroll
-            for (int k = 0; k < P; ++k) c[k] = 0.0;
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k < P; ++k) c[r][k] = 0.0;
 #pragma unroll
             for (int a1 = 0; a1 < P; ++a1) {
-                const double h = hx[a1];
+                double h[R];
 #pragma unroll
-                for (int a2 = 0; a2 < P; ++a2) c[a2] = fma(As[a1 * P + a2], h, c[a2]);
+                for (int r = 0; r < R; ++r) h[r] = hx[a1 + r * G::kLanes];
+#pragma unroll
+                for (int a2 = 0; a2 < P; ++a2) {
+                    const double av = As[a1 * P + a2];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) c[r][a2] = fma(av, h[r], c[r][a2]);
+                }
             }
 #pragma unroll
             for (int b2 = 0; b2 < P; ++b2) {
-                double s = acc[b2];
 #pragma unroll
-                for (int a2 = 0; a2 < P; ++a2) s = fma(c[a2], hy[a2 + b2], s);
-                acc[b2] = s;
+                for (int r = 0; r < R; ++r) {
+                    double s = acc[r][b2];
+#pragma unroll
+                    for (int a2 = 0; a2 < P; ++a2) s = fma(c[r][a2], hy[a2 + b2], s);
+                    acc[r][b2] = s;
+                }
             }
         }
     }
     // (-1)^(b1+b2) / (b1! b2!), zero for terms >= p; partial expansion blockIdx.y
-    double* dst = B + (int64_t(blockIdx.y) * side * side + m) * (P * P) + b1 * P;
-    const double f1 = (b1 & 1) ? -fk[b1] : fk[b1];
 #pragma unroll
-    for (int b2 = 0; b2 < P; ++b2) dst[b2] = acc[b2] * ((b2 & 1) ? -f1 : f1) * fk[b2];
+    for (int r = 0; r < R; ++r) {
+        const int b1 = q + r * G::kLanes;
+        double* dst = B + (int64_t(blockIdx.y) * side * side + m) * (P * P) + b1 * P;
+        const double f1 = (b1 & 1) ? -fk[b1] : fk[b1];
+#pragma unroll
+        for (int b2 = 0; b2 < P; ++b2) dst[b2] = acc[r][b2] * ((b2 & 1) ? -f1 : f1) * fk[b2];
+    }
 }
 
 // Partial expansions 1 .. parts-1 added to partial 0, in that order.
@@ -179,13 +211,15 @@ hipError_t fgt_impl(const Buffers& b, int n, int L, double sigma, int nc, int pa
                     hipStream_t st)
 {
     using G = Groups<P>;
+    using H = H2TGroups<P>;
     const int64_t nbox = int64_t(1) << (2 * L);
     const double rsd = 1.0 / std::sqrt(2.0 * sigma * sigma);
     const unsigned gx = unsigned((nbox + G::kPerBlock - 1) / G::kPerBlock);
     hipLaunchKernelGGL(k_p2h<P>, dim3(gx), dim3(kFgtThreads), 0, st, L, b.inst, b.leaf_start, b.xs, b.ys, b.gs,
                        b.t_sout, rsd, b.fgt_a);
     const size_t lds = sizeof(double) * size_t(2 * nc + 1) * (2 * P - 1);
-    hipLaunchKernelGGL(k_h2t<P>, dim3(gx, unsigned(parts)), dim3(kFgtThreads), lds, st, L, nc, b.fgt_a, b.fgt_h,
+    const unsigned hx = unsigned((nbox + H::kPerBlock - 1) / H::kPerBlock);
+    hipLaunchKernelGGL(k_h2t<P>, dim3(hx, unsigned(parts)), dim3(kFgtThreads), lds, st, L, nc, b.fgt_a, b.fgt_h,
                        b.t_sout, b.fgt_b);
     if (parts > 1) {
         const int64_t len = nbox * P * P;
@@ -216,7 +250,8 @@ int fgt_parts(int P, int L, int nc)
 {
     // enough workgroup rows for about 4096 wavefronts, at most 8 and at most
     // one per row of the range
-    const int64_t waves = ((int64_t(1) << (2 * L)) + (64 / P) - 1) / (64 / P);
+    const int per_wave = P == 8 ? H2TGroups<8>::kPerWave : P == 12 ? H2TGroups<12>::kPerWave : H2TGroups<16>::kPerWave;
+    const int64_t waves = ((int64_t(1) << (2 * L)) + per_wave - 1) / per_wave;
     const int64_t want = (4096 + waves - 1) / waves;
     return int(std::max<int64_t>(1, std::min<int64_t>({want, 8, 2 * nc + 1})));
 }
