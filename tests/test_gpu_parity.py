@@ -142,6 +142,8 @@ def test_c1_fp64_matches_oracle_and_coefficients():
     (3000, 4, 24, 0.005, 8),
     (3000, 3, 32, 0.005, 9),
     (65, 6, 12, 0.01, 10),
+    (900, 3, 1, 0.01, 11),      # a single term: the smallest expansion
+    (900, 4, 2, 0.01, 12),
 ])
 def test_fp64_parameter_grid(n, L, p, sigma, seed):
     x, y, g = workloads.uniform_square(n, seed)
