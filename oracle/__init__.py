@@ -89,6 +89,10 @@ def _load():
     lib.oracle_fgt.argtypes = [i64, dp, dp, dp, C.c_double, C.c_int, C.c_int, C.c_double, C.c_double,
                                C.c_double, C.c_int, dp]
     lib.oracle_fgt.restype = i64
+    lib.oracle_gauss_direct_at.argtypes = [i64, dp, dp, dp, C.c_double, i64, dp, dp, dp]
+    lib.oracle_fgt_at.argtypes = [i64, dp, dp, dp, C.c_double, C.c_int, C.c_int, C.c_double, C.c_double,
+                                  C.c_double, C.c_int, i64, dp, dp, dp]
+    lib.oracle_fgt_at.restype = i64
     lib.oracle_init()
     _lib = lib
     return lib
@@ -372,5 +376,24 @@ def fgt(x, y, q, sigma, p, L, nc, x0=0.0, y0=0.0, W=1.0):
     x, y, q = _f64(x), _f64(y), _f64(q)
     G = np.zeros(x.shape[0])
     nbad = lib.oracle_fgt(x.shape[0], _d(x), _d(y), _d(q), sigma, int(p), int(L), x0, y0, W, int(nc), _d(G))
+    return G, int(nbad)
+
+
+def gauss_direct_at(x, y, q, sigma, tx, ty):
+    """Plain Gauss transform at points apart from the particles."""
+    lib = _load()
+    x, y, q, tx, ty = _f64(x), _f64(y), _f64(q), _f64(tx), _f64(ty)
+    G = np.zeros(tx.shape[0])
+    lib.oracle_gauss_direct_at(x.shape[0], _d(x), _d(y), _d(q), sigma, tx.shape[0], _d(tx), _d(ty), _d(G))
+    return G
+
+
+def fgt_at(x, y, q, sigma, p, L, nc, tx, ty, x0=0.0, y0=0.0, W=1.0):
+    """Fast Gauss transform at points apart from the particles; returns (G, nbad)."""
+    lib = _load()
+    x, y, q, tx, ty = _f64(x), _f64(y), _f64(q), _f64(tx), _f64(ty)
+    G = np.zeros(tx.shape[0])
+    nbad = lib.oracle_fgt_at(x.shape[0], _d(x), _d(y), _d(q), sigma, int(p), int(L), x0, y0, W, int(nc),
+                             tx.shape[0], _d(tx), _d(ty), _d(G))
     return G, int(nbad)
 

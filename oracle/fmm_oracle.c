@@ -775,11 +775,29 @@ void oracle_gauss_direct(int64_t n, const double* x, const double* y, const doub
     }
 }
 
+/* The plain sum at m points (tx, ty) apart from the particles. */
+void oracle_gauss_direct_at(int64_t n, const double* x, const double* y, const double* q, double sigma,
+                            int64_t m, const double* tx, const double* ty, double* G)
+{
+    const double inv_delta = 1.0 / (2.0 * sigma * sigma);
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < m; ++t) {
+        double acc = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            const double dx = tx[t] - x[j], dy = ty[t] - y[j];
+            acc += q[j] * exp(-(dx * dx + dy * dy) * inv_delta);
+        }
+        G[t] = acc;
+    }
+}
+
 /* The fast form on the 4^L leaf boxes of [x0, x0+W]^2, p Hermite terms per
- * axis (1 <= p <= 32), boxes within Chebyshev distance nc.  Returns the
- * number of particles outside the square. */
-int64_t oracle_fgt(int64_t n, const double* x, const double* y, const double* q, double sigma, int p, int L,
-                   double x0, double y0, double W, int nc, double* G)
+ * axis (1 <= p <= 32), boxes within Chebyshev distance nc, evaluated at the
+ * particles (tx == NULL) or at the m points (tx, ty), each in its own leaf
+ * box.  Returns the number of particles and points outside the square. */
+static int64_t fgt_core(int64_t n, const double* x, const double* y, const double* q, double sigma, int p, int L,
+                        double x0, double y0, double W, int nc, int64_t m, const double* tx, const double* ty,
+                        double* G)
 {
     const int64_t side = (int64_t)1 << L;
     const int64_t nbox = side * side;
@@ -829,19 +847,44 @@ int64_t oracle_fgt(int64_t n, const double* x, const double* y, const double* q,
         }
     }
     /* evaluation */
+    const int64_t ne = tx ? m : n;
+    int32_t* ea = ia;
+    int32_t* eb = ib;
+    int64_t ebad = 0;
+    if (tx) {
+        ea = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+        eb = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+        ebad = oracle_quantize(m, tx, ty, L, x0, y0, W, ea, eb);
+    }
     #pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t i = 0; i < ne; ++i) {
         double cx, cy;
-        box_centre(L, ia[i], ib[i], x0, y0, W, &cx, &cy);
-        const double u1 = (x[i] - cx) / sd, u2 = (y[i] - cy) / sd;
-        const double* Bc = B + ((int64_t)ib[i] * side + ia[i]) * pp;
+        box_centre(L, ea[i], eb[i], x0, y0, W, &cx, &cy);
+        const double px = tx ? tx[i] : x[i], py = tx ? ty[i] : y[i];
+        const double u1 = (px - cx) / sd, u2 = (py - cy) / sd;
+        const double* Bc = B + ((int64_t)eb[i] * side + ea[i]) * pp;
         double acc = 0.0;
         for (int b1 = 0; b1 < p; ++b1)
             for (int b2 = 0; b2 < p; ++b2) acc += Bc[b1 * p + b2] * pow(u1, b1) * pow(u2, b2);
         G[i] = acc;
     }
+    if (tx) { free(ea); free(eb); }
     free(A); free(B); free(ia); free(ib);
-    return nbad;
+    return nbad + ebad;
+}
+
+int64_t oracle_fgt(int64_t n, const double* x, const double* y, const double* q, double sigma, int p, int L,
+                   double x0, double y0, double W, int nc, double* G)
+{
+    return fgt_core(n, x, y, q, sigma, p, L, x0, y0, W, nc, 0, NULL, NULL, G);
+}
+
+/* The fast form evaluated at m points (tx, ty) apart from the particles. */
+int64_t oracle_fgt_at(int64_t n, const double* x, const double* y, const double* q, double sigma, int p, int L,
+                      double x0, double y0, double W, int nc, int64_t m, const double* tx, const double* ty,
+                      double* G)
+{
+    return fgt_core(n, x, y, q, sigma, p, L, x0, y0, W, nc, m, tx, ty, G);
 }
 
 /* ---------------------------------------------------------------------- */

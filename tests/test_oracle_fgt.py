@@ -82,3 +82,23 @@ def test_range_truncation_within_the_tail_bound():
         assert np.max(np.abs(G - Gd)) <= bound + floor
     G2, _ = oracle.fgt(x, y, q, sigma, p, L, 2)
     assert np.max(np.abs(G2 - Gd)) > 10 * floor          # the truncation shows
+
+
+def test_fast_form_at_points():
+    """At points apart from the particles: convergence to the plain sum, and
+    points on top of the particles reproduce the particle evaluation bit for
+    bit (the same boxes, expansions and Taylor sums)."""
+    x, y, q = workloads.uniform_square(3000, 94)
+    rng = np.random.default_rng(95)
+    tx, ty = rng.random(500), rng.random(500)
+    sigma, L, p = 0.05, 5, 16
+    nc = math.ceil(math.sqrt(36.8) * math.sqrt(2) * sigma / 2 ** -L)
+    G, nbad = oracle.fgt_at(x, y, q, sigma, p, L, nc, tx, ty)
+    Gd = oracle.gauss_direct_at(x, y, q, sigma, tx, ty)
+    assert nbad == 0 and np.linalg.norm(G - Gd) / np.linalg.norm(Gd) < 1e-14
+    G1, _ = oracle.fgt(x, y, q, sigma, 12, L, nc)
+    G2, _ = oracle.fgt_at(x, y, q, sigma, 12, L, nc, x, y)
+    assert np.array_equal(G1, G2)
+    Gp = oracle.gauss_direct(x, y, q, sigma)
+    Gpa = oracle.gauss_direct_at(x, y, q, sigma, x, y)
+    assert np.allclose(Gp, Gpa, rtol=1e-14, atol=0)
