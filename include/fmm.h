@@ -92,7 +92,8 @@ typedef enum {
                                 falls with p and with w / sigma: w <= sigma and p = 12-16
                                 give 1e-10 to 1e-14 relative.  Needs an explicit square,
                                 FP64, a single-instance plan, nc <= 63 (else
-                                FMM_E_UNSUPPORTED); fmm_evaluate only.  Stage timing
+                                FMM_E_UNSUPPORTED); fmm_evaluate, and fmm_evaluate_at
+                                for the transform at target points.  Stage timing
                                 reports the transform's three launches under "p2m_m2m" */
 } fmm_kernel;
 
@@ -167,8 +168,9 @@ fmm_status fmm_evaluate(fmm_plan_t plan, int64_t n,
  * the particles (fmm_get_status).  m == 0 does nothing.  Asynchronous on
  * `stream`.  FP64 single-instance plans only.  Errors (synchronous):
  * FMM_E_ARG (NULL plan or pointers, negative counts, a batched plan),
- * FMM_E_UNSUPPORTED (a mixed-precision plan), FMM_E_CAPACITY (n > n_max or
- * m > m_max), FMM_E_DEVICE. */
+ * FMM_E_UNSUPPORTED (a mixed-precision or Lennard-Jones plan), FMM_E_CAPACITY
+ * (n > n_max or m > m_max), FMM_E_DEVICE.  A Gauss transform plan writes the
+ * transform at the points into d_u (d_v cleared). */
 fmm_status fmm_evaluate_at(fmm_plan_t plan, int64_t n, const double* d_x, const double* d_y,
                            const double* d_gamma, int64_t m, const double* d_tx, const double* d_ty,
                            double* d_u, double* d_v, void* stream);

@@ -250,8 +250,9 @@ class Plan(_PlanBase):
     point vortices; ``sigma`` ignored) for the near field, or
     "lennard-jones" (length ``sigma``, energy ``lj_epsilon``, ``cutoff`` at
     most the leaf width): ``evaluate`` then returns the forces; or
-    "gauss-transform" (``evaluate`` returns the Gauss transform with width
-    ``sigma`` in u, and zeros in v; p <= 16 Hermite terms per axis).
+    "gauss-transform" (``evaluate`` and ``evaluate_at`` return the Gauss
+    transform with width ``sigma`` in u, and zeros in v; p <= 16 Hermite
+    terms per axis).
     """
 
     def __init__(self, n_max, sigma, p, depth, domain=(0.0, 0.0, 1.0), precision="fp64",

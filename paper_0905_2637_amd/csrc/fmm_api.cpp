@@ -196,7 +196,6 @@ fmm_status single_shape(const fmm_params* prm, Shape& sh)
     sh.m_cap = prm->m_max;
     if (!cutoff_fits(prm, prm->depth)) return FMM_E_UNSUPPORTED;
     if (prm->kernel == FMM_KERNEL_GAUSS_TRANSFORM) {
-        if (prm->m_max != 0) return FMM_E_UNSUPPORTED;
         sh.fgt_nc = fgt_range(prm->sigma, std::ldexp(prm->width, -prm->depth), prm->depth);
         if (sh.fgt_nc > kFgtMaxRange) return FMM_E_UNSUPPORTED;
     }
@@ -593,7 +592,7 @@ hipError_t enqueue_all(fmm_plan_s* pl, int64_t n, const double* x, const double*
     if (pl->shape.fgt_nc >= 0) {   // Gauss transform: Hermite, Hermite to Taylor, Taylor evaluation
         mark(ST_UP);
         const int L = pl->shape.depth[0], nc = pl->shape.fgt_nc;
-        chk(launch_fgt(b, P, int(n), L, pl->prm.sigma, nc, fgt_parts(P, L, nc), u, v, st));
+        chk(launch_fgt(b, P, int(n), L, pl->prm.sigma, nc, fgt_parts(P, L, nc), int(m), u, v, st));
         for (int s2 = ST_M2L; s2 <= ST_COUNT; ++s2) mark(s2);
         return e;
     }
@@ -865,8 +864,7 @@ fmm_status fmm_evaluate_at(fmm_plan_t plan, int64_t n, const double* d_x, const 
 {
     if (!plan || plan->batch) return FMM_E_ARG;
     if (n < 0 || m < 0) return FMM_E_ARG;
-    if (plan->mixed || plan->prm.kernel == FMM_KERNEL_LENNARD_JONES || plan->prm.kernel == FMM_KERNEL_GAUSS_TRANSFORM)
-        return FMM_E_UNSUPPORTED;
+    if (plan->mixed || plan->prm.kernel == FMM_KERNEL_LENNARD_JONES) return FMM_E_UNSUPPORTED;
     if (n > plan->shape.n_cap || m > plan->shape.m_cap) return FMM_E_CAPACITY;
     if (n > 0 && (!d_x || !d_y || !d_gamma)) return FMM_E_ARG;
     if (m > 0 && (!d_tx || !d_ty || !d_u || !d_v)) return FMM_E_ARG;

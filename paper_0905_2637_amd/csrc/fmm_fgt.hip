@@ -177,8 +177,8 @@ __global__ void __launch_bounds__(kFgtThreads) k_fgt_join(int64_t len, int parts
     B[e] = s;
 }
 
-// T2P: one particle per thread (sorted order), G to its input position; v
-// is cleared.
+// T2P: one particle (or target point) per thread in sorted order, G to its
+// input position; v is cleared.
 template <int P>
 __global__ void __launch_bounds__(kFgtThreads)
 k_t2p(int n, int L, const Inst* __restrict__ inst, const uint32_t* __restrict__ ksorted,
@@ -207,7 +207,7 @@ k_t2p(int n, int L, const Inst* __restrict__ inst, const uint32_t* __restrict__ 
 }
 
 template <int P>
-hipError_t fgt_impl(const Buffers& b, int n, int L, double sigma, int nc, int parts, double* u, double* v,
+hipError_t fgt_impl(const Buffers& b, int n, int L, double sigma, int nc, int parts, int m, double* u, double* v,
                     hipStream_t st)
 {
     using G = Groups<P>;
@@ -226,22 +226,26 @@ hipError_t fgt_impl(const Buffers& b, int n, int L, double sigma, int nc, int pa
         hipLaunchKernelGGL(k_fgt_join, dim3(unsigned((len + kFgtThreads - 1) / kFgtThreads)), dim3(kFgtThreads), 0,
                            st, len, parts, b.fgt_b);
     }
-    hipLaunchKernelGGL(k_t2p<P>, dim3(unsigned((n + kFgtThreads - 1) / kFgtThreads)), dim3(kFgtThreads), 0, st, n,
-                       L, b.inst, b.ksorted, b.xs, b.ys, b.perm, b.fgt_b, rsd, u, v);
+    if (m > 0)   // at the sorted target points
+        hipLaunchKernelGGL(k_t2p<P>, dim3(unsigned((m + kFgtThreads - 1) / kFgtThreads)), dim3(kFgtThreads), 0, st,
+                           m, L, b.inst, b.tks, b.txs, b.tys, b.tperm, b.fgt_b, rsd, u, v);
+    else
+        hipLaunchKernelGGL(k_t2p<P>, dim3(unsigned((n + kFgtThreads - 1) / kFgtThreads)), dim3(kFgtThreads), 0, st,
+                           n, L, b.inst, b.ksorted, b.xs, b.ys, b.perm, b.fgt_b, rsd, u, v);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_fgt(const Buffers& b, int P, int n, int L, double sigma, int nc, int parts, double* u, double* v,
-                      hipStream_t st)
+hipError_t launch_fgt(const Buffers& b, int P, int n, int L, double sigma, int nc, int parts, int m, double* u,
+                      double* v, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     if (parts < 1 || parts > 2 * nc + 1) return hipErrorInvalidValue;
     switch (P) {
-        case 8: return fgt_impl<8>(b, n, L, sigma, nc, parts, u, v, st);
-        case 12: return fgt_impl<12>(b, n, L, sigma, nc, parts, u, v, st);
-        case 16: return fgt_impl<16>(b, n, L, sigma, nc, parts, u, v, st);
+        case 8: return fgt_impl<8>(b, n, L, sigma, nc, parts, m, u, v, st);
+        case 12: return fgt_impl<12>(b, n, L, sigma, nc, parts, m, u, v, st);
+        case 16: return fgt_impl<16>(b, n, L, sigma, nc, parts, m, u, v, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -213,9 +213,10 @@ hipError_t launch_p2p_at(const Buffers& b, int P, int L, const NearKernel& nk, d
 hipError_t launch_ilist(const Buffers& b, int L, hipStream_t st);
 // the fast Gauss transform of a single-instance plan (after the tree): P
 // Hermite terms per axis (8, 12 or 16), boxes within Chebyshev distance nc,
-// the range's rows split over `parts` partial expansions
-hipError_t launch_fgt(const Buffers& b, int P, int n, int L, double sigma, int nc, int parts, double* u, double* v,
-                      hipStream_t st);
+// the range's rows split over `parts` partial expansions; evaluated at the
+// particles, or at the m sorted target points when m > 0
+hipError_t launch_fgt(const Buffers& b, int P, int n, int L, double sigma, int nc, int parts, int m, double* u,
+                      double* v, hipStream_t st);
 int fgt_parts(int P, int L, int nc);
 // h_n(d w / sqrt(delta)), |d| <= nc, n < 2P - 1, into out[(d + nc) (2P - 1) + n]
 void fgt_hermite_table(int P, int nc, double w_over_sd, double* out);
