@@ -177,3 +177,41 @@ def test_batch_entry_points_reject_null(lib):
 
 def test_advance_rejects_bad_arguments(lib):
     assert lib.fmm_advance_rk2(None, 10, None, None, None, 1e-3, 1, None, None) == fm.FMM_E_ARG
+
+
+def test_params_layout_and_enums_match_the_header(tmp_path):
+    """fmm_params as the C compiler lays it out (field offsets and size) and
+    the enum values of the header agree with the Python binding's mirror."""
+    import subprocess
+    fields = [f for f, _ in fm.FmmParams._fields_]
+    enums = ["FMM_OK", "FMM_E_ARG", "FMM_E_CAPACITY", "FMM_E_DOMAIN", "FMM_E_NOMEM", "FMM_E_DEVICE",
+             "FMM_E_UNSUPPORTED", "FMM_PREC_FP64", "FMM_PREC_MIXED", "FMM_KERNEL_GAUSSIAN", "FMM_KERNEL_SINGULAR",
+             "FMM_KERNEL_LENNARD_JONES", "FMM_KERNEL_GAUSS_TRANSFORM", "FMM_DUMP_KEYS", "FMM_DUMP_PERM",
+             "FMM_DUMP_LEAF_START", "FMM_DUMP_ME", "FMM_DUMP_LE", "FMM_DUMP_DOMAIN", "FMM_DUMP_ILIST",
+             "FMM_DUMP_TKEYS", "FMM_DUMP_TPERM", "FMM_DUMP_TLEAF_START"]
+    src = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void) {",
+           '  printf("size %zu\\n", sizeof(fmm_params));']
+    src += [f'  printf("{f} %zu\\n", offsetof(fmm_params, {f}));' for f in fields]
+    src += [f'  printf("{e} %d\\n", (int){e});' for e in enums]
+    src += ["  return 0;", "}"]
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-Wall", "-o", str(exe), str(c)], check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                       text=True).stdout.splitlines())
+    assert int(out["size"]) == C.sizeof(fm.FmmParams)
+    for f in fields:
+        assert int(out[f]) == getattr(fm.FmmParams, f).offset, f
+    py = {"FMM_OK": fm.FMM_OK, "FMM_E_ARG": fm.FMM_E_ARG, "FMM_E_CAPACITY": fm.FMM_E_CAPACITY,
+          "FMM_E_DOMAIN": fm.FMM_E_DOMAIN, "FMM_E_NOMEM": fm.FMM_E_NOMEM, "FMM_E_DEVICE": fm.FMM_E_DEVICE,
+          "FMM_E_UNSUPPORTED": fm.FMM_E_UNSUPPORTED, "FMM_PREC_FP64": fm.FMM_PREC_FP64,
+          "FMM_PREC_MIXED": fm.FMM_PREC_MIXED, "FMM_KERNEL_GAUSSIAN": fm.FMM_KERNEL_GAUSSIAN,
+          "FMM_KERNEL_SINGULAR": fm.FMM_KERNEL_SINGULAR, "FMM_KERNEL_LENNARD_JONES": fm.FMM_KERNEL_LENNARD_JONES,
+          "FMM_KERNEL_GAUSS_TRANSFORM": fm.FMM_KERNEL_GAUSS_TRANSFORM, "FMM_DUMP_KEYS": fm.DUMP_KEYS,
+          "FMM_DUMP_PERM": fm.DUMP_PERM, "FMM_DUMP_LEAF_START": fm.DUMP_LEAF_START, "FMM_DUMP_ME": fm.DUMP_ME,
+          "FMM_DUMP_LE": fm.DUMP_LE, "FMM_DUMP_DOMAIN": fm.DUMP_DOMAIN, "FMM_DUMP_ILIST": fm.DUMP_ILIST,
+          "FMM_DUMP_TKEYS": fm.DUMP_TKEYS, "FMM_DUMP_TPERM": fm.DUMP_TPERM,
+          "FMM_DUMP_TLEAF_START": fm.DUMP_TLEAF_START}
+    for e in enums:
+        assert int(out[e]) == py[e], e
