@@ -16,6 +16,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfmm_mi355x.so")
+# a host program that drives the library through the C ABI alone
+EXAMPLE_SRC = os.path.join(HERE, "examples", "fmm_eval_file.cpp")
+EXAMPLE = os.path.join(HERE, "fmm_eval_file")
 
 SOURCES = ["fmm_api.cpp", "fmm_tables.cpp", "fmm_tree.hip", "fmm_upward.hip", "fmm_downward.hip",
            "fmm_near.hip", "fmm_step.hip", "fmm_fgt.hip"]
@@ -56,6 +59,12 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, LIB)
+    cmd = [hipcc(), *COMMON, "-x", "hip", EXAMPLE_SRC, "-o", EXAMPLE + ".tmp", f"-L{HERE}", "-lfmm_mi355x",
+           "-Wl,-rpath,$ORIGIN"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"example build failed:\n{r.stderr}")
+    os.replace(EXAMPLE + ".tmp", EXAMPLE)
     if verbose:
         print(f"built {LIB}")
     return LIB
