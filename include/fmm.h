@@ -15,13 +15,17 @@
  * the evaluation step (L2P plus near-field direct interactions), Section 2.2
  * and Fig. 2.  Expansions have p complex terms, k = 0 .. p-1 ("truncated
  * after p terms", Section 2; 16p bytes per box in Table 1).
+ * A plan may choose another kernel (fmm_params.kernel, Sections 6.1 and 8):
+ * the singular kernel of eq. 7 in the near field, Lennard-Jones forces (near
+ * field only), or the discrete Gauss transform by the fast Gauss transform.
  *
  * Conventions shared by every entry point:
  *   - Every function returns an fmm_status; no C++ exception crosses the ABI.
  *   - "Device pointer" means memory on the current HIP device (hipMalloc or a
  *     PyTorch CUDA/HIP tensor).  The library never frees caller memory.
  *   - "stream" is a hipStream_t passed as void* (NULL = the default stream).
- *     fmm_evaluate and fmm_evaluate_batch only enqueue work on it: they never
+ *     fmm_evaluate, fmm_evaluate_at and fmm_evaluate_batch only enqueue work on
+ *     it (the batched form as one graph launch): they never
  *     synchronise, never allocate device memory and never read device data
  *     back to the host.
  *   - A plan is not re-entrant: two evaluations of one plan must not overlap
@@ -103,8 +107,10 @@ typedef enum {
 typedef struct {
     int64_t n_max;            /* capacity: largest n passed to fmm_evaluate (>= 0, < 2^31) */
     double  sigma;            /* Gaussian core size, > 0 (eqs. 5 and 8); ignored by the singular
-                                 kernel */
-    int32_t p;                /* number of expansion terms, 1 <= p <= 32 (<= 22 in mixed mode) */
+                                 kernel; the length s of the Lennard-Jones kernel; the width
+                                 of the Gauss transform's exp(-r^2 / (2 sigma^2)) */
+    int32_t p;                /* number of expansion terms, 1 <= p <= 32 (<= 22 in mixed mode;
+                                 Hermite terms per axis, <= 16, for the Gauss transform) */
     int32_t depth;            /* leaf level L, 0 <= L <= 13; levels 0..L, 4^L leaves */
     double  x0, y0, width;    /* domain [x0, x0+width]^2; width <= 0 selects the bounding
                                  square of the particles, recomputed at every evaluation */
@@ -120,7 +126,8 @@ typedef struct {
 
 /* Number of bytes of device workspace a plan with these parameters needs.
  * Host only; touches no device.  Errors: FMM_E_ARG for invalid parameters
- * or a NULL pointer, FMM_E_UNSUPPORTED for p > 22 in mixed mode. */
+ * or a NULL pointer, FMM_E_UNSUPPORTED for p > 22 in mixed mode and for the
+ * kernel-specific limits listed with fmm_kernel. */
 fmm_status fmm_workspace_size(const fmm_params* prm, size_t* bytes);
 
 /* Create a plan.  d_workspace: caller-owned device buffer of at least
