@@ -21,6 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fmm_oracle.c")
+_SRC3 = os.path.join(_HERE, "fmm3d_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 _lib = None
@@ -29,7 +30,7 @@ _lib = None
 def build() -> str:
     """Compile the oracle into ``oracle/liboracle.so`` (always rebuilds)."""
     cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fcx-limited-range",
-           "-fPIC", "-shared", "-std=gnu11", "-Wall", "-o", _LIB + ".tmp", _SRC,
+           "-fPIC", "-shared", "-std=gnu11", "-Wall", "-o", _LIB + ".tmp", _SRC, _SRC3,
            "-lm", "-lpthread"]
     subprocess.run(cmd, check=True)
     os.replace(_LIB + ".tmp", _LIB)
@@ -93,6 +94,21 @@ def _load():
     lib.oracle_fgt_at.argtypes = [i64, dp, dp, dp, C.c_double, C.c_int, C.c_int, C.c_double, C.c_double,
                                   C.c_double, C.c_int, i64, dp, dp, dp]
     lib.oracle_fgt_at.restype = i64
+    lib.oracle3_deriv.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, dp]
+    lib.oracle3_direct.argtypes = [i64, dp, dp, dp, dp, i64, i64p, dp, dp, dp, dp]
+    lib.oracle3_p2m.argtypes = [i64, dp, dp, dp, dp, C.c_double, C.c_double, C.c_double, C.c_int, dp]
+    lib.oracle3_me_eval.argtypes = [C.c_int, dp, C.c_double, C.c_double, C.c_double]
+    lib.oracle3_me_eval.restype = C.c_double
+    for f in (lib.oracle3_m2m, lib.oracle3_m2l, lib.oracle3_l2l, lib.oracle3_l2p):
+        f.argtypes = [C.c_int, dp, C.c_double, C.c_double, C.c_double, dp]
+    lib.oracle3_leaf_coords.argtypes = [i64, dp, dp, dp, C.c_int, C.c_double, C.c_double, C.c_double,
+                                        C.c_double, i32p, i32p, i32p]
+    lib.oracle3_leaf_coords.restype = i64
+    lib.oracle3_morton.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32]
+    lib.oracle3_morton.restype = C.c_uint32
+    lib.oracle3_fmm.argtypes = [i64, dp, dp, dp, dp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
+                                C.c_double, dp, dp, dp, dp]
+    lib.oracle3_fmm.restype = i64
     lib.oracle_init()
     _lib = lib
     return lib
@@ -397,3 +413,103 @@ def fgt_at(x, y, q, sigma, p, L, nc, tx, ty, x0=0.0, y0=0.0, W=1.0):
                              tx.shape[0], _d(tx), _d(ty), _d(G))
     return G, int(nbad)
 
+
+
+# ---------------------------------------------------------------------------
+# 3D form: Laplace kernel 1/r, Cartesian Taylor expansions (fmm3d_oracle.c)
+# ---------------------------------------------------------------------------
+
+P3MAX = 12
+
+
+def _cube(p):
+    return np.zeros((p + 1) ** 3)
+
+
+def deriv3(q, r):
+    """D[a, b, c] = d^(a,b,c) (1/|R|) at R = r for a + b + c <= q (else 0)."""
+    D = _cube(q)
+    _load().oracle3_deriv(q, float(r[0]), float(r[1]), float(r[2]), _d(D))
+    return D.reshape(q + 1, q + 1, q + 1)
+
+
+def direct3(x, y, z, q, targets=None):
+    """Potential and its gradient from the plain sum over all other particles."""
+    lib = _load()
+    x, y, z, q = _f64(x), _f64(y), _f64(z), _f64(q)
+    n = x.shape[0]
+    t, nt, tp = _targets(targets, n)
+    out = [np.zeros(nt) for _ in range(4)]
+    lib.oracle3_direct(n, _d(x), _d(y), _d(z), _d(q), nt, tp, *(_d(a) for a in out))
+    return tuple(out)
+
+
+def p2m3(x, y, z, q, c, p):
+    M = _cube(p)
+    x, y, z, q = _f64(x), _f64(y), _f64(z), _f64(q)
+    _load().oracle3_p2m(x.shape[0], _d(x), _d(y), _d(z), _d(q), float(c[0]), float(c[1]), float(c[2]), p, _d(M))
+    return M
+
+
+def me_eval3(M, p, r):
+    M = _f64(M)
+    return float(_load().oracle3_me_eval(p, _d(M), float(r[0]), float(r[1]), float(r[2])))
+
+
+def _op3(fn, p, A, d, n_out=None):
+    A = _f64(A)
+    out = np.zeros(n_out if n_out else (p + 1) ** 3)
+    fn(p, _d(A), float(d[0]), float(d[1]), float(d[2]), _d(out))
+    return out
+
+
+def m2m3(M, p, d):
+    """Moments about c' = c + d from moments about c."""
+    return _op3(_load().oracle3_m2m, p, M, d)
+
+
+def m2l3(M, p, r):
+    """Local coefficients about t from moments about s, r = t - s."""
+    return _op3(_load().oracle3_m2l, p, M, r)
+
+
+def l2l3(Lc, p, d):
+    """Local coefficients about t' = t + d from those about t."""
+    return _op3(_load().oracle3_l2l, p, Lc, d)
+
+
+def l2p3(Lc, p, e):
+    """(phi, dphi/dx, dphi/dy, dphi/dz) at t + e."""
+    return _op3(_load().oracle3_l2p, p, Lc, e, 4)
+
+
+def morton3(a, b, c):
+    return int(_load().oracle3_morton(a, b, c))
+
+
+def leaf_keys3(x, y, z, L, origin=(0.0, 0.0, 0.0), W=1.0):
+    """Morton leaf key per particle (2^(3L) for one outside the cube) and the
+    stable key order: what the GPU tree must reproduce bit for bit."""
+    lib = _load()
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    n = x.shape[0]
+    ia, ib, ic = (np.zeros(n, np.int32) for _ in range(3))
+    ip = C.POINTER(C.c_int32)
+    lib.oracle3_leaf_coords(n, _d(x), _d(y), _d(z), L, float(origin[0]), float(origin[1]), float(origin[2]),
+                            float(W), ia.ctypes.data_as(ip), ib.ctypes.data_as(ip), ic.ctypes.data_as(ip))
+    keys = np.array([morton3(int(a), int(b), int(c)) if a >= 0 else 1 << (3 * L)
+                     for a, b, c in zip(ia, ib, ic)], dtype=np.uint32)
+    return keys, np.argsort(keys, kind="stable").astype(np.uint32)
+
+
+def fmm3(x, y, z, q, p, L, origin=(0.0, 0.0, 0.0), W=1.0):
+    """One FP64 FMM evaluation of the 3D form: (phi, gx, gy, gz, nbad)."""
+    lib = _load()
+    if not (0 <= p <= P3MAX) or not (0 <= L <= 7):
+        raise ValueError("p or L out of range")
+    x, y, z, q = _f64(x), _f64(y), _f64(z), _f64(q)
+    n = x.shape[0]
+    out = [np.zeros(n) for _ in range(4)]
+    nbad = lib.oracle3_fmm(n, _d(x), _d(y), _d(z), _d(q), p, L, float(origin[0]), float(origin[1]),
+                           float(origin[2]), float(W), *(_d(a) for a in out))
+    return (*out, int(nbad))
