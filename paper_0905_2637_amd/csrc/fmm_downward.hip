@@ -204,6 +204,92 @@ k_m2l(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restrict__
     }
 }
 
+// FP64 M2L with the sources of the workgroup's tile staged in LDS once: the
+// 16 x 16 target boxes of a workgroup (four child classes of an 8 x 8 parent
+// block) draw their interaction lists from the 20 x 20 boxes around them;
+// boxes outside the grid are staged as zeros.  Same work decomposition and
+// summation order as k_m2l, so the two give the same bits.  The stage takes
+// 6.4 KB per expansion term (109 KB at p = 17), which leaves room for one
+// workgroup per CU.  Measured at p = 17: on grids of 9 and 21 workgroups it
+// halves the M2L time (the shared loads shorten each member's wait); at 69
+// and more it loses to k_m2l, whose smaller footprint lets more wavefronts
+// hide the loads.
+constexpr int kHalo = 20;
+constexpr int kM2LStageMaxWg = 32;
+template <int P>
+__global__ void __launch_bounds__(256)
+k_m2l64_lds(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restrict__ me_all, M2LOut dst_,
+            const cplx<double>* __restrict__ H, const double* __restrict__ sout_)
+{
+    constexpr int NH = 2 * P - 1;
+    __shared__ cd sA[kHalo * kHalo * P];
+    const int lin = xcd_runs(int(blockIdx.x + gridDim.x * blockIdx.y), int(gridDim.x * gridDim.y), kM2LXcdRun);
+    const int g = lin / int(gridDim.x), blk = lin % int(gridDim.x);
+    const int pos = find_inst(wk.wg_begin, n_inst, blk);
+    const int q = wk.order[pos];
+    const int G = min(int(gridDim.y), inst[q].g64);
+    if (g >= G) return;
+    int bl = blk - wk.wg_begin[pos];
+    int l = wk.arg[2 * pos];
+    while (bl >= level_blocks(l)) { bl -= level_blocks(l); ++l; }
+    const cd* me = me_all + inst[q].box_off * P;
+    cd* __restrict__ le = g == 0 ? dst_.out[0] + inst[q].box_off * P : dst_.out[g] + inst[q].split_off * P;
+    const int side = 1 << l;
+    const int bpr = side >= 16 ? side / 16 : 1;
+    const int bx = bl % bpr, by = bl / bpr;
+    const cd* me_l = me + level_offset(l) * P;
+    const int x_lo = 16 * bx - 2, y_lo = 16 * by - 2;
+    for (int e = threadIdx.x; e < kHalo * kHalo * P; e += 256) {
+        const int hb = e / P, k = e - hb * P;
+        const int sa = x_lo + hb % kHalo, sb = y_lo + hb / kHalo;
+        const bool in = sa >= 0 && sb >= 0 && sa < side && sb < side;
+        const cd v = me_l[int64_t(morton(uint32_t(in ? sa : 0), uint32_t(in ? sb : 0))) * P + k];
+        sA[e] = in ? v : cd{0.0, 0.0};
+    }
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int cx = wave & 1, cy = wave >> 1;
+    const int ta = 2 * (bx * 8 + (lane & 7)) + cx;
+    const int tb = 2 * (by * 8 + (lane >> 3)) + cy;
+    const bool active = ta < side && tb < side;
+    double bx_[P], by_[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) { bx_[k] = 0.0; by_[k] = 0.0; }
+    int member = 0;
+    for (int o = 0; o < 36; ++o) {
+        int dx, dy;
+        if (!il_offset(cx, cy, o, dx, dy)) continue;
+        if ((member++) % G != g) continue;
+        const cd* src = sA + ((tb + dy - y_lo) * kHalo + (ta + dx - x_lo)) * P;
+        double ax[P], ay[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const cd t = src[k];
+            ax[k] = t.x;
+            ay[k] = t.y;
+        }
+        const cplx<double>* h = H + ((dy + 3) * kHankelGrid + (dx + 3)) * NH;
+#pragma unroll
+        for (int nn = 0; nn < 2 * P - 1; ++nn) {
+            const cplx<double> hn = h[nn];
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                const int j = nn - k;
+                if (j >= 0 && j < P) cmac(bx_[j], by_[j], hn.x, hn.y, ax[k], ay[k]);
+            }
+        }
+    }
+    if (active) {
+        cd* dst = le + (level_offset(l) + int64_t(morton(uint32_t(ta), uint32_t(tb)))) * P;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const double sc = sout_[k];
+            dst[k] = cd{bx_[k] * sc, by_[k] * sc};
+        }
+    }
+}
+
 // FP32 M2L on the matrix cores.  Written real-valued, the factored M2L of
 // one interaction-list member is a dense product
 //   [Re b; Im b] = [[Hr, -Hi], [Hi, Hr]] [Re abar; Im abar],  H[l][k] = h_{k+l}(tau),
@@ -507,6 +593,13 @@ hipError_t m2l_impl(const Buffers& b, const Work& w, int nwg, bool fp32, bool mf
         if (fp32) {
             hipLaunchKernelGGL((k_m2l<P, float>), grid, dim3(256), 0, st, w, b.n_inst, b.inst, b.me, out,
                                reinterpret_cast<const cplx<float>*>(b.t_h32), b.t_sout);
+            return hipGetLastError();
+        }
+    }
+    if constexpr (P <= 20) {       // beyond, the staged form spills registers
+        if (int64_t(nwg) * groups <= kM2LStageMaxWg) {
+            hipLaunchKernelGGL((k_m2l64_lds<P>), grid, dim3(256), 0, st, w, b.n_inst, b.inst, b.me, out,
+                               reinterpret_cast<const cplx<double>*>(b.t_h64), b.t_sout);
             return hipGetLastError();
         }
     }

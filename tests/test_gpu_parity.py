@@ -155,6 +155,33 @@ def test_fp64_parameter_grid(n, L, p, sigma, seed):
     assert oracle.rel_l2(u, v, uo, vo) < FP64_TOL
 
 
+@pytest.mark.parametrize("p", [17, 20])
+def test_fp64_m2l_register_and_staged_forms(p):
+    """Depth 7 has 87 M2L tiles.  Split three ways (the default) they take 261
+    workgroups, unsplit 87: the register form of the FP64 M2L runs.  Split up
+    to level 5, levels 2-5 take 21 workgroups and run in the form with the
+    sources staged in LDS, levels 6-7 in the register form.  All match the
+    oracle and each other (the splits only reassociate the sums)."""
+    import torch
+    fm = _fm()
+    x, y, g = workloads.uniform_square(40000, 13)
+    uo, vo = oracle.fmm(x, y, g, 0.002, p, 7)
+    plan = fm.Plan(len(x), 0.002, p, 7)
+    xd, yd, gd = (torch.as_tensor(a, device="cuda") for a in (x, y, g))
+    ref = None
+    for split in (8, 0, 5):
+        plan.set_tuning(4, split, 0)
+        u, v = plan.evaluate(xd, yd, gd, check=True)
+        torch.cuda.synchronize()
+        u, v = u.cpu().numpy(), v.cpu().numpy()
+        assert oracle.rel_l2(u, v, uo, vo) < FP64_TOL, split
+        if ref is None:
+            ref = (u, v)
+        else:
+            assert oracle.rel_l2(u, v, *ref) < 1e-14, split
+    plan.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_quad_pairs(precision):
     """The near field inside a 2 x 2 block of sibling leaves is evaluated once
