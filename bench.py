@@ -349,6 +349,26 @@ def run_gauss_transform(wl, args, dev, sigma=0.02, depth=6, p=12):
     return sec, G, {"tree": round(stages["tree"], 4), "transform": round(stages["p2m_m2m"], 4)}
 
 
+def run_laplace_3d(args, dev, n=1 << 20, depth=5, p=6):
+    """The 3D form: 2^20 charges uniform in the unit cube, octree depth 5
+    (about 32 per leaf), Cartesian Taylor expansions of degree 6, FP64
+    potential and gradient."""
+    import torch
+    import paper_0905_2637_amd as fm
+    arrs = workloads.uniform_cube(n, 3003)
+    x, y, z, q = (torch.as_tensor(a, device=dev) for a in arrs)
+    out = tuple(torch.empty(n, dtype=torch.float64, device=dev) for _ in range(4))
+    plan = fm.Plan3D(n, p, depth)
+    for _ in range(args.warmup):
+        plan.evaluate(x, y, z, q, out)
+    torch.cuda.synchronize()
+    sec = timed(lambda: plan.evaluate(x, y, z, q, out), args.steps, 0)
+    if plan.out_of_domain():
+        raise RuntimeError("3D form: particles outside the cube")
+    plan.close()
+    return sec, arrs, out
+
+
 # ---------------------------------------------------------------------------
 # CPU oracle leg (the only part of the bench that touches the oracle)
 # ---------------------------------------------------------------------------
@@ -388,6 +408,17 @@ def cpu_baseline_leg(wl, res, args, forms):
             forms["mixed"]["rel_l2_vs_fp64_split_direct"] = oracle.rel_l2(um[tgt], vm[tgt], us, vs)
             forms["mixed"]["rel_l2_vs_regularised_direct"] = oracle.rel_l2(um[tgt], vm[tgt], ur, vr)
             forms["mixed"]["rel_l2_vs_gpu_fp64"] = oracle.rel_l2(um, vm, u_gpu, v_gpu)
+        if forms and "_l3d" in forms:
+            (x3, y3, z3, q3), out3 = forms.pop("_l3d")
+            g3 = [o.cpu().numpy() for o in out3]
+            t3 = workloads.sample_targets(len(x3), 256, 3004)
+            d3 = oracle.direct3(x3, y3, z3, q3, targets=t3)
+            num = sum(float(np.sum((g3[k][t3] - d3[k]) ** 2)) for k in (1, 2, 3))
+            den = sum(float(np.sum(d3[k] ** 2)) for k in (1, 2, 3))
+            forms["laplace_3d"]["rel_l2_gradient_vs_plain_sum"] = (num / den) ** 0.5
+            forms["laplace_3d"]["rel_l2_potential_vs_plain_sum"] = float(
+                np.linalg.norm(g3[0][t3] - d3[0]) / np.linalg.norm(d3[0]))
+            forms["laplace_3d"]["plain_sum_targets"] = int(t3.shape[0])
         if forms and "_gauss_G" in forms:
             Gg = forms.pop("_gauss_G").cpu().numpy()
             Gd = oracle.gauss_direct(wl.x, wl.y, wl.gamma, 0.02, targets=tgt)
@@ -488,6 +519,11 @@ def main() -> int:
                                                 "sigma = 0.02, 4096 leaf boxes (depth 6), p = 12 per axis, FP64",
                                     "ms": round(tg * 1e3, 4), "particles_per_s": wl.n / tg, "stages_ms": sg}
         forms["_gauss_G"] = Gg
+        t3, arrs3, out3 = run_laplace_3d(args, dev)
+        forms["laplace_3d"] = {"workload": "3D form: 2^20 charges uniform in the unit cube, octree depth 5, "
+                                           "Cartesian Taylor expansions of degree 6, FP64 potential and gradient",
+                               "ms": round(t3 * 1e3, 4), "particles_per_s": (1 << 20) / t3}
+        forms["_l3d"] = (arrs3, out3)
         w4 = workloads.make("C4")
         rb = run_batch(w4, args, dev)
         rb64 = run_batch(w4, args, dev, precision="fp64")
@@ -535,6 +571,7 @@ def main() -> int:
     if forms is not None:
         forms.pop("_mixed_uv", None)
         forms.pop("_gauss_G", None)
+        forms.pop("_l3d", None)
         out["forms"] = forms
     print(json.dumps(out))
     return 0

@@ -318,6 +318,61 @@ fmm_status fmm_destroy(fmm_plan_t plan);
 /* Static description of a status code. */
 const char* fmm_status_string(fmm_status s);
 
+/* ---- 3D form ------------------------------------------------------------
+ * The method on a uniform octree (Section 8: in 3D the tree, the sweeps and
+ * the lists stay; the kernel, its series expansions and translation
+ * operators change), for the Laplace kernel 1/r:
+ *     phi(x_i)      = sum_{j != i} q_j / |x_i - x_j|
+ *     grad phi(x_i) = sum_{j != i} -q_j (x_i - x_j) / |x_i - x_j|^3
+ * (pairs at zero distance contribute nothing).  Near field = the leaf and
+ * the 26 leaves touching it, evaluated directly; interaction list = the up
+ * to 189 boxes of the same level whose parents touch the box's parent but
+ * which do not touch the box.  Far field through Cartesian Taylor
+ * expansions of total degree <= p ((p+1)(p+2)(p+3)/6 terms per box): P2M,
+ * M2M, M2L, L2L, L2P.  FP64 throughout.  The 3D vortex velocity is the curl
+ * of three such potentials (one per vorticity component); that combination
+ * is left to the caller.
+ *
+ * Particles must lie in the cube [x0, x0 + width)^3; one outside it (or with
+ * a NaN coordinate) gets zero outputs, acts on nothing and is counted by
+ * fmm3d_get_status.  Same workspace, stream and error conventions as the 2D
+ * entry points: the caller owns the 256-byte aligned device workspace; the
+ * evaluation only enqueues work on the stream. */
+typedef struct fmm3d_plan_s* fmm3d_plan_t;     /* opaque host handle */
+
+typedef struct {
+    int64_t n_max;      /* particle capacity, 0 .. 2^31 - 1 */
+    int32_t p;          /* expansion degree, 0 .. 9 (FMM_E_UNSUPPORTED above) */
+    int32_t depth;      /* octree depth L, 0 .. 7 (8^L leaves; FMM_E_UNSUPPORTED above);
+                           L <= 1 leaves no far field: the direct sum */
+    double x0, y0, z0;  /* lower corner of the cube */
+    double width;       /* its side, > 0 */
+} fmm3d_params;
+
+/* Bytes of device workspace a plan with these parameters needs.  Host only.
+ * Errors: FMM_E_ARG (NULL, negative or non-finite values), FMM_E_UNSUPPORTED
+ * (p > 9 or depth > 7). */
+fmm_status fmm3d_workspace_size(const fmm3d_params* prm, size_t* bytes);
+
+/* Bind the parameters to a workspace of at least fmm3d_workspace_size bytes
+ * (256-byte aligned, else FMM_E_ARG; smaller: FMM_E_CAPACITY).  Uploads the
+ * M2L derivative table on `stream` and waits for it. */
+fmm_status fmm3d_plan(const fmm3d_params* prm, void* d_workspace, size_t bytes, void* stream,
+                      fmm3d_plan_t* out);
+
+/* Potential and gradient at the n particles (device FP64 arrays of length
+ * n, outputs in input order).  n > n_max: FMM_E_CAPACITY.  Enqueues only. */
+fmm_status fmm3d_evaluate(fmm3d_plan_t plan, int64_t n, const double* d_x, const double* d_y,
+                          const double* d_z, const double* d_q, double* d_phi, double* d_gx,
+                          double* d_gy, double* d_gz, void* stream);
+
+/* Waits for `stream` and reports the particles the last evaluation found
+ * outside the cube: FMM_E_DOMAIN if there were any. */
+fmm_status fmm3d_get_status(fmm3d_plan_t plan, void* stream, int64_t* n_outside);
+
+/* Release the host handle (never the workspace).  NULL is accepted. */
+fmm_status fmm3d_destroy(fmm3d_plan_t plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -35,7 +35,13 @@ DUMP_TKEYS, DUMP_TPERM, DUMP_TLEAF_START = range(7, 10)
 EXPORTED = ["fmm_workspace_size", "fmm_plan", "fmm_evaluate", "fmm_evaluate_at", "fmm_workspace_size_batch",
             "fmm_plan_batch", "fmm_evaluate_batch", "fmm_advance_rk2", "fmm_get_status", "fmm_set_timing", "fmm_stats", "fmm_stage_name",
             "fmm_get_tuning", "fmm_set_tuning", "fmm_autotune", "fmm_work_estimate", "fmm_debug_dump", "fmm_destroy",
-            "fmm_status_string"]
+            "fmm_status_string", "fmm3d_workspace_size", "fmm3d_plan", "fmm3d_evaluate", "fmm3d_get_status",
+            "fmm3d_destroy"]
+
+
+class Fmm3dParams(C.Structure):
+    _fields_ = [("n_max", C.c_int64), ("p", C.c_int32), ("depth", C.c_int32), ("x0", C.c_double),
+                ("y0", C.c_double), ("z0", C.c_double), ("width", C.c_double)]
 
 
 class FmmParams(C.Structure):
@@ -86,6 +92,11 @@ def load():
     lib.fmm_destroy.argtypes = [vp]
     lib.fmm_status_string.argtypes = [C.c_int]
     lib.fmm_status_string.restype = C.c_char_p
+    lib.fmm3d_workspace_size.argtypes = [C.POINTER(Fmm3dParams), C.POINTER(C.c_size_t)]
+    lib.fmm3d_plan.argtypes = [C.POINTER(Fmm3dParams), vp, C.c_size_t, vp, C.POINTER(vp)]
+    lib.fmm3d_evaluate.argtypes = [vp, C.c_int64] + [vp] * 9
+    lib.fmm3d_get_status.argtypes = [vp, vp, C.POINTER(C.c_int64)]
+    lib.fmm3d_destroy.argtypes = [vp]
     for name in EXPORTED:
         if name in ("fmm_stage_name", "fmm_status_string"):
             continue
@@ -421,3 +432,64 @@ class BatchPlan(_PlanBase):
         if s != FMM_OK:
             raise FmmError(s, "fmm_autotune")
         return self.tuning()
+
+
+class Plan3D:
+    """The 3D form (octree, Laplace kernel 1/r, Cartesian Taylor expansions of
+    total degree ``p`` <= 9, ``depth`` <= 7) bound to a device workspace.
+    ``evaluate`` returns the potential and its gradient at every particle of
+    the cube ``origin`` + [0, ``width``)^3."""
+
+    def __init__(self, n_max, p, depth, origin=(0.0, 0.0, 0.0), width=1.0, device="cuda"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the FMM runs only on the GPU")
+        self.params = Fmm3dParams(int(n_max), int(p), int(depth), float(origin[0]), float(origin[1]),
+                                  float(origin[2]), float(width))
+        self.n_max, self.p, self.depth = int(n_max), int(p), int(depth)
+        self.device = torch.device(device)
+        lib = load()
+        nbytes = C.c_size_t(0)
+        s = lib.fmm3d_workspace_size(C.byref(self.params), C.byref(nbytes))
+        if s != FMM_OK:
+            raise FmmError(s, "fmm3d_workspace_size")
+        self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        base = (self.workspace.data_ptr() + 255) & ~255
+        handle = C.c_void_p()
+        s = lib.fmm3d_plan(C.byref(self.params), C.c_void_p(base), nbytes, _stream_handle(), C.byref(handle))
+        if s != FMM_OK:
+            raise FmmError(s, "fmm3d_plan")
+        self._h = handle
+
+    def evaluate(self, x, y, z, q, out=None, check=False):
+        """(phi, dphi/dx, dphi/dy, dphi/dz) at every particle; FP64 device tensors."""
+        import torch
+        n = int(x.shape[0])
+        if out is None:
+            out = tuple(torch.empty(n, dtype=torch.float64, device=x.device) for _ in range(4))
+        _check_inputs(n, (x, y, z, q) + tuple(out))
+        s = load().fmm3d_evaluate(self._h, n, *(C.c_void_p(t.data_ptr()) for t in (x, y, z, q) + tuple(out)),
+                                  _stream_handle())
+        if s != FMM_OK:
+            raise FmmError(s, "fmm3d_evaluate")
+        if check and self.out_of_domain():
+            raise FmmError(FMM_E_DOMAIN, "fmm3d_evaluate")
+        return out
+
+    def out_of_domain(self) -> int:
+        v = C.c_int64(0)
+        s = load().fmm3d_get_status(self._h, _stream_handle(), C.byref(v))
+        if s not in (FMM_OK, FMM_E_DOMAIN):
+            raise FmmError(s, "fmm3d_get_status")
+        return int(v.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().fmm3d_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -670,4 +670,41 @@ hipError_t launch_tree_points(const Buffers& b, int m, const double* tx, const d
     return hipGetLastError();
 }
 
+hipError_t launch_sort_keys(const Buffers& b, int n, const uint32_t* key, const double* x, const double* y,
+                            const double* g, uint32_t* ks, uint32_t* perm, double* xs, double* ys, double* gs,
+                            int key_bits, hipStream_t st)
+{
+    const int npass = radix_passes(key_bits);
+    if (n <= 0 || npass <= 0) return hipErrorInvalidValue;
+    const int nblk = int(radix_blocks(n));
+    const int64_t m = int64_t(kRadixBins) * nblk;
+    const Records fin{ks, perm, xs, ys, gs};
+    const Records tmp{b.ktmp, b.itmp, b.xt, b.yt, b.gt};
+    const bool wide = nblk <= kWideTilesMax;
+    const uint32_t* kin = key;
+    const uint32_t* iin = nullptr;
+    const double *xin = x, *yin = y, *gin = g;
+    for (int pass = 0; pass < npass; ++pass) {
+        const Records& out = ((npass - 1 - pass) & 1) ? tmp : fin;
+        const int shift = 8 * pass;
+        if (wide)
+            hipLaunchKernelGGL(k_rhist<1024>, dim3(nblk), dim3(1024), 0, st, n, kin, shift, nblk, b.hist);
+        else
+            hipLaunchKernelGGL(k_rhist<256>, dim3(nblk), dim3(256), 0, st, n, kin, shift, nblk, b.hist);
+        scan_table(b, m, st);
+        if (wide)
+            hipLaunchKernelGGL(k_rscatter<1024>, dim3(nblk), dim3(1024), 0, st, n, kin, iin, xin, yin, gin, shift,
+                               nblk, b.hist, b.hist_scan, out, nullptr, nullptr, 0);
+        else
+            hipLaunchKernelGGL(k_rscatter<256>, dim3(nblk), dim3(256), 0, st, n, kin, iin, xin, yin, gin, shift,
+                               nblk, b.hist, b.hist_scan, out, nullptr, nullptr, 0);
+        kin = out.k;
+        iin = out.idx;
+        xin = out.x;
+        yin = out.y;
+        gin = out.g;
+    }
+    return hipGetLastError();
+}
+
 }  // namespace fmm

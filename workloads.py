@@ -65,6 +65,16 @@ def uniform_square(n: int, seed: int) -> tuple[np.ndarray, np.ndarray, np.ndarra
     return x, y, g
 
 
+def uniform_cube(n: int, seed: int) -> tuple[np.ndarray, np.ndarray, np.ndarray, np.ndarray]:
+    """n points uniform in [0,1)^3 with charges q ~ U(-1,1) (the 3D form)."""
+    rng = np.random.default_rng(seed)
+    x = rng.random(n)
+    y = rng.random(n)
+    z = rng.random(n)
+    q = rng.uniform(-1.0, 1.0, n)
+    return x, y, z, q
+
+
 def lamb_oseen_lattice(m: int, core: float, total_circulation: float = 1.0,
                        jitter: float = 0.0, seed: int = 0,
                        lo: float = 0.0, hi: float = 1.0,
