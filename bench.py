@@ -463,6 +463,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-forms", action="store_true", help="skip the mixed and batched form comparison")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="time budget of the CPU oracle leg")
+    ap.add_argument("--form", default=None, choices=["laplace_3d"],
+                    help="time only this form (one JSON line with its timing; for profiling)")
     ap.add_argument("--accuracy-targets", type=int, default=1024)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the timed region, run a plain device copy of this size (counter calibration)")
@@ -479,6 +481,11 @@ def main() -> int:
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no HIP device"}))
         return 1
+    if args.form == "laplace_3d":
+        t3, _, _ = run_laplace_3d(args, torch.device("cuda"))
+        print(json.dumps({"form": "laplace_3d", "ms": t3 * 1e3, "particles_per_s": (1 << 20) / t3,
+                          "steps": args.steps, "warmup": args.warmup}))
+        return 0
     dev = torch.device("cuda:0")
     wl = workloads.make(args.config)
     batched = wl.offsets is not None

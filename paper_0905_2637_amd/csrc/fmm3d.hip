@@ -224,6 +224,116 @@ k3_m2l(Geo3 g, int l, const double* __restrict__ me, double* __restrict__ le, co
     if (t < T) le[(lvl_off3(l) + box) * T + t] = acc;
 }
 
+// M2L for p <= kLaneMaxP3, all levels in one launch.  One lane per target box:
+// a workgroup takes the 64 boxes of one parity class (child position in the
+// parent) under a 4 x 4 x 4 block of parents, so all its lanes walk the same
+// 189 offsets, and each wavefront computes a quarter of the output terms.
+// The derivative row of the current offset is the same for every lane: it is
+// staged in LDS as a dense (2p+1)^3 cube and read back as broadcasts.  In the
+// cube the entry of k + n sits at cube(k) + cube(n): cube(n) is a
+// compile-time constant of the unrolled output loop, cube(k) one LDS read per
+// source term.
+template <int P>
+__host__ __device__ constexpr int cube_of(int t)
+{
+    int d = 0;
+    while (tet3(d + 1) <= t) ++d;
+    int r = t - tet3(d), s = 0;
+    while (tri3(s + 1) <= r) ++s;
+    const int c = r - tri3(s), b = s - c, a = d - s;
+    return (a * (2 * P + 1) + b) * (2 * P + 1) + c;
+}
+
+struct LaneLevels {
+    int n_levels;
+    int first_level;
+    int blk_begin[kDepth3Max + 1];   // first workgroup of each level, then the total
+};
+
+// FMA block of one wavefront for one interaction offset: outputs
+// [W Q, W Q + Q) of its lane's target, all terms of the lane's source
+template <int P, int W>
+__device__ __forceinline__ void m2l_lanes_fma(double (&acc)[(tet3(P + 1) + 3) / 4], const double* __restrict__ sD,
+                                              const double* __restrict__ src, bool vs, const int* __restrict__ sK)
+{
+    constexpr int T = tet3(P + 1), Q = (T + 3) / 4, N0 = W * Q, N1 = N0 + Q < T ? N0 + Q : T;
+#pragma unroll 1
+    for (int k0 = 0; k0 < T; k0 += 4) {
+        double m[4];
+        int ik[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = k0 + j;
+            const bool in = k < T;
+            m[j] = (vs && in) ? src[k] : 0.0;
+            ik[j] = in ? sK[k] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double* d = sD + ik[j];
+#pragma unroll
+            for (int n = N0; n < N1; ++n) acc[n - N0] = fma(d[cube_of<P>(n)], m[j], acc[n - N0]);
+            // one source term at a time: keeps the scheduler from hoisting the
+            // LDS reads of all four terms (which spills)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+template <int P>
+__global__ void __launch_bounds__(256)
+k3_m2l_lanes(Geo3 g, LaneLevels lv, const double* __restrict__ me, double* __restrict__ le,
+             const double* __restrict__ dcube, const int* __restrict__ kcube)
+{
+    constexpr int T = tet3(P + 1), Q = (T + 3) / 4;
+    constexpr int S = 2 * P + 1, S3 = S * S * S;
+    __shared__ double sD[S3];
+    __shared__ int sK[T];
+    int li = 0;
+    while (li + 1 < lv.n_levels && int(blockIdx.x) >= lv.blk_begin[li + 1]) ++li;
+    const int l = lv.first_level + li;
+    const int blk = int(blockIdx.x) - lv.blk_begin[li];
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+    const int lane = int(threadIdx.x) & 63;
+    const int cls = int(blockIdx.y);
+    const int cx = cls & 1, cy = (cls >> 1) & 1, cz = cls >> 2;
+    const int h = 1 << (l - 1), nb = h >= 4 ? h / 4 : 1, side = 2 * h;
+    const int bx = blk % nb, by = (blk / nb) % nb, bz = blk / (nb * nb);
+    const int px = 4 * bx + (lane & 3), py = 4 * by + ((lane >> 2) & 3), pz = 4 * bz + (lane >> 4);
+    const bool vt = px < h && py < h && pz < h;
+    const int ta = 2 * px + cx, tb = 2 * py + cy, tc = 2 * pz + cz;
+    const double* me_l = me + lvl_off3(l) * T;
+    for (int e = int(threadIdx.x); e < T; e += 256) sK[e] = kcube[e];
+    double acc[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) acc[i] = 0.0;
+    for (int oz = cz - 3; oz <= cz + 2; ++oz)
+        for (int oy = cy - 3; oy <= cy + 2; ++oy)
+            for (int ox = cx - 3; ox <= cx + 2; ++ox) {
+                if (abs(ox) <= 1 && abs(oy) <= 1 && abs(oz) <= 1) continue;
+                const double* drow = dcube + int64_t(off3_index(ox, oy, oz)) * S3;
+                __syncthreads();
+                for (int e = int(threadIdx.x); e < S3; e += 256) sD[e] = drow[e];
+                __syncthreads();
+                const int sa = ta - ox, sb = tb - oy, sc = tc - oz;
+                const bool vs = vt && sa >= 0 && sb >= 0 && sc >= 0 && sa < side && sb < side && sc < side;
+                const double* src = me_l + (vs ? int64_t(morton3(uint32_t(sa), uint32_t(sb), uint32_t(sc))) * T : 0);
+                switch (wave) {
+                    case 0: m2l_lanes_fma<P, 0>(acc, sD, src, vs, sK); break;
+                    case 1: m2l_lanes_fma<P, 1>(acc, sD, src, vs, sK); break;
+                    case 2: m2l_lanes_fma<P, 2>(acc, sD, src, vs, sK); break;
+                    default: m2l_lanes_fma<P, 3>(acc, sD, src, vs, sK); break;
+                }
+            }
+    if (vt) {
+        double* dst = le + (lvl_off3(l) + int64_t(morton3(uint32_t(ta), uint32_t(tb), uint32_t(tc)))) * T + wave * Q;
+        const int cnt = wave * Q + Q < T ? Q : T - wave * Q;
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            if (i < cnt) dst[i] = acc[i];
+    }
+}
+
 // L2L into level l (>= 3): one workgroup per child box
 __global__ void __launch_bounds__(kTpb)
 k3_l2l(Geo3 g, int l, double* __restrict__ le)
@@ -332,9 +442,10 @@ k3_eval(Geo3 g, int far, const int32_t* __restrict__ ls, const double* __restric
                                 const double ddx = xi - sx[jj], ddy = yi - sy[jj], ddz = zi - sz[jj];
                                 const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
                                 if (r2 == 0.0) continue;
-                                const double r = sqrt(r2);
-                                f += sq[jj] / r;
-                                const double cc = sq[jj] / (r2 * r);
+                                const double ir = 1.0 / sqrt(r2);
+                                const double qr = sq[jj] * ir;
+                                f += qr;
+                                const double cc = qr * ir * ir;
                                 fx -= cc * ddx;
                                 fy -= cc * ddy;
                                 fz -= cc * ddz;
@@ -383,8 +494,36 @@ hipError_t launch3_upward(const Bufs3& b, const Geo3& g, hipStream_t st)
     return hipGetLastError();
 }
 
+namespace {
+template <int P>
+void m2l_lanes(const Bufs3& b, const Geo3& g, hipStream_t st)
+{
+    LaneLevels lv{};
+    lv.first_level = 2;
+    lv.n_levels = g.L - 1;
+    int total = 0;
+    for (int l = 2; l <= g.L; ++l) {
+        lv.blk_begin[l - 2] = total;
+        const int h = 1 << (l - 1), nb = h >= 4 ? h / 4 : 1;
+        total += nb * nb * nb;
+    }
+    lv.blk_begin[g.L - 1] = total;
+    hipLaunchKernelGGL((k3_m2l_lanes<P>), dim3(unsigned(total), 8u), dim3(256), 0, st, g, lv, b.me, b.le, b.dcube,
+                       b.kcube);
+}
+}  // namespace
+
 hipError_t launch3_m2l(const Bufs3& b, const Geo3& g, hipStream_t st)
 {
+    switch (g.p) {
+        case 1: m2l_lanes<1>(b, g, st); return hipGetLastError();
+        case 2: m2l_lanes<2>(b, g, st); return hipGetLastError();
+        case 3: m2l_lanes<3>(b, g, st); return hipGetLastError();
+        case 4: m2l_lanes<4>(b, g, st); return hipGetLastError();
+        case 5: m2l_lanes<5>(b, g, st); return hipGetLastError();
+        case 6: m2l_lanes<6>(b, g, st); return hipGetLastError();
+        default: break;
+    }
     for (int l = 2; l <= g.L; ++l)
         hipLaunchKernelGGL(k3_m2l, dim3(1u << (3 * l)), dim3(kTpb), 0, st, g, l, b.me, b.le, b.dtab);
     return hipGetLastError();

@@ -16,7 +16,7 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout3 {
     size_t hist, hist_scan, scan_part, ktmp, itmp, xt, yt, gt;
-    size_t key, ks, perm, xs, ys, zs, qs, leaf_start, me, le, dtab, nbad;
+    size_t key, ks, perm, xs, ys, zs, qs, leaf_start, me, le, dtab, dcube, kcube, nbad;
     size_t total;
 };
 
@@ -61,6 +61,10 @@ Layout3 layout3(const fmm3d_params* prm)
     ly.me = take(sizeof(double) * nbox * size_t(T));
     ly.le = take(sizeof(double) * nbox * size_t(T));
     ly.dtab = take(sizeof(double) * size_t(kOffsets3) * size_t(T2));
+    const size_t S = size_t(2 * prm->p + 1);
+    const bool lanes = prm->p >= 1 && prm->p <= kLaneMaxP3;
+    ly.dcube = take(lanes ? sizeof(double) * size_t(kOffsets3) * S * S * S : 0);
+    ly.kcube = take(lanes ? sizeof(int32_t) * size_t(T) : 0);
     ly.nbad = take(sizeof(unsigned long long));
     ly.total = off;
     return ly;
@@ -122,6 +126,8 @@ struct fmm3d_plan_s {
     Bufs3 buf;
     Geo3 geo;
     std::vector<double> dtab_host;   // source of the table upload, kept until the plan ends
+    std::vector<double> dcube_host;
+    std::vector<int32_t> kcube_host;
     int64_t last_n = 0;
 };
 
@@ -172,6 +178,8 @@ fmm_status fmm3d_plan(const fmm3d_params* prm, void* d_workspace, size_t bytes, 
     b.me = static_cast<double*>(at(ly.me));
     b.le = static_cast<double*>(at(ly.le));
     b.dtab = static_cast<double*>(at(ly.dtab));
+    b.dcube = static_cast<double*>(at(ly.dcube));
+    b.kcube = static_cast<int32_t*>(at(ly.kcube));
     b.nbad = static_cast<unsigned long long*>(at(ly.nbad));
     Geo3& g = pl->geo;
     g.x0 = prm->x0;
@@ -183,11 +191,39 @@ fmm_status fmm3d_plan(const fmm3d_params* prm, void* d_workspace, size_t bytes, 
     g.T = tet3(prm->p + 1);
     g.T2 = tet3(2 * prm->p + 1);
     hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool lanes = prm->p >= 1 && prm->p <= kLaneMaxP3;
     try {
         pl->dtab_host = derivative_table(prm->p);
+        if (lanes) {
+            // the graded rows rearranged as dense (2p+1)^3 cubes (entries of degree > 2p stay 0)
+            const int S = 2 * prm->p + 1, T2 = g.T2;
+            pl->dcube_host.assign(size_t(kOffsets3) * size_t(S * S * S), 0.0);
+            for (int o = 0; o < kOffsets3; ++o)
+                for (int d = 0; d <= 2 * prm->p; ++d)
+                    for (int s2 = 0; s2 <= d; ++s2)
+                        for (int c = 0; c <= s2; ++c) {
+                            const int a = d - s2, bb = s2 - c;
+                            pl->dcube_host[size_t(o) * size_t(S * S * S) + size_t((a * S + bb) * S + c)] =
+                                pl->dtab_host[size_t(o) * size_t(T2) + size_t(pos3(a, bb, c))];
+                        }
+            pl->kcube_host.assign(size_t(g.T), 0);
+            for (int d = 0; d <= prm->p; ++d)
+                for (int s2 = 0; s2 <= d; ++s2)
+                    for (int c = 0; c <= s2; ++c) {
+                        const int a = d - s2, bb = s2 - c;
+                        pl->kcube_host[size_t(pos3(a, bb, c))] = (a * S + bb) * S + c;
+                    }
+        }
     } catch (...) {
         delete pl;
         return FMM_E_NOMEM;
+    }
+    if (lanes && (hipMemcpyAsync(b.dcube, pl->dcube_host.data(), pl->dcube_host.size() * sizeof(double),
+                                 hipMemcpyHostToDevice, st) != hipSuccess ||
+                  hipMemcpyAsync(b.kcube, pl->kcube_host.data(), pl->kcube_host.size() * sizeof(int32_t),
+                                 hipMemcpyHostToDevice, st) != hipSuccess)) {
+        delete pl;
+        return FMM_E_DEVICE;
     }
     if (hipMemcpyAsync(b.dtab, pl->dtab_host.data(), pl->dtab_host.size() * sizeof(double), hipMemcpyHostToDevice,
                        st) != hipSuccess ||

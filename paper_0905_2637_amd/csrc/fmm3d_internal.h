@@ -27,6 +27,7 @@ constexpr int kT3Max = 220;        // terms of degree <= 9
 constexpr int kT3Max2 = 1330;      // terms of degree <= 18 (derivatives for the M2L)
 constexpr int kDepth3Max = 7;      // 21 key bits plus the outside flag
 constexpr int kOffsets3 = 343;     // offsets in [-3, 3]^3
+constexpr int kLaneMaxP3 = 6;      // degrees whose M2L takes one lane per target box
 
 __host__ __device__ constexpr int tet3(int d) { return d * (d + 1) * (d + 2) / 6; }
 __host__ __device__ constexpr int tri3(int s) { return s * (s + 1) / 2; }
@@ -51,6 +52,8 @@ struct Bufs3 {
     double* me;                 // [boxes of levels 0..L][T] scaled moments
     double* le;                 // [boxes of levels 0..L][T] scaled local coefficients
     double* dtab;               // [343][T2] derivatives of 1/r at the integer offsets, graded order
+    double* dcube;              // p <= kLaneMaxP3: [343][(2p+1)^3] the same derivatives as dense cubes
+    int32_t* kcube;             // p <= kLaneMaxP3: [T] cube index of each graded multi-index
     unsigned long long* nbad;   // particles outside the cube or NaN
 };
 
