@@ -28,6 +28,7 @@ namespace fmm3 {
 namespace {
 
 constexpr int kTpb = 256;
+constexpr int kEvalTpb = 64;
 
 __device__ inline uint32_t morton3(uint32_t a, uint32_t b, uint32_t c)
 {
@@ -61,21 +62,22 @@ __device__ inline void decode3(int t, int& a, int& b, int& c)
     a = d - s;
 }
 
-// u^a / a!
-__device__ inline double mono(double u, int a)
+// 1 / j! and 4^-j / j! for j <= kP3Max (the shift coefficients of M2M and L2L)
+__constant__ double kInvFact3[kP3Max + 1] = {1.0, 1.0, 1.0 / 2, 1.0 / 6, 1.0 / 24, 1.0 / 120, 1.0 / 720,
+                                             1.0 / 5040, 1.0 / 40320, 1.0 / 362880};
+__constant__ double kQuarterFact3[kP3Max + 1] = {1.0, 0.25, 1.0 / 32, 1.0 / 384, 1.0 / 6144, 1.0 / 122880,
+                                                 1.0 / 2949120, 1.0 / 82575360, 1.0 / 2642411520.0,
+                                                 1.0 / 95126814720.0};
+
+// u^a (a <= kP3Max)
+__device__ inline double ipow3(double u, int a)
 {
     double r = 1.0;
-    for (int i = 1; i <= a; ++i) r = r * u / double(i);
+    for (int i = 0; i < a; ++i) r *= u;
     return r;
 }
 
-// 4^-j / j!
-__device__ inline double quarter_f(int j)
-{
-    double r = 1.0;
-    for (int i = 1; i <= j; ++i) r = r * 0.25 / double(i);
-    return r;
-}
+__device__ inline double quarter_f(int j) { return kQuarterFact3[j]; }
 
 // ---- tree -------------------------------------------------------------------
 
@@ -147,10 +149,12 @@ k3_p2m(Geo3 g, const int32_t* __restrict__ ls, const double* __restrict__ xs, co
     const double cx = g.x0 + (la + 0.5) * w, cy = g.y0 + (lb + 0.5) * w, cz = g.z0 + (lc + 0.5) * w;
     int a, b, c;
     decode3(t, a, b, c);
+    const double inv_w = 1.0 / w;
     double acc = 0.0;
     for (int j = ls[leaf]; j < ls[leaf + 1]; ++j)
-        acc += qs[j] * mono((cx - xs[j]) / w, a) * mono((cy - ys[j]) / w, b) * mono((cz - zs[j]) / w, c);
-    me[(lvl_off3(g.L) + leaf) * g.T + t] = acc;
+        acc += qs[j] * ipow3((cx - xs[j]) * inv_w, a) * ipow3((cy - ys[j]) * inv_w, b) *
+               ipow3((cz - zs[j]) * inv_w, c);
+    me[(lvl_off3(g.L) + leaf) * g.T + t] = acc * (kInvFact3[a] * kInvFact3[b] * kInvFact3[c]);
 }
 
 // parents at level l from their eight children; one workgroup per parent
@@ -161,7 +165,7 @@ k3_m2m(Geo3 g, int l, double* __restrict__ me)
     const uint32_t par = blockIdx.x;
     const int t = int(threadIdx.x), T = g.T;
     const double* src = me + (lvl_off3(l + 1) + int64_t(8) * par) * T;
-    for (int e = t; e < 8 * T; e += kTpb) sm[e] = src[e];
+    for (int e = t; e < 8 * T; e += int(blockDim.x)) sm[e] = src[e];
     __syncthreads();
     if (t >= T) return;
     int a, b, c;
@@ -342,7 +346,7 @@ k3_l2l(Geo3 g, int l, double* __restrict__ le)
     const uint32_t box = blockIdx.x;
     const int t = int(threadIdx.x), T = g.T, p = g.p;
     const double* par = le + (lvl_off3(l - 1) + (box >> 3)) * T;
-    for (int e = t; e < T; e += kTpb) sL[e] = par[e];
+    for (int e = t; e < T; e += int(blockDim.x)) sL[e] = par[e];
     __syncthreads();
     if (t >= T) return;
     const int bx = box & 1, by = (box >> 1) & 1, bz = (box >> 2) & 1;
@@ -362,10 +366,10 @@ k3_l2l(Geo3 g, int l, double* __restrict__ le)
 
 // ---- evaluation: L2P and the near field -----------------------------------------
 
-// one workgroup per leaf; targets in chunks of 256, the sources of each of the
-// 27 near leaves staged in LDS in chunks of 256
+// one wavefront per leaf (leaves hold tens of particles); targets in chunks of
+// 64, the sources of each of the 27 near leaves staged in LDS in chunks of 64
 template <int P>
-__global__ void __launch_bounds__(kTpb)
+__global__ void __launch_bounds__(kEvalTpb)
 k3_eval(Geo3 g, int far, const int32_t* __restrict__ ls, const double* __restrict__ xs,
         const double* __restrict__ ys, const double* __restrict__ zs, const double* __restrict__ qs,
         const uint32_t* __restrict__ perm, const double* __restrict__ le, double* __restrict__ phi,
@@ -373,7 +377,7 @@ k3_eval(Geo3 g, int far, const int32_t* __restrict__ ls, const double* __restric
 {
     constexpr int T = tet3(P + 1);
     __shared__ double sL[T];
-    __shared__ double sx[kTpb], sy[kTpb], sz[kTpb], sq[kTpb];
+    __shared__ double sx[kEvalTpb], sy[kEvalTpb], sz[kEvalTpb], sq[kEvalTpb];
     const uint32_t leaf = blockIdx.x;
     const int t0 = ls[leaf], t1 = ls[leaf + 1];
     if (t0 == t1) return;
@@ -383,8 +387,8 @@ k3_eval(Geo3 g, int far, const int32_t* __restrict__ ls, const double* __restric
     const double w = ldexp(g.W, -g.L);
     const double cx = g.x0 + (la + 0.5) * w, cy = g.y0 + (lb + 0.5) * w, cz = g.z0 + (lc + 0.5) * w;
     if (far)
-        for (int e = int(threadIdx.x); e < T; e += kTpb) sL[e] = le[(lvl_off3(g.L) + leaf) * T + e];
-    for (int base = t0; base < t1; base += kTpb) {
+        for (int e = int(threadIdx.x); e < T; e += kEvalTpb) sL[e] = le[(lvl_off3(g.L) + leaf) * T + e];
+    for (int base = t0; base < t1; base += kEvalTpb) {
         const int i = base + int(threadIdx.x);
         const bool act = i < t1;
         const double xi = act ? xs[i] : 0.0, yi = act ? ys[i] : 0.0, zi = act ? zs[i] : 0.0;
@@ -396,9 +400,10 @@ k3_eval(Geo3 g, int far, const int32_t* __restrict__ ls, const double* __restric
             px[0] = py[0] = pz[0] = 1.0;
 #pragma unroll
             for (int k = 1; k <= P; ++k) {
-                px[k] = px[k - 1] * ux / double(k);
-                py[k] = py[k - 1] * uy / double(k);
-                pz[k] = pz[k - 1] * uz / double(k);
+                const double rk = 1.0 / double(k);     // a compile-time constant once unrolled
+                px[k] = px[k - 1] * ux * rk;
+                py[k] = py[k - 1] * uy * rk;
+                pz[k] = pz[k - 1] * uz * rk;
             }
 #pragma unroll
             for (int d = 0; d <= P; ++d)
@@ -426,7 +431,7 @@ k3_eval(Geo3 g, int far, const int32_t* __restrict__ ls, const double* __restric
                     if (na < 0 || nb < 0 || nc < 0 || na >= side || nb >= side || nc >= side) continue;
                     const uint32_t nl = morton3(uint32_t(na), uint32_t(nb), uint32_t(nc));
                     const int s0 = ls[nl], s1 = ls[nl + 1];
-                    for (int cb = s0; cb < s1; cb += kTpb) {
+                    for (int cb = s0; cb < s1; cb += kEvalTpb) {
                         __syncthreads();
                         const int j = cb + int(threadIdx.x);
                         if (j < s1) {
@@ -436,7 +441,7 @@ k3_eval(Geo3 g, int far, const int32_t* __restrict__ ls, const double* __restric
                             sq[threadIdx.x] = qs[j];
                         }
                         __syncthreads();
-                        const int cnt = min(kTpb, s1 - cb);
+                        const int cnt = min(kEvalTpb, s1 - cb);
                         if (act)
                             for (int jj = 0; jj < cnt; ++jj) {
                                 const double ddx = xi - sx[jj], ddy = yi - sy[jj], ddz = zi - sz[jj];
@@ -485,12 +490,16 @@ hipError_t launch3_tree(const Bufs3& b, const Geo3& g, int n, const double* x, c
     return hipGetLastError();
 }
 
+// the coefficient kernels take one thread per term: T rounded up to wavefronts
+static unsigned coef_threads(const Geo3& g) { return unsigned((g.T + 63) / 64 * 64); }
+
 hipError_t launch3_upward(const Bufs3& b, const Geo3& g, hipStream_t st)
 {
     const unsigned nleaf = 1u << (3 * g.L);
-    hipLaunchKernelGGL(k3_p2m, dim3(nleaf), dim3(kTpb), 0, st, g, b.leaf_start, b.xs, b.ys, b.zs, b.qs, b.me);
+    hipLaunchKernelGGL(k3_p2m, dim3(nleaf), dim3(coef_threads(g)), 0, st, g, b.leaf_start, b.xs, b.ys, b.zs, b.qs,
+                       b.me);
     for (int l = g.L - 1; l >= 2; --l)
-        hipLaunchKernelGGL(k3_m2m, dim3(1u << (3 * l)), dim3(kTpb), 0, st, g, l, b.me);
+        hipLaunchKernelGGL(k3_m2m, dim3(1u << (3 * l)), dim3(coef_threads(g)), 0, st, g, l, b.me);
     return hipGetLastError();
 }
 
@@ -532,7 +541,7 @@ hipError_t launch3_m2l(const Bufs3& b, const Geo3& g, hipStream_t st)
 hipError_t launch3_l2l(const Bufs3& b, const Geo3& g, hipStream_t st)
 {
     for (int l = 3; l <= g.L; ++l)
-        hipLaunchKernelGGL(k3_l2l, dim3(1u << (3 * l)), dim3(kTpb), 0, st, g, l, b.le);
+        hipLaunchKernelGGL(k3_l2l, dim3(1u << (3 * l)), dim3(coef_threads(g)), 0, st, g, l, b.le);
     return hipGetLastError();
 }
 
@@ -541,7 +550,7 @@ template <int P>
 void eval_p(const Bufs3& b, const Geo3& g, hipStream_t st, double* phi, double* gx, double* gy, double* gz)
 {
     const unsigned nleaf = 1u << (3 * g.L);
-    hipLaunchKernelGGL((k3_eval<P>), dim3(nleaf), dim3(kTpb), 0, st, g, g.L >= 2 ? 1 : 0, b.leaf_start, b.xs,
+    hipLaunchKernelGGL((k3_eval<P>), dim3(nleaf), dim3(kEvalTpb), 0, st, g, g.L >= 2 ? 1 : 0, b.leaf_start, b.xs,
                        b.ys, b.zs, b.qs, b.perm, b.le, phi, gx, gy, gz);
 }
 }  // namespace
