@@ -228,7 +228,7 @@ k3_m2l(Geo3 g, int l, const double* __restrict__ me, double* __restrict__ le, co
     if (t < T) le[(lvl_off3(l) + box) * T + t] = acc;
 }
 
-// M2L for p <= kLaneMaxP3, all levels in one launch.  One lane per target box:
+// M2L for 1 <= p <= kLaneMaxP3 (8), all levels in one launch.  One lane per target box:
 // a workgroup takes the 64 boxes of one parity class (child position in the
 // parent) under a 4 x 4 x 4 block of parents, so all its lanes walk the same
 // 189 offsets, and each wavefront computes a quarter of the output terms.
@@ -524,14 +524,21 @@ void m2l_lanes(const Bufs3& b, const Geo3& g, hipStream_t st)
 
 hipError_t launch3_m2l(const Bufs3& b, const Geo3& g, hipStream_t st)
 {
-    switch (g.p) {
-        case 1: m2l_lanes<1>(b, g, st); return hipGetLastError();
-        case 2: m2l_lanes<2>(b, g, st); return hipGetLastError();
-        case 3: m2l_lanes<3>(b, g, st); return hipGetLastError();
-        case 4: m2l_lanes<4>(b, g, st); return hipGetLastError();
-        case 5: m2l_lanes<5>(b, g, st); return hipGetLastError();
-        case 6: m2l_lanes<6>(b, g, st); return hipGetLastError();
-        default: break;
+    // the lane kernel reads the derivative cubes, which the plan holds only
+    // for 1 <= p <= kLaneMaxP3
+    static_assert(kLaneMaxP3 <= 8, "lane M2L instantiated for p <= 8 only");
+    if (g.p >= 1 && g.p <= kLaneMaxP3) {
+        switch (g.p) {
+            case 1: m2l_lanes<1>(b, g, st); return hipGetLastError();
+            case 2: m2l_lanes<2>(b, g, st); return hipGetLastError();
+            case 3: m2l_lanes<3>(b, g, st); return hipGetLastError();
+            case 4: m2l_lanes<4>(b, g, st); return hipGetLastError();
+            case 5: m2l_lanes<5>(b, g, st); return hipGetLastError();
+            case 6: m2l_lanes<6>(b, g, st); return hipGetLastError();
+            case 7: m2l_lanes<7>(b, g, st); return hipGetLastError();
+            case 8: m2l_lanes<8>(b, g, st); return hipGetLastError();
+            default: break;
+        }
     }
     for (int l = 2; l <= g.L; ++l)
         hipLaunchKernelGGL(k3_m2l, dim3(1u << (3 * l)), dim3(kTpb), 0, st, g, l, b.me, b.le, b.dtab);
