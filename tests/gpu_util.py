@@ -35,11 +35,13 @@ def gpu_coeffs_to_oracle(coef: np.ndarray, L: int, W: float, kind: str) -> np.nd
     """Scaled z-order coefficients [Lambda, p] -> unscaled row-major [Lambda, p].
 
     Multipole: a_k = ahat_k w^k; local: b_l = bhat_l / w^(l+1); w = W / 2^l.
+    Levels 0 and 1 carry no expansions (nothing is far from anything there):
+    the library leaves those rows of its workspace unwritten, so they stay 0.
     """
     p = coef.shape[1]
     out = np.zeros_like(coef)
     k = np.arange(p)
-    for l in range(L + 1):
+    for l in range(2, L + 1):
         side = 1 << l
         off = level_offset(l)
         m = np.arange(side * side)
