@@ -261,25 +261,24 @@ __device__ __forceinline__ void m2l_lanes_fma(double (&acc)[(tet3(P + 1) + 3) / 
                                               const double* __restrict__ src, bool vs, const int* __restrict__ sK)
 {
     constexpr int T = tet3(P + 1), Q = (T + 3) / 4, N0 = W * Q, N1 = N0 + Q < T ? N0 + Q : T;
+    // two source terms per step, the step loop kept rolled: unrolled, the
+    // scheduler hoists the LDS reads of many terms and spills
 #pragma unroll 1
-    for (int k0 = 0; k0 < T; k0 += 4) {
-        double m[4];
-        int ik[4];
+    for (int k0 = 0; k0 < T; k0 += 2) {
+        double m[2];
+        int ik[2];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < 2; ++j) {
             const int k = k0 + j;
             const bool in = k < T;
             m[j] = (vs && in) ? src[k] : 0.0;
             ik[j] = in ? sK[k] : 0;
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < 2; ++j) {
             const double* d = sD + ik[j];
 #pragma unroll
             for (int n = N0; n < N1; ++n) acc[n - N0] = fma(d[cube_of<P>(n)], m[j], acc[n - N0]);
-            // one source term at a time: keeps the scheduler from hoisting the
-            // LDS reads of all four terms (which spills)
-            __builtin_amdgcn_sched_barrier(0);
         }
     }
 }
