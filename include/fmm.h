@@ -370,6 +370,16 @@ fmm_status fmm3d_evaluate(fmm3d_plan_t plan, int64_t n, const double* d_x, const
  * outside the cube: FMM_E_DOMAIN if there were any. */
 fmm_status fmm3d_get_status(fmm3d_plan_t plan, void* stream, int64_t* n_outside);
 
+/* Parity inspection of the last evaluation's tree (waits for the device):
+ *   FMM_DUMP_KEYS        uint32 [n]        3D Morton leaf key per input particle
+ *                        (2^(3 depth) for one outside the cube)
+ *   FMM_DUMP_PERM        uint32 [n]        sorted position -> input index (stable)
+ *   FMM_DUMP_LEAF_START  int32 [8^depth+1] first sorted position of every leaf;
+ *                        the last entry counts the particles inside the cube
+ * Other kinds: FMM_E_ARG.  If bytes is too small, *needed is set and
+ * FMM_E_CAPACITY returned. */
+fmm_status fmm3d_debug_dump(fmm3d_plan_t plan, int32_t what, void* host_buf, size_t bytes, size_t* needed);
+
 /* Release the host handle (never the workspace).  NULL is accepted. */
 fmm_status fmm3d_destroy(fmm3d_plan_t plan);
 

@@ -36,7 +36,7 @@ EXPORTED = ["fmm_workspace_size", "fmm_plan", "fmm_evaluate", "fmm_evaluate_at",
             "fmm_plan_batch", "fmm_evaluate_batch", "fmm_advance_rk2", "fmm_get_status", "fmm_set_timing", "fmm_stats", "fmm_stage_name",
             "fmm_get_tuning", "fmm_set_tuning", "fmm_autotune", "fmm_work_estimate", "fmm_debug_dump", "fmm_destroy",
             "fmm_status_string", "fmm3d_workspace_size", "fmm3d_plan", "fmm3d_evaluate", "fmm3d_get_status",
-            "fmm3d_destroy"]
+            "fmm3d_debug_dump", "fmm3d_destroy"]
 
 
 class Fmm3dParams(C.Structure):
@@ -97,6 +97,7 @@ def load():
     lib.fmm3d_evaluate.argtypes = [vp, C.c_int64] + [vp] * 9
     lib.fmm3d_get_status.argtypes = [vp, vp, C.POINTER(C.c_int64)]
     lib.fmm3d_destroy.argtypes = [vp]
+    lib.fmm3d_debug_dump.argtypes = [vp, C.c_int32, vp, C.c_size_t, C.POINTER(C.c_size_t)]
     for name in EXPORTED:
         if name in ("fmm_stage_name", "fmm_status_string"):
             continue
@@ -475,6 +476,19 @@ class Plan3D:
         if check and self.out_of_domain():
             raise FmmError(FMM_E_DOMAIN, "fmm3d_evaluate")
         return out
+
+    def dump(self, what: int) -> np.ndarray:
+        """Keys, permutation or leaf ranges of the last evaluation (DUMP_KEYS,
+        DUMP_PERM, DUMP_LEAF_START)."""
+        lib = load()
+        need = C.c_size_t(0)
+        lib.fmm3d_debug_dump(self._h, what, None, 0, C.byref(need))
+        dtype = np.int32 if what == DUMP_LEAF_START else np.uint32
+        arr = np.zeros(max(1, need.value // 4), dtype=dtype)
+        s = lib.fmm3d_debug_dump(self._h, what, C.c_void_p(arr.ctypes.data), C.c_size_t(arr.nbytes), C.byref(need))
+        if s != FMM_OK:
+            raise FmmError(s, "fmm3d_debug_dump")
+        return arr[: need.value // 4]
 
     def out_of_domain(self) -> int:
         v = C.c_int64(0)

@@ -272,6 +272,28 @@ fmm_status fmm3d_get_status(fmm3d_plan_t plan, void* stream, int64_t* n_outside)
     return v == 0 ? FMM_OK : FMM_E_DOMAIN;
 }
 
+fmm_status fmm3d_debug_dump(fmm3d_plan_t plan, int32_t what, void* host_buf, size_t bytes, size_t* needed)
+{
+    if (!plan || !needed) return FMM_E_ARG;
+    const size_t n = size_t(plan->last_n > 0 ? plan->last_n : 0);
+    const void* src = nullptr;
+    size_t sz = 0;
+    switch (what) {
+        case FMM_DUMP_KEYS: src = plan->buf.key; sz = n * sizeof(uint32_t); break;
+        case FMM_DUMP_PERM: src = plan->buf.perm; sz = n * sizeof(uint32_t); break;
+        case FMM_DUMP_LEAF_START:
+            src = plan->buf.leaf_start;
+            sz = n > 0 ? ((size_t(1) << (3 * plan->geo.L)) + 1) * sizeof(int32_t) : 0;
+            break;
+        default: return FMM_E_ARG;
+    }
+    *needed = sz;
+    if (!host_buf || bytes < sz) return FMM_E_CAPACITY;
+    if (sz == 0) return FMM_OK;
+    if (hipDeviceSynchronize() != hipSuccess) return FMM_E_DEVICE;
+    return hipMemcpy(host_buf, src, sz, hipMemcpyDeviceToHost) == hipSuccess ? FMM_OK : FMM_E_DEVICE;
+}
+
 fmm_status fmm3d_destroy(fmm3d_plan_t plan)
 {
     delete plan;

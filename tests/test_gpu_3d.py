@@ -1,6 +1,8 @@
 """The 3D form on the GPU (octree, Laplace kernel 1/r, Cartesian Taylor
 expansions): parity with the oracle's 3D FMM, through the C ABI.
 
+* the tree bit for bit: Morton keys, the stable permutation and the leaf
+  ranges against the oracle's keys and stable order;
 * FP64 potential and gradient within 1e-12 relative L2 of the oracle FMM
   (same tree, lists, degree), for degrees 0-9, depths 0-4, uniform and
   clustered particles, a cube that is not the unit cube;
@@ -156,3 +158,29 @@ def test_million_particles_sampled():
     eg, ep = _rel(tuple(a[t] for a in g), d)
     assert eg < 1e-3 and ep < 1e-3, (eg, ep)
     assert np.all(np.isfinite(g[0]))
+
+
+@pytest.mark.parametrize("L,clustered", [(3, False), (5, True), (0, False)])
+def test_tree_bit_exact(L, clustered):
+    import torch
+    import paper_0905_2637_amd as fm
+    rng = np.random.default_rng(70 + L)
+    n = 20000
+    if clustered:
+        x, y, z = (np.clip(0.4 + 0.01 * rng.standard_normal(n), 0.0, 0.999) for _ in range(3))
+    else:
+        x, y, z = rng.random(n), rng.random(n), rng.random(n)
+    x[5], y[77] = 1.0, np.nan                 # outside: keys 2^(3L), sorted last in input order
+    q = rng.uniform(-1, 1, n)
+    plan = fm.Plan3D(n, 4, L)
+    plan.evaluate(_dev(x), _dev(y), _dev(z), _dev(q))
+    torch.cuda.synchronize()
+    keys, perm, ls = plan.dump(fm.DUMP_KEYS), plan.dump(fm.DUMP_PERM), plan.dump(fm.DUMP_LEAF_START)
+    assert plan.out_of_domain() == 2
+    plan.close()
+    ko, po = oracle.leaf_keys3(x, y, z, L)
+    assert np.array_equal(keys, ko)
+    assert np.array_equal(perm, po)
+    expect = np.searchsorted(ko[po].astype(np.int64), np.arange((1 << (3 * L)) + 1), side="left")
+    assert np.array_equal(ls, expect.astype(np.int32))
+    assert ls[-1] == n - 2
