@@ -228,7 +228,7 @@ k3_m2l(Geo3 g, int l, const double* __restrict__ me, double* __restrict__ le, co
     if (t < T) le[(lvl_off3(l) + box) * T + t] = acc;
 }
 
-// M2L for 1 <= p <= kLaneMaxP3 (8), all levels in one launch.  One lane per target box:
+// M2L for 1 <= p <= kLaneMaxP3 (9), all levels in one launch.  One lane per target box:
 // a workgroup takes the 64 boxes of one parity class (child position in the
 // parent) under a 4 x 4 x 4 block of parents, so all its lanes walk the same
 // 189 offsets, and each wavefront computes a quarter of the output terms.
@@ -237,6 +237,13 @@ k3_m2l(Geo3 g, int l, const double* __restrict__ me, double* __restrict__ le, co
 // cube the entry of k + n sits at cube(k) + cube(n): cube(n) is a
 // compile-time constant of the unrolled output loop, cube(k) one LDS read per
 // source term.
+// wavefronts per workgroup (each takes 1/waves of the output terms): eight
+// from p = 7 on keeps the accumulators of a lane within about 60 registers
+template <int P>
+__host__ __device__ constexpr int lane_waves() { return P >= 7 ? 8 : 4; }
+template <int P>
+__host__ __device__ constexpr int lane_terms() { return (tet3(P + 1) + lane_waves<P>() - 1) / lane_waves<P>(); }
+
 template <int P>
 __host__ __device__ constexpr int cube_of(int t)
 {
@@ -257,10 +264,10 @@ struct LaneLevels {
 // FMA block of one wavefront for one interaction offset: outputs
 // [W Q, W Q + Q) of its lane's target, all terms of the lane's source
 template <int P, int W>
-__device__ __forceinline__ void m2l_lanes_fma(double (&acc)[(tet3(P + 1) + 3) / 4], const double* __restrict__ sD,
+__device__ __forceinline__ void m2l_lanes_fma(double (&acc)[lane_terms<P>()], const double* __restrict__ sD,
                                               const double* __restrict__ src, bool vs, const int* __restrict__ sK)
 {
-    constexpr int T = tet3(P + 1), Q = (T + 3) / 4, N0 = W * Q, N1 = N0 + Q < T ? N0 + Q : T;
+    constexpr int T = tet3(P + 1), Q = lane_terms<P>(), N0 = W * Q, N1 = N0 + Q < T ? N0 + Q : T;
     // two source terms per step, the step loop kept rolled: unrolled, the
     // scheduler hoists the LDS reads of many terms and spills
 #pragma unroll 1
@@ -284,11 +291,11 @@ __device__ __forceinline__ void m2l_lanes_fma(double (&acc)[(tet3(P + 1) + 3) / 
 }
 
 template <int P>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64 * lane_waves<P>())
 k3_m2l_lanes(Geo3 g, LaneLevels lv, const double* __restrict__ me, double* __restrict__ le,
              const double* __restrict__ dcube, const int* __restrict__ kcube)
 {
-    constexpr int T = tet3(P + 1), Q = (T + 3) / 4;
+    constexpr int T = tet3(P + 1), Q = lane_terms<P>(), NT = 64 * lane_waves<P>();
     constexpr int S = 2 * P + 1, S3 = S * S * S;
     __shared__ double sD[S3];
     __shared__ int sK[T];
@@ -306,7 +313,7 @@ k3_m2l_lanes(Geo3 g, LaneLevels lv, const double* __restrict__ me, double* __res
     const bool vt = px < h && py < h && pz < h;
     const int ta = 2 * px + cx, tb = 2 * py + cy, tc = 2 * pz + cz;
     const double* me_l = me + lvl_off3(l) * T;
-    for (int e = int(threadIdx.x); e < T; e += 256) sK[e] = kcube[e];
+    for (int e = int(threadIdx.x); e < T; e += NT) sK[e] = kcube[e];
     double acc[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) acc[i] = 0.0;
@@ -316,7 +323,7 @@ k3_m2l_lanes(Geo3 g, LaneLevels lv, const double* __restrict__ me, double* __res
                 if (abs(ox) <= 1 && abs(oy) <= 1 && abs(oz) <= 1) continue;
                 const double* drow = dcube + int64_t(off3_index(ox, oy, oz)) * S3;
                 __syncthreads();
-                for (int e = int(threadIdx.x); e < S3; e += 256) sD[e] = drow[e];
+                for (int e = int(threadIdx.x); e < S3; e += NT) sD[e] = drow[e];
                 __syncthreads();
                 const int sa = ta - ox, sb = tb - oy, sc = tc - oz;
                 const bool vs = vt && sa >= 0 && sb >= 0 && sc >= 0 && sa < side && sb < side && sc < side;
@@ -325,7 +332,11 @@ k3_m2l_lanes(Geo3 g, LaneLevels lv, const double* __restrict__ me, double* __res
                     case 0: m2l_lanes_fma<P, 0>(acc, sD, src, vs, sK); break;
                     case 1: m2l_lanes_fma<P, 1>(acc, sD, src, vs, sK); break;
                     case 2: m2l_lanes_fma<P, 2>(acc, sD, src, vs, sK); break;
-                    default: m2l_lanes_fma<P, 3>(acc, sD, src, vs, sK); break;
+                    case 3: m2l_lanes_fma<P, 3>(acc, sD, src, vs, sK); break;
+                    case 4: if constexpr (lane_waves<P>() > 4) m2l_lanes_fma<P, 4>(acc, sD, src, vs, sK); break;
+                    case 5: if constexpr (lane_waves<P>() > 4) m2l_lanes_fma<P, 5>(acc, sD, src, vs, sK); break;
+                    case 6: if constexpr (lane_waves<P>() > 4) m2l_lanes_fma<P, 6>(acc, sD, src, vs, sK); break;
+                    default: if constexpr (lane_waves<P>() > 4) m2l_lanes_fma<P, 7>(acc, sD, src, vs, sK); break;
                 }
             }
     if (vt) {
@@ -516,7 +527,7 @@ void m2l_lanes(const Bufs3& b, const Geo3& g, hipStream_t st)
         total += nb * nb * nb;
     }
     lv.blk_begin[g.L - 1] = total;
-    hipLaunchKernelGGL((k3_m2l_lanes<P>), dim3(unsigned(total), 8u), dim3(256), 0, st, g, lv, b.me, b.le, b.dcube,
+    hipLaunchKernelGGL((k3_m2l_lanes<P>), dim3(unsigned(total), 8u), dim3(64 * lane_waves<P>()), 0, st, g, lv, b.me, b.le, b.dcube,
                        b.kcube);
 }
 }  // namespace
@@ -525,7 +536,7 @@ hipError_t launch3_m2l(const Bufs3& b, const Geo3& g, hipStream_t st)
 {
     // the lane kernel reads the derivative cubes, which the plan holds only
     // for 1 <= p <= kLaneMaxP3
-    static_assert(kLaneMaxP3 <= 8, "lane M2L instantiated for p <= 8 only");
+    static_assert(kLaneMaxP3 <= 9, "lane M2L instantiated for p <= 9 only");
     if (g.p >= 1 && g.p <= kLaneMaxP3) {
         switch (g.p) {
             case 1: m2l_lanes<1>(b, g, st); return hipGetLastError();
@@ -536,6 +547,7 @@ hipError_t launch3_m2l(const Bufs3& b, const Geo3& g, hipStream_t st)
             case 6: m2l_lanes<6>(b, g, st); return hipGetLastError();
             case 7: m2l_lanes<7>(b, g, st); return hipGetLastError();
             case 8: m2l_lanes<8>(b, g, st); return hipGetLastError();
+            case 9: m2l_lanes<9>(b, g, st); return hipGetLastError();
             default: break;
         }
     }

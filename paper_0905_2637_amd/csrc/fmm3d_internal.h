@@ -27,7 +27,7 @@ constexpr int kT3Max = 220;        // terms of degree <= 9
 constexpr int kT3Max2 = 1330;      // terms of degree <= 18 (derivatives for the M2L)
 constexpr int kDepth3Max = 7;      // 21 key bits plus the outside flag
 constexpr int kOffsets3 = 343;     // offsets in [-3, 3]^3
-constexpr int kLaneMaxP3 = 8;      // degrees whose M2L takes one lane per target box (1 .. this);
+constexpr int kLaneMaxP3 = 9;      // degrees whose M2L takes one lane per target box (1 .. this);
                                    // the derivative cubes are allocated and the lane kernel
                                    // dispatched for exactly these
 
