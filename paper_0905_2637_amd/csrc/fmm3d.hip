@@ -453,6 +453,7 @@ k3_eval(Geo3 g, int far, const int32_t* __restrict__ ls, const double* __restric
                         __syncthreads();
                         const int cnt = min(kEvalTpb, s1 - cb);
                         if (act)
+#pragma unroll 4
                             for (int jj = 0; jj < cnt; ++jj) {
                                 const double ddx = xi - sx[jj], ddy = yi - sy[jj], ddz = zi - sz[jj];
                                 const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
