@@ -90,3 +90,16 @@ def test_no_cpu_path_without_device():
         pytest.skip("a device is present")
     with pytest.raises(RuntimeError):
         fm.Plan3D(100, 4, 2)
+
+
+@pytest.mark.parametrize("p", range(1, 10))
+def test_workspace_holds_the_derivative_cubes_of_the_lane_m2l(lib, p):
+    """The lane M2L (every p from 1 to 9) reads the derivative cubes
+    343 x (2p+1)^3 from the workspace: it must hold them on top of the
+    moments, locals and graded derivative table."""
+    L = 3
+    nbox = (8 ** (L + 1) - 1) // 7
+    T, T2, S = (p + 1) * (p + 2) * (p + 3) // 6, (2 * p + 1) * (2 * p + 2) * (2 * p + 3) // 6, 2 * p + 1
+    s, size = _ws(lib, p=p, depth=L, n_max=1)
+    assert s == fm.FMM_OK
+    assert size >= 8 * (2 * nbox * T + 343 * T2 + 343 * S ** 3)
