@@ -48,10 +48,10 @@ def test_workspace_grows_with_depth_p_and_n(lib):
     s, base = _ws(lib)
     assert s == fm.FMM_OK and base > 0
     assert _ws(lib, depth=4)[1] > base
-    # within each M2L form, more terms need more room (p <= 8 also holds the
-    # derivatives as dense (2p+1)^3 cubes, p = 9 does not)
-    assert _ws(lib, p=5)[1] < base < _ws(lib, p=8)[1]
-    assert _ws(lib, p=9)[1] < _ws(lib, p=8)[1]
+    # more terms need more room (p >= 1 also holds the derivatives as dense
+    # (2p+1)^3 cubes for the lane M2L)
+    assert _ws(lib, p=5)[1] < base < _ws(lib, p=8)[1] < _ws(lib, p=9)[1]
+    assert _ws(lib, p=0)[1] < _ws(lib, p=1)[1]
     assert _ws(lib, n_max=100000)[1] > base
     # coefficient storage dominates at depth 7, p = 9: 2 * (8^8 - 1) / 7 boxes * 220 terms * 8 B
     s, big = _ws(lib, depth=7, p=9, n_max=1 << 24)
