@@ -18,13 +18,15 @@
  * A plan may choose another kernel (fmm_params.kernel, Sections 6.1 and 8):
  * the singular kernel of eq. 7 in the near field, Lennard-Jones forces (near
  * field only), or the discrete Gauss transform by the fast Gauss transform.
+ * The fmm3d_* entry points at the end carry the method to three dimensions
+ * (Section 8): a uniform octree with the Laplace kernel 1/r.
  *
  * Conventions shared by every entry point:
  *   - Every function returns an fmm_status; no C++ exception crosses the ABI.
  *   - "Device pointer" means memory on the current HIP device (hipMalloc or a
  *     PyTorch CUDA/HIP tensor).  The library never frees caller memory.
  *   - "stream" is a hipStream_t passed as void* (NULL = the default stream).
- *     fmm_evaluate, fmm_evaluate_at and fmm_evaluate_batch only enqueue work on
+ *     fmm_evaluate, fmm_evaluate_at, fmm_evaluate_batch and fmm3d_evaluate only enqueue work on
  *     it (the batched form as one graph launch): they never
  *     synchronise, never allocate device memory and never read device data
  *     back to the host.
