@@ -167,21 +167,39 @@ k3_m2m(Geo3 g, int l, double* __restrict__ me)
     const double* src = me + (lvl_off3(l + 1) + int64_t(8) * par) * T;
     for (int e = t; e < 8 * T; e += int(blockDim.x)) sm[e] = src[e];
     __syncthreads();
+    // A child's sign in the shift depends only on the parities of k - m: for
+    // every term m replace the eight children's moments by their signed sums
+    // H_pi(m) = sum_ch (-1)^popcount(ch & pi) Ms_m(ch) (a Walsh-Hadamard
+    // transform over the children, one column per thread), so that each
+    // output sums over m once instead of eight times.
+    for (int m = t; m < T; m += int(blockDim.x)) {
+        double v[8];
+#pragma unroll
+        for (int ch = 0; ch < 8; ++ch) v[ch] = sm[ch * T + m];
+#pragma unroll
+        for (int h = 1; h < 8; h <<= 1)
+#pragma unroll
+            for (int ch = 0; ch < 8; ++ch)
+                if (!(ch & h)) {
+                    const double u = v[ch], w = v[ch | h];
+                    v[ch] = u + w;
+                    v[ch | h] = u - w;
+                }
+#pragma unroll
+        for (int pi = 0; pi < 8; ++pi) sm[pi * T + m] = v[pi];
+    }
+    __syncthreads();
     if (t >= T) return;
     int a, b, c;
     decode3(t, a, b, c);
     double acc = 0.0;
-    for (int ch = 0; ch < 8; ++ch) {
-        const int bx = ch & 1, by = (ch >> 1) & 1, bz = ch >> 2;
-        for (int i = 0; i <= a; ++i)
-            for (int j = 0; j <= b; ++j)
-                for (int k = 0; k <= c; ++k) {
-                    const bool neg = ((bx & (a - i)) ^ (by & (b - j)) ^ (bz & (c - k))) & 1;
-                    const double coef = ldexp(1.0, -(i + j + k)) * quarter_f(a - i) * quarter_f(b - j) * quarter_f(c - k);
-                    const double v = sm[ch * T + pos3(i, j, k)] * coef;
-                    acc += neg ? -v : v;
-                }
-    }
+    for (int i = 0; i <= a; ++i)
+        for (int j = 0; j <= b; ++j)
+            for (int k = 0; k <= c; ++k) {
+                const int pi = ((a - i) & 1) | (((b - j) & 1) << 1) | (((c - k) & 1) << 2);
+                const double coef = ldexp(1.0, -(i + j + k)) * quarter_f(a - i) * quarter_f(b - j) * quarter_f(c - k);
+                acc += sm[pi * T + pos3(i, j, k)] * coef;
+            }
     me[(lvl_off3(l) + par) * T + t] = acc;
 }
 
