@@ -1,12 +1,14 @@
 #!/usr/bin/env python3
 """Throughput of one full FMM evaluation on one MI355X.
 
-Default workload (the configuration the headline metric is quoted on): the
-1,048,576-particle jittered Lamb-Oseen lattice, sigma = 0.002, depth 8,
-p = 17, every stage in FP64.  A "step" is one complete evaluation -- tree
-build (z-order keys, radix sort, leaf ranges), P2M, M2M, M2L, L2L, L2P and
-P2P -- with inputs already resident in HBM.  ``--config C4`` runs the
-batched form instead: 512 uneven instances, one graph replay per step.
+Default workload (the configuration the headline metric is quoted on, the
+paper's largest run: one evaluation of 64 million particles, Section 7.2):
+2^26 particles uniform in the unit square, gamma ~ U(-1, 1), sigma = 2e-4,
+depth 11, p = 20, every stage in FP64.  A "step" is one complete evaluation
+-- tree build (z-order keys, radix sort, leaf ranges), P2M, M2M, M2L, L2L,
+L2P and P2P -- with inputs already resident in HBM.  ``--config`` picks
+another workload (C1, C2, C3, C5; C4 runs the batched form: 512 uneven
+instances, one graph replay per step) and ``--precision`` its precision.
 
 Prints ONE JSON line.  ``value`` is particles per second over the timed
 steps (wall clock, bracketed by device synchronisation).  ``roofline``
@@ -14,13 +16,15 @@ describes the kernel of the stage with the largest GPU time; its duration
 is measured with HIP events that the library records on the evaluation's
 own stream during the timed steps (for the batched form: during extra,
 eagerly enqueued timed evaluations, since a replayed graph carries no
-events).  ``forms`` (default workload only) times the mixed-precision form
-of the same workload, the batched form against plain FP64 single
-evaluations of the same instances, and the vortex-method time stepping
-(explicit midpoint steps, graph-replayed).  ``cpu_baseline`` times the FP64 CPU
-oracle on the host cores (rank 0, N = 1 only) and, from the same leg,
-reports the GPU result's parity with the oracle and its accuracy against
-the direct sums.
+events).  ``forms`` (default workload) times the mixed-precision form of
+the same workload, the 2^20-particle Lamb-Oseen workload in FP64, and the
+batched form against plain FP64 single evaluations of the same instances;
+``--extra-forms`` adds the vortex-method time stepping, the singular
+kernel, target points, Lennard-Jones forces, the fast Gauss transform and
+the 3D form.  ``cpu_baseline`` times the FP64 CPU oracle on the host cores
+(rank 0, N = 1 only) and, from the same leg, reports the GPU results'
+parity with the oracle and their accuracy against the direct sums on a
+seeded sample of targets.
 """
 from __future__ import annotations
 
@@ -168,19 +172,20 @@ def run_single(wl, args, dev, kernel="gaussian"):
     plan = fm.Plan(wl.n, wl.sigma, wl.p, wl.depth, domain=(wl.x0, wl.y0, wl.width),
                    precision=wl.precision, fp32_fine_levels=wl.fp32_fine_levels, kernel=kernel)
     for _ in range(args.warmup):
-        plan.evaluate(x, y, g, u, v)
+        plan.evaluate(x, y, g, u, v, check=False)
     torch.cuda.synchronize()
     if plan.out_of_domain():
         raise SystemExit("particles outside the domain")
     plan.set_timing(True)
-    sec = timed(lambda: plan.evaluate(x, y, g, u, v), args.steps, 0)
+    sec = timed(lambda: plan.evaluate(x, y, g, u, v, check=False), args.steps, 0)
     stages = plan.stats()
     plan.set_timing(False)
     stage_ms = {k: vv for k, vv in stages.items() if k != "evaluations"}
     leaf_start = plan.dump(fm.DUMP_LEAF_START)
     pn, pm = near_pairs(leaf_start, wl.depth), m2l_pairs(wl.depth)
     res = {"sec": sec, "stage_ms": stage_ms, "near_pairs": pn, "m2l_pairs": pm,
-           "roofline": roofline_of(stage_ms, pn, pm, wl.p, "f64" if wl.precision == "fp64" else "f32", wl.name),
+           "roofline": roofline_of(stage_ms, pn, pm, wl.p, "f64" if wl.precision == "fp64" else "f32",
+                                   f"{wl.name}_{wl.precision}"),
            "u": u, "v": v, "tuning": plan.tuning()}
     plan.close()
     return res
@@ -207,15 +212,15 @@ def run_batch(wl, args, dev, precision=None, autotune=True, work_order=1):
         t = bp.tuning()
         t["work_order"] = work_order
         bp.set_tuning(**t)
-    bp.evaluate(x, y, g, u, v)
+    bp.evaluate(x, y, g, u, v, check=False)
     torch.cuda.synchronize()
     if bp.out_of_domain():
         raise SystemExit("particles outside the domain")
-    sec = timed(lambda: bp.evaluate(x, y, g, u, v), args.steps, args.warmup)
+    sec = timed(lambda: bp.evaluate(x, y, g, u, v, check=False), args.steps, args.warmup)
     # stage breakdown from eagerly enqueued timed evaluations (same kernels)
     bp.set_timing(True)
     for _ in range(max(3, min(args.steps, 10))):
-        bp.evaluate(x, y, g, u, v)
+        bp.evaluate(x, y, g, u, v, check=False)
     torch.cuda.synchronize()
     stages = bp.stats()
     bp.set_timing(False)
@@ -228,7 +233,8 @@ def run_batch(wl, args, dev, precision=None, autotune=True, work_order=1):
         pm += m2l_pairs(L)
         seg += 4 ** L + 1
     res = {"sec": sec, "stage_ms": stage_ms, "near_pairs": pn, "m2l_pairs": pm,
-           "roofline": roofline_of(stage_ms, pn, pm, wl.p, "f64" if precision == "fp64" else "f32", wl.name),
+           "roofline": roofline_of(stage_ms, pn, pm, wl.p, "f64" if precision == "fp64" else "f32",
+                                   f"{wl.name}_{precision}"),
            "u": u, "v": v, "tuning": bp.tuning()}
     bp.close()
     return res
@@ -290,12 +296,12 @@ def run_points(wl, args, dev, m_side=1024):
     v = torch.empty(m, dtype=torch.float64, device=dev)
     plan = fm.Plan(wl.n, wl.sigma, wl.p, wl.depth, domain=(wl.x0, wl.y0, wl.width), m_max=m)
     for _ in range(args.warmup):
-        plan.evaluate_at(x, y, g, px, py, u, v)
+        plan.evaluate_at(x, y, g, px, py, u, v, check=False)
     torch.cuda.synchronize()
     if plan.out_of_domain():
         raise SystemExit("particles or points outside the domain")
     plan.set_timing(True)
-    sec = timed(lambda: plan.evaluate_at(x, y, g, px, py, u, v), args.steps, 0)
+    sec = timed(lambda: plan.evaluate_at(x, y, g, px, py, u, v, check=False), args.steps, 0)
     stages = plan.stats()
     plan.close()
     return sec, m, {k: round(vv, 4) for k, vv in stages.items() if k != "evaluations"}
@@ -320,10 +326,10 @@ def run_lennard_jones(args, dev, m_side=1024):
     s = a / 1.12
     plan = fm.Plan(n, s, 8, 8, kernel="lennard-jones", lj_epsilon=1.0, cutoff=2.5 * s)
     for _ in range(args.warmup):
-        plan.evaluate(x, y, g, fx, fy)
+        plan.evaluate(x, y, g, fx, fy, check=False)
     torch.cuda.synchronize()
     plan.set_timing(True)
-    sec = timed(lambda: plan.evaluate(x, y, g, fx, fy), args.steps, 0)
+    sec = timed(lambda: plan.evaluate(x, y, g, fx, fy, check=False), args.steps, 0)
     stages = plan.stats()
     plan.close()
     return sec, n, {k: round(vv, 4) for k, vv in stages.items() if k in ("tree", "p2p_l2p")}
@@ -340,10 +346,10 @@ def run_gauss_transform(wl, args, dev, sigma=0.02, depth=6, p=12):
     v = torch.empty_like(G)
     plan = fm.Plan(wl.n, sigma, p, depth, domain=(wl.x0, wl.y0, wl.width), kernel="gauss-transform")
     for _ in range(args.warmup):
-        plan.evaluate(x, y, g, G, v)
+        plan.evaluate(x, y, g, G, v, check=False)
     torch.cuda.synchronize()
     plan.set_timing(True)
-    sec = timed(lambda: plan.evaluate(x, y, g, G, v), args.steps, 0)
+    sec = timed(lambda: plan.evaluate(x, y, g, G, v, check=False), args.steps, 0)
     stages = plan.stats()
     plan.close()
     return sec, G, {"tree": round(stages["tree"], 4), "transform": round(stages["p2m_m2m"], 4)}
@@ -360,9 +366,9 @@ def run_laplace_3d(args, dev, n=1 << 20, depth=5, p=6):
     out = tuple(torch.empty(n, dtype=torch.float64, device=dev) for _ in range(4))
     plan = fm.Plan3D(n, p, depth)
     for _ in range(args.warmup):
-        plan.evaluate(x, y, z, q, out)
+        plan.evaluate(x, y, z, q, out, check=False)
     torch.cuda.synchronize()
-    sec = timed(lambda: plan.evaluate(x, y, z, q, out), args.steps, 0)
+    sec = timed(lambda: plan.evaluate(x, y, z, q, out, check=False), args.steps, 0)
     if plan.out_of_domain():
         raise RuntimeError("3D form: particles outside the cube")
     plan.close()
@@ -373,99 +379,218 @@ def run_laplace_3d(args, dev, n=1 << 20, depth=5, p=6):
 # CPU oracle leg (the only part of the bench that touches the oracle)
 # ---------------------------------------------------------------------------
 
-def cpu_baseline_leg(wl, res, args, forms):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _pooled(pairs):
+    num = sum(float(np.sum((u - uo) ** 2 + (v - vo) ** 2)) for u, v, uo, vo in pairs)
+    den = sum(float(np.sum(uo ** 2 + vo ** 2)) for _, _, uo, vo in pairs)
+    return (num / den) ** 0.5 if den > 0 else 0.0
+
+
+def oracle_sample(wl):
+    """A bounded sample of the workload for timing the CPU oracle: the
+    particles in the lower-left quarter of the square, as a problem of its
+    own on that quarter with one level less (same density, same leaf width,
+    same sigma and p, so the same work per particle); the whole workload
+    when it is small."""
+    if wl.n <= (1 << 22) or wl.offsets is not None:
+        return wl, "the whole workload"
+    h = 0.5 * wl.width
+    keep = (wl.x < wl.x0 + h) & (wl.y < wl.y0 + h)
+    sub = workloads.Workload(wl.name, wl.x[keep], wl.y[keep], wl.gamma[keep], sigma=wl.sigma, depth=wl.depth - 1,
+                             p=wl.p, x0=wl.x0, y0=wl.y0, width=h)
+    return sub, (f"the {sub.n:,} particles in the lower-left quarter of the square, as a problem of their own "
+                 f"(depth {sub.depth}: same density, leaf width, sigma and p)")
+
+
+def accuracy_single(wl, res, args, forms):
+    """The CPU baseline (one oracle FMM of a bounded sample of the workload,
+    timed), then the GPU results against the oracle FMM and against the
+    direct sums at seeded targets."""
     import oracle
     oracle.build()
-    budget = args.cpu_seconds
     u_gpu = res["u"].cpu().numpy()
     v_gpu = res["v"].cpu().numpy()
-    out = {}
-    if wl.offsets is None:
-        # whole evaluations of the same workload, repeated until the budget is spent
-        reps, t_cpu = 0, 0.0
-        while True:
-            t1 = time.perf_counter()
-            uo, vo = oracle.fmm(wl.x, wl.y, wl.gamma, wl.sigma, wl.p, wl.depth, wl.x0, wl.y0, wl.width)
-            t_cpu += time.perf_counter() - t1
-            reps += 1
-            if t_cpu >= budget or reps >= 50:
-                break
-        out["cpu_baseline"] = {
-            "value": wl.n * reps / t_cpu, "unit": "particles/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{reps} full FP64 oracle FMM evaluations of the same {wl.n:,}-particle workload "
-                      f"({t_cpu:.1f} s)"}
-        tgt = workloads.sample_targets(wl.n, args.accuracy_targets, 1000 + int(wl.name[1]))
-        us, vs = oracle.direct_split(wl.x, wl.y, wl.gamma, wl.sigma, wl.depth, wl.x0, wl.y0, wl.width,
-                                     targets=tgt)
-        ur, vr = oracle.direct(wl.x, wl.y, wl.gamma, wl.sigma, targets=tgt)
-        acc = {"rel_l2_vs_oracle_fmm": oracle.rel_l2(u_gpu, v_gpu, uo, vo),
-               "rel_l2_vs_split_direct": oracle.rel_l2(u_gpu[tgt], v_gpu[tgt], us, vs),
-               "rel_l2_vs_regularised_direct": oracle.rel_l2(u_gpu[tgt], v_gpu[tgt], ur, vr),
-               "direct_targets": int(tgt.shape[0])}
-        if forms and "mixed" in forms:
-            um, vm = forms.pop("_mixed_uv")
-            um, vm = um.cpu().numpy(), vm.cpu().numpy()
-            forms["mixed"]["rel_l2_vs_fp64_split_direct"] = oracle.rel_l2(um[tgt], vm[tgt], us, vs)
-            forms["mixed"]["rel_l2_vs_regularised_direct"] = oracle.rel_l2(um[tgt], vm[tgt], ur, vr)
-            forms["mixed"]["rel_l2_vs_gpu_fp64"] = oracle.rel_l2(um, vm, u_gpu, v_gpu)
-        if forms and "_l3d" in forms:
-            (x3, y3, z3, q3), out3 = forms.pop("_l3d")
-            g3 = [o.cpu().numpy() for o in out3]
-            t3 = workloads.sample_targets(len(x3), 256, 3004)
-            d3 = oracle.direct3(x3, y3, z3, q3, targets=t3)
-            num = sum(float(np.sum((g3[k][t3] - d3[k]) ** 2)) for k in (1, 2, 3))
-            den = sum(float(np.sum(d3[k] ** 2)) for k in (1, 2, 3))
-            forms["laplace_3d"]["rel_l2_gradient_vs_plain_sum"] = (num / den) ** 0.5
-            forms["laplace_3d"]["rel_l2_potential_vs_plain_sum"] = float(
-                np.linalg.norm(g3[0][t3] - d3[0]) / np.linalg.norm(d3[0]))
-            forms["laplace_3d"]["plain_sum_targets"] = int(t3.shape[0])
-        if forms and "_gauss_G" in forms:
-            Gg = forms.pop("_gauss_G").cpu().numpy()
-            Gd = oracle.gauss_direct(wl.x, wl.y, wl.gamma, 0.02, targets=tgt)
-            forms["gauss_transform"]["rel_l2_vs_plain_sum"] = float(np.linalg.norm(Gg[tgt] - Gd) /
-                                                                    np.linalg.norm(Gd))
-        out["accuracy"] = acc
-    else:
-        # oracle FMM over instances in workload order until the budget is spent
-        done, n_done, t_cpu = 0, 0, 0.0
-        errs = []
-        for i, L in enumerate(wl.depths.tolist()):
-            a, b = int(wl.offsets[i]), int(wl.offsets[i + 1])
-            t1 = time.perf_counter()
-            uo, vo = oracle.fmm(wl.x[a:b], wl.y[a:b], wl.gamma[a:b], wl.sigma, wl.p, L, wl.x0, wl.y0, wl.width)
-            t_cpu += time.perf_counter() - t1
-            done += 1
-            n_done += b - a
-            tgt = workloads.sample_targets(b - a, 64, 2000 + i)
-            us, vs = oracle.direct_split(wl.x[a:b], wl.y[a:b], wl.gamma[a:b], wl.sigma, L, wl.x0, wl.y0,
-                                         wl.width, targets=tgt)
-            errs.append((oracle.rel_l2(u_gpu[a:b], v_gpu[a:b], uo, vo),
-                         oracle.rel_l2(u_gpu[a:b][tgt], v_gpu[a:b][tgt], us, vs)))
-            if t_cpu >= budget:
-                break
-        out["cpu_baseline"] = {
-            "value": n_done / t_cpu, "unit": "particles/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"FP64 oracle FMM of the first {done} of {len(wl.depths)} instances "
-                      f"({n_done:,} particles, {t_cpu:.1f} s)"}
-        out["accuracy"] = {"instances_checked": done,
-                           "max_rel_l2_vs_oracle_fmm": max(e[0] for e in errs),
-                           "max_rel_l2_vs_split_direct": max(e[1] for e in errs),
-                           "direct_targets_per_instance": 64}
-    return out
+    sub, what = oracle_sample(wl)
+    t1 = time.perf_counter()
+    oracle.fmm(sub.x, sub.y, sub.gamma, sub.sigma, sub.p, sub.depth, sub.x0, sub.y0, sub.width)
+    t_cpu = time.perf_counter() - t1
+    base = {"value": sub.n / t_cpu, "unit": "particles/s", "cores": oracle.threads(), "kind": "oracle",
+            "cpu": cpu_model(),
+            "sample": f"one full FP64 oracle FMM evaluation of {what} ({t_cpu:.1f} s)"}
+    del sub
+    cfg = int(wl.name[1])
+    m_split = args.accuracy_targets or (4096 if wl.n > (1 << 24) else 16384)
+    tgt = workloads.sample_targets(wl.n, m_split, 1000 + cfg)
+    uo, vo = oracle.fmm(wl.x, wl.y, wl.gamma, wl.sigma, wl.p, wl.depth, wl.x0, wl.y0, wl.width, targets=tgt)
+    t1 = time.perf_counter()
+    us, vs = oracle.direct_split(wl.x, wl.y, wl.gamma, wl.sigma, wl.depth, wl.x0, wl.y0, wl.width, targets=tgt)
+    t_split = time.perf_counter() - t1
+    treg = workloads.sample_targets(wl.n, min(m_split, args.regularised_targets), 2000 + cfg)
+    ur, vr = oracle.direct(wl.x, wl.y, wl.gamma, wl.sigma, targets=treg)
+    acc = {"rel_l2_vs_oracle_fmm": oracle.rel_l2(u_gpu[tgt], v_gpu[tgt], uo, vo),
+           "oracle_fmm_targets": int(tgt.shape[0]),
+           "rel_l2_vs_split_direct": oracle.rel_l2(u_gpu[tgt], v_gpu[tgt], us, vs),
+           "split_direct_targets": int(tgt.shape[0]),
+           "split_direct_pairs_per_s": float(tgt.shape[0]) * (wl.n - 1) / t_split,
+           "rel_l2_vs_regularised_direct": oracle.rel_l2(u_gpu[treg], v_gpu[treg], ur, vr),
+           "regularised_direct_targets": int(treg.shape[0]),
+           "oracle_fmm_vs_split_direct": oracle.rel_l2(uo, vo, us, vs)}
+    if forms and "_mixed_uv" in forms:
+        um, vm = forms.pop("_mixed_uv")
+        um, vm = um.cpu().numpy(), vm.cpu().numpy()
+        f = forms["mixed"]
+        f["rel_l2_vs_fp64_split_direct"] = oracle.rel_l2(um[tgt], vm[tgt], us, vs)
+        f["split_direct_targets"] = int(tgt.shape[0])
+        f["rel_l2_vs_regularised_direct"] = oracle.rel_l2(um[treg], vm[treg], ur, vr)
+        f["rel_l2_vs_oracle_fmm"] = oracle.rel_l2(um[tgt], vm[tgt], uo, vo)
+        f["within_gate"] = bool(f["rel_l2_vs_fp64_split_direct"] <= 1e-6)
+    return {"cpu_baseline": base, "accuracy": acc}
+
+
+def accuracy_c2(forms):
+    """The C2 form against the oracle FMM at its 16,384 sampled targets and the
+    split direct sum there."""
+    import oracle
+    u, v, wl = forms.pop("_c2")
+    u, v = u.cpu().numpy(), v.cpu().numpy()
+    tgt = workloads.sample_targets(wl.n, 16384, 1002)
+    uo, vo = oracle.fmm(wl.x, wl.y, wl.gamma, wl.sigma, wl.p, wl.depth, wl.x0, wl.y0, wl.width, targets=tgt)
+    us, vs = oracle.direct_split(wl.x, wl.y, wl.gamma, wl.sigma, wl.depth, wl.x0, wl.y0, wl.width, targets=tgt)
+    forms["c2_fp64"].update({"rel_l2_vs_oracle_fmm": oracle.rel_l2(u[tgt], v[tgt], uo, vo),
+                             "rel_l2_vs_split_direct": oracle.rel_l2(u[tgt], v[tgt], us, vs),
+                             "targets": int(tgt.shape[0])})
+
+
+def accuracy_batched(wl, fp64_uv, mixed_uv, per_inst_targets=64):
+    """Pooled per-instance accuracy of the batched forms: FP64 against the
+    oracle FMM of every instance; mixed against the FP64 split direct sum at
+    seeded targets of every instance.  Also times the oracle FMM over all
+    instances (the CPU baseline of the batched workload)."""
+    import oracle
+    oracle.build()
+    u64, v64 = (a.cpu().numpy() for a in fp64_uv)
+    um, vm = (a.cpu().numpy() for a in mixed_uv)
+    fmm_pairs, split_pairs, worst = [], [], 0.0
+    t_cpu = 0.0
+    for i, L in enumerate(wl.depths.tolist()):
+        a, b = int(wl.offsets[i]), int(wl.offsets[i + 1])
+        t1 = time.perf_counter()
+        uo, vo = oracle.fmm(wl.x[a:b], wl.y[a:b], wl.gamma[a:b], wl.sigma, wl.p, L, wl.x0, wl.y0, wl.width)
+        t_cpu += time.perf_counter() - t1
+        fmm_pairs.append((u64[a:b], v64[a:b], uo, vo))
+        worst = max(worst, oracle.rel_l2(u64[a:b], v64[a:b], uo, vo))
+        t = workloads.sample_targets(b - a, per_inst_targets, 3000 + i)
+        us, vs = oracle.direct_split(wl.x[a:b], wl.y[a:b], wl.gamma[a:b], wl.sigma, L, wl.x0, wl.y0, wl.width,
+                                     targets=t)
+        split_pairs.append((um[a:b][t], vm[a:b][t], us, vs))
+    return {"fp64_pooled_rel_l2_vs_oracle_fmm": _pooled(fmm_pairs),
+            "fp64_worst_instance_rel_l2_vs_oracle_fmm": worst,
+            "mixed_pooled_rel_l2_vs_fp64_split_direct": _pooled(split_pairs),
+            "split_direct_targets_per_instance": per_inst_targets,
+            "instances": len(wl.depths),
+            "oracle_fmm_particles_per_s": wl.n / t_cpu, "oracle_fmm_seconds": t_cpu}
+
+
+def run_forms(wl, res, args, dev):
+    forms = {}
+    value = wl.n / res["sec"]
+    # the mixed-precision form of the same workload
+    wm = workloads.Workload(**{**wl.__dict__})
+    wm.precision, wm.fp32_fine_levels = "mixed", 2
+    rm = run_single(wm, args, dev)
+    forms["mixed"] = {"workload": describe(wm), "ms": round(rm["sec"] * 1e3, 4), "value": wm.n / rm["sec"],
+                      "speedup_vs_fp64": res["sec"] / rm["sec"],
+                      "stages_ms": {k: round(x, 4) for k, x in rm["stage_ms"].items()},
+                      "roofline": rm["roofline"], "tuning": rm["tuning"]}
+    forms["_mixed_uv"] = (rm["u"], rm["v"])
+    del rm
+    # the Lamb-Oseen workload in FP64
+    w2 = workloads.make("C2")
+    r2 = run_single(w2, args, dev)
+    forms["c2_fp64"] = {"workload": describe(w2), "ms": round(r2["sec"] * 1e3, 4), "value": w2.n / r2["sec"],
+                        "stages_ms": {k: round(x, 4) for k, x in r2["stage_ms"].items()},
+                        "roofline": r2["roofline"]}
+    forms["_c2"] = (r2["u"], r2["v"], w2)
+    # the batched form
+    w4 = workloads.make("C4")
+    rb = run_batch(w4, args, dev)
+    rb64 = run_batch(w4, args, dev, precision="fp64")
+    rb_in_order = run_batch(w4, args, dev, work_order=0)
+    seq = run_sequential_fp64(w4, args, dev)
+    forms["batched"] = {"workload": describe(w4), "ms": round(rb["sec"] * 1e3, 4), "value": w4.n / rb["sec"],
+                        "fp64_batched_ms": round(rb64["sec"] * 1e3, 4),
+                        "fp64_sequential_single_ms": round(seq * 1e3, 4),
+                        "speedup_vs_fp64_sequential": seq / rb["sec"],
+                        "speedup_fp64_batched_vs_sequential": seq / rb64["sec"],
+                        "input_order_ms": round(rb_in_order["sec"] * 1e3, 4),
+                        "work_order_speedup": rb_in_order["sec"] / rb["sec"],
+                        "tuning": rb["tuning"], "roofline": rb["roofline"]}
+    forms["_c4"] = (w4, (rb64["u"], rb64["v"]), (rb["u"], rb["v"]))
+    if args.extra_forms:
+        extra_forms(forms, args, dev)
+    return forms
+
+
+def extra_forms(forms, args, dev):
+    wl = workloads.make("C2")
+    base = run_single(wl, args, dev)["sec"]
+    ts = run_time_stepping(wl, args, dev)
+    forms["time_stepping"] = {"workload": "C2 particles moved by the explicit midpoint rule (two FP64 "
+                                          "evaluations per step, bounding-square domain)",
+                              "ms_per_step": round(ts * 1e3, 4), "particle_steps_per_s": wl.n / ts,
+                              "step_vs_two_evaluations": ts / (2 * base)}
+    rs = run_single(workloads.make("C2"), args, dev, kernel="singular")
+    forms["singular_kernel"] = {"workload": "C2 with the singular kernel of eq. 7 in the near field (point "
+                                            "vortices, FP64)",
+                                "ms": round(rs["sec"] * 1e3, 4), "value": wl.n / rs["sec"],
+                                "stages_ms": {k: round(x, 4) for k, x in rs["stage_ms"].items()}}
+    tp, mp, sp = run_points(workloads.make("C2"), args, dev)
+    forms["points"] = {"workload": "C2 particles, velocity on a 1024 x 1024 vertex lattice of points "
+                                   "(FP64, eq. 1 with targets apart from the sources)",
+                       "ms": round(tp * 1e3, 4), "points_per_s": mp / tp, "stages_ms": sp}
+    tl, nl, sl = run_lennard_jones(args, dev)
+    forms["lennard_jones"] = {"workload": "2^20 Lennard-Jones particles, jittered 1024 x 1024 lattice, s = a/1.12, "
+                                          "cutoff 2.5 s, depth 8 (FP64 forces, near field only)",
+                              "ms": round(tl * 1e3, 4), "particles_per_s": nl / tl, "stages_ms": sl}
+    tg, _, sg = run_gauss_transform(wl, args, dev)
+    forms["gauss_transform"] = {"workload": "fast Gauss transform of C2's particles (strengths = circulations), "
+                                            "sigma = 0.02, 4096 leaf boxes (depth 6), p = 12 per axis, FP64",
+                                "ms": round(tg * 1e3, 4), "particles_per_s": wl.n / tg, "stages_ms": sg}
+    t3, _, _ = run_laplace_3d(args, dev)
+    forms["laplace_3d"] = {"workload": "3D form: 2^20 charges uniform in the unit cube, octree depth 5, "
+                                       "Cartesian Taylor expansions of degree 6, FP64 potential and gradient",
+                           "ms": round(t3 * 1e3, 4), "particles_per_s": (1 << 20) / t3}
 
 
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="C2", help="workload: C1, C2 (default), C3, C4 (batched) or C5")
+    ap.add_argument("--config", default="C5", help="workload: C1, C2, C3, C4 (batched) or C5 (default)")
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
+                    help="precision of the headline workload (default: FP64 for C5, the workload's own otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--no-forms", action="store_true", help="skip the mixed and batched form comparison")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="time budget of the CPU oracle leg")
+    ap.add_argument("--no-forms", action="store_true", help="skip the mixed, C2 and batched forms")
+    ap.add_argument("--extra-forms", action="store_true",
+                    help="also time time stepping, the singular kernel, target points, Lennard-Jones, the fast "
+                         "Gauss transform and the 3D form")
     ap.add_argument("--form", default=None, choices=["laplace_3d"],
                     help="time only this form (one JSON line with its timing; for profiling)")
-    ap.add_argument("--accuracy-targets", type=int, default=1024)
+    ap.add_argument("--accuracy-targets", type=int, default=0,
+                    help="targets of the split direct sum (default 4,096 at C5, 16,384 otherwise)")
+    ap.add_argument("--regularised-targets", type=int, default=1024,
+                    help="targets of the fully regularised direct sum (reported, not gated)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the timed region, run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -488,62 +613,20 @@ def main() -> int:
         return 0
     dev = torch.device("cuda:0")
     wl = workloads.make(args.config)
+    if args.precision:
+        wl.precision = args.precision
+        wl.fp32_fine_levels = 2 if args.precision == "mixed" else 0
+    elif wl.name == "C5":
+        wl.precision, wl.fp32_fine_levels = "fp64", 0
     batched = wl.offsets is not None
     res = run_batch(wl, args, dev) if batched else run_single(wl, args, dev)
     value = wl.n / res["sec"]
+    print(f"# headline {wl.name} {wl.precision}: {res['sec'] * 1e3:.3f} ms", file=sys.stderr, flush=True)
 
     forms = None
-    if not args.no_forms and not batched and wl.name == "C2":
-        forms = {"fp64": {"ms": round(res["sec"] * 1e3, 4), "value": value}}
-        wm = workloads.make("C2")
-        wm.precision, wm.fp32_fine_levels = "mixed", 2
-        rm = run_single(wm, args, dev)
-        forms["mixed"] = {"workload": describe(wm), "ms": round(rm["sec"] * 1e3, 4), "value": wm.n / rm["sec"],
-                          "speedup_vs_fp64": res["sec"] / rm["sec"],
-                          "stages_ms": {k: round(x, 4) for k, x in rm["stage_ms"].items()},
-                          "roofline": rm["roofline"]}
-        forms["_mixed_uv"] = (rm["u"], rm["v"])
-        ts = run_time_stepping(workloads.make("C2"), args, dev)
-        forms["time_stepping"] = {"workload": "C2 particles moved by the explicit midpoint rule (two FP64 "
-                                              "evaluations per step, bounding-square domain)",
-                                  "ms_per_step": round(ts * 1e3, 4), "particle_steps_per_s": wl.n / ts,
-                                  "step_vs_two_evaluations": ts / (2 * res["sec"])}
-        rs = run_single(workloads.make("C2"), args, dev, kernel="singular")
-        forms["singular_kernel"] = {"workload": "C2 with the singular kernel of eq. 7 in the near field (point "
-                                                "vortices, FP64)",
-                                    "ms": round(rs["sec"] * 1e3, 4), "value": wl.n / rs["sec"],
-                                    "stages_ms": {k: round(x, 4) for k, x in rs["stage_ms"].items()}}
-        tp, mp, sp = run_points(workloads.make("C2"), args, dev)
-        forms["points"] = {"workload": "C2 particles, velocity on a 1024 x 1024 vertex lattice of points "
-                                       "(FP64, eq. 1 with targets apart from the sources)",
-                           "ms": round(tp * 1e3, 4), "points_per_s": mp / tp, "stages_ms": sp}
-        tl, nl, sl = run_lennard_jones(args, dev)
-        forms["lennard_jones"] = {"workload": "2^20 Lennard-Jones particles, jittered 1024 x 1024 lattice, s = a/1.12, "
-                                              "cutoff 2.5 s, depth 8 (FP64 forces, near field only)",
-                                  "ms": round(tl * 1e3, 4), "particles_per_s": nl / tl, "stages_ms": sl}
-        tg, Gg, sg = run_gauss_transform(workloads.make("C2"), args, dev)
-        forms["gauss_transform"] = {"workload": "fast Gauss transform of C2's particles (strengths = circulations), "
-                                                "sigma = 0.02, 4096 leaf boxes (depth 6), p = 12 per axis, FP64",
-                                    "ms": round(tg * 1e3, 4), "particles_per_s": wl.n / tg, "stages_ms": sg}
-        forms["_gauss_G"] = Gg
-        t3, arrs3, out3 = run_laplace_3d(args, dev)
-        forms["laplace_3d"] = {"workload": "3D form: 2^20 charges uniform in the unit cube, octree depth 5, "
-                                           "Cartesian Taylor expansions of degree 6, FP64 potential and gradient",
-                               "ms": round(t3 * 1e3, 4), "particles_per_s": (1 << 20) / t3}
-        forms["_l3d"] = (arrs3, out3)
-        w4 = workloads.make("C4")
-        rb = run_batch(w4, args, dev)
-        rb64 = run_batch(w4, args, dev, precision="fp64")
-        rb_in_order = run_batch(w4, args, dev, work_order=0)
-        seq = run_sequential_fp64(w4, args, dev)
-        forms["batched"] = {"workload": describe(w4), "ms": round(rb["sec"] * 1e3, 4), "value": w4.n / rb["sec"],
-                            "fp64_batched_ms": round(rb64["sec"] * 1e3, 4),
-                            "fp64_sequential_single_ms": round(seq * 1e3, 4),
-                            "speedup_vs_fp64_sequential": seq / rb["sec"],
-                            "speedup_fp64_batched_vs_sequential": seq / rb64["sec"],
-                            "input_order_ms": round(rb_in_order["sec"] * 1e3, 4),
-                            "work_order_speedup": rb_in_order["sec"] / rb["sec"],
-                            "tuning": rb["tuning"], "roofline": rb["roofline"]}
+    if not args.no_forms and not batched and wl.name == "C5":
+        forms = run_forms(wl, res, args, dev)
+        print("# forms timed", file=sys.stderr, flush=True)
 
     if args.calibrate_copy_mib > 0:
         nel = args.calibrate_copy_mib * (1 << 20) // 8
@@ -552,6 +635,7 @@ def main() -> int:
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
+        del src, dst
 
     out = {
         "metric": METRIC,
@@ -573,12 +657,16 @@ def main() -> int:
         "tuning": res["tuning"],
         "roofline": res["roofline"],
     }
-    if not args.no_cpu_baseline:
-        out.update(cpu_baseline_leg(wl, res, args, forms))
+    if not args.no_cpu_baseline and not batched:
+        out.update(accuracy_single(wl, res, args, forms))
+        print("# oracle leg done", file=sys.stderr, flush=True)
+        if forms is not None:
+            accuracy_c2(forms)
+            w4, f64uv, mixuv = forms.pop("_c4")
+            forms["batched"]["accuracy"] = accuracy_batched(w4, f64uv, mixuv)
     if forms is not None:
-        forms.pop("_mixed_uv", None)
-        forms.pop("_gauss_G", None)
-        forms.pop("_l3d", None)
+        for k in [k for k in forms if k.startswith("_")]:
+            forms.pop(k)
         out["forms"] = forms
     print(json.dumps(out))
     return 0

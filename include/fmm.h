@@ -286,8 +286,10 @@ fmm_status fmm_stats(fmm_plan_t plan, double* stage_ms, int32_t n_stages, int32_
                      int64_t* n_evaluations);
 const char* fmm_stage_name(int32_t stage);
 
-/* Parity inspection (not on the hot path).  Synchronises and copies one of
- * the plan's device arrays from the last evaluation into host_buf:
+/* Parity inspection (not on the hot path).  Waits for the stream of the
+ * plan's last evaluation (before any: the stream given to fmm_plan) and
+ * copies one of the plan's device arrays from that evaluation into host_buf,
+ * on that stream; it allocates no device memory:
  *   FMM_DUMP_KEYS       uint32 [n]      leaf z-order key of every particle (input order)
  *   FMM_DUMP_PERM       uint32 [n]      sorted position -> input index
  *   FMM_DUMP_LEAF_START int32 [4^L+1]   sorted range of every leaf, z-order (batched:
@@ -297,6 +299,9 @@ const char* fmm_stage_name(int32_t stage);
  *   FMM_DUMP_DOMAIN     double [4]      x0, y0, width, 2^L / width
  *   FMM_DUMP_ILIST      int32 [Lambda][27]  interaction list of every box as
  *                       global box ids, -1 padded, as the M2L kernel walks it
+                       (single-instance plans; written in chunks into the
+                       workspace's sort temporaries, which every tree build
+                       rewrites, and copied out chunk by chunk)
  *   FMM_DUMP_TKEYS, FMM_DUMP_TPERM, FMM_DUMP_TLEAF_START  the same three
  *                       arrays for the m target points of the last
  *                       fmm_evaluate_at (empty after other evaluations)

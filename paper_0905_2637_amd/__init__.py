@@ -38,7 +38,6 @@ EXPORTED = ["fmm_workspace_size", "fmm_plan", "fmm_evaluate", "fmm_evaluate_at",
             "fmm_status_string", "fmm3d_workspace_size", "fmm3d_plan", "fmm3d_evaluate", "fmm3d_get_status",
             "fmm3d_debug_dump", "fmm3d_destroy"]
 
-
 class Fmm3dParams(C.Structure):
     _fields_ = [("n_max", C.c_int64), ("p", C.c_int32), ("depth", C.c_int32), ("x0", C.c_double),
                 ("y0", C.c_double), ("z0", C.c_double), ("width", C.c_double)]
@@ -298,7 +297,7 @@ class Plan(_PlanBase):
             v = torch.empty(n, dtype=torch.float64, device=x.device)
         return u, v
 
-    def evaluate(self, x, y, gamma, u=None, v=None, check=False):
+    def evaluate(self, x, y, gamma, u=None, v=None, check=True):
         """Velocity (u, v) of eq. 9 at every particle (with the Lennard-Jones
         kernel: the force); FP64 device tensors."""
         n = int(x.shape[0])
@@ -316,7 +315,7 @@ class Plan(_PlanBase):
                 raise FmmError(FMM_E_DOMAIN, f"fmm_evaluate: {nbad} particles outside the domain")
         return u, v
 
-    def evaluate_at(self, x, y, gamma, tx, ty, u=None, v=None, check=False):
+    def evaluate_at(self, x, y, gamma, tx, ty, u=None, v=None, check=True):
         """Velocity (u, v) at the target points (tx, ty) induced by the
         particles (eq. 1 with distinct targets); FP64 device tensors."""
         n, m = int(x.shape[0]), int(tx.shape[0])
@@ -409,7 +408,7 @@ class BatchPlan(_PlanBase):
             v = torch.empty(self.n, dtype=torch.float64, device=self.device)
         return u, v
 
-    def evaluate(self, x, y, gamma, u=None, v=None, check=False):
+    def evaluate(self, x, y, gamma, u=None, v=None, check=True):
         """Velocities of every instance, concatenated like the inputs."""
         u, v = self._outputs(u, v)
         _check_inputs(self.n, (x, y, gamma, u, v))
@@ -462,7 +461,7 @@ class Plan3D:
             raise FmmError(s, "fmm3d_plan")
         self._h = handle
 
-    def evaluate(self, x, y, z, q, out=None, check=False):
+    def evaluate(self, x, y, z, q, out=None, check=True):
         """(phi, dphi/dx, dphi/dy, dphi/dz) at every particle; FP64 device tensors."""
         import torch
         n = int(x.shape[0])

@@ -316,6 +316,11 @@ struct fmm_plan_s {
     Buffers buf;
     int64_t last_n;
     int64_t last_m;                      // target points of the last evaluation (0: none)
+    hipStream_t last_stream;             // stream of the last evaluation (inspection waits on it)
+    // the radix sort's ping-pong arrays, dead outside the tree build: the
+    // interaction-list dump stages its chunks there
+    char* dump_scratch;
+    size_t dump_scratch_bytes;
     // stage timing
     bool timing;
     bool have_events;
@@ -651,6 +656,7 @@ fmm_status make_plan(const fmm_params* prm, Shape&& sh, bool batch, void* d_work
     pl->shape = std::move(sh);
     pl->last_n = -1;
     pl->last_m = 0;
+    pl->last_stream = static_cast<hipStream_t>(stream);
     pl->sn = -1;
     char* base = static_cast<char*>(d_workspace);
     Buffers& b = pl->buf;
@@ -688,7 +694,8 @@ fmm_status make_plan(const fmm_params* prm, Shape&& sh, bool batch, void* d_work
     b.le = reinterpret_cast<cd*>(base + ly.le);
     b.le_part[0] = reinterpret_cast<cd*>(base + ly.le_part[0]);
     b.le_part[1] = reinterpret_cast<cd*>(base + ly.le_part[1]);
-    b.ilist = nullptr;
+    pl->dump_scratch = base + ly.ktmp;
+    pl->dump_scratch_bytes = ly.tkey - ly.ktmp;
     b.t_m2m = reinterpret_cast<cd*>(base + ly.t_m2m);
     b.t_l2l = reinterpret_cast<cd*>(base + ly.t_l2l);
     b.t_h64 = reinterpret_cast<cd*>(base + ly.t_h64);
@@ -845,6 +852,7 @@ fmm_status fmm_evaluate(fmm_plan_t plan, int64_t n, const double* d_x, const dou
     if (n > 0 && (!d_x || !d_y || !d_gamma || !d_u || !d_v)) return FMM_E_ARG;
     plan->last_n = n;
     plan->last_m = 0;
+    plan->last_stream = static_cast<hipStream_t>(stream);
     if (n == 0) return FMM_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e = hipSuccess;
@@ -871,6 +879,7 @@ fmm_status fmm_evaluate_at(fmm_plan_t plan, int64_t n, const double* d_x, const 
     hipStream_t st = static_cast<hipStream_t>(stream);
     plan->last_n = 0;
     plan->last_m = 0;
+    plan->last_stream = static_cast<hipStream_t>(stream);
     if (m == 0) return FMM_OK;
     if (n == 0) {   // no sources: the velocity vanishes everywhere
         return launch_zero2(m, d_u, d_v, st) == hipSuccess ? FMM_OK : FMM_E_DEVICE;
@@ -897,6 +906,7 @@ fmm_status fmm_evaluate_batch(fmm_plan_t plan, const double* d_x, const double* 
     if (n > 0 && (!d_x || !d_y || !d_gamma || !d_u || !d_v)) return FMM_E_ARG;
     plan->last_n = n;
     plan->last_m = 0;
+    plan->last_stream = static_cast<hipStream_t>(stream);
     if (n == 0) return FMM_OK;
     if (plan->timing) {
         // timed: enqueued eagerly with stage events, no graph
@@ -938,6 +948,7 @@ fmm_status fmm_advance_rk2(fmm_plan_t plan, int64_t n, double* d_x, double* d_y,
     if (!d_x || !d_y || !d_gamma || !d_scratch) return FMM_E_ARG;
     plan->last_n = n;
     plan->last_m = 0;
+    plan->last_stream = static_cast<hipStream_t>(stream);
     double* u = d_scratch;
     double* v = d_scratch + n;
     double* xm = d_scratch + 2 * n;
@@ -1167,25 +1178,31 @@ fmm_status fmm_debug_dump(fmm_plan_t plan, int32_t what, void* host_buf, size_t 
     *needed = sz;
     if (!host_buf || bytes < sz) return FMM_E_CAPACITY;
     if (sz == 0) return FMM_OK;
-    if (hipDeviceSynchronize() != hipSuccess) return FMM_E_DEVICE;
+    hipStream_t st = plan->last_stream;
+    if (hipStreamSynchronize(st) != hipSuccess) return FMM_E_DEVICE;
+    auto fetch = [&](void* dst, const void* from, size_t nbytes) {
+        if (hipMemcpyAsync(dst, from, nbytes, hipMemcpyDeviceToHost, st) != hipSuccess) return false;
+        return hipStreamSynchronize(st) == hipSuccess;
+    };
     if (what == FMM_DUMP_ILIST) {
-        // inspection only: a temporary device buffer for the lists
-        int32_t* d = nullptr;
-        if (hipMalloc(&d, sz) != hipSuccess) return FMM_E_DEVICE;
-        Buffers b = plan->buf;
-        b.ilist = d;
-        hipError_t e = launch_ilist(b, plan->shape.depth[0], nullptr);
-        if (e == hipSuccess) e = hipMemcpy(host_buf, d, sz, hipMemcpyDeviceToHost);
-        hipFree(d);
-        return e == hipSuccess ? FMM_OK : FMM_E_DEVICE;
+        // inspection only: the lists are written in chunks into the sort's
+        // ping-pong arrays (rewritten by every tree build) and copied out
+        const int64_t per = int64_t(plan->dump_scratch_bytes / (27 * sizeof(int32_t)));
+        int32_t* d = reinterpret_cast<int32_t*>(plan->dump_scratch);
+        int32_t* h = static_cast<int32_t*>(host_buf);
+        for (int64_t b0 = 0; b0 < int64_t(nbox); b0 += per) {
+            const int64_t cnt = std::min<int64_t>(per, int64_t(nbox) - b0);
+            if (launch_ilist(plan->shape.depth[0], b0, cnt, d, st) != hipSuccess) return FMM_E_DEVICE;
+            if (!fetch(h + b0 * 27, d, size_t(cnt) * 27 * sizeof(int32_t))) return FMM_E_DEVICE;
+        }
+        return FMM_OK;
     }
     if (what == FMM_DUMP_ME || what == FMM_DUMP_LE) {
         // device rows hold P coefficients; hand out the first p of each.
         // Multipole rows hold abar_k = (-1)^(k+1) ahat_k / k!: undo that.
         const int P = plan->P, p = prm.p;
         std::vector<cd> tmp(nbox * size_t(P));
-        if (hipMemcpy(tmp.data(), src, tmp.size() * sizeof(cd), hipMemcpyDeviceToHost) != hipSuccess)
-            return FMM_E_DEVICE;
+        if (!fetch(tmp.data(), src, tmp.size() * sizeof(cd))) return FMM_E_DEVICE;
         std::vector<double> unscale(p, 1.0);
         if (what == FMM_DUMP_ME) {
             long double f = 1.0L;
@@ -1200,8 +1217,7 @@ fmm_status fmm_debug_dump(fmm_plan_t plan, int32_t what, void* host_buf, size_t 
                 out[bx * p + k] = cd{tmp[bx * P + k].x * unscale[k], tmp[bx * P + k].y * unscale[k]};
         return FMM_OK;
     }
-    if (hipMemcpy(host_buf, src, sz, hipMemcpyDeviceToHost) != hipSuccess) return FMM_E_DEVICE;
-    return FMM_OK;
+    return fetch(host_buf, src, sz) ? FMM_OK : FMM_E_DEVICE;
 }
 
 fmm_status fmm_destroy(fmm_plan_t plan)

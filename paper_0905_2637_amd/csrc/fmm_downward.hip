@@ -552,19 +552,20 @@ k_downward(Work wk, int n_inst, const Inst* __restrict__ inst, cd* __restrict__ 
     }
 }
 
-// Debug: the interaction list of every box exactly as k_m2l walks it, as
-// global box ids, -1 padded to 27 entries.
-__global__ void __launch_bounds__(256) k_ilist(int L, int32_t* __restrict__ out)
+// Debug: the interaction list of boxes [b0, b0 + cnt) exactly as k_m2l
+// walks it, as global box ids, -1 padded to 27 entries, box b0 first.
+__global__ void __launch_bounds__(256) k_ilist(int L, int64_t b0, int64_t cnt, int32_t* __restrict__ out)
 {
-    const int64_t nbox = level_offset(L + 1);
-    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (g >= nbox) return;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    const int64_t g = b0 + i;
+    if (g >= level_offset(L + 1)) return;
     int l = 0;
     while (level_offset(l + 1) <= g) ++l;
     const uint32_t k = uint32_t(g - level_offset(l));
     const int ta = int(morton_x(k)), tb = int(morton_y(k)), side = 1 << l;
-    int32_t* dst = out + g * 27;
-    int cnt = 0;
+    int32_t* dst = out + i * 27;
+    int n = 0;
     if (l >= 2) {
         const int cx = ta & 1, cy = tb & 1;
         for (int o = 0; o < 36; ++o) {
@@ -572,10 +573,10 @@ __global__ void __launch_bounds__(256) k_ilist(int L, int32_t* __restrict__ out)
             if (!il_offset(cx, cy, o, dx, dy)) continue;
             const int sa = ta + dx, sb = tb + dy;
             if (sa < 0 || sb < 0 || sa >= side || sb >= side) continue;
-            dst[cnt++] = int32_t(level_offset(l) + morton(uint32_t(sa), uint32_t(sb)));
+            dst[n++] = int32_t(level_offset(l) + morton(uint32_t(sa), uint32_t(sb)));
         }
     }
-    for (; cnt < 27; ++cnt) dst[cnt] = -1;
+    for (; n < 27; ++n) dst[n] = -1;
 }
 
 template <int P>
@@ -649,10 +650,10 @@ hipError_t launch_downward(const Buffers& b, int P, const Work& w, int nwg, hipS
     }
 }
 
-hipError_t launch_ilist(const Buffers& b, int L, hipStream_t st)
+hipError_t launch_ilist(int L, int64_t b0, int64_t cnt, int32_t* out, hipStream_t st)
 {
-    const int64_t nbox = level_offset(L + 1);
-    hipLaunchKernelGGL(k_ilist, dim3(unsigned((nbox + 255) / 256)), dim3(256), 0, st, L, b.ilist);
+    if (cnt <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ilist, dim3(unsigned((cnt + 255) / 256)), dim3(256), 0, st, L, b0, cnt, out);
     return hipGetLastError();
 }
 

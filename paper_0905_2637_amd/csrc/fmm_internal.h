@@ -164,7 +164,6 @@ struct Buffers {
     cd* me;                // [sum Lambda_i * P] scaled multipole coefficients, zero-padded to P
     cd* le;                // [sum Lambda_i * P] scaled local coefficients
     cd* le_part[2];        // [sum Lambda(split)_i * P] partial M2L sums of the split levels
-    int32_t* ilist;        // debug: interaction lists
     cd* t_m2m;             // [4][P][P]
     cd* t_l2l;             // [4][P][P]
     cd* t_h64;             // [49][2P-1] M2L translation data, FP64
@@ -210,7 +209,8 @@ hipError_t launch_p2p(const Buffers& b, int P, const Work& w, int nwg, int waves
 // near field + L2P at the sorted target points of a single-instance FP64 plan
 // (Gaussian or singular kernel)
 hipError_t launch_p2p_at(const Buffers& b, int P, int L, const NearKernel& nk, double* u, double* v, hipStream_t st);
-hipError_t launch_ilist(const Buffers& b, int L, hipStream_t st);
+// interaction lists of boxes [b0, b0 + cnt) of a depth-L tree into out[cnt][27]
+hipError_t launch_ilist(int L, int64_t b0, int64_t cnt, int32_t* out, hipStream_t st);
 // the fast Gauss transform of a single-instance plan (after the tree): P
 // Hermite terms per axis (8, 12 or 16), boxes within Chebyshev distance nc,
 // the range's rows split over `parts` partial expansions; evaluated at the

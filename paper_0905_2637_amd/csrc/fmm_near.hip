@@ -131,11 +131,15 @@ __device__ __forceinline__ void p2p_f32(const float4* __restrict__ src, int padd
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const float dx = ox[r] - t.x, dy = oy[r] - t.y;
-            const float r2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));    // > 0, as in the FP64 form
             float q2;
             if constexpr (KER == kNearSingular) {
-                q2 = t.z * __builtin_amdgcn_rcpf(r2);
+                // a select, not a guard term: gamma / guard would overflow
+                // for large circulations and the product with dx = 0 give NaN
+                const float r2 = fmaf(dx, dx, dy * dy);
+                q2 = r2 > 0.0f ? t.z * __builtin_amdgcn_rcpf(r2) : 0.0f;
             } else {
+                // > 0 for coincident points, whose term is then 0 through 1 - e = 0
+                const float r2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));
                 const float e = __builtin_amdgcn_exp2f(-r2 * c2);
                 q2 = fmaf(-t.z, e, t.z) * __builtin_amdgcn_rcpf(r2);
             }
@@ -166,16 +170,20 @@ __device__ __forceinline__ void p2p_f64(const Src64* __restrict__ src, int padde
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const double dx = x[r] - t.x, dy = y[r] - t.y;
-            // 1e-300 keeps r2 positive for coincident points, whose term
-            // then vanishes through dx = dy = 0; it changes r2 only for
-            // points closer than about 1e-142
             double q2;
             if constexpr (KER == kNearLJ) {
                 q2 = lj_term(fma(dx, dx, dy * dy), k);   // gamma takes no part
+            } else if constexpr (KER == kNearSingular) {
+                // coincident points by a select: a guard term in r2 would
+                // let gamma / guard overflow for large circulations
+                const double r2 = fma(dx, dx, dy * dy);
+                q2 = r2 > 0.0 ? t.g * recip(r2) : 0.0;
             } else {
+                // 1e-300 keeps r2 positive for coincident points, whose term
+                // then vanishes through 1 - e = 0 and dx = dy = 0; it changes
+                // r2 only for points closer than about 1e-142
                 const double r2 = fma(dx, dx, fma(dy, dy, 1e-300));
-                if constexpr (KER == kNearSingular) q2 = t.g * recip(r2);
-                else q2 = t.g * one_minus_exp(r2 * k.ninv2s2) * recip(r2);
+                q2 = t.g * one_minus_exp(r2 * k.ninv2s2) * recip(r2);
             }
             ax[r] = fma(q2, dx, ax[r]);
             ay[r] = fma(-q2, dy, ay[r]);
@@ -440,10 +448,14 @@ __device__ __forceinline__ void quad_pairs(const Src64* qsh, int lane, int w, co
             qi = act ? q : 0.0;
             qj = qi;
         } else {
-            const double r2 = fma(dx, dx, fma(dy, dy, 1e-300));
             double q;
-            if constexpr (KER == kNearSingular) q = recip(r2);
-            else q = one_minus_exp(r2 * k.ninv2s2) * recip(r2);
+            if constexpr (KER == kNearSingular) {
+                const double r2 = fma(dx, dx, dy * dy);
+                q = r2 > 0.0 ? recip(r2) : 0.0;
+            } else {
+                const double r2 = fma(dx, dx, fma(dy, dy, 1e-300));
+                q = one_minus_exp(r2 * k.ninv2s2) * recip(r2);
+            }
             qi = act ? t.g * q : 0.0;
             qj = act ? me.g * q : 0.0;
         }

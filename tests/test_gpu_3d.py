@@ -63,6 +63,8 @@ def _uniform(n, seed):
     (800, 2, 1, 5),
     (20000, 4, 5, 6),
     (4000, 3, 8, 7),
+    (2500, 3, 2, 8),          # the M2L lane split of degree 2
+    (2500, 4, 3, 9),          # and of degree 3
 ])
 def test_matches_oracle(n, L, p, seed):
     x, y, z, q = _uniform(n, seed)
@@ -173,7 +175,7 @@ def test_tree_bit_exact(L, clustered):
     x[5], y[77] = 1.0, np.nan                 # outside: keys 2^(3L), sorted last in input order
     q = rng.uniform(-1, 1, n)
     plan = fm.Plan3D(n, 4, L)
-    plan.evaluate(_dev(x), _dev(y), _dev(z), _dev(q))
+    plan.evaluate(_dev(x), _dev(y), _dev(z), _dev(q), check=False)
     torch.cuda.synchronize()
     keys, perm, ls = plan.dump(fm.DUMP_KEYS), plan.dump(fm.DUMP_PERM), plan.dump(fm.DUMP_LEAF_START)
     assert plan.out_of_domain() == 2

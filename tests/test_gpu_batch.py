@@ -163,9 +163,12 @@ def test_batch_out_of_domain_counted():
     x[5] = 1.5
     y[150] = -0.25
     bp = fm.BatchPlan(counts, [2, 3], 0.01, 8)
-    bp.evaluate(_dev(x), _dev(y), _dev(g))
+    bp.evaluate(_dev(x), _dev(y), _dev(g), check=False)
     torch.cuda.synchronize()
     assert bp.out_of_domain() == 2
+    with pytest.raises(fm.FmmError) as ei:        # the default call reads the status and raises
+        bp.evaluate(_dev(x), _dev(y), _dev(g))
+    assert ei.value.status == fm.FMM_E_DOMAIN
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -251,6 +254,31 @@ def test_c4_batch_sampled_against_single_and_direct():
         ud, vd = oracle.direct_split(wl.x[a:b], wl.y[a:b], wl.gamma[a:b], wl.sigma, depths[i], targets=t)
         err = oracle.rel_l2(u[a:b][t], v[a:b][t], ud, vd)
         assert err < 1e-5, f"instance {i}: rel L2 vs split direct {err:.3e}"
+
+
+def test_c4_fp64_batch_every_instance_matches_oracle():
+    """The 512-instance workload at full size in FP64: every instance of the
+    batched evaluation against the oracle FMM of that instance (1e-12), and
+    the pooled error against the oracle over all 10 million particles."""
+    import torch
+    fm = _fm()
+    wl = workloads.make("C4")
+    counts = np.diff(wl.offsets).tolist()
+    depths = wl.depths.tolist()
+    bp = fm.BatchPlan(counts, depths, wl.sigma, wl.p, precision="fp64")
+    u, v = bp.evaluate(_dev(wl.x), _dev(wl.y), _dev(wl.gamma), check=True)
+    torch.cuda.synchronize()
+    u, v = u.cpu().numpy(), v.cpu().numpy()
+    bp.close()
+    num = den = 0.0
+    for i, L in enumerate(depths):
+        a, b = int(wl.offsets[i]), int(wl.offsets[i + 1])
+        uo, vo = oracle.fmm(wl.x[a:b], wl.y[a:b], wl.gamma[a:b], wl.sigma, wl.p, L)
+        err = oracle.rel_l2(u[a:b], v[a:b], uo, vo)
+        assert err < FP64_TOL, f"instance {i} (n = {b - a}, depth {L}): rel L2 {err:.3e}"
+        num += float(np.sum((u[a:b] - uo) ** 2 + (v[a:b] - vo) ** 2))
+        den += float(np.sum(uo ** 2 + vo ** 2))
+    assert (num / den) ** 0.5 < FP64_TOL
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])

@@ -46,18 +46,40 @@ def _tree_bit_exact(wl, keys, perm, leaf_start):
     assert np.array_equal(leaf_start.astype(np.int64), ls_o), "leaf ranges differ from the oracle"
 
 
+# Sampled accuracy targets: a seeded subset, 16,384 particles at C2 and C3 and
+# 4,096 at C5 (the split direct sum over 2^26 sources per target is the cost).
+SAMPLE = {"C2": 16384, "C3": 16384, "C5": 4096}
+
+
+def _targets(wl):
+    return workloads.sample_targets(wl.n, SAMPLE[wl.name], 1000 + int(wl.name[1]))
+
+
+_C5 = {}
+
+
+def _c5():
+    """The C5 workload and its FP64 split-kernel direct sum at the sampled
+    targets, computed once for the FP64 and the mixed tests."""
+    if not _C5:
+        wl = workloads.make("C5")
+        t = _targets(wl)
+        us, vs = oracle.direct_split(wl.x, wl.y, wl.gamma, wl.sigma, wl.depth, wl.x0, wl.y0, wl.width, targets=t)
+        _C5.update(wl=wl, t=t, us=us, vs=vs)
+    return _C5
+
+
 def test_c2_full_size_fp64():
     """1,048,576-particle Lamb-Oseen lattice, depth 8, p = 17, FP64."""
     wl = workloads.make("C2")
     u, v, keys, perm, ls = _run(wl)
     _tree_bit_exact(wl, keys, perm, ls)
-    t = workloads.sample_targets(wl.n, 4096, 1002)
+    t = _targets(wl)
     uo, vo = oracle.fmm(wl.x, wl.y, wl.gamma, wl.sigma, wl.p, wl.depth, wl.x0, wl.y0, wl.width, targets=t)
     err = oracle.rel_l2(u[t], v[t], uo, vo)
     assert err < 1e-12, f"rel L2 vs the oracle FMM {err:.3e}"
-    t2 = workloads.sample_targets(wl.n, 1024, 1012)
-    us, vs = oracle.direct_split(wl.x, wl.y, wl.gamma, wl.sigma, wl.depth, wl.x0, wl.y0, wl.width, targets=t2)
-    gate = oracle.rel_l2(u[t2], v[t2], us, vs)
+    us, vs = oracle.direct_split(wl.x, wl.y, wl.gamma, wl.sigma, wl.depth, wl.x0, wl.y0, wl.width, targets=t)
+    gate = oracle.rel_l2(u[t], v[t], us, vs)
     assert gate < 1e-6, f"rel L2 vs the FP64 split direct sum {gate:.3e}"
 
 
@@ -67,20 +89,39 @@ def test_c3_full_size_mixed():
     wl = workloads.make("C3")
     u, v, keys, perm, ls = _run(wl)
     _tree_bit_exact(wl, keys, perm, ls)
-    t = workloads.sample_targets(wl.n, 1024, 1003)
+    t = _targets(wl)
     us, vs = oracle.direct_split(wl.x, wl.y, wl.gamma, wl.sigma, wl.depth, wl.x0, wl.y0, wl.width, targets=t)
     gate = oracle.rel_l2(u[t], v[t], us, vs)
     assert gate < 1e-6, f"rel L2 vs the FP64 split direct sum {gate:.3e}"
 
 
+def test_c5_full_size_fp64():
+    """2^26 particles uniform in the unit square, depth 11, p = 20, every
+    stage in FP64 (the paper's largest run, one evaluation of 64 million
+    particles): the tree bit for bit, sampled velocities against the oracle
+    FMM (1e-12) and against the FP64 split-kernel direct sum (the gate)."""
+    c = _c5()
+    wl, t = c["wl"], c["t"]
+    wl.precision, wl.fp32_fine_levels = "fp64", 0
+    try:
+        u, v, keys, perm, ls = _run(wl)
+    finally:
+        wl.precision, wl.fp32_fine_levels = "mixed", 2
+    _tree_bit_exact(wl, keys, perm, ls)
+    uo, vo = oracle.fmm(wl.x, wl.y, wl.gamma, wl.sigma, wl.p, wl.depth, wl.x0, wl.y0, wl.width, targets=t)
+    err = oracle.rel_l2(u[t], v[t], uo, vo)
+    assert err < 1e-12, f"rel L2 vs the oracle FMM {err:.3e}"
+    gate = oracle.rel_l2(u[t], v[t], c["us"], c["vs"])
+    assert gate < 1e-6, f"rel L2 vs the FP64 split direct sum {gate:.3e}"
+
+
 def test_c5_full_size_mixed():
     """2^26 particles uniform in the unit square, depth 11, p = 20, mixed."""
-    wl = workloads.make("C5")
+    c = _c5()
+    wl, t = c["wl"], c["t"]
     u, v, keys, perm, ls = _run(wl)
     _tree_bit_exact(wl, keys, perm, ls)
-    t = workloads.sample_targets(wl.n, 256, 1005)
-    us, vs = oracle.direct_split(wl.x, wl.y, wl.gamma, wl.sigma, wl.depth, wl.x0, wl.y0, wl.width, targets=t)
-    gate = oracle.rel_l2(u[t], v[t], us, vs)
+    gate = oracle.rel_l2(u[t], v[t], c["us"], c["vs"])
     assert gate < 1e-6, f"rel L2 vs the FP64 split direct sum {gate:.3e}"
 
 

@@ -22,6 +22,11 @@ def _fm():
     return fm
 
 
+def _dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, np.float64), device="cuda")
+
+
 @pytest.fixture(scope="module", autouse=True)
 def _built():
     oracle.build()
@@ -246,6 +251,29 @@ def test_out_of_domain_points_are_counted():
     assert oracle.rel_l2(u, v, uo, vo) < FP64_TOL
 
 
+def test_default_call_raises_on_out_of_domain():
+    """The binding reads the device status word after every call unless told
+    not to: a particle outside the explicit square, or a target point outside
+    it, raises FMM_E_DOMAIN."""
+    import torch
+    fm = _fm()
+    x, y, g = workloads.uniform_square(600, 18)
+    x[7] = 1.25
+    plan = fm.Plan(600, 0.01, 8, 3, m_max=10)
+    with pytest.raises(fm.FmmError) as ei:
+        plan.evaluate(_dev(x), _dev(y), _dev(g))
+    assert ei.value.status == fm.FMM_E_DOMAIN
+    x[7] = 0.5
+    plan.evaluate(_dev(x), _dev(y), _dev(g))      # inside again: no error
+    tx = np.full(10, 0.5)
+    tx[3] = -2.0
+    with pytest.raises(fm.FmmError) as ei:
+        plan.evaluate_at(_dev(x), _dev(y), _dev(g), _dev(tx), _dev(np.full(10, 0.5)))
+    assert ei.value.status == fm.FMM_E_DOMAIN
+    torch.cuda.synchronize()
+    plan.close()
+
+
 def test_nan_position_is_counted():
     x, y, g = workloads.uniform_square(500, 17)
     x[20] = np.nan
@@ -305,6 +333,36 @@ def test_mixed_within_gate_of_split_direct(n, L, p, sigma, fine, seed):
     assert oracle.rel_l2(u, v, uo, vo) < 5e-7, (err, trunc)
     assert err < trunc + 5e-7
     if trunc < 5e-7:            # the expansion order can meet the gate at all
+        assert err < MIXED_TOL
+
+
+@pytest.mark.parametrize("n,L,p,sigma,fine,split,seed", [
+    (20000, 6, 17, 0.002, 2, 5, 26),    # FP32 level 5 split over wavefronts, level 6 not
+    (20000, 6, 20, 0.0015, 3, 5, 27),   # FP32 levels 4-5 split, 6 not
+    (6000, 5, 12, 0.003, 2, 8, 28),     # every FP32 level split
+    (20000, 6, 12, 0.002, 2, 0, 29),    # no level split
+])
+def test_mixed_mfma_m2l_matches_oracle(n, L, p, sigma, fine, split, seed):
+    """The FP32 M2L levels on the matrix cores (the launch shape the
+    autotuner may choose for a mixed plan) against the oracle FMM and the
+    FP64 split-kernel direct sum, at the mixed form's tolerances."""
+    import torch
+    fm = _fm()
+    x, y, g = workloads.uniform_square(n, seed)
+    plan = fm.Plan(n, sigma, p, L, precision="mixed", fp32_fine_levels=fine)
+    plan.set_tuning(4, split, 1)
+    assert plan.tuning()["m2l_mfma"] == 1
+    u, v = plan.evaluate(_dev(x), _dev(y), _dev(g))
+    torch.cuda.synchronize()
+    u, v = u.cpu().numpy(), v.cpu().numpy()
+    plan.close()
+    uo, vo = oracle.fmm(x, y, g, sigma, p, L)
+    us, vs = oracle.direct_split(x, y, g, sigma, L)
+    trunc = oracle.rel_l2(uo, vo, us, vs)
+    err = oracle.rel_l2(u, v, us, vs)
+    assert oracle.rel_l2(u, v, uo, vo) < 5e-7, (err, trunc)
+    assert err < trunc + 5e-7
+    if trunc < 5e-7:
         assert err < MIXED_TOL
 
 

@@ -147,3 +147,28 @@ def test_singular_polygon_rotates_rigidly():
         errs.append(float(np.max(np.hypot(x.cpu().numpy() - xe, y.cpu().numpy() - ye))))
     assert errs[0] < 1e-3, errs
     assert 3.5 < errs[0] / errs[1] < 4.5, errs
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_singular_coincident_large_circulation(precision):
+    """Coincident particles contribute nothing (a pair at zero distance has no
+    kernel value), also when the circulations are so large that a guard term
+    in the squared distance would overflow gamma / r^2: 100 particles of the
+    C1 workload are duplicated exactly (inside quads of sibling leaves and in
+    the general near-field path alike) and every circulation is scaled to
+    about 1e9.  The velocities must stay finite and equal the oracle's."""
+    wl = workloads.make("C1")
+    idx = np.arange(0, wl.n, wl.n // 100)[:100]
+    x = np.concatenate([wl.x, wl.x[idx]])
+    y = np.concatenate([wl.y, wl.y[idx]])
+    g = 1e9 * np.concatenate([wl.gamma, -wl.gamma[idx] + 0.5])
+    u, v = _evaluate(x, y, g, 17, wl.depth, precision=precision)
+    assert np.all(np.isfinite(u)) and np.all(np.isfinite(v))
+    if precision == "fp64":
+        uo, vo = oracle.fmm(x, y, g, 0.0, 17, wl.depth)
+        err = oracle.rel_l2(u, v, uo, vo)
+        assert err < 1e-12, f"rel L2 vs the oracle FMM {err:.3e}"
+    else:
+        ud, vd = oracle.direct(x, y, g, 0.0)
+        err = oracle.rel_l2(u, v, ud, vd)
+        assert err < 1e-5, f"rel L2 vs the singular direct sum {err:.3e}"
