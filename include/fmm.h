@@ -317,6 +317,30 @@ enum {
 fmm_status fmm_debug_dump(fmm_plan_t plan, int32_t what, void* host_buf,
                           size_t bytes, size_t* needed);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid allocation): one full
+ * evaluation exactly as fmm_plan + fmm_evaluate compute it with the same
+ * parameters (same kernels, same results bit for bit), whose workspace is a
+ * fixed array of FMM_STATIC_SCRATCH_BYTES bytes of device memory that the
+ * library holds on every GPU it is loaded on until the process ends.  It
+ * allocates no device memory and creates no plan handle for the caller.
+ *   prm                single-instance parameters as for fmm_plan; the
+ *                      workspace they need (fmm_workspace_size) must fit in
+ *                      FMM_STATIC_SCRATCH_BYTES, else FMM_E_CAPACITY (checked
+ *                      on the host, nothing enqueued)
+ *   n, d_x .. d_v      as for fmm_evaluate (0 <= n <= prm->n_max)
+ * The first call on a device, and every call whose parameters differ from
+ * the previous call's on that device, uploads the operator tables into the
+ * array on `stream` and waits for it; later calls with the same parameters
+ * only enqueue kernels.  All calls on one GPU share its array: calls whose
+ * work overlaps on one GPU (other streams, other host threads) race and
+ * their results are undefined.  No stage timing, status word or inspection.
+ * Errors: FMM_E_ARG, FMM_E_CAPACITY, FMM_E_UNSUPPORTED and FMM_E_DEVICE as
+ * for fmm_plan and fmm_evaluate. */
+#define FMM_STATIC_SCRATCH_BYTES (64u << 20)
+fmm_status fmm_evaluate_static(const fmm_params* prm, int64_t n, const double* d_x, const double* d_y,
+                               const double* d_gamma, double* d_u, double* d_v, void* stream);
+
 /* Release the host handle, its HIP events, captured graph and private
  * stream.  Never frees the workspace or any other caller memory.  NULL is
  * accepted. */

@@ -36,7 +36,16 @@ EXPORTED = ["fmm_workspace_size", "fmm_plan", "fmm_evaluate", "fmm_evaluate_at",
             "fmm_plan_batch", "fmm_evaluate_batch", "fmm_advance_rk2", "fmm_get_status", "fmm_set_timing", "fmm_stats", "fmm_stage_name",
             "fmm_get_tuning", "fmm_set_tuning", "fmm_autotune", "fmm_work_estimate", "fmm_debug_dump", "fmm_destroy",
             "fmm_status_string", "fmm3d_workspace_size", "fmm3d_plan", "fmm3d_evaluate", "fmm3d_get_status",
-            "fmm3d_debug_dump", "fmm3d_destroy"]
+            "fmm3d_debug_dump", "fmm3d_destroy", "fmm_evaluate_static"]
+
+# Inspection aid: when set to a byte value, every new plan's workspace is
+# filled with it before the plan is made (results must not depend on what
+# the workspace held before).
+WORKSPACE_FILL = None
+
+# bytes of the fixed device array behind fmm_evaluate_static (FMM_STATIC_SCRATCH_BYTES)
+STATIC_SCRATCH_BYTES = 64 << 20
+
 
 class Fmm3dParams(C.Structure):
     _fields_ = [("n_max", C.c_int64), ("p", C.c_int32), ("depth", C.c_int32), ("x0", C.c_double),
@@ -97,6 +106,7 @@ def load():
     lib.fmm3d_get_status.argtypes = [vp, vp, C.POINTER(C.c_int64)]
     lib.fmm3d_destroy.argtypes = [vp]
     lib.fmm3d_debug_dump.argtypes = [vp, C.c_int32, vp, C.c_size_t, C.POINTER(C.c_size_t)]
+    lib.fmm_evaluate_static.argtypes = [C.POINTER(FmmParams), C.c_int64, vp, vp, vp, vp, vp, vp]
     for name in EXPORTED:
         if name in ("fmm_stage_name", "fmm_status_string"):
             continue
@@ -158,6 +168,28 @@ def _check_inputs(n, tensors):
             raise ValueError(f"inputs and outputs must be contiguous float64 CUDA tensors of length {n}")
 
 
+def evaluate_static(x, y, gamma, sigma, p, depth, domain=(0.0, 0.0, 1.0), precision="fp64", fp32_fine_levels=2,
+                    kernel="gaussian", n_max=None, u=None, v=None):
+    """One evaluation through fmm_evaluate_static: the library's fixed device
+    array serves as the workspace, so nothing is allocated for it (u and v are
+    allocated here when not given)."""
+    import torch
+    n = int(x.shape[0])
+    if u is None:
+        u = torch.empty(n, dtype=torch.float64, device=x.device)
+    if v is None:
+        v = torch.empty(n, dtype=torch.float64, device=x.device)
+    _check_inputs(n, (x, y, gamma, u, v))
+    prm = make_params(n if n_max is None else n_max, sigma, p, depth, domain, precision, fp32_fine_levels,
+                      kernel=kernel)
+    s = load().fmm_evaluate_static(C.byref(prm), n, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                   C.c_void_p(gamma.data_ptr()), C.c_void_p(u.data_ptr()), C.c_void_p(v.data_ptr()),
+                                   _stream_handle())
+    if s != FMM_OK:
+        raise FmmError(s, "fmm_evaluate_static")
+    return u, v
+
+
 class _PlanBase:
     """Shared handle management, status, timing, tuning and inspection."""
 
@@ -166,6 +198,8 @@ class _PlanBase:
     def _alloc_workspace(self, nbytes):
         import torch
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        if WORKSPACE_FILL is not None:
+            self.workspace.fill_(int(WORKSPACE_FILL))
         base = self.workspace.data_ptr()
         self._ws_ptr = (base + 255) & ~255
         self._ws_bytes = nbytes

@@ -637,7 +637,7 @@ void rank_by_work(Shape& sh, int p)
 }
 
 fmm_status make_plan(const fmm_params* prm, Shape&& sh, bool batch, void* d_workspace, size_t bytes, void* stream,
-                     fmm_plan_t* out)
+                     fmm_plan_t* out, bool events = true)
 {
     rank_by_work(sh, prm->p);
     if ((reinterpret_cast<uintptr_t>(d_workspace) & 255) != 0) return FMM_E_ARG;
@@ -737,7 +737,7 @@ fmm_status make_plan(const fmm_params* prm, Shape&& sh, bool batch, void* d_work
         delete pl;
         return FMM_E_DEVICE;
     }
-    pl->have_events = true;
+    pl->have_events = events;
     for (int r = 0; r < kTimingRing && pl->have_events; ++r)
         for (int i = 0; i <= ST_COUNT; ++i)
             if (hipEventCreate(&pl->ev[r][i]) != hipSuccess) {
@@ -757,6 +757,25 @@ fmm_status run_once(fmm_plan_s* pl, int64_t n, const double* x, const double* y,
 }
 
 }  // namespace
+
+namespace fmm {
+
+// A single-instance plan over a device buffer the library itself provides
+// (no stage-timing events, so building it creates no HIP objects beyond the
+// uploads it enqueues).
+fmm_status plan_in_buffer(const fmm_params* prm, void* d_buffer, size_t bytes, void* stream, fmm_plan_t* out)
+{
+    if (!out || !d_buffer) return FMM_E_ARG;
+    *out = nullptr;
+    fmm_status s = validate_common(prm);
+    if (s != FMM_OK) return s;
+    Shape sh;
+    s = single_shape(prm, sh);
+    if (s != FMM_OK) return s;
+    return make_plan(prm, std::move(sh), false, d_buffer, bytes, stream, out, false);
+}
+
+}  // namespace fmm
 
 extern "C" {
 

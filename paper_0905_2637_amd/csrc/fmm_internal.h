@@ -15,6 +15,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/fmm.h"
+
 namespace fmm {
 
 // Square domain of one instance: [x0, x0 + W]^2 and s = 2^L / W, the
@@ -225,6 +227,11 @@ hipError_t launch_zero2(int64_t n, double* a, double* b, hipStream_t st);
 // time stepping: (xo, yo) = (x, y) + c (u, v); xo, yo may alias x, y
 hipError_t launch_advance(int64_t n, const double* x, const double* y, const double* u, const double* v, double c,
                           double* xo, double* yo, hipStream_t st);
+
+// ---- plans over a library-provided buffer ----------------------------------
+// a single-instance plan whose workspace is d_buffer (bytes, 256-byte aligned)
+// and which records no stage-timing events
+fmm_status plan_in_buffer(const fmm_params* prm, void* d_buffer, size_t bytes, void* stream, fmm_plan_t* out);
 
 // ---- host-side operator tables (FP64, built once per plan) -----------------
 void build_tables(int P, int p, cd* m2m, cd* l2l, cd* h64, cf* h32, double* sin_, double* sout_);
