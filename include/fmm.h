@@ -27,7 +27,7 @@
  *     PyTorch CUDA/HIP tensor).  The library never frees caller memory.
  *   - "stream" is a hipStream_t passed as void* (NULL = the default stream).
  *     fmm_evaluate, fmm_evaluate_at, fmm_evaluate_batch and fmm3d_evaluate only enqueue work on
- *     it (the batched form as one graph launch): they never
+ *     it (the batched form as one table kernel and one graph launch): they never
  *     synchronise, never allocate device memory and never read device data
  *     back to the host.
  *   - A plan is not re-entrant: two evaluations of one plan must not overlap
@@ -124,10 +124,17 @@ typedef struct {
     int32_t kernel;           /* an fmm_kernel value (0: the Gaussian kernel of eq. 8) */
     double  lj_epsilon;       /* Lennard-Jones energy eps (kernel FMM_KERNEL_LENNARD_JONES only) */
     double  cutoff;           /* Lennard-Jones cutoff (kernel FMM_KERNEL_LENNARD_JONES only) */
+    int32_t max_instances;    /* 0 or 1: the single form (fmm_evaluate); 2 .. 65536: the batched
+                                 form (fmm_evaluate_batch), at most this many instances per call;
+                                 n_max then caps their total particle count and depth their
+                                 deepest tree */
+    int64_t max_leaves;       /* batched form: capacity for sum over a call's instances of
+                                 4^depth_i (leaf boxes; the expansions of all levels are sized
+                                 from it); 0 = max_instances * 4^depth, the worst case */
 } fmm_params;
 
-/* Number of bytes of device workspace a plan with these parameters needs.
- * Host only; touches no device.  Errors: FMM_E_ARG for invalid parameters
+/* Number of bytes of device workspace a plan with these parameters needs
+ * (either form, after prm->max_instances).  Host only; touches no device.  Errors: FMM_E_ARG for invalid parameters
  * or a NULL pointer, FMM_E_UNSUPPORTED for p > 22 in mixed mode and for the
  * kernel-specific limits listed with fmm_kernel. */
 fmm_status fmm_workspace_size(const fmm_params* prm, size_t* bytes);
@@ -184,36 +191,45 @@ fmm_status fmm_evaluate_at(fmm_plan_t plan, int64_t n, const double* d_x, const 
                            const double* d_gamma, int64_t m, const double* d_tx, const double* d_ty,
                            double* d_u, double* d_v, void* stream);
 
-/* Batched form: many independent problems, each evaluated exactly as
- * fmm_evaluate would (the same operation; only the schedule differs),
- * sharing sigma, p, precision and one explicit square [x0, x0+width]^2,
- * each with its own
- * particle count counts[i] >= 0 and tree depth depths[i] in 0..13.  Their
- * particles are concatenated in instance order (instance i owns the
- * counts[i] entries after those of instances 0..i-1); every stage is one
- * launch over the work of all instances.  n_max and depth of prm are
- * ignored; m_max must be 0 (else FMM_E_ARG); width must be > 0 (else
- * FMM_E_UNSUPPORTED); 1 <= n_inst <= 65536
- * and ceil(log2 n_inst) + 2 max(depths) <= 32 (else FMM_E_UNSUPPORTED).
- * counts and depths are host arrays read during the call only. */
-fmm_status fmm_workspace_size_batch(const fmm_params* prm, int32_t n_inst, const int32_t* counts,
-                                    const int32_t* depths, size_t* bytes);
-fmm_status fmm_plan_batch(const fmm_params* prm, int32_t n_inst, const int32_t* counts,
-                          const int32_t* depths, void* d_workspace, size_t bytes, void* stream,
-                          fmm_plan_t* out);
-
-/* Evaluate every instance of a batched plan: device FP64 arrays of
- * sum(counts) entries, laid out as described above; results in the same
- * order.  The first call with a given set of five pointers captures the
- * evaluation into a HIP graph (on a stream the plan owns); later calls with
- * the same pointers replay it on `stream` with one launch.  Calls on one
- * plan must not overlap.  Errors: FMM_E_ARG (a single-instance plan, NULL
- * pointers), FMM_E_DEVICE.  fmm_get_status and fmm_debug_dump (KEYS, PERM,
- * LEAF_START of all instances, segment after segment) work as for a single
- * plan.  With stage timing on (fmm_set_timing) the evaluation is enqueued
- * eagerly, with the stage events between its launches, instead of replayed. */
-fmm_status fmm_evaluate_batch(fmm_plan_t plan, const double* d_x, const double* d_y,
-                              const double* d_gamma, double* d_u, double* d_v, void* stream);
+/* Batched form (Sections 4 and 5.2: many trees of uneven size, and sizes
+ * that change from call to call): a plan made with prm->max_instances >= 2
+ * fixes capacities only -- n_max particles in total, max_instances
+ * instances, trees no deeper than prm->depth, max_leaves leaf boxes in
+ * total -- and every call evaluates the instance set it is given, each
+ * instance exactly as fmm_evaluate would (the same operation and kernels,
+ * the same results bit for bit), sharing sigma, p, precision, kernel and one
+ * explicit square [x0, x0+width]^2 (width <= 0: FMM_E_UNSUPPORTED; m_max
+ * must be 0, else FMM_E_ARG; the Gauss transform: FMM_E_UNSUPPORTED;
+ * ceil(log2 max_instances) + 2 depth <= 32, else FMM_E_UNSUPPORTED).
+ *   n_inst      instances of this call, 1 <= n_inst <= max_instances (host)
+ *   d_offsets   device int64 [n_inst + 1]: CSR offsets into the arrays below;
+ *               instance i owns entries [d_offsets[i], d_offsets[i+1]),
+ *               d_offsets[0] = 0, non-decreasing
+ *   d_depths    device int32 [n_inst]: tree depth of every instance, 0 .. depth
+ *   d_x .. d_v  device FP64 arrays of d_offsets[n_inst] entries, as for
+ *               fmm_evaluate, results in the same order
+ * The instance table is read on the device: one kernel validates it against
+ * the capacities, lays out the instances' segments, orders them by the
+ * paper's work estimate (eqs. 13-15, heaviest first; see
+ * fmm_work_estimate) and writes the work tables of every launch; the stage
+ * kernels are launched with grids sized for the capacities, and a
+ * workgroup past its launch's work returns at once.  The first call with a
+ * given set of the five arrays captures those launches into a HIP graph (on
+ * a stream the plan owns); later calls with the same arrays -- whatever
+ * their instance sets -- run the table kernel and replay the graph on
+ * `stream`.  An instance set that does not fit the capacities, or is
+ * malformed, computes nothing (d_u, d_v are left as they were) and
+ * fmm_get_status then returns FMM_E_CAPACITY or FMM_E_ARG.  Calls on one
+ * plan must not overlap.  Errors (synchronous): FMM_E_ARG (a single-instance
+ * plan, n_inst out of range, NULL pointers), FMM_E_DEVICE.
+ * fmm_get_status and fmm_debug_dump (KEYS and PERM over n_max entries,
+ * LEAF_START over the leaf capacity: the segments of the call's instances,
+ * 4^depth_i + 1 entries each, come first) work as for a single plan.  With
+ * stage timing on (fmm_set_timing) the launches are enqueued eagerly, with
+ * the stage events between them, instead of replayed. */
+fmm_status fmm_evaluate_batch(fmm_plan_t plan, int32_t n_inst, const int64_t* d_offsets, const int32_t* d_depths,
+                              const double* d_x, const double* d_y, const double* d_gamma, double* d_u, double* d_v,
+                              void* stream);
 
 /* Vortex-method time stepping (Section 3, eq. 6: in ideal 2D flow every
  * particle moves with its velocity and keeps its circulation).  Advances
@@ -244,33 +260,49 @@ fmm_status fmm_advance_rk2(fmm_plan_t plan, int64_t n, double* d_x, double* d_y,
  * (eqs. 13-15, see fmm_work_estimate), so the heaviest workgroups are
  * dispatched first; 0 keeps the input order.  Results are identical up to
  * the summation order (bit for bit for work_order).
- * fmm_set_tuning synchronises `stream`.  fmm_autotune times every
- * combination of p2p_waves in {2, 4}, m2l_split_max in {0, 5, 8} and, for a
- * mixed plan, m2l_mfma in {0, 1} on the caller's data (reps timed
- * evaluations each, after one warm-up; the output arrays are overwritten),
- * keeps the fastest and, when the environment variable FMM_AUTOTUNE_CACHE
- * names a file, looks the choice up there first and appends it after a
- * search.  For batched plans n is ignored. */
+ * fmm_set_tuning synchronises `stream`.  fmm_autotune times candidates from
+ * p2p_waves in {2, 4}, m2l_split_max in {0, 5, 8} and, for a mixed plan,
+ * m2l_mfma in {0, 1} on the caller's data (reps timed evaluations each,
+ * after one warm-up; the output arrays are overwritten) and keeps the
+ * fastest.  The search is seeded by the paper's work model (Section 5.2):
+ * the estimate of eqs. 13-15 is split into its near-field part (n_nd N_i^2
+ * and 2 N_i p per leaf) and its far-field part (p^2 (2 n_c + n_IL) per
+ * non-leaf box, p^2 n_IL per leaf); starting from the current shape, the
+ * knobs of the larger part (near field: p2p_waves; far field: the M2L
+ * knobs) are searched first, those of the smaller part only when it holds at
+ * least 10 % of the estimate.  The environment variable
+ * FMM_AUTOTUNE_EXHAUSTIVE=1 times the whole grid instead.  When
+ * FMM_AUTOTUNE_CACHE names a file, the choice is looked up there first and
+ * appended after a search.  For batched plans n is ignored and the instance set of the plan's
+ * last fmm_evaluate_batch call is timed (FMM_E_ARG before the first call). */
 fmm_status fmm_get_tuning(fmm_plan_t plan, int32_t* p2p_waves, int32_t* m2l_split_max, int32_t* m2l_mfma,
                           int32_t* work_order);
 fmm_status fmm_set_tuning(fmm_plan_t plan, int32_t p2p_waves, int32_t m2l_split_max, int32_t m2l_mfma,
                           int32_t work_order, void* stream);
 fmm_status fmm_autotune(fmm_plan_t plan, int64_t n, const double* d_x, const double* d_y,
                         const double* d_gamma, double* d_u, double* d_v, void* stream, int32_t reps);
+/* The plan's last fmm_autotune: the number of candidates it timed (0 when
+ * the choice came from the cache) and the near-field share of the work
+ * model's estimate that ordered the search.  Host only. */
+fmm_status fmm_autotune_report(fmm_plan_t plan, int32_t* candidates_timed, double* near_share);
 
 /* The paper's work model (Section 5.2) for every instance of the plan, in
  * input order: non-leaf boxes p^2 (2 n_c + n_IL) each (eq. 13), leaves
  * 2 N_i p + p^2 n_IL + n_nd N_i^2 each (eq. 14), summed over the tree of
  * depth L (eq. 15), with n_c = 4, n_IL = 27, n_nd = 9 and the mean leaf
- * occupancy N_i = N / 4^L (N = n_max for a single-instance plan).  Host only.
- * Writes min(n_out, instances) values; *n_written (may be NULL) gets that
- * count. */
+ * occupancy N_i = N / 4^L (N = n_max for a single-instance plan; for a
+ * batched plan the instances of its last fmm_evaluate_batch call, whose
+ * estimates the device computed for the launch order: the call waits for
+ * that call's stream).  Writes min(n_out, instances) values; *n_written (may
+ * be NULL) gets that count. */
 fmm_status fmm_work_estimate(fmm_plan_t plan, double* work, int32_t n_out, int32_t* n_written);
 
 /* Synchronises `stream` and reports the number of particles of the last
  * evaluation (with fmm_evaluate_at: particles and target points) that fell
  * outside the explicit domain or had a NaN coordinate.
- * Returns FMM_OK if there were none, FMM_E_DOMAIN otherwise. */
+ * Returns FMM_OK if there were none, FMM_E_DOMAIN otherwise; for a batched
+ * plan whose last call's instance set was rejected on the device,
+ * FMM_E_CAPACITY or FMM_E_ARG (with *n_bad = 0). */
 fmm_status fmm_get_status(fmm_plan_t plan, void* stream, int64_t* n_bad);
 
 /* Stage timing.  fmm_set_timing(plan, 1) clears the totals; every later

@@ -32,9 +32,8 @@ FMM_PREC_MIXED = 1
 DUMP_KEYS, DUMP_PERM, DUMP_LEAF_START, DUMP_ME, DUMP_LE, DUMP_DOMAIN, DUMP_ILIST = range(7)
 DUMP_TKEYS, DUMP_TPERM, DUMP_TLEAF_START = range(7, 10)
 
-EXPORTED = ["fmm_workspace_size", "fmm_plan", "fmm_evaluate", "fmm_evaluate_at", "fmm_workspace_size_batch",
-            "fmm_plan_batch", "fmm_evaluate_batch", "fmm_advance_rk2", "fmm_get_status", "fmm_set_timing", "fmm_stats", "fmm_stage_name",
-            "fmm_get_tuning", "fmm_set_tuning", "fmm_autotune", "fmm_work_estimate", "fmm_debug_dump", "fmm_destroy",
+EXPORTED = ["fmm_workspace_size", "fmm_plan", "fmm_evaluate", "fmm_evaluate_at", "fmm_evaluate_batch", "fmm_advance_rk2", "fmm_get_status", "fmm_set_timing", "fmm_stats", "fmm_stage_name",
+            "fmm_get_tuning", "fmm_set_tuning", "fmm_autotune", "fmm_autotune_report", "fmm_work_estimate", "fmm_debug_dump", "fmm_destroy",
             "fmm_status_string", "fmm3d_workspace_size", "fmm3d_plan", "fmm3d_evaluate", "fmm3d_get_status",
             "fmm3d_debug_dump", "fmm3d_destroy", "fmm_evaluate_static"]
 
@@ -56,7 +55,8 @@ class FmmParams(C.Structure):
     _fields_ = [("n_max", C.c_int64), ("sigma", C.c_double), ("p", C.c_int32), ("depth", C.c_int32),
                 ("x0", C.c_double), ("y0", C.c_double), ("width", C.c_double),
                 ("precision", C.c_int32), ("fp32_fine_levels", C.c_int32), ("m_max", C.c_int64),
-                ("kernel", C.c_int32), ("lj_epsilon", C.c_double), ("cutoff", C.c_double)]
+                ("kernel", C.c_int32), ("lj_epsilon", C.c_double), ("cutoff", C.c_double),
+                ("max_instances", C.c_int32), ("max_leaves", C.c_int64)]
 
 
 class FmmError(RuntimeError):
@@ -82,14 +82,13 @@ def load():
     lib.fmm_evaluate.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp]
     lib.fmm_evaluate_at.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_int64, vp, vp, vp, vp, vp]
     i32p = C.POINTER(C.c_int32)
-    lib.fmm_workspace_size_batch.argtypes = [C.POINTER(FmmParams), C.c_int32, i32p, i32p, C.POINTER(C.c_size_t)]
-    lib.fmm_plan_batch.argtypes = [C.POINTER(FmmParams), C.c_int32, i32p, i32p, vp, C.c_size_t, vp, C.POINTER(vp)]
-    lib.fmm_evaluate_batch.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.fmm_evaluate_batch.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.fmm_advance_rk2.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_double, C.c_int32, vp, vp]
     lib.fmm_get_tuning.argtypes = [vp, i32p, i32p, i32p, i32p]
     lib.fmm_set_tuning.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp]
     lib.fmm_work_estimate.argtypes = [vp, C.POINTER(C.c_double), C.c_int32, i32p]
     lib.fmm_autotune.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp, C.c_int32]
+    lib.fmm_autotune_report.argtypes = [vp, i32p, C.POINTER(C.c_double)]
     lib.fmm_get_status.argtypes = [vp, vp, C.POINTER(C.c_int64)]
     lib.fmm_set_timing.argtypes = [vp, C.c_int32]
     lib.fmm_stats.argtypes = [vp, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32),
@@ -120,7 +119,7 @@ def status_string(s: int) -> str:
 
 
 def make_params(n_max, sigma, p, depth, domain=(0.0, 0.0, 1.0), precision="fp64", fp32_fine_levels=2, m_max=0,
-                kernel="gaussian", lj_epsilon=0.0, cutoff=0.0):
+                kernel="gaussian", lj_epsilon=0.0, cutoff=0.0, max_instances=0, max_leaves=0):
     if domain is None:
         x0, y0, w = 0.0, 0.0, 0.0
     else:
@@ -128,7 +127,7 @@ def make_params(n_max, sigma, p, depth, domain=(0.0, 0.0, 1.0), precision="fp64"
     prec = {"fp64": FMM_PREC_FP64, "mixed": FMM_PREC_MIXED}[precision]
     return FmmParams(int(n_max), float(sigma), int(p), int(depth), float(x0), float(y0), float(w), prec,
                      int(fp32_fine_levels if precision == "mixed" else 0), int(m_max), KERNELS[kernel],
-                     float(lj_epsilon), float(cutoff))
+                     float(lj_epsilon), float(cutoff), int(max_instances), int(max_leaves))
 
 
 def workspace_size(prm: FmmParams) -> int:
@@ -136,22 +135,6 @@ def workspace_size(prm: FmmParams) -> int:
     s = load().fmm_workspace_size(C.byref(prm), C.byref(out))
     if s != FMM_OK:
         raise FmmError(s, "fmm_workspace_size")
-    return int(out.value)
-
-
-def _i32_array(vals):
-    arr = (C.c_int32 * len(vals))(*[int(v) for v in vals])
-    return arr
-
-
-def workspace_size_batch(prm: FmmParams, counts, depths) -> int:
-    if len(counts) != len(depths):
-        raise ValueError("counts and depths differ in length")
-    out = C.c_size_t(0)
-    s = load().fmm_workspace_size_batch(C.byref(prm), len(counts), _i32_array(counts), _i32_array(depths),
-                                        C.byref(out))
-    if s != FMM_OK:
-        raise FmmError(s, "fmm_workspace_size_batch")
     return int(out.value)
 
 
@@ -242,6 +225,14 @@ class _PlanBase:
                                   _stream_handle())
         if s != FMM_OK:
             raise FmmError(s, "fmm_set_tuning")
+
+    def autotune_report(self) -> dict:
+        """Candidates the last autotune timed, and the work model's near-field share."""
+        t, sh = C.c_int32(0), C.c_double(0.0)
+        s = load().fmm_autotune_report(self._h, C.byref(t), C.byref(sh))
+        if s != FMM_OK:
+            raise FmmError(s, "fmm_autotune_report")
+        return {"candidates_timed": int(t.value), "near_share": float(sh.value)}
 
     def work_estimate(self) -> np.ndarray:
         """The paper's work model (eqs. 13-15) per instance, in input order."""
@@ -401,38 +392,59 @@ class Plan(_PlanBase):
 
 
 class BatchPlan(_PlanBase):
-    """Many independent FMM problems evaluated together (one graph replay).
+    """Many independent FMM problems evaluated together (fmm_evaluate_batch:
+    the instance table on the device, one table kernel and one graph replay).
 
     ``counts[i]`` particles of instance i follow those of instances 0..i-1
     in the concatenated input arrays; instance i uses tree depth
     ``depths[i]``.  All instances share ``sigma``, ``p``, the precision, the
     near-field ``kernel`` and the explicit square ``domain`` = (x0, y0, width).
+    The plan holds capacities only -- ``n_max`` particles, ``max_instances``
+    instances, trees no deeper than ``max_depth``, ``max_leaves`` leaf boxes
+    in total (by default those of the first instance set) -- and every
+    ``evaluate`` may bring another instance set (``counts``, ``depths``).
     """
 
     def __init__(self, counts, depths, sigma, p, domain=(0.0, 0.0, 1.0), precision="fp64",
-                 fp32_fine_levels=2, device="cuda", kernel="gaussian", lj_epsilon=0.0, cutoff=0.0):
+                 fp32_fine_levels=2, device="cuda", kernel="gaussian", lj_epsilon=0.0, cutoff=0.0,
+                 n_max=None, max_instances=None, max_depth=None, max_leaves=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the FMM runs only on the GPU")
         if domain is None:
             raise ValueError("a batched plan needs an explicit square domain")
+        counts = [int(c) for c in counts]
+        depths = [int(d) for d in depths]
+        self.p = int(p)
+        self.precision = precision
+        self.device = torch.device(device)
+        self.n_max = int(n_max) if n_max is not None else sum(counts)
+        self.max_instances = int(max_instances) if max_instances is not None else len(counts)
+        self.max_depth = int(max_depth) if max_depth is not None else max(depths)
+        self.max_leaves = int(max_leaves) if max_leaves is not None else sum(4 ** d for d in depths)
+        self.params = make_params(self.n_max, sigma, p, self.max_depth, domain, precision, fp32_fine_levels,
+                                  kernel=kernel, lj_epsilon=lj_epsilon, cutoff=cutoff,
+                                  max_instances=max(2, self.max_instances), max_leaves=self.max_leaves)
+        self._alloc_workspace(workspace_size(self.params))
+        handle = C.c_void_p()
+        s = load().fmm_plan(C.byref(self.params), C.c_void_p(self._ws_ptr), C.c_size_t(self._ws_bytes),
+                            _stream_handle(), C.byref(handle))
+        if s != FMM_OK:
+            raise FmmError(s, "fmm_plan")
+        self._h = handle
+        self.set_instances(counts, depths)
+
+    def set_instances(self, counts, depths):
+        """The instance set of the following evaluations (uploaded to the device)."""
+        import torch
+        if len(counts) != len(depths) or not 1 <= len(counts) <= max(2, self.max_instances):
+            raise ValueError("counts and depths: 1 .. max_instances instances of equal length")
         self.counts = [int(c) for c in counts]
         self.depths = [int(d) for d in depths]
         self.n = sum(self.counts)
-        self.p = int(p)
-        self.precision = precision
-        self.params = make_params(self.n, sigma, p, max(self.depths), domain, precision, fp32_fine_levels,
-                                  kernel=kernel, lj_epsilon=lj_epsilon, cutoff=cutoff)
-        self.device = torch.device(device)
-        self._alloc_workspace(workspace_size_batch(self.params, self.counts, self.depths))
-        handle = C.c_void_p()
-        s = load().fmm_plan_batch(C.byref(self.params), len(self.counts), _i32_array(self.counts),
-                                  _i32_array(self.depths), C.c_void_p(self._ws_ptr), C.c_size_t(self._ws_bytes),
-                                  _stream_handle(), C.byref(handle))
-        if s != FMM_OK:
-            raise FmmError(s, "fmm_plan_batch")
-        self._h = handle
         self.offsets = np.concatenate([[0], np.cumsum(self.counts)]).astype(np.int64)
+        self._d_offsets = torch.as_tensor(self.offsets, device=self.device)
+        self._d_depths = torch.as_tensor(np.asarray(self.depths, np.int32), device=self.device)
 
     def _outputs(self, u, v):
         import torch
@@ -442,24 +454,56 @@ class BatchPlan(_PlanBase):
             v = torch.empty(self.n, dtype=torch.float64, device=self.device)
         return u, v
 
-    def evaluate(self, x, y, gamma, u=None, v=None, check=True):
-        """Velocities of every instance, concatenated like the inputs."""
+    def evaluate(self, x, y, gamma, u=None, v=None, check=True, counts=None, depths=None):
+        """Velocities of every instance, concatenated like the inputs; with
+        counts and depths, of that instance set (kept for later calls)."""
+        if counts is not None or depths is not None:
+            self.set_instances(counts, depths)
         u, v = self._outputs(u, v)
         _check_inputs(self.n, (x, y, gamma, u, v))
-        s = load().fmm_evaluate_batch(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
-                                      C.c_void_p(gamma.data_ptr()), C.c_void_p(u.data_ptr()),
-                                      C.c_void_p(v.data_ptr()), _stream_handle())
+        return self.evaluate_csr(len(self.counts), self._d_offsets, self._d_depths, x, y, gamma, u, v, check)
+
+    def evaluate_csr(self, n_inst, d_offsets, d_depths, x, y, gamma, u, v, check=True):
+        """fmm_evaluate_batch with a caller's device instance table: int64
+        offsets [n_inst + 1] and int32 depths [n_inst] (device tensors)."""
+        import torch
+        if d_offsets.dtype != torch.int64 or d_depths.dtype != torch.int32:
+            raise ValueError("offsets must be int64 and depths int32 device tensors")
+        s = load().fmm_evaluate_batch(self._h, int(n_inst), C.c_void_p(d_offsets.data_ptr()),
+                                      C.c_void_p(d_depths.data_ptr()), C.c_void_p(x.data_ptr()),
+                                      C.c_void_p(y.data_ptr()), C.c_void_p(gamma.data_ptr()),
+                                      C.c_void_p(u.data_ptr()), C.c_void_p(v.data_ptr()), _stream_handle())
         if s != FMM_OK:
             raise FmmError(s, "fmm_evaluate_batch")
         if check:
-            nbad = self.out_of_domain()
-            if nbad:
-                raise FmmError(FMM_E_DOMAIN, f"fmm_evaluate_batch: {nbad} particles outside the domain")
+            self.check_status()
         return u, v
 
+    def check_status(self):
+        """Raise if the last call's instance set was rejected or had particles
+        outside the square (synchronises)."""
+        out = C.c_int64(0)
+        s = load().fmm_get_status(self._h, _stream_handle(), C.byref(out))
+        if s == FMM_E_DOMAIN:
+            raise FmmError(s, f"fmm_evaluate_batch: {int(out.value)} particles outside the domain")
+        if s != FMM_OK:
+            raise FmmError(s, "fmm_evaluate_batch")
+
+    def dump(self, what: int) -> np.ndarray:
+        """As for a single plan; KEYS and PERM cut to the current instances'
+        particles, LEAF_START to their segments."""
+        out = super().dump(what)
+        if what in (DUMP_KEYS, DUMP_PERM):
+            return out[:self.n]
+        if what == DUMP_LEAF_START:
+            return out[:sum(4 ** d + 1 for d in self.depths)]
+        return out
+
     def autotune(self, x, y, gamma, u=None, v=None, reps=3) -> dict:
+        """Time the launch-shape candidates on the current instance set."""
         u, v = self._outputs(u, v)
         _check_inputs(self.n, (x, y, gamma, u, v))
+        self.evaluate(x, y, gamma, u, v, check=False)      # the set the tuner re-times
         s = load().fmm_autotune(self._h, self.n, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
                                 C.c_void_p(gamma.data_ptr()), C.c_void_p(u.data_ptr()),
                                 C.c_void_p(v.data_ptr()), _stream_handle(), int(reps))

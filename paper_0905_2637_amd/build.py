@@ -21,7 +21,7 @@ EXAMPLE_SRC = os.path.join(HERE, "examples", "fmm_eval_file.cpp")
 EXAMPLE = os.path.join(HERE, "fmm_eval_file")
 
 SOURCES = ["fmm_api.cpp", "fmm_tables.cpp", "fmm_tree.hip", "fmm_upward.hip", "fmm_downward.hip",
-           "fmm_near.hip", "fmm_step.hip", "fmm_fgt.hip", "fmm3d.hip", "fmm3d_api.cpp", "fmm_static.hip"]
+           "fmm_near.hip", "fmm_step.hip", "fmm_fgt.hip", "fmm3d.hip", "fmm3d_api.cpp", "fmm_static.hip", "fmm_batch.hip"]
 
 ARCH = os.environ.get("FMM_OFFLOAD_ARCH", "gfx950")
 

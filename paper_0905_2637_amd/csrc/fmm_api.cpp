@@ -46,26 +46,22 @@ struct Shape {
     std::vector<int64_t> leaf_off, box_off, split_off;
     std::vector<double> work;            // eq. 13-15 estimate per instance
     std::vector<int32_t> by_work;        // instances by decreasing estimate (stable)
+    // batched plans: the instance set arrives with every call, so the plan
+    // holds capacities (n_inst above is the instance capacity, leaf_entries,
+    // boxes and split_boxes the segment capacities) and no per-instance data
+    bool batched = false;
 };
-
-// Launches of one evaluation after the tree build: at most 4 upward groups,
-// 4 M2L (FP64 / FP32 x split / unsplit), 4 downward groups and the P2P.
-constexpr int kMaxLaunches = 16;
 
 // Gauss transform plans: at most 16 Hermite terms per axis and a box range of
 // at most 63 (the Hermite table of the range fits in a workgroup's LDS).
 constexpr int kFgtMaxP = 16;
 constexpr int kFgtMaxRange = 63;
 
-enum LaunchKind { L_UP, L_M2L, L_DOWN, L_P2P };
-
 struct Launch {
-    LaunchKind kind;
-    int nwg;
+    LaunchDesc desc;
+    int nwg;         // workgroups (batched plans: the capacity bound)
     int table;       // its work table
-    bool fp32;       // M2L
-    int groups;      // M2L: 2 or 3 with the list split, else 1
-    bool leaves;     // upward: the first group, from the particles
+    int groups;      // M2L: 3 or 2 with the list split, else 1
 };
 
 int ceil_log2(int64_t v)
@@ -76,38 +72,6 @@ int ceil_log2(int64_t v)
 }
 
 int table_ints(int n_inst) { return 4 * n_inst + 1; }   // wg_begin [n+1], arg [2n], order [n]
-
-int split_level(int L, int split_max) { return (L <= 2 || split_max < 2) ? 1 : std::min(L, split_max); }
-
-// Split M2L levels: FP32 levels split each list over three wavefronts; the
-// FP64 levels of an instance over two when they have at least this many
-// workgroup tiles, else three (few tiles are bound by one wavefront's serial
-// work).  Decided per instance, so that a batched evaluation computes every
-// instance exactly as a single one does.  Measured on 1M-64M particle trees.
-constexpr int kM2LFewTiles = 256;
-
-// The paper's work model (Section 5.2): a non-leaf box costs p^2 (2 n_c +
-// n_IL) (eq. 13), a leaf 2 N_i p + p^2 n_IL + n_nd N_i^2 (eq. 14), and a tree
-// the sum over its boxes (eq. 15, read for the whole tree of depth L: levels
-// 0 .. L-1 non-leaf, 4^L leaves).  N_i is the mean occupancy N / 4^L; n_c =
-// 4, n_IL = 27 (Table 1), n_nd = 9 (the leaf and its 8 neighbours).
-double work_estimate(int64_t n, int L, int p)
-{
-    const double pp = double(p) * p;
-    const double nc = 4.0, nil = 27.0, nnd = 9.0;
-    double nonleaf = 0.0;
-    for (int l = 0; l < L; ++l) nonleaf += std::ldexp(1.0, 2 * l) * pp * (2.0 * nc + nil);
-    const double leaves = std::ldexp(1.0, 2 * L);
-    const double ni = double(n) / leaves;
-    return nonleaf + leaves * (2.0 * ni * p + pp * nil + nnd * ni * ni);
-}
-
-int level_blocks_host(int l)
-{
-    const int side = 1 << l;
-    const int bpr = side >= 16 ? side / 16 : 1;
-    return bpr * bpr;
-}
 
 fmm_status validate_common(const fmm_params* prm)
 {
@@ -139,6 +103,7 @@ fmm_status validate_common(const fmm_params* prm)
         if (prm->fp32_fine_levels < 0 || prm->fp32_fine_levels > kMaxDepth) return FMM_E_ARG;
         if (prm->p > kMaxPMixed) return FMM_E_UNSUPPORTED;
     }
+    if (prm->max_instances < 0) return FMM_E_ARG;
     return FMM_OK;
 }
 
@@ -202,26 +167,31 @@ fmm_status single_shape(const fmm_params* prm, Shape& sh)
     return finish_shape(sh);
 }
 
-fmm_status batch_shape(const fmm_params* prm, int32_t n_inst, const int32_t* counts, const int32_t* depths,
-                       Shape& sh)
+// A batched plan: capacities only (the instance set arrives with every call).
+fmm_status batch_shape(const fmm_params* prm, Shape& sh, int64_t& max_leaves)
 {
-    if (n_inst < 1 || n_inst > kMaxInstances || !counts || !depths) return FMM_E_ARG;
+    const int M = prm->max_instances;
+    if (M < 2 || M > kMaxInstances) return FMM_E_ARG;
+    if (prm->n_max < 0 || prm->n_max > int64_t(0x7fffffff)) return FMM_E_ARG;
+    if (prm->depth < 0 || prm->depth > kMaxDepth || prm->max_leaves < 0) return FMM_E_ARG;
     if (!(prm->width > 0.0)) return FMM_E_UNSUPPORTED;   // batched instances need the explicit square
     if (prm->m_max != 0) return FMM_E_ARG;                 // target points: single plans only
     if (prm->kernel == FMM_KERNEL_GAUSS_TRANSFORM) return FMM_E_UNSUPPORTED;
-    sh.n_inst = n_inst;
-    sh.depth.assign(depths, depths + n_inst);
-    sh.part_off.resize(n_inst);
-    int64_t tot = 0;
-    for (int i = 0; i < n_inst; ++i) {
-        if (counts[i] < 0 || depths[i] < 0 || depths[i] > kMaxDepth) return FMM_E_ARG;
-        sh.part_off[i] = tot;
-        tot += counts[i];
-    }
-    if (tot > int64_t(0x7fffffff)) return FMM_E_ARG;
-    sh.n_cap = tot;
-    if (!cutoff_fits(prm, *std::max_element(depths, depths + n_inst))) return FMM_E_UNSUPPORTED;
-    return finish_shape(sh);
+    if (!cutoff_fits(prm, prm->depth)) return FMM_E_UNSUPPORTED;
+    max_leaves = prm->max_leaves > 0 ? prm->max_leaves : int64_t(M) << (2 * prm->depth);
+    sh.batched = true;
+    sh.n_inst = M;
+    sh.n_cap = prm->n_max;
+    sh.Lmax = prm->depth;
+    sh.key_bits = ceil_log2(M) + 2 * sh.Lmax;
+    if (sh.key_bits > 32) return FMM_E_UNSUPPORTED;
+    // sum over instances of (4^L + 1) leaf entries, and of Lambda(L) = (4 4^L - 1) / 3 boxes
+    sh.leaf_entries = max_leaves + M;
+    sh.boxes = (4 * max_leaves + 2) / 3;
+    sh.split_boxes = sh.boxes;
+    // workgroup numbers of a launch are int32
+    if (sh.boxes > int64_t(0x3fffffff) || sh.leaf_entries > int64_t(0x7fffffff)) return FMM_E_UNSUPPORTED;
+    return FMM_OK;
 }
 
 struct Layout {
@@ -230,6 +200,7 @@ struct Layout {
     size_t tkey, tks, tperm, txs, tys, tleaf_start, tbad;
     size_t fgt_a, fgt_b, fgt_h;
     size_t t_m2m, t_l2l, t_h64, t_h32, t_sin, t_sout;
+    size_t counts, status, work, order;
     size_t total;
 };
 
@@ -288,6 +259,11 @@ Layout make_layout(const Shape& sh, int P, bool mixed)
     const size_t parts = fgt ? size_t(fgt_parts(P, sh.depth[0], sh.fgt_nc)) : 0;
     ly.fgt_b = take(sizeof(double) * parts * fgt_boxes * P * P);
     ly.fgt_h = take(fgt ? sizeof(double) * size_t(2 * sh.fgt_nc + 1) * (2 * P - 1) : 0);
+    // batched plans: what the table kernel reports of a call
+    ly.counts = take(sizeof(int32_t) * 2);
+    ly.status = take(sizeof(int32_t));
+    ly.work = take(sh.batched ? sizeof(double) * size_t(sh.n_inst) : 0);
+    ly.order = take(sh.batched ? sizeof(int32_t) * size_t(sh.n_inst) : 0);
     ly.total = off;
     return ly;
 }
@@ -314,6 +290,17 @@ struct fmm_plan_s {
     std::vector<int32_t> g64;            // per instance: wavefronts per list on its split FP64 M2L levels
     int32_t* d_tables;
     Buffers buf;
+    // batched plans: capacities and the device outputs of the table kernel
+    int64_t max_leaves;
+    int32_t* d_counts;                   // [2] particles and leaf entries of the last call
+    int32_t* d_status;                   // the last call's instance set: FMM_OK or why it was rejected
+    double* d_work;                      // [max_inst] work estimates of the last call's instances
+    int32_t* d_order;                    // [max_inst] their launch order
+    int32_t last_inst;                   // instance set of the last call (autotuning re-times it)
+    int32_t tune_timed;                  // the last autotuning: candidates timed
+    double tune_near_share;              // and the work model's near-field share that ordered them
+    const int64_t* last_offsets;
+    const int32_t* last_depths;
     int64_t last_n;
     int64_t last_m;                      // target points of the last evaluation (0: none)
     hipStream_t last_stream;             // stream of the last evaluation (inspection waits on it)
@@ -413,118 +400,91 @@ hipError_t capture(fmm_plan_s* pl, F&& enqueue, hipGraph_t* graph, hipGraphExec_
     return hipSuccess;
 }
 
-// Launch list and work tables for the current tuning.  Workgroups of a launch
-// are numbered instance after instance; an instance without work in a launch
-// gets an empty range.
+SchedCfg sched_cfg(const fmm_plan_s* pl)
+{
+    return SchedCfg{pl->mixed ? 1 : 0, pl->prm.fp32_fine_levels, pl->tune.split_max, pl->tune.p2p_waves};
+}
+
+// The fixed launch list for trees no deeper than Lmax: upward groups, the
+// four M2L launches (FP64 / FP32 levels x split / unsplit), downward groups,
+// the near field.
+std::vector<LaunchDesc> launch_list(int Lmax, bool mixed)
+{
+    std::vector<LaunchDesc> v;
+    for (int g = 0; g < sched_up_groups(Lmax); ++g) v.push_back(LaunchDesc{L_UP, g, 0, 0});
+    for (int fp32 = 0; fp32 < (mixed ? 2 : 1); ++fp32)
+        for (int part = 0; part < 2; ++part) v.push_back(LaunchDesc{L_M2L, 0, fp32, part});
+    for (int g = 0; g < sched_down_groups(Lmax); ++g) v.push_back(LaunchDesc{L_DOWN, g, 0, 0});
+    v.push_back(LaunchDesc{L_P2P, 0, 0, 0});
+    return v;
+}
+
+// Workgroups a launch can need over any instance set that fits a batched
+// plan: with c = max over depths L <= Lmax of (wg(L) - b 4^L), b = wg(Lmax) /
+// 4^Lmax, every instance needs at most c + b 4^L, so a set needs at most
+// n_inst c + b sum 4^L <= max_inst c + b max_leaves.
+int64_t capacity_bound(const SchedCfg& cfg, const LaunchDesc& d, int Lmax, int max_inst, int64_t max_leaves)
+{
+    int wg, a0, a1;
+    sched_inst(cfg, d, Lmax, wg, a0, a1);
+    const double b = double(wg) / std::ldexp(1.0, 2 * Lmax);
+    double c = 0.0;
+    for (int L = 0; L <= Lmax; ++L) {
+        sched_inst(cfg, d, L, wg, a0, a1);
+        c = std::max(c, double(wg) - b * std::ldexp(1.0, 2 * L));
+    }
+    return int64_t(std::ceil(double(max_inst) * c + b * double(max_leaves)));
+}
+
+// Launch list and, for single plans, the work tables for the current
+// tuning.  Workgroups of a launch are numbered instance after instance (in
+// the launch order); an instance without work in a launch gets an empty
+// range.  Single plans keep only the launches with work and size them
+// exactly; batched plans keep the whole list, sized for their capacities,
+// and get their tables from the device at every call.
 void build_schedule(fmm_plan_s* pl)
 {
     const Shape& sh = pl->shape;
     const int n = sh.n_inst;
     const int ti = table_ints(n);
+    const SchedCfg cfg = sched_cfg(pl);
     pl->launches.clear();
     pl->host_tables.assign(size_t(kMaxLaunches) * ti, 0);
-    std::vector<int32_t> wg(n), arg(2 * n);
+    const std::vector<LaunchDesc> list = launch_list(sh.Lmax, pl->mixed);
+    if (sh.batched) {
+        // launches no instance that fits can use are left out
+        for (const LaunchDesc& d : list) {
+            const int64_t bound = capacity_bound(cfg, d, sh.Lmax, n, pl->max_leaves);
+            if (bound <= 0) continue;
+            const int groups = d.kind == L_M2L && d.part == 0 ? 3 : 1;
+            pl->launches.push_back(Launch{d, int(bound), int(pl->launches.size()), groups});
+        }
+        return;
+    }
     // launch order of the instances: by decreasing estimated work, or as given
     std::vector<int32_t> ord(n);
     for (int k = 0; k < n; ++k) ord[k] = pl->tune.work_order ? sh.by_work[k] : k;
     pl->part1_levels.assign(n, 0);
     pl->g64.assign(n, 2);
-    auto add = [&](LaunchKind kind, bool fp32, int groups, bool leaves) {
+    for (int i = 0; i < n; ++i) sched_m2l_groups(cfg, sh.depth[i], pl->g64[i], pl->part1_levels[i]);
+    for (const LaunchDesc& d : list) {
         const int t = int(pl->launches.size());
         int32_t* tb = pl->host_tables.data() + size_t(t) * ti;
         tb[0] = 0;
+        int groups = 1;
         for (int k = 0; k < n; ++k) {
             const int i = ord[k];
-            tb[k + 1] = tb[k] + wg[i];
-            tb[n + 1 + 2 * k] = arg[2 * i];
-            tb[n + 2 + 2 * k] = arg[2 * i + 1];
+            int wg, a0, a1;
+            sched_inst(cfg, d, sh.depth[i], wg, a0, a1);
+            tb[k + 1] = tb[k] + wg;
+            tb[n + 1 + 2 * k] = a0;
+            tb[n + 2 + 2 * k] = a1;
             tb[3 * n + 1 + k] = i;
+            if (d.kind == L_M2L && d.part == 0 && wg > 0)
+                groups = std::max(groups, d.fp32 ? 3 : pl->g64[i]);
         }
-        if (tb[n] > 0) pl->launches.push_back(Launch{kind, tb[n], t, fp32, groups, leaves});
-    };
-    auto clear = [&]() {
-        std::fill(wg.begin(), wg.end(), 0);
-        std::fill(arg.begin(), arg.end(), 0);
-    };
-
-    // upward: groups of up to three M2M levels, leaves (P2M) first, to level 2
-    for (int g = 0;; ++g) {
-        clear();
-        bool any = false;
-        for (int i = 0; i < n; ++i) {
-            const int L = sh.depth[i];
-            if (L < 2) continue;
-            int lb = L, lt = std::max(2, L - 3), k = 0;
-            while (k < g && lt > 2) { lb = lt; lt = std::max(2, lb - 3); ++k; }
-            if (k < g) continue;                       // fewer groups for this instance
-            wg[i] = int(int64_t(1) << (2 * lt));
-            arg[2 * i] = lt;
-            arg[2 * i + 1] = lb - lt;
-            any = true;
-        }
-        if (!any) break;
-        add(L_UP, false, 1, g == 0);
+        if (tb[n] > 0) pl->launches.push_back(Launch{d, tb[n], t, groups});
     }
-    // M2L: levels [2, f32) in FP64 and [f32, L] in FP32; levels <= the split
-    // level with the interaction list split over two or three wavefronts
-    for (int prec = 0; prec < 2; ++prec)
-        for (int part = 0; part < 2; ++part) {
-            clear();
-            for (int i = 0; i < n; ++i) {
-                const int L = sh.depth[i];
-                if (L < 2) continue;
-                const int fine = pl->mixed ? pl->prm.fp32_fine_levels : 0;
-                const int f32 = std::max(2, L - fine + 1);
-                const int lo = prec == 0 ? 2 : f32, hi = prec == 0 ? f32 - 1 : L;
-                const int sl = split_level(L, pl->tune.split_max);
-                const int a = part == 0 ? lo : std::max(lo, sl + 1);
-                const int b = part == 0 ? std::min(hi, sl) : hi;
-                if (b < a) continue;
-                int cnt = 0;
-                for (int l = a; l <= b; ++l) cnt += level_blocks_host(l);
-                wg[i] = cnt;
-                arg[2 * i] = a;
-                arg[2 * i + 1] = b;
-            }
-            int groups = 1;
-            if (part == 0)
-                for (int i = 0; i < n; ++i) {
-                    if (wg[i] == 0) continue;
-                    const int gi = (prec == 1 || wg[i] < kM2LFewTiles) ? 3 : 2;
-                    if (prec == 0) pl->g64[i] = gi;
-                    groups = std::max(groups, gi);
-                    if (gi == 3)
-                        for (int l = arg[2 * i]; l <= arg[2 * i + 1]; ++l) pl->part1_levels[i] |= 1 << l;
-                }
-            add(L_M2L, prec == 1, groups, false);
-        }
-    // downward: L2L in groups of up to three levels from level 2, the
-    // remainder of (L - 2) / 3 first, so that the large launches near the
-    // leaves cover three full levels
-    for (int g = 0;; ++g) {
-        clear();
-        bool any = false;
-        for (int i = 0; i < n; ++i) {
-            const int L = sh.depth[i];
-            if (L < 3) continue;
-            const int r = (L - 2) % 3;
-            const int lt = g == 0 ? 2 : 2 + (r ? r : 3) + 3 * (g - 1);
-            if (lt >= L) continue;
-            wg[i] = int(int64_t(1) << (2 * lt));
-            arg[2 * i] = lt;
-            arg[2 * i + 1] = g == 0 && r ? r : 3;
-            any = true;
-        }
-        if (!any) break;
-        add(L_DOWN, false, 1, false);
-    }
-    // near field and L2P: p2p_waves leaves per workgroup
-    clear();
-    for (int i = 0; i < n; ++i) {
-        const int64_t nleaf = int64_t(1) << (2 * sh.depth[i]);
-        wg[i] = int((nleaf + pl->tune.p2p_waves - 1) / pl->tune.p2p_waves);
-    }
-    add(L_P2P, false, 1, false);
 }
 
 std::vector<Inst> build_inst(const fmm_plan_s* pl)
@@ -538,7 +498,7 @@ std::vector<Inst> build_inst(const fmm_plan_s* pl)
         I.box_off = sh.box_off[i];
         I.split_off = sh.split_off[i];
         I.L = sh.depth[i];
-        I.split = split_level(I.L, pl->tune.split_max);
+        I.split = sched_split_level(I.L, pl->tune.split_max);
         I.part1 = pl->part1_levels[i];
         I.g64 = pl->g64[i];
         if (pl->auto_domain)   // the bounding square is written on the device by every evaluation
@@ -552,6 +512,8 @@ std::vector<Inst> build_inst(const fmm_plan_s* pl)
 hipError_t upload_schedule(fmm_plan_s* pl, hipStream_t st)
 {
     build_schedule(pl);
+    drop_graph(pl);
+    if (pl->shape.batched) return hipSuccess;   // tables come from the device at every call
     std::vector<Inst> iv = build_inst(pl);
     hipError_t e = hipSuccess;
     if (pl->auto_domain && pl->last_n > 0) {
@@ -565,7 +527,6 @@ hipError_t upload_schedule(fmm_plan_s* pl, hipStream_t st)
         e = hipMemcpyAsync(pl->d_tables, pl->host_tables.data(), pl->host_tables.size() * sizeof(int32_t),
                            hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);   // the host vectors go out of scope
-    drop_graph(pl);
     return e;
 }
 
@@ -592,7 +553,9 @@ hipError_t enqueue_all(fmm_plan_s* pl, int64_t n, const double* x, const double*
 
     mark(ST_TREE);
     if (pl->auto_domain) chk(launch_domain(b, int(n), x, y, pl->shape.depth[0], st, int(m), tx, ty));
-    chk(launch_tree(b, int(n), x, y, g, pl->shape.key_bits, pl->shape.leaf_entries, pl->mixed, st));
+    // batched plans: n and the leaf entries are capacities; the call's counts are on the device
+    chk(launch_tree(b, int(n), x, y, g, pl->shape.key_bits, pl->shape.leaf_entries, pl->mixed, st,
+                    pl->shape.batched ? pl->d_counts : nullptr));
     if (m > 0) chk(launch_tree_points(b, int(m), tx, ty, pl->shape.key_bits, pl->shape.leaf_entries, st));
     if (pl->shape.fgt_nc >= 0) {   // Gauss transform: Hermite, Hermite to Taylor, Taylor evaluation
         mark(ST_UP);
@@ -603,13 +566,16 @@ hipError_t enqueue_all(fmm_plan_s* pl, int64_t n, const double* x, const double*
     }
     int stage = ST_TREE;
     for (const Launch& ln : pl->launches) {
-        const int want = ln.kind == L_UP ? ST_UP : ln.kind == L_M2L ? ST_M2L : ln.kind == L_DOWN ? ST_DOWN : ST_P2P;
+        const int kind = ln.desc.kind;
+        const int want = kind == L_UP ? ST_UP : kind == L_M2L ? ST_M2L : kind == L_DOWN ? ST_DOWN : ST_P2P;
         while (stage < want) mark(++stage);
         const Work w = work_of(pl, ln);
-        if (!far && ln.kind != L_P2P) continue;
-        switch (ln.kind) {
-            case L_UP: chk(launch_upward(b, P, p, w, ln.nwg, ln.leaves, st)); break;
-            case L_M2L: chk(launch_m2l(b, P, w, ln.nwg, ln.fp32, pl->tune.m2l_mfma != 0, ln.groups, st)); break;
+        if (!far && kind != L_P2P) continue;
+        switch (kind) {
+            case L_UP: chk(launch_upward(b, P, p, w, ln.nwg, ln.desc.group == 0, st)); break;
+            case L_M2L:
+                chk(launch_m2l(b, P, w, ln.nwg, ln.desc.fp32 != 0, pl->tune.m2l_mfma != 0, ln.groups, st));
+                break;
             case L_DOWN: chk(launch_downward(b, P, w, ln.nwg, st)); break;
             case L_P2P:
                 if (m > 0)
@@ -628,7 +594,7 @@ void rank_by_work(Shape& sh, int p)
     sh.work.resize(sh.n_inst);
     for (int i = 0; i < sh.n_inst; ++i) {
         const int64_t end = i + 1 < sh.n_inst ? sh.part_off[i + 1] : sh.n_cap;
-        sh.work[i] = work_estimate(end - sh.part_off[i], sh.depth[i], p);
+        sh.work[i] = sched_work(end - sh.part_off[i], sh.depth[i], p);
     }
     sh.by_work.resize(sh.n_inst);
     for (int i = 0; i < sh.n_inst; ++i) sh.by_work[i] = i;
@@ -637,9 +603,9 @@ void rank_by_work(Shape& sh, int p)
 }
 
 fmm_status make_plan(const fmm_params* prm, Shape&& sh, bool batch, void* d_workspace, size_t bytes, void* stream,
-                     fmm_plan_t* out, bool events = true)
+                     fmm_plan_t* out, bool events = true, int64_t max_leaves = 0)
 {
-    rank_by_work(sh, prm->p);
+    if (!sh.batched) rank_by_work(sh, prm->p);
     if ((reinterpret_cast<uintptr_t>(d_workspace) & 255) != 0) return FMM_E_ARG;
     const int P = instantiated_terms(prm->p);
     const bool mixed = prm->precision == FMM_PREC_MIXED;
@@ -696,6 +662,12 @@ fmm_status make_plan(const fmm_params* prm, Shape&& sh, bool batch, void* d_work
     b.le_part[1] = reinterpret_cast<cd*>(base + ly.le_part[1]);
     pl->dump_scratch = base + ly.ktmp;
     pl->dump_scratch_bytes = ly.tkey - ly.ktmp;
+    pl->max_leaves = max_leaves;
+    pl->d_counts = reinterpret_cast<int32_t*>(base + ly.counts);
+    pl->d_status = reinterpret_cast<int32_t*>(base + ly.status);
+    pl->d_work = reinterpret_cast<double*>(base + ly.work);
+    pl->d_order = reinterpret_cast<int32_t*>(base + ly.order);
+    pl->last_inst = 0;
     b.t_m2m = reinterpret_cast<cd*>(base + ly.t_m2m);
     b.t_l2l = reinterpret_cast<cd*>(base + ly.t_l2l);
     b.t_h64 = reinterpret_cast<cd*>(base + ly.t_h64);
@@ -753,7 +725,9 @@ fmm_status make_plan(const fmm_params* prm, Shape&& sh, bool batch, void* d_work
 fmm_status run_once(fmm_plan_s* pl, int64_t n, const double* x, const double* y, const double* g, double* u,
                     double* v, void* stream)
 {
-    return pl->batch ? fmm_evaluate_batch(pl, x, y, g, u, v, stream) : fmm_evaluate(pl, n, x, y, g, u, v, stream);
+    if (pl->batch)   // the instance set of the plan's last call
+        return fmm_evaluate_batch(pl, pl->last_inst, pl->last_offsets, pl->last_depths, x, y, g, u, v, stream);
+    return fmm_evaluate(pl, n, x, y, g, u, v, stream);
 }
 
 }  // namespace
@@ -805,20 +779,8 @@ fmm_status fmm_workspace_size(const fmm_params* prm, size_t* bytes)
     fmm_status s = validate_common(prm);
     if (s != FMM_OK) return s;
     Shape sh;
-    s = single_shape(prm, sh);
-    if (s != FMM_OK) return s;
-    *bytes = make_layout(sh, instantiated_terms(prm->p), prm->precision == FMM_PREC_MIXED).total;
-    return FMM_OK;
-}
-
-fmm_status fmm_workspace_size_batch(const fmm_params* prm, int32_t n_inst, const int32_t* counts,
-                                    const int32_t* depths, size_t* bytes)
-{
-    if (!bytes) return FMM_E_ARG;
-    fmm_status s = validate_common(prm);
-    if (s != FMM_OK) return s;
-    Shape sh;
-    s = batch_shape(prm, n_inst, counts, depths, sh);
+    int64_t max_leaves = 0;
+    s = prm->max_instances > 1 ? batch_shape(prm, sh, max_leaves) : single_shape(prm, sh);
     if (s != FMM_OK) return s;
     *bytes = make_layout(sh, instantiated_terms(prm->p), prm->precision == FMM_PREC_MIXED).total;
     return FMM_OK;
@@ -831,22 +793,15 @@ fmm_status fmm_plan(const fmm_params* prm, void* d_workspace, size_t bytes, void
     fmm_status s = validate_common(prm);
     if (s != FMM_OK) return s;
     Shape sh;
+    if (prm->max_instances > 1) {
+        int64_t max_leaves = 0;
+        s = batch_shape(prm, sh, max_leaves);
+        if (s != FMM_OK) return s;
+        return make_plan(prm, std::move(sh), true, d_workspace, bytes, stream, out, true, max_leaves);
+    }
     s = single_shape(prm, sh);
     if (s != FMM_OK) return s;
     return make_plan(prm, std::move(sh), false, d_workspace, bytes, stream, out);
-}
-
-fmm_status fmm_plan_batch(const fmm_params* prm, int32_t n_inst, const int32_t* counts, const int32_t* depths,
-                          void* d_workspace, size_t bytes, void* stream, fmm_plan_t* out)
-{
-    if (!out || !d_workspace) return FMM_E_ARG;
-    *out = nullptr;
-    fmm_status s = validate_common(prm);
-    if (s != FMM_OK) return s;
-    Shape sh;
-    s = batch_shape(prm, n_inst, counts, depths, sh);
-    if (s != FMM_OK) return s;
-    return make_plan(prm, std::move(sh), true, d_workspace, bytes, stream, out);
 }
 
 fmm_status fmm_set_timing(fmm_plan_t plan, int32_t on)
@@ -917,19 +872,47 @@ fmm_status fmm_evaluate_at(fmm_plan_t plan, int64_t n, const double* d_x, const 
     return e == hipSuccess ? FMM_OK : FMM_E_DEVICE;
 }
 
-fmm_status fmm_evaluate_batch(fmm_plan_t plan, const double* d_x, const double* d_y, const double* d_gamma,
-                              double* d_u, double* d_v, void* stream)
+fmm_status fmm_evaluate_batch(fmm_plan_t plan, int32_t n_inst, const int64_t* d_offsets, const int32_t* d_depths,
+                              const double* d_x, const double* d_y, const double* d_gamma, double* d_u, double* d_v,
+                              void* stream)
 {
     if (!plan || !plan->batch) return FMM_E_ARG;
-    const int64_t n = plan->shape.n_cap;
-    if (n > 0 && (!d_x || !d_y || !d_gamma || !d_u || !d_v)) return FMM_E_ARG;
+    if (n_inst < 1 || n_inst > plan->shape.n_inst) return FMM_E_ARG;
+    if (!d_offsets || !d_depths || !d_x || !d_y || !d_gamma || !d_u || !d_v) return FMM_E_ARG;
+    const int64_t n = plan->shape.n_cap;   // capacity: the grids are sized for it
+    hipStream_t st = static_cast<hipStream_t>(stream);
     plan->last_n = n;
     plan->last_m = 0;
-    plan->last_stream = static_cast<hipStream_t>(stream);
-    if (n == 0) return FMM_OK;
+    plan->last_stream = st;
+    plan->last_inst = n_inst;
+    plan->last_offsets = d_offsets;
+    plan->last_depths = d_depths;
+    // the call's instance table -> the plan's work tables, on the device
+    BatchSched bs{};
+    bs.n_inst = n_inst;
+    bs.offsets = d_offsets;
+    bs.depths = d_depths;
+    bs.max_inst = plan->shape.n_inst;
+    bs.n_max = n;
+    bs.leaf_cap = plan->shape.leaf_entries;
+    bs.box_cap = plan->shape.boxes;
+    bs.split_cap = plan->shape.split_boxes;
+    bs.depth_max = plan->shape.Lmax;
+    bs.p = plan->prm.p;
+    bs.work_order = plan->tune.work_order;
+    bs.dom = Domain{plan->prm.x0, plan->prm.y0, plan->prm.width, 0.0};
+    bs.cfg = sched_cfg(plan);
+    bs.n_launch = int(plan->launches.size());
+    for (int t = 0; t < bs.n_launch; ++t) bs.launch[t] = plan->launches[size_t(t)].desc;
+    bs.inst = plan->buf.inst;
+    bs.tables = plan->d_tables;
+    bs.counts = plan->d_counts;
+    bs.status = plan->d_status;
+    bs.work = plan->d_work;
+    bs.order = plan->d_order;
+    if (launch_batch_schedule(bs, st) != hipSuccess) return FMM_E_DEVICE;
     if (plan->timing) {
         // timed: enqueued eagerly with stage events, no graph
-        hipStream_t st = static_cast<hipStream_t>(stream);
         const int slot = int(plan->next_slot % kTimingRing);
         hipError_t e = harvest(plan, slot);
         plan->next_slot += 1;
@@ -941,7 +924,7 @@ fmm_status fmm_evaluate_batch(fmm_plan_t plan, const double* d_x, const double* 
     bool same = plan->gexec != nullptr;
     for (int i = 0; i < 5 && same; ++i) same = plan->gptr[i] == ptrs[i];
     if (!same) {
-        // capture the evaluation for these arrays on the plan's own stream
+        // capture the stage launches for these arrays on the plan's own stream
         if (plan->gexec) hipGraphExecDestroy(plan->gexec);
         if (plan->graph) hipGraphDestroy(plan->graph);
         plan->gexec = nullptr;
@@ -952,7 +935,7 @@ fmm_status fmm_evaluate_batch(fmm_plan_t plan, const double* d_x, const double* 
         if (e != hipSuccess) return FMM_E_DEVICE;
         for (int i = 0; i < 5; ++i) plan->gptr[i] = ptrs[i];
     }
-    return hipGraphLaunch(plan->gexec, static_cast<hipStream_t>(stream)) == hipSuccess ? FMM_OK : FMM_E_DEVICE;
+    return hipGraphLaunch(plan->gexec, st) == hipSuccess ? FMM_OK : FMM_E_DEVICE;
 }
 
 fmm_status fmm_advance_rk2(fmm_plan_t plan, int64_t n, double* d_x, double* d_y, const double* d_gamma, double dt,
@@ -1014,7 +997,12 @@ fmm_status fmm_get_status(fmm_plan_t plan, void* stream, int64_t* n_bad)
     if (tblk > 0 && hipMemcpyAsync(per.data() + nblk, plan->buf.tbad, tblk * sizeof(int32_t),
                                    hipMemcpyDeviceToHost, st) != hipSuccess)
         return FMM_E_DEVICE;
+    int32_t rejected = 0;
+    if (plan->batch &&
+        hipMemcpyAsync(&rejected, plan->d_status, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess)
+        return FMM_E_DEVICE;
     if (hipStreamSynchronize(st) != hipSuccess) return FMM_E_DEVICE;
+    if (rejected != 0) return fmm_status(rejected);   // the call's instance set computed nothing
     int64_t v = 0;
     for (int32_t c : per) v += c;
     *n_bad = v;
@@ -1066,6 +1054,17 @@ fmm_status fmm_set_tuning(fmm_plan_t plan, int32_t p2p_waves, int32_t m2l_split_
 fmm_status fmm_work_estimate(fmm_plan_t plan, double* work, int32_t n_out, int32_t* n_written)
 {
     if (!plan || (n_out > 0 && !work)) return FMM_E_ARG;
+    if (plan->batch) {   // computed on the device for the last call's instances
+        const int m = std::max(0, std::min<int>(n_out, plan->last_inst));
+        if (m > 0) {
+            if (hipMemcpyAsync(work, plan->d_work, size_t(m) * sizeof(double), hipMemcpyDeviceToHost,
+                               plan->last_stream) != hipSuccess ||
+                hipStreamSynchronize(plan->last_stream) != hipSuccess)
+                return FMM_E_DEVICE;
+        }
+        if (n_written) *n_written = m;
+        return FMM_OK;
+    }
     const int m = std::min<int>(n_out, plan->shape.n_inst);
     for (int i = 0; i < m; ++i) work[i] = plan->shape.work[i];
     if (n_written) *n_written = m;
@@ -1076,17 +1075,34 @@ fmm_status fmm_autotune(fmm_plan_t plan, int64_t n, const double* d_x, const dou
                         double* d_u, double* d_v, void* stream, int32_t reps)
 {
     if (!plan) return FMM_E_ARG;
-    if (plan->batch) n = plan->shape.n_cap;
-    if (n <= 0 || n > plan->shape.n_cap) return FMM_E_ARG;
     if (!d_x || !d_y || !d_gamma || !d_u || !d_v) return FMM_E_ARG;
     if (reps < 1) reps = 3;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    std::vector<int32_t> depths = plan->shape.depth;
+    std::vector<int64_t> offs = {0, n};
+    if (plan->batch) {
+        // the instance set of the last call: its particle count, offsets and depths
+        if (plan->last_inst < 1) return FMM_E_ARG;
+        int32_t cnt[2] = {0, 0};
+        depths.resize(size_t(plan->last_inst));
+        offs.resize(size_t(plan->last_inst) + 1);
+        if (hipStreamSynchronize(plan->last_stream) != hipSuccess ||
+            hipMemcpy(cnt, plan->d_counts, sizeof(cnt), hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(depths.data(), plan->last_depths, depths.size() * sizeof(int32_t), hipMemcpyDeviceToHost) !=
+                hipSuccess ||
+            hipMemcpy(offs.data(), plan->last_offsets, offs.size() * sizeof(int64_t), hipMemcpyDeviceToHost) !=
+                hipSuccess)
+            return FMM_E_DEVICE;
+        n = cnt[0];
+        if (n <= 0) return FMM_E_ARG;   // rejected or empty instance set
+    }
+    if (n <= 0 || n > plan->shape.n_cap) return FMM_E_ARG;
 
     // signature of the problem: compiled size, precision, n and the depth mix
     char sig[512];
     {
         int64_t hist[kMaxDepth + 1] = {0};
-        for (int L : plan->shape.depth) hist[L]++;
+        for (int L : depths) hist[std::min(std::max(L, 0), kMaxDepth)]++;
         std::string d;
         for (int L = 0; L <= kMaxDepth; ++L)
             if (hist[L]) d += std::to_string(L) + "x" + std::to_string(hist[L]) + ",";
@@ -1102,7 +1118,10 @@ fmm_status fmm_autotune(fmm_plan_t plan, int64_t n, const double* d_x, const dou
             while (std::fscanf(f, "%511s %d %d %d", key, &w, &sm, &mf) == 4)
                 if (std::strcmp(key, sig) == 0) found = true;   // the last entry wins
             std::fclose(f);
-            if (found) return fmm_set_tuning(plan, w, sm, mf, plan->tune.work_order, stream);
+            if (found) {
+                plan->tune_timed = 0;
+                return fmm_set_tuning(plan, w, sm, mf, plan->tune.work_order, stream);
+            }
         }
     }
 
@@ -1122,30 +1141,77 @@ fmm_status fmm_autotune(fmm_plan_t plan, int64_t n, const double* d_x, const dou
     float best = 1e30f;
     Tuning best_t = saved;
     fmm_status rs = FMM_OK;
-    for (int mi = 0; mi < n_mfma && rs == FMM_OK; ++mi)
-        for (int wi = 0; wi < 2 && rs == FMM_OK; ++wi)
-            for (int si = 0; si < 3 && rs == FMM_OK; ++si) {
-                rs = fmm_set_tuning(plan, waves[wi], splits[si], n_mfma == 2 ? mi : saved.m2l_mfma, saved.work_order,
-                                    stream);
-                if (rs == FMM_OK) rs = run_once(plan, n, d_x, d_y, d_gamma, d_u, d_v, stream);   // warm-up, capture
-                float tmin = 1e30f;
-                for (int r = 0; r < reps && rs == FMM_OK; ++r) {
-                    if (hipEventRecord(e0, st) != hipSuccess) { rs = FMM_E_DEVICE; break; }
-                    rs = run_once(plan, n, d_x, d_y, d_gamma, d_u, d_v, stream);
-                    if (rs != FMM_OK) break;
-                    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-                        rs = FMM_E_DEVICE;
-                        break;
-                    }
-                    float ms = 0.f;
-                    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rs = FMM_E_DEVICE; break; }
-                    tmin = std::min(tmin, ms);
-                }
-                if (rs == FMM_OK && tmin < best) {
-                    best = tmin;
-                    best_t = plan->tune;
-                }
+    int timed = 0;
+    auto time_one = [&](int w, int sm, int mf) {
+        if (rs != FMM_OK) return;
+        rs = fmm_set_tuning(plan, w, sm, mf, saved.work_order, stream);
+        if (rs == FMM_OK) rs = run_once(plan, n, d_x, d_y, d_gamma, d_u, d_v, stream);   // warm-up, capture
+        float tmin = 1e30f;
+        for (int r = 0; r < reps && rs == FMM_OK; ++r) {
+            if (hipEventRecord(e0, st) != hipSuccess) { rs = FMM_E_DEVICE; break; }
+            rs = run_once(plan, n, d_x, d_y, d_gamma, d_u, d_v, stream);
+            if (rs != FMM_OK) break;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                rs = FMM_E_DEVICE;
+                break;
             }
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rs = FMM_E_DEVICE; break; }
+            tmin = std::min(tmin, ms);
+        }
+        ++timed;
+        if (rs == FMM_OK && tmin < best) {
+            best = tmin;
+            best_t = plan->tune;
+        }
+    };
+    // The paper's work model (Section 5.2) splits each instance's estimate
+    // into the near field (n_nd N_i^2 per leaf, eq. 14, with 2 N_i p for
+    // P2M/L2P) and the far field (p^2 (2 n_c + n_IL) per non-leaf box, eq.
+    // 13, and p^2 n_IL per leaf): the launch shapes of the larger part are
+    // searched first, those of the other part only if it holds at least
+    // kTuneMinShare of the estimate.  FMM_AUTOTUNE_EXHAUSTIVE=1 times the
+    // whole grid instead.
+    double near = 0.0, far = 0.0;
+    for (size_t i = 0; i < depths.size(); ++i) {
+        const int L = std::min(std::max(int(depths[i]), 0), kMaxDepth);
+        const double leaves = std::ldexp(1.0, 2 * L), pp = double(plan->prm.p) * plan->prm.p;
+        const double ni = double(offs[i + 1] - offs[i]) / leaves;
+        near += leaves * (9.0 * ni * ni + 2.0 * ni * plan->prm.p);
+        far += (leaves - 1.0) / 3.0 * pp * 35.0 + (L >= 2 ? leaves * pp * 27.0 : 0.0);
+    }
+    const double near_share = near + far > 0.0 ? near / (near + far) : 1.0;
+    const char* ex = std::getenv("FMM_AUTOTUNE_EXHAUSTIVE");
+    if (ex && std::atoi(ex) == 1) {
+        for (int mi = 0; mi < n_mfma; ++mi)
+            for (int wi = 0; wi < 2; ++wi)
+                for (int si = 0; si < 3; ++si) time_one(waves[wi], splits[si], n_mfma == 2 ? mi : saved.m2l_mfma);
+    } else {
+        constexpr double kTuneMinShare = 0.1;
+        time_one(saved.p2p_waves, saved.split_max, saved.m2l_mfma);      // the current shape
+        auto near_group = [&]() {
+            const Tuning b = best_t;
+            for (int w : waves)
+                if (w != b.p2p_waves) time_one(w, b.split_max, b.m2l_mfma);
+        };
+        auto far_group = [&]() {
+            const Tuning b = best_t;
+            for (int mi = 0; mi < n_mfma; ++mi)
+                for (int sm : splits) {
+                    const int mf = n_mfma == 2 ? mi : b.m2l_mfma;
+                    if (sm != b.split_max || mf != b.m2l_mfma) time_one(b.p2p_waves, sm, mf);
+                }
+        };
+        if (near_share >= 0.5) {
+            near_group();
+            if (1.0 - near_share >= kTuneMinShare) far_group();
+        } else {
+            far_group();
+            if (near_share >= kTuneMinShare) near_group();
+        }
+    }
+    plan->tune_timed = timed;
+    plan->tune_near_share = near_share;
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     plan->timing = was_timing;
@@ -1162,6 +1228,14 @@ fmm_status fmm_autotune(fmm_plan_t plan, int64_t n, const double* d_x, const dou
         }
     }
     return rs;
+}
+
+fmm_status fmm_autotune_report(fmm_plan_t plan, int32_t* candidates_timed, double* near_share)
+{
+    if (!plan || !candidates_timed || !near_share) return FMM_E_ARG;
+    *candidates_timed = plan->tune_timed;
+    *near_share = plan->tune_near_share;
+    return FMM_OK;
 }
 
 fmm_status fmm_debug_dump(fmm_plan_t plan, int32_t what, void* host_buf, size_t bytes, size_t* needed)

@@ -65,14 +65,15 @@ k_m2l(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restrict__
     constexpr bool kF32 = std::is_same<T, float>::value;
     constexpr int NH = 2 * P - 1;
     __shared__ cplx<T> sH[kF32 ? kHankelGrid * kHankelGrid * NH : 1];
+    const int lin = xcd_runs(int(blockIdx.x + gridDim.x * blockIdx.y), int(gridDim.x * gridDim.y), kM2LXcdRun);
+    const int g = lin / int(gridDim.x), blk = lin % int(gridDim.x);
+    if (blk >= wk.wg_begin[n_inst]) return;                // past the launch's work (batched plans)
     const cplx<T>* Hs = H;
     if constexpr (kF32) {
         for (int e = threadIdx.x; e < kHankelGrid * kHankelGrid * NH; e += 256) sH[e] = H[e];
         __syncthreads();
         Hs = sH;
     }
-    const int lin = xcd_runs(int(blockIdx.x + gridDim.x * blockIdx.y), int(gridDim.x * gridDim.y), kM2LXcdRun);
-    const int g = lin / int(gridDim.x), blk = lin % int(gridDim.x);
     const int pos = find_inst(wk.wg_begin, n_inst, blk);   // place in the launch order
     const int q = wk.order[pos];
     // a split FP64 launch serves instances split two or three ways
@@ -225,6 +226,7 @@ k_m2l64_lds(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __rest
     __shared__ cd sA[kHalo * kHalo * P];
     const int lin = xcd_runs(int(blockIdx.x + gridDim.x * blockIdx.y), int(gridDim.x * gridDim.y), kM2LXcdRun);
     const int g = lin / int(gridDim.x), blk = lin % int(gridDim.x);
+    if (blk >= wk.wg_begin[n_inst]) return;                // past the launch's work (batched plans)
     const int pos = find_inst(wk.wg_begin, n_inst, blk);
     const int q = wk.order[pos];
     const int G = min(int(gridDim.y), inst[q].g64);
@@ -312,12 +314,13 @@ k_m2l_mfma(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restr
     constexpr int MT = (R2 + 15) / 16;         // output row tiles
     constexpr int KS = (R2 + 3) / 4;           // steps of 4 input terms
     __shared__ cplx<float> sH[kHankelGrid * kHankelGrid * NH];
-    for (int e = threadIdx.x; e < kHankelGrid * kHankelGrid * NH; e += 256) sH[e] = H[e];
-    __syncthreads();
-
     const int G = gridDim.y;
     const int lin = xcd_runs(int(blockIdx.x + gridDim.x * blockIdx.y), int(gridDim.x * gridDim.y), kM2LXcdRun);
     const int g = lin / int(gridDim.x), blk = lin % int(gridDim.x);
+    if (blk >= wk.wg_begin[n_inst]) return;                // past the launch's work (batched plans)
+    for (int e = threadIdx.x; e < kHankelGrid * kHankelGrid * NH; e += 256) sH[e] = H[e];
+    __syncthreads();
+
     const int pos = find_inst(wk.wg_begin, n_inst, blk);   // place in the launch order
     const int q = wk.order[pos];
     int bl = blk - wk.wg_begin[pos];
@@ -439,6 +442,7 @@ k_downward(Work wk, int n_inst, const Inst* __restrict__ inst, cd* __restrict__ 
     __shared__ cd sh[21 * P];            // levels lt, lt+1, lt+2 (1 + 4 + 16 boxes) at P (4^t - 1) / 3
     __shared__ cd sL[4 * P * P];
     const int tid = threadIdx.x;
+    if (int(blockIdx.x) >= wk.wg_begin[n_inst]) return;           // past the launch's work (batched plans)
     const int pos = find_inst(wk.wg_begin, n_inst, blockIdx.x);   // place in the launch order
     const int q = wk.order[pos];
     const int64_t root = blockIdx.x - wk.wg_begin[pos];

@@ -16,6 +16,7 @@
 #include <stdint.h>
 
 #include "../../include/fmm.h"
+#include "fmm_schedule.h"
 
 namespace fmm {
 
@@ -193,8 +194,11 @@ int64_t radix_blocks(int64_t n);
 // target points into inst[0].dom
 hipError_t launch_domain(const Buffers& b, int n, const double* x, const double* y, int L, hipStream_t st,
                          int m = 0, const double* tx = nullptr, const double* ty = nullptr);
+// n_dev (batched plans): the call's particle count and leaf entries on the
+// device; n and leaf_entries are then the capacities the grids are sized for
 hipError_t launch_tree(const Buffers& b, int n, const double* x, const double* y, const double* g,
-                       int key_bits, int64_t leaf_entries, bool mixed, hipStream_t st);
+                       int key_bits, int64_t leaf_entries, bool mixed, hipStream_t st,
+                       const int32_t* n_dev = nullptr);
 // the target points' keys, sort and leaf ranges (single instance)
 hipError_t launch_tree_points(const Buffers& b, int m, const double* tx, const double* ty, int key_bits,
                               int64_t leaf_entries, hipStream_t st);
@@ -227,6 +231,31 @@ hipError_t launch_zero2(int64_t n, double* a, double* b, hipStream_t st);
 // time stepping: (xo, yo) = (x, y) + c (u, v); xo, yo may alias x, y
 hipError_t launch_advance(int64_t n, const double* x, const double* y, const double* u, const double* v, double c,
                           double* xo, double* yo, hipStream_t st);
+
+// The instance table of a batched call, turned into the plan's work tables
+// on the device (fmm_batch.hip).
+struct BatchSched {
+    // the call
+    int n_inst;
+    const int64_t* offsets;       // [n_inst + 1]
+    const int32_t* depths;        // [n_inst]
+    // the plan
+    int max_inst;
+    int64_t n_max, leaf_cap, box_cap, split_cap;
+    int depth_max, p, work_order;
+    Domain dom;                   // the shared explicit square (s is set per depth)
+    SchedCfg cfg;
+    int n_launch;
+    LaunchDesc launch[kMaxLaunches];
+    // outputs
+    Inst* inst;                   // [max_inst]
+    int32_t* tables;              // [n_launch][4 max_inst + 1]
+    int32_t* counts;              // [2]: particles of the call, leaf entries (0 when rejected)
+    int32_t* status;              // FMM_OK or the rejection's status code
+    double* work;                 // [max_inst] work estimates, input order
+    int32_t* order;               // [max_inst] launch order
+};
+hipError_t launch_batch_schedule(const BatchSched& s, hipStream_t st);
 
 // ---- plans over a library-provided buffer ----------------------------------
 // a single-instance plan whose workspace is d_buffer (bytes, 256-byte aligned)

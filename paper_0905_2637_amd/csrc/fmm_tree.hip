@@ -210,14 +210,20 @@ template <int TPB>
 __global__ void __launch_bounds__(TPB)
 k_rhist_keys(int n, const double* __restrict__ x, const double* __restrict__ y, const Inst* __restrict__ inst,
              int n_inst, int key_shift, int nblk, uint32_t* __restrict__ key, int32_t* __restrict__ hist,
-             int32_t* __restrict__ bad_blk)
+             int32_t* __restrict__ bad_blk, const int32_t* __restrict__ n_dev)
 {
+    if (n_dev) n = *n_dev;       // batched plans: the call's particle count, from the device
     constexpr int kTileRounds = kRadixTile / TPB;
     __shared__ int h[kRadixBins];
     __shared__ int nbad;
+    const int64_t base = int64_t(blockIdx.x) * kRadixTile;
+    if (base >= n) {             // a tile past the call's particles: empty (no input read)
+        if (threadIdx.x < kRadixBins) hist[int64_t(threadIdx.x) * nblk + blockIdx.x] = 0;
+        if (threadIdx.x == 0) bad_blk[blockIdx.x] = 0;
+        return;
+    }
     if (threadIdx.x == 0) nbad = 0;
     if (threadIdx.x < kRadixBins) h[threadIdx.x] = 0;
-    const int64_t base = int64_t(blockIdx.x) * kRadixTile;
     int mybad = 0;
     // all coordinate loads first, then keys and counting
     double xv[kTileRounds], yv[kTileRounds];
@@ -271,12 +277,18 @@ __device__ __forceinline__ KeyLeaf key_leaf(uint32_t k, const Inst* __restrict__
 // Digit histogram of one tile, written digit-major: hist[d * nblk + block].
 template <int TPB>
 __global__ void __launch_bounds__(TPB)
-k_rhist(int n, const uint32_t* __restrict__ kin, int shift, int nblk, int32_t* __restrict__ hist)
+k_rhist(int n, const uint32_t* __restrict__ kin, int shift, int nblk, int32_t* __restrict__ hist,
+        const int32_t* __restrict__ n_dev)
 {
+    if (n_dev) n = *n_dev;
     constexpr int kTileRounds = kRadixTile / TPB;
     __shared__ int h[kRadixBins];
-    if (threadIdx.x < kRadixBins) h[threadIdx.x] = 0;
     const int64_t base = int64_t(blockIdx.x) * kRadixTile;
+    if (base >= n) {             // a tile past the call's particles: empty
+        if (threadIdx.x < kRadixBins) hist[int64_t(threadIdx.x) * nblk + blockIdx.x] = 0;
+        return;
+    }
+    if (threadIdx.x < kRadixBins) h[threadIdx.x] = 0;
     uint32_t kv[kTileRounds];
 #pragma unroll
     for (int r = 0; r < kTileRounds; ++r) {
@@ -326,8 +338,9 @@ __global__ void __launch_bounds__(TPB)
 k_rscatter(int n, const uint32_t* __restrict__ kin, const uint32_t* __restrict__ iin,
            const double* __restrict__ xin, const double* __restrict__ yin, const double* __restrict__ gin,
            int shift, int nblk, const int32_t* __restrict__ hist, const int32_t* __restrict__ offs, Records out,
-           float4* __restrict__ pk, const Inst* __restrict__ inst, int key_shift)
+           float4* __restrict__ pk, const Inst* __restrict__ inst, int key_shift, const int32_t* __restrict__ n_dev)
 {
+    if (n_dev) n = *n_dev;
     constexpr int kScatterThreads = TPB;
     constexpr int kScatterWaves = TPB / 64;
     constexpr int kPerThread = kRadixTile / TPB;
@@ -344,6 +357,7 @@ k_rscatter(int n, const uint32_t* __restrict__ kin, const uint32_t* __restrict__
     // in one L2 (whole lines go out) instead of leaving partial lines in two
     const int blk = nblk >= kScatterXcdMinTiles ? xcd_runs(int(blockIdx.x), nblk, kScatterXcdRun) : int(blockIdx.x);
     const int64_t tile = int64_t(blk) * kRadixTile;
+    if (tile >= n) return;       // a tile past the call's particles: nothing to move
     const int tile_n = int(min(int64_t(kRadixTile), int64_t(n) - tile));
     constexpr int kWaveKeys = kRadixTile / kScatterWaves;
 
@@ -534,15 +548,19 @@ constexpr int kBoundsRounds = 16;
 
 __global__ void __launch_bounds__(256)
 k_bounds(int n, int64_t entries, const uint32_t* __restrict__ ks, const Inst* __restrict__ inst, int n_inst,
-         int key_shift, int32_t* __restrict__ leaf_start)
+         int key_shift, int32_t* __restrict__ leaf_start, const int32_t* __restrict__ n_dev)
 {
+    if (n_dev) {                 // batched plans: particles and leaf entries of the call
+        n = n_dev[0];
+        entries = n_dev[1];
+    }
     const int64_t base = int64_t(blockIdx.x) * (256 * kBoundsRounds) + threadIdx.x;
     uint32_t kp[kBoundsRounds], kc[kBoundsRounds];      // keys of i - 1 and i
 #pragma unroll
     for (int r = 0; r < kBoundsRounds; ++r) {
         const int64_t i = base + int64_t(r) * 256;
-        const int64_t ip = i - 1 < 0 ? 0 : (i - 1 < n ? i - 1 : n - 1);
-        const int64_t ic = i < n ? i : n - 1;
+        const int64_t ip = i - 1 < 0 ? 0 : (i - 1 < n ? i - 1 : (n > 0 ? n - 1 : 0));
+        const int64_t ic = i < n ? i : (n > 0 ? n - 1 : 0);
         kp[r] = ks[ip];
         kc[r] = ks[ic];
     }
@@ -605,7 +623,7 @@ namespace {
 // when g != nullptr, gamma), final arrays in fin, leaf ranges in leaf_start.
 void sort_points(const Buffers& b, int n, const double* x, const double* y, const double* g, uint32_t* key,
                  int32_t* bad_blk, const Records& fin, float4* pk, int32_t* leaf_start, int key_bits,
-                 int64_t leaf_entries, hipStream_t st)
+                 int64_t leaf_entries, hipStream_t st, const int32_t* n_dev = nullptr)
 {
     const int nblk = int(radix_blocks(n));
     const int64_t m = int64_t(kRadixBins) * nblk;
@@ -613,10 +631,10 @@ void sort_points(const Buffers& b, int n, const double* x, const double* y, cons
     const bool wide = FMM_TREE_TPB == 1024 || (FMM_TREE_TPB == 0 && nblk <= kWideTilesMax);
     if (wide)
         hipLaunchKernelGGL(k_rhist_keys<1024>, dim3(nblk), dim3(1024), 0, st, n, x, y, b.inst, b.n_inst,
-                           b.key_shift, nblk, key, b.hist, bad_blk);
+                           b.key_shift, nblk, key, b.hist, bad_blk, n_dev);
     else
         hipLaunchKernelGGL(k_rhist_keys<256>, dim3(nblk), dim3(256), 0, st, n, x, y, b.inst, b.n_inst,
-                           b.key_shift, nblk, key, b.hist, bad_blk);
+                           b.key_shift, nblk, key, b.hist, bad_blk, n_dev);
     const int npass = radix_passes(key_bits);
     if (npass == 0) {
         hipLaunchKernelGGL(k_copy_one_leaf, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, x, y, g, fin, pk, b.inst);
@@ -629,17 +647,19 @@ void sort_points(const Buffers& b, int n, const double* x, const double* y, cons
             const Records& out = ((npass - 1 - pass) & 1) ? tmp : fin;
             const int shift = 8 * pass;
             if (pass > 0 && wide)
-                hipLaunchKernelGGL(k_rhist<1024>, dim3(nblk), dim3(1024), 0, st, n, kin, shift, nblk, b.hist);
+                hipLaunchKernelGGL(k_rhist<1024>, dim3(nblk), dim3(1024), 0, st, n, kin, shift, nblk, b.hist, n_dev);
             else if (pass > 0)
-                hipLaunchKernelGGL(k_rhist<256>, dim3(nblk), dim3(256), 0, st, n, kin, shift, nblk, b.hist);
+                hipLaunchKernelGGL(k_rhist<256>, dim3(nblk), dim3(256), 0, st, n, kin, shift, nblk, b.hist, n_dev);
             scan_table(b, m, st);
             const bool last = pass == npass - 1;
             if (wide)
                 hipLaunchKernelGGL(k_rscatter<1024>, dim3(nblk), dim3(1024), 0, st, n, kin, iin, xin, yin, gin,
-                                   shift, nblk, b.hist, b.hist_scan, out, last ? pk : nullptr, b.inst, b.key_shift);
+                                   shift, nblk, b.hist, b.hist_scan, out, last ? pk : nullptr, b.inst, b.key_shift,
+                                   n_dev);
             else
                 hipLaunchKernelGGL(k_rscatter<256>, dim3(nblk), dim3(256), 0, st, n, kin, iin, xin, yin, gin,
-                                   shift, nblk, b.hist, b.hist_scan, out, last ? pk : nullptr, b.inst, b.key_shift);
+                                   shift, nblk, b.hist, b.hist_scan, out, last ? pk : nullptr, b.inst, b.key_shift,
+                                   n_dev);
             kin = out.k;
             iin = out.idx;
             xin = out.x;
@@ -648,17 +668,17 @@ void sort_points(const Buffers& b, int n, const double* x, const double* y, cons
         }
     }
     hipLaunchKernelGGL(k_bounds, dim3(blocks_for(int64_t(n) + 1, 256 * kBoundsRounds)), dim3(256), 0, st, n,
-                       leaf_entries, fin.k, b.inst, b.n_inst, b.key_shift, leaf_start);
+                       leaf_entries, fin.k, b.inst, b.n_inst, b.key_shift, leaf_start, n_dev);
 }
 
 }  // namespace
 
 hipError_t launch_tree(const Buffers& b, int n, const double* x, const double* y, const double* g,
-                       int key_bits, int64_t leaf_entries, bool mixed, hipStream_t st)
+                       int key_bits, int64_t leaf_entries, bool mixed, hipStream_t st, const int32_t* n_dev)
 {
     const Records fin{b.ksorted, b.perm, b.xs, b.ys, b.gs};
     sort_points(b, n, x, y, g, b.key, b.bad_blk, fin, mixed ? b.pk : nullptr, b.leaf_start, key_bits,
-                leaf_entries, st);
+                leaf_entries, st, n_dev);
     return hipGetLastError();
 }
 
@@ -688,16 +708,16 @@ hipError_t launch_sort_keys(const Buffers& b, int n, const uint32_t* key, const 
         const Records& out = ((npass - 1 - pass) & 1) ? tmp : fin;
         const int shift = 8 * pass;
         if (wide)
-            hipLaunchKernelGGL(k_rhist<1024>, dim3(nblk), dim3(1024), 0, st, n, kin, shift, nblk, b.hist);
+            hipLaunchKernelGGL(k_rhist<1024>, dim3(nblk), dim3(1024), 0, st, n, kin, shift, nblk, b.hist, nullptr);
         else
-            hipLaunchKernelGGL(k_rhist<256>, dim3(nblk), dim3(256), 0, st, n, kin, shift, nblk, b.hist);
+            hipLaunchKernelGGL(k_rhist<256>, dim3(nblk), dim3(256), 0, st, n, kin, shift, nblk, b.hist, nullptr);
         scan_table(b, m, st);
         if (wide)
             hipLaunchKernelGGL(k_rscatter<1024>, dim3(nblk), dim3(1024), 0, st, n, kin, iin, xin, yin, gin, shift,
-                               nblk, b.hist, b.hist_scan, out, nullptr, nullptr, 0);
+                               nblk, b.hist, b.hist_scan, out, nullptr, nullptr, 0, nullptr);
         else
             hipLaunchKernelGGL(k_rscatter<256>, dim3(nblk), dim3(256), 0, st, n, kin, iin, xin, yin, gin, shift,
-                               nblk, b.hist, b.hist_scan, out, nullptr, nullptr, 0);
+                               nblk, b.hist, b.hist_scan, out, nullptr, nullptr, 0, nullptr);
         kin = out.k;
         iin = out.idx;
         xin = out.x;

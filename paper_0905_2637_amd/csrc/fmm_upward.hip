@@ -51,6 +51,7 @@ k_upward(Work wk, int n_inst, const Inst* __restrict__ inst, int p, int from_par
     __shared__ cd sh[64 * P + 1];        // the current level of the subtree (<= 64 boxes) + a junk slot
     __shared__ cd sM[4 * P * P];         // the four M2M matrices
     const int tid = threadIdx.x;
+    if (int(blockIdx.x) >= wk.wg_begin[n_inst]) return;           // past the launch's work (batched plans)
     const int pos = find_inst(wk.wg_begin, n_inst, blockIdx.x);   // place in the launch order
     const int q = wk.order[pos];
     const int64_t root = blockIdx.x - wk.wg_begin[pos];     // z-order index at level lt

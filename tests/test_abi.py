@@ -121,53 +121,53 @@ def test_no_cpu_fallback_without_device():
         fm.Plan(100, 0.01, 12, 3)
 
 
-def _ws_batch(counts, depths, **kw):
+def _ws_batch(n_max, max_instances, depth, max_leaves=0, **kw):
     base = dict(sigma=0.005, p=12)
     base.update(kw)
-    prm = fm.make_params(sum(counts) if counts else 0, base.pop("sigma"), base.pop("p"),
-                         max(depths) if depths else 0, **base)
+    prm = fm.make_params(n_max, base.pop("sigma"), base.pop("p"), depth, max_instances=max_instances,
+                         max_leaves=max_leaves, **base)
     out = C.c_size_t(0)
-    n = len(counts)
-    ca = (C.c_int32 * max(n, 1))(*counts) if n else None
-    da = (C.c_int32 * max(n, 1))(*depths) if n else None
-    return fm.load().fmm_workspace_size_batch(C.byref(prm), n, ca, da, C.byref(out)), out.value
+    return fm.load().fmm_workspace_size(C.byref(prm), C.byref(out)), out.value
 
 
-def test_batch_workspace_adds_up_instances(lib):
-    """A batch needs at least the expansion storage of every instance's full quadtree."""
-    s, b = _ws_batch([1000, 3000, 0], [3, 4, 2])
+def test_batch_workspace_follows_the_capacities(lib):
+    """A batched plan holds the expansions of max_leaves leaf boxes' trees:
+    sum Lambda(L_i) <= 4/3 sum 4^L_i boxes, for ME and LE; the default leaf
+    capacity is the worst case max_instances * 4^depth."""
+    leaves = 4 ** 3 + 4 ** 4 + 4 ** 2
+    s, b = _ws_batch(4000, 3, 4, max_leaves=leaves)
     assert s == fm.FMM_OK
     boxes = sum((4 ** (L + 1) - 1) // 3 for L in (3, 4, 2))
     assert b >= 2 * 16 * 12 * boxes
-    s1, b1 = _ws_batch([1000], [3])
-    assert s1 == fm.FMM_OK and b1 < b
+    s1, b1 = _ws_batch(4000, 3, 4)                  # default: 3 * 4^4 leaves
+    assert s1 == fm.FMM_OK and b1 > b
+    s2, b2 = _ws_batch(4000, 3, 4, max_leaves=4 ** 3)
+    assert s2 == fm.FMM_OK and b2 < b
 
 
-@pytest.mark.parametrize("counts,depths,kw,err", [
-    ([], [], {}, fm.FMM_E_ARG),                                    # no instance
-    ([10, -1], [2, 2], {}, fm.FMM_E_ARG),                          # negative count
-    ([10, 10], [2, 14], {}, fm.FMM_E_ARG),                         # depth beyond 13
-    ([10, 10], [2, 2], dict(domain=None), fm.FMM_E_UNSUPPORTED),   # no explicit square
-    ([1] * 70000, [2] * 70000, {}, fm.FMM_E_ARG),                  # more than 65536 instances
-    ([1] * 1024, [12] * 1024, {}, fm.FMM_E_UNSUPPORTED),           # 10 + 24 key bits
-    ([10], [2], dict(p=23, precision="mixed"), fm.FMM_E_UNSUPPORTED),
+@pytest.mark.parametrize("n_max,max_inst,depth,kw,err", [
+    (100, 2, 14, {}, fm.FMM_E_ARG),                                # depth beyond 13
+    (-1, 2, 3, {}, fm.FMM_E_ARG),                                  # negative capacity
+    (100, 2, 3, dict(max_leaves=-1), fm.FMM_E_ARG),
+    (100, 2, 3, dict(domain=None), fm.FMM_E_UNSUPPORTED),          # no explicit square
+    (100, 70000, 2, {}, fm.FMM_E_ARG),                             # more than 65536 instances
+    (100, 1024, 12, dict(max_leaves=1 << 20), fm.FMM_E_UNSUPPORTED),   # 10 + 24 key bits
+    (100, 4, 2, dict(p=23, precision="mixed"), fm.FMM_E_UNSUPPORTED),
+    (100, 4, 2, dict(m_max=10), fm.FMM_E_ARG),                     # target points: single plans only
+    (100, 4, 2, dict(kernel="gauss-transform", sigma=0.1), fm.FMM_E_UNSUPPORTED),
+    (100, -3, 2, {}, fm.FMM_E_ARG),
 ])
-def test_invalid_batches_rejected(lib, counts, depths, kw, err):
-    s, _ = _ws_batch(counts, depths, **kw)
+def test_invalid_batches_rejected(lib, n_max, max_inst, depth, kw, err):
+    s, _ = _ws_batch(n_max, max_inst, depth, **kw)
     assert s == err
 
 
 def test_batch_entry_points_reject_null(lib):
-    prm = fm.make_params(20, 0.01, 12, 2)
+    prm = fm.make_params(20, 0.01, 12, 2, max_instances=2)
     h = C.c_void_p()
-    cnt = (C.c_int32 * 2)(10, 10)
-    dep = (C.c_int32 * 2)(2, 2)
-    assert lib.fmm_plan_batch(C.byref(prm), 2, cnt, dep, None, 1 << 20, None, C.byref(h)) == fm.FMM_E_ARG
-    assert lib.fmm_plan_batch(C.byref(prm), 2, None, dep, C.c_void_p(256), 1 << 20, None,
-                              C.byref(h)) == fm.FMM_E_ARG
-    assert lib.fmm_plan_batch(C.byref(prm), 2, cnt, dep, C.c_void_p(1 << 20), 16, None,
-                              C.byref(h)) == fm.FMM_E_CAPACITY
-    assert lib.fmm_evaluate_batch(None, None, None, None, None, None, None) == fm.FMM_E_ARG
+    assert lib.fmm_plan(C.byref(prm), None, 1 << 20, None, C.byref(h)) == fm.FMM_E_ARG
+    assert lib.fmm_plan(C.byref(prm), C.c_void_p(1 << 20), 16, None, C.byref(h)) == fm.FMM_E_CAPACITY
+    assert lib.fmm_evaluate_batch(None, 1, None, None, None, None, None, None, None, None) == fm.FMM_E_ARG
     assert lib.fmm_set_tuning(None, 4, 8, 1, 1, None) == fm.FMM_E_ARG
     assert lib.fmm_work_estimate(None, None, 0, None) == fm.FMM_E_ARG
     assert lib.fmm_autotune(None, 10, None, None, None, None, None, None, 3) == fm.FMM_E_ARG

@@ -223,6 +223,36 @@ def test_autotune_and_cache(tmp_path, monkeypatch):
     plan2.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_autotune_seeded_by_the_work_model(precision, monkeypatch):
+    """The work model (eqs. 13-15) orders the search: the part of the
+    estimate that dominates is tuned first and a minor part is skipped, so
+    the seeded search times fewer candidates than the whole grid (6 in FP64,
+    12 in the mixed form) and its choice still gives the oracle's velocities."""
+    import torch
+    fm = _fm()
+    monkeypatch.delenv("FMM_AUTOTUNE_CACHE", raising=False)
+    wl = workloads.make("C1")
+    x, y, g = _dev(wl.x), _dev(wl.y), _dev(wl.gamma)
+    plan = fm.Plan(wl.n, wl.sigma, wl.p, 5, precision=precision)
+    monkeypatch.setenv("FMM_AUTOTUNE_EXHAUSTIVE", "1")
+    plan.autotune(x, y, g, reps=1)
+    full = plan.autotune_report()
+    assert full["candidates_timed"] == (12 if precision == "mixed" else 6)
+    monkeypatch.delenv("FMM_AUTOTUNE_EXHAUSTIVE")
+    t = plan.autotune(x, y, g, reps=1)
+    rep = plan.autotune_report()
+    assert 2 <= rep["candidates_timed"] < full["candidates_timed"]
+    # N = 4096 on 4^5 leaves (4 per leaf): the far field dominates the estimate
+    assert 0.0 < rep["near_share"] < 0.5
+    u, v = plan.evaluate(x, y, g)
+    torch.cuda.synchronize()
+    uo, vo = oracle.fmm(wl.x, wl.y, wl.gamma, wl.sigma, wl.p, 5)
+    tol = FP64_TOL if precision == "fp64" else 5e-7
+    assert oracle.rel_l2(u.cpu().numpy(), v.cpu().numpy(), uo, vo) < tol, t
+    plan.close()
+
+
 def test_c4_batch_sampled_against_single_and_direct():
     """The 512-instance workload at full size: a batched, autotuned graph
     replay; sampled instances equal their single evaluations bit for bit and
@@ -303,7 +333,8 @@ def test_work_order_leaves_results_unchanged(precision):
 
 
 def test_work_estimate_is_the_papers_model():
-    """eqs. 13-15 with n_c = 4, n_IL = 27, n_nd = 9: an empty tree of depth L
+    """eqs. 13-15 with n_c = 4, n_IL = 27, n_nd = 9 (computed on the device for
+    the call's instances): an empty tree of depth L
     costs (4^L - 1)/3 p^2 (2*4 + 27) + 4^L p^2 27, and particles add
     4^L (2 N_i p + 9 N_i^2) with N_i = N / 4^L."""
     fm = _fm()
@@ -311,6 +342,8 @@ def test_work_estimate_is_the_papers_model():
     depths = [3, 3, 5, 5, 2]
     p = 12
     bp = fm.BatchPlan(counts, depths, 0.004, p)
+    x, y, g, _ = _instances(counts, depths, 16)
+    bp.evaluate(_dev(x), _dev(y), _dev(g))       # the estimates are made on the device, per call
     w = bp.work_estimate()
     assert w.shape == (5,)
     for n, L, got in zip(counts, depths, w):

@@ -144,10 +144,8 @@ def test_fgt_unsupported_combinations():
     assert ws(p=17) == fm.FMM_E_UNSUPPORTED
     assert ws(sigma=0.3, L=9) == fm.FMM_E_UNSUPPORTED        # a range beyond 63 boxes
     assert ws(m_max=5) == fm.FMM_OK
-    prm = fm.make_params(100, 0.05, 12, 3, kernel="gauss-transform")
-    cnt = (C.c_int32 * 2)(50, 50)
-    dep = (C.c_int32 * 2)(3, 3)
-    assert lib.fmm_workspace_size_batch(C.byref(prm), 2, cnt, dep, C.byref(out)) == fm.FMM_E_UNSUPPORTED
+    prm = fm.make_params(100, 0.05, 12, 3, kernel="gauss-transform", max_instances=2)
+    assert lib.fmm_workspace_size(C.byref(prm), C.byref(out)) == fm.FMM_E_UNSUPPORTED
     x, y, q = (_dev(a) for a in workloads.uniform_square(100, 920))
     plan = fm.Plan(100, 0.05, 12, 3, kernel="gauss-transform")
     with pytest.raises(fm.FmmError) as ei:

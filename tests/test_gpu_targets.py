@@ -171,14 +171,12 @@ def test_empty_and_error_cases():
     plan.close()
     # batched plans take no points
     import ctypes as C
-    prm = fm.make_params(256, 0.01, 12, 3, m_max=10)
+    prm = fm.make_params(256, 0.01, 12, 3, m_max=10, max_instances=2)
     lib = fm.load()
-    cnt = (C.c_int32 * 2)(128, 128)
-    dep = (C.c_int32 * 2)(3, 3)
     out = C.c_size_t(0)
-    assert lib.fmm_workspace_size_batch(C.byref(prm), 2, cnt, dep, C.byref(out)) == fm.FMM_E_ARG
+    assert lib.fmm_workspace_size(C.byref(prm), C.byref(out)) == fm.FMM_E_ARG
     prm.m_max = 0
-    assert lib.fmm_workspace_size_batch(C.byref(prm), 2, cnt, dep, C.byref(out)) == fm.FMM_OK
+    assert lib.fmm_workspace_size(C.byref(prm), C.byref(out)) == fm.FMM_OK
 
 
 @pytest.mark.slow
