@@ -206,8 +206,23 @@ def run_batch(wl, args, dev, precision=None, autotune=True, work_order=1):
     depths = wl.depths.tolist()
     bp = fm.BatchPlan(counts, depths, wl.sigma, wl.p, domain=(wl.x0, wl.y0, wl.width), precision=precision,
                       fp32_fine_levels=wl.fp32_fine_levels)
+    tune_info = None
     if autotune:
-        bp.autotune(x, y, g, u, v, reps=2)
+        # the whole grid first (for comparison), then the search the work model seeds
+        os.environ["FMM_AUTOTUNE_EXHAUSTIVE"] = "1"
+        try:
+            full = bp.autotune(x, y, g, u, v, reps=2)
+            full_timed = bp.autotune_report()["candidates_timed"]
+        finally:
+            del os.environ["FMM_AUTOTUNE_EXHAUSTIVE"]
+        full_ms = timed(lambda: bp.evaluate(x, y, g, u, v, check=False), 10, 2) * 1e3
+        seeded = bp.autotune(x, y, g, u, v, reps=2)
+        rep = bp.autotune_report()
+        seeded_ms = timed(lambda: bp.evaluate(x, y, g, u, v, check=False), 10, 2) * 1e3
+        tune_info = {"seeded_choice": seeded, "seeded_candidates_timed": rep["candidates_timed"],
+                     "seeded_choice_ms": round(seeded_ms, 4), "work_model_near_share": rep["near_share"],
+                     "exhaustive_choice": full, "exhaustive_candidates_timed": full_timed,
+                     "exhaustive_choice_ms": round(full_ms, 4)}
     if work_order != 1:
         t = bp.tuning()
         t["work_order"] = work_order
@@ -235,9 +250,57 @@ def run_batch(wl, args, dev, precision=None, autotune=True, work_order=1):
     res = {"sec": sec, "stage_ms": stage_ms, "near_pairs": pn, "m2l_pairs": pm,
            "roofline": roofline_of(stage_ms, pn, pm, wl.p, "f64" if precision == "fp64" else "f32",
                                    f"{wl.name}_{precision}"),
-           "u": u, "v": v, "tuning": bp.tuning()}
+           "u": u, "v": v, "tuning": bp.tuning(), "autotune": tune_info}
     bp.close()
     return res
+
+
+def work_model_check(w4, args, dev, every=8):
+    """The paper's work model (Section 5.2, eqs. 13-15) against measured cost:
+    single FP64 evaluations of every `every`-th instance of the batched
+    workload, GPU time per stage (HIP events) against the model's terms --
+    eq. 15's whole-tree estimate for the total, its p^2 n_IL term (per box)
+    for M2L, its n_nd N_i^2 term (per leaf) for the near field -- with a
+    least-squares line t = a + b W and its R^2 for each."""
+    import torch
+    import paper_0905_2637_amd as fm
+    p, pp = w4.p, float(w4.p) ** 2
+    rows = []
+    for i in range(0, len(w4.depths), every):
+        a, b = int(w4.offsets[i]), int(w4.offsets[i + 1])
+        L = int(w4.depths[i])
+        x, y, g = (torch.as_tensor(arr[a:b], device=dev) for arr in (w4.x, w4.y, w4.gamma))
+        u, v = torch.empty_like(x), torch.empty_like(x)
+        plan = fm.Plan(b - a, w4.sigma, p, L, domain=(w4.x0, w4.y0, w4.width))
+        for _ in range(3):
+            plan.evaluate(x, y, g, u, v, check=False)
+        plan.set_timing(True)
+        for _ in range(5):
+            plan.evaluate(x, y, g, u, v, check=False)
+        st = plan.stats()
+        plan.close()
+        leaves = 4.0 ** L
+        ni = (b - a) / leaves
+        boxes = (4.0 ** (L + 1) - 1.0) / 3.0
+        rows.append({"n": b - a, "L": L,
+                     "total_ms": sum(vv for k, vv in st.items() if k != "evaluations"),
+                     "m2l_ms": st["m2l"], "p2p_ms": st["p2p_l2p"],
+                     "W": (leaves - 1.0) / 3.0 * pp * 35.0 + leaves * (2.0 * ni * p + pp * 27.0 + 9.0 * ni * ni),
+                     "W_m2l": pp * 27.0 * boxes, "W_p2p": 9.0 * ni * ni * leaves})
+
+    def fit(xs, ys):
+        xs, ys = np.asarray(xs), np.asarray(ys)
+        A = np.vstack([np.ones_like(xs), xs]).T
+        (a0, b0), *_ = np.linalg.lstsq(A, ys, rcond=None)
+        res = ys - (a0 + b0 * xs)
+        r2 = 1.0 - float(np.sum(res ** 2)) / float(np.sum((ys - ys.mean()) ** 2))
+        return {"intercept_ms": float(a0), "ms_per_unit": float(b0), "r2": r2}
+
+    return {"instances": len(rows), "every": every,
+            "total_vs_eq15": fit([r["W"] for r in rows], [r["total_ms"] for r in rows]),
+            "m2l_vs_p2_nIL_term": fit([r["W_m2l"] for r in rows], [r["m2l_ms"] for r in rows]),
+            "p2p_vs_nnd_Ni2_term": fit([r["W_p2p"] for r in rows], [r["p2p_ms"] for r in rows]),
+            "depths": sorted(set(r["L"] for r in rows))}
 
 
 def run_sequential_fp64(wl, args, dev):
@@ -534,7 +597,8 @@ def run_forms(wl, res, args, dev):
                         "speedup_fp64_batched_vs_sequential": seq / rb64["sec"],
                         "input_order_ms": round(rb_in_order["sec"] * 1e3, 4),
                         "work_order_speedup": rb_in_order["sec"] / rb["sec"],
-                        "tuning": rb["tuning"], "roofline": rb["roofline"]}
+                        "tuning": rb["tuning"], "autotune": rb["autotune"], "roofline": rb["roofline"],
+                        "work_model": work_model_check(w4, args, dev)}
     forms["_c4"] = (w4, (rb64["u"], rb64["v"]), (rb["u"], rb["v"]))
     if args.extra_forms:
         extra_forms(forms, args, dev)

@@ -253,32 +253,41 @@ fmm_status fmm_advance_rk2(fmm_plan_t plan, int64_t n, double* d_x, double* d_y,
  * 2 or 4 (default 4).  m2l_split_max: M2L levels <= min(L, m2l_split_max)
  * split each box's interaction list over two or three wavefronts (more
  * parallelism on levels with few boxes), 0 .. 8 (default 8; below 2: never).
- * m2l_mfma: 1 runs the FP32 M2L levels of the mixed form on the matrix
- * cores (MFMA), 0 (default) on the vector units; FP64 levels always use the
- * vector units.  work_order (batched plans): 1 (default) launches the
+ * m2l_mfma: 1 runs the FP32 M2L levels of the mixed form whose lists are not
+ * split (those above m2l_split_max) on the matrix cores (MFMA; the default
+ * of a mixed plan), 0 on the vector units; FP64 levels and split levels
+ * always use the vector units.  work_order (batched plans): 1 (default) launches the
  * instances of every stage in decreasing order of the paper's work estimate
  * (eqs. 13-15, see fmm_work_estimate), so the heaviest workgroups are
- * dispatched first; 0 keeps the input order.  Results are identical up to
- * the summation order (bit for bit for work_order).
+ * dispatched first; 0 keeps the input order.  p2p_block chooses how a
+ * near-field wavefront lays out a chunk of t target particles (t <= 64):
+ * R targets per lane, TG = ceil(t / R) lanes per target group and S source
+ * slices (S x TG <= 64 lanes); 0 (the default of a mixed plan) pads t to a
+ * power of two (R = 4 at 64 targets, 2 at 32, else 1), 1 (the default of an
+ * FP64 plan) keeps the most lanes on real pairs (largest t S / (64 R), the
+ * larger R on a tie).  Results are identical up
+ * to the summation order (bit for bit for work_order).
  * fmm_set_tuning synchronises `stream`.  fmm_autotune times candidates from
- * p2p_waves in {2, 4}, m2l_split_max in {0, 5, 8} and, for a mixed plan,
+ * p2p_waves in {2, 4} x p2p_block in {0, 1}, m2l_split_max in {0, 5, 8} and, for a mixed plan,
  * m2l_mfma in {0, 1} on the caller's data (reps timed evaluations each,
  * after one warm-up; the output arrays are overwritten) and keeps the
  * fastest.  The search is seeded by the paper's work model (Section 5.2):
  * the estimate of eqs. 13-15 is split into its near-field part (n_nd N_i^2
  * and 2 N_i p per leaf) and its far-field part (p^2 (2 n_c + n_IL) per
  * non-leaf box, p^2 n_IL per leaf); starting from the current shape, the
- * knobs of the larger part (near field: p2p_waves; far field: the M2L
+ * knobs of the larger part (near field: p2p_waves, p2p_block; far field: the M2L
  * knobs) are searched first, those of the smaller part only when it holds at
  * least 10 % of the estimate.  The environment variable
  * FMM_AUTOTUNE_EXHAUSTIVE=1 times the whole grid instead.  When
  * FMM_AUTOTUNE_CACHE names a file, the choice is looked up there first and
- * appended after a search.  For batched plans n is ignored and the instance set of the plan's
+ * appended after a search (one line per choice: the problem's signature,
+ * then p2p_waves, m2l_split_max, m2l_mfma and p2p_block; the last line with
+ * the signature wins).  For batched plans n is ignored and the instance set of the plan's
  * last fmm_evaluate_batch call is timed (FMM_E_ARG before the first call). */
 fmm_status fmm_get_tuning(fmm_plan_t plan, int32_t* p2p_waves, int32_t* m2l_split_max, int32_t* m2l_mfma,
-                          int32_t* work_order);
+                          int32_t* work_order, int32_t* p2p_block);
 fmm_status fmm_set_tuning(fmm_plan_t plan, int32_t p2p_waves, int32_t m2l_split_max, int32_t m2l_mfma,
-                          int32_t work_order, void* stream);
+                          int32_t work_order, int32_t p2p_block, void* stream);
 fmm_status fmm_autotune(fmm_plan_t plan, int64_t n, const double* d_x, const double* d_y,
                         const double* d_gamma, double* d_u, double* d_v, void* stream, int32_t reps);
 /* The plan's last fmm_autotune: the number of candidates it timed (0 when

@@ -84,8 +84,8 @@ def load():
     i32p = C.POINTER(C.c_int32)
     lib.fmm_evaluate_batch.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.fmm_advance_rk2.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_double, C.c_int32, vp, vp]
-    lib.fmm_get_tuning.argtypes = [vp, i32p, i32p, i32p, i32p]
-    lib.fmm_set_tuning.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp]
+    lib.fmm_get_tuning.argtypes = [vp, i32p, i32p, i32p, i32p, i32p]
+    lib.fmm_set_tuning.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp]
     lib.fmm_work_estimate.argtypes = [vp, C.POINTER(C.c_double), C.c_int32, i32p]
     lib.fmm_autotune.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp, C.c_int32]
     lib.fmm_autotune_report.argtypes = [vp, i32p, C.POINTER(C.c_double)]
@@ -213,16 +213,21 @@ class _PlanBase:
         return out
 
     def tuning(self) -> dict:
-        w, sm, mf, wo = C.c_int32(0), C.c_int32(0), C.c_int32(0), C.c_int32(0)
-        s = load().fmm_get_tuning(self._h, C.byref(w), C.byref(sm), C.byref(mf), C.byref(wo))
+        w, sm, mf, wo, bk = (C.c_int32(0) for _ in range(5))
+        s = load().fmm_get_tuning(self._h, C.byref(w), C.byref(sm), C.byref(mf), C.byref(wo), C.byref(bk))
         if s != FMM_OK:
             raise FmmError(s, "fmm_get_tuning")
         return {"p2p_waves": int(w.value), "m2l_split_max": int(sm.value), "m2l_mfma": int(mf.value),
-                "work_order": int(wo.value)}
+                "work_order": int(wo.value), "p2p_block": int(bk.value)}
 
-    def set_tuning(self, p2p_waves=4, m2l_split_max=8, m2l_mfma=0, work_order=1):
-        s = load().fmm_set_tuning(self._h, int(p2p_waves), int(m2l_split_max), int(m2l_mfma), int(work_order),
-                                  _stream_handle())
+    def set_tuning(self, p2p_waves=None, m2l_split_max=None, m2l_mfma=None, work_order=None, p2p_block=None):
+        """Sets the given launch-shape knobs; those left None keep their value."""
+        t = self.tuning()
+        given = dict(p2p_waves=p2p_waves, m2l_split_max=m2l_split_max, m2l_mfma=m2l_mfma, work_order=work_order,
+                     p2p_block=p2p_block)
+        t.update({k: int(v) for k, v in given.items() if v is not None})
+        s = load().fmm_set_tuning(self._h, t["p2p_waves"], t["m2l_split_max"], t["m2l_mfma"], t["work_order"],
+                                  t["p2p_block"], _stream_handle())
         if s != FMM_OK:
             raise FmmError(s, "fmm_set_tuning")
 

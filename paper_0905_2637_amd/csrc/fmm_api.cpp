@@ -26,8 +26,9 @@ size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 struct Tuning {
     int p2p_waves = 4;                   // leaves (wavefronts) per P2P workgroup: 2 or 4
     int split_max = kM2LSplitMaxLevel;   // M2L list split on levels <= this; < 2: never
-    int m2l_mfma = 0;                    // FP32 M2L levels on the matrix cores (else vector units)
+    int m2l_mfma = 0;                    // unsplit FP32 M2L levels on the matrix cores (else vector units)
     int work_order = 1;                  // launch order: most estimated work first (else input order)
+    int p2p_block = 0;                   // near-field register-blocking policy (block_table)
 };
 
 // Host description of the instances of a plan.
@@ -196,7 +197,7 @@ fmm_status batch_shape(const fmm_params* prm, Shape& sh, int64_t& max_leaves)
 
 struct Layout {
     size_t inst, tables, bad_blk, bbox, leaf_start, hist, hist_scan, scan_part;
-    size_t key, ksorted, perm, xs, ys, gs, ktmp, itmp, xt, yt, gt, pk, me, le, le_part[2];
+    size_t key, ksorted, perm, xs, ys, gs, ktmp, itmp, xt, yt, gt, pk, blk_tab, me, le, le_part[2];
     size_t tkey, tks, tperm, txs, tys, tleaf_start, tbad;
     size_t fgt_a, fgt_b, fgt_h;
     size_t t_m2m, t_l2l, t_h64, t_h32, t_sin, t_sout;
@@ -242,6 +243,7 @@ Layout make_layout(const Shape& sh, int P, bool mixed)
     ly.tleaf_start = take(m ? sizeof(int32_t) * size_t(sh.leaf_entries) : 0);
     ly.tbad = take(sizeof(int32_t) * size_t(radix_blocks(int64_t(m))));
     ly.pk = take(mixed ? sizeof(float4) * n : 0);
+    ly.blk_tab = take(size_t(kBlockPolicies) * kBlockTabBytes);
     // expansions: P >= p coefficients per box (the compiled size), zero-padded
     ly.me = take(sizeof(cd) * size_t(sh.boxes) * P);
     ly.le = take(sizeof(cd) * size_t(sh.boxes) * P);
@@ -452,7 +454,9 @@ void build_schedule(fmm_plan_s* pl)
     pl->host_tables.assign(size_t(kMaxLaunches) * ti, 0);
     const std::vector<LaunchDesc> list = launch_list(sh.Lmax, pl->mixed);
     if (sh.batched) {
-        // launches no instance that fits can use are left out
+        // one workgroup per work item of the largest instance set that fits
+        // (a workgroup past the call's work returns at once); launches no
+        // instance that fits can use are left out
         for (const LaunchDesc& d : list) {
             const int64_t bound = capacity_bound(cfg, d, sh.Lmax, n, pl->max_leaves);
             if (bound <= 0) continue;
@@ -573,15 +577,16 @@ hipError_t enqueue_all(fmm_plan_s* pl, int64_t n, const double* x, const double*
         if (!far && kind != L_P2P) continue;
         switch (kind) {
             case L_UP: chk(launch_upward(b, P, p, w, ln.nwg, ln.desc.group == 0, st)); break;
-            case L_M2L:
-                chk(launch_m2l(b, P, w, ln.nwg, ln.desc.fp32 != 0, pl->tune.m2l_mfma != 0, ln.groups, st));
+            case L_M2L:   // the matrix cores take the unsplit FP32 levels (split ones stage too much per item)
+                chk(launch_m2l(b, P, w, ln.nwg, ln.desc.fp32 != 0, pl->tune.m2l_mfma != 0 && ln.desc.part == 1,
+                               ln.groups, st));
                 break;
             case L_DOWN: chk(launch_downward(b, P, w, ln.nwg, st)); break;
             case L_P2P:
                 if (m > 0)
-                    chk(launch_p2p_at(b, P, pl->shape.depth[0], nk, u, v, st));
+                    chk(launch_p2p_at(b, P, pl->shape.depth[0], nk, pl->tune.p2p_block, u, v, st));
                 else
-                    chk(launch_p2p(b, P, w, ln.nwg, pl->tune.p2p_waves, pl->mixed, nk, u, v, st));
+                    chk(launch_p2p(b, P, w, ln.nwg, pl->tune.p2p_waves, pl->mixed, nk, pl->tune.p2p_block, u, v, st));
                 break;
         }
     }
@@ -619,6 +624,11 @@ fmm_status make_plan(const fmm_params* prm, Shape&& sh, bool batch, void* d_work
     pl->auto_domain = !(prm->width > 0.0);
     pl->mixed = mixed;
     pl->batch = batch;
+    // measured defaults: in FP64 the utilisation-first blocking is faster on
+    // every workload, in the mixed form the power-of-two one on uniform
+    // particles; the FP32 M2L levels that run unsplit go to the matrix cores
+    pl->tune.p2p_block = mixed ? 0 : 1;
+    pl->tune.m2l_mfma = mixed ? 1 : 0;
     pl->shape = std::move(sh);
     pl->last_n = -1;
     pl->last_m = 0;
@@ -648,6 +658,7 @@ fmm_status make_plan(const fmm_params* prm, Shape&& sh, bool batch, void* d_work
     b.yt = reinterpret_cast<double*>(base + ly.yt);
     b.gt = reinterpret_cast<double*>(base + ly.gt);
     b.pk = mixed ? reinterpret_cast<float4*>(base + ly.pk) : nullptr;
+    b.blk_tab = reinterpret_cast<uint8_t*>(base + ly.blk_tab);
     const bool targets = pl->shape.m_cap > 0;
     b.tkey = targets ? reinterpret_cast<uint32_t*>(base + ly.tkey) : nullptr;
     b.tks = targets ? reinterpret_cast<uint32_t*>(base + ly.tks) : nullptr;
@@ -696,6 +707,9 @@ fmm_status make_plan(const fmm_params* prm, Shape&& sh, bool batch, void* d_work
     cp(b.t_h32, h32.data(), h32.size() * sizeof(cf));
     cp(b.t_sin, sin_.data(), sin_.size() * sizeof(double));
     cp(b.t_sout, sout_.data(), sout_.size() * sizeof(double));
+    std::vector<uint8_t> blk(size_t(kBlockPolicies) * kBlockTabBytes);
+    for (int k = 0; k < kBlockPolicies; ++k) block_table(k, blk.data() + size_t(k) * kBlockTabBytes);
+    cp(b.blk_tab, blk.data(), blk.size());
     std::vector<double> fgt_h;
     if (fgt) {
         const int nc = pl->shape.fgt_nc;
@@ -1027,27 +1041,30 @@ fmm_status fmm_stats(fmm_plan_t plan, double* stage_ms, int32_t n_stages, int32_
 }
 
 fmm_status fmm_get_tuning(fmm_plan_t plan, int32_t* p2p_waves, int32_t* m2l_split_max, int32_t* m2l_mfma,
-                          int32_t* work_order)
+                          int32_t* work_order, int32_t* p2p_block)
 {
-    if (!plan || !p2p_waves || !m2l_split_max || !m2l_mfma || !work_order) return FMM_E_ARG;
+    if (!plan || !p2p_waves || !m2l_split_max || !m2l_mfma || !work_order || !p2p_block) return FMM_E_ARG;
     *p2p_waves = plan->tune.p2p_waves;
     *m2l_split_max = plan->tune.split_max;
     *m2l_mfma = plan->tune.m2l_mfma;
     *work_order = plan->tune.work_order;
+    *p2p_block = plan->tune.p2p_block;
     return FMM_OK;
 }
 
 fmm_status fmm_set_tuning(fmm_plan_t plan, int32_t p2p_waves, int32_t m2l_split_max, int32_t m2l_mfma,
-                          int32_t work_order, void* stream)
+                          int32_t work_order, int32_t p2p_block, void* stream)
 {
     if (!plan) return FMM_E_ARG;
     if (p2p_waves != 2 && p2p_waves != 4) return FMM_E_ARG;
     if (m2l_split_max < 0 || m2l_split_max > kM2LSplitMaxLevel) return FMM_E_ARG;
     if ((m2l_mfma != 0 && m2l_mfma != 1) || (work_order != 0 && work_order != 1)) return FMM_E_ARG;
+    if (p2p_block < 0 || p2p_block >= kBlockPolicies) return FMM_E_ARG;
     plan->tune.p2p_waves = p2p_waves;
     plan->tune.split_max = m2l_split_max;
     plan->tune.m2l_mfma = m2l_mfma;
     plan->tune.work_order = work_order;
+    plan->tune.p2p_block = p2p_block;
     return upload_schedule(plan, static_cast<hipStream_t>(stream)) == hipSuccess ? FMM_OK : FMM_E_DEVICE;
 }
 
@@ -1113,14 +1130,20 @@ fmm_status fmm_autotune(fmm_plan_t plan, int64_t n, const double* d_x, const dou
     if (cache && *cache) {
         if (FILE* f = std::fopen(cache, "r")) {
             char key[512];
-            int w = 0, sm = 0, mf = 0;
+            int w = 0, sm = 0, mf = 0, bk = 0, fw = 0, fsm = 0, fmf = 0, fbk = 0;
             bool found = false;
-            while (std::fscanf(f, "%511s %d %d %d", key, &w, &sm, &mf) == 4)
-                if (std::strcmp(key, sig) == 0) found = true;   // the last entry wins
+            while (std::fscanf(f, "%511s %d %d %d %d", key, &w, &sm, &mf, &bk) == 5)
+                if (std::strcmp(key, sig) == 0) {   // the last entry wins
+                    found = true;
+                    fw = w;
+                    fsm = sm;
+                    fmf = mf;
+                    fbk = bk;
+                }
             std::fclose(f);
             if (found) {
                 plan->tune_timed = 0;
-                return fmm_set_tuning(plan, w, sm, mf, plan->tune.work_order, stream);
+                return fmm_set_tuning(plan, fw, fsm, fmf, plan->tune.work_order, fbk, stream);
             }
         }
     }
@@ -1142,9 +1165,9 @@ fmm_status fmm_autotune(fmm_plan_t plan, int64_t n, const double* d_x, const dou
     Tuning best_t = saved;
     fmm_status rs = FMM_OK;
     int timed = 0;
-    auto time_one = [&](int w, int sm, int mf) {
+    auto time_one = [&](int w, int sm, int mf, int bk) {
         if (rs != FMM_OK) return;
-        rs = fmm_set_tuning(plan, w, sm, mf, saved.work_order, stream);
+        rs = fmm_set_tuning(plan, w, sm, mf, saved.work_order, bk, stream);
         if (rs == FMM_OK) rs = run_once(plan, n, d_x, d_y, d_gamma, d_u, d_v, stream);   // warm-up, capture
         float tmin = 1e30f;
         for (int r = 0; r < reps && rs == FMM_OK; ++r) {
@@ -1185,21 +1208,24 @@ fmm_status fmm_autotune(fmm_plan_t plan, int64_t n, const double* d_x, const dou
     if (ex && std::atoi(ex) == 1) {
         for (int mi = 0; mi < n_mfma; ++mi)
             for (int wi = 0; wi < 2; ++wi)
-                for (int si = 0; si < 3; ++si) time_one(waves[wi], splits[si], n_mfma == 2 ? mi : saved.m2l_mfma);
+                for (int bk = 0; bk < kBlockPolicies; ++bk)
+                    for (int si = 0; si < 3; ++si)
+                        time_one(waves[wi], splits[si], n_mfma == 2 ? mi : saved.m2l_mfma, bk);
     } else {
         constexpr double kTuneMinShare = 0.1;
-        time_one(saved.p2p_waves, saved.split_max, saved.m2l_mfma);      // the current shape
+        time_one(saved.p2p_waves, saved.split_max, saved.m2l_mfma, saved.p2p_block);   // the current shape
         auto near_group = [&]() {
             const Tuning b = best_t;
             for (int w : waves)
-                if (w != b.p2p_waves) time_one(w, b.split_max, b.m2l_mfma);
+                for (int bk = 0; bk < kBlockPolicies; ++bk)
+                    if (w != b.p2p_waves || bk != b.p2p_block) time_one(w, b.split_max, b.m2l_mfma, bk);
         };
         auto far_group = [&]() {
             const Tuning b = best_t;
             for (int mi = 0; mi < n_mfma; ++mi)
                 for (int sm : splits) {
                     const int mf = n_mfma == 2 ? mi : b.m2l_mfma;
-                    if (sm != b.split_max || mf != b.m2l_mfma) time_one(b.p2p_waves, sm, mf);
+                    if (sm != b.split_max || mf != b.m2l_mfma) time_one(b.p2p_waves, sm, mf, b.p2p_block);
                 }
         };
         if (near_share >= 0.5) {
@@ -1220,10 +1246,12 @@ fmm_status fmm_autotune(fmm_plan_t plan, int64_t n, const double* d_x, const dou
         upload_schedule(plan, st);
         return rs;
     }
-    rs = fmm_set_tuning(plan, best_t.p2p_waves, best_t.split_max, best_t.m2l_mfma, best_t.work_order, stream);
+    rs = fmm_set_tuning(plan, best_t.p2p_waves, best_t.split_max, best_t.m2l_mfma, best_t.work_order,
+                        best_t.p2p_block, stream);
     if (rs == FMM_OK && cache && *cache) {
         if (FILE* f = std::fopen(cache, "a")) {
-            std::fprintf(f, "%s %d %d %d\n", sig, best_t.p2p_waves, best_t.split_max, best_t.m2l_mfma);
+            std::fprintf(f, "%s %d %d %d %d\n", sig, best_t.p2p_waves, best_t.split_max, best_t.m2l_mfma,
+                         best_t.p2p_block);
             std::fclose(f);
         }
     }

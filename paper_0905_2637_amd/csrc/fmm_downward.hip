@@ -295,32 +295,56 @@ k_m2l64_lds(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __rest
 // FP32 M2L on the matrix cores.  Written real-valued, the factored M2L of
 // one interaction-list member is a dense product
 //   [Re b; Im b] = [[Hr, -Hi], [Hi, Hr]] [Re abar; Im abar],  H[l][k] = h_{k+l}(tau),
-// a (2P x 2P) matrix times the 2P terms of the source.  A wavefront holds
-// the 64 targets of one child class (the same tau for all of them) as four
-// column tiles of 16, and accumulates 16 x 16 output tiles over all its
-// members with v_mfma_f32_16x16x4f32 (A[i][k] in lane i + 16k, B[k][j] in
-// lane j + 16k, D[i][j] in lane j + 16 (i/4), element i % 4).  The operator
-// fragments are read from the workgroup's LDS copy of the h_n; rows and
-// columns past 2P are zero.  Same grid, member split and outputs as k_m2l.
+// a (2P x 2P) matrix times the 2P terms of the source: for all targets of
+// one offset tau together, a GEMM.  A wavefront holds the 64 targets of one
+// child class (the same 27 offsets for all of them) as four column tiles of
+// 16, and accumulates 16 x 16 output tiles over all its members with
+// v_mfma_f32_16x16x4f32 (A[i][k] in lane i + 16k, B[k][j] in lane j + 16k,
+// D[i][j] in lane j + 16 (i/4), element i % 4).
+//   Operands.  The workgroup's 16 x 16 targets draw every source from the
+// 20 x 20 boxes around them; those boxes' multipole terms are staged once per
+// workgroup in LDS, converted to FP32 and laid out real-valued (2P terms per
+// box, one word of padding against bank conflicts; boxes outside the level
+// are zeros), so a B fragment is one LDS word per lane.  The operator
+// fragments are formed from the workgroup's LDS copy of the h_n of the 40
+// offsets (rows and columns past 2P are zero), once per member and k-step,
+// and serve all four column tiles.  78 KB of LDS per workgroup: two per CU.
+// Same work items, member split and outputs as k_m2l.
 typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 
+constexpr int kMfmaHalo = 20;
+// compact slot of offset (dx, dy), max(|dx|, |dy|) in {2, 3}: the 49 slots of
+// the 7 x 7 grid without its inner 3 x 3
+__device__ __forceinline__ int far_slot(int dx, int dy)
+{
+    const int s = (dy + 3) * kHankelGrid + (dx + 3);
+    const int inner_before = dy < -1 ? 0 : (dy > 1 ? 9 : 3 * (dy + 1) + (dx < -1 ? 0 : (dx > 1 ? 3 : dx + 1)));
+    return s - inner_before;
+}
+
 template <int P>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 2)
 k_m2l_mfma(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restrict__ me_all, M2LOut dst_,
-           const cplx<float>* __restrict__ H, const double* __restrict__ sout_)
+           const cplx<float>* __restrict__ H, const double* __restrict__ sout_, int GG)
 {
     constexpr int NH = 2 * P - 1;
     constexpr int R2 = 2 * P;                  // real-valued size
     constexpr int MT = (R2 + 15) / 16;         // output row tiles
     constexpr int KS = (R2 + 3) / 4;           // steps of 4 input terms
-    __shared__ cplx<float> sH[kHankelGrid * kHankelGrid * NH];
-    const int G = gridDim.y;
-    const int lin = xcd_runs(int(blockIdx.x + gridDim.x * blockIdx.y), int(gridDim.x * gridDim.y), kM2LXcdRun);
-    const int g = lin / int(gridDim.x), blk = lin % int(gridDim.x);
-    if (blk >= wk.wg_begin[n_inst]) return;                // past the launch's work (batched plans)
-    for (int e = threadIdx.x; e < kHankelGrid * kHankelGrid * NH; e += 256) sH[e] = H[e];
-    __syncthreads();
+    constexpr int HS = R2 + 1;                 // words per staged box
+    constexpr int NSLOT = kHankelGrid * kHankelGrid - 9;
+    __shared__ cplx<float> sH[NSLOT * NH];
+    __shared__ float hal[kMfmaHalo * kMfmaHalo * HS];
+    const int G = GG;
+    const int total = wk.wg_begin[n_inst];
+    const int items = total * GG;
+    if (int(blockIdx.x) >= items) return;                  // past the launch's work (batched plans)
+    for (int e = threadIdx.x; e < kHankelGrid * kHankelGrid * NH; e += 256) {
+        const int slot = e / NH, dx = slot % kHankelGrid - 3, dy = slot / kHankelGrid - 3;
+        if (dx < -1 || dx > 1 || dy < -1 || dy > 1) sH[far_slot(dx, dy) * NH + e % NH] = H[e];
+    }
 
+    auto item = [&](const int g, const int blk) {
     const int pos = find_inst(wk.wg_begin, n_inst, blk);   // place in the launch order
     const int q = wk.order[pos];
     int bl = blk - wk.wg_begin[pos];
@@ -331,20 +355,37 @@ k_m2l_mfma(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restr
     const int side = 1 << l;
     const int bpr = side >= 16 ? side / 16 : 1;
     const int bx = bl % bpr, by = bl / bpr;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const int cx = wave & 1, cy = wave >> 1;
-    const int li = lane & 15, lq = lane >> 4;  // fragment row / column, and k quarter
+    const int tid = threadIdx.x;
     const cd* me_l = me + level_offset(l) * P;
 
-    // the lane's target in each column tile: t = 16 n + li, laid out 8 x 8
-    int ta[4], tb[4];
+    // stage the 20 x 20 source boxes from (16 bx - 2, 16 by - 2) on
+    const int ox = 16 * bx - 2, oy = 16 * by - 2;
+    for (int e = tid; e < kMfmaHalo * kMfmaHalo * P; e += 256) {
+        const int box = e / P, k = e % P;
+        const int sa = ox + box % kMfmaHalo, sb = oy + box / kMfmaHalo;
+        cd v{0.0, 0.0};
+        if (sa >= 0 && sb >= 0 && sa < side && sb < side) v = me_l[int64_t(morton(uint32_t(sa), uint32_t(sb))) * P + k];
+        hal[box * HS + k] = float(v.x);
+        hal[box * HS + P + k] = float(v.y);
+    }
+    __syncthreads();
+
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int cx = wave & 1, cy = wave >> 1;
+    const int li = lane & 15, lq = lane >> 4;  // fragment row / column, and k quarter
+
+    // the lane's target in each column tile: t = 16 n + li, laid out 8 x 8,
+    // and its place in the staged halo
+    int ta[4], tb[4], hx[4], hy[4];
     bool act[4];
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
         const int t = 16 * n + li;
         ta[n] = 2 * (bx * 8 + (t & 7)) + cx;
         tb[n] = 2 * (by * 8 + (t >> 3)) + cy;
+        hx[n] = ta[n] - ox;
+        hy[n] = tb[n] - oy;
         act[n] = ta[n] < side && tb[n] < side;
     }
 
@@ -359,29 +400,23 @@ k_m2l_mfma(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restr
         int dx, dy;
         if (!il_offset(cx, cy, o, dx, dy)) continue;
         if ((member++) % G != g) continue;
-        // source terms (B fragments): column li of tile n, rows 4 ks + lq
-        float bv[4][KS];
+        // source terms (B fragments): column li of tile n, rows 4 ks + lq,
+        // from the staged halo (zeros past 2P and outside the level)
+        const float* src[4];
 #pragma unroll
-        for (int n = 0; n < 4; ++n) {
-            const int sa = ta[n] + dx, sb = tb[n] + dy;
-            const bool ok = act[n] && sa >= 0 && sb >= 0 && sa < side && sb < side;
-            const cd* src = me_l + int64_t(morton(uint32_t(ok ? sa : 0), uint32_t(ok ? sb : 0))) * P;
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                const int sidx = 4 * ks + lq;
-                float val = 0.f;
-                if (ok && sidx < R2) val = float(sidx < P ? src[sidx].x : src[sidx - P].y);
-                bv[n][ks] = val;
-            }
-        }
-        const cplx<float>* h = sH + ((dy + 3) * kHankelGrid + (dx + 3)) * NH;
+        for (int n = 0; n < 4; ++n) src[n] = hal + ((hy[n] + dy) * kMfmaHalo + hx[n] + dx) * HS;
+        const cplx<float>* h = sH + far_slot(dx, dy) * NH;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            // operator fragments: row 16 m + li, column 4 ks + lq
+            const int c = 4 * ks + lq;
+            float bv[4];
+#pragma unroll
+            for (int n = 0; n < 4; ++n) bv[n] = c < R2 ? src[n][c] : 0.f;
+            // operator fragments: row 16 m + li, column c
             float av[MT];
 #pragma unroll
             for (int m = 0; m < MT; ++m) {
-                const int r = 16 * m + li, c = 4 * ks + lq;
+                const int r = 16 * m + li;
                 float val = 0.f;
                 if (r < R2 && c < R2) {
                     const bool rim = r >= P, cim = c >= P;
@@ -394,7 +429,7 @@ k_m2l_mfma(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restr
             for (int m = 0; m < MT; ++m)
 #pragma unroll
                 for (int n = 0; n < 4; ++n)
-                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[m], bv[n][ks], acc[m][n], 0, 0, 0);
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[m], bv[n], acc[m][n], 0, 0, 0);
         }
     }
 
@@ -413,6 +448,14 @@ k_m2l_mfma(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restr
                     dst[2 * k + (r < P ? 0 : 1)] = double(acc[m][n][v]) * sout_[k];   // zero for k >= p
                 }
             }
+    }
+    };
+    // items in turn; the staged halo is reused by the next item
+    for (int it = int(blockIdx.x); it < items;) {
+        const int lin = xcd_runs(it, items, kM2LXcdRun);
+        item(lin / total, lin % total);
+        it += int(gridDim.x);
+        if (it < items) __syncthreads();
     }
 }
 
@@ -590,9 +633,9 @@ hipError_t m2l_impl(const Buffers& b, const Work& w, int nwg, bool fp32, bool mf
     const dim3 grid{unsigned(nwg), unsigned(groups), 1u};
     const M2LOut out{{b.le, b.le_part[0], b.le_part[1]}};
     if constexpr (P <= 24) {
-        if (fp32 && mfma) {
-            hipLaunchKernelGGL((k_m2l_mfma<P>), grid, dim3(256), 0, st, w, b.n_inst, b.inst, b.me, out,
-                               reinterpret_cast<const cplx<float>*>(b.t_h32), b.t_sout);
+        if (fp32 && mfma) {   // one-dimensional: work items (tile, list share), one per workgroup
+            hipLaunchKernelGGL((k_m2l_mfma<P>), dim3(unsigned(int64_t(nwg) * groups)), dim3(256), 0, st, w, b.n_inst,
+                               b.inst, b.me, out, reinterpret_cast<const cplx<float>*>(b.t_h32), b.t_sout, groups);
             return hipGetLastError();
         }
         if (fp32) {

@@ -155,6 +155,7 @@ struct Buffers {
     double* yt;
     double* gt;
     float4* pk;            // [n_max] mixed: leaf-relative FP32 (ox, oy, gamma, 0)
+    uint8_t* blk_tab;      // [kBlockPolicies][kBlockTabBytes] near-field register-blocking tables
     // target points (fmm_evaluate_at), sorted like the particles; null when
     // the plan has no target capacity
     uint32_t* tkey;        // [m_max] leaf key per input point
@@ -210,11 +211,18 @@ hipError_t launch_m2l(const Buffers& b, int P, const Work& w, int nwg, bool fp32
                       hipStream_t st);
 hipError_t launch_downward(const Buffers& b, int P, const Work& w, int nwg, hipStream_t st);   // L2L
 // near field (+ L2P where there is a far field) with the plan's pair kernel
+// block: the near-field register-blocking policy (block_table)
 hipError_t launch_p2p(const Buffers& b, int P, const Work& w, int nwg, int waves, bool mixed, const NearKernel& nk,
-                      double* u, double* v, hipStream_t st);
+                      int block, double* u, double* v, hipStream_t st);
+// Near-field register-blocking tables: per policy, R, TG and S by chunk size
+// t = 0 .. 64 (65 bytes each)
+constexpr int kBlockPolicies = 2;
+constexpr int kBlockTabBytes = 3 * 65;
+void block_table(int policy, uint8_t* out);
 // near field + L2P at the sorted target points of a single-instance FP64 plan
 // (Gaussian or singular kernel)
-hipError_t launch_p2p_at(const Buffers& b, int P, int L, const NearKernel& nk, double* u, double* v, hipStream_t st);
+hipError_t launch_p2p_at(const Buffers& b, int P, int L, const NearKernel& nk, int block, double* u, double* v,
+                         hipStream_t st);
 // interaction lists of boxes [b0, b0 + cnt) of a depth-L tree into out[cnt][27]
 hipError_t launch_ilist(int L, int64_t b0, int64_t cnt, int32_t* out, hipStream_t st);
 // the fast Gauss transform of a single-instance plan (after the tree): P

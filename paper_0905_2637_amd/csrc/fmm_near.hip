@@ -117,16 +117,16 @@ __device__ __forceinline__ void wave_sync()
 }
 constexpr int kR = 4;              // most targets per lane
 
-// Sum over staged sources jb + si, jb = 0, S, 2S, ... < padded for the R
+// Sum over staged sources jb + si, jb = 0, S, 2S, ... < cnt for the R
 // targets a lane owns.  FP32 leaf-relative form: coordinates in leaf widths,
 // exp(-t) = 2^(-t log2 e) with c2 = w^2 log2(e) / (2 sigma^2).  The singular
 // kernel of eq. 7 has no Gaussian factor.  (No Lennard-Jones form in FP32.)
 template <int R, int KER>
-__device__ __forceinline__ void p2p_f32(const float4* __restrict__ src, int padded, int S, int si, float c2,
+__device__ __forceinline__ void p2p_f32(const float4* __restrict__ src, int cnt, int S, int si, float c2,
                                         const float* ox, const float* oy, float* fx, float* fy)
 {
 #pragma unroll 2
-    for (int jb = 0; jb < padded; jb += S) {
+    for (int jb = 0; jb < cnt; jb += S) {
         const float4 t = src[jb + si];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -162,10 +162,10 @@ __device__ __forceinline__ double lj_term(double r2, const PairK& k)
 }
 
 template <int R, int KER>
-__device__ __forceinline__ void p2p_f64(const Src64* __restrict__ src, int padded, int S, int si, const PairK& k,
+__device__ __forceinline__ void p2p_f64(const Src64* __restrict__ src, int cnt, int S, int si, const PairK& k,
                                         const double* x, const double* y, double* ax, double* ay)
 {
-    for (int jb = 0; jb < padded; jb += S) {
+    for (int jb = 0; jb < cnt; jb += S) {
         const Src64 t = src[jb + si];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -196,7 +196,8 @@ struct LeafCtx {
     uint32_t m;                 // z-order index of the target leaf
     int s0, nt;                 // its sorted particle range
     int nbeg[9], npre[10];      // the 3 x 3 neighbourhood: starts and running counts
-    int lgT;                    // log2 of the targets per chunk
+    int R, TG, S;               // targets per lane, target groups, source slices (TG S <= 64)
+    int chunk;                  // staged sources per chunk: a multiple of S, at most kNearStage
     double cx, cy, s;           // leaf centre, 1/leaf width
     float c2;                   // w^2 log2(e) / (2 sigma^2)
     PairK k;                    // the pair kernel's constants
@@ -204,7 +205,10 @@ struct LeafCtx {
 
 constexpr int kStageSlots = kNearStage / 64;   // staged sources per lane and chunk
 
-// All targets of one leaf, in chunks of T = 2^lgT; R targets per lane.
+// All targets of one leaf, in chunks of T = R TG: lane (slice si, group tg)
+// owns targets tg + TG r (r < R) of the chunk and sums them over the staged
+// sources si, si + S, ...; lanes past TG S repeat slice 0's work and are
+// left out of the sums.
 // le_sh: this wavefront's LDS copy of the leaf's local expansion (P terms).
 // sink != nullptr: the near-field sums (physical units, before the 1 / 2 pi)
 // go to sink[i] for target i of the leaf instead of being finished here.
@@ -220,13 +224,19 @@ __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* 
 {
     using Stage = typename std::conditional<MIXED, float4, Src64>::type;
     Stage* src = static_cast<Stage*>(stage_raw);
-    constexpr int lgR = R == 4 ? 2 : (R == 2 ? 1 : 0);
-    const int T = 1 << c.lgT;
-    const int lgTG = c.lgT - lgR;
-    const int TG = 1 << lgTG;        // target groups
-    const int S = 64 >> lgTG;        // source slices
-    const int tg = lane & (TG - 1);
-    const int si = lane >> lgTG;
+    const int TG = c.TG;             // target groups
+    const int S = c.S;               // source slices
+    const int T = R * TG;            // targets per chunk
+    // power-of-two groups filling the wavefront: slices meet by xor shuffles
+    const bool pow2 = (TG & (TG - 1)) == 0 && TG * S == 64;
+    // lane / TG without an integer division: the float quotient is within
+    // 2e-5 of lane / TG (lane < 64, TG <= 64), and a non-multiple lies at
+    // least 1/64 above an integer
+    const int si0 = int(float(lane) * __builtin_amdgcn_rcpf(float(TG)) + 1e-3f);
+    const int tg = lane - si0 * TG;
+    const int si = si0 < S ? si0 : 0;   // idle lanes shadow slice 0
+    // staged chunks of whole slices' worth of sources (a multiple of S)
+    const int chunk = c.chunk;
     const int tot = c.npre[9];
 
     // the leaf's local expansion goes through LDS (read back as broadcasts),
@@ -253,8 +263,8 @@ __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* 
         }
         // slice lane si < R finishes target c0 + tg + TG si; its output slot
         // (and, in mixed mode, its FP64 position for L2P) is fetched up front
-        const int il = c0 + tg + TG * si;
-        const bool own = si < R && il < c.nt;
+        const int il = c0 + tg + TG * si0;
+        const bool own = si0 < R && il < c.nt;
         uint32_t o = 0;
         double px = 0.0, py = 0.0;
         if (own && !sink) {
@@ -262,9 +272,8 @@ __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* 
             if constexpr (MIXED) { px = tx[c.s0 + il]; py = ty[c.s0 + il]; }
         }
 
-        for (int base = 0; base < tot; base += kNearStage) {
-            const int cnt = min(kNearStage, tot - base);
-            const int padded = ((cnt + S - 1) / S) * S;
+        for (int base = 0; base < tot; base += chunk) {
+            const int cnt = min(chunk, tot - base);
             // every lane finds the neighbour leaf of each of its slots, then all
             // loads are issued before the first wait (one memory round trip)
             Stage val[kStageSlots];
@@ -298,41 +307,82 @@ __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* 
 #pragma unroll
             for (int sl = 0; sl < kStageSlots; ++sl) {
                 const int k = lane + 64 * sl;
-                if (k < padded) src[k] = val[sl];
+                src[k] = val[sl];   // inert past cnt: a slice's last step reads them
             }
             wave_sync();
-            if constexpr (MIXED) p2p_f32<R, KER>(src, padded, S, si, c.c2, oxi, oyi, fx, fy);
-            else p2p_f64<R, KER>(src, padded, S, si, c.k, xi, yi, ax, ay);
+            if constexpr (MIXED) p2p_f32<R, KER>(src, cnt, S, si, c.c2, oxi, oyi, fx, fy);
+            else p2p_f64<R, KER>(src, cnt, S, si, c.k, xi, yi, ax, ay);
         }
 
-        // combine the S slices: every lane of a target group ends with the sums
+        // combine the S slices.  Power-of-two groups: xor shuffles leave the
+        // sums in every lane of the group.  Otherwise through the staging
+        // area: every slice lane writes its partial sums, and the lane that
+        // finishes target r of a group adds the S partial sums in slice order.
         double sx[R], sy[R];
+        if (pow2) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
+            for (int r = 0; r < R; ++r) {
+                if constexpr (MIXED) {
+                    float vx = fx[r], vy = fy[r];
+                    for (int off = TG; off < 64; off <<= 1) {
+                        vx += __shfl_xor(vx, off, 64);
+                        vy += __shfl_xor(vy, off, 64);
+                    }
+                    sx[r] = double(vx) * c.s;   // leaf units -> physical: 1/(w z) = s/z
+                    sy[r] = double(vy) * c.s;
+                } else {
+                    double vx = ax[r], vy = ay[r];
+                    for (int off = TG; off < 64; off <<= 1) {
+                        vx += __shfl_xor(vx, off, 64);
+                        vy += __shfl_xor(vy, off, 64);
+                    }
+                    sx[r] = vx;
+                    sy[r] = vy;
+                }
+            }
+        } else {
+            using Part = typename std::conditional<MIXED, float2, cd>::type;
+            Part* red = static_cast<Part*>(stage_raw);   // S TG R partial sums: within the staging area
+            wave_sync();                                 // every lane is done with the staged sources
+            if (si0 < S) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if constexpr (MIXED) red[(si0 * TG + tg) * R + r] = make_float2(fx[r], fy[r]);
+                    else red[(si0 * TG + tg) * R + r] = cd{ax[r], ay[r]};
+                }
+            }
+            wave_sync();
+            const int rr = si0 < R ? si0 : 0;            // the target this lane may finish
+            double vx = 0.0, vy = 0.0;
             if constexpr (MIXED) {
-                float vx = fx[r], vy = fy[r];
-                for (int off = TG; off < 64; off <<= 1) {
-                    vx += __shfl_xor(vx, off, 64);
-                    vy += __shfl_xor(vy, off, 64);
+                float fxs = 0.f, fys = 0.f;
+                for (int k = 0; k < S; ++k) {
+                    const float2 t = red[(k * TG + tg) * R + rr];
+                    fxs += t.x;
+                    fys += t.y;
                 }
-                sx[r] = double(vx) * c.s;   // leaf units -> physical: 1/(w z) = s/z
-                sy[r] = double(vy) * c.s;
+                vx = double(fxs) * c.s;
+                vy = double(fys) * c.s;
             } else {
-                double vx = ax[r], vy = ay[r];
-                for (int off = TG; off < 64; off <<= 1) {
-                    vx += __shfl_xor(vx, off, 64);
-                    vy += __shfl_xor(vy, off, 64);
+                for (int k = 0; k < S; ++k) {
+                    const cd t = red[(k * TG + tg) * R + rr];
+                    vx += t.x;
+                    vy += t.y;
                 }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
                 sx[r] = vx;
                 sy[r] = vy;
             }
+            wave_sync();                                 // before the area is staged again
         }
         if (own) {
             double accx = sx[0], accy = sy[0];
             if constexpr (!MIXED) { px = xi[0]; py = yi[0]; }
 #pragma unroll
             for (int r = 1; r < R; ++r)
-                if (si == r) {
+                if (si0 == r) {
                     accx = sx[r];
                     accy = sy[r];
                     if constexpr (!MIXED) { px = xi[r]; py = yi[r]; }
@@ -365,11 +415,28 @@ __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* 
     }
 }
 
+// The blocking of a leaf of nt targets: ceil(nt / 64) chunks of equal size
+// t <= 64, blocked as the plan's table says for t (bt: R, TG, S, each 65
+// bytes, indexed by t).
+__device__ __forceinline__ void set_blocking(LeafCtx& c, const uint8_t* __restrict__ bt)
+{
+    int t = c.nt > 0 ? c.nt : 1;
+    if (t > 64) {
+        const int chunks = (t + 63) >> 6;
+        t = (t + chunks - 1) / chunks;
+    }
+    c.R = bt[t];
+    c.TG = bt[65 + t];
+    c.S = bt[130 + t];
+    c.chunk = (kNearStage / c.S) * c.S;
+}
+
 // Context of leaf m of an instance: its range and its 3 x 3 neighbourhood,
 // row by row (clipped leaves are empty; with no_siblings, so are the other
 // three leaves of its quad).
 __device__ __forceinline__ void make_ctx(LeafCtx& c, uint32_t m, int L, const int32_t* __restrict__ leaf_start,
-                                         const Domain& d, const PairK& k, bool no_siblings)
+                                         const Domain& d, const PairK& k, bool no_siblings,
+                                         const uint8_t* __restrict__ bt)
 {
     const double inv2s2 = -k.ninv2s2;
     c.k = k;
@@ -391,7 +458,7 @@ __device__ __forceinline__ void make_ctx(LeafCtx& c, uint32_t m, int L, const in
         c.nbeg[q] = beg;
         c.npre[q + 1] = c.npre[q] + cnt;
     }
-    c.lgT = c.nt >= 64 ? 6 : (c.nt <= 1 ? 0 : 32 - __clz(c.nt - 1));
+    set_blocking(c, bt);
     const double w = ldexp(d.W, -L);
     c.cx = d.x0 + (double(a) + 0.5) * w;
     c.cy = d.y0 + (double(b) + 0.5) * w;
@@ -411,9 +478,9 @@ __device__ __forceinline__ void leaf_dispatch(const LeafCtx& c, int lane, void* 
                                               const uint32_t* __restrict__ perm, const cd* __restrict__ le_leaf,
                                               cd* sink, double* __restrict__ u, double* __restrict__ v)
 {
-    if (c.lgT == 6)
+    if (c.R == 4)
         leaf_near_far<P, MIXED, 4, KER>(c, lane, st, lsh, has_far, tx, ty, xs, ys, gs, pk, perm, le_leaf, sink, u, v);
-    else if (c.lgT == 5)
+    else if (c.R == 2)
         leaf_near_far<P, MIXED, 2, KER>(c, lane, st, lsh, has_far, tx, ty, xs, ys, gs, pk, perm, le_leaf, sink, u, v);
     else
         leaf_near_far<P, MIXED, 1, KER>(c, lane, st, lsh, has_far, tx, ty, xs, ys, gs, pk, perm, le_leaf, sink, u, v);
@@ -478,7 +545,7 @@ __global__ void __launch_bounds__(64 * WAVES)
 k_p2p_l2p(Work wk, int n_inst, const Inst* __restrict__ inst, const int32_t* __restrict__ leaf_start_all,
           const double* __restrict__ xs, const double* __restrict__ ys, const double* __restrict__ gs,
           const float4* __restrict__ pk, const uint32_t* __restrict__ perm, const cd* __restrict__ le_all,
-          PairK kp, double* __restrict__ u, double* __restrict__ v)
+          PairK kp, const uint8_t* __restrict__ bt, double* __restrict__ u, double* __restrict__ v)
 {
     using Stage = typename std::conditional<MIXED, float4, Src64>::type;
     constexpr bool kQuads = WAVES == 4 && !MIXED;
@@ -516,14 +583,14 @@ k_p2p_l2p(Work wk, int n_inst, const Inst* __restrict__ inst, const int32_t* __r
     if (!(kQuads && nq > 1 && nq <= kQuadMax)) {
         if (mm >= nleaf) return;
         LeafCtx c;
-        make_ctx(c, uint32_t(mm), L, leaf_start, d, kp, false);
+        make_ctx(c, uint32_t(mm), L, leaf_start, d, kp, false, bt);
         if (c.nt == 0) return;
         leaf_dispatch<P, MIXED, KER>(c, lane, st, lsh, has_far, xs, ys, xs, ys, gs, pk, perm, le_leaf, nullptr, u, v);
         return;
     }
 
     LeafCtx c;
-    make_ctx(c, uint32_t(mm), L, leaf_start, d, kp, true);
+    make_ctx(c, uint32_t(mm), L, leaf_start, d, kp, true, bt);
     // stage the quad, one particle per lane (past nq: inert, far away and
     // without circulation)
     if (wv == 0) {
@@ -586,8 +653,8 @@ __global__ void __launch_bounds__(256)
 k_p2p_at(int L, const Inst* __restrict__ inst, const int32_t* __restrict__ leaf_start,
          const int32_t* __restrict__ tleaf_start, const double* __restrict__ xs, const double* __restrict__ ys,
          const double* __restrict__ gs, const double* __restrict__ txs, const double* __restrict__ tys,
-         const uint32_t* __restrict__ tperm, const cd* __restrict__ le_all, PairK kp, double* __restrict__ u,
-         double* __restrict__ v)
+         const uint32_t* __restrict__ tperm, const cd* __restrict__ le_all, PairK kp, const uint8_t* __restrict__ bt,
+         double* __restrict__ u, double* __restrict__ v)
 {
     __shared__ Src64 stage_all[4][kNearStage];
     __shared__ cd le_all_sh[4][P];
@@ -596,11 +663,11 @@ k_p2p_at(int L, const Inst* __restrict__ inst, const int32_t* __restrict__ leaf_
     const int64_t mm = flat_block() * 4 + wv;
     if (mm >= (int64_t(1) << (2 * L))) return;
     LeafCtx c;
-    make_ctx(c, uint32_t(mm), L, leaf_start, inst[0].dom, kp, false);   // the particles around the leaf
+    make_ctx(c, uint32_t(mm), L, leaf_start, inst[0].dom, kp, false, bt);   // the particles around the leaf
     c.s0 = tleaf_start[mm];                                                    // and the leaf's points
     c.nt = tleaf_start[mm + 1] - c.s0;
     if (c.nt == 0) return;
-    c.lgT = c.nt >= 64 ? 6 : (c.nt <= 1 ? 0 : 32 - __clz(c.nt - 1));
+    set_blocking(c, bt);
     const cd* le_leaf = le_all + (inst[0].box_off + level_offset(L)) * P;
     leaf_dispatch<P, false, KER>(c, lane, stage_all[wv], le_all_sh[wv], L >= 2 ? 1 : 0, txs, tys, xs, ys, gs,
                                  nullptr, tperm, le_leaf, nullptr, u, v);
@@ -620,47 +687,49 @@ PairK pair_constants(const NearKernel& nk)
 }
 
 template <int P, int WAVES, int KER>
-void p2p_launch(const Buffers& b, const Work& w, int nwg, bool mixed, const PairK& k, double* u, double* v,
-                hipStream_t st)
+void p2p_launch(const Buffers& b, const Work& w, int nwg, bool mixed, const PairK& k, const uint8_t* bt, double* u,
+                double* v, hipStream_t st)
 {
     if constexpr (KER != kNearLJ) {
         if (mixed) {
             hipLaunchKernelGGL((k_p2p_l2p<P, true, WAVES, KER>), row_grid(nwg), dim3(64 * WAVES), 0, st, w,
-                               b.n_inst, b.inst, b.leaf_start, b.xs, b.ys, b.gs, b.pk, b.perm, b.le, k, u, v);
+                               b.n_inst, b.inst, b.leaf_start, b.xs, b.ys, b.gs, b.pk, b.perm, b.le, k, bt, u, v);
             return;
         }
     }
     hipLaunchKernelGGL((k_p2p_l2p<P, false, WAVES, KER>), row_grid(nwg), dim3(64 * WAVES), 0, st, w, b.n_inst,
-                       b.inst, b.leaf_start, b.xs, b.ys, b.gs, b.pk, b.perm, b.le, k, u, v);
+                       b.inst, b.leaf_start, b.xs, b.ys, b.gs, b.pk, b.perm, b.le, k, bt, u, v);
 }
 
 template <int P, int WAVES>
-void p2p_kernel(const Buffers& b, const Work& w, int nwg, bool mixed, const NearKernel& nk, double* u, double* v,
-                hipStream_t st)
+void p2p_kernel(const Buffers& b, const Work& w, int nwg, bool mixed, const NearKernel& nk, const uint8_t* bt,
+                double* u, double* v, hipStream_t st)
 {
     const PairK k = pair_constants(nk);
-    if (nk.kind == kNearSingular) p2p_launch<P, WAVES, kNearSingular>(b, w, nwg, mixed, k, u, v, st);
-    else if (nk.kind == kNearLJ) p2p_launch<P, WAVES, kNearLJ>(b, w, nwg, mixed, k, u, v, st);
-    else p2p_launch<P, WAVES, kNearGauss>(b, w, nwg, mixed, k, u, v, st);
+    if (nk.kind == kNearSingular) p2p_launch<P, WAVES, kNearSingular>(b, w, nwg, mixed, k, bt, u, v, st);
+    else if (nk.kind == kNearLJ) p2p_launch<P, WAVES, kNearLJ>(b, w, nwg, mixed, k, bt, u, v, st);
+    else p2p_launch<P, WAVES, kNearGauss>(b, w, nwg, mixed, k, bt, u, v, st);
 }
 
 template <int P>
 hipError_t p2p_waves(const Buffers& b, const Work& w, int nwg, int waves, bool mixed, const NearKernel& nk,
-                     double* u, double* v, hipStream_t st)
+                     const uint8_t* bt, double* u, double* v, hipStream_t st)
 {
     if (nwg <= 0) return hipSuccess;
     if (waves != 2 && waves != 4) return hipErrorInvalidValue;
     if (nk.kind != kNearGauss && nk.kind != kNearSingular && nk.kind != kNearLJ) return hipErrorInvalidValue;
     if (mixed && nk.kind == kNearLJ) return hipErrorInvalidValue;
-    if (waves == 2) p2p_kernel<P, 2>(b, w, nwg, mixed, nk, u, v, st);
-    else p2p_kernel<P, 4>(b, w, nwg, mixed, nk, u, v, st);
+    if (waves == 2) p2p_kernel<P, 2>(b, w, nwg, mixed, nk, bt, u, v, st);
+    else p2p_kernel<P, 4>(b, w, nwg, mixed, nk, bt, u, v, st);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_p2p_at(const Buffers& b, int P, int L, const NearKernel& nk, double* u, double* v, hipStream_t st)
+hipError_t launch_p2p_at(const Buffers& b, int P, int L, const NearKernel& nk, int block, double* u, double* v,
+                         hipStream_t st)
 {
+    const uint8_t* bt = b.blk_tab + block * kBlockTabBytes;
     if (nk.kind != kNearGauss && nk.kind != kNearSingular) return hipErrorInvalidValue;
     const bool singular = nk.kind == kNearSingular;
     const PairK kp = pair_constants(nk);
@@ -669,10 +738,10 @@ hipError_t launch_p2p_at(const Buffers& b, int P, int L, const NearKernel& nk, d
     case PP:                                                                                                       \
         if (singular)                                                                                              \
             hipLaunchKernelGGL((k_p2p_at<PP, kNearSingular>), grid, dim3(256), 0, st, L, b.inst, b.leaf_start,    \
-                               b.tleaf_start, b.xs, b.ys, b.gs, b.txs, b.tys, b.tperm, b.le, kp, u, v);            \
+                               b.tleaf_start, b.xs, b.ys, b.gs, b.txs, b.tys, b.tperm, b.le, kp, bt, u, v);        \
         else                                                                                                       \
             hipLaunchKernelGGL((k_p2p_at<PP, kNearGauss>), grid, dim3(256), 0, st, L, b.inst, b.leaf_start,       \
-                               b.tleaf_start, b.xs, b.ys, b.gs, b.txs, b.tys, b.tperm, b.le, kp, u, v);            \
+                               b.tleaf_start, b.xs, b.ys, b.gs, b.txs, b.tys, b.tperm, b.le, kp, bt, u, v);        \
         return hipGetLastError();
     switch (P) {
         FMM_AT_CASE(8)
@@ -687,17 +756,52 @@ hipError_t launch_p2p_at(const Buffers& b, int P, int L, const NearKernel& nk, d
 #undef FMM_AT_CASE
 }
 
-hipError_t launch_p2p(const Buffers& b, int P, const Work& w, int nwg, int waves, bool mixed, const NearKernel& nk,
-                      double* u, double* v, hipStream_t st)
+// Blocking table of a policy: 0 pads a chunk's targets to a power of two T
+// (R = 4 at T = 64, 2 at T = 32, 1 below; TG = T / R, S = 64 / TG); 1 keeps
+// the most lanes on real pairs, t S / (64 R) with TG = ceil(t / R) and S =
+// floor(64 / TG), the larger R on a tie.
+void block_table(int policy, uint8_t* out)
 {
+    for (int t = 0; t <= 64; ++t) {
+        int R = 1, TG = 1, S = 64;
+        if (t > 0 && policy == 0) {
+            int T = 1;
+            while (T < t) T <<= 1;
+            R = T >= 64 ? 4 : (T == 32 ? 2 : 1);
+            TG = T / R;
+            S = 64 / TG;
+        } else if (t > 0) {
+            int bR = 1, bTG = t, bS = 64 / t;
+            for (int r = 2; r <= 4; r <<= 1) {
+                const int tg = (t + r - 1) / r, sl = 64 / tg;
+                if (t * sl * bR >= t * bS * r) {
+                    bR = r;
+                    bTG = tg;
+                    bS = sl;
+                }
+            }
+            R = bR;
+            TG = bTG;
+            S = bS;
+        }
+        out[t] = uint8_t(R);
+        out[65 + t] = uint8_t(TG);
+        out[130 + t] = uint8_t(S);
+    }
+}
+
+hipError_t launch_p2p(const Buffers& b, int P, const Work& w, int nwg, int waves, bool mixed, const NearKernel& nk,
+                      int block, double* u, double* v, hipStream_t st)
+{
+    const uint8_t* bt = b.blk_tab + block * kBlockTabBytes;
     switch (P) {
-        case 8: return p2p_waves<8>(b, w, nwg, waves, mixed, nk, u, v, st);
-        case 12: return p2p_waves<12>(b, w, nwg, waves, mixed, nk, u, v, st);
-        case 16: return p2p_waves<16>(b, w, nwg, waves, mixed, nk, u, v, st);
-        case 17: return p2p_waves<17>(b, w, nwg, waves, mixed, nk, u, v, st);
-        case 20: return p2p_waves<20>(b, w, nwg, waves, mixed, nk, u, v, st);
-        case 24: return p2p_waves<24>(b, w, nwg, waves, mixed, nk, u, v, st);
-        case 32: return p2p_waves<32>(b, w, nwg, waves, mixed, nk, u, v, st);
+        case 8: return p2p_waves<8>(b, w, nwg, waves, mixed, nk, bt, u, v, st);
+        case 12: return p2p_waves<12>(b, w, nwg, waves, mixed, nk, bt, u, v, st);
+        case 16: return p2p_waves<16>(b, w, nwg, waves, mixed, nk, bt, u, v, st);
+        case 17: return p2p_waves<17>(b, w, nwg, waves, mixed, nk, bt, u, v, st);
+        case 20: return p2p_waves<20>(b, w, nwg, waves, mixed, nk, bt, u, v, st);
+        case 24: return p2p_waves<24>(b, w, nwg, waves, mixed, nk, bt, u, v, st);
+        case 32: return p2p_waves<32>(b, w, nwg, waves, mixed, nk, bt, u, v, st);
         default: return hipErrorInvalidValue;
     }
 }

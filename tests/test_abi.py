@@ -168,11 +168,11 @@ def test_batch_entry_points_reject_null(lib):
     assert lib.fmm_plan(C.byref(prm), None, 1 << 20, None, C.byref(h)) == fm.FMM_E_ARG
     assert lib.fmm_plan(C.byref(prm), C.c_void_p(1 << 20), 16, None, C.byref(h)) == fm.FMM_E_CAPACITY
     assert lib.fmm_evaluate_batch(None, 1, None, None, None, None, None, None, None, None) == fm.FMM_E_ARG
-    assert lib.fmm_set_tuning(None, 4, 8, 1, 1, None) == fm.FMM_E_ARG
+    assert lib.fmm_set_tuning(None, 4, 8, 1, 1, 0, None) == fm.FMM_E_ARG
     assert lib.fmm_work_estimate(None, None, 0, None) == fm.FMM_E_ARG
     assert lib.fmm_autotune(None, 10, None, None, None, None, None, None, 3) == fm.FMM_E_ARG
     w = C.c_int32(0)
-    assert lib.fmm_get_tuning(None, C.byref(w), C.byref(w), C.byref(w), C.byref(w)) == fm.FMM_E_ARG
+    assert lib.fmm_get_tuning(None, C.byref(w), C.byref(w), C.byref(w), C.byref(w), C.byref(w)) == fm.FMM_E_ARG
 
 
 def test_advance_rejects_bad_arguments(lib):

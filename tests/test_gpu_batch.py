@@ -184,17 +184,18 @@ def test_every_launch_shape_agrees(precision):
     for mfma in ((0, 1) if precision == "mixed" else (0,)):
         for waves in (2, 4):
             for split in (0, 5, 8):
-                plan.set_tuning(waves, split, mfma)
-                assert plan.tuning() == {"p2p_waves": waves, "m2l_split_max": split, "m2l_mfma": mfma,
-                                         "work_order": 1}
-                u, v = plan.evaluate(x, y, g)
-                torch.cuda.synchronize()
-                u, v = u.cpu().numpy(), v.cpu().numpy()
-                if ref is None:
-                    ref = (u, v)
-                else:
-                    err = oracle.rel_l2(u, v, *ref)
-                    assert err < (1e-14 if precision == "fp64" else 1e-6), (mfma, waves, split, err)
+                for block in (0, 1):
+                    plan.set_tuning(waves, split, mfma, 1, block)
+                    assert plan.tuning() == {"p2p_waves": waves, "m2l_split_max": split, "m2l_mfma": mfma,
+                                             "work_order": 1, "p2p_block": block}
+                    u, v = plan.evaluate(x, y, g)
+                    torch.cuda.synchronize()
+                    u, v = u.cpu().numpy(), v.cpu().numpy()
+                    if ref is None:
+                        ref = (u, v)
+                    else:
+                        err = oracle.rel_l2(u, v, *ref)
+                        assert err < (1e-14 if precision == "fp64" else 1e-6), (mfma, waves, split, block, err)
     plan.close()
 
 
@@ -208,13 +209,15 @@ def test_autotune_and_cache(tmp_path, monkeypatch):
     plan = fm.Plan(wl.n, wl.sigma, wl.p, wl.depth)
     t = plan.autotune(x, y, g, reps=2)
     assert t["p2p_waves"] in (2, 4) and t["m2l_split_max"] in (0, 5, 8) and t["m2l_mfma"] in (0, 1)
+    assert t["p2p_block"] in (0, 1)
     lines = cache.read_text().split("\n")
     assert len([ln for ln in lines if ln.strip()]) == 1
     # a planted entry is taken from the cache without a search
     key = lines[0].split()[0]
-    cache.write_text(f"{key} 2 0 0\n")
+    cache.write_text(f"{key} 2 0 0 1\n")
     plan2 = fm.Plan(wl.n, wl.sigma, wl.p, wl.depth)
-    assert plan2.autotune(x, y, g) == {"p2p_waves": 2, "m2l_split_max": 0, "m2l_mfma": 0, "work_order": 1}
+    assert plan2.autotune(x, y, g) == {"p2p_waves": 2, "m2l_split_max": 0, "m2l_mfma": 0, "work_order": 1,
+                                       "p2p_block": 1}
     u, v = plan2.evaluate(x, y, g)
     torch.cuda.synchronize()
     uo, vo = oracle.fmm(wl.x, wl.y, wl.gamma, wl.sigma, wl.p, wl.depth)
@@ -227,8 +230,8 @@ def test_autotune_and_cache(tmp_path, monkeypatch):
 def test_autotune_seeded_by_the_work_model(precision, monkeypatch):
     """The work model (eqs. 13-15) orders the search: the part of the
     estimate that dominates is tuned first and a minor part is skipped, so
-    the seeded search times fewer candidates than the whole grid (6 in FP64,
-    12 in the mixed form) and its choice still gives the oracle's velocities."""
+    the seeded search times fewer candidates than the whole grid (12 in FP64,
+    24 in the mixed form) and its choice still gives the oracle's velocities."""
     import torch
     fm = _fm()
     monkeypatch.delenv("FMM_AUTOTUNE_CACHE", raising=False)
@@ -238,7 +241,7 @@ def test_autotune_seeded_by_the_work_model(precision, monkeypatch):
     monkeypatch.setenv("FMM_AUTOTUNE_EXHAUSTIVE", "1")
     plan.autotune(x, y, g, reps=1)
     full = plan.autotune_report()
-    assert full["candidates_timed"] == (12 if precision == "mixed" else 6)
+    assert full["candidates_timed"] == (24 if precision == "mixed" else 12)
     monkeypatch.delenv("FMM_AUTOTUNE_EXHAUSTIVE")
     t = plan.autotune(x, y, g, reps=1)
     rep = plan.autotune_report()
