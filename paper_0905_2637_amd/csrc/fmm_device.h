@@ -53,4 +53,48 @@ __device__ __forceinline__ void cmac(T& ax, T& ay, T bx, T by, T cx, T cy)
     ay = fma(by, cx, ay);
 }
 
+// The child-centre offset of child position c (bit 0: x, bit 1: y) in
+// units of the parent width, (+-1 +- i) / 4: exact in binary.
+__device__ __forceinline__ void child_delta(int c, double& dx, double& dy)
+{
+    dx = (c & 1) ? 0.25 : -0.25;
+    dy = (c & 2) ? 0.25 : -0.25;
+}
+
+// Translation of a truncated series by the complex offset d = (dx, dy), in
+// registers (repeated synthetic division, P (P - 1) / 2 complex
+// multiply-adds; no operator matrix).
+//
+// Moments (multipole side): u_k <- sum_{m <= k} C(k, m) d^(k-m) u_m, the
+// coefficients of sum_j g_j (z_j - c + d)^k from those of (z_j - c)^k.
+template <int P>
+__device__ __forceinline__ void shift_moments(cd* u, double dx, double dy)
+{
+#pragma unroll
+    for (int i = 0; i < P - 1; ++i) {
+#pragma unroll
+        for (int l = P - 1; l > i; --l) {       // u_l += d u_(l-1), the old u_(l-1)
+            const cd a = u[l - 1];
+            u[l].x = fma(dx, a.x, fma(-dy, a.y, u[l].x));
+            u[l].y = fma(dx, a.y, fma(dy, a.x, u[l].y));
+        }
+    }
+}
+
+// Taylor series (local side): b_k <- sum_{j >= k} C(j, k) d^(j-k) b_j, the
+// coefficients of p(x + d) from those of p(x) = sum_j b_j x^j.
+template <int P>
+__device__ __forceinline__ void shift_taylor(cd* b, double dx, double dy)
+{
+#pragma unroll
+    for (int i = 0; i < P - 1; ++i) {
+#pragma unroll
+        for (int j = P - 2; j >= i; --j) {      // b_j += d b_(j+1), the new b_(j+1)
+            const cd a = b[j + 1];
+            b[j].x = fma(dx, a.x, fma(-dy, a.y, b[j].x));
+            b[j].y = fma(dx, a.y, fma(dy, a.x, b[j].y));
+        }
+    }
+}
+
 }  // namespace fmm

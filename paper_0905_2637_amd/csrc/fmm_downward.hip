@@ -463,7 +463,11 @@ k_m2l_mfma(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restr
 // lt (whose local expansion is final) and walks up to three levels down its
 // z-order-contiguous subtree in LDS.  Each child adds the parent's shifted
 // expansion to what M2L wrote for it:
-//   bhat^c_m += sum_{j>=m} C(j,m) delta^(j-m) 2^-(m+1) bhat^P_j .
+//   bhat^c_m += sum_{j>=m} C(j,m) delta^(j-m) 2^-(m+1) bhat^P_j ,
+// the parent's Taylor series translated by delta (shift_taylor, in the
+// registers of the thread that owns the child), then scaled by the exact
+// 2^-(m+1).  (P = 32, whose P complex registers would not fit beside the
+// rest, keeps the operator matrix Lt[c][m][j] in LDS.)
 constexpr int kDownThreads = 256;
 
 // part[0], part[1]: partial M2L sums of levels <= split_level (M2L ran with
@@ -482,8 +486,11 @@ k_downward(Work wk, int n_inst, const Inst* __restrict__ inst, cd* __restrict__ 
 {
     constexpr int kUp = (21 * P + kDownThreads - 1) / kDownThreads;     // levels lt .. lt+d-1 per thread
     constexpr int kLast = (64 * P + kDownThreads - 1) / kDownThreads;   // last level per thread
-    __shared__ cd sh[21 * P];            // levels lt, lt+1, lt+2 (1 + 4 + 16 boxes) at P (4^t - 1) / 3
-    __shared__ cd sL[4 * P * P];
+    constexpr bool kMatrix = P > 24;     // operator matrix in LDS instead of register shifts
+    // levels lt, lt+1, lt+2 (1 + 4 + 16 boxes; with register shifts also the
+    // last level, 64 more) at P (4^t - 1) / 3
+    __shared__ cd sh[kMatrix ? 21 * P : 85 * P];
+    __shared__ cd sL[kMatrix ? 4 * P * P : 1];
     const int tid = threadIdx.x;
     if (int(blockIdx.x) >= wk.wg_begin[n_inst]) return;           // past the launch's work (batched plans)
     const int pos = find_inst(wk.wg_begin, n_inst, blockIdx.x);   // place in the launch order
@@ -557,7 +564,8 @@ k_downward(Work wk, int n_inst, const Inst* __restrict__ inst, cd* __restrict__ 
         if (i < kUp) up[i] = cd{x, y};
         else lastv[i - kUp] = cd{x, y};
     }
-    for (int e = tid; e < 4 * P * P; e += kDownThreads) sL[e] = Lt[e];
+    if constexpr (kMatrix)
+        for (int e = tid; e < 4 * P * P; e += kDownThreads) sL[e] = Lt[e];
 #pragma unroll
     for (int i = 0; i < kUp; ++i) {
         const int e = tid + kDownThreads * i;
@@ -565,6 +573,43 @@ k_downward(Work wk, int n_inst, const Inst* __restrict__ inst, cd* __restrict__ 
             sh[e] = up[i];
             if (e < P && lt == 2 && lt <= split_level) le[level_offset(lt) * P + root * P + e] = up[i];
         }
+    }
+    if constexpr (!kMatrix) {
+#pragma unroll
+        for (int i = 0; i < kLast; ++i) {
+            const int e = tid + kDownThreads * i;
+            if (e < n_last) sh[n_up + e] = lastv[i];
+        }
+        __syncthreads();
+        // level by level: thread t < 4^(j - lt) finishes child t in LDS (all
+        // in the first wavefront: a wavefront's instruction stream costs the
+        // same however few lanes are live), then the level goes out in whole
+        // rows
+        for (int j = lt + 1; j <= last; ++j) {
+            const int n_out = 1 << (2 * (j - lt));
+            const int in_off = P * ((n_out >> 2) - 1) / 3, out_off = P * (n_out - 1) / 3;
+            const int t = tid;
+            if (t < n_out) {
+                cd b[P];
+                const cd* par = sh + in_off + (t >> 2) * P;
+#pragma unroll
+                for (int k = 0; k < P; ++k) b[k] = par[k];
+                double dx, dy;
+                child_delta(t & 3, dx, dy);
+                shift_taylor<P>(b, dx, dy);
+                cd* mine = sh + out_off + t * P;
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    const double f = ldexp(1.0, -(k + 1));
+                    const cd c = mine[k];
+                    mine[k] = cd{fma(b[k].x, f, c.x), fma(b[k].y, f, c.y)};
+                }
+            }
+            __syncthreads();
+            cd* g = le + (level_offset(j) + (root << (2 * (j - lt)))) * P;
+            for (int e = tid; e < n_out * P; e += kDownThreads) g[e] = sh[out_off + e];
+        }
+        return;
     }
     __syncthreads();
     int n_in = 1;

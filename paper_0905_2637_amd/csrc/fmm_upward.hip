@@ -8,12 +8,17 @@
 // (z - c)^(k+1), with a_k = ahat_k w_l^k.  The M2M shift from a child in
 // position c (delta = (c_child - c_parent) / w_parent = (+-1 +- i)/4) reads
 //   ahat^P_k = sum_{m<=k} C(k,m) 2^-m delta^(k-m) ahat^child_m,
-// one of four fixed lower-triangular matrices built on the host.
+// the moments 2^-m ahat^child_m translated by delta (the same for every
+// level).
 //
 // What is stored is abar_k = s_k ahat_k, s_k = (-1)^(k+1) / k! (the input
 // scaling of the factored M2L, which then reads the coefficients as they
-// are): P2M multiplies by s_k once, and the M2M matrices are built for abar
-// (S M S^-1, entries (-1)^(k-m) 2^-m delta^(k-m) / (k-m)!).
+// are): P2M multiplies by s_k once.  M2M undoes the scaling, multiplies by
+// the exact 2^-m, shifts the moments by delta in registers (shift_moments:
+// C(k,m) delta^(k-m), no matrix) and scales the sum of the four children
+// by s_k again.  (P = 32, whose P complex registers would not fit beside
+// the rest, keeps the operator matrices, built for abar: S M S^-1, entries
+// (-1)^(k-m) 2^-m delta^(k-m) / (k-m)!, read from LDS.)
 //
 // Storage: every box holds P >= p coefficients (P the compiled expansion
 // size), terms k >= p zero; the operator rows k >= p are zero as well, so
@@ -37,10 +42,11 @@ constexpr int kP2MLanes = 4;            // threads per leaf in P2M
 // table arg: lt, d).  from_particles: the 4^d boxes of level lb are leaves
 // and get their expansion from P2M; otherwise they are read from global
 // memory, all loads issued before the first wait.  LDS holds one level at a
-// time (each M2M level is computed into registers, then written over its
-// input after a barrier), and the kernel is held to 128 VGPRs: four
-// workgroups fit on a CU, so a launch of 4 x 256 workgroups runs in one
-// round.
+// time: thread t shifts child t in place, then the threads of the parents'
+// coefficients add the four children (in child order) and, after a barrier,
+// write the parents over their input.  The kernel is held to 128 VGPRs:
+// four workgroups fit on a CU, so a launch of 4 x 256 workgroups runs in
+// one round.
 template <int P>
 __global__ void __launch_bounds__(kUpThreads, 4)
 k_upward(Work wk, int n_inst, const Inst* __restrict__ inst, int p, int from_particles,
@@ -48,8 +54,10 @@ k_upward(Work wk, int n_inst, const Inst* __restrict__ inst, int p, int from_par
          const double* __restrict__ gs, cd* __restrict__ me_all, const cd* __restrict__ M,
          const double* __restrict__ sk)
 {
+    constexpr bool kMatrix = P > 24;     // operator matrices in LDS instead of register shifts
     __shared__ cd sh[64 * P + 1];        // the current level of the subtree (<= 64 boxes) + a junk slot
-    __shared__ cd sM[4 * P * P];         // the four M2M matrices
+    __shared__ cd sM[kMatrix ? 4 * P * P : 1];   // the four M2M matrices
+    __shared__ double s_in[P];           // 2^-m / s_m (zero for m >= p): abar -> 2^-m ahat
     const int tid = threadIdx.x;
     if (int(blockIdx.x) >= wk.wg_begin[n_inst]) return;           // past the launch's work (batched plans)
     const int pos = find_inst(wk.wg_begin, n_inst, blockIdx.x);   // place in the launch order
@@ -59,8 +67,9 @@ k_upward(Work wk, int n_inst, const Inst* __restrict__ inst, int p, int from_par
     const int L = inst[q].L;
     const int32_t* leaf_start = leaf_start_all + inst[q].leaf_off;
     cd* me = me_all + inst[q].box_off * P;
-    if (d > 0)
+    if (kMatrix && d > 0)
         for (int e = tid; e < 4 * P * P; e += kUpThreads) sM[e] = M[e];
+    if (!kMatrix && tid < P) s_in[tid] = sk[tid] != 0.0 ? ldexp(1.0 / sk[tid], -tid) : 0.0;
     const int lb = lt + d;
     const int nb = 1 << (2 * d);         // boxes at level lb under this root
     const int64_t first = root << (2 * d);
@@ -150,6 +159,27 @@ k_upward(Work wk, int n_inst, const Inst* __restrict__ inst, int p, int from_par
         const int n_out = n_in >> 2;
         const int64_t gfirst = root << (2 * (j - lt));
         cd* gdst = me + (level_offset(j) + gfirst) * P;
+        if constexpr (!kMatrix) {
+            // child t: abar -> 2^-m ahat, moments shifted to the parent
+            // centre (all children in the first wavefront: a wavefront's
+            // instruction stream costs the same however few lanes are live)
+            const int t = tid;
+            if (t < n_in) {
+                cd u[P];
+#pragma unroll
+                for (int m = 0; m < P; ++m) {
+                    const cd a = sh[t * P + m];
+                    const double f = s_in[m];
+                    u[m] = cd{a.x * f, a.y * f};
+                }
+                double dx, dy;
+                child_delta(t & 3, dx, dy);
+                shift_moments<P>(u, dx, dy);
+#pragma unroll
+                for (int m = 0; m < P; ++m) sh[t * P + m] = u[m];
+            }
+            __syncthreads();
+        }
         cd res[kOut];
 #pragma unroll
         for (int i = 0; i < kOut; ++i) {
@@ -158,17 +188,29 @@ k_upward(Work wk, int n_inst, const Inst* __restrict__ inst, int p, int from_par
             if (e >= n_out * P) continue;
             const int o = e / P, k = e % P;
             double bx = 0.0, by = 0.0;
-            // the full row (entries m > k are zero): a fixed trip count lets
-            // the LDS loads be issued together
+            if constexpr (!kMatrix) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const cd* a = sh + (4 * o + c) * P;
-                const cd* Mr = sM + (c * P + k) * P;     // rows k >= p are zero
+                for (int c = 0; c < 4; ++c) {
+                    const cd t = sh[(4 * o + c) * P + k];
+                    bx += t.x;
+                    by += t.y;
+                }
+                const double sc = sk[k];                 // zero for k >= p
+                bx *= sc;
+                by *= sc;
+            } else {
+                // the full row (entries m > k are zero): a fixed trip count
+                // lets the LDS loads be issued together
 #pragma unroll
-                for (int m = 0; m < P; ++m) {
-                    const cd t = Mr[m];
-                    const cd s = a[m];
-                    cmac(bx, by, t.x, t.y, s.x, s.y);
+                for (int c = 0; c < 4; ++c) {
+                    const cd* a = sh + (4 * o + c) * P;
+                    const cd* Mr = sM + (c * P + k) * P;     // rows k >= p are zero
+#pragma unroll
+                    for (int m = 0; m < P; ++m) {
+                        const cd t = Mr[m];
+                        const cd s = a[m];
+                        cmac(bx, by, t.x, t.y, s.x, s.y);
+                    }
                 }
             }
             res[i] = cd{bx, by};
