@@ -171,6 +171,15 @@ def run_single(wl, args, dev, kernel="gaussian"):
     v = torch.empty(wl.n, dtype=torch.float64, device=dev)
     plan = fm.Plan(wl.n, wl.sigma, wl.p, wl.depth, domain=(wl.x0, wl.y0, wl.width),
                    precision=wl.precision, fp32_fine_levels=wl.fp32_fine_levels, kernel=kernel)
+    default_tuning = plan.tuning()
+    tune = None
+    if not args.no_autotune:
+        # the launch shape the library's own autotuner picks for this problem
+        # (seeded by the work model); outside the timed region
+        t0 = time.perf_counter()
+        plan.autotune(x, y, g, u, v, reps=2)
+        tune = {"default": default_tuning, "chosen": plan.tuning(), **plan.autotune_report(),
+                "seconds": round(time.perf_counter() - t0, 3)}
     for _ in range(args.warmup):
         plan.evaluate(x, y, g, u, v, check=False)
     torch.cuda.synchronize()
@@ -186,7 +195,7 @@ def run_single(wl, args, dev, kernel="gaussian"):
     res = {"sec": sec, "stage_ms": stage_ms, "near_pairs": pn, "m2l_pairs": pm,
            "roofline": roofline_of(stage_ms, pn, pm, wl.p, "f64" if wl.precision == "fp64" else "f32",
                                    f"{wl.name}_{wl.precision}"),
-           "u": u, "v": v, "tuning": plan.tuning()}
+           "u": u, "v": v, "tuning": plan.tuning(), "autotune": tune}
     plan.close()
     return res
 
@@ -574,7 +583,7 @@ def run_forms(wl, res, args, dev):
     forms["mixed"] = {"workload": describe(wm), "ms": round(rm["sec"] * 1e3, 4), "value": wm.n / rm["sec"],
                       "speedup_vs_fp64": res["sec"] / rm["sec"],
                       "stages_ms": {k: round(x, 4) for k, x in rm["stage_ms"].items()},
-                      "roofline": rm["roofline"], "tuning": rm["tuning"]}
+                      "roofline": rm["roofline"], "tuning": rm["tuning"], "autotune": rm["autotune"]}
     forms["_mixed_uv"] = (rm["u"], rm["v"])
     del rm
     # the Lamb-Oseen workload in FP64
@@ -582,7 +591,7 @@ def run_forms(wl, res, args, dev):
     r2 = run_single(w2, args, dev)
     forms["c2_fp64"] = {"workload": describe(w2), "ms": round(r2["sec"] * 1e3, 4), "value": w2.n / r2["sec"],
                         "stages_ms": {k: round(x, 4) for k, x in r2["stage_ms"].items()},
-                        "roofline": r2["roofline"]}
+                        "roofline": r2["roofline"], "tuning": r2["tuning"], "autotune": r2["autotune"]}
     forms["_c2"] = (r2["u"], r2["v"], w2)
     # the batched form
     w4 = workloads.make("C4")
@@ -646,6 +655,8 @@ def main() -> int:
                     help="precision of the headline workload (default: FP64 for C5, the workload's own otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-forms", action="store_true", help="skip the mixed, C2 and batched forms")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the default launch shape instead of the autotuner's choice")
     ap.add_argument("--extra-forms", action="store_true",
                     help="also time time stepping, the singular kernel, target points, Lennard-Jones, the fast "
                          "Gauss transform and the 3D form")
@@ -719,6 +730,7 @@ def main() -> int:
         "stages_ms": {k: round(x, 4) for k, x in res["stage_ms"].items()},
         "work": {"near_pairs": res["near_pairs"], "m2l_pairs": res["m2l_pairs"]},
         "tuning": res["tuning"],
+        "autotune": res.get("autotune"),
         "roofline": res["roofline"],
     }
     if not args.no_cpu_baseline and not batched:
