@@ -19,6 +19,9 @@ LIB = os.path.join(HERE, "libfmm_mi355x.so")
 # a host program that drives the library through the C ABI alone
 EXAMPLE_SRC = os.path.join(HERE, "examples", "fmm_eval_file.cpp")
 EXAMPLE = os.path.join(HERE, "fmm_eval_file")
+# the register-only FMA loop that measures the sustained FMA rate
+FMA_PROBE_SRC = os.path.join(HERE, "examples", "fma_issue_rate.cpp")
+FMA_PROBE = os.path.join(HERE, "fma_issue_rate")
 
 SOURCES = ["fmm_api.cpp", "fmm_tables.cpp", "fmm_tree.hip", "fmm_upward.hip", "fmm_downward.hip",
            "fmm_near.hip", "fmm_step.hip", "fmm_fgt.hip", "fmm3d.hip", "fmm3d_api.cpp", "fmm_static.hip", "fmm_batch.hip"]
@@ -65,6 +68,11 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"example build failed:\n{r.stderr}")
     os.replace(EXAMPLE + ".tmp", EXAMPLE)
+    cmd = [hipcc(), *COMMON, "-x", "hip", FMA_PROBE_SRC, "-o", FMA_PROBE + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"FMA probe build failed:\n{r.stderr}")
+    os.replace(FMA_PROBE + ".tmp", FMA_PROBE)
     if verbose:
         print(f"built {LIB}")
     return LIB
