@@ -177,7 +177,7 @@ def run_single(wl, args, dev, kernel="gaussian"):
         # the launch shape the library's own autotuner picks for this problem
         # (seeded by the work model); outside the timed region
         t0 = time.perf_counter()
-        plan.autotune(x, y, g, u, v, reps=2)
+        plan.autotune(x, y, g, u, v, reps=3)
         tune = {"default": default_tuning, "chosen": plan.tuning(), **plan.autotune_report(),
                 "seconds": round(time.perf_counter() - t0, 3)}
     for _ in range(args.warmup):
