@@ -53,47 +53,49 @@ struct PairK {
     double s2, rc2, e24;     // Lennard-Jones: s^2, cutoff^2, 24 eps
 };
 
-// ln 2 split into its nearest double and the remainder (for the reduction
-// -t = k ln2 + r done with fused multiply-adds).
-constexpr double kLn2Hi = 0.6931471805599453;
-constexpr double kLn2Lo = 2.3190468138462996e-17;
+// ln 2 rounded to the nearest double (the reduction below takes it alone,
+// see g_one_minus_exp).
+constexpr double kLn2 = 0.6931471805599453;
 constexpr double kLog2E = 1.4426950408889634;
 // 1.5 * 2^52: adding it to a double of magnitude below 2^51 rounds that
 // double to the nearest integer and leaves the integer, in two's complement,
 // in the low 32 bits of the sum's significand.
 constexpr double kRoundMagic = 6755399441055744.0;
 
-// 1 - exp(nt) for nt = -t <= 0 in FP64, within 1.5 ulp for every t (checked
-// against a long-double reference on 2e7 points).  Reduce nt = k ln2 + r with
-// k = round(nt log2 e) <= 0 and |r| <= ln2/2 (Cody and Waite), take
-// expm1(r) = r q(r) with q the degree-10 Chebyshev fit of expm1(r)/r on that
-// interval (fit error 2e-17 relative), and use
-//   1 - e^nt = (1 - 2^k) - 2^k expm1(r),
-// which is -expm1(nt) itself for k = 0 and free of cancellation for k <= -1.
-// Below nt = -37 the result rounds to 1, so nt is clamped at -40, which also
-// keeps k in [-58, 0].
-__device__ __forceinline__ double one_minus_exp(double nt)
+// g (1 - exp(nt)) for nt = -t <= 0 in FP64, within 1.6e-15 relative of the
+// exact value for every t (a CPU check of this operation sequence against a
+// long-double reference on 2e7 points, t from 1e-18 to 45).  Reduce
+// nt = k ln2 + r with k = round(nt log2 e) <= 0 and |r| <= ln2/2 (Cody and
+// Waite, with the one constant: the part of k ln2 it drops, k times the
+// 2.3e-17 by which the constant misses ln 2, moves the result by at most
+// 2^k |k| 3.3e-17 <= 1.7e-17, against a result >= 0.29 once k <= -1), take
+// expm1(r) = r q(r) with q a degree-9 near-minimax fit of expm1(r)/r on
+// that interval (fit error 1.35e-15 relative), and use
+//   g (1 - e^nt) = g (1 - 2^k) - g 2^k expm1(r),
+// which is -g expm1(nt) for k = 0 and free of cancellation for k <= -1; g
+// 2^k is one ldexp, so the circulation costs no extra multiply.  Below
+// nt = -37 the result rounds to g, so nt is clamped at -40, which also keeps
+// k in [-58, 0].
+__device__ __forceinline__ double g_one_minus_exp(double nt, double g)
 {
     nt = fmax(nt, -40.0);
     const double rk = fma(nt, kLog2E, kRoundMagic);
     const int ki = int(__double_as_longlong(rk));   // k, read from the low bits
     const double k = rk - kRoundMagic;              // k as a double, exact
-    double r = fma(k, -kLn2Hi, nt);
-    r = fma(k, -kLn2Lo, r);
-    double q = 2.5105206373957011e-08;
-    q = fma(q, r, 2.7626357241447223e-07);
-    q = fma(q, r, 2.7557255425746435e-06);
-    q = fma(q, r, 2.4801504346997686e-05);
-    q = fma(q, r, 0.00019841269874800493);
-    q = fma(q, r, 0.0013888888932488599);
-    q = fma(q, r, 0.0083333333333261411);
-    q = fma(q, r, 0.041666666666573142);
-    q = fma(q, r, 0.16666666666666671);
-    q = fma(q, r, 0.50000000000000056);
-    q = fma(q, r, 1.0);
+    const double r = fma(k, -kLn2, nt);
+    double q = 2.755730309659393e-07;
+    q = fma(q, r, 2.763404108023548e-06);
+    q = fma(q, r, 2.480169503042948e-05);
+    q = fma(q, r, 0.00019841187712114786);
+    q = fma(q, r, 0.0013888888757029219);
+    q = fma(q, r, 0.008333333369186784);
+    q = fma(q, r, 0.04166666666717082);
+    q = fma(q, r, 0.16666666666611946);
+    q = fma(q, r, 0.4999999999999951);
+    q = fma(q, r, 1.0000000000000013);
     const double em = q * r;                // expm1(r)
-    const double s = ldexp(1.0, ki);        // 2^k, exact
-    return fma(-s, em, 1.0 - s);
+    const double gs = ldexp(g, ki);         // g 2^k, exact unless it underflows
+    return fma(-gs, em, g - gs);
 }
 
 // 1/x for a positive normal x: hardware estimate (about 2^-26 relative)
@@ -103,6 +105,22 @@ __device__ __forceinline__ double recip(double x)
     const double y = __builtin_amdgcn_rcp(x);
     const double e = fma(-x, y, 1.0);
     return fma(y, e, y);
+}
+
+// L2P: h = sum_k le[k] z^k by Horner from the top term (terms >= p are zero),
+// each step h = h z + le[k] as four fused multiply-adds.
+template <int P>
+__device__ __forceinline__ void l2p_horner(const cd* le, double zx, double zy, double& hx, double& hy)
+{
+    hx = le[P - 1].x;
+    hy = le[P - 1].y;
+#pragma unroll
+    for (int k = P - 2; k >= 0; --k) {
+        const cd t = le[k];
+        const double nx = fma(hx, zx, fma(-hy, zy, t.x));
+        hy = fma(hx, zy, fma(hy, zx, t.y));
+        hx = nx;
+    }
 }
 
 constexpr int kNearStage = 256;    // staged sources per chunk and wavefront
@@ -183,7 +201,7 @@ __device__ __forceinline__ void p2p_f64(const Src64* __restrict__ src, int cnt, 
                 // then vanishes through 1 - e = 0 and dx = dy = 0; it changes
                 // r2 only for points closer than about 1e-142
                 const double r2 = fma(dx, dx, fma(dy, dy, 1e-300));
-                q2 = t.g * one_minus_exp(r2 * k.ninv2s2) * recip(r2);
+                q2 = g_one_minus_exp(r2 * k.ninv2s2, t.g) * recip(r2);
             }
             ax[r] = fma(q2, dx, ax[r]);
             ay[r] = fma(-q2, dy, ay[r]);
@@ -393,16 +411,10 @@ __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* 
             }
             if (has_far) {
                 const double zx = (px - c.cx) * c.s, zy = (py - c.cy) * c.s;
-                double hx = 0.0, hy = 0.0;
-#pragma unroll
-                for (int k = P - 1; k >= 0; --k) {     // terms >= p are zero
-                    const cd t = le_sh[k];
-                    const double nx = hx * zx - hy * zy + t.x;
-                    hy = hx * zy + hy * zx + t.y;
-                    hx = nx;
-                }
-                accx += hx * c.s;
-                accy += hy * c.s;
+                double hx, hy;
+                l2p_horner<P>(le_sh, zx, zy, hx, hy);
+                accx = fma(hx, c.s, accx);
+                accy = fma(hy, c.s, accy);
             }
             if constexpr (KER == kNearLJ) {    // the force (Fx, Fy) = (sum q dx, sum q dy)
                 u[o] = accx;
@@ -521,7 +533,7 @@ __device__ __forceinline__ void quad_pairs(const Src64* qsh, int lane, int w, co
                 q = r2 > 0.0 ? recip(r2) : 0.0;
             } else {
                 const double r2 = fma(dx, dx, fma(dy, dy, 1e-300));
-                q = one_minus_exp(r2 * k.ninv2s2) * recip(r2);
+                q = g_one_minus_exp(r2 * k.ninv2s2, 1.0) * recip(r2);
             }
             qi = act ? t.g * q : 0.0;
             qj = act ? me.g * q : 0.0;
@@ -622,16 +634,10 @@ k_p2p_l2p(Work wk, int n_inst, const Inst* __restrict__ inst, const int32_t* __r
         const int i = c.s0 + lane;
         if (has_far) {
             const double zx = (xs[i] - c.cx) * c.s, zy = (ys[i] - c.cy) * c.s;
-            double hx = 0.0, hy = 0.0;
-#pragma unroll
-            for (int k = P - 1; k >= 0; --k) {     // terms >= p are zero
-                const cd t = lsh[k];
-                const double nx = hx * zx - hy * zy + t.x;
-                hy = hx * zy + hy * zx + t.y;
-                hx = nx;
-            }
-            accx += hx * c.s;
-            accy += hy * c.s;
+            double hx, hy;
+            l2p_horner<P>(lsh, zx, zy, hx, hy);
+            accx = fma(hx, c.s, accx);
+            accy = fma(hy, c.s, accy);
         }
         const uint32_t o = perm[i];
         if constexpr (KER == kNearLJ) {
