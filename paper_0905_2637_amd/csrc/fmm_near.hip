@@ -27,8 +27,11 @@
 // sums are combined with cross-lane shuffles.  Leaves with more than 64
 // particles are walked in target chunks of 64.
 //
-// FP64: 1 - exp(-t) and the reciprocal are evaluated inline (polynomial and
-// Newton-refined hardware estimate) instead of library calls.
+// FP64: the Gaussian factor, as 1 - 2^(r^2 (-log2 e / 2 sigma^2)), and the
+// reciprocal are evaluated inline (polynomial and Newton-refined hardware
+// estimate) instead of library calls.  Differences are taken between
+// physical positions, exact for nearby points, so a pair's term keeps its
+// relative accuracy however close the pair is.
 //
 // Mixed precision: sources and targets are FP32 offsets from their own leaf
 // centre in leaf-width units; a source's leaf offset (-1, 0 or +1 per axis)
@@ -49,51 +52,41 @@ struct Src64 { double x, y, g; };
 
 // Constants of the pair kernel (uniform over a launch).
 struct PairK {
-    double ninv2s2;          // Gaussian core: -1 / (2 sigma^2)
+    double nl2;              // Gaussian core: -log2(e) / (2 sigma^2), so exp(-r^2/2s^2) = 2^(nl2 r^2)
     double s2, rc2, e24;     // Lennard-Jones: s^2, cutoff^2, 24 eps
 };
 
-// ln 2 rounded to the nearest double (the reduction below takes it alone,
-// see g_one_minus_exp).
-constexpr double kLn2 = 0.6931471805599453;
-constexpr double kLog2E = 1.4426950408889634;
-// 1.5 * 2^52: adding it to a double of magnitude below 2^51 rounds that
-// double to the nearest integer and leaves the integer, in two's complement,
-// in the low 32 bits of the sum's significand.
-constexpr double kRoundMagic = 6755399441055744.0;
-
-// g (1 - exp(nt)) for nt = -t <= 0 in FP64, within 1.6e-15 relative of the
-// exact value for every t (a CPU check of this operation sequence against a
-// long-double reference on 2e7 points, t from 1e-18 to 45).  Reduce
-// nt = k ln2 + r with k = round(nt log2 e) <= 0 and |r| <= ln2/2 (Cody and
-// Waite, with the one constant: the part of k ln2 it drops, k times the
-// 2.3e-17 by which the constant misses ln 2, moves the result by at most
-// 2^k |k| 3.3e-17 <= 1.7e-17, against a result >= 0.29 once k <= -1), take
-// expm1(r) = r q(r) with q a degree-9 near-minimax fit of expm1(r)/r on
-// that interval (fit error 1.35e-15 relative), and use
-//   g (1 - e^nt) = g (1 - 2^k) - g 2^k expm1(r),
-// which is -g expm1(nt) for k = 0 and free of cancellation for k <= -1; g
-// 2^k is one ldexp, so the circulation costs no extra multiply.  Below
-// nt = -37 the result rounds to g, so nt is clamped at -40, which also keeps
-// k in [-58, 0].
-__device__ __forceinline__ double g_one_minus_exp(double nt, double g)
+// g (1 - 2^x) for x <= 0 in FP64, within 1.5e-15 relative of the exact
+// value for every x (a CPU check of this operation sequence against a
+// long-double reference on 2e7 points, x from -1e-18 to -70).  Split x = k +
+// f with k = rint(x) and f = x - k, both exact, |f| <= 1/2; take 2^f - 1 =
+// f q(f) with q a degree-9 near-minimax fit of (2^f - 1)/f on [-1/2, 1/2]
+// (fit error 1.25e-15 relative), and use
+//   g (1 - 2^x) = g (1 - 2^k) - g 2^k (2^f - 1),
+// which is -g (2^f - 1) for k = 0 and free of cancellation for k <= -1; g 2^k
+// is one ldexp, so the circulation costs no extra multiply.  No clamp is
+// needed: f stays in [-1/2, 1/2] for every x (x - rint(x) is exact, and 0
+// once |x| >= 2^52), and the hardware conversion of k to an integer
+// saturates, so for k below -2^31 the ldexp gives 0 and the result is g.
+__device__ __forceinline__ double g_one_minus_exp2(double x, double g)
 {
-    nt = fmax(nt, -40.0);
-    const double rk = fma(nt, kLog2E, kRoundMagic);
-    const int ki = int(__double_as_longlong(rk));   // k, read from the low bits
-    const double k = rk - kRoundMagic;              // k as a double, exact
-    const double r = fma(k, -kLn2, nt);
-    double q = 2.755730309659393e-07;
-    q = fma(q, r, 2.763404108023548e-06);
-    q = fma(q, r, 2.480169503042948e-05);
-    q = fma(q, r, 0.00019841187712114786);
-    q = fma(q, r, 0.0013888888757029219);
-    q = fma(q, r, 0.008333333369186784);
-    q = fma(q, r, 0.04166666666717082);
-    q = fma(q, r, 0.16666666666611946);
-    q = fma(q, r, 0.4999999999999951);
-    q = fma(q, r, 1.0000000000000013);
-    const double em = q * r;                // expm1(r)
+    const double k = __builtin_rint(x);
+    const double f = x - k;
+    int ki;
+    // the instruction's own saturation (a C++ conversion would be undefined
+    // out of range)
+    asm("v_cvt_i32_f64 %0, %1" : "=v"(ki) : "v"(k));
+    double q = 7.054911498517923e-09;
+    q = fma(q, f, 1.0205975487818139e-07);
+    q = fma(q, f, 1.3215542376478124e-06);
+    q = fma(q, f, 1.5252672644100859e-05);
+    q = fma(q, f, 0.00015403530253982429);
+    q = fma(q, f, 0.0013333558201124075);
+    q = fma(q, f, 0.009618129107737676);
+    q = fma(q, f, 0.055504108664650574);
+    q = fma(q, f, 0.24022650695909853);
+    q = fma(q, f, 0.6931471805599462);
+    const double em = q * f;                // 2^f - 1
     const double gs = ldexp(g, ki);         // g 2^k, exact unless it underflows
     return fma(-gs, em, g - gs);
 }
@@ -198,10 +191,10 @@ __device__ __forceinline__ void p2p_f64(const Src64* __restrict__ src, int cnt, 
                 q2 = r2 > 0.0 ? t.g * recip(r2) : 0.0;
             } else {
                 // 1e-300 keeps r2 positive for coincident points, whose term
-                // then vanishes through 1 - e = 0 and dx = dy = 0; it changes
-                // r2 only for points closer than about 1e-142
+                // then vanishes through 1 - 2^0 = 0 and dx = dy = 0; it
+                // changes r2 only for points closer than about 1e-142
                 const double r2 = fma(dx, dx, fma(dy, dy, 1e-300));
-                q2 = g_one_minus_exp(r2 * k.ninv2s2, t.g) * recip(r2);
+                q2 = g_one_minus_exp2(r2 * k.nl2, t.g) * recip(r2);
             }
             ax[r] = fma(q2, dx, ax[r]);
             ay[r] = fma(-q2, dy, ay[r]);
@@ -450,7 +443,6 @@ __device__ __forceinline__ void make_ctx(LeafCtx& c, uint32_t m, int L, const in
                                          const Domain& d, const PairK& k, bool no_siblings,
                                          const uint8_t* __restrict__ bt)
 {
-    const double inv2s2 = -k.ninv2s2;
     c.k = k;
     c.m = m;
     c.s0 = leaf_start[m];
@@ -477,7 +469,7 @@ __device__ __forceinline__ void make_ctx(LeafCtx& c, uint32_t m, int L, const in
     c.s = d.s;
     // leaf-width units: |z|^2 / (2 sigma^2) = |zhat|^2 w^2 / (2 sigma^2), and
     // exp(-t) = 2^(-t log2(e)); w = 1/s
-    c.c2 = float(inv2s2 * 1.4426950408889634074 / (d.s * d.s));
+    c.c2 = float(-k.nl2 / (d.s * d.s));
 }
 
 // register blocking pays once a chunk is full; sparse leaves keep one target
@@ -533,7 +525,7 @@ __device__ __forceinline__ void quad_pairs(const Src64* qsh, int lane, int w, co
                 q = r2 > 0.0 ? recip(r2) : 0.0;
             } else {
                 const double r2 = fma(dx, dx, fma(dy, dy, 1e-300));
-                q = g_one_minus_exp(r2 * k.ninv2s2, 1.0) * recip(r2);
+                q = g_one_minus_exp2(r2 * k.nl2, 1.0) * recip(r2);
             }
             qi = act ? t.g * q : 0.0;
             qj = act ? me.g * q : 0.0;
@@ -683,7 +675,10 @@ k_p2p_at(int L, const Inst* __restrict__ inst, const int32_t* __restrict__ leaf_
 PairK pair_constants(const NearKernel& nk)
 {
     PairK k{};
-    if (nk.kind == kNearGauss) k.ninv2s2 = -1.0 / (2.0 * nk.sigma * nk.sigma);
+    if (nk.kind == kNearGauss) {
+        const double l2 = 1.4426950408889634074 / (2.0 * nk.sigma * nk.sigma);
+        k.nl2 = -l2;
+    }
     if (nk.kind == kNearLJ) {
         k.s2 = nk.sigma * nk.sigma;
         k.rc2 = nk.cutoff * nk.cutoff;

@@ -238,6 +238,24 @@ def test_coincident_particles():
     assert oracle.rel_l2(u, v, uo, vo) < FP64_TOL
 
 
+@pytest.mark.parametrize("sigma", [1e-6, 1e-9])
+def test_core_far_below_leaf_width(sigma):
+    """The FP64 Gaussian factor is 1 - 2^x with x = -r^2 log2(e) / (2 sigma^2).
+    With the core far below the leaf width (depth 4, w = 1/16) x reaches
+    about -3e9 (sigma 1e-6: its integer part past the 32-bit range, where
+    the conversion must saturate) and -3e15 (sigma 1e-9: past 2^52, where x
+    has no fraction); the factor must come out exactly 1 there.  A row of
+    particles 0.7 sigma apart keeps the Gaussian itself in play."""
+    x, y, g = workloads.uniform_square(3000, 41)
+    x[1:20] = x[0] + sigma * 0.7 * np.arange(1, 20)
+    y[1:20] = y[0]
+    u, v, _ = run(x, y, g, sigma, 12, 4)
+    uo, vo = oracle.fmm(x, y, g, sigma, 12, 4)
+    assert np.all(np.isfinite(u)) and np.all(np.isfinite(v))
+    assert oracle.rel_l2(u, v, uo, vo) < FP64_TOL
+    assert oracle.rel_l2(u[20:], v[20:], uo[20:], vo[20:]) < FP64_TOL
+
+
 def test_out_of_domain_points_are_counted():
     """Points outside an explicit domain are clamped into the nearest leaf,
     counted, and computed exactly as the oracle computes them."""
