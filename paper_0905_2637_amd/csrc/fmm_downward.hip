@@ -15,7 +15,9 @@
 // the scalar/L1 caches.  The multipole arrays already hold abar (the upward
 // sweep stores them that way), so only the output scaling 1/l! remains.  The
 // product is dense: every (k, l) pair is one complex multiply-add, 8 p^2
-// flops per interaction-list pair.
+// flops per interaction-list pair; in FP64 the members are taken two at a
+// time where the square's symmetries relate their data, which halves that
+// (see the work items below).
 //
 // Lane mapping: a workgroup of 4 wavefronts covers 16 x 16 target boxes of
 // one level; wavefront c holds the 64 boxes in child position c of their
@@ -44,15 +46,226 @@ __host__ __device__ inline int level_blocks(int l)
 // round-robin placement on 1M-64M particle trees.
 constexpr int kM2LXcdRun = 8;
 
+// FP64 M2L by symmetric pairs.  The Hankel data of two offsets related by a
+// symmetry of the square differ only by conjugation and the sign
+// (-1)^(n+1): h_n(conj tau) = conj h_n(tau), h_n(-tau) = (-1)^(n+1) h_n(tau).
+// For such a pair (tau, tau') with sources A and B, and S = A + B, D = A - B,
+//   tau' = conj tau:   h A + h' B = u S + i v D                  (h = u + i v)
+//   tau' = -conj tau:  the same for n odd, u D + i v S for n even
+//   tau' = -tau, real: u S for n odd, u D for n even
+// so one complex multiply-add (four FMAs, two for a real tau) serves two
+// list members.  On an axis or a diagonal the data of one offset have a zero
+// component (tau real: all real; tau = i y: imaginary for n even, real for n
+// odd; tau = a (1 + i s), s = +-1: real or imaginary for n odd, and for n
+// even u and v of equal size, v = s u for n = 2 mod 4 and -s u for n = 0 mod
+// 4), so a single member costs two FMAs per term there: with p = ax - s ay
+// and q = ax + s ay, b += u p + i v q (n = 2 mod 4) or u q + i v p (n = 0 mod
+// 4).  The 27 offsets of child (0, 0), dx, dy in [-2, 3] and not both in
+// [-1, 1], make 15 work items: 9 conjugate pairs, 2 negated-conjugate pairs,
+// the real pair (-2, 0), (2, 0), and (3, 0), (0, 3), (3, 3) alone; the
+// other children mirror them (dx -> -dx for child x = 1, dy -> -dy for
+// y = 1), which keeps every relation.  Against 27 general members (4 FMAs
+// per term each) the items take 52 / 108 of the FMAs.
+enum : int { kItemConj = 0, kItemNegConj = 1, kItemNegReal = 2, kItemOneReal = 3, kItemOneImag = 4, kItemOneDiag = 5 };
+constexpr int kM2LItems = 15;
+// largest P with the paired form (the five unrolled item bodies of larger
+// expansions outgrow the instruction cache)
+constexpr int kM2LPairedMaxP = 20;
+__constant__ int8_t kM2LItemTab[kM2LItems][3] = {
+    {-2, 1, kItemConj}, {2, 1, kItemConj}, {3, 1, kItemConj}, {-2, 2, kItemConj}, {2, 2, kItemConj},
+    {3, 2, kItemConj}, {-1, 2, kItemConj}, {0, 2, kItemConj}, {1, 2, kItemConj},
+    {-2, 3, kItemNegConj}, {-1, 3, kItemNegConj},
+    {-2, 0, kItemNegReal}, {3, 0, kItemOneReal},
+    {0, 3, kItemOneImag}, {3, 3, kItemOneDiag},
+};
+
+// The terms of a box that does not exist: lanes whose source lies outside
+// the level read these zeros, so that every load is unconditional.
+__device__ cd m2l_zero_box[32];
+
+// Work items run in blocks of kM2LK consecutive source terms k, with the
+// next block's loads in flight while the current block's products run: two
+// blocks of both members and the 2P accumulators fit the registers of three
+// wavefronts per SIMD.  (Carrying the next item's first block across the
+// item loop as well made the compiler spill.)
+constexpr int kM2LK = 4;
+struct M2LBlock {
+    cd a[kM2LK], b[kM2LK];
+};
+
+template <int P, bool TWO>
+__device__ __forceinline__ void m2l_load(M2LBlock& r, const cd* sa, const cd* sb, int k0)
+{
+#pragma unroll
+    for (int kk = 0; kk < kM2LK; ++kk) {
+        if (k0 + kk < P) {                  // abar_k, zero for k >= p
+            r.a[kk] = sa[k0 + kk];
+            if (TWO) r.b[kk] = sb[k0 + kk];
+        }
+    }
+}
+
+// The products of one block (terms k0 .. k0 + kM2LK - 1) of a work item of
+// kind KIND with Hankel data h; s = dy / dx for a diagonal.
+template <int P, int KIND>
+__device__ __forceinline__ void m2l_block(double* bx, double* by, const cplx<double>* __restrict__ h,
+                                          const M2LBlock& r, int k0, double s)
+{
+    constexpr int K = kM2LK;
+    const int nk = k0 + K <= P ? K : P - k0;
+    if constexpr (KIND <= kItemNegReal) {
+        double Sx[K], Sy[K], Dx[K], Dy[K];
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk) {
+            if (kk < nk) {
+                Sx[kk] = r.a[kk].x + r.b[kk].x;
+                Sy[kk] = r.a[kk].y + r.b[kk].y;
+                Dx[kk] = r.a[kk].x - r.b[kk].x;
+                Dy[kk] = r.a[kk].y - r.b[kk].y;
+            }
+        }
+#pragma unroll
+        for (int nn = 0; nn < 2 * P - 1; ++nn) {
+            if (nn < k0 || nn > k0 + nk + P - 2) continue;
+            const cplx<double> hn = h[nn];
+            const double u = hn.x, v = hn.y;
+#pragma unroll
+            for (int kk = 0; kk < K; ++kk) {
+                const int j = nn - k0 - kk;
+                if (kk >= nk || j < 0 || j >= P) continue;
+                if (KIND == kItemNegReal) {
+                    const double X = (nn & 1) ? Sx[kk] : Dx[kk], Y = (nn & 1) ? Sy[kk] : Dy[kk];
+                    bx[j] = fma(u, X, bx[j]);
+                    by[j] = fma(u, Y, by[j]);
+                } else if (KIND == kItemConj || (nn & 1)) {
+                    bx[j] = fma(u, Sx[kk], fma(-v, Dy[kk], bx[j]));
+                    by[j] = fma(u, Sy[kk], fma(v, Dx[kk], by[j]));
+                } else {
+                    bx[j] = fma(u, Dx[kk], fma(-v, Sy[kk], bx[j]));
+                    by[j] = fma(u, Dy[kk], fma(v, Sx[kk], by[j]));
+                }
+            }
+        }
+    } else {
+        // a single member: n odd first with the source as it is, then n even
+        // with (p, q) = (ax - s ay, ax + s ay) in its place (diagonal)
+        double ax[K], ay[K];
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk) {
+            if (kk < nk) {
+                ax[kk] = r.a[kk].x;
+                ay[kk] = r.a[kk].y;
+            }
+        }
+#pragma unroll
+        for (int par = 1; par >= 0; --par) {
+            if (KIND == kItemOneDiag && par == 0) {
+#pragma unroll
+                for (int kk = 0; kk < K; ++kk) {
+                    if (kk < nk) {
+                        const double pk = fma(-s, ay[kk], ax[kk]), qk = fma(s, ay[kk], ax[kk]);
+                        ax[kk] = pk;
+                        ay[kk] = qk;
+                    }
+                }
+            }
+#pragma unroll
+            for (int nn = par; nn < 2 * P - 1; nn += 2) {
+                if (nn < k0 || nn > k0 + nk + P - 2) continue;
+                const cplx<double> hn = h[nn];
+                const double u = hn.x, v = hn.y;
+#pragma unroll
+                for (int kk = 0; kk < K; ++kk) {
+                    const int j = nn - k0 - kk;
+                    if (kk >= nk || j < 0 || j >= P) continue;
+                    if (KIND == kItemOneImag ? par == 1 : (nn & 3) == 3) {        // real data
+                        bx[j] = fma(u, ax[kk], bx[j]);
+                        by[j] = fma(u, ay[kk], by[j]);
+                    } else if (KIND == kItemOneImag || (nn & 3) == 1) {          // imaginary data
+                        bx[j] = fma(-v, ay[kk], bx[j]);
+                        by[j] = fma(v, ax[kk], by[j]);
+                    } else if ((nn & 3) == 2) {                                  // diagonal, v = s u
+                        bx[j] = fma(u, ax[kk], bx[j]);
+                        by[j] = fma(v, ay[kk], by[j]);
+                    } else {                                                     // diagonal, v = -s u
+                        bx[j] = fma(u, ay[kk], bx[j]);
+                        by[j] = fma(v, ax[kk], by[j]);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// The work items it0 <= it < it1 (all of kind KIND, or kItemNegReal with
+// the single (3, 0) among them) that workgroup row g of G takes, for child
+// (cx, cy); src(dx, dy) gives the terms of the source box at offset (dx,
+// dy), or zeros where there is none, and zero points at zeros.  One loop per
+// kind, so that the items of different kinds do not share (and lengthen)
+// register live ranges.
+template <int P, int KIND, typename Src>
+__device__ __forceinline__ void m2l_kind64(double* bx, double* by, const cplx<double>* __restrict__ H, int cx,
+                                           int cy, int g, int G, int it0, int it1, Src src, const cd* zero)
+{
+    constexpr int NH = 2 * P - 1;
+    constexpr bool TWO = KIND <= kItemNegReal;
+    constexpr int NB = (P + kM2LK - 1) / kM2LK;
+    int it = it0 + (g - it0 % G + G) % G;
+    if (it >= it1) return;
+    auto locate = [&](int i, const cd*& pa, const cd*& pb, const cplx<double>*& ph, double& sg) {
+        int dx = kM2LItemTab[i][0], dy = kM2LItemTab[i][1];
+        const bool pair = kM2LItemTab[i][2] != kItemOneReal;
+        if (cx) dx = -dx;
+        if (cy) dy = -dy;
+        ph = H + ((dy + 3) * kHankelGrid + (dx + 3)) * NH;
+        pa = src(dx, dy);
+        pb = TWO && pair ? src(KIND == kItemConj ? dx : -dx, KIND == kItemNegConj ? dy : -dy) : zero;
+        sg = dx == dy ? 1.0 : -1.0;
+    };
+    for (; it < it1; it += G) {
+        const cd *sa, *sb;
+        const cplx<double>* h;
+        double sg;
+        locate(it, sa, sb, h, sg);
+        M2LBlock cur;
+        m2l_load<P, TWO>(cur, sa, sb, 0);
+#pragma unroll
+        for (int blk = 0; blk < NB; ++blk) {
+            M2LBlock nxt;
+            if (blk + 1 < NB) m2l_load<P, TWO>(nxt, sa, sb, (blk + 1) * kM2LK);
+            // the loads above go out before this block's products
+            __builtin_amdgcn_sched_barrier(0);
+            m2l_block<P, KIND>(bx, by, h, cur, blk * kM2LK, sg);
+            __builtin_amdgcn_sched_barrier(0);
+            if (blk + 1 < NB) cur = nxt;
+        }
+    }
+}
+
+// All 15 work items of row g of G (the table's kinds in order).
+template <int P, typename Src>
+__device__ __forceinline__ void m2l_items64(double* bx, double* by, const cplx<double>* __restrict__ H, int cx, int cy,
+                                            int g, int G, Src src, const cd* zero)
+{
+    m2l_kind64<P, kItemConj>(bx, by, H, cx, cy, g, G, 0, 9, src, zero);
+    m2l_kind64<P, kItemNegConj>(bx, by, H, cx, cy, g, G, 9, 11, src, zero);
+    m2l_kind64<P, kItemNegReal>(bx, by, H, cx, cy, g, G, 11, 13, src, zero);
+    m2l_kind64<P, kItemOneImag>(bx, by, H, cx, cy, g, G, 13, 14, src, zero);
+    m2l_kind64<P, kItemOneDiag>(bx, by, H, cx, cy, g, G, 14, 15, src, zero);
+}
+
 // gridDim.y = G in {1, 2, 3}: workgroup row g takes every G-th member of the
-// interaction list and writes its partial sum to out[g] (out[0] = le).
+// interaction list (FP64: every G-th work item) and writes its partial sum
+// to out[g] (out[0] = le).
 struct M2LOut {
     cd* out[3];
 };
 
 // Work table arg: the instance's level range [lmin, lmax] in this launch.
+// (three wavefronts per SIMD: the FP64 accumulators and one work item's
+// staged terms fit in 168 registers)
 template <int P, typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 k_m2l(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restrict__ me_all, M2LOut dst_,
       const cplx<T>* __restrict__ H, const double* __restrict__ sout_)
 {
@@ -126,7 +339,14 @@ k_m2l(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restrict__
         return Hs + ((dy + 3) * kHankelGrid + (dx + 3)) * NH;
     };
 
-    if constexpr (!kF32) {
+    if constexpr (!kF32 && P <= kM2LPairedMaxP) {
+        // FP64: symmetric pairs of members (the work items above)
+        m2l_items64<P>(bx_, by_, H, cx, cy, g, G, [&](int dx, int dy) -> const cd* {
+            const int sa = ta + dx, sb = tb + dy;
+            const bool ok = active && sa >= 0 && sb >= 0 && sa < side && sb < side;
+            return ok ? me_l + int64_t(morton(uint32_t(sa), uint32_t(sb))) * P : m2l_zero_box;
+        }, m2l_zero_box);
+    } else if constexpr (!kF32) {
         // FP64: all p source terms of a member at once (a software prefetch
         // of the next member measured no faster)
         T ax[P], ay[P];
@@ -224,6 +444,7 @@ k_m2l64_lds(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __rest
 {
     constexpr int NH = 2 * P - 1;
     __shared__ cd sA[kHalo * kHalo * P];
+    __shared__ cd sZero[P];
     const int lin = xcd_runs(int(blockIdx.x + gridDim.x * blockIdx.y), int(gridDim.x * gridDim.y), kM2LXcdRun);
     const int g = lin / int(gridDim.x), blk = lin % int(gridDim.x);
     if (blk >= wk.wg_begin[n_inst]) return;                // past the launch's work (batched plans)
@@ -248,6 +469,7 @@ k_m2l64_lds(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __rest
         const cd v = me_l[int64_t(morton(uint32_t(in ? sa : 0), uint32_t(in ? sb : 0))) * P + k];
         sA[e] = in ? v : cd{0.0, 0.0};
     }
+    for (int k = threadIdx.x; k < P; k += 256) sZero[k] = cd{0.0, 0.0};
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -258,8 +480,16 @@ k_m2l64_lds(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __rest
     double bx_[P], by_[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) { bx_[k] = 0.0; by_[k] = 0.0; }
+    if constexpr (P <= kM2LPairedMaxP) {
+        // the same work items as k_m2l, the sources from the stage
+        // every member lies in the stage; zeros for the one item without a
+        // partner
+        m2l_items64<P>(bx_, by_, H, cx, cy, g, G, [&](int dx, int dy) -> const cd* {
+            return sA + ((tb + dy - y_lo) * kHalo + (ta + dx - x_lo)) * P;
+        }, sZero);
+    }
     int member = 0;
-    for (int o = 0; o < 36; ++o) {
+    for (int o = 0; o < (P <= kM2LPairedMaxP ? 0 : 36); ++o) {
         int dx, dy;
         if (!il_offset(cx, cy, o, dx, dy)) continue;
         if ((member++) % G != g) continue;
