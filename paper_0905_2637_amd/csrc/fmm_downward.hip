@@ -29,6 +29,7 @@
 #include "fmm_device.h"
 
 #include <type_traits>
+#include <utility>
 
 namespace fmm {
 namespace {
@@ -79,10 +80,6 @@ __constant__ int8_t kM2LItemTab[kM2LItems][3] = {
     {0, 3, kItemOneImag}, {3, 3, kItemOneDiag},
 };
 
-// The terms of a box that does not exist: lanes whose source lies outside
-// the level read these zeros, so that every load is unconditional.
-__device__ cd m2l_zero_box[32];
-
 // Work items run in blocks of kM2LK consecutive source terms k, with the
 // next block's loads in flight while the current block's products run: two
 // blocks of both members and the 2P accumulators fit the registers of three
@@ -92,18 +89,6 @@ constexpr int kM2LK = 4;
 struct M2LBlock {
     cd a[kM2LK], b[kM2LK];
 };
-
-template <int P, bool TWO>
-__device__ __forceinline__ void m2l_load(M2LBlock& r, const cd* sa, const cd* sb, int k0)
-{
-#pragma unroll
-    for (int kk = 0; kk < kM2LK; ++kk) {
-        if (k0 + kk < P) {                  // abar_k, zero for k >= p
-            r.a[kk] = sa[k0 + kk];
-            if (TWO) r.b[kk] = sb[k0 + kk];
-        }
-    }
-}
 
 // The products of one block (terms k0 .. k0 + kM2LK - 1) of a work item of
 // kind KIND with Hankel data h; s = dy / dx for a diagonal.
@@ -197,61 +182,57 @@ __device__ __forceinline__ void m2l_block(double* bx, double* by, const cplx<dou
     }
 }
 
-// The work items it0 <= it < it1 (all of kind KIND, or kItemNegReal with
-// the single (3, 0) among them) that workgroup row g of G takes, for child
-// (cx, cy); src(dx, dy) gives the terms of the source box at offset (dx,
-// dy), or zeros where there is none, and zero points at zeros.  One loop per
-// kind, so that the items of different kinds do not share (and lengthen)
-// register live ranges.
-template <int P, int KIND, typename Src>
-__device__ __forceinline__ void m2l_kind64(double* bx, double* by, const cplx<double>* __restrict__ H, int cx,
-                                           int cy, int g, int G, int it0, int it1, Src src, const cd* zero)
+// Block k0 .. k0 + kM2LK - 1 of the work items it0 <= it < it1 (all of kind
+// KIND, or kItemNegReal with the single (3, 0) among them) that workgroup row
+// g of G takes, for child (cx, cy): slot(dx, dy) names the source box at
+// offset (dx, dy), term(slot, k) reads its term k, and zero_slot is a box of
+// zeros (the partner of the item that has none).  K0 is a template argument:
+// the accumulators are indexed by it and must stay in registers.
+template <int P, int KIND, int K0, typename Slot, typename Term>
+__device__ __forceinline__ void m2l_kind_block(double* bx, double* by, const cplx<double>* __restrict__ H, int cx,
+                                               int cy, int g, int G, int it0, int it1, int zero_slot, Slot slot,
+                                               Term term)
 {
     constexpr int NH = 2 * P - 1;
-    constexpr bool TWO = KIND <= kItemNegReal;
-    constexpr int NB = (P + kM2LK - 1) / kM2LK;
-    int it = it0 + (g - it0 % G + G) % G;
-    if (it >= it1) return;
-    auto locate = [&](int i, const cd*& pa, const cd*& pb, const cplx<double>*& ph, double& sg) {
-        int dx = kM2LItemTab[i][0], dy = kM2LItemTab[i][1];
-        const bool pair = kM2LItemTab[i][2] != kItemOneReal;
+    for (int it = it0 + (g - it0 % G + G) % G; it < it1; it += G) {
+        int dx = kM2LItemTab[it][0], dy = kM2LItemTab[it][1];
+        const bool pair = kM2LItemTab[it][2] != kItemOneReal;
         if (cx) dx = -dx;
         if (cy) dy = -dy;
-        ph = H + ((dy + 3) * kHankelGrid + (dx + 3)) * NH;
-        pa = src(dx, dy);
-        pb = TWO && pair ? src(KIND == kItemConj ? dx : -dx, KIND == kItemNegConj ? dy : -dy) : zero;
-        sg = dx == dy ? 1.0 : -1.0;
-    };
-    for (; it < it1; it += G) {
-        const cd *sa, *sb;
-        const cplx<double>* h;
-        double sg;
-        locate(it, sa, sb, h, sg);
-        M2LBlock cur;
-        m2l_load<P, TWO>(cur, sa, sb, 0);
+        const cplx<double>* h = H + ((dy + 3) * kHankelGrid + (dx + 3)) * NH;
+        const int ia = slot(dx, dy);
+        const int ib = KIND <= kItemNegReal && pair
+                           ? slot(KIND == kItemConj ? dx : -dx, KIND == kItemNegConj ? dy : -dy)
+                           : zero_slot;
+        M2LBlock r;
 #pragma unroll
-        for (int blk = 0; blk < NB; ++blk) {
-            M2LBlock nxt;
-            if (blk + 1 < NB) m2l_load<P, TWO>(nxt, sa, sb, (blk + 1) * kM2LK);
-            // the loads above go out before this block's products
-            __builtin_amdgcn_sched_barrier(0);
-            m2l_block<P, KIND>(bx, by, h, cur, blk * kM2LK, sg);
-            __builtin_amdgcn_sched_barrier(0);
-            if (blk + 1 < NB) cur = nxt;
+        for (int kk = 0; kk < kM2LK; ++kk) {
+            if (K0 + kk < P) {                  // abar_k, zero for k >= p
+                r.a[kk] = term(ia, K0 + kk);
+                if (KIND <= kItemNegReal) r.b[kk] = term(ib, K0 + kk);
+            }
         }
+        m2l_block<P, KIND>(bx, by, h, r, K0, dx == dy ? 1.0 : -1.0);
     }
 }
 
-// All 15 work items of row g of G (the table's kinds in order).
-template <int P, typename Src>
-__device__ __forceinline__ void m2l_items64(double* bx, double* by, const cplx<double>* __restrict__ H, int cx, int cy,
-                                            int g, int G, Src src, const cd* zero)
+// Block K0 of all 15 work items of row g of G (the table's kinds in order).
+template <int P, int K0, typename Slot, typename Term>
+__device__ __forceinline__ void m2l_items_block(double* bx, double* by, const cplx<double>* __restrict__ H, int cx,
+                                                int cy, int g, int G, int zero_slot, Slot slot, Term term)
 {
-    m2l_kind64<P, kItemConj>(bx, by, H, cx, cy, g, G, 0, 9, src, zero);
-    m2l_kind64<P, kItemNegConj>(bx, by, H, cx, cy, g, G, 9, 11, src, zero);
-    m2l_kind64<P, kItemNegReal>(bx, by, H, cx, cy, g, G, 11, 13, src, zero);
-    m2l_kind64<P, kItemOneImag>(bx, by, H, cx, cy, g, G, 13, 14, src, zero);
-    m2l_kind64<P, kItemOneDiag>(bx, by, H, cx, cy, g, G, 14, 15, src, zero);
+    m2l_kind_block<P, kItemConj, K0>(bx, by, H, cx, cy, g, G, 0, 9, zero_slot, slot, term);
+    m2l_kind_block<P, kItemNegConj, K0>(bx, by, H, cx, cy, g, G, 9, 11, zero_slot, slot, term);
+    m2l_kind_block<P, kItemNegReal, K0>(bx, by, H, cx, cy, g, G, 11, 13, zero_slot, slot, term);
+    m2l_kind_block<P, kItemOneImag, K0>(bx, by, H, cx, cy, g, G, 13, 14, zero_slot, slot, term);
+    m2l_kind_block<P, kItemOneDiag, K0>(bx, by, H, cx, cy, g, G, 14, 15, zero_slot, slot, term);
+}
+
+// f(std::integral_constant<int, c>) for c = 0 .. sizeof...(C) - 1, in order.
+template <typename F, int... C>
+__device__ __forceinline__ void m2l_for_chunks(F f, std::integer_sequence<int, C...>)
+{
+    (f(std::integral_constant<int, C>{}), ...);
 }
 
 // gridDim.y = G in {1, 2, 3}: workgroup row g takes every G-th member of the
@@ -339,14 +320,7 @@ k_m2l(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restrict__
         return Hs + ((dy + 3) * kHankelGrid + (dx + 3)) * NH;
     };
 
-    if constexpr (!kF32 && P <= kM2LPairedMaxP) {
-        // FP64: symmetric pairs of members (the work items above)
-        m2l_items64<P>(bx_, by_, H, cx, cy, g, G, [&](int dx, int dy) -> const cd* {
-            const int sa = ta + dx, sb = tb + dy;
-            const bool ok = active && sa >= 0 && sb >= 0 && sa < side && sb < side;
-            return ok ? me_l + int64_t(morton(uint32_t(sa), uint32_t(sb))) * P : m2l_zero_box;
-        }, m2l_zero_box);
-    } else if constexpr (!kF32) {
+    if constexpr (!kF32) {
         // FP64: all p source terms of a member at once (a software prefetch
         // of the next member measured no faster)
         T ax[P], ay[P];
@@ -443,8 +417,7 @@ k_m2l64_lds(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __rest
             const cplx<double>* __restrict__ H, const double* __restrict__ sout_)
 {
     constexpr int NH = 2 * P - 1;
-    __shared__ cd sA[kHalo * kHalo * P];
-    __shared__ cd sZero[P];
+    __shared__ cd sA[(kHalo * kHalo + 1) * P];        // + a box of zeros
     const int lin = xcd_runs(int(blockIdx.x + gridDim.x * blockIdx.y), int(gridDim.x * gridDim.y), kM2LXcdRun);
     const int g = lin / int(gridDim.x), blk = lin % int(gridDim.x);
     if (blk >= wk.wg_begin[n_inst]) return;                // past the launch's work (batched plans)
@@ -469,7 +442,7 @@ k_m2l64_lds(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __rest
         const cd v = me_l[int64_t(morton(uint32_t(in ? sa : 0), uint32_t(in ? sb : 0))) * P + k];
         sA[e] = in ? v : cd{0.0, 0.0};
     }
-    for (int k = threadIdx.x; k < P; k += 256) sZero[k] = cd{0.0, 0.0};
+    for (int k = threadIdx.x; k < P; k += 256) sA[kHalo * kHalo * P + k] = cd{0.0, 0.0};
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -481,12 +454,12 @@ k_m2l64_lds(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __rest
 #pragma unroll
     for (int k = 0; k < P; ++k) { bx_[k] = 0.0; by_[k] = 0.0; }
     if constexpr (P <= kM2LPairedMaxP) {
-        // the same work items as k_m2l, the sources from the stage
-        // every member lies in the stage; zeros for the one item without a
-        // partner
-        m2l_items64<P>(bx_, by_, H, cx, cy, g, G, [&](int dx, int dy) -> const cd* {
-            return sA + ((tb + dy - y_lo) * kHalo + (ta + dx - x_lo)) * P;
-        }, sZero);
+        // the work items block by block, in the order of k_m2l64_chunks
+        auto slot = [&](int dx, int dy) { return (tb + dy - y_lo) * kHalo + (ta + dx - x_lo); };
+        auto term = [&](int sl, int k) { return sA[sl * P + k]; };
+        m2l_for_chunks([&](auto c) {
+            m2l_items_block<P, decltype(c)::value * kM2LK>(bx_, by_, H, cx, cy, g, G, kHalo * kHalo, slot, term);
+        }, std::make_integer_sequence<int, (P + kM2LK - 1) / kM2LK>{});
     }
     int member = 0;
     for (int o = 0; o < (P <= kM2LPairedMaxP ? 0 : 36); ++o) {
@@ -512,6 +485,78 @@ k_m2l64_lds(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __rest
             }
         }
     }
+    if (active) {
+        cd* dst = le + (level_offset(l) + int64_t(morton(uint32_t(ta), uint32_t(tb)))) * P;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const double sc = sout_[k];
+            dst[k] = cd{bx_[k] * sc, by_[k] * sc};
+        }
+    }
+}
+
+// FP64 M2L by symmetric pairs with the workgroup's sources staged in LDS
+// kM2LK terms at a time: the 16 x 16 targets of a workgroup draw every
+// source from the 20 x 20 boxes around them, so chunk c holds terms 4c ..
+// 4c + 3 of those 400 boxes (25.6 KB, k-major, zeros outside the level and
+// past p, one zero box at the end for the item without a partner) and every
+// wavefront runs block c of all its work items from it.  The loads of a
+// chunk are coalesced and shared by the workgroup's 256 targets instead of
+// issued per lane and member; the same items and block order as k_m2l64_lds,
+// so the two give the same bits.
+template <int P>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_m2l64_chunks(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restrict__ me_all, M2LOut dst_,
+               const cplx<double>* __restrict__ H, const double* __restrict__ sout_)
+{
+    constexpr int NB = (P + kM2LK - 1) / kM2LK;
+    constexpr int NBOX = kHalo * kHalo;
+    __shared__ cd sA[kM2LK][NBOX + 1];
+    const int lin = xcd_runs(int(blockIdx.x + gridDim.x * blockIdx.y), int(gridDim.x * gridDim.y), kM2LXcdRun);
+    const int g = lin / int(gridDim.x), blk = lin % int(gridDim.x);
+    if (blk >= wk.wg_begin[n_inst]) return;                // past the launch's work (batched plans)
+    const int pos = find_inst(wk.wg_begin, n_inst, blk);
+    const int q = wk.order[pos];
+    const int G = min(int(gridDim.y), inst[q].g64);
+    if (g >= G) return;
+    int bl = blk - wk.wg_begin[pos];
+    int l = wk.arg[2 * pos];
+    while (bl >= level_blocks(l)) { bl -= level_blocks(l); ++l; }
+    const cd* me = me_all + inst[q].box_off * P;
+    cd* __restrict__ le = g == 0 ? dst_.out[0] + inst[q].box_off * P : dst_.out[g] + inst[q].split_off * P;
+    const int side = 1 << l;
+    const int bpr = side >= 16 ? side / 16 : 1;
+    const int bx = bl % bpr, by = bl / bpr;
+    const cd* me_l = me + level_offset(l) * P;
+    const int x_lo = 16 * bx - 2, y_lo = 16 * by - 2;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int cx = wave & 1, cy = wave >> 1;
+    const int ta = 2 * (bx * 8 + (lane & 7)) + cx;
+    const int tb = 2 * (by * 8 + (lane >> 3)) + cy;
+    const bool active = ta < side && tb < side;
+    constexpr int NH = 2 * P - 1;
+    double bx_[P], by_[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) { bx_[k] = 0.0; by_[k] = 0.0; }
+    // halo slot of the source at offset (dx, dy) from this lane's target
+    auto slot = [&](int dx, int dy) { return (tb + dy - y_lo) * kHalo + (ta + dx - x_lo); };
+    m2l_for_chunks([&](auto c) {
+        constexpr int k0 = decltype(c)::value * kM2LK;
+        if (k0 > 0) __syncthreads();                        // every wavefront is done with the last chunk
+        for (int e = threadIdx.x; e < NBOX * kM2LK; e += 256) {
+            const int hb = e / kM2LK, kk = e - hb * kM2LK;  // a box's terms from consecutive threads
+            const int sa = x_lo + hb % kHalo, sb = y_lo + hb / kHalo;
+            const bool in = sa >= 0 && sb >= 0 && sa < side && sb < side && k0 + kk < P;
+            cd v{0.0, 0.0};
+            if (in) v = me_l[int64_t(morton(uint32_t(sa), uint32_t(sb))) * P + k0 + kk];
+            sA[kk][hb] = v;
+        }
+        if (threadIdx.x < kM2LK) sA[threadIdx.x][NBOX] = cd{0.0, 0.0};
+        __syncthreads();
+        // block c of every work item of this row
+        m2l_items_block<P, k0>(bx_, by_, H, cx, cy, g, G, NBOX, slot, [&](int sl, int k) { return sA[k - k0][sl]; });
+    }, std::make_integer_sequence<int, NB>{});
     if (active) {
         cd* dst = le + (level_offset(l) + int64_t(morton(uint32_t(ta), uint32_t(tb)))) * P;
 #pragma unroll
@@ -925,6 +970,11 @@ hipError_t m2l_impl(const Buffers& b, const Work& w, int nwg, bool fp32, bool mf
                                reinterpret_cast<const cplx<double>*>(b.t_h64), b.t_sout);
             return hipGetLastError();
         }
+    }
+    if constexpr (P <= kM2LPairedMaxP) {
+        hipLaunchKernelGGL((k_m2l64_chunks<P>), grid, dim3(256), 0, st, w, b.n_inst, b.inst, b.me, out,
+                           reinterpret_cast<const cplx<double>*>(b.t_h64), b.t_sout);
+        return hipGetLastError();
     }
     hipLaunchKernelGGL((k_m2l<P, double>), grid, dim3(256), 0, st, w, b.n_inst, b.inst, b.me, out,
                        reinterpret_cast<const cplx<double>*>(b.t_h64), b.t_sout);
