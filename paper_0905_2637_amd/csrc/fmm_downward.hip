@@ -544,13 +544,24 @@ k_m2l64_chunks(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __r
     m2l_for_chunks([&](auto c) {
         constexpr int k0 = decltype(c)::value * kM2LK;
         if (k0 > 0) __syncthreads();                        // every wavefront is done with the last chunk
-        for (int e = threadIdx.x; e < NBOX * kM2LK; e += 256) {
+        // every load issued before the first LDS write (one memory round
+        // trip); outside the level, past p and past the stage: the level's
+        // first term is read and replaced by zero
+        constexpr int NE = NBOX * kM2LK, NIT = (NE + 255) / 256;
+        cd v[NIT];
+#pragma unroll
+        for (int i = 0; i < NIT; ++i) {
+            const int e = int(threadIdx.x) + 256 * i;
             const int hb = e / kM2LK, kk = e - hb * kM2LK;  // a box's terms from consecutive threads
             const int sa = x_lo + hb % kHalo, sb = y_lo + hb / kHalo;
-            const bool in = sa >= 0 && sb >= 0 && sa < side && sb < side && k0 + kk < P;
-            cd v{0.0, 0.0};
-            if (in) v = me_l[int64_t(morton(uint32_t(sa), uint32_t(sb))) * P + k0 + kk];
-            sA[kk][hb] = v;
+            const bool in = e < NE && sa >= 0 && sb >= 0 && sa < side && sb < side && k0 + kk < P;
+            v[i] = me_l[in ? int64_t(morton(uint32_t(sa), uint32_t(sb))) * P + k0 + kk : 0];
+            if (!in) v[i] = cd{0.0, 0.0};
+        }
+#pragma unroll
+        for (int i = 0; i < NIT; ++i) {
+            const int e = int(threadIdx.x) + 256 * i;
+            if (e < NE) sA[e % kM2LK][e / kM2LK] = v[i];
         }
         if (threadIdx.x < kM2LK) sA[threadIdx.x][NBOX] = cd{0.0, 0.0};
         __syncthreads();
