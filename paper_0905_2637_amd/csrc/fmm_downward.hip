@@ -435,12 +435,20 @@ k_m2l64_lds(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __rest
     const int bx = bl % bpr, by = bl / bpr;
     const cd* me_l = me + level_offset(l) * P;
     const int x_lo = 16 * bx - 2, y_lo = 16 * by - 2;
-    for (int e = threadIdx.x; e < kHalo * kHalo * P; e += 256) {
-        const int hb = e / P, k = e - hb * P;
-        const int sa = x_lo + hb % kHalo, sb = y_lo + hb / kHalo;
-        const bool in = sa >= 0 && sb >= 0 && sa < side && sb < side;
-        const cd v = me_l[int64_t(morton(uint32_t(in ? sa : 0), uint32_t(in ? sb : 0))) * P + k];
-        sA[e] = in ? v : cd{0.0, 0.0};
+    // eight loads in flight per thread before their LDS writes
+    for (int e0 = threadIdx.x; e0 < kHalo * kHalo * P; e0 += 256 * 8) {
+        cd v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + 256 * u, hb = e / P, k = e - hb * P;
+            const int sa = x_lo + hb % kHalo, sb = y_lo + hb / kHalo;
+            const bool in = e < kHalo * kHalo * P && sa >= 0 && sb >= 0 && sa < side && sb < side;
+            v[u] = me_l[in ? int64_t(morton(uint32_t(sa), uint32_t(sb))) * P + k : 0];
+            if (!in) v[u] = cd{0.0, 0.0};
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (e0 + 256 * u < kHalo * kHalo * P) sA[e0 + 256 * u] = v[u];
     }
     for (int k = threadIdx.x; k < P; k += 256) sA[kHalo * kHalo * P + k] = cd{0.0, 0.0};
     __syncthreads();
@@ -646,13 +654,26 @@ k_m2l_mfma(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restr
 
     // stage the 20 x 20 source boxes from (16 bx - 2, 16 by - 2) on
     const int ox = 16 * bx - 2, oy = 16 * by - 2;
-    for (int e = tid; e < kMfmaHalo * kMfmaHalo * P; e += 256) {
-        const int box = e / P, k = e % P;
-        const int sa = ox + box % kMfmaHalo, sb = oy + box / kMfmaHalo;
-        cd v{0.0, 0.0};
-        if (sa >= 0 && sb >= 0 && sa < side && sb < side) v = me_l[int64_t(morton(uint32_t(sa), uint32_t(sb))) * P + k];
-        hal[box * HS + k] = float(v.x);
-        hal[box * HS + P + k] = float(v.y);
+    // eight loads in flight per thread before their LDS writes
+    constexpr int NHAL = kMfmaHalo * kMfmaHalo * P;
+    for (int e0 = tid; e0 < NHAL; e0 += 256 * 8) {
+        cd v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + 256 * u, box = e / P, k = e % P;
+            const int sa = ox + box % kMfmaHalo, sb = oy + box / kMfmaHalo;
+            const bool in = e < NHAL && sa >= 0 && sb >= 0 && sa < side && sb < side;
+            v[u] = me_l[in ? int64_t(morton(uint32_t(sa), uint32_t(sb))) * P + k : 0];
+            if (!in) v[u] = cd{0.0, 0.0};
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + 256 * u, box = e / P, k = e % P;
+            if (e < NHAL) {
+                hal[box * HS + k] = float(v[u].x);
+                hal[box * HS + P + k] = float(v[u].y);
+            }
+        }
     }
     __syncthreads();
 
