@@ -24,7 +24,7 @@
 // count so every lane runs the same, unrollable trip count.  Register
 // blocking: a lane owns R targets and one of S interleaved slices of the
 // staged sources, so each LDS read feeds R pair interactions; the S partial
-// sums are combined with cross-lane shuffles.  Leaves with more than 64
+// sums meet through LDS.  Leaves with more than 64
 // particles are walked in target chunks of 64.
 //
 // FP64: the Gaussian factor, as 1 - 2^(r^2 (-log2 e / 2 sigma^2)), and the
@@ -238,8 +238,6 @@ __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* 
     const int TG = c.TG;             // target groups
     const int S = c.S;               // source slices
     const int T = R * TG;            // targets per chunk
-    // power-of-two groups filling the wavefront: slices meet by xor shuffles
-    const bool pow2 = (TG & (TG - 1)) == 0 && TG * S == 64;
     // lane / TG without an integer division: the float quotient is within
     // 2e-5 of lane / TG (lane < 64, TG <= 64), and a non-multiple lies at
     // least 1/64 above an integer
@@ -325,33 +323,13 @@ __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* 
             else p2p_f64<R, KER>(src, cnt, S, si, c.k, xi, yi, ax, ay);
         }
 
-        // combine the S slices.  Power-of-two groups: xor shuffles leave the
-        // sums in every lane of the group.  Otherwise through the staging
-        // area: every slice lane writes its partial sums, and the lane that
-        // finishes target r of a group adds the S partial sums in slice order.
+        // combine the S slices through the staging area: every slice lane
+        // writes its partial sums, and the lane that finishes target r of a
+        // group adds the S partial sums in slice order.  (Cross-lane xor
+        // shuffles, log2(S) rounds per target and component, measured slower
+        // for every layout of the C2, C3 and C5 workloads.)
         double sx[R], sy[R];
-        if (pow2) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if constexpr (MIXED) {
-                    float vx = fx[r], vy = fy[r];
-                    for (int off = TG; off < 64; off <<= 1) {
-                        vx += __shfl_xor(vx, off, 64);
-                        vy += __shfl_xor(vy, off, 64);
-                    }
-                    sx[r] = double(vx) * c.s;   // leaf units -> physical: 1/(w z) = s/z
-                    sy[r] = double(vy) * c.s;
-                } else {
-                    double vx = ax[r], vy = ay[r];
-                    for (int off = TG; off < 64; off <<= 1) {
-                        vx += __shfl_xor(vx, off, 64);
-                        vy += __shfl_xor(vy, off, 64);
-                    }
-                    sx[r] = vx;
-                    sy[r] = vy;
-                }
-            }
-        } else {
+        {
             using Part = typename std::conditional<MIXED, float2, cd>::type;
             Part* red = static_cast<Part*>(stage_raw);   // S TG R partial sums: within the staging area
             wave_sync();                                 // every lane is done with the staged sources
