@@ -69,9 +69,6 @@ constexpr int kM2LXcdRun = 8;
 // per term each) the items take 52 / 108 of the FMAs.
 enum : int { kItemConj = 0, kItemNegConj = 1, kItemNegReal = 2, kItemOneReal = 3, kItemOneImag = 4, kItemOneDiag = 5 };
 constexpr int kM2LItems = 15;
-// largest P with the paired form (the five unrolled item bodies of larger
-// expansions outgrow the instruction cache)
-constexpr int kM2LPairedMaxP = 20;
 __constant__ int8_t kM2LItemTab[kM2LItems][3] = {
     {-2, 1, kItemConj}, {2, 1, kItemConj}, {3, 1, kItemConj}, {-2, 2, kItemConj}, {2, 2, kItemConj},
     {3, 2, kItemConj}, {-1, 2, kItemConj}, {0, 2, kItemConj}, {1, 2, kItemConj},
@@ -242,36 +239,30 @@ struct M2LOut {
     cd* out[3];
 };
 
-// Work table arg: the instance's level range [lmin, lmax] in this launch.
-// (three wavefronts per SIMD: the FP64 accumulators and one work item's
-// staged terms fit in 168 registers)
+// FP32 M2L on the vector units (T = float; FP64 levels take the paired
+// kernels below).  Work table arg: the instance's level range [lmin, lmax]
+// in this launch.
 template <int P, typename T>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(256)
 k_m2l(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restrict__ me_all, M2LOut dst_,
       const cplx<T>* __restrict__ H, const double* __restrict__ sout_)
 {
-    // FP32 (fine levels, the bulk of the pairs): the translation data of all
-    // 49 offset slots is staged once per workgroup and read back as LDS
-    // broadcasts, and the source terms are applied in blocks of at most 8;
-    // both keep the register count down (more wavefronts per SIMD).  FP64
-    // reads the data through scalar loads and applies all terms at once,
-    // which measured faster there.
-    constexpr bool kF32 = std::is_same<T, float>::value;
+    // the translation data of all 49 offset slots is staged once per
+    // workgroup and read back as LDS broadcasts, and the source terms are
+    // applied in blocks of at most 8; both keep the register count down (more
+    // wavefronts per SIMD)
+    static_assert(std::is_same<T, float>::value, "FP64 M2L runs in k_m2l64_chunks / k_m2l64_lds");
     constexpr int NH = 2 * P - 1;
-    __shared__ cplx<T> sH[kF32 ? kHankelGrid * kHankelGrid * NH : 1];
+    __shared__ cplx<T> sH[kHankelGrid * kHankelGrid * NH];
     const int lin = xcd_runs(int(blockIdx.x + gridDim.x * blockIdx.y), int(gridDim.x * gridDim.y), kM2LXcdRun);
     const int g = lin / int(gridDim.x), blk = lin % int(gridDim.x);
     if (blk >= wk.wg_begin[n_inst]) return;                // past the launch's work (batched plans)
-    const cplx<T>* Hs = H;
-    if constexpr (kF32) {
-        for (int e = threadIdx.x; e < kHankelGrid * kHankelGrid * NH; e += 256) sH[e] = H[e];
-        __syncthreads();
-        Hs = sH;
-    }
+    for (int e = threadIdx.x; e < kHankelGrid * kHankelGrid * NH; e += 256) sH[e] = H[e];
+    __syncthreads();
+    const cplx<T>* Hs = sH;
     const int pos = find_inst(wk.wg_begin, n_inst, blk);   // place in the launch order
     const int q = wk.order[pos];
-    // a split FP64 launch serves instances split two or three ways
-    const int G = kF32 ? int(gridDim.y) : min(int(gridDim.y), inst[q].g64);
+    const int G = int(gridDim.y);
     if (g >= G) return;
     int bl = blk - wk.wg_begin[pos];
     int l = wk.arg[2 * pos];
@@ -290,7 +281,7 @@ k_m2l(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restrict__
     const cd* me_l = me + level_offset(l) * P;
 
     constexpr int kHStep = 4;                  // FP32: translation values in flight
-    constexpr int NB = kF32 ? (P + 7) / 8 : 1; // input blocks
+    constexpr int NB = (P + 7) / 8;            // input blocks
     constexpr int KB = (P + NB - 1) / NB;      // terms per block
     T bx_[P], by_[P];
 #pragma unroll
@@ -320,41 +311,7 @@ k_m2l(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restrict__
         return Hs + ((dy + 3) * kHankelGrid + (dx + 3)) * NH;
     };
 
-    if constexpr (!kF32) {
-        // FP64: all p source terms of a member at once (a software prefetch
-        // of the next member measured no faster)
-        T ax[P], ay[P];
-        bool ok = false;
-        auto load = [&](int o) {
-            const cd* src = source(o, ok);
-            if (ok) {
-#pragma unroll
-                for (int k = 0; k < P; ++k) {
-                    const cd t = src[k];            // abar_k, zero for k >= p
-                    ax[k] = t.x;
-                    ay[k] = t.y;
-                }
-            }
-        };
-        auto apply = [&](int o) {
-            const cplx<T>* h = table(o);
-            if (ok) {
-#pragma unroll
-                for (int nn = 0; nn < 2 * P - 1; ++nn) {
-                    const cplx<T> hn = h[nn];
-#pragma unroll
-                    for (int k = 0; k < P; ++k) {
-                        const int j = nn - k;
-                        if (j >= 0 && j < P) cmac(bx_[j], by_[j], hn.x, hn.y, ax[k], ay[k]);
-                    }
-                }
-            }
-        };
-        for (int o = next_member(0); o < 36; o = next_member(o + 1)) {
-            load(o);
-            apply(o);
-        }
-    } else {
+    {
         // FP32: source terms in blocks of KB, only one block live next to the
         // P accumulators
         for (int o = next_member(0); o < 36; o = next_member(o + 1)) {
@@ -416,7 +373,6 @@ __global__ void __launch_bounds__(256)
 k_m2l64_lds(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restrict__ me_all, M2LOut dst_,
             const cplx<double>* __restrict__ H, const double* __restrict__ sout_)
 {
-    constexpr int NH = 2 * P - 1;
     __shared__ cd sA[(kHalo * kHalo + 1) * P];        // + a box of zeros
     const int lin = xcd_runs(int(blockIdx.x + gridDim.x * blockIdx.y), int(gridDim.x * gridDim.y), kM2LXcdRun);
     const int g = lin / int(gridDim.x), blk = lin % int(gridDim.x);
@@ -461,38 +417,12 @@ k_m2l64_lds(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __rest
     double bx_[P], by_[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) { bx_[k] = 0.0; by_[k] = 0.0; }
-    if constexpr (P <= kM2LPairedMaxP) {
-        // the work items block by block, in the order of k_m2l64_chunks
-        auto slot = [&](int dx, int dy) { return (tb + dy - y_lo) * kHalo + (ta + dx - x_lo); };
-        auto term = [&](int sl, int k) { return sA[sl * P + k]; };
-        m2l_for_chunks([&](auto c) {
-            m2l_items_block<P, decltype(c)::value * kM2LK>(bx_, by_, H, cx, cy, g, G, kHalo * kHalo, slot, term);
-        }, std::make_integer_sequence<int, (P + kM2LK - 1) / kM2LK>{});
-    }
-    int member = 0;
-    for (int o = 0; o < (P <= kM2LPairedMaxP ? 0 : 36); ++o) {
-        int dx, dy;
-        if (!il_offset(cx, cy, o, dx, dy)) continue;
-        if ((member++) % G != g) continue;
-        const cd* src = sA + ((tb + dy - y_lo) * kHalo + (ta + dx - x_lo)) * P;
-        double ax[P], ay[P];
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
-            const cd t = src[k];
-            ax[k] = t.x;
-            ay[k] = t.y;
-        }
-        const cplx<double>* h = H + ((dy + 3) * kHankelGrid + (dx + 3)) * NH;
-#pragma unroll
-        for (int nn = 0; nn < 2 * P - 1; ++nn) {
-            const cplx<double> hn = h[nn];
-#pragma unroll
-            for (int k = 0; k < P; ++k) {
-                const int j = nn - k;
-                if (j >= 0 && j < P) cmac(bx_[j], by_[j], hn.x, hn.y, ax[k], ay[k]);
-            }
-        }
-    }
+    // the work items block by block, in the order of k_m2l64_chunks
+    auto slot = [&](int dx, int dy) { return (tb + dy - y_lo) * kHalo + (ta + dx - x_lo); };
+    auto term = [&](int sl, int k) { return sA[sl * P + k]; };
+    m2l_for_chunks([&](auto c) {
+        m2l_items_block<P, decltype(c)::value * kM2LK>(bx_, by_, H, cx, cy, g, G, kHalo * kHalo, slot, term);
+    }, std::make_integer_sequence<int, (P + kM2LK - 1) / kM2LK>{});
     if (active) {
         cd* dst = le + (level_offset(l) + int64_t(morton(uint32_t(ta), uint32_t(tb)))) * P;
 #pragma unroll
@@ -513,7 +443,7 @@ k_m2l64_lds(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __rest
 // issued per lane and member; the same items and block order as k_m2l64_lds,
 // so the two give the same bits.
 template <int P>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P > 24 ? 2 : 3)))
 k_m2l64_chunks(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restrict__ me_all, M2LOut dst_,
                const cplx<double>* __restrict__ H, const double* __restrict__ sout_)
 {
@@ -543,7 +473,6 @@ k_m2l64_chunks(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __r
     const int ta = 2 * (bx * 8 + (lane & 7)) + cx;
     const int tb = 2 * (by * 8 + (lane >> 3)) + cy;
     const bool active = ta < side && tb < side;
-    constexpr int NH = 2 * P - 1;
     double bx_[P], by_[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) { bx_[k] = 0.0; by_[k] = 0.0; }
@@ -656,10 +585,11 @@ k_m2l_mfma(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restr
     const int ox = 16 * bx - 2, oy = 16 * by - 2;
     // eight loads in flight per thread before their LDS writes
     constexpr int NHAL = kMfmaHalo * kMfmaHalo * P;
-    for (int e0 = tid; e0 < NHAL; e0 += 256 * 8) {
-        cd v[8];
+    constexpr int NU = 8;
+    for (int e0 = tid; e0 < NHAL; e0 += 256 * NU) {
+        cd v[NU];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < NU; ++u) {
             const int e = e0 + 256 * u, box = e / P, k = e % P;
             const int sa = ox + box % kMfmaHalo, sb = oy + box / kMfmaHalo;
             const bool in = e < NHAL && sa >= 0 && sb >= 0 && sa < side && sb < side;
@@ -667,7 +597,7 @@ k_m2l_mfma(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restr
             if (!in) v[u] = cd{0.0, 0.0};
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < NU; ++u) {
             const int e = e0 + 256 * u, box = e / P, k = e % P;
             if (e < NHAL) {
                 hal[box * HS + k] = float(v[u].x);
@@ -1003,12 +933,7 @@ hipError_t m2l_impl(const Buffers& b, const Work& w, int nwg, bool fp32, bool mf
             return hipGetLastError();
         }
     }
-    if constexpr (P <= kM2LPairedMaxP) {
-        hipLaunchKernelGGL((k_m2l64_chunks<P>), grid, dim3(256), 0, st, w, b.n_inst, b.inst, b.me, out,
-                           reinterpret_cast<const cplx<double>*>(b.t_h64), b.t_sout);
-        return hipGetLastError();
-    }
-    hipLaunchKernelGGL((k_m2l<P, double>), grid, dim3(256), 0, st, w, b.n_inst, b.inst, b.me, out,
+    hipLaunchKernelGGL((k_m2l64_chunks<P>), grid, dim3(256), 0, st, w, b.n_inst, b.inst, b.me, out,
                        reinterpret_cast<const cplx<double>*>(b.t_h64), b.t_sout);
     return hipGetLastError();
 }
