@@ -52,7 +52,8 @@ typedef enum {
     FMM_OK = 0,
     FMM_E_ARG = -1,          /* invalid argument (checked on the host, synchronously) */
     FMM_E_CAPACITY = -2,     /* n larger than the plan's capacity, or workspace too small */
-    FMM_E_DOMAIN = -3,       /* fmm_get_status: particles outside the explicit domain or NaN */
+    FMM_E_DOMAIN = -3,       /* fmm_get_status: particles outside the explicit domain or NaN
+                                (or all of them, the bounding square being wider than 1e36) */
     FMM_E_NOMEM = -4,        /* host allocation failed */
     FMM_E_DEVICE = -5,       /* a HIP runtime call failed */
     FMM_E_UNSUPPORTED = -6   /* valid but not supported combination (e.g. p too large for FP32) */
@@ -108,14 +109,16 @@ typedef enum {
  * (Section 7.1), expansion order p and tree level (Section 7.2). */
 typedef struct {
     int64_t n_max;            /* capacity: largest n passed to fmm_evaluate (>= 0, < 2^31) */
-    double  sigma;            /* Gaussian core size, > 0 (eqs. 5 and 8); ignored by the singular
+    double  sigma;            /* Gaussian core size, >= 1e-30 (eqs. 5 and 8); ignored by the singular
                                  kernel; the length s of the Lennard-Jones kernel; the width
                                  of the Gauss transform's exp(-r^2 / (2 sigma^2)) */
     int32_t p;                /* number of expansion terms, 1 <= p <= 32 (<= 22 in mixed mode;
                                  Hermite terms per axis, <= 16, for the Gauss transform) */
     int32_t depth;            /* leaf level L, 0 <= L <= 13; levels 0..L, 4^L leaves */
-    double  x0, y0, width;    /* domain [x0, x0+width]^2; width <= 0 selects the bounding
-                                 square of the particles, recomputed at every evaluation */
+    double  x0, y0, width;    /* domain [x0, x0+width]^2, width <= 1e36; width <= 0 selects
+                                 the bounding square of the particles, recomputed at every
+                                 evaluation (one wider than 1e36 counts every particle as
+                                 outside, FMM_E_DOMAIN) */
     int32_t precision;        /* an fmm_precision value */
     int32_t fp32_fine_levels; /* mixed mode: M2L at levels > L - fp32_fine_levels runs in
                                  FP32 (0 .. L-1); ignored in FP64 mode */

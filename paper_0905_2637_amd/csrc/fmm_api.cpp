@@ -82,6 +82,7 @@ fmm_status validate_common(const fmm_params* prm)
         return FMM_E_ARG;
     if (prm->kernel != FMM_KERNEL_SINGULAR && (!(prm->sigma > 0.0) || !std::isfinite(prm->sigma)))
         return FMM_E_ARG;
+    if (prm->kernel == FMM_KERNEL_GAUSSIAN && !(prm->sigma >= kMinGaussSigma)) return FMM_E_ARG;
     if (prm->kernel == FMM_KERNEL_LENNARD_JONES) {
         if (!(prm->lj_epsilon > 0.0) || !std::isfinite(prm->lj_epsilon)) return FMM_E_ARG;
         if (!(prm->cutoff > 0.0) || !std::isfinite(prm->cutoff)) return FMM_E_ARG;
@@ -99,6 +100,7 @@ fmm_status validate_common(const fmm_params* prm)
     if (prm->m_max < 0 || prm->m_max > int64_t(0x7fffffff)) return FMM_E_ARG;
     if (prm->width > 0.0) {
         if (!std::isfinite(prm->width) || !std::isfinite(prm->x0) || !std::isfinite(prm->y0)) return FMM_E_ARG;
+        if (prm->width > kMaxWidth) return FMM_E_ARG;
     }
     if (prm->precision == FMM_PREC_MIXED) {
         if (prm->fp32_fine_levels < 0 || prm->fp32_fine_levels > kMaxDepth) return FMM_E_ARG;

@@ -35,6 +35,12 @@ constexpr int kMaxPMixed = 22;      // FP32 translation data overflows beyond th
 constexpr int kHankelGrid = 7;      // integer M2L offsets (dx, dy) with |dx|, |dy| <= 3
 constexpr int kBBoxBlocks = 256;
 constexpr int kMaxInstances = 1 << 16;
+// Widest domain and narrowest Gaussian core: the FP64 near field takes four
+// squared separations, each floored at 1e-76, through one reciprocal of their
+// product, which stays normal for separations below about 1e37; the floor
+// changes a pair term by less than an ulp for sigma >= 1e-30.
+constexpr double kMaxWidth = 1e36;
+constexpr double kMinGaussSigma = 1e-30;
 
 // Number of boxes in levels 0 .. l-1, i.e. the global id of the first box of
 // level l (Section 5.3 counts (4^(L+1) - 1)/3 boxes in a full quadtree).

@@ -100,6 +100,37 @@ __device__ __forceinline__ double recip(double x)
     return fma(y, e, y);
 }
 
+// 1/a[r] for R positive values with one hardware reciprocal (about four
+// times the cost of an FMA): that of their product, refined by one Newton
+// step, times the other factors; a few ulp.  The product must stay normal:
+// every a[r] within [1e-76, 1e75] keeps it so.
+template <int R>
+__device__ __forceinline__ void recip_n(const double* a, double* ia)
+{
+    if constexpr (R == 1) {
+        ia[0] = recip(a[0]);
+    } else if constexpr (R == 2) {
+        const double y = recip(a[0] * a[1]);
+        ia[0] = y * a[1];
+        ia[1] = y * a[0];
+    } else {
+        static_assert(R == 4, "one, two or four values");
+        const double p01 = a[0] * a[1], p23 = a[2] * a[3];
+        const double y = recip(p01 * p23);
+        const double y01 = y * p23, y23 = y * p01;
+        ia[0] = y01 * a[1];
+        ia[1] = y01 * a[0];
+        ia[2] = y23 * a[3];
+        ia[3] = y23 * a[2];
+    }
+}
+
+// Floor of the Gaussian pair term's r^2: positive for coincident points,
+// whose term then vanishes through 1 - 2^0 = 0 and dx = dy = 0.  It changes
+// the term by a relative 1e-76 / sigma^2 at most (below an ulp for sigma >=
+// 1e-30) and keeps four r^2 of separations up to 1e37 within recip_n's range.
+constexpr double kGaussR2Floor = 1e-76;
+
 // L2P: h = sum_k le[k] z^k by Horner from the top term (terms >= p are zero),
 // each step h = h z + le[k] as four fused multiply-adds.
 template <int P>
@@ -176,6 +207,27 @@ template <int R, int KER>
 __device__ __forceinline__ void p2p_f64(const Src64* __restrict__ src, int cnt, int S, int si, const PairK& k,
                                         const double* x, const double* y, double* ax, double* ay)
 {
+    if constexpr (KER == kNearGauss) {
+        // the R targets' 1 / r^2 share one hardware reciprocal
+        for (int jb = 0; jb < cnt; jb += S) {
+            const Src64 t = src[jb + si];
+            double dx[R], dy[R], r2[R], ir[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                dx[r] = x[r] - t.x;
+                dy[r] = y[r] - t.y;
+                r2[r] = fma(dx[r], dx[r], fma(dy[r], dy[r], kGaussR2Floor));
+            }
+            recip_n<R>(r2, ir);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double q2 = g_one_minus_exp2(r2[r] * k.nl2, t.g) * ir[r];
+                ax[r] = fma(q2, dx[r], ax[r]);
+                ay[r] = fma(-q2, dy[r], ay[r]);
+            }
+        }
+        return;
+    }
     for (int jb = 0; jb < cnt; jb += S) {
         const Src64 t = src[jb + si];
 #pragma unroll
@@ -184,17 +236,11 @@ __device__ __forceinline__ void p2p_f64(const Src64* __restrict__ src, int cnt, 
             double q2;
             if constexpr (KER == kNearLJ) {
                 q2 = lj_term(fma(dx, dx, dy * dy), k);   // gamma takes no part
-            } else if constexpr (KER == kNearSingular) {
+            } else {
                 // coincident points by a select: a guard term in r2 would
                 // let gamma / guard overflow for large circulations
                 const double r2 = fma(dx, dx, dy * dy);
                 q2 = r2 > 0.0 ? t.g * recip(r2) : 0.0;
-            } else {
-                // 1e-300 keeps r2 positive for coincident points, whose term
-                // then vanishes through 1 - 2^0 = 0 and dx = dy = 0; it
-                // changes r2 only for points closer than about 1e-142
-                const double r2 = fma(dx, dx, fma(dy, dy, 1e-300));
-                q2 = g_one_minus_exp2(r2 * k.nl2, t.g) * recip(r2);
             }
             ax[r] = fma(q2, dx, ax[r]);
             ay[r] = fma(-q2, dy, ay[r]);
@@ -259,7 +305,9 @@ __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* 
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int i = c0 + tg + TG * r;
-            xi[r] = 0.0; yi[r] = 0.0; oxi[r] = 0.f; oyi[r] = 0.f;
+            // a target past the leaf's count sits at the leaf centre, so that
+            // its distances stay on the leaf's scale (its sums are dropped)
+            xi[r] = c.cx; yi[r] = c.cy; oxi[r] = 0.f; oyi[r] = 0.f;
             ax[r] = 0.0; ay[r] = 0.0; fx[r] = 0.f; fy[r] = 0.f;
             if (i < c.nt) {
                 if constexpr (MIXED) {
@@ -289,7 +337,10 @@ __device__ __forceinline__ void leaf_near_far(const LeafCtx& c, int lane, void* 
 #pragma unroll
             for (int sl = 0; sl < kStageSlots; ++sl) {
                 const int k = lane + 64 * sl;
-                if constexpr (MIXED) val[sl] = make_float4(1.0e4f, 1.0e4f, 0.0f, 0.0f);   // inert
+                // inert slots: no circulation; for the Gaussian kernel at the
+                // leaf centre (distances on the leaf's scale), else far away
+                if constexpr (MIXED) val[sl] = make_float4(1.0e4f, 1.0e4f, 0.0f, 0.0f);
+                else if constexpr (KER == kNearGauss) val[sl] = Src64{c.cx, c.cy, 0.0};
                 else val[sl] = Src64{1.0e10, 1.0e10, 0.0};
                 if (k < cnt) {
                     const int j = base + k;             // position in the neighbourhood run
@@ -497,14 +548,8 @@ __device__ __forceinline__ void quad_pairs(const Src64* qsh, int lane, int w, co
             qi = act ? q : 0.0;
             qj = qi;
         } else {
-            double q;
-            if constexpr (KER == kNearSingular) {
-                const double r2 = fma(dx, dx, dy * dy);
-                q = r2 > 0.0 ? recip(r2) : 0.0;
-            } else {
-                const double r2 = fma(dx, dx, fma(dy, dy, 1e-300));
-                q = g_one_minus_exp2(r2 * k.nl2, 1.0) * recip(r2);
-            }
+            const double r2 = fma(dx, dx, dy * dy);
+            const double q = r2 > 0.0 ? recip(r2) : 0.0;
             qi = act ? t.g * q : 0.0;
             qj = act ? me.g * q : 0.0;
         }
@@ -514,8 +559,34 @@ __device__ __forceinline__ void quad_pairs(const Src64* qsh, int lane, int w, co
         ax += __shfl(-qj * dx, from, 64);
         ay += __shfl(qj * dy, from, 64);
     };
-    for (int k = 0; k < (w == 3 ? 7 : 8); ++k) step(8 * w + 1 + k, true);
-    if (w == 3) step(32, lane < 32);
+    if constexpr (KER == kNearGauss) {
+        // rotations s0 and s0 + 1 together: their 1 / r^2 share one reciprocal
+        auto step2 = [&](int s0, bool act1) {
+            const Src64 t0 = qsh[(lane + s0) & 63], t1 = qsh[(lane + s0 + 1) & 63];
+            const double dx0 = me.x - t0.x, dy0 = me.y - t0.y;
+            const double dx1 = me.x - t1.x, dy1 = me.y - t1.y;
+            double r2[2], ir[2];
+            r2[0] = fma(dx0, dx0, fma(dy0, dy0, kGaussR2Floor));
+            r2[1] = fma(dx1, dx1, fma(dy1, dy1, kGaussR2Floor));
+            recip_n<2>(r2, ir);
+            const double q0 = g_one_minus_exp2(r2[0] * k.nl2, 1.0) * ir[0];
+            const double q1 = g_one_minus_exp2(r2[1] * k.nl2, 1.0) * ir[1];
+            const double qi0 = t0.g * q0, qj0 = me.g * q0;
+            const double qi1 = act1 ? t1.g * q1 : 0.0, qj1 = act1 ? me.g * q1 : 0.0;
+            ax = fma(qi0, dx0, ax);
+            ay = fma(-qi0, dy0, ay);
+            ax += __shfl(-qj0 * dx0, (lane - s0) & 63, 64);
+            ay += __shfl(qj0 * dy0, (lane - s0) & 63, 64);
+            ax = fma(qi1, dx1, ax);
+            ay = fma(-qi1, dy1, ay);
+            ax += __shfl(-qj1 * dx1, (lane - s0 - 1) & 63, 64);
+            ay += __shfl(qj1 * dy1, (lane - s0 - 1) & 63, 64);
+        };
+        for (int k = 0; k < 4; ++k) step2(8 * w + 1 + 2 * k, w != 3 || k != 3 || lane < 32);
+    } else {
+        for (int k = 0; k < (w == 3 ? 7 : 8); ++k) step(8 * w + 1 + k, true);
+        if (w == 3) step(32, lane < 32);
+    }
     sx = ax;
     sy = ay;
 }
@@ -573,11 +644,13 @@ k_p2p_l2p(Work wk, int n_inst, const Inst* __restrict__ inst, const int32_t* __r
 
     LeafCtx c;
     make_ctx(c, uint32_t(mm), L, leaf_start, d, kp, true, bt);
-    // stage the quad, one particle per lane (past nq: inert, far away and
-    // without circulation)
+    // stage the quad, one particle per lane; past nq inert padding without
+    // circulation: for the Gaussian kernel on the last particle (distances
+    // stay on the quad's scale), else far away
     if (wv == 0) {
         const int i = sq + min(lane, nq - 1);
-        qsh[lane] = lane < nq ? Src64{xs[i], ys[i], gs[i]} : Src64{1.0e10, 1.0e10, 0.0};
+        const Src64 pad = KER == kNearGauss ? Src64{xs[i], ys[i], 0.0} : Src64{1.0e10, 1.0e10, 0.0};
+        qsh[lane] = lane < nq ? Src64{xs[i], ys[i], gs[i]} : pad;
     }
     __syncthreads();
     // the leaf's targets against the neighbours outside the quad

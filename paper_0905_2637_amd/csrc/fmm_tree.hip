@@ -204,8 +204,9 @@ __device__ __forceinline__ int particle_inst(const Inst* __restrict__ inst, int 
 // keys per thread, which measured faster there.
 
 // First pass: the sort key of every particle (kept in input order for
-// inspection), the out-of-domain count of the tile, and the tile's histogram
-// of the lowest digit.
+// inspection), the out-of-domain count of the tile (every particle counts
+// when the domain is wider than kMaxWidth), and the tile's histogram of the
+// lowest digit.
 template <int TPB>
 __global__ void __launch_bounds__(TPB)
 k_rhist_keys(int n, const double* __restrict__ x, const double* __restrict__ y, const Inst* __restrict__ inst,
@@ -243,7 +244,7 @@ k_rhist_keys(int n, const double* __restrict__ x, const double* __restrict__ y, 
             const int L = inst[q].L;
             const Domain d = inst[q].dom;
             const int side = 1 << L;
-            bool bad = false;
+            bool bad = !(d.W <= kMaxWidth);    // a bounding square wider than the limit
             const int a = axis_box(xv[r], d.x0, d.s, side, bad);
             const int b = axis_box(yv[r], d.y0, d.s, side, bad);
             const uint32_t k = (uint32_t(q) << key_shift) | (morton(uint32_t(a), uint32_t(b)) << (key_shift - 2 * L));

@@ -73,10 +73,20 @@ def test_workspace_size_grows_with_problem(lib):
     (dict(depth=4, precision="mixed", fp32_fine_levels=4), fm.FMM_E_ARG),
     (dict(m_max=-1), fm.FMM_E_ARG),
     (dict(m_max=1 << 31), fm.FMM_E_ARG),
+    (dict(sigma=1e-31), fm.FMM_E_ARG),                    # Gaussian core below 1e-30
+    (dict(domain=(0.0, 0.0, 2e36)), fm.FMM_E_ARG),        # domain wider than 1e36
 ])
 def test_invalid_parameters_rejected(lib, kw, err):
     s, _ = _ws(**kw)
     assert s == err
+
+
+def test_parameter_limits_are_inclusive(lib):
+    """sigma = 1e-30 and width = 1e36 are the last accepted values; the
+    singular kernel ignores sigma."""
+    assert _ws(sigma=1e-30)[0] == fm.FMM_OK
+    assert _ws(domain=(0.0, 0.0, 1e36))[0] == fm.FMM_OK
+    assert _ws(sigma=1e-31, kernel="singular")[0] == fm.FMM_OK
 
 
 def test_kernel_choice(lib):

@@ -256,6 +256,46 @@ def test_core_far_below_leaf_width(sigma):
     assert oracle.rel_l2(u[20:], v[20:], uo[20:], vo[20:]) < FP64_TOL
 
 
+def test_far_from_origin():
+    """The unit-square problem moved to x, y near +-2^130 and scaled by
+    2^93 (all positions exact, on a 2^-15 grid of the square): velocities
+    scale by 2^-93 exactly.  The FP64 near field takes the reciprocal of a
+    product of four squared separations; the padding it adds (targets past a
+    leaf's count, inert source slots, the quad's spare lanes) sits on the
+    leaf's scale, so the product stays in range (at 1e10, as distance from
+    a point near 2^130, four squares would overflow).  Compared with the
+    oracle on the unit square, where its unscaled expansions are exact
+    enough; a few coincident particles included."""
+    ux, uy, g = workloads.uniform_square(3000, 43)
+    ux = np.floor(ux * 2.0 ** 15) / 2.0 ** 15
+    uy = np.floor(uy * 2.0 ** 15) / 2.0 ** 15
+    ux[200:210] = ux[5]
+    uy[200:210] = uy[5]
+    x0, y0, w = 2.0 ** 130, -(2.0 ** 130), 2.0 ** 93
+    x, y = x0 + w * ux, y0 + w * uy
+    assert np.array_equal((x - x0) / w, ux) and np.array_equal((y - y0) / w, uy)
+    u, v, plan = run(x, y, g, 0.004 * w, 12, 4, domain=(x0, y0, w))
+    assert plan.out_of_domain() == 0
+    assert np.all(np.isfinite(u)) and np.all(np.isfinite(v))
+    uo, vo = oracle.fmm(ux, uy, g, 0.004, 12, 4)
+    assert oracle.rel_l2(u * w, v * w, uo, vo) < FP64_TOL
+
+
+def test_bounding_square_wider_than_limit_is_flagged():
+    """A bounding square wider than 1e36 counts every particle as outside
+    the domain; the default call raises FMM_E_DOMAIN."""
+    fm = _fm()
+    x, y, g = workloads.uniform_square(500, 44)
+    x = x.copy()
+    x[0] = 2e36
+    _, _, plan = run(x, y, g, 0.01, 8, 3, domain=None)
+    assert plan.out_of_domain() == 500
+    with pytest.raises(fm.FmmError) as ei:
+        plan.evaluate(_dev(x), _dev(y), _dev(g))
+    assert ei.value.status == fm.FMM_E_DOMAIN
+    plan.close()
+
+
 def test_out_of_domain_points_are_counted():
     """Points outside an explicit domain are clamped into the nearest leaf,
     counted, and computed exactly as the oracle computes them."""
