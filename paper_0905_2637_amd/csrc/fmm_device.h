@@ -61,22 +61,22 @@ __device__ __forceinline__ void child_delta(int c, double& dx, double& dy)
     dy = (c & 2) ? 0.25 : -0.25;
 }
 
-// Translation of a truncated series by the complex offset d = (dx, dy), in
-// registers (repeated synthetic division, P (P - 1) / 2 complex
-// multiply-adds; no operator matrix).
+// Translation of a truncated series, in registers (repeated synthetic
+// division, P (P - 1) / 2 steps; no operator matrix).
 //
-// Moments (multipole side): u_k <- sum_{m <= k} C(k, m) d^(k-m) u_m, the
-// coefficients of sum_j g_j (z_j - c + d)^k from those of (z_j - c)^k.
+// Moments (multipole side) by d = 1: u_k <- sum_{m <= k} C(k, m) u_m, the
+// coefficients of sum_j g_j (z_j - c + 1)^k from those of (z_j - c)^k, by
+// additions only (a shift by any d is this between the scalings u_m d^-m
+// and u_k d^k).
 template <int P>
-__device__ __forceinline__ void shift_moments(cd* u, double dx, double dy)
+__device__ __forceinline__ void binomial_sums(cd* u)
 {
 #pragma unroll
     for (int i = 0; i < P - 1; ++i) {
 #pragma unroll
-        for (int l = P - 1; l > i; --l) {       // u_l += d u_(l-1), the old u_(l-1)
-            const cd a = u[l - 1];
-            u[l].x = fma(dx, a.x, fma(-dy, a.y, u[l].x));
-            u[l].y = fma(dx, a.y, fma(dy, a.x, u[l].y));
+        for (int l = P - 1; l > i; --l) {       // u_l += u_(l-1), the old u_(l-1)
+            u[l].x += u[l - 1].x;
+            u[l].y += u[l - 1].y;
         }
     }
 }
