@@ -20,8 +20,9 @@
 // with itself.  The particles of the
 // 3 x 3 neighbourhood are staged through LDS in chunks with coalesced loads
 // (each leaf's particles are contiguous in the sorted arrays), padded with
-// inert sources (zero circulation, far away) to a multiple of the slice
-// count so every lane runs the same, unrollable trip count.  Register
+// inert sources (zero circulation; at the leaf centre for the FP64 Gaussian
+// kernel, far away otherwise) to a multiple of the slice count so every lane
+// runs the same, unrollable trip count.  Register
 // blocking: a lane owns R targets and one of S interleaved slices of the
 // staged sources, so each LDS read feeds R pair interactions; the S partial
 // sums meet through LDS.  Leaves with more than 64
@@ -29,7 +30,8 @@
 //
 // FP64: the Gaussian factor, as 1 - 2^(r^2 (-log2 e / 2 sigma^2)), and the
 // reciprocal are evaluated inline (polynomial and Newton-refined hardware
-// estimate) instead of library calls.  Differences are taken between
+// estimate) instead of library calls; a lane's R targets share one
+// reciprocal per source (that of the product of their r^2).  Differences are taken between
 // physical positions, exact for nearby points, so a pair's term keeps its
 // relative accuracy however close the pair is.
 //
