@@ -256,22 +256,26 @@ def test_core_far_below_leaf_width(sigma):
     assert oracle.rel_l2(u[20:], v[20:], uo[20:], vo[20:]) < FP64_TOL
 
 
-def test_far_from_origin():
-    """The unit-square problem moved to x, y near +-2^130 and scaled by
-    2^93 (all positions exact, on a 2^-15 grid of the square): velocities
-    scale by 2^-93 exactly.  The FP64 near field takes the reciprocal of a
-    product of four squared separations; the padding it adds (targets past a
-    leaf's count, inert source slots, the quad's spare lanes) sits on the
-    leaf's scale, so the product stays in range (at 1e10, as distance from
-    a point near 2^130, four squares would overflow).  Compared with the
-    oracle on the unit square, where its unscaled expansions are exact
-    enough; a few coincident particles included."""
+@pytest.mark.parametrize("ex0,ew", [(130, 93), (-80, -90)])
+def test_scaled_copies_of_the_unit_square(ex0, ew):
+    """The unit-square problem moved to x, y near +-2^ex0 and scaled by 2^ew
+    (all positions exact, on a 2^-15 grid of the square): velocities scale
+    by 2^-ew exactly, so the result times 2^ew is compared with the oracle
+    on the unit square, where its unscaled expansions are exact enough.
+    Near 2^130 with width 2^93 (within the 1e36 limit): the FP64 near field
+    takes the reciprocal of a product of four squared separations, and the
+    padding it adds (targets past a leaf's count, inert source slots, the
+    quad's spare lanes) sits on the leaf's scale, so the product stays in
+    range (at 1e10, as distance from a point near 2^130, four squares would
+    overflow).  At width 2^-90 (sigma 3.2e-30, just above the 1e-30 limit):
+    squared separations near 1e-63, far above the 1e-76 floor.  A few
+    coincident particles included."""
     ux, uy, g = workloads.uniform_square(3000, 43)
     ux = np.floor(ux * 2.0 ** 15) / 2.0 ** 15
     uy = np.floor(uy * 2.0 ** 15) / 2.0 ** 15
     ux[200:210] = ux[5]
     uy[200:210] = uy[5]
-    x0, y0, w = 2.0 ** 130, -(2.0 ** 130), 2.0 ** 93
+    x0, y0, w = 2.0 ** ex0, -(2.0 ** ex0), 2.0 ** ew
     x, y = x0 + w * ux, y0 + w * uy
     assert np.array_equal((x - x0) / w, ux) and np.array_equal((y - y0) / w, uy)
     u, v, plan = run(x, y, g, 0.004 * w, 12, 4, domain=(x0, y0, w))
