@@ -303,7 +303,7 @@ def test_fmm_converges_to_split_direct(L, n):
 
 
 def test_fmm_brute_force_small_n_error_vs_p():
-    """N <= 256 against brute force; error falls with p (SURVEY-style table)."""
+    """N <= 256 against brute force: the error falls monotonically with p."""
     x, y, g = _uniform(200, 41)
     us, vs = oracle.direct_split(x, y, g, 0.01, 2)
     errs = [oracle.rel_l2(*oracle.fmm(x, y, g, 0.01, p, 2), us, vs) for p in (4, 8, 12, 16, 24)]
