@@ -257,9 +257,9 @@ fmm_status fmm_advance_rk2(fmm_plan_t plan, int64_t n, double* d_x, double* d_y,
  * split each box's interaction list over two or three wavefronts (more
  * parallelism on levels with few boxes), 0 .. 8 (default 8; below 2: never).
  * m2l_mfma: 1 runs the FP32 M2L levels of the mixed form whose lists are not
- * split (those above m2l_split_max) on the matrix cores (MFMA; the default
- * of a mixed plan), 0 on the vector units; FP64 levels and split levels
- * always use the vector units.  work_order (batched plans): 1 (default) launches the
+ * split (those above m2l_split_max) on the matrix cores (MFMA), 0 (default)
+ * on the vector units with the interaction-list members taken in symmetric
+ * pairs, as the FP64 levels and all split levels always are.  work_order (batched plans): 1 (default) launches the
  * instances of every stage in decreasing order of the paper's work estimate
  * (eqs. 13-15, see fmm_work_estimate), so the heaviest workgroups are
  * dispatched first; 0 keeps the input order.  p2p_block chooses how a

@@ -26,7 +26,7 @@ size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 struct Tuning {
     int p2p_waves = 4;                   // leaves (wavefronts) per P2P workgroup: 2 or 4
     int split_max = kM2LSplitMaxLevel;   // M2L list split on levels <= this; < 2: never
-    int m2l_mfma = 0;                    // unsplit FP32 M2L levels on the matrix cores (else vector units)
+    int m2l_mfma = 0;                    // unsplit FP32 M2L levels on the matrix cores (else paired, vector units)
     int work_order = 1;                  // launch order: most estimated work first (else input order)
     int p2p_block = 0;                   // near-field register-blocking policy (block_table)
 };
@@ -628,9 +628,10 @@ fmm_status make_plan(const fmm_params* prm, Shape&& sh, bool batch, void* d_work
     pl->batch = batch;
     // measured defaults: in FP64 the utilisation-first blocking is faster on
     // every workload, in the mixed form the power-of-two one on uniform
-    // particles; the FP32 M2L levels that run unsplit go to the matrix cores
+    // particles; the FP32 M2L levels run paired on the vector units (faster
+    // than the matrix cores on C2 and C5)
     pl->tune.p2p_block = mixed ? 0 : 1;
-    pl->tune.m2l_mfma = mixed ? 1 : 0;
+    pl->tune.m2l_mfma = 0;
     pl->shape = std::move(sh);
     pl->last_n = -1;
     pl->last_m = 0;

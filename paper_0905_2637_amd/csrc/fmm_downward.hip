@@ -15,9 +15,10 @@
 // the scalar/L1 caches.  The multipole arrays already hold abar (the upward
 // sweep stores them that way), so only the output scaling 1/l! remains.  The
 // product is dense: every (k, l) pair is one complex multiply-add, 8 p^2
-// flops per interaction-list pair; in FP64 the members are taken two at a
-// time where the square's symmetries relate their data, which halves that
-// (see the work items below).
+// flops per interaction-list pair; on the vector units (FP64, and FP32 in
+// the mixed form) the members are taken two at a time where the square's
+// symmetries relate their data, which halves that (see the work items
+// below).
 //
 // Lane mapping: a workgroup of 4 wavefronts covers 16 x 16 target boxes of
 // one level; wavefront c holds the 64 boxes in child position c of their
@@ -47,7 +48,7 @@ __host__ __device__ inline int level_blocks(int l)
 // round-robin placement on 1M-64M particle trees.
 constexpr int kM2LXcdRun = 8;
 
-// FP64 M2L by symmetric pairs.  The Hankel data of two offsets related by a
+// M2L by symmetric pairs.  The Hankel data of two offsets related by a
 // symmetry of the square differ only by conjugation and the sign
 // (-1)^(n+1): h_n(conj tau) = conj h_n(tau), h_n(-tau) = (-1)^(n+1) h_n(tau).
 // For such a pair (tau, tau') with sources A and B, and S = A + B, D = A - B,
@@ -83,20 +84,21 @@ __constant__ int8_t kM2LItemTab[kM2LItems][3] = {
 // wavefronts per SIMD.  (Carrying the next item's first block across the
 // item loop as well made the compiler spill.)
 constexpr int kM2LK = 4;
+template <typename T>
 struct M2LBlock {
-    cd a[kM2LK], b[kM2LK];
+    cplx<T> a[kM2LK], b[kM2LK];
 };
 
 // The products of one block (terms k0 .. k0 + kM2LK - 1) of a work item of
 // kind KIND with Hankel data h; s = dy / dx for a diagonal.
-template <int P, int KIND>
-__device__ __forceinline__ void m2l_block(double* bx, double* by, const cplx<double>* __restrict__ h,
-                                          const M2LBlock& r, int k0, double s)
+template <typename T, int P, int KIND>
+__device__ __forceinline__ void m2l_block(T* bx, T* by, const cplx<T>* __restrict__ h, const M2LBlock<T>& r,
+                                          int k0, T s)
 {
     constexpr int K = kM2LK;
     const int nk = k0 + K <= P ? K : P - k0;
     if constexpr (KIND <= kItemNegReal) {
-        double Sx[K], Sy[K], Dx[K], Dy[K];
+        T Sx[K], Sy[K], Dx[K], Dy[K];
 #pragma unroll
         for (int kk = 0; kk < K; ++kk) {
             if (kk < nk) {
@@ -109,14 +111,14 @@ __device__ __forceinline__ void m2l_block(double* bx, double* by, const cplx<dou
 #pragma unroll
         for (int nn = 0; nn < 2 * P - 1; ++nn) {
             if (nn < k0 || nn > k0 + nk + P - 2) continue;
-            const cplx<double> hn = h[nn];
-            const double u = hn.x, v = hn.y;
+            const cplx<T> hn = h[nn];
+            const T u = hn.x, v = hn.y;
 #pragma unroll
             for (int kk = 0; kk < K; ++kk) {
                 const int j = nn - k0 - kk;
                 if (kk >= nk || j < 0 || j >= P) continue;
                 if (KIND == kItemNegReal) {
-                    const double X = (nn & 1) ? Sx[kk] : Dx[kk], Y = (nn & 1) ? Sy[kk] : Dy[kk];
+                    const T X = (nn & 1) ? Sx[kk] : Dx[kk], Y = (nn & 1) ? Sy[kk] : Dy[kk];
                     bx[j] = fma(u, X, bx[j]);
                     by[j] = fma(u, Y, by[j]);
                 } else if (KIND == kItemConj || (nn & 1)) {
@@ -131,7 +133,7 @@ __device__ __forceinline__ void m2l_block(double* bx, double* by, const cplx<dou
     } else {
         // a single member: n odd first with the source as it is, then n even
         // with (p, q) = (ax - s ay, ax + s ay) in its place (diagonal)
-        double ax[K], ay[K];
+        T ax[K], ay[K];
 #pragma unroll
         for (int kk = 0; kk < K; ++kk) {
             if (kk < nk) {
@@ -145,7 +147,7 @@ __device__ __forceinline__ void m2l_block(double* bx, double* by, const cplx<dou
 #pragma unroll
                 for (int kk = 0; kk < K; ++kk) {
                     if (kk < nk) {
-                        const double pk = fma(-s, ay[kk], ax[kk]), qk = fma(s, ay[kk], ax[kk]);
+                        const T pk = fma(-s, ay[kk], ax[kk]), qk = fma(s, ay[kk], ax[kk]);
                         ax[kk] = pk;
                         ay[kk] = qk;
                     }
@@ -154,8 +156,8 @@ __device__ __forceinline__ void m2l_block(double* bx, double* by, const cplx<dou
 #pragma unroll
             for (int nn = par; nn < 2 * P - 1; nn += 2) {
                 if (nn < k0 || nn > k0 + nk + P - 2) continue;
-                const cplx<double> hn = h[nn];
-                const double u = hn.x, v = hn.y;
+                const cplx<T> hn = h[nn];
+                const T u = hn.x, v = hn.y;
 #pragma unroll
                 for (int kk = 0; kk < K; ++kk) {
                     const int j = nn - k0 - kk;
@@ -185,10 +187,9 @@ __device__ __forceinline__ void m2l_block(double* bx, double* by, const cplx<dou
 // offset (dx, dy), term(slot, k) reads its term k, and zero_slot is a box of
 // zeros (the partner of the item that has none).  K0 is a template argument:
 // the accumulators are indexed by it and must stay in registers.
-template <int P, int KIND, int K0, typename Slot, typename Term>
-__device__ __forceinline__ void m2l_kind_block(double* bx, double* by, const cplx<double>* __restrict__ H, int cx,
-                                               int cy, int g, int G, int it0, int it1, int zero_slot, Slot slot,
-                                               Term term)
+template <typename T, int P, int KIND, int K0, typename Slot, typename Term>
+__device__ __forceinline__ void m2l_kind_block(T* bx, T* by, const cplx<T>* __restrict__ H, int cx, int cy, int g,
+                                               int G, int it0, int it1, int zero_slot, Slot slot, Term term)
 {
     constexpr int NH = 2 * P - 1;
     for (int it = it0 + (g - it0 % G + G) % G; it < it1; it += G) {
@@ -196,33 +197,37 @@ __device__ __forceinline__ void m2l_kind_block(double* bx, double* by, const cpl
         const bool pair = kM2LItemTab[it][2] != kItemOneReal;
         if (cx) dx = -dx;
         if (cy) dy = -dy;
-        const cplx<double>* h = H + ((dy + 3) * kHankelGrid + (dx + 3)) * NH;
+        const cplx<T>* h = H + ((dy + 3) * kHankelGrid + (dx + 3)) * NH;
         const int ia = slot(dx, dy);
         const int ib = KIND <= kItemNegReal && pair
                            ? slot(KIND == kItemConj ? dx : -dx, KIND == kItemNegConj ? dy : -dy)
                            : zero_slot;
-        M2LBlock r;
+        M2LBlock<T> r;
 #pragma unroll
         for (int kk = 0; kk < kM2LK; ++kk) {
             if (K0 + kk < P) {                  // abar_k, zero for k >= p
-                r.a[kk] = term(ia, K0 + kk);
-                if (KIND <= kItemNegReal) r.b[kk] = term(ib, K0 + kk);
+                const auto ta = term(ia, K0 + kk);
+                r.a[kk] = cplx<T>{T(ta.x), T(ta.y)};
+                if (KIND <= kItemNegReal) {
+                    const auto tb = term(ib, K0 + kk);
+                    r.b[kk] = cplx<T>{T(tb.x), T(tb.y)};
+                }
             }
         }
-        m2l_block<P, KIND>(bx, by, h, r, K0, dx == dy ? 1.0 : -1.0);
+        m2l_block<T, P, KIND>(bx, by, h, r, K0, dx == dy ? T(1) : T(-1));
     }
 }
 
 // Block K0 of all 15 work items of row g of G (the table's kinds in order).
-template <int P, int K0, typename Slot, typename Term>
-__device__ __forceinline__ void m2l_items_block(double* bx, double* by, const cplx<double>* __restrict__ H, int cx,
-                                                int cy, int g, int G, int zero_slot, Slot slot, Term term)
+template <typename T, int P, int K0, typename Slot, typename Term>
+__device__ __forceinline__ void m2l_items_block(T* bx, T* by, const cplx<T>* __restrict__ H, int cx, int cy, int g,
+                                                int G, int zero_slot, Slot slot, Term term)
 {
-    m2l_kind_block<P, kItemConj, K0>(bx, by, H, cx, cy, g, G, 0, 9, zero_slot, slot, term);
-    m2l_kind_block<P, kItemNegConj, K0>(bx, by, H, cx, cy, g, G, 9, 11, zero_slot, slot, term);
-    m2l_kind_block<P, kItemNegReal, K0>(bx, by, H, cx, cy, g, G, 11, 13, zero_slot, slot, term);
-    m2l_kind_block<P, kItemOneImag, K0>(bx, by, H, cx, cy, g, G, 13, 14, zero_slot, slot, term);
-    m2l_kind_block<P, kItemOneDiag, K0>(bx, by, H, cx, cy, g, G, 14, 15, zero_slot, slot, term);
+    m2l_kind_block<T, P, kItemConj, K0>(bx, by, H, cx, cy, g, G, 0, 9, zero_slot, slot, term);
+    m2l_kind_block<T, P, kItemNegConj, K0>(bx, by, H, cx, cy, g, G, 9, 11, zero_slot, slot, term);
+    m2l_kind_block<T, P, kItemNegReal, K0>(bx, by, H, cx, cy, g, G, 11, 13, zero_slot, slot, term);
+    m2l_kind_block<T, P, kItemOneImag, K0>(bx, by, H, cx, cy, g, G, 13, 14, zero_slot, slot, term);
+    m2l_kind_block<T, P, kItemOneDiag, K0>(bx, by, H, cx, cy, g, G, 14, 15, zero_slot, slot, term);
 }
 
 // f(std::integral_constant<int, c>) for c = 0 .. sizeof...(C) - 1, in order.
@@ -232,140 +237,22 @@ __device__ __forceinline__ void m2l_for_chunks(F f, std::integer_sequence<int, C
     (f(std::integral_constant<int, C>{}), ...);
 }
 
-// gridDim.y = G in {1, 2, 3}: workgroup row g takes every G-th member of the
-// interaction list (FP64: every G-th work item) and writes its partial sum
-// to out[g] (out[0] = le).
+// gridDim.y = G in {1, 2, 3}: workgroup row g takes every G-th work item
+// (the matrix-core kernel: every G-th member of the interaction list) and
+// writes its partial sum to out[g] (out[0] = le).
 struct M2LOut {
     cd* out[3];
 };
 
-// FP32 M2L on the vector units (T = float; FP64 levels take the paired
-// kernels below).  Work table arg: the instance's level range [lmin, lmax]
-// in this launch.
-template <int P, typename T>
-__global__ void __launch_bounds__(256)
-k_m2l(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restrict__ me_all, M2LOut dst_,
-      const cplx<T>* __restrict__ H, const double* __restrict__ sout_)
-{
-    // the translation data of all 49 offset slots is staged once per
-    // workgroup and read back as LDS broadcasts, and the source terms are
-    // applied in blocks of at most 8; both keep the register count down (more
-    // wavefronts per SIMD)
-    static_assert(std::is_same<T, float>::value, "FP64 M2L runs in k_m2l64_chunks / k_m2l64_lds");
-    constexpr int NH = 2 * P - 1;
-    __shared__ cplx<T> sH[kHankelGrid * kHankelGrid * NH];
-    const int lin = xcd_runs(int(blockIdx.x + gridDim.x * blockIdx.y), int(gridDim.x * gridDim.y), kM2LXcdRun);
-    const int g = lin / int(gridDim.x), blk = lin % int(gridDim.x);
-    if (blk >= wk.wg_begin[n_inst]) return;                // past the launch's work (batched plans)
-    for (int e = threadIdx.x; e < kHankelGrid * kHankelGrid * NH; e += 256) sH[e] = H[e];
-    __syncthreads();
-    const cplx<T>* Hs = sH;
-    const int pos = find_inst(wk.wg_begin, n_inst, blk);   // place in the launch order
-    const int q = wk.order[pos];
-    const int G = int(gridDim.y);
-    if (g >= G) return;
-    int bl = blk - wk.wg_begin[pos];
-    int l = wk.arg[2 * pos];
-    while (bl >= level_blocks(l)) { bl -= level_blocks(l); ++l; }
-    const cd* me = me_all + inst[q].box_off * P;
-    cd* __restrict__ le = g == 0 ? dst_.out[0] + inst[q].box_off * P : dst_.out[g] + inst[q].split_off * P;
-    const int side = 1 << l;
-    const int bpr = side >= 16 ? side / 16 : 1;
-    const int bx = bl % bpr, by = bl / bpr;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const int cx = wave & 1, cy = wave >> 1;
-    const int ta = 2 * (bx * 8 + (lane & 7)) + cx;
-    const int tb = 2 * (by * 8 + (lane >> 3)) + cy;
-    const bool active = ta < side && tb < side;
-    const cd* me_l = me + level_offset(l) * P;
-
-    constexpr int kHStep = 4;                  // FP32: translation values in flight
-    constexpr int NB = (P + 7) / 8;            // input blocks
-    constexpr int KB = (P + NB - 1) / NB;      // terms per block
-    T bx_[P], by_[P];
-#pragma unroll
-    for (int k = 0; k < P; ++k) { bx_[k] = T(0); by_[k] = T(0); }
-
-    int member = 0;
-    // next interaction-list slot at or after o that belongs to this
-    // workgroup row (uniform), 36 when there is none
-    auto next_member = [&](int o) -> int {
-        for (; o < 36; ++o) {
-            int dx, dy;
-            if (!il_offset(cx, cy, o, dx, dy)) continue;
-            if ((member++) % G == g) return o;
-        }
-        return 36;
-    };
-    auto source = [&](int o, bool& ok) -> const cd* {
-        int dx, dy;
-        il_offset(cx, cy, o, dx, dy);
-        const int sa = ta + dx, sb = tb + dy;
-        ok = active && sa >= 0 && sb >= 0 && sa < side && sb < side;
-        return me_l + int64_t(morton(uint32_t(ok ? sa : 0), uint32_t(ok ? sb : 0))) * P;
-    };
-    auto table = [&](int o) -> const cplx<T>* {
-        int dx, dy;
-        il_offset(cx, cy, o, dx, dy);
-        return Hs + ((dy + 3) * kHankelGrid + (dx + 3)) * NH;
-    };
-
-    {
-        // FP32: source terms in blocks of KB, only one block live next to the
-        // P accumulators
-        for (int o = next_member(0); o < 36; o = next_member(o + 1)) {
-            bool ok;
-            const cd* src = source(o, ok);
-            if (!ok) continue;
-            const cplx<T>* h = table(o);
-#pragma unroll
-            for (int kb = 0; kb < P; kb += KB) {
-                T ax[KB], ay[KB];
-#pragma unroll
-                for (int kk = 0; kk < KB; ++kk) {
-                    const int k = kb + kk;
-                    if (k < P) {
-                        const cd t = src[k];        // abar_k, zero for k >= p
-                        ax[kk] = T(t.x);
-                        ay[kk] = T(t.y);
-                    }
-                }
-#pragma unroll
-                for (int nn = kb; nn < kb + KB + P - 1; ++nn) {
-                    if (nn > 2 * P - 2) break;
-                    const cplx<T> hn = h[nn];
-#pragma unroll
-                    for (int kk = 0; kk < KB; ++kk) {
-                        const int k = kb + kk, j = nn - k;
-                        if (k < P && j >= 0 && j < P) cmac(bx_[j], by_[j], hn.x, hn.y, ax[kk], ay[kk]);
-                    }
-                    if ((nn - kb) % kHStep == kHStep - 1) __builtin_amdgcn_sched_barrier(0);
-                }
-                if (NB > 1) __builtin_amdgcn_sched_barrier(0);
-            }
-        }
-    }
-    if (active) {
-        cd* dst = le + (level_offset(l) + int64_t(morton(uint32_t(ta), uint32_t(tb)))) * P;
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
-            const double sc = sout_[k];         // zero for k >= p
-            dst[k] = cd{double(bx_[k]) * sc, double(by_[k]) * sc};
-        }
-    }
-}
-
 // FP64 M2L with the sources of the workgroup's tile staged in LDS once: the
 // 16 x 16 target boxes of a workgroup (four child classes of an 8 x 8 parent
 // block) draw their interaction lists from the 20 x 20 boxes around them;
-// boxes outside the grid are staged as zeros.  Same work decomposition and
-// summation order as k_m2l, so the two give the same bits.  The stage takes
+// boxes outside the grid are staged as zeros.  Same work items and block
+// order as k_m2l_chunks, so the two give the same bits.  The stage takes
 // 6.4 KB per expansion term (109 KB at p = 17), which leaves room for one
-// workgroup per CU.  Measured at p = 17: on grids of 9 and 21 workgroups it
-// halves the M2L time (the shared loads shorten each member's wait); at 69
-// and more it loses to k_m2l, whose smaller footprint lets more wavefronts
-// hide the loads.
+// workgroup per CU: on grids of a few tens of workgroups it is the faster
+// (the whole stage loaded once); on larger ones the chunked stage, whose
+// smaller footprint lets more wavefronts hide the loads.
 constexpr int kHalo = 20;
 constexpr int kM2LStageMaxWg = 32;
 template <int P>
@@ -417,11 +304,11 @@ k_m2l64_lds(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __rest
     double bx_[P], by_[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) { bx_[k] = 0.0; by_[k] = 0.0; }
-    // the work items block by block, in the order of k_m2l64_chunks
+    // the work items block by block, in the order of k_m2l_chunks
     auto slot = [&](int dx, int dy) { return (tb + dy - y_lo) * kHalo + (ta + dx - x_lo); };
     auto term = [&](int sl, int k) { return sA[sl * P + k]; };
     m2l_for_chunks([&](auto c) {
-        m2l_items_block<P, decltype(c)::value * kM2LK>(bx_, by_, H, cx, cy, g, G, kHalo * kHalo, slot, term);
+        m2l_items_block<double, P, decltype(c)::value * kM2LK>(bx_, by_, H, cx, cy, g, G, kHalo * kHalo, slot, term);
     }, std::make_integer_sequence<int, (P + kM2LK - 1) / kM2LK>{});
     if (active) {
         cd* dst = le + (level_offset(l) + int64_t(morton(uint32_t(ta), uint32_t(tb)))) * P;
@@ -433,29 +320,33 @@ k_m2l64_lds(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __rest
     }
 }
 
-// FP64 M2L by symmetric pairs with the workgroup's sources staged in LDS
-// kM2LK terms at a time: the 16 x 16 targets of a workgroup draw every
-// source from the 20 x 20 boxes around them, so chunk c holds terms 4c ..
-// 4c + 3 of those 400 boxes (25.6 KB, k-major, zeros outside the level and
-// past p, one zero box at the end for the item without a partner) and every
-// wavefront runs block c of all its work items from it.  The loads of a
-// chunk are coalesced and shared by the workgroup's 256 targets instead of
-// issued per lane and member; the same items and block order as k_m2l64_lds,
+// M2L by symmetric pairs (T = double: every FP64 level but the smallest
+// launches; T = float: the FP32 levels of the mixed form on the vector
+// units) with the workgroup's sources staged in LDS kM2LK terms at a time:
+// the 16 x 16 targets of a workgroup draw every source from the 20 x 20
+// boxes around them, so chunk c holds terms 4c .. 4c + 3 of those 400 boxes
+// (25.6 KB in FP64, k-major, zeros outside the level and past p, one zero
+// box at the end for the item without a partner) and every wavefront runs
+// block c of all its work items from it.  The loads of a chunk are
+// coalesced and shared by the workgroup's 256 targets instead of issued per
+// lane and member; in FP64 the same items and block order as k_m2l64_lds,
 // so the two give the same bits.
-template <int P>
+template <int P, typename T>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P > 24 ? 2 : 3)))
-k_m2l64_chunks(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restrict__ me_all, M2LOut dst_,
-               const cplx<double>* __restrict__ H, const double* __restrict__ sout_)
+k_m2l_chunks(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __restrict__ me_all, M2LOut dst_,
+             const cplx<T>* __restrict__ H, const double* __restrict__ sout_)
 {
     constexpr int NB = (P + kM2LK - 1) / kM2LK;
     constexpr int NBOX = kHalo * kHalo;
-    __shared__ cd sA[kM2LK][NBOX + 1];
+    __shared__ cplx<T> sA[kM2LK][NBOX + 1];
     const int lin = xcd_runs(int(blockIdx.x + gridDim.x * blockIdx.y), int(gridDim.x * gridDim.y), kM2LXcdRun);
     const int g = lin / int(gridDim.x), blk = lin % int(gridDim.x);
     if (blk >= wk.wg_begin[n_inst]) return;                // past the launch's work (batched plans)
     const int pos = find_inst(wk.wg_begin, n_inst, blk);
     const int q = wk.order[pos];
-    const int G = min(int(gridDim.y), inst[q].g64);
+    // split lists: FP32 levels always over the launch's three rows, FP64
+    // levels over the instance's g64 (the rows past it have nothing to do)
+    const int G = std::is_same<T, float>::value ? int(gridDim.y) : min(int(gridDim.y), inst[q].g64);
     if (g >= G) return;
     int bl = blk - wk.wg_begin[pos];
     int l = wk.arg[2 * pos];
@@ -473,9 +364,9 @@ k_m2l64_chunks(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __r
     const int ta = 2 * (bx * 8 + (lane & 7)) + cx;
     const int tb = 2 * (by * 8 + (lane >> 3)) + cy;
     const bool active = ta < side && tb < side;
-    double bx_[P], by_[P];
+    T bx_[P], by_[P];
 #pragma unroll
-    for (int k = 0; k < P; ++k) { bx_[k] = 0.0; by_[k] = 0.0; }
+    for (int k = 0; k < P; ++k) { bx_[k] = T(0); by_[k] = T(0); }
     // halo slot of the source at offset (dx, dy) from this lane's target
     auto slot = [&](int dx, int dy) { return (tb + dy - y_lo) * kHalo + (ta + dx - x_lo); };
     m2l_for_chunks([&](auto c) {
@@ -485,32 +376,33 @@ k_m2l64_chunks(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __r
         // trip); outside the level, past p and past the stage: the level's
         // first term is read and replaced by zero
         constexpr int NE = NBOX * kM2LK, NIT = (NE + 255) / 256;
-        cd v[NIT];
+        cplx<T> v[NIT];
 #pragma unroll
         for (int i = 0; i < NIT; ++i) {
             const int e = int(threadIdx.x) + 256 * i;
             const int hb = e / kM2LK, kk = e - hb * kM2LK;  // a box's terms from consecutive threads
             const int sa = x_lo + hb % kHalo, sb = y_lo + hb / kHalo;
             const bool in = e < NE && sa >= 0 && sb >= 0 && sa < side && sb < side && k0 + kk < P;
-            v[i] = me_l[in ? int64_t(morton(uint32_t(sa), uint32_t(sb))) * P + k0 + kk : 0];
-            if (!in) v[i] = cd{0.0, 0.0};
+            const cd t = me_l[in ? int64_t(morton(uint32_t(sa), uint32_t(sb))) * P + k0 + kk : 0];
+            v[i] = cplx<T>{T(t.x), T(t.y)};
+            if (!in) v[i] = cplx<T>{T(0), T(0)};
         }
 #pragma unroll
         for (int i = 0; i < NIT; ++i) {
             const int e = int(threadIdx.x) + 256 * i;
             if (e < NE) sA[e % kM2LK][e / kM2LK] = v[i];
         }
-        if (threadIdx.x < kM2LK) sA[threadIdx.x][NBOX] = cd{0.0, 0.0};
+        if (threadIdx.x < kM2LK) sA[threadIdx.x][NBOX] = cplx<T>{T(0), T(0)};
         __syncthreads();
         // block c of every work item of this row
-        m2l_items_block<P, k0>(bx_, by_, H, cx, cy, g, G, NBOX, slot, [&](int sl, int k) { return sA[k - k0][sl]; });
+        m2l_items_block<T, P, k0>(bx_, by_, H, cx, cy, g, G, NBOX, slot, [&](int sl, int k) { return sA[k - k0][sl]; });
     }, std::make_integer_sequence<int, NB>{});
     if (active) {
         cd* dst = le + (level_offset(l) + int64_t(morton(uint32_t(ta), uint32_t(tb)))) * P;
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             const double sc = sout_[k];
-            dst[k] = cd{bx_[k] * sc, by_[k] * sc};
+            dst[k] = cd{double(bx_[k]) * sc, double(by_[k]) * sc};
         }
     }
 }
@@ -532,7 +424,8 @@ k_m2l64_chunks(Work wk, int n_inst, const Inst* __restrict__ inst, const cd* __r
 // fragments are formed from the workgroup's LDS copy of the h_n of the 40
 // offsets (rows and columns past 2P are zero), once per member and k-step,
 // and serve all four column tiles.  78 KB of LDS per workgroup: two per CU.
-// Same work items, member split and outputs as k_m2l.
+// Same outputs as k_m2l_chunks; a list split over G rows takes every G-th
+// interaction-list member.
 typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMfmaHalo = 20;
@@ -881,8 +774,9 @@ k_downward(Work wk, int n_inst, const Inst* __restrict__ inst, cd* __restrict__ 
     }
 }
 
-// Debug: the interaction list of boxes [b0, b0 + cnt) exactly as k_m2l
-// walks it, as global box ids, -1 padded to 27 entries, box b0 first.
+// Debug: the interaction list of boxes [b0, b0 + cnt) in the order of the
+// list offsets (il_offset), as global box ids, -1 padded to 27 entries, box
+// b0 first.
 __global__ void __launch_bounds__(256) k_ilist(int L, int64_t b0, int64_t cnt, int32_t* __restrict__ out)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -921,7 +815,7 @@ hipError_t m2l_impl(const Buffers& b, const Work& w, int nwg, bool fp32, bool mf
             return hipGetLastError();
         }
         if (fp32) {
-            hipLaunchKernelGGL((k_m2l<P, float>), grid, dim3(256), 0, st, w, b.n_inst, b.inst, b.me, out,
+            hipLaunchKernelGGL((k_m2l_chunks<P, float>), grid, dim3(256), 0, st, w, b.n_inst, b.inst, b.me, out,
                                reinterpret_cast<const cplx<float>*>(b.t_h32), b.t_sout);
             return hipGetLastError();
         }
@@ -933,7 +827,7 @@ hipError_t m2l_impl(const Buffers& b, const Work& w, int nwg, bool fp32, bool mf
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((k_m2l64_chunks<P>), grid, dim3(256), 0, st, w, b.n_inst, b.inst, b.me, out,
+    hipLaunchKernelGGL((k_m2l_chunks<P, double>), grid, dim3(256), 0, st, w, b.n_inst, b.inst, b.me, out,
                        reinterpret_cast<const cplx<double>*>(b.t_h64), b.t_sout);
     return hipGetLastError();
 }

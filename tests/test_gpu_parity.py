@@ -398,22 +398,25 @@ def test_mixed_within_gate_of_split_direct(n, L, p, sigma, fine, seed):
         assert err < MIXED_TOL
 
 
+@pytest.mark.parametrize("mfma", [0, 1])
 @pytest.mark.parametrize("n,L,p,sigma,fine,split,seed", [
     (20000, 6, 17, 0.002, 2, 5, 26),    # FP32 level 5 split over wavefronts, level 6 not
     (20000, 6, 20, 0.0015, 3, 5, 27),   # FP32 levels 4-5 split, 6 not
     (6000, 5, 12, 0.003, 2, 8, 28),     # every FP32 level split
     (20000, 6, 12, 0.002, 2, 0, 29),    # no level split
+    (3000, 3, 12, 0.01, 2, 8, 30),      # every level FP32 and split: no FP64 split level
 ])
-def test_mixed_mfma_m2l_matches_oracle(n, L, p, sigma, fine, split, seed):
-    """The FP32 M2L levels on the matrix cores (the launch shape the
-    autotuner may choose for a mixed plan) against the oracle FMM and the
-    FP64 split-kernel direct sum, at the mixed form's tolerances."""
+def test_mixed_m2l_forms_match_oracle(n, L, p, sigma, fine, split, seed, mfma):
+    """The FP32 M2L levels on the matrix cores (mfma = 1) and paired on the
+    vector units (mfma = 0, the default), the two launch shapes the
+    autotuner chooses between for a mixed plan, against the oracle FMM and
+    the FP64 split-kernel direct sum, at the mixed form's tolerances."""
     import torch
     fm = _fm()
     x, y, g = workloads.uniform_square(n, seed)
     plan = fm.Plan(n, sigma, p, L, precision="mixed", fp32_fine_levels=fine)
-    plan.set_tuning(4, split, 1)
-    assert plan.tuning()["m2l_mfma"] == 1
+    plan.set_tuning(4, split, mfma)
+    assert plan.tuning()["m2l_mfma"] == mfma
     u, v = plan.evaluate(_dev(x), _dev(y), _dev(g))
     torch.cuda.synchronize()
     u, v = u.cpu().numpy(), v.cpu().numpy()
