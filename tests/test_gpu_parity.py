@@ -405,6 +405,9 @@ def test_mixed_within_gate_of_split_direct(n, L, p, sigma, fine, seed):
     (6000, 5, 12, 0.003, 2, 8, 28),     # every FP32 level split
     (20000, 6, 12, 0.002, 2, 0, 29),    # no level split
     (3000, 3, 12, 0.01, 2, 8, 30),      # every level FP32 and split: no FP64 split level
+    (6000, 5, 8, 0.003, 2, 0, 31),      # the compiled sizes 8, 16 and 24 of the FP32 kernels
+    (6000, 5, 15, 0.003, 2, 0, 32),
+    (6000, 5, 22, 0.003, 2, 5, 33),
 ])
 def test_mixed_m2l_forms_match_oracle(n, L, p, sigma, fine, split, seed, mfma):
     """The FP32 M2L levels on the matrix cores (mfma = 1) and paired on the
